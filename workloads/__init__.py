@@ -1,0 +1,426 @@
+"""Seeded synthetic DEM workloads, shared by the FP64 oracle and the HIP path.
+
+This module only *builds inputs*: sphere/clump arrays, clump templates, walls,
+materials and an initial state. It holds none of the method's arithmetic
+(no contact detection, no force law, no integration).  Every array it returns
+is snapped to a value that both sides can hold exactly:
+
+* positions are multiples of 2^-36 m, so an integer voxel index plus a 32-bit
+  float offset represents them without rounding, and their FP64 value is the
+  same on both sides;
+* velocities, angular velocities, radii, masses, inertias and template
+  positions are float32-representable, because the GPU stores them as float32;
+* quaternions are FP64 unit quaternions (the GPU stores them in FP64).
+
+Random draws use ``numpy.random.default_rng(seed)`` (PCG64) in a fixed order:
+radii, jitter, orientations, velocities, types.
+
+The workloads stand in for the paper's experiments (Sec. 5, Sec. 6), whose
+meshes and measured data are not available; they follow the shapes, sizes and
+value ranges of the five benchmark configurations documented with the bench.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+POS_QUANTUM = 2.0 ** -36          # positions snap to this grid (metres)
+VOXEL_SIZE = 2.0 ** -14           # voxel edge; offsets live in [0, VOXEL_SIZE)
+RHO = 2600.0                      # particle density, kg/m^3
+
+PLANE = 0
+CYLINDER = 1
+
+
+def snap_pos(x):
+    return np.round(np.asarray(x, dtype=np.float64) / POS_QUANTUM) * POS_QUANTUM
+
+
+def f32(x):
+    return np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+@dataclass
+class System:
+    """All inputs of one DEM problem plus an initial state (host, numpy)."""
+    # owners (clumps or single spheres)
+    own_sph0: np.ndarray      # int32 [No+1]  spheres of owner o are sph0[o]..sph0[o+1]-1
+    own_tmpl: np.ndarray      # int32 [No]    -1 = single sphere at the owner centre
+    own_mass: np.ndarray      # f64   [No]
+    own_moi: np.ndarray       # f64   [No,3] principal moments (template frame)
+    # spheres (owner-major order; sphere id = row)
+    sph_owner: np.ndarray     # int32 [Ns]
+    sph_comp: np.ndarray      # int32 [Ns]   component index inside the template
+    sph_local: np.ndarray     # f64   [Ns,3] position in the owner's principal frame
+    sph_rad: np.ndarray       # f64   [Ns]
+    sph_mat: np.ndarray       # int32 [Ns]
+    # clump templates (component positions, principal frame)
+    tmpl_sph0: np.ndarray     # int32 [T+1]
+    tmpl_local: np.ndarray    # f64   [sum,3]
+    # analytic walls with prescribed motion
+    wall_type: np.ndarray     # int32 [W]  0 plane, 1 cylinder
+    wall_geom: np.ndarray     # f64   [W,8] plane: p0,n ; cylinder: c,axis,R,L
+    wall_vel: np.ndarray      # f64   [W,3]
+    wall_omega: np.ndarray    # f64   [W,3]
+    wall_mat: np.ndarray      # int32 [W]
+    # materials: E, nu per material; CoR, mu, Crr per material pair
+    mat_E: np.ndarray
+    mat_nu: np.ndarray
+    mat_cor: np.ndarray
+    mat_mu: np.ndarray
+    mat_crr: np.ndarray
+    gravity: np.ndarray
+    dt: float
+    margin: float
+    domain_lo: np.ndarray
+    domain_hi: np.ndarray
+    # initial state
+    X: np.ndarray             # f64 [No,3]
+    q: np.ndarray             # f64 [No,4] (w,x,y,z), body -> world
+    V: np.ndarray             # f64 [No,3]
+    W: np.ndarray             # f64 [No,3] angular velocity in the body frame
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_owners(self):
+        return int(self.own_tmpl.shape[0])
+
+    @property
+    def n_spheres(self):
+        return int(self.sph_rad.shape[0])
+
+    @property
+    def n_walls(self):
+        return int(self.wall_type.shape[0])
+
+    def copy_state(self):
+        return dict(X=self.X.copy(), q=self.q.copy(), V=self.V.copy(), W=self.W.copy())
+
+
+# --------------------------------------------------------------------------
+# building blocks
+# --------------------------------------------------------------------------
+
+def materials(E=1e8, nu=0.3, cor=0.6, mu=0.5, crr=0.0, n=1):
+    """Material table in the form the paper's LoadMaterial takes (Sec. 3):
+    E and nu per material, CoR / mu / Crr per material pair."""
+    return dict(mat_E=np.full(n, E), mat_nu=np.full(n, nu),
+                mat_cor=np.full((n, n), cor), mat_mu=np.full((n, n), mu),
+                mat_crr=np.full((n, n), crr))
+
+
+def box_walls(lo, hi, mat=0, moving=None):
+    """Six inward-facing planes bounding [lo, hi]; ``moving`` maps a wall index
+    (0:-x 1:+x 2:-y 3:+y 4:-z 5:+z) to a prescribed velocity."""
+    lo = snap_pos(lo)
+    hi = snap_pos(hi)
+    geom, vel = [], []
+    for ax in range(3):
+        for side in (0, 1):
+            p = np.zeros(3)
+            n = np.zeros(3)
+            p[ax] = lo[ax] if side == 0 else hi[ax]
+            n[ax] = 1.0 if side == 0 else -1.0
+            geom.append(np.r_[p, n, 0.0, 0.0])
+            vel.append(np.zeros(3))
+    if moving:
+        for k, v in moving.items():
+            vel[k] = np.asarray(v, dtype=np.float64)
+    W = len(geom)
+    return dict(wall_type=np.zeros(W, np.int32), wall_geom=np.array(geom),
+                wall_vel=np.array(vel), wall_omega=np.zeros((W, 3)),
+                wall_mat=np.full(W, mat, np.int32))
+
+
+def concat_walls(*ws):
+    if not ws:
+        return dict(wall_type=np.zeros(0, np.int32), wall_geom=np.zeros((0, 8)),
+                    wall_vel=np.zeros((0, 3)), wall_omega=np.zeros((0, 3)),
+                    wall_mat=np.zeros(0, np.int32))
+    return {k: np.concatenate([w[k] for w in ws]) for k in ws[0]}
+
+
+def plane(p0, normal, vel=(0, 0, 0), mat=0):
+    n = np.asarray(normal, dtype=np.float64)
+    n = n / np.linalg.norm(n)
+    return dict(wall_type=np.array([PLANE], np.int32),
+                wall_geom=np.array([np.r_[snap_pos(p0), n, 0.0, 0.0]]),
+                wall_vel=np.array([vel], dtype=np.float64),
+                wall_omega=np.zeros((1, 3)), wall_mat=np.array([mat], np.int32))
+
+
+def cylinder(centre, axis, radius, length, vel=(0, 0, 0), omega=(0, 0, 0), mat=0):
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    return dict(wall_type=np.array([CYLINDER], np.int32),
+                wall_geom=np.array([np.r_[snap_pos(centre), a, radius, length]]),
+                wall_vel=np.array([vel], dtype=np.float64),
+                wall_omega=np.array([omega], dtype=np.float64),
+                wall_mat=np.array([mat], np.int32))
+
+
+def template_mass_props(local, radii, rho=RHO, n=128):
+    """Mass, centroid and principal moments of a union of spheres, integrated
+    on a fixed n^3 midpoint grid (the paper takes these as user input)."""
+    local = np.asarray(local, dtype=np.float64)
+    radii = np.asarray(radii, dtype=np.float64)
+    lo = (local - radii[:, None]).min(0)
+    hi = (local + radii[:, None]).max(0)
+    ext = hi - lo
+    step = ext / n
+    ax = [lo[k] + (np.arange(n) + 0.5) * step[k] for k in range(3)]
+    gx, gy, gz = np.meshgrid(*ax, indexing="ij")
+    inside = np.zeros(gx.shape, dtype=bool)
+    for c, r in zip(local, radii):
+        inside |= (gx - c[0]) ** 2 + (gy - c[1]) ** 2 + (gz - c[2]) ** 2 < r * r
+    dv = float(np.prod(step))
+    x, y, z = gx[inside], gy[inside], gz[inside]
+    mass = rho * dv * x.size
+    cm = np.array([x.mean(), y.mean(), z.mean()])
+    x, y, z = x - cm[0], y - cm[1], z - cm[2]
+    Ixx = rho * dv * np.sum(y * y + z * z)
+    Iyy = rho * dv * np.sum(x * x + z * z)
+    Izz = rho * dv * np.sum(x * x + y * y)
+    Ixy = -rho * dv * np.sum(x * y)
+    Ixz = -rho * dv * np.sum(x * z)
+    Iyz = -rho * dv * np.sum(y * z)
+    return mass, cm, np.array([[Ixx, Ixy, Ixz], [Ixy, Iyy, Iyz], [Ixz, Iyz, Izz]])
+
+
+def tri_template(r, circumradius):
+    ang = np.deg2rad([90.0, 210.0, 330.0])
+    loc = np.stack([circumradius * np.cos(ang), circumradius * np.sin(ang), np.zeros(3)], 1)
+    return f32(loc), f32(np.full(3, r))
+
+
+def penta_template(r, circumradius):
+    v = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], dtype=np.float64)
+    v *= circumradius / math.sqrt(3.0)
+    loc = np.vstack([v, np.zeros((1, 3))])
+    return f32(loc), f32(np.full(5, r))
+
+
+def random_quaternions(rng, n):
+    """Uniform random unit quaternions (Shoemake's subgroup algorithm)."""
+    u1, u2, u3 = rng.random(n), rng.random(n), rng.random(n)
+    a, b = np.sqrt(1.0 - u1), np.sqrt(u1)
+    q = np.stack([b * np.cos(2 * np.pi * u3), a * np.sin(2 * np.pi * u2),
+                  a * np.cos(2 * np.pi * u2), b * np.sin(2 * np.pi * u3)], 1)
+    return q / np.linalg.norm(q, axis=1, keepdims=True)
+
+
+def assemble(owner_tmpl, X, q, V, W, templates, single_rad, sph_mat_of_tmpl,
+             walls, mats, gravity, dt, margin, domain_lo, domain_hi, name="",
+             single_mass=None, single_moi=None, meta=None):
+    """Expand owners into the owner-major sphere arrays.
+
+    owner_tmpl: -1 for a single sphere (radius from ``single_rad``), else the
+    template index. ``templates`` is a list of (local[k,3], radii[k]) in the
+    template's principal frame with the centroid at the origin.
+    """
+    owner_tmpl = np.asarray(owner_tmpl, dtype=np.int32)
+    No = owner_tmpl.shape[0]
+    counts = np.ones(No, dtype=np.int64)
+    tmass, tmoi = [], []
+    for (loc, rad) in templates:
+        m, cm, I = template_mass_props(loc, rad)
+        tmass.append(float(np.float32(m)))
+        tmoi.append(f32(np.diag(I)))
+    for t, (loc, rad) in enumerate(templates):
+        counts[owner_tmpl == t] = len(rad)
+    sph0 = np.zeros(No + 1, dtype=np.int64)
+    np.cumsum(counts, out=sph0[1:])
+    Ns = int(sph0[-1])
+    sph_owner = np.repeat(np.arange(No, dtype=np.int64), counts)
+    comp = np.arange(Ns, dtype=np.int64) - sph0[sph_owner]
+    sph_local = np.zeros((Ns, 3))
+    sph_rad = np.zeros(Ns)
+    sph_mat = np.zeros(Ns, dtype=np.int32)
+    own_mass = np.zeros(No)
+    own_moi = np.zeros((No, 3))
+    single = owner_tmpl < 0
+    if single.any():
+        sidx = sph0[:-1][single]
+        r = f32(np.asarray(single_rad)[single] if np.ndim(single_rad) else np.full(single.sum(), single_rad))
+        sph_rad[sidx] = r
+        m = f32(RHO * 4.0 / 3.0 * np.pi * r ** 3) if single_mass is None else f32(single_mass)
+        own_mass[single] = m
+        own_moi[single] = f32(0.4 * m * r * r)[:, None] if single_moi is None else f32(single_moi)
+    tmpl_sph0 = [0]
+    tmpl_local = []
+    for t, (loc, rad) in enumerate(templates):
+        sel = owner_tmpl == t
+        tmpl_local.append(loc)
+        tmpl_sph0.append(tmpl_sph0[-1] + len(rad))
+        if not sel.any():
+            continue
+        own_mass[sel] = tmass[t]
+        own_moi[sel] = tmoi[t]
+        for k in range(len(rad)):
+            sidx = sph0[:-1][sel] + k
+            sph_local[sidx] = loc[k]
+            sph_rad[sidx] = rad[k]
+            sph_mat[sidx] = sph_mat_of_tmpl[t] if sph_mat_of_tmpl is not None else 0
+    tmpl_local = np.vstack(tmpl_local) if tmpl_local else np.zeros((0, 3))
+    return System(own_sph0=sph0.astype(np.int32), own_tmpl=owner_tmpl,
+                  own_mass=own_mass, own_moi=own_moi,
+                  sph_owner=sph_owner.astype(np.int32), sph_comp=comp.astype(np.int32),
+                  sph_local=sph_local, sph_rad=sph_rad, sph_mat=sph_mat,
+                  tmpl_sph0=np.asarray(tmpl_sph0, dtype=np.int32), tmpl_local=tmpl_local,
+                  **walls, **mats,
+                  gravity=np.asarray(gravity, dtype=np.float64), dt=float(dt),
+                  margin=float(margin), domain_lo=snap_pos(domain_lo),
+                  domain_hi=snap_pos(domain_hi),
+                  X=snap_pos(X), q=np.asarray(q, dtype=np.float64),
+                  V=f32(V), W=f32(W), name=name, meta=dict(meta or {}))
+
+
+def lattice(counts, spacing, origin, n_take=None, order="zyx"):
+    """Lattice sites filled bottom layer first (z slowest, x fastest)."""
+    nx, ny, nz = counts
+    iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    pts = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], 1).astype(np.float64)
+    pts = np.asarray(origin) + pts * spacing
+    if n_take is not None:
+        pts = pts[:n_take]
+    return pts
+
+
+# --------------------------------------------------------------------------
+# the benchmark configurations
+# --------------------------------------------------------------------------
+
+def config0(seed=0):
+    """1,000 monodisperse spheres (r = 5 mm) on a jittered 10^3 lattice with
+    12 mm spacing inside a 0.2 m box of six planes; N(0, 0.1 m/s) velocities;
+    dt = 1e-5 s, 2,000 steps; detection every step."""
+    rng = np.random.default_rng(seed)
+    n = 1000
+    r = 0.005
+    base = lattice((10, 10, 10), 0.012, -4.5 * 0.012 * np.ones(3))
+    jit = rng.uniform(-0.001, 0.001, size=(n, 3))
+    V = rng.normal(0.0, 0.1, size=(n, 3))
+    lo, hi = -0.1 * np.ones(3), 0.1 * np.ones(3)
+    return assemble(np.full(n, -1), base + jit, _qid(n), V, np.zeros((n, 3)), [], r, None,
+                    box_walls(lo, hi), materials(), (0, 0, -9.81), 1e-5, 0.0, lo, hi,
+                    name="config0", meta=dict(steps=2000, seed=seed))
+
+
+def config1(seed=0, n=1_000_000):
+    """Polydisperse spheres r ~ U(2,3) mm on a jittered lattice (7.5 mm
+    spacing, bottom layers first) in a 0.6 x 0.6 x 1.2 m box, released from
+    rest; dt = 5e-6 s; margin 0.1 r_min = 0.2 mm."""
+    rng = np.random.default_rng(seed)
+    s = 0.0075
+    counts = (80, 80, 160)
+    if n > counts[0] * counts[1] * counts[2]:
+        raise ValueError("config1 lattice holds at most 1,024,000 spheres")
+    base = lattice(counts, s, 0.5 * s * np.ones(3), n_take=n)
+    rad = rng.uniform(0.002, 0.003, size=n)
+    jit = rng.uniform(-0.0007, 0.0007, size=(n, 3))
+    lo, hi = np.zeros(3), np.array([0.6, 0.6, 1.2])
+    return assemble(np.full(n, -1), base + jit, _qid(n), np.zeros((n, 3)), np.zeros((n, 3)),
+                    [], rad, None, box_walls(lo, hi), materials(), (0, 0, -9.81), 5e-6,
+                    0.0002, lo, hi, name="config1", meta=dict(steps=5000, seed=seed, k=10))
+
+
+def config2(seed=0, n_tri=900_000, n_penta=100_000):
+    """Tri-sphere clumps (r = 3 mm, 2 mm circumradius) and five-sphere clumps
+    (tetrahedron + centre, r = 2.5 mm, 2.5 mm circumradius) with uniform
+    random orientations on a 10.5 mm lattice in a 1.0 x 1.0 x 1.2 m box; the
+    -x wall is a plate pushing at +0.1 m/s; dt = 5e-6 s."""
+    rng = np.random.default_rng(seed)
+    n = n_tri + n_penta
+    s = 0.0105
+    counts = (95, 95, 111)
+    if n > counts[0] * counts[1] * counts[2]:
+        raise ValueError("config2 lattice too small")
+    base = lattice(counts, s, 0.5 * s * np.ones(3) + np.array([0.0, 0.0, 0.0]), n_take=n)
+    jit = rng.uniform(-0.0002, 0.0002, size=(n, 3))
+    q = random_quaternions(rng, n)
+    types = np.r_[np.zeros(n_tri, np.int32), np.ones(n_penta, np.int32)]
+    types = types[rng.permutation(n)]
+    lo, hi = np.zeros(3), np.array([1.0, 1.0, 1.2])
+    walls = box_walls(lo, hi, moving={0: (0.1, 0.0, 0.0)})
+    return assemble(types, base + jit, q, np.zeros((n, 3)), np.zeros((n, 3)),
+                    [tri_template(0.003, 0.002), penta_template(0.0025, 0.0025)], 0.0,
+                    [0, 0], walls, materials(), (0, 0, -9.81), 5e-6, 0.00025, lo, hi,
+                    name="config2", meta=dict(steps=5000, seed=seed, k=10))
+
+
+def config3(seed=7, n=8_000_000):
+    """Granular column: lognormal radii (median 3 mm, sigma 0.25, clipped to
+    [1.5, 6] mm) on a 12.5 mm lattice in a 2 x 2 m footprint, released onto
+    a floor inside far side walls; dt = 5e-6 s; margin 0.15 mm."""
+    rng = np.random.default_rng(seed)
+    s = 0.0125
+    per = 160
+    layers = -(-n // (per * per))
+    base = lattice((per, per, layers), s, np.array([-1.0 + 0.5 * s, -1.0 + 0.5 * s, 0.5 * s]),
+                   n_take=n)
+    rad = np.clip(0.003 * np.exp(0.25 * rng.standard_normal(n)), 0.0015, 0.006)
+    jit = rng.uniform(-0.0002, 0.0002, size=(n, 3))
+    top = base[:, 2].max() + 0.02
+    lo, hi = np.array([-5.0, -5.0, 0.0]), np.array([5.0, 5.0, max(top, 1.0)])
+    walls = concat_walls(plane(lo, (0, 0, 1)), plane((-5.0, 0, 0), (1, 0, 0)),
+                         plane((5.0, 0, 0), (-1, 0, 0)), plane((0, -5.0, 0), (0, 1, 0)),
+                         plane((0, 5.0, 0), (0, -1, 0)))
+    lo_dom = np.array([-1.25, -1.25, 0.0])
+    hi_dom = np.array([1.25, 1.25, top])
+    return assemble(np.full(n, -1), base + jit, _qid(n), np.zeros((n, 3)), np.zeros((n, 3)),
+                    [], rad, None, walls, materials(), (0, 0, -9.81), 5e-6, 0.00015,
+                    lo_dom, hi_dom, name="config3", meta=dict(steps=20000, seed=seed))
+
+
+def _qid(n):
+    q = np.zeros((n, 4))
+    q[:, 0] = 1.0
+    return q
+
+
+def small_spheres(seed, n=200, box=0.05, r=(0.002, 0.003), vel=0.2, walls=True, gravity=(0, 0, -9.81),
+                  dt=5e-6, margin=0.0002, mats=None, gap=0.0002, jitter=0.0008):
+    """A small random sphere cloud for parity tests (jittered lattice; with
+    the default gap and jitter neighbours start overlapping)."""
+    rng = np.random.default_rng(seed)
+    side = int(math.ceil(n ** (1 / 3)))
+    s = 2 * r[1] + gap
+    base = lattice((side, side, side), s, -0.5 * (side - 1) * s * np.ones(3), n_take=n)
+    rad = rng.uniform(r[0], r[1], size=n)
+    jit = rng.uniform(-jitter, jitter, size=(n, 3))
+    V = rng.normal(0.0, vel, size=(n, 3))
+    Wb = rng.normal(0.0, 20.0, size=(n, 3))
+    half = max(box, 0.5 * side * s + 0.004)
+    lo, hi = -half * np.ones(3), half * np.ones(3)
+    w = box_walls(lo, hi) if walls else concat_walls()
+    return assemble(np.full(n, -1), base + jit, _qid(n), V, Wb, [], rad, None, w,
+                    mats or materials(), gravity, dt, margin, lo, hi, name=f"small_spheres{seed}")
+
+
+def small_clumps(seed, n=120, vel=0.2, walls=True, gravity=(0, 0, -9.81), dt=5e-6, margin=0.0002,
+                 with_cylinder=False, with_singles=True, spacing=0.0095, jitter=0.0004):
+    """Mixed tri-sphere clumps, five-sphere clumps and single spheres (with
+    the default spacing neighbouring clumps can start overlapping)."""
+    rng = np.random.default_rng(seed)
+    side = int(math.ceil(n ** (1 / 3)))
+    s = spacing
+    base = lattice((side, side, side), s, -0.5 * (side - 1) * s * np.ones(3), n_take=n)
+    jit = rng.uniform(-jitter, jitter, size=(n, 3))
+    q = random_quaternions(rng, n)
+    V = rng.normal(0.0, vel, size=(n, 3))
+    Wb = rng.normal(0.0, 20.0, size=(n, 3))
+    types = rng.integers(-1 if with_singles else 0, 2, size=n).astype(np.int32)
+    q[types < 0] = np.array([1.0, 0, 0, 0])
+    half = 0.5 * side * s + 0.006
+    lo, hi = -half * np.ones(3), half * np.ones(3)
+    ws = [box_walls(lo, hi, moving={0: (0.1, 0.0, 0.0)})] if walls else []
+    if with_cylinder:
+        ws.append(cylinder((0.0, 0.0, hi[2] - 0.004), (0, 1, 0), 0.01, 0.6 * half, vel=(0.2, 0, 0),
+                           omega=(0, 20.0, 0)))
+    return assemble(types, base + jit, q, V, Wb,
+                    [tri_template(0.003, 0.002), penta_template(0.0025, 0.0025)], 0.0025,
+                    [0, 0], concat_walls(*ws), materials(), gravity, dt, margin, lo, hi,
+                    name=f"small_clumps{seed}")
