@@ -1,0 +1,1171 @@
+// Host side of the DEM library: context, workspace layout inside one
+// caller-owned device buffer, the delayed contact-detection schedule on two
+// HIP streams (paper Sec. 2.1), and the C ABI declared in include/dem.h.
+//
+// Schedule (FIXED / LEARNED): a work order at step s copies the owner state
+// into a snapshot on the dynamics stream, records an event, and the
+// detection stream builds the next active set from the snapshot into the
+// buffer not in use.  The dynamics stream adopts it at the deterministic
+// step s + lambda (waiting on the detection event only there), remaps the
+// contact history from the set in use, and carries on.  Because adoption
+// happens at a fixed step, the trajectory does not depend on timing.
+#include "dem_device.h"
+#include "../../include/dem.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+struct dem_ctx {
+    std::string err;
+    dem_params P;
+    int64_t No = 0, Ns = 0;
+    int32_t W = 0, T = 0, nmat = 0, ncomp = 0;
+    bool has_clumps = false;
+    std::vector<OwnerAux> aux;
+    std::vector<uint32_t> sph0;
+    std::vector<SphRec> sph;
+    std::vector<float> tpos;
+    std::vector<WallDev> walls;
+    std::vector<MatPair> mat;
+    std::vector<float> mass;
+    std::vector<int32_t> tmpl;
+    double rmax = 0.0;
+    Grid grid{};
+    Grid fgrid{};
+    Origin org{};
+    double bin_size = 0.0;
+    int sort_bits = 0;
+    // binding
+    bool bound = false;
+    char *ws = nullptr;
+    int64_t ws_bytes = 0, cap = 0;
+    OwnerRec *rec = nullptr, *snap_rec = nullptr;
+    double *q = nullptr, *snap_q = nullptr;
+    OwnerAux *d_aux = nullptr;
+    uint32_t *d_sph0 = nullptr;
+    SphRec *d_sph = nullptr;
+    float *d_tpos = nullptr;
+    WallDev *d_walls = nullptr;
+    MatPair *d_mat = nullptr;
+    AcsBuf acs[2]{};
+    StepBufs sb{};
+    CdWork cdK{}, cdD{};
+    DevCounters *ctr = nullptr;
+    DevCounters *h_ctr = nullptr;
+    // learned interval
+    float *d_mlp = nullptr;
+    float *d_feat = nullptr, *d_pred = nullptr;
+    uint32_t *d_cellmap = nullptr;    // feature cell of each owner [No]
+    uint32_t *d_fraw = nullptr;       // raw per-cell accumulators [16 ncell]
+    uint32_t *d_fflag = nullptr, *d_fpos = nullptr, *d_fids = nullptr;
+    uint32_t *d_lab_start = nullptr, *d_lab_j = nullptr;   // label set (training logs)
+    int64_t ncell_cap = 0;
+    int64_t snap_step = 0;
+    std::vector<float> mlp;
+    bool mlp_set = false;
+    float *h_pred = nullptr;
+    // schedule
+    int64_t step = 0;
+    int cur = 0;
+    bool sched_init = false;
+    bool pending = false;
+    int64_t pend_swap = 0, next_wo = 0, last_wo = 0;
+    int pend_buf = 1;
+    hipEvent_t ev_wo = nullptr, ev_cd = nullptr;
+    int64_t n_wo = 0;
+    double interval_sum = 0.0;
+};
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);              \
+            return DEM_ERR_HIP;                                                        \
+        }                                                                              \
+    } while (0)
+
+#define ARGCHK(cond, msg)                                                              \
+    do {                                                                               \
+        if (!(cond)) {                                                                 \
+            ctx->err = (msg);                                                          \
+            return DEM_ERR_ARG;                                                        \
+        }                                                                              \
+    } while (0)
+
+namespace {
+
+// Carves aligned sub-buffers out of the caller's workspace (base == nullptr:
+// only measure).
+struct Carver {
+    char *base;
+    int64_t off = 0;
+    explicit Carver(char *b) : base(b) {}
+    template <typename T>
+    T *take(int64_t n)
+    {
+        off = (off + 255) & ~int64_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += (int64_t)sizeof(T) * std::max<int64_t>(n, 1);
+        return p;
+    }
+};
+
+int64_t partial_elems(const dem_ctx *ctx)
+{
+    int64_t n = std::max<int64_t>(ctx->Ns + 1, (int64_t)ctx->grid.nbins + 1);
+    n = std::max<int64_t>(n, radix_hist_elems(ctx->Ns));
+    return scan_tmp_elems(n) + 16;
+}
+
+void carve_cd(Carver &c, const dem_ctx *ctx, CdWork &w)
+{
+    int64_t ns = ctx->Ns;
+    w.keys = c.take<uint32_t>(ns);
+    w.vals = c.take<uint32_t>(ns);
+    w.keys_alt = c.take<uint32_t>(ns);
+    w.vals_alt = c.take<uint32_t>(ns);
+    w.cand_tmp = c.take<Cand>(ns);
+    w.cand = c.take<Cand>(ns);
+    w.cell_count = c.take<uint32_t>((int64_t)ctx->grid.nbins + 1);
+    w.cell_start = c.take<uint32_t>((int64_t)ctx->grid.nbins + 1);
+    w.count = c.take<uint32_t>(ns + 1);
+    w.hist = c.take<uint32_t>(radix_hist_elems(ns));
+    w.partials = c.take<uint32_t>(partial_elems(ctx));
+    w.sort_bits = ctx->sort_bits;
+}
+
+void carve(Carver &c, dem_ctx *ctx, int64_t cap)
+{
+    int64_t No = ctx->No, Ns = ctx->Ns;
+    ctx->rec = c.take<OwnerRec>(No);
+    ctx->snap_rec = c.take<OwnerRec>(No);
+    ctx->q = c.take<double>(4 * No);
+    ctx->snap_q = c.take<double>(4 * No);
+    ctx->d_aux = c.take<OwnerAux>(No);
+    ctx->d_sph0 = c.take<uint32_t>(No + 1);
+    ctx->d_sph = c.take<SphRec>(Ns);
+    ctx->d_tpos = c.take<float>(4 * std::max(ctx->ncomp, 1));
+    ctx->d_walls = c.take<WallDev>(std::max(ctx->W, 1));
+    ctx->d_mat = c.take<MatPair>((int64_t)ctx->nmat * ctx->nmat);
+    for (int b = 0; b < 2; ++b) {
+        AcsBuf &a = ctx->acs[b];
+        a.start = c.take<uint32_t>(Ns + 1);
+        a.j = c.take<uint32_t>(cap);
+        a.hx = c.take<float>(cap);
+        a.hy = c.take<float>(cap);
+        a.hz = c.take<float>(cap);
+        a.bstart = c.take<uint32_t>(Ns + 1);
+        a.bidx = c.take<uint32_t>(cap);
+        a.bcur = c.take<uint32_t>(Ns + 1);
+    }
+    ctx->sb.aF = c.take<float>(3 * Ns);
+    ctx->sb.aT = c.take<float>(3 * Ns);
+    ctx->sb.bF = c.take<float>(3 * cap);
+    ctx->sb.bT = c.take<float>(3 * cap);
+    ctx->sb.Fo = c.take<float>(3 * No);
+    ctx->sb.To = c.take<float>(3 * No);
+    ctx->sb.cap = cap;
+    carve_cd(c, ctx, ctx->cdK);
+    carve_cd(c, ctx, ctx->cdD);
+    ctx->ctr = c.take<DevCounters>(1);
+    ctx->ncell_cap = (int64_t)ctx->fgrid.nbins;
+    ctx->d_mlp = c.take<float>(DEM_MLP_NPARAM + 3);
+    ctx->d_cellmap = c.take<uint32_t>(No);
+    ctx->d_fraw = c.take<uint32_t>(16 * ctx->ncell_cap);
+    ctx->d_fflag = c.take<uint32_t>(ctx->ncell_cap + 1);
+    ctx->d_fpos = c.take<uint32_t>(ctx->ncell_cap + 1);
+    ctx->d_fids = c.take<uint32_t>(ctx->ncell_cap + 1);
+    ctx->d_feat = c.take<float>(DEM_MLP_NFEAT * ctx->ncell_cap);
+    ctx->d_pred = c.take<float>(ctx->ncell_cap + 4);
+    ctx->d_lab_start = c.take<uint32_t>(Ns + 1);
+    ctx->d_lab_j = c.take<uint32_t>(cap);
+}
+
+DetectArgs detect_args(const dem_ctx *ctx, bool snapshot, double margin, int64_t step)
+{
+    DetectArgs a;
+    a.rec = snapshot ? ctx->snap_rec : ctx->rec;
+    a.q = snapshot ? ctx->snap_q : ctx->q;
+    a.aux = ctx->d_aux;
+    a.sph = ctx->d_sph;
+    a.tpos = ctx->d_tpos;
+    a.walls = ctx->d_walls;
+    a.n_walls = ctx->W;
+    a.n_spheres = ctx->Ns;
+    a.grid = ctx->grid;
+    a.org = ctx->org;
+    a.margin = margin;
+    a.h = ctx->P.dt;
+    a.step = step;
+    return a;
+}
+
+DynArgs dyn_args(const dem_ctx *ctx, int64_t step)
+{
+    DynArgs a;
+    a.rec = ctx->rec;
+    a.q = ctx->q;
+    a.aux = ctx->d_aux;
+    a.own_sph0 = ctx->d_sph0;
+    a.sph = ctx->d_sph;
+    a.tpos = ctx->d_tpos;
+    a.walls = ctx->d_walls;
+    a.mat = ctx->d_mat;
+    a.n_mat = ctx->nmat;
+    a.n_walls = ctx->W;
+    a.n_owners = ctx->No;
+    a.n_spheres = ctx->Ns;
+    a.org = ctx->org;
+    a.h = ctx->P.dt;
+    for (int k = 0; k < 3; ++k) a.g[k] = (float)ctx->P.gravity[k];
+    a.v_err2 = (float)(ctx->P.v_error_out * ctx->P.v_error_out);
+    a.step = step;
+    a.has_clumps = ctx->has_clumps ? 1 : 0;
+    return a;
+}
+
+inline hipStream_t S(dem_stream s) { return reinterpret_cast<hipStream_t>(s); }
+
+dem_status read_counters(dem_ctx *ctx, hipStream_t s)
+{
+    HIPCHK(hipMemcpyAsync(ctx->h_ctr, ctx->ctr, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return DEM_OK;
+}
+
+void host_rot(const double *q, double *R)
+{
+    Mat3d M = rot_from_q(q[0], q[1], q[2], q[3]);
+    for (int k = 0; k < 9; ++k) R[k] = M.m[k];
+}
+
+// Empty active set in buffer b (all rows empty, no B lists).
+void clear_set(dem_ctx *ctx, int b, hipStream_t s)
+{
+    launch_fill_u32(ctx->acs[b].start, ctx->Ns + 1, 0u, s);
+    launch_fill_u32(ctx->acs[b].bstart, ctx->Ns + 1, 0u, s);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *dem_last_error(const dem_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : "null context";
+}
+
+dem_status dem_create(const dem_params *params, const dem_materials *mats, const dem_templates *tmpls,
+                      const dem_walls *walls, const dem_bodies *bodies, dem_ctx **out)
+{
+    if (!out) return DEM_ERR_ARG;
+    *out = nullptr;
+    dem_ctx *ctx = new dem_ctx();
+    auto fail = [&](const std::string &m) {
+        ctx->err = m;
+        *out = ctx;   // hand the context back so the caller can read the message
+        return DEM_ERR_ARG;
+    };
+    if (!params || !mats || !bodies) return fail("params, materials and bodies are required");
+    ctx->P = *params;
+    const dem_params &P = ctx->P;
+    if (!(P.dt > 0.0)) return fail("dt must be positive");
+    if (!(P.margin >= 0.0)) return fail("margin must be >= 0");
+    if (P.cd_mode < 0 || P.cd_mode > 2) return fail("unknown cd_mode");
+    if (P.cd_mode != DEM_CD_EVERY) {
+        if (P.cd_interval < 1) return fail("cd_interval must be >= 1");
+        if (P.cd_latency < 0 || P.cd_latency > P.cd_interval) return fail("need 0 <= cd_latency <= cd_interval");
+    }
+    if (P.cd_interval_max < 1) ctx->P.cd_interval_max = std::max(P.cd_interval, 1) * 16;
+    ctx->No = bodies->n_owners;
+    ctx->Ns = bodies->n_spheres;
+    if (ctx->No < 1 || ctx->Ns < ctx->No) return fail("need n_spheres >= n_owners >= 1");
+    if (ctx->Ns >= (int64_t)0xffffff00) return fail("too many spheres for 32-bit ids");
+    ctx->nmat = mats->n;
+    if (ctx->nmat < 1 || ctx->nmat > 256) return fail("material count must be 1..256");
+    ctx->W = walls ? walls->n : 0;
+    ctx->T = tmpls ? tmpls->n : 0;
+    // materials: pairwise constants of Sec. 4.2.1 (E*, G*, beta, mu)
+    for (int a = 0; a < ctx->nmat; ++a) {
+        if (!(mats->E[a] > 0.0) || !(mats->nu[a] > -1.0 && mats->nu[a] < 0.5))
+            return fail("material E must be > 0 and -1 < nu < 0.5");
+    }
+    ctx->mat.resize((size_t)ctx->nmat * ctx->nmat);
+    for (int a = 0; a < ctx->nmat; ++a)
+        for (int b = 0; b < ctx->nmat; ++b) {
+            double Ea = mats->E[a], na = mats->nu[a], Eb = mats->E[b], nb = mats->nu[b];
+            double Es = 1.0 / ((1.0 - na * na) / Ea + (1.0 - nb * nb) / Eb);
+            double Gs = 1.0 / (2.0 * (2.0 - na) * (1.0 + na) / Ea + 2.0 * (2.0 - nb) * (1.0 + nb) / Eb);
+            double cor = mats->cor[a * ctx->nmat + b];
+            double le = (cor < 1e-12) ? std::log(1e-12) : std::log(cor);
+            double beta = le / std::sqrt(le * le + M_PI * M_PI);
+            MatPair mp;
+            mp.Estar = (float)Es;
+            mp.Gstar = (float)Gs;
+            mp.beta = (float)beta;
+            mp.mu = (float)mats->mu[a * ctx->nmat + b];
+            ctx->mat[(size_t)a * ctx->nmat + b] = mp;
+        }
+    // templates
+    std::vector<int32_t> tb(ctx->T + 1, 0);
+    if (ctx->T > 0) {
+        for (int t = 0; t <= ctx->T; ++t) tb[t] = tmpls->sph_begin[t];
+        ctx->ncomp = tb[ctx->T];
+        ctx->tpos.resize(4 * (size_t)std::max(ctx->ncomp, 1), 0.0f);
+        for (int k = 0; k < ctx->ncomp; ++k)
+            for (int d = 0; d < 3; ++d) {
+                double v = tmpls->sph_pos[3 * k + d];
+                float f = (float)v;
+                if ((double)f != v) return fail("template positions must be float32-representable");
+                ctx->tpos[4 * k + d] = f;
+            }
+    } else {
+        ctx->tpos.assign(4, 0.0f);
+    }
+    // owners and spheres
+    ctx->aux.resize(ctx->No);
+    ctx->sph0.resize(ctx->No + 1);
+    ctx->mass.resize(ctx->No);
+    ctx->tmpl.resize(ctx->No);
+    ctx->sph.resize(ctx->Ns);
+    for (int64_t o = 0; o <= ctx->No; ++o) ctx->sph0[o] = (uint32_t)bodies->own_sph0[o];
+    if (ctx->sph0[0] != 0 || (int64_t)ctx->sph0[ctx->No] != ctx->Ns) return fail("own_sph0 must span all spheres");
+    for (int64_t o = 0; o < ctx->No; ++o) {
+        int32_t t = bodies->own_tmpl[o];
+        uint32_t s0 = ctx->sph0[o], s1 = ctx->sph0[o + 1];
+        if (s1 <= s0) return fail("every owner needs at least one sphere");
+        if (t >= ctx->T) return fail("owner template index out of range");
+        if (t < 0 && s1 - s0 != 1) return fail("a single-sphere owner must have exactly one sphere");
+        if (t >= 0 && (int)(s1 - s0) != tb[t + 1] - tb[t]) return fail("owner sphere count differs from its template");
+        if (t >= 0) ctx->has_clumps = true;
+        double m = bodies->own_mass[o];
+        if (!(m > 0.0)) return fail("owner mass must be positive");
+        ctx->mass[o] = (float)m;
+        ctx->tmpl[o] = t;
+        OwnerAux a;
+        for (int d = 0; d < 3; ++d) {
+            double I = bodies->own_moi[3 * o + d];
+            if (!(I > 0.0)) return fail("owner inertia must be positive");
+            a.inv_moi[d] = (float)(1.0 / (double)(float)I);
+        }
+        if (t < 0) {
+            a.inv_moi[1] = a.inv_moi[0];
+            a.inv_moi[2] = a.inv_moi[0];
+        }
+        a.tmpl = t;
+        ctx->aux[o] = a;
+        for (uint32_t s = s0; s < s1; ++s) {
+            SphRec r;
+            r.owner = (uint32_t)o;
+            double rad = bodies->sph_rad[s];
+            if (!(rad > 0.0)) return fail("sphere radius must be positive");
+            r.rad = (float)rad;
+            int32_t mt = bodies->sph_mat[s];
+            if (mt < 0 || mt >= ctx->nmat) return fail("sphere material out of range");
+            r.mat = (uint32_t)mt;
+            if (t < 0) {
+                r.tcomp = DEM_NO_COMP;
+            } else {
+                int32_t comp = bodies->sph_comp[s];
+                if (comp < 0 || comp >= tb[t + 1] - tb[t]) return fail("sphere component out of range");
+                r.tcomp = (uint32_t)(tb[t] + comp);
+            }
+            ctx->sph[s] = r;
+            ctx->rmax = std::max(ctx->rmax, rad);
+        }
+    }
+    // walls
+    ctx->walls.resize(std::max(ctx->W, 1));
+    for (int w = 0; w < ctx->W; ++w) {
+        WallDev d{};
+        d.type = walls->type[w];
+        if (d.type != DEM_WALL_PLANE && d.type != DEM_WALL_CYLINDER) return fail("unknown wall type");
+        for (int k = 0; k < 8; ++k) d.geom[k] = walls->geom[8 * w + k];
+        for (int k = 0; k < 3; ++k) {
+            d.vel[k] = walls->vel ? walls->vel[3 * w + k] : 0.0;
+            d.omega[k] = walls->omega ? walls->omega[3 * w + k] : 0.0;
+        }
+        d.mat = walls->mat[w];
+        if (d.mat < 0 || d.mat >= ctx->nmat) return fail("wall material out of range");
+        ctx->walls[w] = d;
+    }
+    // bins: edge >= 2 (r_max + m) with a small safety factor
+    double b = 2.0 * (ctx->rmax + P.margin) * (1.0 + 1e-6) + 1e-12;
+    ctx->bin_size = b;
+    uint64_t nb = 1;
+    int dims[3];
+    for (int k = 0; k < 3; ++k) {
+        double lo = P.domain_lo[k] - b, hi = P.domain_hi[k] + b;
+        if (!(hi > lo)) return fail("domain_hi must exceed domain_lo");
+        int64_t nint = (int64_t)std::ceil((hi - lo) / b);
+        if (nint < 1) nint = 1;
+        dims[k] = (int)std::min<int64_t>(nint + 2, 1 << 30);
+        ctx->grid.lo[k] = lo;
+        nb *= (uint64_t)dims[k];
+    }
+    if (nb >= 0xfffffff0ull) return fail("domain too large for the bin grid (more than 2^32 bins)");
+    ctx->grid.nx = dims[0];
+    ctx->grid.ny = dims[1];
+    ctx->grid.nz = dims[2];
+    ctx->grid.nbins = (uint32_t)nb;
+    ctx->grid.inv_b = 1.0 / b;
+    int bits = 1;
+    while (bits < 32 && (1ull << bits) < nb) ++bits;
+    ctx->sort_bits = bits;
+    // feature cells for the learned interval: cubes of 4 bins
+    ctx->fgrid = ctx->grid;
+    {
+        uint64_t fn = 1;
+        int fd[3] = {dims[0], dims[1], dims[2]};
+        for (int k = 0; k < 3; ++k) {
+            fd[k] = (dims[k] + 3) / 4;
+            fn *= (uint64_t)fd[k];
+        }
+        ctx->fgrid.nx = fd[0];
+        ctx->fgrid.ny = fd[1];
+        ctx->fgrid.nz = fd[2];
+        ctx->fgrid.nbins = (uint32_t)fn;
+        ctx->fgrid.inv_b = 1.0 / (4.0 * b);
+    }
+    // voxel origin: a multiple of the voxel edge below the grid
+    for (int k = 0; k < 3; ++k) {
+        double o = std::floor((ctx->grid.lo[k] - b) * DEM_VOXEL_INV) * DEM_VOXEL_SIZE;
+        ctx->org.o[k] = o;
+        if (P.domain_hi[k] + 2 * b - o >= 127.0) return fail("domain extent must stay below 127 m");
+    }
+    *out = ctx;
+    return DEM_OK;
+}
+
+dem_status dem_workspace_size(const dem_ctx *cctx, int64_t contact_capacity, int64_t *bytes)
+{
+    dem_ctx *ctx = const_cast<dem_ctx *>(cctx);
+    if (!ctx || !bytes) return DEM_ERR_ARG;
+    ARGCHK(contact_capacity >= 1 && contact_capacity < (int64_t)0xfffffff0, "contact capacity must be 1..2^32-16");
+    dem_ctx tmp = *ctx;
+    Carver c(nullptr);
+    carve(c, &tmp, contact_capacity);
+    *bytes = c.off + 256;
+    return DEM_OK;
+}
+
+dem_status dem_bind(dem_ctx *ctx, void *device_workspace, int64_t bytes, int64_t contact_capacity)
+{
+    if (!ctx) return DEM_ERR_ARG;
+    int64_t need = 0;
+    dem_status st = dem_workspace_size(ctx, contact_capacity, &need);
+    if (st != DEM_OK) return st;
+    ARGCHK(device_workspace != nullptr, "workspace pointer is NULL");
+    ARGCHK(((uintptr_t)device_workspace & 255) == 0, "workspace must be 256-byte aligned");
+    ARGCHK(bytes >= need, "workspace smaller than dem_workspace_size");
+    ctx->ws = reinterpret_cast<char *>(device_workspace);
+    ctx->ws_bytes = bytes;
+    ctx->cap = contact_capacity;
+    Carver c(ctx->ws);
+    carve(c, ctx, contact_capacity);
+    if (!ctx->h_ctr) HIPCHK(hipHostMalloc((void **)&ctx->h_ctr, sizeof(DevCounters)));
+    if (!ctx->h_pred) HIPCHK(hipHostMalloc((void **)&ctx->h_pred, 64));
+    if (!ctx->ev_wo) HIPCHK(hipEventCreateWithFlags(&ctx->ev_wo, hipEventDisableTiming));
+    if (!ctx->ev_cd) HIPCHK(hipEventCreateWithFlags(&ctx->ev_cd, hipEventDisableTiming));
+    HIPCHK(hipMemcpy(ctx->d_aux, ctx->aux.data(), sizeof(OwnerAux) * ctx->No, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_sph0, ctx->sph0.data(), sizeof(uint32_t) * (ctx->No + 1), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_sph, ctx->sph.data(), sizeof(SphRec) * ctx->Ns, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_tpos, ctx->tpos.data(), sizeof(float) * ctx->tpos.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_walls, ctx->walls.data(), sizeof(WallDev) * ctx->walls.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_mat, ctx->mat.data(), sizeof(MatPair) * ctx->mat.size(), hipMemcpyHostToDevice));
+    DevCounters z{};
+    HIPCHK(hipMemcpy(ctx->ctr, &z, sizeof(DevCounters), hipMemcpyHostToDevice));
+    if (ctx->mlp_set)
+        HIPCHK(hipMemcpy(ctx->d_mlp, ctx->mlp.data(), sizeof(float) * DEM_MLP_NPARAM, hipMemcpyHostToDevice));
+    clear_set(ctx, 0, nullptr);
+    clear_set(ctx, 1, nullptr);
+    HIPCHK(hipDeviceSynchronize());
+    ctx->cur = 0;
+    ctx->sched_init = false;
+    ctx->pending = false;
+    ctx->bound = true;
+    return DEM_OK;
+}
+
+dem_status dem_set_state(dem_ctx *ctx, const double *X, const double *q, const float *v, const float *w,
+                         int64_t step, dem_stream stream)
+{
+    if (!ctx) return DEM_ERR_ARG;
+    if (!ctx->bound) {
+        ctx->err = "dem_set_state before dem_bind";
+        return DEM_ERR_STATE;
+    }
+    ARGCHK(X && q && v && w, "X, q, v, w are required");
+    hipStream_t s = S(stream);
+    std::vector<OwnerRec> rec(ctx->No);
+    std::vector<double> qd(4 * ctx->No);
+    for (int64_t o = 0; o < ctx->No; ++o) {
+        OwnerRec r{};
+        uint32_t iv[3];
+        for (int k = 0; k < 3; ++k) {
+            ARGCHK(std::isfinite(X[3 * o + k]), "non-finite position");
+            encode_axis(X[3 * o + k], ctx->org.o[k], &iv[k], &r.off[k]);
+        }
+        r.vox = pack_vox(iv[0], iv[1], iv[2]);
+        double qq[4] = {q[4 * o], q[4 * o + 1], q[4 * o + 2], q[4 * o + 3]};
+        double nn = std::sqrt(qq[0] * qq[0] + qq[1] * qq[1] + qq[2] * qq[2] + qq[3] * qq[3]);
+        ARGCHK(nn > 0.5 && nn < 2.0, "quaternions must be (close to) unit length");
+        for (int k = 0; k < 3; ++k) r.v[k] = v[3 * o + k];
+        if (ctx->tmpl[o] < 0) {
+            double R[9];
+            host_rot(qq, R);
+            for (int k = 0; k < 3; ++k)
+                r.w[k] = (float)((R[3 * k] * w[3 * o] + R[3 * k + 1] * w[3 * o + 1]) + R[3 * k + 2] * w[3 * o + 2]);
+            qd[4 * o] = 1.0;
+            qd[4 * o + 1] = qd[4 * o + 2] = qd[4 * o + 3] = 0.0;
+        } else {
+            for (int k = 0; k < 3; ++k) r.w[k] = w[3 * o + k];
+            for (int k = 0; k < 4; ++k) qd[4 * o + k] = qq[k];
+        }
+        r.mass = ctx->mass[o];
+        rec[o] = r;
+    }
+    HIPCHK(hipMemcpyAsync(ctx->rec, rec.data(), sizeof(OwnerRec) * ctx->No, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->q, qd.data(), sizeof(double) * 4 * ctx->No, hipMemcpyHostToDevice, s));
+    DevCounters z{};
+    HIPCHK(hipMemcpyAsync(ctx->ctr, &z, sizeof(DevCounters), hipMemcpyHostToDevice, s));
+    clear_set(ctx, 0, s);
+    clear_set(ctx, 1, s);
+    HIPCHK(hipStreamSynchronize(s));
+    ctx->step = step;
+    ctx->cur = 0;
+    ctx->sched_init = false;
+    ctx->pending = false;
+    return DEM_OK;
+}
+
+dem_status dem_get_state(dem_ctx *ctx, double *X, double *q, float *v, float *w, int64_t *step,
+                         dem_stream stream)
+{
+    if (!ctx) return DEM_ERR_ARG;
+    if (!ctx->bound) {
+        ctx->err = "dem_get_state before dem_bind";
+        return DEM_ERR_STATE;
+    }
+    hipStream_t s = S(stream);
+    std::vector<OwnerRec> rec(ctx->No);
+    std::vector<double> qd(4 * ctx->No);
+    HIPCHK(hipMemcpyAsync(rec.data(), ctx->rec, sizeof(OwnerRec) * ctx->No, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(qd.data(), ctx->q, sizeof(double) * 4 * ctx->No, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int64_t o = 0; o < ctx->No; ++o) {
+        const OwnerRec &r = rec[o];
+        for (int k = 0; k < 3; ++k) {
+            if (X) X[3 * o + k] = decode_axis(r.vox, r.off[k], ctx->org.o[k], k);
+            if (v) v[3 * o + k] = r.v[k];
+            if (w) w[3 * o + k] = r.w[k];
+        }
+        if (q)
+            for (int k = 0; k < 4; ++k) q[4 * o + k] = qd[4 * o + k];
+    }
+    if (step) *step = ctx->step;
+    return DEM_OK;
+}
+
+dem_status dem_bin(dem_ctx *ctx, dem_stream stream, uint32_t *sorted_keys, uint32_t *sorted_ids)
+{
+    if (!ctx) return DEM_ERR_ARG;
+    if (!ctx->bound) {
+        ctx->err = "dem_bin before dem_bind";
+        return DEM_ERR_STATE;
+    }
+    hipStream_t s = S(stream);
+    DetectArgs a = detect_args(ctx, false, ctx->P.margin, ctx->step);
+    launch_bin(a, ctx->cdD, s);
+    HIPCHK(hipGetLastError());
+    if (sorted_keys || sorted_ids) {
+        if (sorted_keys)
+            HIPCHK(hipMemcpyAsync(sorted_keys, ctx->cdD.keys, 4 * ctx->Ns, hipMemcpyDeviceToHost, s));
+        if (sorted_ids)
+            HIPCHK(hipMemcpyAsync(sorted_ids, ctx->cdD.vals, 4 * ctx->Ns, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    return DEM_OK;
+}
+
+static dem_status detect_now(dem_ctx *ctx, double margin, hipStream_t s, int target)
+{
+    DetectArgs a = detect_args(ctx, false, margin, ctx->step);
+    launch_detect(a, ctx->cdD, ctx->acs[target], ctx->cap, ctx->ctr, target, s);
+    HIPCHK(hipGetLastError());
+    return DEM_OK;
+}
+
+static dem_status adopt(dem_ctx *ctx, int target, hipStream_t s)
+{
+    launch_remap(ctx->acs[ctx->cur], ctx->acs[target], ctx->Ns, ctx->ctr, target, s);
+    HIPCHK(hipGetLastError());
+    ctx->cur = target;
+    return DEM_OK;
+}
+
+dem_status dem_detect_contacts(dem_ctx *ctx, double margin, dem_stream stream, int64_t *n_contacts)
+{
+    if (!ctx) return DEM_ERR_ARG;
+    if (!ctx->bound) {
+        ctx->err = "dem_detect_contacts before dem_bind";
+        return DEM_ERR_STATE;
+    }
+    ARGCHK(margin >= 0.0 && margin <= ctx->P.margin * (1.0 + 1e-12), "margin must be in [0, params.margin]");
+    hipStream_t s = S(stream);
+    int target = 1 - ctx->cur;
+    dem_status st = detect_now(ctx, margin, s, target);
+    if (st != DEM_OK) return st;
+    st = adopt(ctx, target, s);
+    if (st != DEM_OK) return st;
+    ctx->sched_init = false;
+    ctx->pending = false;
+    if (n_contacts) {
+        st = read_counters(ctx, s);
+        if (st != DEM_OK) return st;
+        if (ctx->h_ctr->overflow[target]) {
+            *n_contacts = ctx->h_ctr->required;
+            ctx->err = "contact capacity exceeded";
+            return DEM_ERR_CAPACITY;
+        }
+        *n_contacts = ctx->h_ctr->n_contacts[target];
+    }
+    return DEM_OK;
+}
+
+dem_status dem_forces(dem_ctx *ctx, dem_stream stream)
+{
+    if (!ctx) return DEM_ERR_ARG;
+    if (!ctx->bound) {
+        ctx->err = "dem_forces before dem_bind";
+        return DEM_ERR_STATE;
+    }
+    hipStream_t s = S(stream);
+    DynArgs a = dyn_args(ctx, ctx->step);
+    launch_force(a, ctx->acs[ctx->cur], ctx->sb, ctx->ctr, s);
+    launch_fold_integrate(a, ctx->acs[ctx->cur], ctx->sb, ctx->ctr, 0, s);
+    HIPCHK(hipGetLastError());
+    return DEM_OK;
+}
+
+dem_status dem_get_forces(dem_ctx *ctx, float *F_owner, float *T_owner, float *F_contact, int64_t cap,
+                          dem_stream stream)
+{
+    if (!ctx) return DEM_ERR_ARG;
+    if (!ctx->bound) {
+        ctx->err = "dem_get_forces before dem_bind";
+        return DEM_ERR_STATE;
+    }
+    hipStream_t s = S(stream);
+    dem_status st = read_counters(ctx, s);
+    if (st != DEM_OK) return st;
+    int64_t No = ctx->No;
+    std::vector<float> tmp(3 * No);
+    if (F_owner) {
+        HIPCHK(hipMemcpy(tmp.data(), ctx->sb.Fo, 12 * No, hipMemcpyDeviceToHost));
+        for (int64_t o = 0; o < No; ++o)
+            for (int k = 0; k < 3; ++k) F_owner[3 * o + k] = tmp[k * No + o];
+    }
+    if (T_owner) {
+        HIPCHK(hipMemcpy(tmp.data(), ctx->sb.To, 12 * No, hipMemcpyDeviceToHost));
+        for (int64_t o = 0; o < No; ++o)
+            for (int k = 0; k < 3; ++k) T_owner[3 * o + k] = tmp[k * No + o];
+    }
+    if (F_contact) {
+        int64_t n = ctx->h_ctr->n_contacts[ctx->cur];
+        ARGCHK(cap >= n, "F_contact capacity smaller than the contact count");
+        std::vector<float> b(3 * (size_t)std::max<int64_t>(n, 1));
+        for (int k = 0; k < 3; ++k)
+            if (n) HIPCHK(hipMemcpy(b.data() + k * n, ctx->sb.bF + k * ctx->cap, 4 * n, hipMemcpyDeviceToHost));
+        for (int64_t c = 0; c < n; ++c)
+            for (int k = 0; k < 3; ++k) F_contact[3 * c + k] = -b[k * n + c];
+    }
+    return DEM_OK;
+}
+
+dem_status dem_get_contacts(dem_ctx *ctx, uint64_t *keys, float *hist, int64_t cap, int64_t *n,
+                            dem_stream stream)
+{
+    if (!ctx || !n) return DEM_ERR_ARG;
+    if (!ctx->bound) {
+        ctx->err = "dem_get_contacts before dem_bind";
+        return DEM_ERR_STATE;
+    }
+    hipStream_t s = S(stream);
+    const AcsBuf &a = ctx->acs[ctx->cur];
+    std::vector<uint32_t> start(ctx->Ns + 1);
+    HIPCHK(hipMemcpyAsync(start.data(), a.start, 4 * (ctx->Ns + 1), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int64_t total = start[ctx->Ns];
+    *n = total;
+    if (total > ctx->cap) {
+        ctx->err = "active set overflowed its capacity";
+        return DEM_ERR_CAPACITY;
+    }
+    if (cap < total) {
+        ctx->err = "output capacity smaller than the contact count";
+        return DEM_ERR_CAPACITY;
+    }
+    std::vector<uint32_t> j(std::max<int64_t>(total, 1));
+    std::vector<float> h(3 * (size_t)std::max<int64_t>(total, 1));
+    if (total) {
+        HIPCHK(hipMemcpyAsync(j.data(), a.j, 4 * total, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(h.data(), a.hx, 4 * total, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(h.data() + total, a.hy, 4 * total, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(h.data() + 2 * total, a.hz, 4 * total, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    for (int64_t i = 0; i < ctx->Ns; ++i)
+        for (uint32_t c = start[i]; c < start[i + 1]; ++c) {
+            if (keys) keys[c] = ((uint64_t)i << 32) | (uint64_t)j[c];
+            if (hist)
+                for (int k = 0; k < 3; ++k) hist[3 * (size_t)c + k] = h[k * total + c];
+        }
+    return DEM_OK;
+}
+
+dem_status dem_set_contacts(dem_ctx *ctx, const uint64_t *keys, const float *hist, int64_t n,
+                            dem_stream stream)
+{
+    if (!ctx) return DEM_ERR_ARG;
+    if (!ctx->bound) {
+        ctx->err = "dem_set_contacts before dem_bind";
+        return DEM_ERR_STATE;
+    }
+    ARGCHK(n >= 0 && (n == 0 || keys), "keys required");
+    if (n > ctx->cap) {
+        ctx->err = "more contacts than the bound capacity";
+        return DEM_ERR_CAPACITY;
+    }
+    hipStream_t s = S(stream);
+    std::vector<uint32_t> start(ctx->Ns + 1, 0), j(std::max<int64_t>(n, 1));
+    std::vector<float> h(3 * (size_t)std::max<int64_t>(n, 1), 0.0f);
+    for (int64_t c = 0; c < n; ++c) {
+        uint64_t key = keys[c];
+        int64_t i = (int64_t)(key >> 32), jj = (int64_t)(key & 0xffffffffu);
+        ARGCHK(c == 0 || keys[c - 1] < key, "keys must be strictly ascending");
+        ARGCHK(i < ctx->Ns, "key sphere id out of range");
+        ARGCHK((jj > i && jj < ctx->Ns) || (jj >= ctx->Ns && jj < ctx->Ns + ctx->W), "key partner out of range");
+        start[i + 1]++;
+        j[c] = (uint32_t)jj;
+        if (hist)
+            for (int k = 0; k < 3; ++k) h[k * n + c] = hist[3 * c + k];
+    }
+    for (int64_t i = 0; i < ctx->Ns; ++i) start[i + 1] += start[i];
+    int b = ctx->cur;
+    AcsBuf &a = ctx->acs[b];
+    HIPCHK(hipMemcpyAsync(a.start, start.data(), 4 * (ctx->Ns + 1), hipMemcpyHostToDevice, s));
+    if (n) {
+        HIPCHK(hipMemcpyAsync(a.j, j.data(), 4 * n, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(a.hx, h.data(), 4 * n, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(a.hy, h.data() + n, 4 * n, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(a.hz, h.data() + 2 * n, 4 * n, hipMemcpyHostToDevice, s));
+    }
+    launch_blists(a, ctx->Ns, ctx->cap, ctx->cdD.partials, s);
+    HIPCHK(hipGetLastError());
+    uint32_t nn = (uint32_t)n, zero = 0;
+    HIPCHK(hipMemcpyAsync(&ctx->ctr->n_contacts[b], &nn, 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(&ctx->ctr->overflow[b], &zero, 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ctx->sched_init = false;
+    ctx->pending = false;
+    return DEM_OK;
+}
+
+dem_status dem_count_missing(dem_ctx *ctx, dem_stream stream, int64_t *missing)
+{
+    if (!ctx || !missing) return DEM_ERR_ARG;
+    if (!ctx->bound) {
+        ctx->err = "dem_count_missing before dem_bind";
+        return DEM_ERR_STATE;
+    }
+    hipStream_t s = S(stream);
+    launch_fill_u32(&ctx->ctr->miss, 1, 0u, s);
+    DetectArgs a = detect_args(ctx, false, 0.0, ctx->step);
+    launch_judge(a, ctx->cdD, ctx->acs[ctx->cur], ctx->cap, ctx->ctr, s);
+    HIPCHK(hipGetLastError());
+    dem_status st = read_counters(ctx, s);
+    if (st != DEM_OK) return st;
+    *missing = ctx->h_ctr->miss;
+    return DEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the step loop
+// ---------------------------------------------------------------------------
+int64_t learned_interval(dem_ctx *ctx, hipStream_t s);
+
+static void issue_work_order(dem_ctx *ctx, hipStream_t dyn, hipStream_t kin, int64_t n)
+{
+    ctx->snap_step = n;
+    hipMemcpyAsync(ctx->snap_rec, ctx->rec, sizeof(OwnerRec) * ctx->No, hipMemcpyDeviceToDevice, dyn);
+    if (ctx->has_clumps)
+        hipMemcpyAsync(ctx->snap_q, ctx->q, sizeof(double) * 4 * ctx->No, hipMemcpyDeviceToDevice, dyn);
+    hipEventRecord(ctx->ev_wo, dyn);
+    hipStreamWaitEvent(kin, ctx->ev_wo, 0);
+    int target = 1 - ctx->cur;
+    DetectArgs a = detect_args(ctx, true, ctx->P.margin, n);
+    launch_detect(a, ctx->cdK, ctx->acs[target], ctx->cap, ctx->ctr, target, kin);
+    hipEventRecord(ctx->ev_cd, kin);
+    ctx->pending = true;
+    ctx->pend_buf = target;
+    ctx->pend_swap = n + ctx->P.cd_latency;
+    if (ctx->n_wo > 0) ctx->interval_sum += (double)(n - ctx->last_wo);
+    ctx->last_wo = n;
+    ctx->n_wo++;
+}
+
+dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream kin_, dem_step_stats *stats)
+{
+    if (!ctx) return DEM_ERR_ARG;
+    if (!ctx->bound) {
+        ctx->err = "dem_step before dem_bind";
+        return DEM_ERR_STATE;
+    }
+    ARGCHK(n_steps >= 0, "n_steps must be >= 0");
+    hipStream_t dyn = S(dyn_), kin = kin_ ? S(kin_) : dyn;
+    auto t0 = std::chrono::steady_clock::now();
+    const dem_params &P = ctx->P;
+    int64_t cds = 0, swaps = 0, misses = 0, repairs = 0;
+    const int64_t step0 = ctx->step;
+    dem_status result = DEM_OK;
+    if (ctx->n_wo == 0) ctx->interval_sum = 0.0;
+    for (int64_t t = 0; t < n_steps; ++t) {
+        const int64_t n = ctx->step;
+        if (P.cd_mode == DEM_CD_EVERY) {
+            int target = 1 - ctx->cur;
+            dem_status st = detect_now(ctx, 0.0, dyn, target);
+            if (st != DEM_OK) return st;
+            st = adopt(ctx, target, dyn);
+            if (st != DEM_OK) return st;
+            ++cds;
+            ++swaps;
+        } else {
+            if (!ctx->sched_init) {
+                if (ctx->pending) hipStreamWaitEvent(dyn, ctx->ev_cd, 0);
+                int target = 1 - ctx->cur;
+                dem_status st = detect_now(ctx, P.margin, dyn, target);
+                if (st != DEM_OK) return st;
+                st = adopt(ctx, target, dyn);
+                if (st != DEM_OK) return st;
+                ++cds;
+                ++swaps;
+                ctx->sched_init = true;
+                ctx->pending = false;
+                ctx->last_wo = n;
+                ctx->n_wo = 1;
+                ctx->interval_sum = 0.0;
+                if (P.cd_mode == DEM_CD_LEARNED) {
+                    hipMemcpyAsync(ctx->snap_rec, ctx->rec, sizeof(OwnerRec) * ctx->No, hipMemcpyDeviceToDevice, dyn);
+                    ctx->snap_step = n;
+                }
+                int64_t k = P.cd_mode == DEM_CD_LEARNED ? learned_interval(ctx, dyn) : P.cd_interval;
+                ctx->next_wo = n + k;
+            } else {
+                int64_t k_next = -1;
+                if (P.cd_latency == 0 && n == ctx->next_wo) {
+                    k_next = P.cd_mode == DEM_CD_LEARNED ? learned_interval(ctx, dyn) : P.cd_interval;
+                    issue_work_order(ctx, dyn, kin, n);
+                    ++cds;
+                }
+                bool swap_due = ctx->pending && n == ctx->pend_swap;
+                if (swap_due) hipStreamWaitEvent(dyn, ctx->ev_cd, 0);
+                if (P.judge) {
+                    int cand = swap_due ? ctx->pend_buf : ctx->cur;
+                    launch_fill_u32(&ctx->ctr->miss, 1, 0u, dyn);
+                    DetectArgs a = detect_args(ctx, false, 0.0, n);
+                    launch_judge(a, ctx->cdD, ctx->acs[cand], ctx->cap, ctx->ctr, dyn);
+                    dem_status st = read_counters(ctx, dyn);
+                    if (st != DEM_OK) return st;
+                    uint32_t miss = ctx->h_ctr->miss;
+                    if (miss > 0) {
+                        misses += miss;
+                        ++repairs;
+                        if (!P.repair) {
+                            ctx->err = "judge found contacts missing from the active set";
+                            result = DEM_ERR_MISSED;
+                            break;
+                        }
+                        if (ctx->pending && !swap_due) hipStreamWaitEvent(dyn, ctx->ev_cd, 0);
+                        int target = 1 - ctx->cur;
+                        st = detect_now(ctx, P.margin, dyn, target);
+                        if (st != DEM_OK) return st;
+                        ++cds;
+                        ctx->pending = false;
+                        swap_due = true;
+                        ctx->pend_buf = target;
+                        int64_t k = P.cd_mode == DEM_CD_LEARNED ? learned_interval(ctx, dyn) : P.cd_interval;
+                        ctx->next_wo = n + k;
+                        k_next = -1;
+                        ctx->last_wo = n;
+                        if (P.cd_mode == DEM_CD_LEARNED) {
+                            hipMemcpyAsync(ctx->snap_rec, ctx->rec, sizeof(OwnerRec) * ctx->No,
+                                           hipMemcpyDeviceToDevice, dyn);
+                            ctx->snap_step = n;
+                        }
+                    }
+                }
+                if (swap_due) {
+                    dem_status st = adopt(ctx, ctx->pend_buf, dyn);
+                    if (st != DEM_OK) return st;
+                    ctx->pending = false;
+                    ++swaps;
+                }
+                if (P.cd_latency > 0 && n == ctx->next_wo) {
+                    int64_t k = P.cd_mode == DEM_CD_LEARNED ? learned_interval(ctx, dyn) : P.cd_interval;
+                    issue_work_order(ctx, dyn, kin, n);
+                    ++cds;
+                    ctx->next_wo = n + k;
+                } else if (P.cd_latency == 0 && k_next > 0) {
+                    ctx->next_wo = n + k_next;
+                }
+            }
+        }
+        DynArgs a = dyn_args(ctx, n);
+        launch_force(a, ctx->acs[ctx->cur], ctx->sb, ctx->ctr, dyn);
+        launch_fold_integrate(a, ctx->acs[ctx->cur], ctx->sb, ctx->ctr, 1, dyn);
+        ctx->step = n + 1;
+    }
+    HIPCHK(hipGetLastError());
+    if (kin != dyn) HIPCHK(hipStreamSynchronize(kin));
+    dem_status st = read_counters(ctx, dyn);
+    if (st != DEM_OK) return st;
+    const DevCounters &c = *ctx->h_ctr;
+    if (c.stop_cd || c.div[0] || c.div[1]) {
+        ctx->step = c.last_step_done > 0 ? c.last_step_done : step0;
+        if (c.stop_cd) {
+            ctx->err = "contact capacity exceeded during detection";
+            result = DEM_ERR_CAPACITY;
+        } else {
+            ctx->err = "simulation diverged (NaN or speed above v_error_out)";
+            result = DEM_ERR_DIVERGED;
+        }
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    if (stats) {
+        stats->steps = ctx->step - step0;
+        stats->step = ctx->step;
+        stats->cds = cds;
+        stats->swaps = swaps;
+        stats->misses = misses;
+        stats->repairs = repairs;
+        stats->n_contacts = c.n_contacts[ctx->cur];
+        stats->required_capacity = c.required;
+        float v2;
+        uint32_t bits = c.maxv2[(ctx->step - 1) & 3];
+        std::memcpy(&v2, &bits, 4);
+        stats->max_speed = std::sqrt((double)v2);
+        stats->ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        stats->mean_interval = ctx->n_wo > 1 ? ctx->interval_sum / (double)(ctx->n_wo - 1)
+                                             : (double)(P.cd_mode == DEM_CD_EVERY ? 1 : P.cd_interval);
+    }
+    return result;
+}
+
+void dem_destroy(dem_ctx *ctx)
+{
+    if (!ctx) return;
+    if (ctx->h_ctr) hipHostFree(ctx->h_ctr);
+    if (ctx->h_pred) hipHostFree(ctx->h_pred);
+    if (ctx->ev_wo) hipEventDestroy(ctx->ev_wo);
+    if (ctx->ev_cd) hipEventDestroy(ctx->ev_cd);
+    delete ctx;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// learned interval: features, MLP, policy, training-log tools
+// ---------------------------------------------------------------------------
+void feature_pipeline(const OwnerRec *rec, const OwnerRec *snap, const uint32_t *own_sph0, const SphRec *sph,
+                      Origin org, Grid fg, float h, float margin, float tau, uint32_t *raw, uint32_t *flags,
+                      uint32_t *pos, uint32_t *partials, uint32_t *cellmap, float *out, uint32_t *cell_ids,
+                      int64_t No, hipStream_t s);
+void mlp_forward(const float *params, const float *X, float *Y, int64_t n, hipStream_t s);
+void pred_min(const float *Y, int64_t n, uint32_t *out, hipStream_t s);
+void launch_label_judge(const DetectArgs &a, CdWork &w, const uint32_t *lab_start, const uint32_t *lab_j,
+                        int64_t cap, const uint32_t *cellmap, uint32_t *first_miss, uint32_t t, hipStream_t s);
+void launch_detect_plain(const DetectArgs &a, CdWork &w, uint32_t *start, uint32_t *j, int64_t cap,
+                         DevCounters *ctr, hipStream_t s);
+
+static void run_features(dem_ctx *ctx, hipStream_t s, float *out, uint32_t *cell_ids)
+{
+    float tau = (float)(ctx->step - ctx->snap_step);
+    float margin = (float)(ctx->P.margin > 0.0 ? ctx->P.margin : 1e-6);
+    feature_pipeline(ctx->rec, ctx->snap_rec, ctx->d_sph0, ctx->d_sph, ctx->org, ctx->fgrid, (float)ctx->P.dt,
+                     margin, tau, ctx->d_fraw, ctx->d_fflag, ctx->d_fpos, ctx->cdD.partials, ctx->d_cellmap, out,
+                     cell_ids, ctx->No, s);
+}
+
+// Analytic interval: the largest n with (k+lambda) steps of motion at the
+// current top speed plus gravity staying inside the margin,
+// v t + g t^2 / 2 < m with t = (n + lambda) h.
+static int64_t analytic_interval(dem_ctx *ctx, double vmax)
+{
+    const dem_params &P = ctx->P;
+    double g = std::sqrt(P.gravity[0] * P.gravity[0] + P.gravity[1] * P.gravity[1] + P.gravity[2] * P.gravity[2]);
+    double m = P.margin;
+    double t;
+    if (g > 0.0) t = (-vmax + std::sqrt(vmax * vmax + 2.0 * g * m)) / g;
+    else t = vmax > 0.0 ? m / vmax : 1e30;
+    double n = std::floor(t / P.dt) - (double)P.cd_latency;
+    int64_t k = n < 1.0 ? 1 : (n > 1e9 ? (int64_t)1e9 : (int64_t)n);
+    return std::min<int64_t>(k, P.cd_interval_max);
+}
+
+// Decides the next detection interval at a work order (LEARNED mode): the
+// MLP predicts, per cell, how many steps a set detected now stays complete;
+// the minimum over cells minus the adoption latency is the interval; the
+// analytic bound is the fallback and the floor.  Synchronises `s`.
+int64_t learned_interval(dem_ctx *ctx, hipStream_t s)
+{
+    // top speed of the last integrated step
+    if (read_counters(ctx, s) != DEM_OK) return 1;
+    float v2;
+    uint32_t bits = ctx->h_ctr->maxv2[(ctx->step - 1) & 3];
+    std::memcpy(&v2, &bits, 4);
+    double vmax = ctx->step > 0 && v2 == v2 ? std::sqrt((double)v2) : 0.0;
+    int64_t k_an = analytic_interval(ctx, vmax);
+    if (!ctx->mlp_set) return k_an;
+    run_features(ctx, s, ctx->d_feat, nullptr);
+    uint32_t ncell = 0;
+    hipMemcpyAsync(&ncell, ctx->d_fpos + ctx->fgrid.nbins, 4, hipMemcpyDeviceToHost, s);
+    hipStreamSynchronize(s);
+    mlp_forward(ctx->d_mlp, ctx->d_feat, ctx->d_pred, ncell, s);
+    pred_min(ctx->d_pred, ncell, reinterpret_cast<uint32_t *>(ctx->d_pred + ctx->ncell_cap), s);
+    hipMemcpyAsync(ctx->h_pred, ctx->d_pred + ctx->ncell_cap, 4, hipMemcpyDeviceToHost, s);
+    hipStreamSynchronize(s);
+    float R = ctx->h_pred[0];
+    if (!(R >= 0.0f) || ncell == 0) return k_an;
+    double kl = std::floor((double)R) - (double)ctx->P.cd_latency - 1.0;
+    int64_t k = kl < 1.0 ? 1 : (int64_t)std::min(kl, 1e9);
+    k = std::max(k, k_an);
+    return std::min<int64_t>(k, ctx->P.cd_interval_max);
+}
+
+extern "C" {
+
+dem_status dem_mlp_set(dem_ctx *ctx, const float *params)
+{
+    if (!ctx) return DEM_ERR_ARG;
+    if (!params) {
+        ctx->mlp_set = false;
+        return DEM_OK;
+    }
+    ctx->mlp.assign(params, params + DEM_MLP_NPARAM);
+    for (float f : ctx->mlp) ARGCHK(std::isfinite(f), "MLP parameters must be finite");
+    ctx->mlp_set = true;
+    if (ctx->bound) HIPCHK(hipMemcpy(ctx->d_mlp, params, sizeof(float) * DEM_MLP_NPARAM, hipMemcpyHostToDevice));
+    return DEM_OK;
+}
+
+dem_status dem_snapshot(dem_ctx *ctx, dem_stream stream)
+{
+    if (!ctx) return DEM_ERR_ARG;
+    if (!ctx->bound) {
+        ctx->err = "dem_snapshot before dem_bind";
+        return DEM_ERR_STATE;
+    }
+    hipStream_t s = S(stream);
+    HIPCHK(hipMemcpyAsync(ctx->snap_rec, ctx->rec, sizeof(OwnerRec) * ctx->No, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->snap_q, ctx->q, sizeof(double) * 4 * ctx->No, hipMemcpyDeviceToDevice, s));
+    ctx->snap_step = ctx->step;
+    return DEM_OK;
+}
+
+dem_status dem_features(dem_ctx *ctx, float *out_dev, int64_t ncell_cap, int64_t *ncell, dem_stream stream)
+{
+    if (!ctx || !ncell) return DEM_ERR_ARG;
+    if (!ctx->bound) {
+        ctx->err = "dem_features before dem_bind";
+        return DEM_ERR_STATE;
+    }
+    hipStream_t s = S(stream);
+    run_features(ctx, s, ctx->d_feat, ctx->d_fids);
+    uint32_t nc = 0;
+    HIPCHK(hipMemcpyAsync(&nc, ctx->d_fpos + ctx->fgrid.nbins, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *ncell = nc;
+    if (out_dev) {
+        if (ncell_cap < (int64_t)nc) {
+            ctx->err = "feature output capacity too small";
+            return DEM_ERR_CAPACITY;
+        }
+        if (nc) HIPCHK(hipMemcpyAsync(out_dev, ctx->d_feat, sizeof(float) * DEM_MLP_NFEAT * nc,
+                                      hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    return DEM_OK;
+}
+
+dem_status dem_feature_cells(dem_ctx *ctx, uint32_t *cell_ids, int64_t cap, uint32_t *owner_cell,
+                             int64_t *n_cells_total, dem_stream stream)
+{
+    if (!ctx) return DEM_ERR_ARG;
+    if (!ctx->bound) {
+        ctx->err = "dem_feature_cells before dem_bind";
+        return DEM_ERR_STATE;
+    }
+    hipStream_t s = S(stream);
+    uint32_t nc = 0;
+    HIPCHK(hipMemcpyAsync(&nc, ctx->d_fpos + ctx->fgrid.nbins, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (n_cells_total) *n_cells_total = (int64_t)ctx->fgrid.nbins;
+    if (cell_ids) {
+        ARGCHK(cap >= (int64_t)nc, "cell id capacity too small");
+        if (nc) HIPCHK(hipMemcpy(cell_ids, ctx->d_fids, 4 * (size_t)nc, hipMemcpyDeviceToHost));
+    }
+    if (owner_cell) HIPCHK(hipMemcpy(owner_cell, ctx->d_cellmap, 4 * (size_t)ctx->No, hipMemcpyDeviceToHost));
+    return DEM_OK;
+}
+
+dem_status dem_label_begin(dem_ctx *ctx, dem_stream stream, int64_t *n_contacts)
+{
+    if (!ctx) return DEM_ERR_ARG;
+    if (!ctx->bound) {
+        ctx->err = "dem_label_begin before dem_bind";
+        return DEM_ERR_STATE;
+    }
+    hipStream_t s = S(stream);
+    DetectArgs a = detect_args(ctx, false, ctx->P.margin, ctx->step);
+    launch_detect_plain(a, ctx->cdD, ctx->d_lab_start, ctx->d_lab_j, ctx->cap, ctx->ctr, s);
+    HIPCHK(hipGetLastError());
+    dem_status st = read_counters(ctx, s);
+    if (st != DEM_OK) return st;
+    if (n_contacts) *n_contacts = ctx->h_ctr->required;
+    return DEM_OK;
+}
+
+dem_status dem_label_update(dem_ctx *ctx, uint32_t t, uint32_t *first_miss_dev, dem_stream stream)
+{
+    if (!ctx || !first_miss_dev) return DEM_ERR_ARG;
+    if (!ctx->bound) {
+        ctx->err = "dem_label_update before dem_bind";
+        return DEM_ERR_STATE;
+    }
+    hipStream_t s = S(stream);
+    DetectArgs a = detect_args(ctx, false, 0.0, ctx->step);
+    launch_label_judge(a, ctx->cdD, ctx->d_lab_start, ctx->d_lab_j, ctx->cap, ctx->d_cellmap, first_miss_dev, t, s);
+    HIPCHK(hipGetLastError());
+    return DEM_OK;
+}
+
+dem_status dem_info(const dem_ctx *ctx, int64_t *vals, int64_t n)
+{
+    if (!ctx || !vals) return DEM_ERR_ARG;
+    int64_t v[8] = {(int64_t)ctx->grid.nbins, (int64_t)ctx->fgrid.nbins, ctx->grid.nx, ctx->grid.ny,
+                    ctx->grid.nz, ctx->sort_bits, ctx->cap, ctx->step};
+    for (int64_t k = 0; k < n && k < 8; ++k) vals[k] = v[k];
+    return DEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,372 @@
+// Contact detection for gfx950 (paper Sec. 2.1: the active contact set is
+// built with every geometry enlarged by a margin m).
+//
+//   bin:     sphere centres (exact FP64) -> bin key (uniform grid of cubic
+//            bins of edge >= 2 (r_max + m), padded by one bin per side),
+//            per-bin counts -> exclusive scan -> cell_start, and a stable
+//            LSD radix sort of (key, sphere id); candidate records are then
+//            gathered into bin order so neighbour rows are contiguous.
+//   detect:  one thread per sphere in bin order walks the 9 neighbour rows
+//            (3 bins each, contiguous in the sorted order) and tests every
+//            candidate j > i of another owner with the FP64 predicate
+//            |xi - xj|^2 < ((ri + rj) + 2m)^2, then the walls.  A count pass,
+//            an exclusive scan (CSR offsets by sphere id) and a write pass
+//            that insertion-sorts each row give the set as ascending keys.
+//   B lists: for every sphere, the contacts in which it is the higher id,
+//            ascending; used by the ordered per-owner reduction.
+//   remap:   per sphere, a merge of the old and the new row carries the
+//            tangential history of surviving pairs; new pairs start at zero.
+//   judge:   the same walk with m = 0 looks every true contact up in the
+//            row of the set in use and counts the missing ones.
+#include "dem_device.h"
+
+namespace {
+
+constexpr int TPB = 256;
+
+enum { MODE_COUNT = 0, MODE_WRITE = 1, MODE_JUDGE = 2, MODE_LABEL = 3 };
+
+inline unsigned nblocks(int64_t n, int t = TPB)
+{
+    int64_t g = (n + t - 1) / t;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+__device__ inline int bin_coord(double x, double lo, double inv_b, int n)
+{
+    double t = floor((x - lo) * inv_b);
+    int c;
+    if (!(t >= 0.0)) c = 0;
+    else if (t > (double)(n - 3)) c = n - 3;
+    else c = (int)t;
+    return c + 1;
+}
+
+__global__ void __launch_bounds__(TPB) k_cd_prepare(DetectArgs a, uint32_t *keys, uint32_t *vals,
+                                                    Cand *cand_tmp, uint32_t *cell_count)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n_spheres) return;
+    SphRec s = load_sph(a.sph + i);
+    OwnerRec r = load_rec(a.rec + s.owner);
+    double x[3];
+    sphere_centre(r, s, a.q, a.tpos, a.org, x);
+    int cx = bin_coord(x[0], a.grid.lo[0], a.grid.inv_b, a.grid.nx);
+    int cy = bin_coord(x[1], a.grid.lo[1], a.grid.inv_b, a.grid.ny);
+    int cz = bin_coord(x[2], a.grid.lo[2], a.grid.inv_b, a.grid.nz);
+    uint32_t key = ((uint32_t)cz * (uint32_t)a.grid.ny + (uint32_t)cy) * (uint32_t)a.grid.nx + (uint32_t)cx;
+    keys[i] = key;
+    vals[i] = (uint32_t)i;
+    Cand c;
+    c.x = x[0];
+    c.y = x[1];
+    c.z = x[2];
+    c.r = s.rad;
+    c.id = (uint32_t)i;
+    cand_tmp[i] = c;
+    atomicAdd(&cell_count[key], 1u);
+}
+
+__global__ void __launch_bounds__(TPB) k_cand_gather(const uint32_t *vals, const Cand *cand_tmp,
+                                                     Cand *cand, int64_t n)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    cand[p] = cand_tmp[vals[p]];
+}
+
+__device__ inline bool sphere_pair_hit(double xi, double yi, double zi, double ri, const Cand &cj,
+                                       double m)
+{
+    double dx = xi - cj.x, dy = yi - cj.y, dz = zi - cj.z;
+    double d2 = (dx * dx + dy * dy) + dz * dz;
+    double T = (ri + (double)cj.r) + 2.0 * m;
+    return d2 < T * T;
+}
+
+__device__ inline bool wall_hit(const WallDev &w, const double *p, double x, double y, double z,
+                                double r, double m)
+{
+    double rx = x - p[0], ry = y - p[1], rz = z - p[2];
+    if (w.type == 0) {
+        double sd = (rx * w.geom[3] + ry * w.geom[4]) + rz * w.geom[5];
+        return sd < r + 2.0 * m;
+    }
+    double ax = (rx * w.geom[3] + ry * w.geom[4]) + rz * w.geom[5];
+    double hl = 0.5 * w.geom[7] + 2.0 * m;
+    if (!(ax <= hl && ax >= -hl)) return false;
+    double px = rx - ax * w.geom[3], py = ry - ax * w.geom[4], pz = rz - ax * w.geom[5];
+    double d2 = (px * px + py * py) + pz * pz;
+    double T = (w.geom[6] + r) + 2.0 * m;
+    return d2 < T * T;
+}
+
+// Binary search of j in the ascending row [lo, hi) of a set.
+__device__ inline bool row_contains(const uint32_t *row_j, uint32_t lo, uint32_t hi, uint32_t j)
+{
+    uint32_t a = lo, b = hi;
+    while (a < b) {
+        uint32_t mid = (a + b) >> 1;
+        if (row_j[mid] < j) a = mid + 1;
+        else b = mid;
+    }
+    return a < hi && row_j[a] == j;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(TPB) k_detect(DetectArgs a, const uint32_t *keys, const Cand *cand,
+                                                const uint32_t *cell_start, uint32_t *count,
+                                                const uint32_t *start, uint32_t *out_j, int64_t cap,
+                                                const uint32_t *cur_start, const uint32_t *cur_j,
+                                                uint32_t *miss, const uint32_t *cellmap = nullptr,
+                                                uint32_t *first_miss = nullptr, uint32_t tval = 0)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n_spheres) return;
+    const Cand ci = cand[p];
+    const uint32_t i = ci.id;
+    const uint32_t key = keys[p];
+    const double xi = ci.x, yi = ci.y, zi = ci.z, ri = (double)ci.r;
+    const double m = a.margin;
+    const uint32_t nx = (uint32_t)a.grid.nx, nxy = (uint32_t)a.grid.nx * (uint32_t)a.grid.ny;
+    uint32_t own_i = 0xffffffffu;
+    uint32_t base = 0;
+    bool can_write = true;
+    if (MODE == MODE_WRITE) {
+        base = start[i];
+        can_write = (int64_t)start[i + 1] <= cap;
+    }
+    uint32_t lo_row = 0, hi_row = 0;
+    if (MODE == MODE_JUDGE || MODE == MODE_LABEL) {
+        // rows of a set that overflowed its capacity are not valid: treat as empty
+        if ((int64_t)cur_start[a.n_spheres] <= cap) {
+            lo_row = cur_start[i];
+            hi_row = cur_start[i + 1];
+        }
+    }
+    uint32_t n = 0, nmiss = 0;
+    for (int dz = -1; dz <= 1; ++dz) {
+        for (int dy = -1; dy <= 1; ++dy) {
+            uint32_t row = key + (uint32_t)((int)nxy * dz) + (uint32_t)((int)nx * dy);
+            uint32_t q0 = cell_start[row - 1], q1 = cell_start[row + 2];
+            for (uint32_t qq = q0; qq < q1; ++qq) {
+                const Cand cj = cand[qq];
+                if (cj.id <= i) continue;
+                if (!sphere_pair_hit(xi, yi, zi, ri, cj, m)) continue;
+                if (own_i == 0xffffffffu) own_i = a.sph[i].owner;
+                if (a.sph[cj.id].owner == own_i) continue;
+                if (MODE == MODE_WRITE) {
+                    if (can_write) out_j[base + n] = cj.id;
+                } else if (MODE == MODE_JUDGE) {
+                    if (!row_contains(cur_j, lo_row, hi_row, cj.id)) ++nmiss;
+                } else if (MODE == MODE_LABEL) {
+                    if (!row_contains(cur_j, lo_row, hi_row, cj.id)) {
+                        atomicMin(&first_miss[cellmap[own_i]], tval);
+                        atomicMin(&first_miss[cellmap[a.sph[cj.id].owner]], tval);
+                    }
+                }
+                ++n;
+            }
+        }
+    }
+    // sort the sphere partners of this row (insertion sort, rows are short)
+    if (MODE == MODE_WRITE && can_write) {
+        for (uint32_t t = 1; t < n; ++t) {
+            uint32_t v = out_j[base + t];
+            uint32_t u = t;
+            while (u > 0 && out_j[base + u - 1] > v) {
+                out_j[base + u] = out_j[base + u - 1];
+                --u;
+            }
+            out_j[base + u] = v;
+        }
+    }
+    for (int w = 0; w < a.n_walls; ++w) {
+        WallDev wd = a.walls[w];
+        double pw[3];
+        wall_point(wd, a.step, a.h, pw);
+        if (!wall_hit(wd, pw, xi, yi, zi, ri, m)) continue;
+        uint32_t jp = (uint32_t)a.n_spheres + (uint32_t)w;
+        if (MODE == MODE_WRITE) {
+            if (can_write) out_j[base + n] = jp;
+        } else if (MODE == MODE_JUDGE) {
+            if (!row_contains(cur_j, lo_row, hi_row, jp)) ++nmiss;
+        } else if (MODE == MODE_LABEL) {
+            if (!row_contains(cur_j, lo_row, hi_row, jp)) atomicMin(&first_miss[cellmap[a.sph[i].owner]], tval);
+        }
+        ++n;
+    }
+    if (MODE == MODE_COUNT) count[i] = n;
+    if (MODE == MODE_JUDGE && nmiss) atomicAdd(miss, nmiss);
+}
+
+__global__ void k_check_capacity(const uint32_t *start, int64_t ns, int64_t cap, DevCounters *ctr,
+                                 int buf)
+{
+    uint32_t total = start[ns];
+    ctr->n_contacts[buf] = total;
+    if ((int64_t)total > cap) {
+        ctr->overflow[buf] = 1u;
+        atomicMax(&ctr->required, total);
+    } else {
+        ctr->overflow[buf] = 0u;
+    }
+}
+
+__global__ void k_record_total(const uint32_t *start, int64_t ns, DevCounters *ctr)
+{
+    ctr->required = start[ns];
+}
+
+__global__ void __launch_bounds__(TPB) k_blist_count(const uint32_t *start, const uint32_t *j,
+                                                     int64_t ns, int64_t cap, uint32_t *bcount)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ns || (int64_t)start[ns] > cap) return;   // an overflowed set has no valid rows
+    for (uint32_t c = start[i]; c < start[i + 1]; ++c) {
+        uint32_t jj = j[c];
+        if ((int64_t)jj < ns) atomicAdd(&bcount[jj], 1u);
+    }
+}
+
+__global__ void __launch_bounds__(TPB) k_blist_fill(const uint32_t *start, const uint32_t *j,
+                                                    int64_t ns, int64_t cap, uint32_t *cursor, uint32_t *bidx)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ns || (int64_t)start[ns] > cap) return;
+    for (uint32_t c = start[i]; c < start[i + 1]; ++c) {
+        uint32_t jj = j[c];
+        if ((int64_t)jj < ns) bidx[atomicAdd(&cursor[jj], 1u)] = c;
+    }
+}
+
+__global__ void __launch_bounds__(TPB) k_blist_sort(const uint32_t *bstart, int64_t ns, uint32_t *bidx)
+{
+    int64_t jv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (jv >= ns) return;
+    uint32_t b0 = bstart[jv], b1 = bstart[jv + 1];
+    for (uint32_t t = b0 + 1; t < b1; ++t) {
+        uint32_t v = bidx[t];
+        uint32_t u = t;
+        while (u > b0 && bidx[u - 1] > v) {
+            bidx[u] = bidx[u - 1];
+            --u;
+        }
+        bidx[u] = v;
+    }
+}
+
+__global__ void __launch_bounds__(TPB) k_remap(const uint32_t *os, const uint32_t *oj, const float *ohx,
+                                               const float *ohy, const float *ohz, const uint32_t *ns_,
+                                               const uint32_t *nj, float *nhx, float *nhy, float *nhz,
+                                               int64_t ns, DevCounters *ctr, int newbuf)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        if (ctr->overflow[newbuf]) ctr->stop_cd = 1u;
+    }
+    if (i >= ns) return;
+    if (ctr->overflow[newbuf]) return;
+    uint32_t p = os[i], pe = os[i + 1];
+    for (uint32_t c = ns_[i]; c < ns_[i + 1]; ++c) {
+        uint32_t jj = nj[c];
+        while (p < pe && oj[p] < jj) ++p;
+        if (p < pe && oj[p] == jj) {
+            nhx[c] = ohx[p];
+            nhy[c] = ohy[p];
+            nhz[c] = ohz[p];
+        } else {
+            nhx[c] = 0.0f;
+            nhy[c] = 0.0f;
+            nhz[c] = 0.0f;
+        }
+    }
+}
+
+}  // namespace
+
+void launch_bin(const DetectArgs &a, CdWork &w, hipStream_t s)
+{
+    int64_t n = a.n_spheres;
+    launch_fill_u32(w.cell_count, (int64_t)a.grid.nbins, 0u, s);
+    hipLaunchKernelGGL(k_cd_prepare, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.vals, w.cand_tmp,
+                       w.cell_count);
+    scan_exclusive_u32(w.cell_count, w.cell_start, (int64_t)a.grid.nbins, w.partials, s);
+    radix_sort_u32(w.keys, w.vals, w.keys_alt, w.vals_alt, n, w.sort_bits, w.hist, w.partials, s);
+    hipLaunchKernelGGL(k_cand_gather, dim3(nblocks(n)), dim3(TPB), 0, s, w.vals, w.cand_tmp, w.cand, n);
+}
+
+void launch_blists(AcsBuf &b, int64_t ns, int64_t cap, uint32_t *partials, hipStream_t s)
+{
+    launch_fill_u32(b.bcur, ns + 1, 0u, s);
+    hipLaunchKernelGGL(k_blist_count, dim3(nblocks(ns)), dim3(TPB), 0, s, b.start, b.j, ns, cap, b.bcur);
+    scan_exclusive_u32(b.bcur, b.bstart, ns, partials, s);
+    launch_copy_u32(b.bcur, b.bstart, ns + 1, s);
+    hipLaunchKernelGGL(k_blist_fill, dim3(nblocks(ns)), dim3(TPB), 0, s, b.start, b.j, ns, cap, b.bcur, b.bidx);
+    hipLaunchKernelGGL(k_blist_sort, dim3(nblocks(ns)), dim3(TPB), 0, s, b.bstart, ns, b.bidx);
+}
+
+void launch_detect(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap, DevCounters *ctr, int buf,
+                   hipStream_t s)
+{
+    int64_t n = a.n_spheres;
+    launch_bin(a, w, s);
+    hipLaunchKernelGGL(k_detect<MODE_COUNT>, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,
+                       w.cell_start, w.count, (const uint32_t *)nullptr, (uint32_t *)nullptr, cap,
+                       (const uint32_t *)nullptr, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                       (const uint32_t *)nullptr, (uint32_t *)nullptr, 0u);
+    scan_exclusive_u32(w.count, out.start, n, w.partials, s);
+    hipLaunchKernelGGL(k_check_capacity, dim3(1), dim3(1), 0, s, out.start, n, cap, ctr, buf);
+    hipLaunchKernelGGL(k_detect<MODE_WRITE>, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,
+                       w.cell_start, (uint32_t *)nullptr, out.start, out.j, cap,
+                       (const uint32_t *)nullptr, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                       (const uint32_t *)nullptr, (uint32_t *)nullptr, 0u);
+    launch_blists(out, n, cap, w.partials, s);
+}
+
+void launch_judge(const DetectArgs &a, CdWork &w, const AcsBuf &cur, int64_t cap, DevCounters *ctr,
+                  hipStream_t s)
+{
+    int64_t n = a.n_spheres;
+    launch_bin(a, w, s);
+    hipLaunchKernelGGL(k_detect<MODE_JUDGE>, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,
+                       w.cell_start, (uint32_t *)nullptr, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                       cap, (const uint32_t *)cur.start, (const uint32_t *)cur.j, &ctr->miss,
+                       (const uint32_t *)nullptr, (uint32_t *)nullptr, 0u);
+}
+
+void launch_remap(const AcsBuf &o, AcsBuf &nb, int64_t ns, DevCounters *ctr, int newbuf, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_remap, dim3(nblocks(ns)), dim3(TPB), 0, s, o.start, o.j, o.hx, o.hy, o.hz,
+                       nb.start, nb.j, nb.hx, nb.hy, nb.hz, ns, ctr, newbuf);
+}
+
+void launch_detect_plain(const DetectArgs &a, CdWork &w, uint32_t *start, uint32_t *j, int64_t cap,
+                         DevCounters *ctr, hipStream_t s)
+{
+    int64_t n = a.n_spheres;
+    launch_bin(a, w, s);
+    hipLaunchKernelGGL(k_detect<MODE_COUNT>, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,
+                       w.cell_start, w.count, (const uint32_t *)nullptr, (uint32_t *)nullptr, cap,
+                       (const uint32_t *)nullptr, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                       (const uint32_t *)nullptr, (uint32_t *)nullptr, 0u);
+    scan_exclusive_u32(w.count, start, n, w.partials, s);
+    hipLaunchKernelGGL(k_record_total, dim3(1), dim3(1), 0, s, start, n, ctr);
+    hipLaunchKernelGGL(k_detect<MODE_WRITE>, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,
+                       w.cell_start, (uint32_t *)nullptr, start, j, cap,
+                       (const uint32_t *)nullptr, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                       (const uint32_t *)nullptr, (uint32_t *)nullptr, 0u);
+}
+
+void launch_label_judge(const DetectArgs &a, CdWork &w, const uint32_t *lab_start, const uint32_t *lab_j,
+                        int64_t cap, const uint32_t *cellmap, uint32_t *first_miss, uint32_t tval,
+                        hipStream_t s)
+{
+    int64_t n = a.n_spheres;
+    launch_bin(a, w, s);
+    hipLaunchKernelGGL(k_detect<MODE_LABEL>, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,
+                       w.cell_start, (uint32_t *)nullptr, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                       cap, lab_start, lab_j, (uint32_t *)nullptr, cellmap, first_miss, tval);
+}

@@ -1,0 +1,162 @@
+// Device (and host) helpers: position codec, rotations, small vector math.
+// Every FP64 expression that decides a contact predicate is written with an
+// explicit operation order; the library is compiled with -ffp-contract=off
+// so no multiply-add is fused and each operation rounds once.
+#pragma once
+
+#include "dem_internal.h"
+
+// ---------------------------------------------------------------------------
+// position codec: world X = origin + vox * 2^-14 + off, off on a 2^-38 grid.
+// Every value of this form is an FP64 number, so decoding is exact.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline uint32_t vox_axis(uint64_t vox, int k)
+{
+    return (uint32_t)((vox >> (DEM_VOX_BITS * k)) & DEM_VOX_MASK);
+}
+
+__host__ __device__ inline double decode_axis(uint64_t vox, float off, double origin, int k)
+{
+    double local = (double)vox_axis(vox, k) * DEM_VOXEL_SIZE + (double)off;
+    return origin + local;
+}
+
+// Encodes one axis of a world coordinate.  Rounds to the nearest 2^-38 m.
+__host__ __device__ inline void encode_axis(double x, double origin, uint32_t *iv, float *off)
+{
+    double local = x - origin;
+    double v = floor(local * DEM_VOXEL_INV);
+    if (!(v >= 0.0)) v = 0.0;                      // also catches NaN
+    if (v > (double)DEM_VOX_MASK) v = (double)DEM_VOX_MASK;
+    double r = local - v * DEM_VOXEL_SIZE;
+    double kq = rint(r * DEM_OFF_QUANT_INV);
+    if (kq < 0.0) kq = 0.0;
+    if (kq >= DEM_OFF_STEPS) {
+        if (v < (double)DEM_VOX_MASK) {
+            v += 1.0;
+            kq = 0.0;
+        } else {
+            kq = DEM_OFF_STEPS - 1.0;
+        }
+    }
+    *iv = (uint32_t)v;
+    *off = (float)(kq * DEM_OFF_QUANT);
+}
+
+__host__ __device__ inline uint64_t pack_vox(uint32_t x, uint32_t y, uint32_t z)
+{
+    return (uint64_t)x | ((uint64_t)y << DEM_VOX_BITS) | ((uint64_t)z << (2 * DEM_VOX_BITS));
+}
+
+// ---------------------------------------------------------------------------
+// rotation of a unit quaternion (w,x,y,z), body -> world, fixed formula
+// ---------------------------------------------------------------------------
+struct Mat3d {
+    double m[9];
+};
+
+__host__ __device__ inline Mat3d rot_from_q(double w, double x, double y, double z)
+{
+    Mat3d R;
+    R.m[0] = 1.0 - 2.0 * (y * y + z * z);
+    R.m[1] = 2.0 * (x * y - w * z);
+    R.m[2] = 2.0 * (x * z + w * y);
+    R.m[3] = 2.0 * (x * y + w * z);
+    R.m[4] = 1.0 - 2.0 * (x * x + z * z);
+    R.m[5] = 2.0 * (y * z - w * x);
+    R.m[6] = 2.0 * (x * z - w * y);
+    R.m[7] = 2.0 * (y * z + w * x);
+    R.m[8] = 1.0 - 2.0 * (x * x + y * y);
+    return R;
+}
+
+__host__ __device__ inline void rot_apply(const Mat3d &R, double px, double py, double pz, double *o)
+{
+    o[0] = (R.m[0] * px + R.m[1] * py) + R.m[2] * pz;
+    o[1] = (R.m[3] * px + R.m[4] * py) + R.m[5] * pz;
+    o[2] = (R.m[6] * px + R.m[7] * py) + R.m[8] * pz;
+}
+
+__device__ inline float3 f3(float x, float y, float z) { return make_float3(x, y, z); }
+__device__ inline float3 operator+(float3 a, float3 b) { return f3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ inline float3 operator-(float3 a, float3 b) { return f3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ inline float3 operator*(float s, float3 a) { return f3(s * a.x, s * a.y, s * a.z); }
+__device__ inline float dot3(float3 a, float3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+__device__ inline float3 cross3(float3 a, float3 b)
+{
+    return f3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+
+// Loads an owner record with three 16-byte loads.
+__device__ inline OwnerRec load_rec(const OwnerRec *p)
+{
+    const uint4 *u = reinterpret_cast<const uint4 *>(p);
+    uint4 a = u[0], b = u[1], c = u[2];
+    OwnerRec r;
+    r.vox = (uint64_t)a.x | ((uint64_t)a.y << 32);
+    r.off[0] = __uint_as_float(a.z);
+    r.off[1] = __uint_as_float(a.w);
+    r.off[2] = __uint_as_float(b.x);
+    r.v[0] = __uint_as_float(b.y);
+    r.v[1] = __uint_as_float(b.z);
+    r.v[2] = __uint_as_float(b.w);
+    r.w[0] = __uint_as_float(c.x);
+    r.w[1] = __uint_as_float(c.y);
+    r.w[2] = __uint_as_float(c.z);
+    r.mass = __uint_as_float(c.w);
+    return r;
+}
+
+__device__ inline void store_rec(OwnerRec *p, const OwnerRec &r)
+{
+    uint4 *u = reinterpret_cast<uint4 *>(p);
+    u[0] = make_uint4((uint32_t)r.vox, (uint32_t)(r.vox >> 32), __float_as_uint(r.off[0]),
+                      __float_as_uint(r.off[1]));
+    u[1] = make_uint4(__float_as_uint(r.off[2]), __float_as_uint(r.v[0]), __float_as_uint(r.v[1]),
+                      __float_as_uint(r.v[2]));
+    u[2] = make_uint4(__float_as_uint(r.w[0]), __float_as_uint(r.w[1]), __float_as_uint(r.w[2]),
+                      __float_as_uint(r.mass));
+}
+
+__device__ inline SphRec load_sph(const SphRec *p)
+{
+    uint4 u = *reinterpret_cast<const uint4 *>(p);
+    SphRec s;
+    s.owner = u.x;
+    s.rad = __uint_as_float(u.y);
+    s.mat = u.z;
+    s.tcomp = u.w;
+    return s;
+}
+
+// Exact FP64 centre of a sphere: owner position (+ R(q) p for clump spheres).
+__device__ inline void sphere_centre(const OwnerRec &r, const SphRec &s, const double *q,
+                                     const float *tpos, const Origin &org, double *x)
+{
+    double X0 = decode_axis(r.vox, r.off[0], org.o[0], 0);
+    double X1 = decode_axis(r.vox, r.off[1], org.o[1], 1);
+    double X2 = decode_axis(r.vox, r.off[2], org.o[2], 2);
+    if (s.tcomp == DEM_NO_COMP) {
+        x[0] = X0;
+        x[1] = X1;
+        x[2] = X2;
+        return;
+    }
+    const double *qq = q + 4 * (size_t)s.owner;
+    double4 qv = *reinterpret_cast<const double4 *>(qq);
+    Mat3d R = rot_from_q(qv.x, qv.y, qv.z, qv.w);
+    float4 p = *reinterpret_cast<const float4 *>(tpos + 4 * (size_t)s.tcomp);
+    double d[3];
+    rot_apply(R, (double)p.x, (double)p.y, (double)p.z, d);
+    x[0] = X0 + d[0];
+    x[1] = X1 + d[1];
+    x[2] = X2 + d[2];
+}
+
+__device__ inline void wall_point(const WallDev &w, int64_t step, double h, double *p)
+{
+    double t = (double)step * h;
+    p[0] = w.geom[0] + w.vel[0] * t;
+    p[1] = w.geom[1] + w.vel[1] * t;
+    p[2] = w.geom[2] + w.vel[2] * t;
+}

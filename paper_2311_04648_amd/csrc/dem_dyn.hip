@@ -1,0 +1,349 @@
+// Per-step dynamics for gfx950: Hertz-Mindlin contact forces, ordered
+// reduction onto owners, explicit integration (paper Sec. 4.1, Eqs. (1)-(3);
+// default-model walk-through of Sec. 4.2.1).
+//
+// k_force: one thread per sphere i walks its row of the active set (the
+// contacts where i is the lower id, geometry A), in ascending partner order.
+// The overlap, the normal and the contact point are evaluated in FP64
+// registers from exact sphere centres; the force law runs in FP32.  The
+// thread keeps the running sum of the forces and torques on A in registers
+// (one 24-byte write per sphere instead of one per contact) and writes the
+// reaction on B (force and torque about B's owner) per contact.  Pairs that
+// do not touch (false positives of the margin) get exactly zero force and
+// their history is released (reset to zero).
+//
+// k_fold_integrate: one thread per owner folds, for each of its spheres in
+// order, the A-side sum and then the B-side reactions in ascending contact
+// order -- a fixed sequential order, so adding the +0.0 terms of false
+// positives changes no bit -- then integrates: semi-implicit Euler on the
+// velocity (FP32 storage), FP64 position update re-encoded to voxel +
+// offset, FP64 quaternion update by the exponential map for clumps.
+// Single spheres keep their angular velocity in the world frame (their
+// orientation has no physical effect).
+#include "dem_device.h"
+
+namespace {
+
+constexpr int TPB = 256;
+
+inline unsigned nblocks(int64_t n, int t = TPB)
+{
+    int64_t g = (n + t - 1) / t;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+struct OwnerKin {
+    double X[3];     // owner centre (exact)
+    float3 v;        // velocity
+    float3 w;        // angular velocity in the world frame
+    float mass;
+};
+
+__device__ inline void owner_kin(const OwnerRec &r, const SphRec &s, const OwnerAux *aux, const double *q,
+                                 const float *tpos, const Origin &org, OwnerKin &k, double *xs)
+{
+    k.X[0] = decode_axis(r.vox, r.off[0], org.o[0], 0);
+    k.X[1] = decode_axis(r.vox, r.off[1], org.o[1], 1);
+    k.X[2] = decode_axis(r.vox, r.off[2], org.o[2], 2);
+    k.v = f3(r.v[0], r.v[1], r.v[2]);
+    k.mass = r.mass;
+    if (s.tcomp == DEM_NO_COMP) {
+        k.w = f3(r.w[0], r.w[1], r.w[2]);
+        xs[0] = k.X[0];
+        xs[1] = k.X[1];
+        xs[2] = k.X[2];
+        return;
+    }
+    double4 qv = *reinterpret_cast<const double4 *>(q + 4 * (size_t)s.owner);
+    Mat3d R = rot_from_q(qv.x, qv.y, qv.z, qv.w);
+    float4 p = *reinterpret_cast<const float4 *>(tpos + 4 * (size_t)s.tcomp);
+    double d[3];
+    rot_apply(R, (double)p.x, (double)p.y, (double)p.z, d);
+    xs[0] = k.X[0] + d[0];
+    xs[1] = k.X[1] + d[1];
+    xs[2] = k.X[2] + d[2];
+    double wb[3];
+    rot_apply(R, (double)r.w[0], (double)r.w[1], (double)r.w[2], wb);
+    k.w = f3((float)wb[0], (float)wb[1], (float)wb[2]);
+}
+
+__device__ inline bool stopped(const DevCounters *c, int64_t step)
+{
+    return c->stop_cd != 0u || c->div[(step + 1) & 1] != 0u;
+}
+
+__global__ void __launch_bounds__(TPB) k_force(DynArgs a, const uint32_t *start, const uint32_t *jarr,
+                                               float *hx, float *hy, float *hz, float *aF, float *aT,
+                                               float *bF, float *bT, int64_t cap, const DevCounters *ctr)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n_spheres) return;
+    if (stopped(ctr, a.step)) return;
+    const int64_t Ns = a.n_spheres, No = a.n_owners;
+    float3 FA = f3(0.f, 0.f, 0.f), TA = f3(0.f, 0.f, 0.f);
+    const uint32_t c0 = start[i], c1 = start[i + 1];
+    if (c0 < c1) {
+        const SphRec sA = load_sph(a.sph + i);
+        const OwnerRec rA = load_rec(a.rec + sA.owner);
+        OwnerKin kA;
+        double xA[3];
+        owner_kin(rA, sA, a.aux, a.q, a.tpos, a.org, kA, xA);
+        const double radA = (double)sA.rad;
+        const float hf = (float)a.h;
+        for (uint32_t c = c0; c < c1; ++c) {
+            const uint32_t jp = jarr[c];
+            double nrm[3], delta = 0.0, XB[3];
+            float Rbar = 0.f, mbar = 0.f;
+            float3 vB = f3(0.f, 0.f, 0.f), wB = f3(0.f, 0.f, 0.f);
+            uint32_t matB = 0;
+            bool touching = false, wall = (int64_t)jp >= Ns;
+            if (!wall) {
+                const SphRec sB = load_sph(a.sph + jp);
+                const OwnerRec rB = load_rec(a.rec + sB.owner);
+                OwnerKin kB;
+                double xB[3];
+                owner_kin(rB, sB, a.aux, a.q, a.tpos, a.org, kB, xB);
+                double dx = xA[0] - xB[0], dy = xA[1] - xB[1], dz = xA[2] - xB[2];
+                double d2 = (dx * dx + dy * dy) + dz * dz;
+                double radB = (double)sB.rad;
+                double T = radA + radB;
+                touching = d2 < T * T;
+                if (touching) {
+                    double d = sqrt(d2);
+                    nrm[0] = dx / d;
+                    nrm[1] = dy / d;
+                    nrm[2] = dz / d;
+                    delta = T - d;
+                    Rbar = (float)(radA * radB / (radA + radB));
+                    mbar = kA.mass * kB.mass / (kA.mass + kB.mass);
+                    matB = sB.mat;
+                    XB[0] = kB.X[0];
+                    XB[1] = kB.X[1];
+                    XB[2] = kB.X[2];
+                    vB = kB.v;
+                    wB = kB.w;
+                }
+            } else {
+                const WallDev wd = a.walls[jp - (uint32_t)Ns];
+                double p[3];
+                wall_point(wd, a.step, a.h, p);
+                double rx = xA[0] - p[0], ry = xA[1] - p[1], rz = xA[2] - p[2];
+                if (wd.type == 0) {
+                    double sd = (rx * wd.geom[3] + ry * wd.geom[4]) + rz * wd.geom[5];
+                    touching = sd < radA;
+                    if (touching) {
+                        nrm[0] = wd.geom[3];
+                        nrm[1] = wd.geom[4];
+                        nrm[2] = wd.geom[5];
+                        delta = radA - sd;
+                        Rbar = (float)radA;
+                    }
+                } else {
+                    double ax = (rx * wd.geom[3] + ry * wd.geom[4]) + rz * wd.geom[5];
+                    double hl = 0.5 * wd.geom[7];
+                    double px = rx - ax * wd.geom[3], py = ry - ax * wd.geom[4], pz = rz - ax * wd.geom[5];
+                    double d2 = (px * px + py * py) + pz * pz;
+                    double T = wd.geom[6] + radA;
+                    touching = (ax <= hl && ax >= -hl) && d2 < T * T && d2 > 0.0;
+                    if (touching) {
+                        double d = sqrt(d2);
+                        nrm[0] = px / d;
+                        nrm[1] = py / d;
+                        nrm[2] = pz / d;
+                        delta = T - d;
+                        Rbar = (float)(radA * wd.geom[6] / (radA + wd.geom[6]));
+                    }
+                }
+                if (touching) {
+                    mbar = kA.mass;
+                    matB = (uint32_t)wd.mat;
+                    XB[0] = p[0];
+                    XB[1] = p[1];
+                    XB[2] = p[2];
+                    vB = f3((float)wd.vel[0], (float)wd.vel[1], (float)wd.vel[2]);
+                    wB = f3((float)wd.omega[0], (float)wd.omega[1], (float)wd.omega[2]);
+                }
+            }
+            if (!touching) {
+                hx[c] = 0.f;
+                hy[c] = 0.f;
+                hz[c] = 0.f;
+                bF[c] = 0.f;
+                bF[cap + c] = 0.f;
+                bF[2 * cap + c] = 0.f;
+                bT[c] = 0.f;
+                bT[cap + c] = 0.f;
+                bT[2 * cap + c] = 0.f;
+                continue;
+            }
+            // contact point in the middle of the overlap; arms to both owner centres
+            const double sc = radA - 0.5 * delta;
+            double cp[3] = {xA[0] - sc * nrm[0], xA[1] - sc * nrm[1], xA[2] - sc * nrm[2]};
+            const float3 armA = f3((float)(cp[0] - kA.X[0]), (float)(cp[1] - kA.X[1]), (float)(cp[2] - kA.X[2]));
+            const float3 armB = f3((float)(cp[0] - XB[0]), (float)(cp[1] - XB[1]), (float)(cp[2] - XB[2]));
+            const float3 n = f3((float)nrm[0], (float)nrm[1], (float)nrm[2]);
+            const MatPair mq = a.mat[(size_t)sA.mat * (size_t)a.n_mat + matB];
+            // relative velocity of A with respect to B at the contact point
+            const float3 u = (kA.v + cross3(kA.w, armA)) - (vB + cross3(wB, armB));
+            const float pn = dot3(u, n);
+            const float3 ut = u - pn * n;
+            float3 xi = f3(hx[c], hy[c], hz[c]);
+            xi = xi + hf * ut;
+            xi = xi - dot3(xi, n) * n;
+            const float df = (float)delta;
+            const float sqrtRd = sqrtf(Rbar * df);
+            const float Sn = 2.0f * mq.Estar * sqrtRd;
+            const float kn = (2.0f / 3.0f) * Sn;
+            const float c56 = 1.8257418583505538f;   // 2 sqrt(5/6)
+            const float gn = c56 * mq.beta * sqrtf(Sn * mbar);
+            float3 F = (kn * df + gn * pn) * n;
+            if (mq.mu > 0.0f) {
+                const float kt = 8.0f * mq.Gstar * sqrtRd;
+                const float gt = -c56 * mq.beta * sqrtf(mbar * kt);
+                float3 ft = (-kt) * xi - gt * ut;
+                const float ftn = sqrtf(dot3(ft, ft));
+                if (ftn > 1e-12f) {
+                    const float ftmax = sqrtf(dot3(F, F)) * mq.mu;
+                    if (ftn > ftmax) {
+                        ft = (ftmax / ftn) * ft;
+                        xi = (-1.0f / kt) * (ft + gt * ut);
+                    }
+                } else {
+                    ft = f3(0.f, 0.f, 0.f);
+                }
+                F = F + ft;
+            }
+            hx[c] = xi.x;
+            hy[c] = xi.y;
+            hz[c] = xi.z;
+            FA = FA + F;
+            TA = TA + cross3(armA, F);
+            const float3 mF = f3(-F.x, -F.y, -F.z);
+            const float3 tB = cross3(armB, mF);
+            bF[c] = mF.x;
+            bF[cap + c] = mF.y;
+            bF[2 * cap + c] = mF.z;
+            bT[c] = tB.x;
+            bT[cap + c] = tB.y;
+            bT[2 * cap + c] = tB.z;
+        }
+    }
+    aF[i] = FA.x;
+    aF[Ns + i] = FA.y;
+    aF[2 * Ns + i] = FA.z;
+    aT[i] = TA.x;
+    aT[Ns + i] = TA.y;
+    aT[2 * Ns + i] = TA.z;
+    (void)No;
+}
+
+__global__ void __launch_bounds__(TPB) k_fold_integrate(DynArgs a, const uint32_t *bstart,
+                                                        const uint32_t *bidx, const float *aF,
+                                                        const float *aT, const float *bF,
+                                                        const float *bT, int64_t cap, float *Fo,
+                                                        float *To, int integrate, DevCounters *ctr)
+{
+    if (stopped(ctr, a.step)) return;
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t Ns = a.n_spheres, No = a.n_owners;
+    const bool valid = o < No;
+    float v2 = 0.0f;
+    if (integrate && o == 0) {
+        ctr->last_step_done = a.step + 1;
+        ctr->maxv2[(a.step + 2) & 3] = 0u;
+    }
+    if (valid) {
+        float3 F = f3(0.f, 0.f, 0.f), T = f3(0.f, 0.f, 0.f);
+        const uint32_t s0 = a.own_sph0[o], s1 = a.own_sph0[o + 1];
+        for (uint32_t s = s0; s < s1; ++s) {
+            F = F + f3(aF[s], aF[Ns + s], aF[2 * Ns + s]);
+            T = T + f3(aT[s], aT[Ns + s], aT[2 * Ns + s]);
+            const uint32_t b1 = bstart[s + 1];
+            for (uint32_t b = bstart[s]; b < b1; ++b) {
+                const uint32_t c = bidx[b];
+                F = F + f3(bF[c], bF[cap + c], bF[2 * cap + c]);
+                T = T + f3(bT[c], bT[cap + c], bT[2 * cap + c]);
+            }
+        }
+        if (!integrate) {
+            Fo[o] = F.x;
+            Fo[No + o] = F.y;
+            Fo[2 * No + o] = F.z;
+            To[o] = T.x;
+            To[No + o] = T.y;
+            To[2 * No + o] = T.z;
+        } else {
+            OwnerRec r = load_rec(a.rec + o);
+            const OwnerAux ax = a.aux[o];
+            const float hf = (float)a.h;
+            const float m = r.mass;
+            float3 v = f3(r.v[0], r.v[1], r.v[2]);
+            v = v + hf * f3(F.x / m + a.g[0], F.y / m + a.g[1], F.z / m + a.g[2]);
+            float3 w = f3(r.w[0], r.w[1], r.w[2]);
+            if (ax.tmpl < 0) {
+                w = w + hf * f3(T.x * ax.inv_moi[0], T.y * ax.inv_moi[1], T.z * ax.inv_moi[2]);
+            } else {
+                double *qp = a.q + 4 * (size_t)o;
+                double4 qv = *reinterpret_cast<const double4 *>(qp);
+                Mat3d R = rot_from_q(qv.x, qv.y, qv.z, qv.w);
+                // torque into the body frame: R^T T
+                const float tbx = (float)((R.m[0] * (double)T.x + R.m[3] * (double)T.y) + R.m[6] * (double)T.z);
+                const float tby = (float)((R.m[1] * (double)T.x + R.m[4] * (double)T.y) + R.m[7] * (double)T.z);
+                const float tbz = (float)((R.m[2] * (double)T.x + R.m[5] * (double)T.y) + R.m[8] * (double)T.z);
+                w = w + hf * f3(tbx * ax.inv_moi[0], tby * ax.inv_moi[1], tbz * ax.inv_moi[2]);
+                // q <- normalize(q (x) exp(h w / 2)) in FP64
+                const double th0 = a.h * (double)w.x, th1 = a.h * (double)w.y, th2 = a.h * (double)w.z;
+                const double ang = sqrt((th0 * th0 + th1 * th1) + th2 * th2);
+                if (ang > 0.0) {
+                    const double sh = sin(0.5 * ang) / ang, ch = cos(0.5 * ang);
+                    const double b0 = ch, b1q = sh * th0, b2 = sh * th1, b3 = sh * th2;
+                    double n0 = qv.x * b0 - qv.y * b1q - qv.z * b2 - qv.w * b3;
+                    double n1 = qv.x * b1q + qv.y * b0 + qv.z * b3 - qv.w * b2;
+                    double n2 = qv.x * b2 - qv.y * b3 + qv.z * b0 + qv.w * b1q;
+                    double n3 = qv.x * b3 + qv.y * b2 - qv.z * b1q + qv.w * b0;
+                    const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2 + n3 * n3);
+                    *reinterpret_cast<double4 *>(qp) = make_double4(n0 / nn, n1 / nn, n2 / nn, n3 / nn);
+                }
+            }
+            // position: FP64 update, re-encoded on the 2^-38 m grid
+            uint32_t iv[3];
+            for (int k = 0; k < 3; ++k) {
+                const float vk = k == 0 ? v.x : (k == 1 ? v.y : v.z);
+                const double X = decode_axis(r.vox, r.off[k], a.org.o[k], k) + a.h * (double)vk;
+                encode_axis(X, a.org.o[k], &iv[k], &r.off[k]);
+            }
+            r.vox = pack_vox(iv[0], iv[1], iv[2]);
+            r.v[0] = v.x;
+            r.v[1] = v.y;
+            r.v[2] = v.z;
+            r.w[0] = w.x;
+            r.w[1] = w.y;
+            r.w[2] = w.z;
+            store_rec(a.rec + o, r);
+            v2 = dot3(v, v);
+            if (!(v2 == v2) || (a.v_err2 > 0.0f && v2 > a.v_err2) || !(dot3(w, w) == dot3(w, w)))
+                ctr->div[a.step & 1] = 1u;
+        }
+    }
+    if (integrate) {
+        // wave-wide max of |v|^2, one atomic per wave (order-free, exact)
+        if (!(v2 == v2)) v2 = 3.0e38f;
+        for (int d = 32; d > 0; d >>= 1) v2 = fmaxf(v2, __shfl_xor(v2, d, 64));
+        if ((threadIdx.x & 63) == 0) atomicMax(&ctr->maxv2[a.step & 3], __float_as_uint(v2));
+    }
+}
+
+}  // namespace
+
+void launch_force(const DynArgs &a, AcsBuf &cur, StepBufs &sb, DevCounters *ctr, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_force, dim3(nblocks(a.n_spheres)), dim3(TPB), 0, s, a, cur.start, cur.j, cur.hx,
+                       cur.hy, cur.hz, sb.aF, sb.aT, sb.bF, sb.bT, sb.cap, ctr);
+}
+
+void launch_fold_integrate(const DynArgs &a, const AcsBuf &cur, StepBufs &sb, DevCounters *ctr,
+                           int integrate, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fold_integrate, dim3(nblocks(a.n_owners)), dim3(TPB), 0, s, a, cur.bstart,
+                       cur.bidx, sb.aF, sb.aT, sb.bF, sb.bT, sb.cap, sb.Fo, sb.To, integrate, ctr);
+}

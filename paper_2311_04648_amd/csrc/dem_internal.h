@@ -1,0 +1,183 @@
+// Internal declarations shared by the HIP kernels and the host side of the
+// DEM library (gfx950).  Device data layout:
+//   owners   OwnerRec[No] (48 B, one 16-byte-aligned record per owner, so a
+//            gather of the other owner of a contact touches one record),
+//            OwnerAux[No] (inverse inertia + template), double4 q[No]
+//   spheres  SphRec[Ns] (owner, radius, material, template component)
+//   contacts per active-set buffer: acs_start[Ns+1] (CSR by lower sphere
+//            id), acs_j[cap] (partner: sphere id, or Ns + wall index),
+//            hist x/y/z [cap] (SoA float), B-side lists bstart/bidx
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define DEM_VOXEL_SIZE (1.0 / 16384.0)          // 2^-14 m
+#define DEM_VOXEL_INV 16384.0
+#define DEM_OFF_QUANT_INV 274877906944.0        // 2^38
+#define DEM_OFF_QUANT (1.0 / 274877906944.0)    // 2^-38 m
+#define DEM_OFF_STEPS 16777216.0                // 2^24 offset steps per voxel
+#define DEM_VOX_BITS 21
+#define DEM_VOX_MASK ((1ull << 21) - 1ull)
+#define DEM_NO_COMP 0xffffffffu
+
+struct __align__(16) OwnerRec {
+    uint64_t vox;      // voxel index, 3 x 21 bits (x low)
+    float off[3];      // offset inside the voxel, multiples of 2^-38 m
+    float v[3];        // velocity (m/s)
+    float w[3];        // angular velocity: body frame (clumps) / world frame (single spheres)
+    float mass;
+};
+static_assert(sizeof(OwnerRec) == 48, "owner record must be 48 bytes");
+
+struct __align__(16) OwnerAux {
+    float inv_moi[3];
+    int32_t tmpl;      // -1: single sphere at the owner centre
+};
+
+struct __align__(16) SphRec {
+    uint32_t owner;
+    float rad;
+    uint32_t mat;
+    uint32_t tcomp;    // index into the template component table, DEM_NO_COMP for single spheres
+};
+
+struct __align__(16) MatPair {
+    float Estar, Gstar, beta, mu;
+};
+
+struct __align__(16) WallDev {
+    double geom[8];
+    double vel[3];
+    double omega[3];
+    int32_t type;
+    int32_t mat;
+};
+
+// Candidate record in bin-sorted order: exact FP64 centre, radius, sphere id.
+struct __align__(16) Cand {
+    double x, y, z;
+    float r;
+    uint32_t id;
+};
+
+struct Grid {
+    double lo[3];
+    double inv_b;
+    int32_t nx, ny, nz;
+    uint32_t nbins;
+};
+
+struct Origin {
+    double o[3];
+};
+
+// Device counters (one block of device memory).
+struct DevCounters {
+    uint32_t n_contacts[2];   // size of each active-set buffer
+    uint32_t overflow[2];     // detection into buffer b overflowed
+    uint32_t required;        // largest set size asked for
+    uint32_t stop_cd;         // set at a swap when the adopted set overflowed
+    uint32_t div[2];          // divergence seen by the integrator, by step parity
+    uint32_t miss;            // judge: missing true contacts
+    uint32_t maxv2[4];        // max |v|^2 bits per step slot
+    uint32_t pad0;
+    int64_t last_step_done;
+    uint32_t ncell;           // feature cells in use
+    uint32_t pad1;
+};
+
+struct ScanTmp {
+    uint32_t *partials;  // >= ceil(n/4096)+1 entries
+};
+
+// ---------------------------------------------------------------------------
+// host-side launchers (implemented in the .hip files)
+// ---------------------------------------------------------------------------
+int64_t scan_tmp_elems(int64_t n);
+void launch_fill_u32(uint32_t *p, int64_t n, uint32_t value, hipStream_t s);
+void launch_copy_u32(uint32_t *dst, const uint32_t *src, int64_t n, hipStream_t s);
+// exclusive scan of in[0..n) into out[0..n], out[n] = total
+void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *partials,
+                        hipStream_t s);
+int64_t radix_hist_elems(int64_t n);
+// stable LSD radix sort of (keys, vals) on the low `bits` bits; result ends
+// in (keys, vals); alt buffers are scratch of the same size.
+void radix_sort_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
+                    int64_t n, int bits, uint32_t *hist, uint32_t *partials, hipStream_t s);
+
+struct DetectArgs {
+    const OwnerRec *rec;
+    const double *q;        // 4 per owner
+    const OwnerAux *aux;
+    const SphRec *sph;
+    const float *tpos;      // 4 per template component
+    const WallDev *walls;
+    int32_t n_walls;
+    int64_t n_spheres;
+    Grid grid;
+    Origin org;
+    double margin;
+    double h;
+    int64_t step;
+};
+
+struct CdWork {
+    uint32_t *keys, *vals, *keys_alt, *vals_alt;
+    Cand *cand_tmp, *cand;
+    uint32_t *cell_count, *cell_start;
+    uint32_t *count;       // [Ns+1]
+    uint32_t *hist, *partials;
+    int sort_bits;
+};
+
+struct AcsBuf {
+    uint32_t *start;   // [Ns+1]
+    uint32_t *j;       // [cap]
+    float *hx, *hy, *hz;
+    uint32_t *bstart;  // [Ns+1]
+    uint32_t *bidx;    // [cap]
+    uint32_t *bcur;    // [Ns+1] scratch cursor
+};
+
+void launch_bin(const DetectArgs &a, CdWork &w, hipStream_t s);
+// full detection into `out` (count, scan, write, sort rows, B lists)
+void launch_detect(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap, DevCounters *ctr,
+                   int buf, hipStream_t s);
+void launch_judge(const DetectArgs &a, CdWork &w, const AcsBuf &cur, int64_t cap, DevCounters *ctr,
+                  hipStream_t s);
+void launch_blists(AcsBuf &b, int64_t n_spheres, int64_t cap, uint32_t *partials, hipStream_t s);
+void launch_remap(const AcsBuf &oldb, AcsBuf &newb, int64_t n_spheres, DevCounters *ctr, int newbuf,
+                  hipStream_t s);
+
+struct DynArgs {
+    OwnerRec *rec;
+    double *q;
+    const OwnerAux *aux;
+    const uint32_t *own_sph0;
+    const SphRec *sph;
+    const float *tpos;
+    const WallDev *walls;
+    const MatPair *mat;
+    int32_t n_mat;
+    int32_t n_walls;
+    int64_t n_owners, n_spheres;
+    Origin org;
+    double h;
+    float g[3];
+    float v_err2;
+    int64_t step;
+    int32_t has_clumps;
+};
+
+struct StepBufs {
+    float *aF, *aT;          // per sphere: 3 floats each (SoA: x[Ns], y[Ns], z[Ns])
+    float *bF, *bT;          // per contact: 3 floats each (SoA, cap stride)
+    float *Fo, *To;          // per owner output of dem_forces (SoA, No stride)
+    int64_t cap;
+};
+
+void launch_force(const DynArgs &a, AcsBuf &cur, StepBufs &sb, DevCounters *ctr, hipStream_t s);
+void launch_fold_integrate(const DynArgs &a, const AcsBuf &cur, StepBufs &sb, DevCounters *ctr,
+                           int integrate, hipStream_t s);
+

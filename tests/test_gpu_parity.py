@@ -1,0 +1,383 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (derived from the arithmetic, see the design notes):
+  * contact pair sets: bit-exact (both sides evaluate the same FP64 predicate
+    on the same exact sphere centres);
+  * per-contact force / torque: |F_gpu - F_orc| <= 1e-5 max(|F_orc|, 1e-3 F_med)
+    (FP32 force law, FP64 overlap);
+  * one-step increments: |d_gpu - d_orc| <= 1e-5 |d_orc| + a storage floor:
+    X on a 2^-38 m grid, velocities stored in FP32 (half an ulp of the new
+    value) plus 1e-5 of the summed contact-force magnitudes of the owner
+    (reductions of cancelling terms).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dem():
+    import paper_2311_04648_amd as d
+    if not os.path.exists(d.LIB_PATH):
+        from paper_2311_04648_amd import build
+        build.build()
+    d._torch()
+    return d
+
+
+def systems():
+    return {
+        "spheres": W.small_spheres(1, n=343),
+        "clumps": W.small_clumps(2, n=150, with_cylinder=True, spacing=0.0085),
+        "config0": W.config0(),
+        "spheres_ragged": W.small_spheres(3, n=1001, r=(0.0015, 0.004)),
+    }
+
+
+SYS = systems()
+
+
+def _gpu_state(ctx):
+    g = ctx.get_state()
+    return {k: np.asarray(g[k], dtype=np.float64) for k in ("X", "q", "V", "W")}, g["step"]
+
+
+def _world_w(s, st):
+    """Angular velocity in the world frame (oracle layout: body frame + q)."""
+    from scipy.spatial.transform import Rotation
+    R = Rotation.from_quat(st["q"][:, [1, 2, 3, 0]]).as_matrix()
+    return np.einsum("nij,nj->ni", R, st["W"])
+
+
+def _gpu_world_w(s, g):
+    w = np.asarray(g["W"], dtype=np.float64)
+    clump = s.own_tmpl >= 0
+    if clump.any():
+        from scipy.spatial.transform import Rotation
+        R = Rotation.from_quat(g["q"][clump][:, [1, 2, 3, 0]]).as_matrix()
+        w[clump] = np.einsum("nij,nj->ni", R, w[clump])
+    return w
+
+
+def _orc_state_from_gpu(s, g):
+    """The oracle takes the GPU's stored state; single spheres carry their
+    world-frame angular velocity with q = identity."""
+    return {"X": g["X"].copy(), "q": g["q"].copy(), "V": g["V"].astype(np.float64),
+            "W": g["W"].astype(np.float64)}
+
+
+@pytest.mark.parametrize("name", list(SYS))
+def test_state_roundtrip_exact(dem, name):
+    s = SYS[name]
+    ctx = dem.DemContext(s, mode="every")
+    ctx.set_state()
+    g = ctx.get_state()
+    np.testing.assert_array_equal(g["X"], s.X)
+    np.testing.assert_array_equal(g["V"], s.V.astype(np.float32))
+    clump = s.own_tmpl >= 0
+    np.testing.assert_array_equal(g["q"][clump], s.q[clump])
+
+
+@pytest.mark.parametrize("name", list(SYS))
+def test_binning_sort_is_stable_permutation(dem, name):
+    s = SYS[name]
+    ctx = dem.DemContext(s, mode="every")
+    ctx.set_state()
+    keys, ids = ctx.bin()
+    assert np.all(np.diff(keys.astype(np.int64)) >= 0)
+    assert np.array_equal(np.sort(ids), np.arange(s.n_spheres))
+    same = np.diff(keys.astype(np.int64)) == 0
+    assert np.all(np.diff(ids.astype(np.int64))[same] > 0)
+
+
+@pytest.mark.parametrize("name", list(SYS))
+@pytest.mark.parametrize("margin_scale", [0.0, 1.0])
+def test_contact_sets_bit_exact(dem, name, margin_scale):
+    s = SYS[name]
+    m = margin_scale * (s.margin if s.margin > 0 else 0.001)
+    ctx = dem.DemContext(s, mode="fixed", margin=max(m, 1e-4))
+    ctx.set_state()
+    n = ctx.detect_contacts(m)
+    keys, hist = ctx.get_contacts()
+    assert n == keys.size
+    o = oracle.Oracle(s)
+    ref = o.detect(o.state(), m)
+    assert ref.size > 0 or (name == "config0" and m == 0.0)
+    np.testing.assert_array_equal(keys, ref)
+    assert np.all(hist == 0)
+
+
+def _force_case(dem, s, seed=0, presteps=0):
+    ctx = dem.DemContext(s, mode="fixed", margin=max(s.margin, 1e-4))
+    ctx.set_state()
+    if presteps:
+        ctx.step(presteps)
+    ctx.detect_contacts(max(s.margin, 1e-4))
+    keys, _ = ctx.get_contacts()
+    rng = np.random.default_rng(seed)
+    hist = W.f32(rng.normal(0.0, 3e-6, size=(keys.size, 3))).astype(np.float32)
+    ctx.set_contacts(keys, hist)
+    ctx.forces()
+    Fo, To, Fc = ctx.get_forces(keys.size)
+    k2, h2 = ctx.get_contacts()
+    g = ctx.get_state()
+    o = oracle.Oracle(s)
+    ost = _orc_state_from_gpu(s, g)
+    ref = o.forces(ost, keys, hist.astype(np.float64), step=g["step"])
+    return keys, Fo, To, Fc, h2, ref
+
+
+@pytest.mark.parametrize("name", list(SYS))
+def test_forces_match_oracle(dem, name):
+    s = SYS[name]
+    keys, Fo, To, Fc, h2, ref = _force_case(dem, s, presteps=1500 if name == "config0" else 0)
+    touch = ref["touch"] > 0
+    assert touch.sum() > 10
+    Fn = np.linalg.norm(ref["Fc"], axis=1)
+    Fmed = np.median(Fn[touch])
+    err = np.linalg.norm(Fc - ref["Fc"], axis=1)
+    rel = err / np.maximum(Fn, 1e-3 * Fmed)
+    print(f"{name}: contacts {keys.size} touching {touch.sum()} max rel F err {rel.max():.2e} "
+          f"median {np.median(rel[touch]):.2e}")
+    assert rel.max() <= 1e-5
+    # false positives: exactly zero force and released history
+    assert np.all(Fc[~touch] == 0.0)
+    assert np.all(h2[~touch] == 0.0)
+    # history
+    hn = np.linalg.norm(ref["hist"], axis=1)
+    hmed = np.median(hn[touch]) if touch.any() else 1.0
+    herr = np.linalg.norm(h2 - ref["hist"], axis=1) / np.maximum(hn, 1e-3 * hmed)
+    assert herr.max() <= 1e-5
+    # owner sums: tolerance relative to the summed magnitudes of the terms
+    own = s.sph_owner
+    ks = (keys >> np.uint64(32)).astype(np.int64)
+    L1 = np.zeros(s.n_owners)
+    np.add.at(L1, own[ks], Fn)
+    js = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    sph = js < s.n_spheres
+    np.add.at(L1, own[js[sph]], Fn[sph])
+    ferr = np.linalg.norm(Fo - ref["Fo"], axis=1)
+    assert np.all(ferr <= 1e-5 * np.maximum(L1, 1e-3 * Fmed) + 1e-30)
+    terr = np.linalg.norm(To - ref["To"], axis=1)
+    Tscale = L1 * 0.006
+    assert np.all(terr <= 1e-5 * np.maximum(Tscale, 1e-3 * Fmed * 0.003) + 1e-30)
+
+
+@pytest.mark.parametrize("name", list(SYS))
+def test_one_step_matches_oracle(dem, name):
+    s = SYS[name]
+    ctx = dem.DemContext(s, mode="every")
+    ctx.set_state()
+    g0 = ctx.get_state()
+    st = _orc_state_from_gpu(s, g0)
+    ctx.step(1)
+    g1 = ctx.get_state()
+    o = oracle.Oracle(s)
+    before = {k: v.copy() for k, v in st.items()}
+    st1, acs, stats, _ = o.run(st, 1, mode="every")
+    keys = acs[0]
+    # per-owner L1 norm of contact forces (tolerance floor for sums)
+    out = o.forces(before, keys, np.zeros((keys.size, 3)))
+    Fn = np.linalg.norm(out["Fc"], axis=1)
+    L1 = np.zeros(s.n_owners)
+    ks = (keys >> np.uint64(32)).astype(np.int64)
+    js = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    np.add.at(L1, s.sph_owner[ks], Fn)
+    sph = js < s.n_spheres
+    np.add.at(L1, s.sph_owner[js[sph]], Fn[sph])
+    h = s.dt
+    # velocity
+    dv_g = g1["V"].astype(np.float64) - before["V"]
+    dv_o = st1["V"] - before["V"]
+    tol_v = 1e-5 * np.linalg.norm(dv_o, axis=1) + 0.5 * np.spacing(np.abs(g1["V"]).max(1).astype(np.float32)) \
+        * 2 + 1e-5 * h * L1 / s.own_mass
+    assert np.all(np.linalg.norm(dv_g - dv_o, axis=1) <= tol_v)
+    # position
+    dx_g = g1["X"] - before["X"]
+    dx_o = st1["X"] - before["X"]
+    tol_x = 1e-5 * np.linalg.norm(dx_o, axis=1) + h * np.linalg.norm(dv_g - dv_o, axis=1) + 2.0 ** -37
+    assert np.all(np.linalg.norm(dx_g - dx_o, axis=1) <= tol_x)
+    # angular velocity (world frame)
+    w0 = _world_w(s, before)
+    wg = _gpu_world_w(s, g1)
+    wo = _world_w(s, st1)
+    dw_g, dw_o = wg - w0, wo - w0
+    Iinv = 1.0 / s.own_moi.min(1)
+    tol_w = 1e-5 * np.linalg.norm(dw_o, axis=1) + 4 * np.spacing(np.abs(wg).max(1).astype(np.float32)) \
+        + 1e-5 * h * L1 * 0.01 * Iinv
+    assert np.all(np.linalg.norm(dw_g - dw_o, axis=1) <= tol_w)
+    clump = s.own_tmpl >= 0
+    if clump.any():
+        dq_g = g1["q"][clump] - before["q"][clump]
+        dq_o = st1["q"][clump] - before["q"][clump]
+        tol_q = 1e-5 * np.linalg.norm(dq_o, axis=1) + h * np.linalg.norm(dw_g - dw_o, axis=1)[clump] + 1e-15
+        assert np.all(np.linalg.norm(dq_g - dq_o, axis=1) <= tol_q)
+
+
+def test_delayed_equals_every_step_bitwise(dem):
+    """Sec. 2.1: delayed detection with a sufficient margin reproduces the
+    every-step trajectory exactly (false positives add exact zeros, the
+    per-owner fold runs in a fixed order)."""
+    s = W.small_spheres(5, n=512, vel=0.3)
+    a = dem.DemContext(s, mode="every")
+    a.set_state()
+    a.step(200)
+    b = dem.DemContext(s, mode="fixed", k=10, lam=5, judge=True)
+    b.set_state()
+    stats = b.step(200)
+    assert stats["misses"] == 0 and stats["cds"] == 20
+    ga, gb = a.get_state(), b.get_state()
+    for k in ("X", "V", "W", "q"):
+        np.testing.assert_array_equal(ga[k], gb[k])
+
+
+def test_delayed_two_streams_equals_every_step_bitwise(dem):
+    import torch
+    s = W.small_clumps(6, n=216, vel=0.3)
+    a = dem.DemContext(s, mode="every")
+    a.set_state()
+    a.step(150)
+    b = dem.DemContext(s, mode="fixed", k=8, lam=4)
+    b.set_state()
+    dyn, kin = torch.cuda.Stream(), torch.cuda.Stream()
+    b.step(150, dyn=dyn, kin=kin)
+    ga, gb = a.get_state(), b.get_state()
+    for k in ("X", "V", "W", "q"):
+        np.testing.assert_array_equal(ga[k], gb[k])
+
+
+def test_judge_counts_misses_and_repair_restores_exactness(dem):
+    s = W.small_spheres(7, n=343, vel=1.0, margin=1e-6)
+    a = dem.DemContext(s, mode="every")
+    a.set_state()
+    a.step(120)
+    b = dem.DemContext(s, mode="fixed", k=30, lam=10, judge=True, repair=True)
+    b.set_state()
+    stats = b.step(120)
+    assert stats["misses"] > 0 and stats["repairs"] > 0
+    ga, gb = a.get_state(), b.get_state()
+    for k in ("X", "V", "W"):
+        np.testing.assert_array_equal(ga[k], gb[k])
+
+
+def test_judge_without_repair_reports_missed(dem):
+    s = W.small_spheres(7, n=343, vel=1.0, margin=1e-6)
+    b = dem.DemContext(s, mode="fixed", k=30, lam=10, judge=True, repair=False)
+    b.set_state()
+    with pytest.raises(dem.DemError) as e:
+        b.step(120)
+    assert e.value.status == dem.DEM_ERR_MISSED
+
+
+def test_run_is_deterministic(dem):
+    s = W.small_clumps(8, n=216, vel=0.5)
+    outs = []
+    for _ in range(2):
+        c = dem.DemContext(s, mode="fixed", k=10, lam=3)
+        c.set_state()
+        c.step(100)
+        outs.append(c.get_state())
+    for k in ("X", "V", "W", "q"):
+        np.testing.assert_array_equal(outs[0][k], outs[1][k])
+
+
+def test_resume_from_checkpoint_is_bitwise(dem):
+    s = W.small_spheres(9, n=343, vel=0.3)
+    a = dem.DemContext(s, mode="every")
+    a.set_state()
+    a.step(60)
+    b = dem.DemContext(s, mode="every")
+    b.set_state()
+    b.step(30)
+    g = b.get_state()
+    keys, hist = b.get_contacts()
+    c = dem.DemContext(s, mode="every")
+    c.set_state(g["X"], g["q"], g["V"], g["W"], step=g["step"])
+    c.set_contacts(keys, hist)
+    c.step(30)
+    ga, gc = a.get_state(), c.get_state()
+    for k in ("X", "V", "W"):
+        np.testing.assert_array_equal(ga[k], gc[k])
+
+
+def test_capacity_error_reports_required_size(dem):
+    s = W.small_spheres(1, n=343)
+    ctx = dem.DemContext(s, mode="every", capacity=20)
+    ctx.set_state()
+    with pytest.raises(dem.DemError) as e:
+        ctx.detect_contacts(0.0)
+    assert e.value.status == dem.DEM_ERR_CAPACITY
+    need = e.value.required
+    o = oracle.Oracle(s)
+    assert need == o.detect(o.state(), 0.0).size
+    ctx.bind(need + 10)
+    ctx.set_state()
+    assert ctx.detect_contacts(0.0) == need
+
+
+def test_capacity_overflow_during_steps_stops(dem):
+    s = W.small_spheres(1, n=343)
+    ctx = dem.DemContext(s, mode="every", capacity=20)
+    ctx.set_state()
+    with pytest.raises(dem.DemError) as e:
+        ctx.step(5)
+    assert e.value.status == dem.DEM_ERR_CAPACITY
+    g = ctx.get_state()
+    np.testing.assert_array_equal(g["X"], s.X)
+
+
+def test_divergence_guard(dem):
+    s = W.small_spheres(1, n=343, vel=0.5)
+    ctx = dem.DemContext(s, mode="every", v_error_out=0.05)
+    ctx.set_state()
+    with pytest.raises(dem.DemError) as e:
+        ctx.step(5)
+    assert e.value.status == dem.DEM_ERR_DIVERGED
+
+
+def test_count_missing_matches_oracle(dem):
+    s = W.small_spheres(4, n=343, vel=1.0)
+    ctx = dem.DemContext(s, mode="fixed", k=10, lam=0)
+    ctx.set_state()
+    ctx.detect_contacts(0.0)
+    keys0, _ = ctx.get_contacts()
+    ctx2 = dem.DemContext(s, mode="every")
+    ctx2.set_state()
+    ctx2.step(40)
+    g = ctx2.get_state()
+    ctx.set_state(g["X"], g["q"], g["V"], g["W"], step=g["step"])
+    ctx.set_contacts(keys0)
+    miss = ctx.count_missing()
+    o = oracle.Oracle(s)
+    ref = o.count_missing(_orc_state_from_gpu(s, g), keys0, step=g["step"])
+    assert miss == ref and miss > 0
+
+
+def test_config0_side_by_side_statistics(dem):
+    """Config 0 (1,000 spheres, every-step detection) on both sides: the
+    trajectories are chaotic, so bulk statistics are compared."""
+    s = W.config0()
+    ctx = dem.DemContext(s, mode="every")
+    ctx.set_state()
+    o = oracle.Oracle(s)
+    st = o.state()
+    ke_g, ke_o = [], []
+    step = 0
+    acs = None
+    for blk in range(4):
+        ctx.step(500)
+        st, acs, _, step = o.run(st, 500, mode="every", acs=acs, step=step)
+        g = ctx.get_state()
+        ke_g.append(0.5 * (s.own_mass * (g["V"].astype(np.float64) ** 2).sum(1)).sum())
+        ke_o.append(0.5 * (s.own_mass * (st["V"] ** 2).sum(1)).sum())
+        zg, zo = g["X"][:, 2].mean(), st["X"][:, 2].mean()
+        assert abs(zg - zo) < 2e-4
+    ke_g, ke_o = np.array(ke_g), np.array(ke_o)
+    assert np.all(np.abs(ke_g - ke_o) <= 0.05 * ke_o + 1e-9)
