@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Benchmark of the DEM hot path on one MI355X.
+
+Workload: 1,000,000 polydisperse spheres, r ~ U(2, 3) mm, on a jittered
+7.5 mm lattice in a 0.6 x 0.6 x 1.2 m box, settling under gravity;
+dt = 5e-6 s; margin 0.1 r_min = 0.2 mm; delayed contact detection every 10
+steps on a second HIP stream (the fixed-margin schedule).  One "step" is
+contact detection (amortised over its interval) + force + reduction +
+integration for all spheres.  The same workload is also timed with
+every-step detection and with the learned interval.
+
+Prints one JSON line: sphere-steps/s of the fixed-margin schedule as
+`value`, the other schedules under `modes`, the roofline of the dominant
+kernel (live HIP-event timing of that kernel over the timed region), and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+STAGES = ["k_force", "k_fold_integrate", "detect", "k_remap"]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--n", type=int, default=1_000_000, help="spheres (workload size)")
+    ap.add_argument("--modes", default="fixed,every,learned")
+    ap.add_argument("--no-judge", action="store_true", help="skip the judged (miss-counting) runs")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-steps", type=int, default=50)
+    ap.add_argument("--k", type=int, default=10)
+    ap.add_argument("--lam", type=int, default=5)
+    return ap.parse_args()
+
+
+def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes):
+    """Bytes one launch of a stage must move at minimum (unique data):
+    k_force: per sphere the row offsets (4) and the A-side sums written
+      (24); per sphere that has a contact its record (16) and its owner's
+      record (48); per contact the partner id (4), history read+write (24)
+      and the B-side reaction written (24).
+    k_fold_integrate: per owner the record read+write (96), inverse inertia
+      and template (16), sphere range (4); per sphere the A-side sums (24)
+      and B-list offsets (4); per sphere-sphere contact the B-list entry (4)
+      and the reaction (24).
+    detect: per sphere record + owner record (64), key/id (8) written,
+      candidate (32) written, radix passes (16 each), candidate gather (36 r
+      + 32 w), count/write passes (2 x 32 candidate reads + 8 offsets), B
+      lists (16); per contact partner id (4) and B-list bytes (16); the bin
+      table (8 per bin).
+    k_remap: per sphere both row offsets (16); per contact new id (4), old id
+      (4), history read (12) and written (12)."""
+    if stage == "k_force":
+        return Ns * 28 + active * 64 + C * 52
+    if stage == "k_fold_integrate":
+        return No * 116 + Ns * 28 + C * 28
+    if stage == "detect":
+        return Ns * (64 + 8 + 32 + 16 * passes + 68 + 72 + 16) + C * 20 + nbins * 8
+    if stage == "k_remap":
+        return Ns * 16 + C * 32
+    raise ValueError(stage)
+
+
+def source_sha(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(kernel):
+    """HBM bytes per launch from committed rocprofv3 PMC summaries, if they
+    were taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "traffic_config1.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+        ent = d.get(kernel)
+        if not ent:
+            return None
+        src = os.path.join(ROOT, "paper_2311_04648_amd", "csrc", ent["source"])
+        if source_sha(src) != ent["source_sha"]:
+            return None
+        return float(ent["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def run_mode(dem, torch, sysm, mode, args, mlp=None, judge=False):
+    ctx = dem.DemContext(sysm, mode=mode, k=args.k, lam=args.lam, judge=judge, timing=not judge,
+                         capacity=max(64, 8 * sysm.n_spheres), k_max=256)
+    if mode == "learned":
+        ctx.mlp_set(mlp)
+    ctx.set_state()
+    dyn, kin = torch.cuda.Stream(), torch.cuda.Stream()
+    if args.warmup:
+        ctx.step(args.warmup, dyn=dyn, kin=kin)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = ctx.step(args.steps, dyn=dyn, kin=kin)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    info = ctx.info()
+    keys, _ = ctx.get_contacts()
+    ii = (keys >> np.uint64(32)).astype(np.int64)
+    jj = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    active = np.unique(np.concatenate([ii, jj[jj < sysm.n_spheres]])).size
+    ctx.close()
+    del ctx
+    return dict(seconds=t1 - t0, stats=stats, info=info, active=int(active))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import paper_2311_04648_amd as dem
+    import workloads as W
+
+    if not os.path.exists(dem.LIB_PATH):
+        from paper_2311_04648_amd import build
+        build.build()
+    torch.cuda.init()
+    t_gen = time.perf_counter()
+    sysm = W.config1(seed=0, n=args.n)
+    print(f"# workload generated: {sysm.n_spheres} spheres in {time.perf_counter() - t_gen:.1f}s",
+          file=sys.stderr, flush=True)
+    Ns, No = sysm.n_spheres, sysm.n_owners
+    mlp = None
+    mlp_path = os.path.join(ROOT, "paper_2311_04648_amd", "mlp_interval.json")
+    if os.path.exists(mlp_path):
+        mlp = np.array(json.load(open(mlp_path))["params"], dtype=np.float32)
+
+    modes = [m for m in args.modes.split(",") if m]
+    results = {}
+    for mode in modes:
+        r = run_mode(dem, torch, sysm, mode, args, mlp=mlp)
+        st = r["stats"]
+        rate = Ns * args.steps / r["seconds"]
+        results[mode] = r
+        print(f"# {mode}: {rate:.4g} sphere-steps/s, {1e3 * r['seconds'] / args.steps:.4f} ms/step, "
+              f"cds {st['cds']}, mean interval {st['mean_interval']:.1f}, mean set {st['mean_contacts']:.0f}, "
+              f"stage ms {['%.2f' % x for x in st['stage_ms']]} n {st['stage_n']}",
+              file=sys.stderr, flush=True)
+    misses = {}
+    if not args.no_judge:
+        for mode in modes:
+            if mode == "every":
+                misses[mode] = 0
+                continue
+            ctx = dem.DemContext(sysm, mode=mode, k=args.k, lam=args.lam, judge=True,
+                                 capacity=max(64, 8 * Ns), k_max=256)
+            if mode == "learned":
+                ctx.mlp_set(mlp)
+            ctx.set_state()
+            st = ctx.step(args.warmup + args.steps)
+            misses[mode] = int(st["misses"])
+            ctx.close()
+            print(f"# judged {mode}: misses {st['misses']} repairs {st['repairs']}", file=sys.stderr, flush=True)
+
+    head = "fixed" if "fixed" in results else modes[0]
+    r = results[head]
+    st = r["stats"]
+    value = Ns * args.steps / r["seconds"]
+    # dominant kernel of the headline run, timed live with HIP events
+    tot = st["stage_ms"]
+    dom = int(np.argmax(tot))
+    n_launch = max(int(st["stage_n"][dom]), 1)
+    avg_ms = tot[dom] / n_launch
+    C = st["mean_contacts"]
+    passes = ((r["info"]["sort_bits"] + 7) // 8 + 1) // 2 * 2
+    algo = algorithmic_bytes(STAGES[dom], Ns, No, C, r["active"], r["info"]["nbins"], passes)
+    achieved = algo / (avg_ms * 1e-3) / 1e9
+    traffic = load_traffic(STAGES[dom])
+    roofline = {"bound": "hbm", "kernel": STAGES[dom], "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes_per_launch": int(algo), "avg_launch_ms": round(avg_ms, 5),
+                "launches": n_launch}
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        o = oracle.Oracle(sysm)
+        ost = o.state()
+        t0 = time.perf_counter()
+        o.run(ost, args.cpu_steps, mode="fixed", k=args.k, lam=args.lam)
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(Ns * args.cpu_steps / dt, 1), "unit": "sphere-steps/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"same workload, first {args.cpu_steps} steps of the fixed-margin schedule "
+                         f"(k={args.k}) from the initial state, single-threaded FP64 C oracle, {dt:.1f} s"}
+        print(f"# cpu oracle: {cpu['value']:.4g} sphere-steps/s in {dt:.1f}s", file=sys.stderr, flush=True)
+
+    modes_out = {}
+    for mode, rr in results.items():
+        s2 = rr["stats"]
+        modes_out[mode] = {"value": round(Ns * args.steps / rr["seconds"], 1),
+                           "ms_per_step": round(1e3 * rr["seconds"] / args.steps, 5),
+                           "cds": int(s2["cds"]), "mean_interval": round(s2["mean_interval"], 2),
+                           "mean_contacts": round(s2["mean_contacts"], 1),
+                           "missed_contacts": misses.get(mode),
+                           "stage_ms": [round(x, 3) for x in s2["stage_ms"]],
+                           "stage_launches": [int(x) for x in s2["stage_n"]]}
+    out = {
+        "metric": "sphere-steps/s (CD+force+integrate) at 1 GPU; learned vs fixed-margin CD",
+        "value": round(value, 1),
+        "unit": "sphere-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * r["seconds"] / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{Ns} polydisperse spheres r~U(2,3) mm settling from a jittered 7.5 mm lattice "
+                               f"in a 0.6x0.6x1.2 m box, dt 5e-6 s, margin 0.2 mm, delayed CD every {args.k} "
+                               f"steps on a second HIP stream (adoption latency {args.lam})",
+                   "n_spheres": Ns, "schedule": head, "k": args.k, "lambda": args.lam},
+        "modes": modes_out,
+        "missed_contacts": misses.get(head),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

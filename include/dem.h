@@ -135,6 +135,7 @@ typedef struct {
     int32_t judge;          /* 1: count contacts missing from the set in use, every step */
     int32_t repair;         /* 1: a missed contact discards the stale set (default) */
     int32_t cd_interval_max;/* LEARNED: upper bound on the interval */
+    int32_t timing;         /* 1: time each kernel stage with HIP events (stats->stage_ms) */
 } dem_params;
 
 /* Statistics of a dem_step call (Sec. 2.1, thread collaboration stats). */
@@ -150,6 +151,13 @@ typedef struct {
     double max_speed;       /* largest owner speed seen at the last step */
     double ms;              /* wall time of the call */
     double mean_interval;   /* mean steps between work orders */
+    /* with params.timing: summed device time and launch count per stage,
+     * measured with HIP events on the stream the stage runs on:
+     * [0] force kernel, [1] fold + integrate kernel, [2] contact detection
+     * (bin, sort, detect, B lists), [3] history remap */
+    double stage_ms[4];
+    int64_t stage_n[4];
+    double mean_contacts;   /* mean size of the active set over the steps */
 } dem_step_stats;
 
 /* Creates a context for one problem.  Copies every array it is given.

@@ -34,7 +34,8 @@ class Params(C.Structure):
     _fields_ = [("gravity", C.c_double * 3), ("dt", C.c_double), ("margin", C.c_double),
                 ("v_error_out", C.c_double), ("domain_lo", C.c_double * 3), ("domain_hi", C.c_double * 3),
                 ("cd_mode", C.c_int32), ("cd_interval", C.c_int32), ("cd_latency", C.c_int32),
-                ("judge", C.c_int32), ("repair", C.c_int32), ("cd_interval_max", C.c_int32)]
+                ("judge", C.c_int32), ("repair", C.c_int32), ("cd_interval_max", C.c_int32),
+                ("timing", C.c_int32)]
 
 
 class Materials(C.Structure):
@@ -61,10 +62,14 @@ class StepStats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("step", C.c_int64), ("cds", C.c_int64), ("swaps", C.c_int64),
                 ("misses", C.c_int64), ("repairs", C.c_int64), ("n_contacts", C.c_int64),
                 ("required_capacity", C.c_int64), ("max_speed", C.c_double), ("ms", C.c_double),
-                ("mean_interval", C.c_double)]
+                ("mean_interval", C.c_double), ("stage_ms", C.c_double * 4), ("stage_n", C.c_int64 * 4),
+                ("mean_contacts", C.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["stage_ms"] = list(self.stage_ms)
+        d["stage_n"] = list(self.stage_n)
+        return d
 
 
 _lib = None
@@ -142,7 +147,7 @@ class DemContext:
     """One DEM problem bound to caller-owned device memory (a torch tensor)."""
 
     def __init__(self, system, mode="every", k=10, lam=5, judge=False, repair=True, capacity=None,
-                 margin=None, v_error_out=0.0, k_max=None, device="cuda:0"):
+                 margin=None, v_error_out=0.0, k_max=None, device="cuda:0", timing=False):
         torch = _torch()
         self.torch = torch
         self.device = torch.device(device)
@@ -170,6 +175,7 @@ class DemContext:
         P.judge = int(bool(judge))
         P.repair = int(bool(repair))
         P.cd_interval_max = int(k_max or 16 * max(int(k), 1))
+        P.timing = int(bool(timing))
         self.params = P
         Mt = Materials(int(np.asarray(s.mat_E).shape[0]), keep(s.mat_E, np.float64), keep(s.mat_nu, np.float64),
                        keep(s.mat_cor, np.float64), keep(s.mat_mu, np.float64), keep(s.mat_crr, np.float64))

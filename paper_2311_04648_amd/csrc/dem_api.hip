@@ -58,6 +58,7 @@ struct dem_ctx {
     DevCounters *ctr = nullptr;
     DevCounters *h_ctr = nullptr;
     // learned interval
+    float *d_blkmax = nullptr;
     float *d_mlp = nullptr;
     float *d_feat = nullptr, *d_pred = nullptr;
     uint32_t *d_cellmap = nullptr;    // feature cell of each owner [No]
@@ -79,6 +80,15 @@ struct dem_ctx {
     hipEvent_t ev_wo = nullptr, ev_cd = nullptr;
     int64_t n_wo = 0;
     double interval_sum = 0.0;
+    // stage timing (params.timing): a ring of event pairs, drained lazily
+    struct TimedPair {
+        hipEvent_t a = nullptr, b = nullptr;
+        int kind = -1;
+    };
+    std::vector<TimedPair> ring;
+    size_t ring_pos = 0;
+    double stage_ms[4] = {0, 0, 0, 0};
+    int64_t stage_n[4] = {0, 0, 0, 0};
 };
 
 #define HIPCHK(expr)                                                                   \
@@ -171,6 +181,7 @@ void carve(Carver &c, dem_ctx *ctx, int64_t cap)
     ctx->sb.Fo = c.take<float>(3 * No);
     ctx->sb.To = c.take<float>(3 * No);
     ctx->sb.cap = cap;
+    ctx->d_blkmax = c.take<float>((No + 255) / 256 + 1);
     carve_cd(c, ctx, ctx->cdK);
     carve_cd(c, ctx, ctx->cdD);
     ctx->ctr = c.take<DevCounters>(1);
@@ -227,6 +238,8 @@ DynArgs dyn_args(const dem_ctx *ctx, int64_t step)
     a.v_err2 = (float)(ctx->P.v_error_out * ctx->P.v_error_out);
     a.step = step;
     a.has_clumps = ctx->has_clumps ? 1 : 0;
+    a.cur = ctx->cur;
+    a.blkmax = ctx->d_blkmax;
     return a;
 }
 
@@ -250,6 +263,45 @@ void clear_set(dem_ctx *ctx, int b, hipStream_t s)
 {
     launch_fill_u32(ctx->acs[b].start, ctx->Ns + 1, 0u, s);
     launch_fill_u32(ctx->acs[b].bstart, ctx->Ns + 1, 0u, s);
+}
+
+void drain_pair(dem_ctx *ctx, dem_ctx::TimedPair &p)
+{
+    if (p.kind < 0) return;
+    float ms = 0.0f;
+    hipEventSynchronize(p.b);
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        ctx->stage_ms[p.kind] += ms;
+        ctx->stage_n[p.kind] += 1;
+    }
+    p.kind = -1;
+}
+
+// Opens a timed stage on stream s; returns the pair to close (or null).
+dem_ctx::TimedPair *stage_begin(dem_ctx *ctx, int kind, hipStream_t s)
+{
+    if (!ctx->P.timing) return nullptr;
+    if (ctx->ring.empty()) ctx->ring.resize(1024);
+    dem_ctx::TimedPair &p = ctx->ring[ctx->ring_pos];
+    ctx->ring_pos = (ctx->ring_pos + 1) % ctx->ring.size();
+    drain_pair(ctx, p);
+    if (!p.a) {
+        hipEventCreateWithFlags(&p.a, hipEventDisableSystemFence);
+        hipEventCreateWithFlags(&p.b, hipEventDisableSystemFence);
+    }
+    p.kind = kind;
+    hipEventRecord(p.a, s);
+    return &p;
+}
+
+void stage_end(dem_ctx::TimedPair *p, hipStream_t s)
+{
+    if (p) hipEventRecord(p->b, s);
+}
+
+void drain_all(dem_ctx *ctx)
+{
+    for (auto &p : ctx->ring) drain_pair(ctx, p);
 }
 
 }  // namespace
@@ -600,14 +652,18 @@ dem_status dem_bin(dem_ctx *ctx, dem_stream stream, uint32_t *sorted_keys, uint3
 static dem_status detect_now(dem_ctx *ctx, double margin, hipStream_t s, int target)
 {
     DetectArgs a = detect_args(ctx, false, margin, ctx->step);
+    auto *tp = stage_begin(ctx, 2, s);
     launch_detect(a, ctx->cdD, ctx->acs[target], ctx->cap, ctx->ctr, target, s);
+    stage_end(tp, s);
     HIPCHK(hipGetLastError());
     return DEM_OK;
 }
 
 static dem_status adopt(dem_ctx *ctx, int target, hipStream_t s)
 {
+    auto *tp = stage_begin(ctx, 3, s);
     launch_remap(ctx->acs[ctx->cur], ctx->acs[target], ctx->Ns, ctx->ctr, target, s);
+    stage_end(tp, s);
     HIPCHK(hipGetLastError());
     ctx->cur = target;
     return DEM_OK;
@@ -814,7 +870,9 @@ static void issue_work_order(dem_ctx *ctx, hipStream_t dyn, hipStream_t kin, int
     hipStreamWaitEvent(kin, ctx->ev_wo, 0);
     int target = 1 - ctx->cur;
     DetectArgs a = detect_args(ctx, true, ctx->P.margin, n);
+    auto *tp = stage_begin(ctx, 2, kin);
     launch_detect(a, ctx->cdK, ctx->acs[target], ctx->cap, ctx->ctr, target, kin);
+    stage_end(tp, kin);
     hipEventRecord(ctx->ev_cd, kin);
     ctx->pending = true;
     ctx->pend_buf = target;
@@ -838,6 +896,17 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
     int64_t cds = 0, swaps = 0, misses = 0, repairs = 0;
     const int64_t step0 = ctx->step;
     dem_status result = DEM_OK;
+    drain_all(ctx);
+    for (int k = 0; k < 4; ++k) {
+        ctx->stage_ms[k] = 0.0;
+        ctx->stage_n[k] = 0;
+    }
+    unsigned long long cs0 = 0;
+    {
+        dem_status st0 = read_counters(ctx, dyn);
+        if (st0 != DEM_OK) return st0;
+        cs0 = ctx->h_ctr->contact_steps;
+    }
     if (ctx->n_wo == 0) ctx->interval_sum = 0.0;
     for (int64_t t = 0; t < n_steps; ++t) {
         const int64_t n = ctx->step;
@@ -931,9 +1000,17 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
             }
         }
         DynArgs a = dyn_args(ctx, n);
+        auto *tf = stage_begin(ctx, 0, dyn);
         launch_force(a, ctx->acs[ctx->cur], ctx->sb, ctx->ctr, dyn);
+        stage_end(tf, dyn);
+        auto *ti = stage_begin(ctx, 1, dyn);
         launch_fold_integrate(a, ctx->acs[ctx->cur], ctx->sb, ctx->ctr, 1, dyn);
+        stage_end(ti, dyn);
         ctx->step = n + 1;
+    }
+    {
+        DynArgs da = dyn_args(ctx, ctx->step);
+        launch_reduce_max(da, ctx->ctr, dyn);
     }
     HIPCHK(hipGetLastError());
     if (kin != dyn) HIPCHK(hipStreamSynchronize(kin));
@@ -961,12 +1038,18 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
         stats->n_contacts = c.n_contacts[ctx->cur];
         stats->required_capacity = c.required;
         float v2;
-        uint32_t bits = c.maxv2[(ctx->step - 1) & 3];
+        uint32_t bits = c.maxv2[0];
         std::memcpy(&v2, &bits, 4);
         stats->max_speed = std::sqrt((double)v2);
         stats->ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
         stats->mean_interval = ctx->n_wo > 1 ? ctx->interval_sum / (double)(ctx->n_wo - 1)
                                              : (double)(P.cd_mode == DEM_CD_EVERY ? 1 : P.cd_interval);
+        drain_all(ctx);
+        for (int k = 0; k < 4; ++k) {
+            stats->stage_ms[k] = ctx->stage_ms[k];
+            stats->stage_n[k] = ctx->stage_n[k];
+        }
+        stats->mean_contacts = stats->steps > 0 ? (double)(c.contact_steps - cs0) / (double)stats->steps : 0.0;
     }
     return result;
 }
@@ -978,6 +1061,10 @@ void dem_destroy(dem_ctx *ctx)
     if (ctx->h_pred) hipHostFree(ctx->h_pred);
     if (ctx->ev_wo) hipEventDestroy(ctx->ev_wo);
     if (ctx->ev_cd) hipEventDestroy(ctx->ev_cd);
+    for (auto &p : ctx->ring) {
+        if (p.a) hipEventDestroy(p.a);
+        if (p.b) hipEventDestroy(p.b);
+    }
     delete ctx;
 }
 
@@ -1029,9 +1116,11 @@ static int64_t analytic_interval(dem_ctx *ctx, double vmax)
 int64_t learned_interval(dem_ctx *ctx, hipStream_t s)
 {
     // top speed of the last integrated step
+    DynArgs da = dyn_args(ctx, ctx->step);
+    launch_reduce_max(da, ctx->ctr, s);
     if (read_counters(ctx, s) != DEM_OK) return 1;
     float v2;
-    uint32_t bits = ctx->h_ctr->maxv2[(ctx->step - 1) & 3];
+    uint32_t bits = ctx->h_ctr->maxv2[0];
     std::memcpy(&v2, &bits, 4);
     double vmax = ctx->step > 0 && v2 == v2 ? std::sqrt((double)v2) : 0.0;
     int64_t k_an = analytic_interval(ctx, vmax);

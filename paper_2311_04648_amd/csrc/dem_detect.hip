@@ -294,7 +294,7 @@ void launch_bin(const DetectArgs &a, CdWork &w, hipStream_t s)
     hipLaunchKernelGGL(k_cd_prepare, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.vals, w.cand_tmp,
                        w.cell_count);
     scan_exclusive_u32(w.cell_count, w.cell_start, (int64_t)a.grid.nbins, w.partials, s);
-    radix_sort_u32(w.keys, w.vals, w.keys_alt, w.vals_alt, n, w.sort_bits, w.hist, w.partials, s);
+    radix_sort_u32(&w.keys, &w.vals, &w.keys_alt, &w.vals_alt, n, w.sort_bits, w.hist, w.partials, s);
     hipLaunchKernelGGL(k_cand_gather, dim3(nblocks(n)), dim3(TPB), 0, s, w.vals, w.cand_tmp, w.cand, n);
 }
 

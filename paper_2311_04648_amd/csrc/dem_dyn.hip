@@ -227,17 +227,20 @@ __global__ void __launch_bounds__(TPB) k_force(DynArgs a, const uint32_t *start,
             bT[cap + c] = tB.y;
             bT[2 * cap + c] = tB.z;
         }
+        // spheres without A-side contacts write nothing: the fold reads the
+        // row offsets and skips them
+        aF[i] = FA.x;
+        aF[Ns + i] = FA.y;
+        aF[2 * Ns + i] = FA.z;
+        aT[i] = TA.x;
+        aT[Ns + i] = TA.y;
+        aT[2 * Ns + i] = TA.z;
     }
-    aF[i] = FA.x;
-    aF[Ns + i] = FA.y;
-    aF[2 * Ns + i] = FA.z;
-    aT[i] = TA.x;
-    aT[Ns + i] = TA.y;
-    aT[2 * Ns + i] = TA.z;
     (void)No;
 }
 
-__global__ void __launch_bounds__(TPB) k_fold_integrate(DynArgs a, const uint32_t *bstart,
+__global__ void __launch_bounds__(TPB) k_fold_integrate(DynArgs a, const uint32_t *start,
+                                                        const uint32_t *bstart,
                                                         const uint32_t *bidx, const float *aF,
                                                         const float *aT, const float *bF,
                                                         const float *bT, int64_t cap, float *Fo,
@@ -250,14 +253,16 @@ __global__ void __launch_bounds__(TPB) k_fold_integrate(DynArgs a, const uint32_
     float v2 = 0.0f;
     if (integrate && o == 0) {
         ctr->last_step_done = a.step + 1;
-        ctr->maxv2[(a.step + 2) & 3] = 0u;
+        ctr->contact_steps += ctr->n_contacts[a.cur];
     }
     if (valid) {
         float3 F = f3(0.f, 0.f, 0.f), T = f3(0.f, 0.f, 0.f);
         const uint32_t s0 = a.own_sph0[o], s1 = a.own_sph0[o + 1];
         for (uint32_t s = s0; s < s1; ++s) {
-            F = F + f3(aF[s], aF[Ns + s], aF[2 * Ns + s]);
-            T = T + f3(aT[s], aT[Ns + s], aT[2 * Ns + s]);
+            if (start[s] != start[s + 1]) {
+                F = F + f3(aF[s], aF[Ns + s], aF[2 * Ns + s]);
+                T = T + f3(aT[s], aT[Ns + s], aT[2 * Ns + s]);
+            }
             const uint32_t b1 = bstart[s + 1];
             for (uint32_t b = bstart[s]; b < b1; ++b) {
                 const uint32_t c = bidx[b];
@@ -326,14 +331,38 @@ __global__ void __launch_bounds__(TPB) k_fold_integrate(DynArgs a, const uint32_
         }
     }
     if (integrate) {
-        // wave-wide max of |v|^2, one atomic per wave (order-free, exact)
+        // block-wide max of |v|^2 written to this block's slot (no atomics);
+        // the maximum over blocks is reduced only when it is read
+        __shared__ float wmax[TPB / 64];
         if (!(v2 == v2)) v2 = 3.0e38f;
         for (int d = 32; d > 0; d >>= 1) v2 = fmaxf(v2, __shfl_xor(v2, d, 64));
-        if ((threadIdx.x & 63) == 0) atomicMax(&ctr->maxv2[a.step & 3], __float_as_uint(v2));
+        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v2;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float m = wmax[0];
+            for (int k = 1; k < TPB / 64; ++k) m = fmaxf(m, wmax[k]);
+            a.blkmax[blockIdx.x] = m;
+        }
     }
 }
 
 }  // namespace
+
+__global__ void __launch_bounds__(256) k_reduce_max(const float *blkmax, int64_t n, DevCounters *ctr)
+{
+    float m = 0.0f;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, blkmax[i]);
+    for (int d = 32; d > 0; d >>= 1) m = fmaxf(m, __shfl_xor(m, d, 64));
+    __shared__ float w[4];
+    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) ctr->maxv2[0] = __float_as_uint(fmaxf(fmaxf(w[0], w[1]), fmaxf(w[2], w[3])));
+}
+
+void launch_reduce_max(const DynArgs &a, DevCounters *ctr, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(256), 0, s, a.blkmax, (int64_t)nblocks(a.n_owners), ctr);
+}
 
 void launch_force(const DynArgs &a, AcsBuf &cur, StepBufs &sb, DevCounters *ctr, hipStream_t s)
 {
@@ -344,6 +373,6 @@ void launch_force(const DynArgs &a, AcsBuf &cur, StepBufs &sb, DevCounters *ctr,
 void launch_fold_integrate(const DynArgs &a, const AcsBuf &cur, StepBufs &sb, DevCounters *ctr,
                            int integrate, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fold_integrate, dim3(nblocks(a.n_owners)), dim3(TPB), 0, s, a, cur.bstart,
+    hipLaunchKernelGGL(k_fold_integrate, dim3(nblocks(a.n_owners)), dim3(TPB), 0, s, a, cur.start, cur.bstart,
                        cur.bidx, sb.aF, sb.aT, sb.bF, sb.bT, sb.cap, sb.Fo, sb.To, integrate, ctr);
 }

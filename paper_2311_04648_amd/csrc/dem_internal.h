@@ -85,6 +85,7 @@ struct DevCounters {
     int64_t last_step_done;
     uint32_t ncell;           // feature cells in use
     uint32_t pad1;
+    unsigned long long contact_steps;   // sum over integrated steps of the set size in use
 };
 
 struct ScanTmp {
@@ -101,9 +102,10 @@ void launch_copy_u32(uint32_t *dst, const uint32_t *src, int64_t n, hipStream_t 
 void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *partials,
                         hipStream_t s);
 int64_t radix_hist_elems(int64_t n);
-// stable LSD radix sort of (keys, vals) on the low `bits` bits; result ends
-// in (keys, vals); alt buffers are scratch of the same size.
-void radix_sort_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
+// stable LSD radix sort of (keys, vals) on the low `bits` bits; the buffer
+// pairs are swapped as needed so the result ends in (*keys, *vals); the alt
+// buffers are scratch of the same size.
+void radix_sort_u32(uint32_t **keys, uint32_t **vals, uint32_t **keys_alt, uint32_t **vals_alt,
                     int64_t n, int bits, uint32_t *hist, uint32_t *partials, hipStream_t s);
 
 struct DetectArgs {
@@ -123,7 +125,7 @@ struct DetectArgs {
 };
 
 struct CdWork {
-    uint32_t *keys, *vals, *keys_alt, *vals_alt;
+    uint32_t *keys, *vals, *keys_alt, *vals_alt;   // sorted result lands in keys/vals
     Cand *cand_tmp, *cand;
     uint32_t *cell_count, *cell_start;
     uint32_t *count;       // [Ns+1]
@@ -168,6 +170,8 @@ struct DynArgs {
     float v_err2;
     int64_t step;
     int32_t has_clumps;
+    int32_t cur;            // active-set buffer in use (for statistics)
+    float *blkmax;          // per-block max |v|^2 of the last integration [ceil(No/256)]
 };
 
 struct StepBufs {
@@ -180,4 +184,6 @@ struct StepBufs {
 void launch_force(const DynArgs &a, AcsBuf &cur, StepBufs &sb, DevCounters *ctr, hipStream_t s);
 void launch_fold_integrate(const DynArgs &a, const AcsBuf &cur, StepBufs &sb, DevCounters *ctr,
                            int integrate, hipStream_t s);
+// max |v|^2 of the last integration into ctr->maxv2[0]
+void launch_reduce_max(const DynArgs &a, DevCounters *ctr, hipStream_t s);
 

@@ -227,17 +227,15 @@ void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *
                        partials, nb);
 }
 
-void radix_sort_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
+void radix_sort_u32(uint32_t **keys, uint32_t **vals, uint32_t **keys_alt, uint32_t **vals_alt,
                     int64_t n, int bits, uint32_t *hist, uint32_t *partials, hipStream_t s)
 {
     if (n <= 1) return;
     int64_t nblk = (n + RADIX_TILE - 1) / RADIX_TILE;
     int passes = (bits + 7) / 8;
-    if (passes % 2) passes += 1;   // even pass count leaves the result in (keys, vals)
-    uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
+    uint32_t *ki = *keys, *vi = *vals, *ko = *keys_alt, *vo = *vals_alt;
     for (int p = 0; p < passes; ++p) {
         int shift = 8 * p;
-        if (shift >= 32) shift = 24;   // an extra pass on a used digit keeps order (stable)
         hipLaunchKernelGGL(k_radix_up, dim3((unsigned)nblk), dim3(RADIX_THREADS), 0, s, ki, n, shift,
                            hist, nblk);
         scan_exclusive_u32(hist, hist, 256 * nblk, partials, s);
@@ -246,4 +244,9 @@ void radix_sort_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t
         uint32_t *t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
     }
+    // after an odd number of passes the result sits in the alt buffers: swap roles
+    *keys = ki;
+    *vals = vi;
+    *keys_alt = ko;
+    *vals_alt = vo;
 }

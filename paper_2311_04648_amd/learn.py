@@ -1,0 +1,149 @@
+"""Training of the learned contact-detection interval on the GPU.
+
+Logs come from the method itself: a run with every-step detection, split
+into windows.  In each window the state at the window start s is the
+reference (snapshot), the dynamics advance tau steps, the per-cell
+features are taken at step s + tau, a "label" active set is detected there
+with the run's margin, and the dynamics advance K = 256 more steps while
+every true contact is looked up in the label set; the label of a cell is the
+first step at which a true contact touching it is missing (censored at K).
+Targets are log(1 + label).  The network is trained with the project's own
+HIP kernels (forward, backward with an ordered gradient reduction, Adam)
+under the expectile loss (tau = 0.05), which favours under-prediction.
+
+Usage (on the GPU):  python -m paper_2311_04648_amd.learn --out model.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+K_CAP = 256
+
+
+def generate_logs(dem, sysm, windows=16, taus=(5, 10, 20, 40, 80), K=K_CAP, warm=0, log=None):
+    """Returns (features float32 [n,6], targets float32 [n]) from one run."""
+    torch = dem._torch()
+    ctx = dem.DemContext(sysm, mode="every", capacity=max(64, 10 * sysm.n_spheres))
+    ctx.set_state()
+    if warm:
+        ctx.step(warm)
+    ncell = ctx.info()["ncells"]
+    feats, targets = [], []
+    for w in range(windows):
+        tau = taus[w % len(taus)]
+        ctx.snapshot()
+        ctx.step(tau)
+        f, ids, _ = ctx.features()
+        ctx.label_begin()
+        first = torch.full((ncell,), K + 1, dtype=torch.int32, device=ctx.device)
+        for t in range(1, K + 1):
+            ctx.step(1)
+            ctx.label_update(t, first)
+        torch.cuda.synchronize()
+        lab = first.cpu().numpy().astype(np.int64)[ids]
+        lab = np.minimum(lab, K)
+        feats.append(f.cpu().numpy())
+        targets.append(np.log1p(lab.astype(np.float64)).astype(np.float32))
+        if log:
+            log(f"  window {w}: tau {tau} cells {ids.size} min label {lab.min()} mean {lab.mean():.1f}")
+    ctx.close()
+    return np.concatenate(feats), np.concatenate(targets)
+
+
+def init_params(seed=0):
+    """Glorot-uniform weights, zero biases, output bias at log(1 + 16)."""
+    rng = np.random.default_rng(seed)
+    H, NF = 32, 6
+
+    def glorot(o, i):
+        a = math.sqrt(6.0 / (o + i))
+        return rng.uniform(-a, a, size=(o, i))
+
+    p = np.concatenate([glorot(H, NF).ravel(), np.zeros(H), glorot(H, H).ravel(), np.zeros(H),
+                        glorot(1, H).ravel(), [math.log1p(16.0)]])
+    return p.astype(np.float32)
+
+
+def train(dem, X, T, epochs=200, batch=4096, lr=3e-3, tau=0.05, seed=0, log=None):
+    """Adam on the expectile loss with fixed-order mini-batches (a seeded
+    permutation per epoch), all on the GPU kernels."""
+    torch = dem._torch()
+    dev = torch.device("cuda:0")
+    Xd = torch.tensor(X, dtype=torch.float32, device=dev)
+    Td = torch.tensor(T, dtype=torch.float32, device=dev)
+    p = torch.tensor(init_params(seed), device=dev)
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    rng = np.random.default_rng(seed + 1)
+    n = X.shape[0]
+    t = 0
+    hist = []
+    for ep in range(epochs):
+        perm = torch.tensor(rng.permutation(n), device=dev)
+        for b0 in range(0, n, batch):
+            idx = perm[b0:b0 + batch]
+            xb = Xd[idx].contiguous()
+            tb = Td[idx].contiguous()
+            g, loss = dem.mlp_backward(p, xb, tb, tau)
+            t += 1
+            dem.mlp_adam(p, g, m, v, t, lr=lr)
+        if ep % max(1, epochs // 10) == 0 or ep == epochs - 1:
+            g, loss = dem.mlp_backward(p, Xd, Td, tau)
+            hist.append(float(loss.item()))
+            if log:
+                log(f"  epoch {ep}: loss {hist[-1]:.5f}")
+    return p.cpu().numpy(), hist
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default="gpurun_out/mlp_interval.json")
+    ap.add_argument("--n1", type=int, default=100_000, help="spheres of the config-1 log runs")
+    ap.add_argument("--n2", type=int, default=30_000, help="clumps of the config-2 log runs")
+    ap.add_argument("--windows", type=int, default=12)
+    ap.add_argument("--epochs", type=int, default=300)
+    args = ap.parse_args()
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import paper_2311_04648_amd as dem
+    import workloads as W
+
+    def log(msg):
+        print(msg, flush=True)
+
+    t0 = time.time()
+    Xs, Ts, meta = [], [], []
+    for seed in (1, 2, 3, 4):
+        for name in ("config1", "config2"):
+            if name == "config1":
+                s = W.config1(seed=seed, n=args.n1)
+            else:
+                nt = int(args.n2 * 0.9)
+                s = W.config2(seed=seed, n_tri=nt, n_penta=args.n2 - nt)
+            log(f"logs {name} seed {seed}: {s.n_spheres} spheres")
+            X, T = generate_logs(dem, s, windows=args.windows, warm=200 * seed, log=log)
+            Xs.append(X)
+            Ts.append(T)
+            meta.append(dict(config=name, seed=seed, n_spheres=s.n_spheres, samples=int(X.shape[0])))
+    X = np.concatenate(Xs)
+    T = np.concatenate(Ts)
+    log(f"{X.shape[0]} samples in {time.time() - t0:.1f}s; training")
+    p, hist = train(dem, X, T, epochs=args.epochs, log=log)
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    with open(args.out, "w") as f:
+        json.dump({"params": [float(x) for x in p], "loss_history": hist, "samples": int(X.shape[0]),
+                   "runs": meta, "tau": 0.05, "K": K_CAP,
+                   "feature_mean": X.mean(0).tolist(), "feature_max": X.max(0).tolist(),
+                   "target_mean": float(T.mean())}, f)
+    np.savez_compressed(os.path.splitext(args.out)[0] + "_logs.npz", X=X, T=T)
+    log(f"saved {args.out} in {time.time() - t0:.1f}s")
+
+
+if __name__ == "__main__":
+    main()

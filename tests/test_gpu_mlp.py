@@ -1,0 +1,161 @@
+"""GPU parity of the learned-interval kernels with the FP64 oracle, and the
+gain of the learned schedule over the fixed-margin one."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def dem():
+    import paper_2311_04648_amd as d
+    if not os.path.exists(d.LIB_PATH):
+        from paper_2311_04648_amd import build
+        build.build()
+    d._torch()
+    return d
+
+
+def _data(seed, n):
+    rng = np.random.default_rng(seed)
+    p = W.f32(rng.normal(0, 0.3, size=omlp.NPARAM))
+    X = W.f32(rng.normal(0, 1.0, size=(n, omlp.NF)))
+    T = W.f32(rng.normal(0, 1.0, size=n))
+    return p, X, T
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 1000, 4097])
+def test_mlp_forward_matches_oracle(dem, n):
+    import torch
+    p, X, _ = _data(n, n)
+    y = dem.mlp_forward(torch.tensor(p, dtype=torch.float32, device="cuda"),
+                        torch.tensor(X, dtype=torch.float32, device="cuda")).cpu().numpy()
+    ref, _ = omlp.forward(p, X)
+    np.testing.assert_allclose(y, ref, rtol=1e-5, atol=1e-5 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("n,tau", [(1, 0.05), (64, 0.05), (1000, 0.05), (4097, 0.3)])
+def test_mlp_backward_matches_oracle(dem, n, tau):
+    import torch
+    p, X, T = _data(100 + n, n)
+    dev = "cuda"
+    g, loss = dem.mlp_backward(torch.tensor(p, dtype=torch.float32, device=dev),
+                               torch.tensor(X, dtype=torch.float32, device=dev),
+                               torch.tensor(T, dtype=torch.float32, device=dev), tau)
+    g = g.cpu().numpy()
+    lref, gref = omlp.loss_and_grad(p, X, T, tau)
+    assert abs(loss.item() - lref) <= 1e-5 * abs(lref)
+    scale = np.abs(gref).max()
+    err = np.abs(g - gref) / np.maximum(np.abs(gref), 1e-3 * scale)
+    assert err.max() <= 1e-5 * 10, err.max()
+    # deterministic: same bits twice
+    g2, _ = dem.mlp_backward(torch.tensor(p, dtype=torch.float32, device=dev),
+                             torch.tensor(X, dtype=torch.float32, device=dev),
+                             torch.tensor(T, dtype=torch.float32, device=dev), tau)
+    assert np.array_equal(g, g2.cpu().numpy())
+
+
+def test_mlp_adam_matches_oracle(dem):
+    import torch
+    rng = np.random.default_rng(5)
+    p = W.f32(rng.normal(0, 0.3, size=omlp.NPARAM))
+    pd = torch.tensor(p, dtype=torch.float32, device="cuda")
+    md = torch.zeros_like(pd)
+    vd = torch.zeros_like(pd)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    for t in range(1, 6):
+        g = W.f32(rng.normal(0, 1, size=p.size))
+        dem.mlp_adam(pd, torch.tensor(g, dtype=torch.float32, device="cuda"), md, vd, t, lr=1e-3)
+        p, m, v = omlp.adam_step(p, g, m, v, t, lr=1e-3)
+    np.testing.assert_allclose(pd.cpu().numpy(), p, rtol=1e-5, atol=1e-7)
+
+
+def _state(g):
+    return g["X"].copy(), g["V"].astype(np.float64)
+
+
+def test_features_match_oracle(dem):
+    s = W.small_spheres(11, n=512, vel=0.4)
+    ctx = dem.DemContext(s, mode="every")
+    ctx.set_state()
+    X0, V0 = _state(ctx.get_state())
+    ctx.snapshot()
+    ctx.step(7)
+    f, ids, own = ctx.features()
+    X1, V1 = _state(ctx.get_state())
+    rids, rf = omlp.features(s, X1, V1, X0, V0, 7)
+    np.testing.assert_array_equal(ids.astype(np.int64), rids)
+    np.testing.assert_array_equal(own.astype(np.int64), omlp.owner_cells(s, X1))
+    f = f.cpu().numpy()
+    np.testing.assert_allclose(f, rf, rtol=1e-5, atol=1e-6)
+
+
+def test_labels_match_oracle(dem):
+    import torch
+    s = W.small_spheres(12, n=343, vel=1.0, margin=5e-5)
+    ctx = dem.DemContext(s, mode="every")
+    ctx.set_state()
+    ctx.snapshot()
+    ctx.step(3)
+    f, ids, own = ctx.features()
+    g0 = ctx.get_state()
+    ctx.label_begin()
+    ncell = ctx.info()["ncells"]
+    first = torch.full((ncell,), 10 ** 6, dtype=torch.int32, device="cuda")
+    states = []
+    for t in range(1, 41):
+        ctx.step(1)
+        ctx.label_update(t, first)
+        states.append(ctx.get_state())
+    got = first.cpu().numpy().astype(np.int64)
+    o = oracle.Oracle(s)
+    st0 = {"X": g0["X"], "q": g0["q"], "V": g0["V"].astype(np.float64), "W": g0["W"].astype(np.float64)}
+    lab = o.detect(st0, s.margin, step=g0["step"])
+    ref = np.full(ncell, 10 ** 6, dtype=np.int64)
+    cells = omlp.owner_cells(s, g0["X"])
+    for t, g in enumerate(states, start=1):
+        st = {"X": g["X"], "q": g["q"], "V": g["V"].astype(np.float64), "W": g["W"].astype(np.float64)}
+        true = o.detect(st, 0.0, step=g["step"])
+        omlp.first_miss_per_cell(s, lab, true, cells, t, ref)
+    assert (ref < 10 ** 6).sum() > 0
+    np.testing.assert_array_equal(got, ref)
+
+
+MODEL = os.path.join(ROOT, "paper_2311_04648_amd", "mlp_interval.json")
+
+
+@pytest.mark.skipif(not os.path.exists(MODEL), reason="no trained interval model in the tree")
+def test_learned_interval_beats_fixed_with_zero_misses(dem):
+    """Held-out workload (granular column, seed 7, reduced size): the learned
+    schedule runs fewer detections than the fixed k = 10 schedule, misses no
+    contact (judged), and its trajectory equals every-step detection."""
+    params = np.array(json.load(open(MODEL))["params"], dtype=np.float32)
+    s = W.config3(seed=7, n=20_000)
+    steps = 1500
+    learned = dem.DemContext(s, mode="learned", k=10, lam=2, judge=True, k_max=256)
+    learned.mlp_set(params)
+    learned.set_state()
+    ls = learned.step(steps)
+    fixed = dem.DemContext(s, mode="fixed", k=10, lam=2, judge=True)
+    fixed.set_state()
+    fs = fixed.step(steps)
+    every = dem.DemContext(s, mode="every")
+    every.set_state()
+    every.step(steps)
+    print(f"learned cds {ls['cds']} mean interval {ls['mean_interval']:.1f} misses {ls['misses']}; "
+          f"fixed cds {fs['cds']} misses {fs['misses']}")
+    assert ls["misses"] == 0
+    assert ls["cds"] < fs["cds"]
+    a, b = learned.get_state(), every.get_state()
+    for k in ("X", "V", "W"):
+        np.testing.assert_array_equal(a[k], b[k])
