@@ -227,13 +227,15 @@ dem_status dem_get_forces(dem_ctx *ctx, float *F_owner, float *T_owner, float *F
 dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn, dem_stream kin,
                     dem_step_stats *stats);
 
-/* Reads the current contact set: keys [cap] and history [3*cap] (float).
+/* Reads the current contact set: keys [cap] and history [4*cap] (float:
+ * tangential displacement xyz, contact age in seconds; the age is tracked
+ * only when some material pair has rolling resistance, else reads 0).
  * n receives the set size; DEM_ERR_CAPACITY if cap is smaller. */
 dem_status dem_get_contacts(dem_ctx *ctx, uint64_t *keys, float *hist, int64_t cap,
                             int64_t *n, dem_stream stream);
 
 /* Installs a contact set (strictly ascending keys as dem_detect_contacts
- * produces) with its history (NULL = zero).  Errors: DEM_ERR_ARG on bad keys,
+ * produces) with its history ([4*n] as dem_get_contacts; NULL = zero).  Errors: DEM_ERR_ARG on bad keys,
  * DEM_ERR_CAPACITY if n exceeds the bound capacity. */
 dem_status dem_set_contacts(dem_ctx *ctx, const uint64_t *keys, const float *hist, int64_t n,
                             dem_stream stream);
@@ -243,12 +245,14 @@ dem_status dem_set_contacts(dem_ctx *ctx, const uint64_t *keys, const float *his
 dem_status dem_count_missing(dem_ctx *ctx, dem_stream stream, int64_t *missing);
 
 /* ---- learned contact-detection interval ---------------------------------
- * A 6-32-32-1 tanh MLP predicts, per feature cell, how many more steps the
- * contact set in use stays complete.  Parameters are 1313 floats in the
+ * A 6-32-32-1 tanh MLP predicts, per feature cell, log(1 + the number of
+ * steps) a contact set detected now stays complete (labels censored at
+ * DEM_MLP_KCAP).  Parameters are 1313 floats in the
  * order W1[32x6], b1[32], W2[32x32], b2[32], W3[1x32], b3[1] (row-major,
  * out x in). */
 #define DEM_MLP_NPARAM 1313
 #define DEM_MLP_NFEAT 6
+#define DEM_MLP_KCAP 1024   /* label horizon K (steps) used by the features */
 
 /* Installs MLP parameters used by DEM_CD_LEARNED (host array). */
 dem_status dem_mlp_set(dem_ctx *ctx, const float *params);

@@ -64,6 +64,8 @@ def lib():
         _lib.orc_detect_brute.restype = i64
         _lib.orc_detect_binned.argtypes = [vp, vp, vp, d, vp, i64]
         _lib.orc_detect_binned.restype = i64
+        _lib.orc_detect_row.argtypes = [vp, vp, vp, d, i64, vp, i64]
+        _lib.orc_detect_row.restype = i64
         _lib.orc_count_missing.argtypes = [vp, vp, vp, vp, i64, vp, i64]
         _lib.orc_count_missing.restype = i64
         _lib.orc_remap.argtypes = [vp, vp, i64, vp, vp, i64]
@@ -77,6 +79,16 @@ def lib():
 
 def _p(a):
     return a.ctypes.data if a is not None else None
+
+
+def _hist4(hist, n):
+    """Contact history as [n,4] float64 (tangential displacement xyz, contact
+    age); a [n,3] input gets age 0."""
+    out = np.zeros((n, 4))
+    if n:
+        h = np.asarray(hist, dtype=np.float64).reshape(n, -1)
+        out[:, : h.shape[1]] = h
+    return np.ascontiguousarray(out)
 
 
 class Oracle:
@@ -148,11 +160,24 @@ class Oracle:
                 return keys[:n].copy()
             cap = -n
 
+    def detect_rows(self, st, margin, spheres, step=0):
+        """Rows of the given spheres by brute force (for sampled checks of
+        inputs too large for a full detection)."""
+        xs = self.sphere_centres(st)
+        wp = np.zeros((max(self.sys.n_walls, 1), 3))
+        lib().orc_wall_positions(self.ps, int(step), _p(wp))
+        out = []
+        buf = np.zeros(4096, dtype=np.uint64)
+        for i in spheres:
+            n = lib().orc_detect_row(self.ps, _p(xs), _p(wp), float(margin), int(i), _p(buf), buf.size)
+            out.append(buf[:n].copy())
+        return out
+
     def forces(self, st, keys, hist, step=0):
         n = int(keys.shape[0])
         No, W = self.sys.n_owners, self.sys.n_walls
         keys = np.ascontiguousarray(keys, dtype=np.uint64)
-        hist = np.ascontiguousarray(hist, dtype=np.float64).reshape(n, 3).copy()
+        hist = _hist4(hist, n)
         out = dict(Fc=np.zeros((n, 3)), TA=np.zeros((n, 3)), TB=np.zeros((n, 3)),
                    Fo=np.zeros((No, 3)), To=np.zeros((No, 3)), Fw=np.zeros((max(W, 1), 3)),
                    touch=np.zeros(n, dtype=np.int32))
@@ -170,9 +195,9 @@ class Oracle:
         return st
 
     def remap(self, old_keys, old_hist, new_keys):
-        new_hist = np.zeros((new_keys.shape[0], 3))
+        new_hist = np.zeros((new_keys.shape[0], 4))
         lib().orc_remap(_p(np.ascontiguousarray(old_keys, dtype=np.uint64)),
-                        _p(np.ascontiguousarray(old_hist, dtype=np.float64)), int(old_keys.shape[0]),
+                        _p(_hist4(old_hist, old_keys.shape[0])), int(old_keys.shape[0]),
                         _p(np.ascontiguousarray(new_keys, dtype=np.uint64)), _p(new_hist),
                         int(new_keys.shape[0]))
         return new_hist
@@ -193,11 +218,11 @@ class Oracle:
         margin = self.sys.margin if margin is None else margin
         cap = cap or max(256, 16 * self.sys.n_spheres)
         keys = np.zeros(cap, dtype=np.uint64)
-        hist = np.zeros((cap, 3))
+        hist = np.zeros((cap, 4))
         n_acs = np.zeros(1, dtype=np.int64)
         if acs is not None:
             keys[: acs[0].shape[0]] = acs[0]
-            hist[: acs[0].shape[0]] = acs[1]
+            hist[: acs[0].shape[0]] = _hist4(acs[1], acs[0].shape[0])
             n_acs[0] = acs[0].shape[0]
         stepv = np.array([step], dtype=np.int64)
         stats = OrcStats()

@@ -278,6 +278,29 @@ int64_t orc_detect_binned(const orc_sys *s, const double *xs, const double *wp, 
     return n <= cap ? n : -n;
 }
 
+/* The row of one sphere i: all partners j > i of other owners within the
+ * margin, ascending, then the walls -- a brute-force scan over all spheres,
+ * for checking sampled rows of very large inputs. Returns the row length. */
+int64_t orc_detect_row(const orc_sys *s, const double *xs, const double *wp, double m, int64_t i,
+                       uint64_t *keys, int64_t cap)
+{
+    int64_t n = 0;
+    for (int64_t j = i + 1; j < s->n_spheres; ++j) {
+        if (s->sph_owner[i] == s->sph_owner[j]) continue;
+        if (pair_hit(xs + 3 * i, xs + 3 * j, s->sph_rad[i], s->sph_rad[j], m)) {
+            if (n < cap) keys[n] = ((uint64_t)i << 32) | (uint64_t)j;
+            ++n;
+        }
+    }
+    for (int64_t w = 0; w < s->n_walls; ++w) {
+        if (wall_hit(s, w, wp, xs + 3 * i, s->sph_rad[i], m)) {
+            if (n < cap) keys[n] = ((uint64_t)i << 32) | (uint64_t)(s->n_spheres + w);
+            ++n;
+        }
+    }
+    return n;
+}
+
 /* Number of true contacts (margin 0) absent from the sorted set `acs`. */
 int64_t orc_count_missing(const orc_sys *s, const double *xs, const double *wp,
                           const uint64_t *acs, int64_t n_acs, uint64_t *scratch, int64_t cap)
@@ -294,6 +317,7 @@ int64_t orc_count_missing(const orc_sys *s, const double *xs, const double *wp,
 
 /* ------------------------------------------------------------------ */
 /* contact history carry-over (Sec. 4.2: wildcards are zero at birth)  */
+/* History per contact: tangential displacement (3) and contact age.    */
 /* ------------------------------------------------------------------ */
 
 void orc_remap(const uint64_t *old_keys, const double *old_hist, int64_t n_old,
@@ -303,9 +327,9 @@ void orc_remap(const uint64_t *old_keys, const double *old_hist, int64_t n_old,
     for (int64_t c = 0; c < n_new; ++c) {
         while (p < n_old && old_keys[p] < new_keys[c]) ++p;
         if (p < n_old && old_keys[p] == new_keys[c]) {
-            for (int k = 0; k < 3; ++k) new_hist[3 * c + k] = old_hist[3 * p + k];
+            for (int k = 0; k < 4; ++k) new_hist[4 * c + k] = old_hist[4 * p + k];
         } else {
-            for (int k = 0; k < 3; ++k) new_hist[3 * c + k] = 0.0;
+            for (int k = 0; k < 4; ++k) new_hist[4 * c + k] = 0.0;
         }
     }
 }
@@ -337,7 +361,8 @@ static void point_velocity(const double *V, const double *Wb, const double *q, c
 }
 
 /* Evaluates every contact of the set on the state (X,q,V,W) at `step`.
- *   hist  [3n] in/out tangential micro-displacement (contact wildcards)
+ *   hist  [4n] in/out tangential micro-displacement and contact age
+ *         (the contact wildcards of the default model)
  *   Fc    [3n] force on geometry A (world); B receives -Fc
  *   TcA   [3n] torque on owner A about its centre; TcB [3n] on owner B
  *   Fo,To [3No] per-owner sums; Fw [3W] force on each wall (may be NULL)
@@ -361,7 +386,7 @@ void orc_forces(const orc_sys *s, const double *X, const double *q, const double
         int64_t oA = s->sph_owner[i];
         const double *xA = xs + 3 * i;
         double rA = s->sph_rad[i];
-        double *xi = hist + 3 * c;
+        double *xi = hist + 4 * c;
         double nrm[3], delta, Rbar, mbar, XB[3], VB[3];
         int matB, is_wall = jp >= Ns, oB = -1;
         int touching = 0;
@@ -420,6 +445,7 @@ void orc_forces(const orc_sys *s, const double *X, const double *q, const double
             for (int k = 0; k < 3; ++k) {
                 xi[k] = 0.0; Fc[3 * c + k] = 0.0; TcA[3 * c + k] = 0.0; TcB[3 * c + k] = 0.0;
             }
+            xi[3] = 0.0;
             continue;
         }
         int matA = s->sph_mat[i];
@@ -427,6 +453,7 @@ void orc_forces(const orc_sys *s, const double *X, const double *q, const double
         pair_moduli(s, matA, matB, &Estar, &Gstar);
         double cor = s->mat_cor[matA * s->n_mat + matB];
         double mu = s->mat_mu[matA * s->n_mat + matB];
+        double crr = s->mat_crr[matA * s->n_mat + matB];
 
         /* contact point: middle of the overlap region */
         double cp[3], armA[3], armB[3], vA[3], vB[3];
@@ -444,14 +471,22 @@ void orc_forces(const orc_sys *s, const double *X, const double *q, const double
             for (int k = 0; k < 3; ++k) vB[k] = s->wall_vel[3 * w + k] + rotv[k];
         }
         /* relative velocity of A w.r.t. B, split along the normal */
+        double VBl[3];
+        if (!is_wall) {
+            for (int k = 0; k < 3; ++k) VBl[k] = V[3 * oB + k];
+        } else {
+            for (int k = 0; k < 3; ++k) VBl[k] = s->wall_vel[3 * (jp - Ns) + k];
+        }
         double u[3], ut[3];
         for (int k = 0; k < 3; ++k) u[k] = vA[k] - vB[k];
         double pn = dot(u, nrm);
         for (int k = 0; k < 3; ++k) ut[k] = u[k] - pn * nrm[k];
-        /* history: add h v_t, then project onto the tangent plane (Eq. (2)) */
+        /* history: add h v_t, then project onto the tangent plane (Eq. (2));
+         * the contact ages by one step */
         for (int k = 0; k < 3; ++k) xi[k] = xi[k] + h * ut[k];
         double xin = dot(xi, nrm);
         for (int k = 0; k < 3; ++k) xi[k] = xi[k] - xin * nrm[k];
+        xi[3] = xi[3] + h;
         /* normal spring-damper */
         double sqrtRd = sqrt(Rbar * delta);
         double Sn = 2.0 * Estar * sqrtRd;
@@ -461,6 +496,33 @@ void orc_forces(const orc_sys *s, const double *X, const double *q, const double
         double gn = 2.0 * sqrt(5.0 / 6.0) * beta * sqrt(Sn * mbar);
         double F[3];
         for (int k = 0; k < 3; ++k) F[k] = (kn * delta + gn * pn) * nrm[k];
+        /* rolling resistance (Eq. (2) and the default-model walk-through): a
+         * torque-only force of magnitude C_rr |F_n| along the rolling part of
+         * the relative velocity at the contact point, applied once the
+         * contact has lasted longer than the damped Hertz collision time
+         * estimated with the walk-through's simplified constants */
+        double Fr[3] = {0.0, 0.0, 0.0};
+        if (crr > 0.0) {
+            int add = 1;
+            double Reff = sqrt(Rbar);
+            double kns = 4.0 / 3.0 * Estar * sqrt(Reff);
+            double gns = -2.0 * sqrt(5.0 / 3.0 * mbar * Estar) * beta * pow(Reff, 0.25);
+            double dc = gns / (2.0 * sqrt(kns * mbar));
+            if (dc < 1.0) {
+                double tcol = M_PI * sqrt(mbar / (kns * (1.0 - dc * dc)));
+                if (xi[3] <= tcol) add = 0;
+            }
+            if (add) {
+                double rvA[3], rvB[3], vr[3];
+                for (int k = 0; k < 3; ++k) { rvA[k] = vA[k] - V[3 * oA + k]; rvB[k] = vB[k] - VBl[k]; }
+                for (int k = 0; k < 3; ++k) vr[k] = rvB[k] - rvA[k];
+                double vrn = sqrt(dot(vr, vr));
+                if (vrn > 1e-12) {
+                    double fn = sqrt(dot(F, F));
+                    for (int k = 0; k < 3; ++k) Fr[k] = vr[k] / vrn * (crr * fn);
+                }
+            }
+        }
         /* Mindlin tangential spring-damper with Coulomb capping */
         if (mu > 0.0) {
             double kt = 8.0 * Gstar * sqrtRd;
@@ -483,8 +545,10 @@ void orc_forces(const orc_sys *s, const double *X, const double *q, const double
             for (int k = 0; k < 3; ++k) F[k] += ft[k];
         }
         double tA[3], tB[3], mF[3] = {-F[0], -F[1], -F[2]};
-        cross(armA, F, tA);
-        cross(armB, mF, tB);
+        double FA_t[3] = {F[0] + Fr[0], F[1] + Fr[1], F[2] + Fr[2]};
+        double FB_t[3] = {-FA_t[0], -FA_t[1], -FA_t[2]};
+        cross(armA, FA_t, tA);
+        cross(armB, FB_t, tB);
         for (int k = 0; k < 3; ++k) {
             Fc[3 * c + k] = F[k]; TcA[3 * c + k] = tA[k]; TcB[3 * c + k] = tB[k];
             Fo[3 * oA + k] += F[k];
@@ -575,11 +639,11 @@ int orc_run(const orc_sys *s, double *X, double *q, double *V, double *Wb, int64
     double *TA = malloc(sizeof(double) * 3 * (size_t)cap);
     double *TB = malloc(sizeof(double) * 3 * (size_t)cap);
     uint64_t *tmp = malloc(sizeof(uint64_t) * (size_t)cap);
-    acs_buf cur = {malloc(sizeof(uint64_t) * (size_t)cap), malloc(sizeof(double) * 3 * (size_t)cap), *acs_n};
-    acs_buf pend = {malloc(sizeof(uint64_t) * (size_t)cap), malloc(sizeof(double) * 3 * (size_t)cap), 0};
-    acs_buf fresh = {malloc(sizeof(uint64_t) * (size_t)cap), malloc(sizeof(double) * 3 * (size_t)cap), 0};
+    acs_buf cur = {malloc(sizeof(uint64_t) * (size_t)cap), malloc(sizeof(double) * 4 * (size_t)cap), *acs_n};
+    acs_buf pend = {malloc(sizeof(uint64_t) * (size_t)cap), malloc(sizeof(double) * 4 * (size_t)cap), 0};
+    acs_buf fresh = {malloc(sizeof(uint64_t) * (size_t)cap), malloc(sizeof(double) * 4 * (size_t)cap), 0};
     memcpy(cur.keys, acs_keys, sizeof(uint64_t) * (size_t)cur.n);
-    memcpy(cur.hist, acs_hist, sizeof(double) * 3 * (size_t)cur.n);
+    memcpy(cur.hist, acs_hist, sizeof(double) * 4 * (size_t)cur.n);
     int rc = 0, pending = 0;
     int64_t pend_swap = 0, next_wo = *step;
     double mm = (mode == 0) ? 0.0 : m;
@@ -647,7 +711,7 @@ int orc_run(const orc_sys *s, double *X, double *q, double *V, double *Wb, int64
     }
     if (rc == 0) {
         memcpy(acs_keys, cur.keys, sizeof(uint64_t) * (size_t)cur.n);
-        memcpy(acs_hist, cur.hist, sizeof(double) * 3 * (size_t)cur.n);
+        memcpy(acs_hist, cur.hist, sizeof(double) * 4 * (size_t)cur.n);
         *acs_n = cur.n;
     }
     free(cur.keys); free(cur.hist); free(pend.keys); free(pend.hist);

@@ -24,7 +24,7 @@ import numpy as np
 H = 32
 NF = 6
 NPARAM = H * NF + H + H * H + H + H + 1
-K_CAP = 256.0
+K_CAP = 1024.0
 
 
 def unpack(p):
@@ -117,7 +117,7 @@ def owner_cells(sysm, X):
 
 def features(sysm, X, V, Xs, Vs, tau_steps):
     """Per occupied cell (ascending cell id), from the owners whose centre
-    lies in it, with K = 256, m the margin, h the step, tau the steps since
+    lies in it, with K = 1024 (the label horizon), m the margin, h the step, tau the steps since
     the snapshot (Xs, Vs):
       f1 log1p(|max V - min V| h K / m)   (componentwise range of velocities)
       f2 log1p(max|V - Vs| K^2 h / (2 max(tau,1) m))

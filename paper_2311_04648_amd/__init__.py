@@ -270,14 +270,19 @@ class DemContext:
         n = C.c_int64()
         cap = self.capacity
         keys = np.zeros(cap, dtype=np.uint64)
-        hist = np.zeros((cap, 3), dtype=np.float32)
+        hist = np.zeros((cap, 4), dtype=np.float32)
         self._check(lib().dem_get_contacts(self.ctx, _p(keys), _p(hist), cap, C.byref(n), _stream_ptr(stream)))
         n = int(n.value)
         return keys[:n].copy(), hist[:n].copy()
 
     def set_contacts(self, keys, hist=None, stream=None):
+        """hist: [n,4] (displacement xyz, age) or [n,3] (age 0)."""
         keys = _c(keys, np.uint64)
-        h = None if hist is None else _c(hist, np.float32).reshape(-1, 3)
+        h = None
+        if hist is not None:
+            hh = _c(hist, np.float32).reshape(keys.shape[0], -1)
+            h = np.zeros((keys.shape[0], 4), dtype=np.float32)
+            h[:, : hh.shape[1]] = hh
         self._check(lib().dem_set_contacts(self.ctx, _p(keys), _p(h), int(keys.shape[0]), _stream_ptr(stream)))
 
     def count_missing(self, stream=None):

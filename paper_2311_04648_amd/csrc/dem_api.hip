@@ -26,6 +26,7 @@ struct dem_ctx {
     int64_t No = 0, Ns = 0;
     int32_t W = 0, T = 0, nmat = 0, ncomp = 0;
     bool has_clumps = false;
+    bool rolling = false;
     std::vector<OwnerAux> aux;
     std::vector<uint32_t> sph0;
     std::vector<SphRec> sph;
@@ -145,6 +146,7 @@ void carve_cd(Carver &c, const dem_ctx *ctx, CdWork &w)
     w.cell_count = c.take<uint32_t>((int64_t)ctx->grid.nbins + 1);
     w.cell_start = c.take<uint32_t>((int64_t)ctx->grid.nbins + 1);
     w.count = c.take<uint32_t>(ns + 1);
+    w.stage = c.take<uint32_t>(16 * ns);
     w.hist = c.take<uint32_t>(radix_hist_elems(ns));
     w.partials = c.take<uint32_t>(partial_elems(ctx));
     w.sort_bits = ctx->sort_bits;
@@ -170,6 +172,7 @@ void carve(Carver &c, dem_ctx *ctx, int64_t cap)
         a.hx = c.take<float>(cap);
         a.hy = c.take<float>(cap);
         a.hz = c.take<float>(cap);
+        a.hw = c.take<float>(cap);
         a.bstart = c.take<uint32_t>(Ns + 1);
         a.bidx = c.take<uint32_t>(cap);
         a.bcur = c.take<uint32_t>(Ns + 1);
@@ -238,6 +241,7 @@ DynArgs dyn_args(const dem_ctx *ctx, int64_t step)
     a.v_err2 = (float)(ctx->P.v_error_out * ctx->P.v_error_out);
     a.step = step;
     a.has_clumps = ctx->has_clumps ? 1 : 0;
+    a.rolling = ctx->rolling ? 1 : 0;
     a.cur = ctx->cur;
     a.blkmax = ctx->d_blkmax;
     return a;
@@ -365,6 +369,13 @@ dem_status dem_create(const dem_params *params, const dem_materials *mats, const
             mp.Gstar = (float)Gs;
             mp.beta = (float)beta;
             mp.mu = (float)mats->mu[a * ctx->nmat + b];
+            double crr = mats->crr ? mats->crr[a * ctx->nmat + b] : 0.0;
+            if (!(crr >= 0.0)) return fail("rolling-resistance coefficients must be >= 0");
+            mp.crr = (float)crr;
+            mp.kns = 0.0f;
+            mp.tcol = 0.0f;
+            mp.pad = 0.0f;
+            if (crr > 0.0) ctx->rolling = true;
             ctx->mat[(size_t)a * ctx->nmat + b] = mp;
         }
     // templates
@@ -662,7 +673,7 @@ static dem_status detect_now(dem_ctx *ctx, double margin, hipStream_t s, int tar
 static dem_status adopt(dem_ctx *ctx, int target, hipStream_t s)
 {
     auto *tp = stage_begin(ctx, 3, s);
-    launch_remap(ctx->acs[ctx->cur], ctx->acs[target], ctx->Ns, ctx->ctr, target, s);
+    launch_remap(ctx->acs[ctx->cur], ctx->acs[target], ctx->Ns, ctx->ctr, target, ctx->rolling ? 1 : 0, s);
     stage_end(tp, s);
     HIPCHK(hipGetLastError());
     ctx->cur = target;
@@ -772,19 +783,20 @@ dem_status dem_get_contacts(dem_ctx *ctx, uint64_t *keys, float *hist, int64_t c
         return DEM_ERR_CAPACITY;
     }
     std::vector<uint32_t> j(std::max<int64_t>(total, 1));
-    std::vector<float> h(3 * (size_t)std::max<int64_t>(total, 1));
+    std::vector<float> h(4 * (size_t)std::max<int64_t>(total, 1), 0.0f);
     if (total) {
         HIPCHK(hipMemcpyAsync(j.data(), a.j, 4 * total, hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(h.data(), a.hx, 4 * total, hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(h.data() + total, a.hy, 4 * total, hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(h.data() + 2 * total, a.hz, 4 * total, hipMemcpyDeviceToHost, s));
+        if (ctx->rolling) HIPCHK(hipMemcpyAsync(h.data() + 3 * total, a.hw, 4 * total, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
     }
     for (int64_t i = 0; i < ctx->Ns; ++i)
         for (uint32_t c = start[i]; c < start[i + 1]; ++c) {
             if (keys) keys[c] = ((uint64_t)i << 32) | (uint64_t)j[c];
             if (hist)
-                for (int k = 0; k < 3; ++k) hist[3 * (size_t)c + k] = h[k * total + c];
+                for (int k = 0; k < 4; ++k) hist[4 * (size_t)c + k] = h[k * total + c];
         }
     return DEM_OK;
 }
@@ -804,7 +816,7 @@ dem_status dem_set_contacts(dem_ctx *ctx, const uint64_t *keys, const float *his
     }
     hipStream_t s = S(stream);
     std::vector<uint32_t> start(ctx->Ns + 1, 0), j(std::max<int64_t>(n, 1));
-    std::vector<float> h(3 * (size_t)std::max<int64_t>(n, 1), 0.0f);
+    std::vector<float> h(4 * (size_t)std::max<int64_t>(n, 1), 0.0f);
     for (int64_t c = 0; c < n; ++c) {
         uint64_t key = keys[c];
         int64_t i = (int64_t)(key >> 32), jj = (int64_t)(key & 0xffffffffu);
@@ -814,7 +826,7 @@ dem_status dem_set_contacts(dem_ctx *ctx, const uint64_t *keys, const float *his
         start[i + 1]++;
         j[c] = (uint32_t)jj;
         if (hist)
-            for (int k = 0; k < 3; ++k) h[k * n + c] = hist[3 * c + k];
+            for (int k = 0; k < 4; ++k) h[k * n + c] = hist[4 * c + k];
     }
     for (int64_t i = 0; i < ctx->Ns; ++i) start[i + 1] += start[i];
     int b = ctx->cur;
@@ -825,6 +837,7 @@ dem_status dem_set_contacts(dem_ctx *ctx, const uint64_t *keys, const float *his
         HIPCHK(hipMemcpyAsync(a.hx, h.data(), 4 * n, hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(a.hy, h.data() + n, 4 * n, hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(a.hz, h.data() + 2 * n, 4 * n, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(a.hw, h.data() + 3 * n, 4 * n, hipMemcpyHostToDevice, s));
     }
     launch_blists(a, ctx->Ns, ctx->cap, ctx->cdD.partials, s);
     HIPCHK(hipGetLastError());

@@ -23,6 +23,7 @@
 namespace {
 
 constexpr int TPB = 256;
+constexpr int STAGE_K = 16;   // staged partners per sphere in the single-traversal detection
 
 enum { MODE_COUNT = 0, MODE_WRITE = 1, MODE_JUDGE = 2, MODE_LABEL = 3 };
 
@@ -202,6 +203,140 @@ __global__ void __launch_bounds__(TPB) k_detect(DetectArgs a, const uint32_t *ke
     if (MODE == MODE_JUDGE && nmiss) atomicAdd(miss, nmiss);
 }
 
+// Single traversal: stages up to STAGE_K partners of each sphere (in
+// traversal order) and counts all of them; also counts, per sphere, the
+// contacts in which it is the higher id (its B list).
+__global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32_t *keys, const Cand *cand,
+                                                      const uint32_t *cell_start, uint32_t *count,
+                                                      uint32_t *stage, uint32_t *bcount)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n_spheres) return;
+    const Cand ci = cand[p];
+    const uint32_t i = ci.id;
+    const uint32_t key = keys[p];
+    const double xi = ci.x, yi = ci.y, zi = ci.z, ri = (double)ci.r;
+    const double m = a.margin;
+    const uint32_t nx = (uint32_t)a.grid.nx, nxy = (uint32_t)a.grid.nx * (uint32_t)a.grid.ny;
+    uint32_t *st = stage + (size_t)i * STAGE_K;
+    uint32_t own_i = 0xffffffffu;
+    uint32_t n = 0;
+    for (int dz = -1; dz <= 1; ++dz) {
+        for (int dy = -1; dy <= 1; ++dy) {
+            uint32_t row = key + (uint32_t)((int)nxy * dz) + (uint32_t)((int)nx * dy);
+            uint32_t q0 = cell_start[row - 1], q1 = cell_start[row + 2];
+            for (uint32_t qq = q0; qq < q1; ++qq) {
+                const Cand cj = cand[qq];
+                if (cj.id <= i) continue;
+                if (!sphere_pair_hit(xi, yi, zi, ri, cj, m)) continue;
+                if (own_i == 0xffffffffu) own_i = a.sph[i].owner;
+                if (a.sph[cj.id].owner == own_i) continue;
+                if (n < STAGE_K) st[n] = cj.id;
+                if (bcount) atomicAdd(&bcount[cj.id], 1u);
+                ++n;
+            }
+        }
+    }
+    for (int w = 0; w < a.n_walls; ++w) {
+        WallDev wd = a.walls[w];
+        double pw[3];
+        wall_point(wd, a.step, a.h, pw);
+        if (!wall_hit(wd, pw, xi, yi, zi, ri, m)) continue;
+        if (n < STAGE_K) st[n] = (uint32_t)a.n_spheres + (uint32_t)w;
+        ++n;
+    }
+    count[i] = n;
+}
+
+// Moves staged rows (at most STAGE_K) to their CSR place, sorted, and fills
+// the B lists (slot order is fixed later by k_blist_sort).
+__global__ void __launch_bounds__(TPB) k_compact(const uint32_t *start, const uint32_t *stage, uint32_t *out_j,
+                                                 int64_t ns, int64_t cap, uint32_t *bcur, uint32_t *bidx)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ns || (int64_t)start[ns] > cap) return;
+    const uint32_t r0 = start[i], n = start[i + 1] - r0;
+    if (n == 0 || n > STAGE_K) return;
+    uint32_t v[STAGE_K];
+    const uint32_t *st = stage + (size_t)i * STAGE_K;
+#pragma unroll
+    for (int t = 0; t < STAGE_K; ++t) v[t] = (uint32_t)t < n ? st[t] : 0xffffffffu;
+    // sorting network on registers (odd-even transposition), ascending
+#pragma unroll
+    for (int r = 0; r < STAGE_K; ++r) {
+#pragma unroll
+        for (int t = (r & 1); t + 1 < STAGE_K; t += 2) {
+            uint32_t lo = v[t] < v[t + 1] ? v[t] : v[t + 1];
+            uint32_t hi = v[t] < v[t + 1] ? v[t + 1] : v[t];
+            v[t] = lo;
+            v[t + 1] = hi;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < STAGE_K; ++t) {
+        if ((uint32_t)t < n) {
+            out_j[r0 + t] = v[t];
+            if (bidx && (int64_t)v[t] < ns) bidx[atomicAdd(&bcur[v[t]], 1u)] = r0 + t;
+        }
+    }
+}
+
+// Rows longer than STAGE_K: traverse again, write, sort in place, fill B lists.
+__global__ void __launch_bounds__(TPB) k_detect_overflow(DetectArgs a, const uint32_t *keys, const Cand *cand,
+                                                         const uint32_t *cell_start, const uint32_t *start,
+                                                         uint32_t *out_j, int64_t cap, uint32_t *bcur,
+                                                         uint32_t *bidx)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n_spheres) return;
+    const uint32_t i = cand[p].id;
+    if ((int64_t)start[a.n_spheres] > cap) return;
+    const uint32_t base = start[i], total = start[i + 1] - base;
+    if (total <= STAGE_K) return;
+    const Cand ci = cand[p];
+    const uint32_t key = keys[p];
+    const double xi = ci.x, yi = ci.y, zi = ci.z, ri = (double)ci.r;
+    const double m = a.margin;
+    const uint32_t nx = (uint32_t)a.grid.nx, nxy = (uint32_t)a.grid.nx * (uint32_t)a.grid.ny;
+    uint32_t own_i = a.sph[i].owner;
+    uint32_t n = 0;
+    for (int dz = -1; dz <= 1; ++dz) {
+        for (int dy = -1; dy <= 1; ++dy) {
+            uint32_t row = key + (uint32_t)((int)nxy * dz) + (uint32_t)((int)nx * dy);
+            uint32_t q0 = cell_start[row - 1], q1 = cell_start[row + 2];
+            for (uint32_t qq = q0; qq < q1; ++qq) {
+                const Cand cj = cand[qq];
+                if (cj.id <= i) continue;
+                if (!sphere_pair_hit(xi, yi, zi, ri, cj, m)) continue;
+                if (a.sph[cj.id].owner == own_i) continue;
+                if (n < total) out_j[base + n] = cj.id;
+                ++n;
+            }
+        }
+    }
+    for (int w = 0; w < a.n_walls; ++w) {
+        WallDev wd = a.walls[w];
+        double pw[3];
+        wall_point(wd, a.step, a.h, pw);
+        if (!wall_hit(wd, pw, xi, yi, zi, ri, m)) continue;
+        if (n < total) out_j[base + n] = (uint32_t)a.n_spheres + (uint32_t)w;
+        ++n;
+    }
+    if (n > total) n = total;
+    for (uint32_t t = 1; t < n; ++t) {
+        uint32_t v = out_j[base + t];
+        uint32_t u = t;
+        while (u > 0 && out_j[base + u - 1] > v) {
+            out_j[base + u] = out_j[base + u - 1];
+            --u;
+        }
+        out_j[base + u] = v;
+    }
+    if (bidx)
+        for (uint32_t t = 0; t < n; ++t)
+            if ((int64_t)out_j[base + t] < a.n_spheres) bidx[atomicAdd(&bcur[out_j[base + t]], 1u)] = base + t;
+}
+
 __global__ void k_check_capacity(const uint32_t *start, int64_t ns, int64_t cap, DevCounters *ctr,
                                  int buf)
 {
@@ -242,10 +377,11 @@ __global__ void __launch_bounds__(TPB) k_blist_fill(const uint32_t *start, const
     }
 }
 
-__global__ void __launch_bounds__(TPB) k_blist_sort(const uint32_t *bstart, int64_t ns, uint32_t *bidx)
+__global__ void __launch_bounds__(TPB) k_blist_sort(const uint32_t *start, const uint32_t *bstart, int64_t ns,
+                                                    int64_t cap, uint32_t *bidx)
 {
     int64_t jv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (jv >= ns) return;
+    if (jv >= ns || (int64_t)start[ns] > cap) return;   // an overflowed set has no B lists
     uint32_t b0 = bstart[jv], b1 = bstart[jv + 1];
     for (uint32_t t = b0 + 1; t < b1; ++t) {
         uint32_t v = bidx[t];
@@ -259,9 +395,10 @@ __global__ void __launch_bounds__(TPB) k_blist_sort(const uint32_t *bstart, int6
 }
 
 __global__ void __launch_bounds__(TPB) k_remap(const uint32_t *os, const uint32_t *oj, const float *ohx,
-                                               const float *ohy, const float *ohz, const uint32_t *ns_,
-                                               const uint32_t *nj, float *nhx, float *nhy, float *nhz,
-                                               int64_t ns, DevCounters *ctr, int newbuf)
+                                               const float *ohy, const float *ohz, const float *ohw,
+                                               const uint32_t *ns_, const uint32_t *nj, float *nhx, float *nhy,
+                                               float *nhz, float *nhw, int64_t ns, DevCounters *ctr, int newbuf,
+                                               int rolling)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) {
@@ -277,10 +414,12 @@ __global__ void __launch_bounds__(TPB) k_remap(const uint32_t *os, const uint32_
             nhx[c] = ohx[p];
             nhy[c] = ohy[p];
             nhz[c] = ohz[p];
+            if (rolling) nhw[c] = ohw[p];
         } else {
             nhx[c] = 0.0f;
             nhy[c] = 0.0f;
             nhz[c] = 0.0f;
+            if (rolling) nhw[c] = 0.0f;
         }
     }
 }
@@ -302,10 +441,9 @@ void launch_blists(AcsBuf &b, int64_t ns, int64_t cap, uint32_t *partials, hipSt
 {
     launch_fill_u32(b.bcur, ns + 1, 0u, s);
     hipLaunchKernelGGL(k_blist_count, dim3(nblocks(ns)), dim3(TPB), 0, s, b.start, b.j, ns, cap, b.bcur);
-    scan_exclusive_u32(b.bcur, b.bstart, ns, partials, s);
-    launch_copy_u32(b.bcur, b.bstart, ns + 1, s);
+    scan_exclusive_u32(b.bcur, b.bstart, ns, partials, s, b.bcur);
     hipLaunchKernelGGL(k_blist_fill, dim3(nblocks(ns)), dim3(TPB), 0, s, b.start, b.j, ns, cap, b.bcur, b.bidx);
-    hipLaunchKernelGGL(k_blist_sort, dim3(nblocks(ns)), dim3(TPB), 0, s, b.bstart, ns, b.bidx);
+    hipLaunchKernelGGL(k_blist_sort, dim3(nblocks(ns)), dim3(TPB), 0, s, b.start, b.bstart, ns, cap, b.bidx);
 }
 
 void launch_detect(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap, DevCounters *ctr, int buf,
@@ -313,17 +451,16 @@ void launch_detect(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap, Dev
 {
     int64_t n = a.n_spheres;
     launch_bin(a, w, s);
-    hipLaunchKernelGGL(k_detect<MODE_COUNT>, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,
-                       w.cell_start, w.count, (const uint32_t *)nullptr, (uint32_t *)nullptr, cap,
-                       (const uint32_t *)nullptr, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                       (const uint32_t *)nullptr, (uint32_t *)nullptr, 0u);
-    scan_exclusive_u32(w.count, out.start, n, w.partials, s);
-    hipLaunchKernelGGL(k_check_capacity, dim3(1), dim3(1), 0, s, out.start, n, cap, ctr, buf);
-    hipLaunchKernelGGL(k_detect<MODE_WRITE>, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,
-                       w.cell_start, (uint32_t *)nullptr, out.start, out.j, cap,
-                       (const uint32_t *)nullptr, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                       (const uint32_t *)nullptr, (uint32_t *)nullptr, 0u);
-    launch_blists(out, n, cap, w.partials, s);
+    launch_fill_u32(out.bcur, n + 1, 0u, s);
+    hipLaunchKernelGGL(k_detect_stage, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand, w.cell_start,
+                       w.count, w.stage, out.bcur);
+    scan_exclusive_u32(w.count, out.start, n, w.partials, s, nullptr, ctr, cap, buf);
+    scan_exclusive_u32(out.bcur, out.bstart, n, w.partials, s, out.bcur);
+    hipLaunchKernelGGL(k_compact, dim3(nblocks(n)), dim3(TPB), 0, s, out.start, w.stage, out.j, n, cap, out.bcur,
+                       out.bidx);
+    hipLaunchKernelGGL(k_detect_overflow, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand, w.cell_start,
+                       out.start, out.j, cap, out.bcur, out.bidx);
+    hipLaunchKernelGGL(k_blist_sort, dim3(nblocks(n)), dim3(TPB), 0, s, out.start, out.bstart, n, cap, out.bidx);
 }
 
 void launch_judge(const DetectArgs &a, CdWork &w, const AcsBuf &cur, int64_t cap, DevCounters *ctr,
@@ -337,10 +474,11 @@ void launch_judge(const DetectArgs &a, CdWork &w, const AcsBuf &cur, int64_t cap
                        (const uint32_t *)nullptr, (uint32_t *)nullptr, 0u);
 }
 
-void launch_remap(const AcsBuf &o, AcsBuf &nb, int64_t ns, DevCounters *ctr, int newbuf, hipStream_t s)
+void launch_remap(const AcsBuf &o, AcsBuf &nb, int64_t ns, DevCounters *ctr, int newbuf, int rolling,
+                  hipStream_t s)
 {
-    hipLaunchKernelGGL(k_remap, dim3(nblocks(ns)), dim3(TPB), 0, s, o.start, o.j, o.hx, o.hy, o.hz,
-                       nb.start, nb.j, nb.hx, nb.hy, nb.hz, ns, ctr, newbuf);
+    hipLaunchKernelGGL(k_remap, dim3(nblocks(ns)), dim3(TPB), 0, s, o.start, o.j, o.hx, o.hy, o.hz, o.hw,
+                       nb.start, nb.j, nb.hx, nb.hy, nb.hz, nb.hw, ns, ctr, newbuf, rolling);
 }
 
 void launch_detect_plain(const DetectArgs &a, CdWork &w, uint32_t *start, uint32_t *j, int64_t cap,
@@ -348,16 +486,14 @@ void launch_detect_plain(const DetectArgs &a, CdWork &w, uint32_t *start, uint32
 {
     int64_t n = a.n_spheres;
     launch_bin(a, w, s);
-    hipLaunchKernelGGL(k_detect<MODE_COUNT>, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,
-                       w.cell_start, w.count, (const uint32_t *)nullptr, (uint32_t *)nullptr, cap,
-                       (const uint32_t *)nullptr, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                       (const uint32_t *)nullptr, (uint32_t *)nullptr, 0u);
+    hipLaunchKernelGGL(k_detect_stage, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand, w.cell_start,
+                       w.count, w.stage, (uint32_t *)nullptr);
     scan_exclusive_u32(w.count, start, n, w.partials, s);
     hipLaunchKernelGGL(k_record_total, dim3(1), dim3(1), 0, s, start, n, ctr);
-    hipLaunchKernelGGL(k_detect<MODE_WRITE>, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,
-                       w.cell_start, (uint32_t *)nullptr, start, j, cap,
-                       (const uint32_t *)nullptr, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                       (const uint32_t *)nullptr, (uint32_t *)nullptr, 0u);
+    hipLaunchKernelGGL(k_compact, dim3(nblocks(n)), dim3(TPB), 0, s, start, w.stage, j, n, cap,
+                       (uint32_t *)nullptr, (uint32_t *)nullptr);
+    hipLaunchKernelGGL(k_detect_overflow, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand, w.cell_start,
+                       start, j, cap, (uint32_t *)nullptr, (uint32_t *)nullptr);
 }
 
 void launch_label_judge(const DetectArgs &a, CdWork &w, const uint32_t *lab_start, const uint32_t *lab_j,

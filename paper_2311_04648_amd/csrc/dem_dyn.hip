@@ -73,7 +73,7 @@ __device__ inline bool stopped(const DevCounters *c, int64_t step)
 }
 
 __global__ void __launch_bounds__(TPB) k_force(DynArgs a, const uint32_t *start, const uint32_t *jarr,
-                                               float *hx, float *hy, float *hz, float *aF, float *aT,
+                                               float *hx, float *hy, float *hz, float *hw, float *aF, float *aT,
                                                float *bF, float *bT, int64_t cap, const DevCounters *ctr)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -168,6 +168,7 @@ __global__ void __launch_bounds__(TPB) k_force(DynArgs a, const uint32_t *start,
                 hx[c] = 0.f;
                 hy[c] = 0.f;
                 hz[c] = 0.f;
+                if (a.rolling) hw[c] = 0.f;
                 bF[c] = 0.f;
                 bF[cap + c] = 0.f;
                 bF[2 * cap + c] = 0.f;
@@ -184,7 +185,9 @@ __global__ void __launch_bounds__(TPB) k_force(DynArgs a, const uint32_t *start,
             const float3 n = f3((float)nrm[0], (float)nrm[1], (float)nrm[2]);
             const MatPair mq = a.mat[(size_t)sA.mat * (size_t)a.n_mat + matB];
             // relative velocity of A with respect to B at the contact point
-            const float3 u = (kA.v + cross3(kA.w, armA)) - (vB + cross3(wB, armB));
+            // (linear parts first, so their difference is exact-ish)
+            const float3 rotA = cross3(kA.w, armA), rotB = cross3(wB, armB);
+            const float3 u = (kA.v - vB) + (rotA - rotB);
             const float pn = dot3(u, n);
             const float3 ut = u - pn * n;
             float3 xi = f3(hx[c], hy[c], hz[c]);
@@ -197,6 +200,30 @@ __global__ void __launch_bounds__(TPB) k_force(DynArgs a, const uint32_t *start,
             const float c56 = 1.8257418583505538f;   // 2 sqrt(5/6)
             const float gn = c56 * mq.beta * sqrtf(Sn * mbar);
             float3 F = (kn * df + gn * pn) * n;
+            // rolling resistance: torque-only force C_rr |F_n| along the rolling
+            // part of the relative velocity, once the contact is older than
+            // the damped collision time of the simplified constants
+            float3 Fr = f3(0.f, 0.f, 0.f);
+            if (a.rolling) {
+                const float age = hw[c] + hf;
+                hw[c] = age;
+                if (mq.crr > 0.0f) {
+                    bool add = true;
+                    const float Reff = sqrtf(Rbar);
+                    const float kns = (4.0f / 3.0f) * mq.Estar * sqrtf(Reff);
+                    const float gns = -2.0f * sqrtf((5.0f / 3.0f) * mbar * mq.Estar) * mq.beta * sqrtf(sqrtf(Reff));
+                    const float dcf = gns / (2.0f * sqrtf(kns * mbar));
+                    if (dcf < 1.0f) {
+                        const float tcol = 3.14159265358979f * sqrtf(mbar / (kns * (1.0f - dcf * dcf)));
+                        if (age <= tcol) add = false;
+                    }
+                    if (add) {
+                        const float3 vr = rotB - rotA;
+                        const float vrn = sqrtf(dot3(vr, vr));
+                        if (vrn > 1e-12f) Fr = ((mq.crr * sqrtf(dot3(F, F))) / vrn) * vr;
+                    }
+                }
+            }
             if (mq.mu > 0.0f) {
                 const float kt = 8.0f * mq.Gstar * sqrtRd;
                 const float gt = -c56 * mq.beta * sqrtf(mbar * kt);
@@ -217,9 +244,10 @@ __global__ void __launch_bounds__(TPB) k_force(DynArgs a, const uint32_t *start,
             hy[c] = xi.y;
             hz[c] = xi.z;
             FA = FA + F;
-            TA = TA + cross3(armA, F);
+            const float3 Ft = F + Fr;
+            TA = TA + cross3(armA, Ft);
             const float3 mF = f3(-F.x, -F.y, -F.z);
-            const float3 tB = cross3(armB, mF);
+            const float3 tB = cross3(armB, f3(-Ft.x, -Ft.y, -Ft.z));
             bF[c] = mF.x;
             bF[cap + c] = mF.y;
             bF[2 * cap + c] = mF.z;
@@ -367,7 +395,7 @@ void launch_reduce_max(const DynArgs &a, DevCounters *ctr, hipStream_t s)
 void launch_force(const DynArgs &a, AcsBuf &cur, StepBufs &sb, DevCounters *ctr, hipStream_t s)
 {
     hipLaunchKernelGGL(k_force, dim3(nblocks(a.n_spheres)), dim3(TPB), 0, s, a, cur.start, cur.j, cur.hx,
-                       cur.hy, cur.hz, sb.aF, sb.aT, sb.bF, sb.bT, sb.cap, ctr);
+                       cur.hy, cur.hz, cur.hw, sb.aF, sb.aT, sb.bF, sb.bT, sb.cap, ctr);
 }
 
 void launch_fold_integrate(const DynArgs &a, const AcsBuf &cur, StepBufs &sb, DevCounters *ctr,

@@ -44,6 +44,9 @@ struct __align__(16) SphRec {
 
 struct __align__(16) MatPair {
     float Estar, Gstar, beta, mu;
+    float crr;         // rolling-resistance coefficient
+    float kns, tcol;   // simplified stiffness and collision time of the rolling-resistance gate (unused: per contact)
+    float pad;
 };
 
 struct __align__(16) WallDev {
@@ -98,9 +101,12 @@ struct ScanTmp {
 int64_t scan_tmp_elems(int64_t n);
 void launch_fill_u32(uint32_t *p, int64_t n, uint32_t value, hipStream_t s);
 void launch_copy_u32(uint32_t *dst, const uint32_t *src, int64_t n, hipStream_t s);
-// exclusive scan of in[0..n) into out[0..n], out[n] = total
+// exclusive scan of in[0..n) into out[0..n], out[n] = total (in may equal
+// out); optionally also into out2, and with ctr set, the total is recorded as
+// the size of active-set buffer `buf` and checked against cap.
 void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *partials,
-                        hipStream_t s);
+                        hipStream_t s, uint32_t *out2 = nullptr, DevCounters *ctr = nullptr,
+                        int64_t cap = 0, int buf = 0);
 int64_t radix_hist_elems(int64_t n);
 // stable LSD radix sort of (keys, vals) on the low `bits` bits; the buffer
 // pairs are swapped as needed so the result ends in (*keys, *vals); the alt
@@ -129,6 +135,7 @@ struct CdWork {
     Cand *cand_tmp, *cand;
     uint32_t *cell_count, *cell_start;
     uint32_t *count;       // [Ns+1]
+    uint32_t *stage;       // [16 Ns] staged partners of the single-traversal detection
     uint32_t *hist, *partials;
     int sort_bits;
 };
@@ -137,6 +144,7 @@ struct AcsBuf {
     uint32_t *start;   // [Ns+1]
     uint32_t *j;       // [cap]
     float *hx, *hy, *hz;
+    float *hw;         // contact age (tracked only with rolling resistance)
     uint32_t *bstart;  // [Ns+1]
     uint32_t *bidx;    // [cap]
     uint32_t *bcur;    // [Ns+1] scratch cursor
@@ -150,7 +158,7 @@ void launch_judge(const DetectArgs &a, CdWork &w, const AcsBuf &cur, int64_t cap
                   hipStream_t s);
 void launch_blists(AcsBuf &b, int64_t n_spheres, int64_t cap, uint32_t *partials, hipStream_t s);
 void launch_remap(const AcsBuf &oldb, AcsBuf &newb, int64_t n_spheres, DevCounters *ctr, int newbuf,
-                  hipStream_t s);
+                  int rolling, hipStream_t s);
 
 struct DynArgs {
     OwnerRec *rec;
@@ -170,6 +178,7 @@ struct DynArgs {
     float v_err2;
     int64_t step;
     int32_t has_clumps;
+    int32_t rolling;        // some material pair has rolling resistance
     int32_t cur;            // active-set buffer in use (for statistics)
     float *blkmax;          // per-block max |v|^2 of the last integration [ceil(No/256)]
 };

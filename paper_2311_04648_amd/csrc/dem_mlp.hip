@@ -9,7 +9,7 @@
 //   f4 tau / K                              steps since the last detection
 //   f5 log1p(max|v| h K / m)                absolute speed
 //   f6 log1p(max|X - X_snap| / m)           margin consumed since the snapshot
-// with K = 256 steps, m the margin, h the step, tau the steps since the
+// with K = DEM_MLP_KCAP steps, m the margin, h the step, tau the steps since the
 // snapshot.  Per-cell maxima and minima use order-free integer atomics and
 // the volume a fixed-point integer sum, so features are deterministic; the
 // occupied cells are compacted in cell order with a scan.
@@ -332,7 +332,7 @@ void feature_pipeline(const OwnerRec *rec, const OwnerRec *snap, const uint32_t 
     double edge = 1.0 / fg.inv_b;
     float cell_vol = (float)(edge * edge * edge);
     hipLaunchKernelGGL(k_feat_write, dim3(nblocks(nc, 256)), dim3(256), 0, s, raw, pos, nc, h, margin, tau,
-                       256.0f, cell_vol, out, cell_ids);
+                       (float)DEM_MLP_KCAP, cell_vol, out, cell_ids);
 }
 
 void mlp_forward(const float *params, const float *X, float *Y, int64_t n, hipStream_t s)

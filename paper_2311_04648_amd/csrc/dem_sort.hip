@@ -79,25 +79,25 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_reduce(const uint32_t *in
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
-// One block scans the tile sums in place (exclusive) and appends the total.
-__global__ void __launch_bounds__(SCAN_THREADS) k_scan_partials(uint32_t *partials, int64_t nb)
-{
-    uint32_t carry = 0;
-    for (int64_t base = 0; base < nb; base += SCAN_THREADS) {
-        int64_t i = base + threadIdx.x;
-        uint32_t v = (i < nb) ? partials[i] : 0u;
-        uint32_t tot;
-        uint32_t ex = block_excl_scan(v, &tot);
-        if (i < nb) partials[i] = ex + carry;
-        carry += tot;
-    }
-    if (threadIdx.x == 0) partials[nb] = carry;
-}
-
+// Tile scan + offset.  Each block adds up the sums of the tiles before it
+// (strided over its threads, then a block reduction; integer sums are exact
+// in any order), so no separate pass over the tile sums is needed.  Also
+// writes out[n] = total, an optional copy of the result, and an optional
+// capacity check of the total.
 __global__ void __launch_bounds__(SCAN_THREADS) k_scan_down(const uint32_t *in, uint32_t *out,
-                                                            int64_t n, const uint32_t *partials,
-                                                            int64_t nb)
+                                                            uint32_t *out2, int64_t n,
+                                                            const uint32_t *partials, int64_t nb,
+                                                            DevCounters *ctr, int64_t cap, int buf)
 {
+    __shared__ uint32_t red[SCAN_THREADS / 64];
+    uint32_t pre = 0;
+    for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += SCAN_THREADS) pre += partials[b];
+    for (int d = 32; d > 0; d >>= 1) pre += __shfl_xor(pre, d, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = pre;
+    __syncthreads();
+    pre = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_THREADS / 64; ++k) pre += red[k];
     int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
     uint32_t v[SCAN_ITEMS];
     uint32_t s = 0;
@@ -108,14 +108,30 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_down(const uint32_t *in, 
         s += v[k];
     }
     uint32_t tot;
-    uint32_t ex = block_excl_scan(s, &tot) + partials[blockIdx.x];
+    uint32_t ex = block_excl_scan(s, &tot) + pre;
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
         int64_t i = base + k;
-        if (i < n) out[i] = ex;
+        if (i < n) {
+            out[i] = ex;
+            if (out2) out2[i] = ex;
+        }
         ex += v[k];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = partials[nb];
+    if (blockIdx.x == nb - 1 && threadIdx.x == SCAN_THREADS - 1) {
+        // ex is now the grand total (last thread of the last tile)
+        out[n] = ex;
+        if (out2) out2[n] = ex;
+        if (ctr) {
+            ctr->n_contacts[buf] = ex;
+            if ((int64_t)ex > cap) {
+                ctr->overflow[buf] = 1u;
+                atomicMax(&ctr->required, ex);
+            } else {
+                ctr->overflow[buf] = 0u;
+            }
+        }
+    }
 }
 
 __global__ void __launch_bounds__(RADIX_THREADS) k_radix_up(const uint32_t *keys, int64_t n, int shift,
@@ -214,17 +230,17 @@ void launch_copy_u32(uint32_t *dst, const uint32_t *src, int64_t n, hipStream_t 
 }
 
 void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *partials,
-                        hipStream_t s)
+                        hipStream_t s, uint32_t *out2, DevCounters *ctr, int64_t cap, int buf)
 {
     int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb == 0) {
         launch_fill_u32(out, 1, 0u, s);
+        if (out2) launch_fill_u32(out2, 1, 0u, s);
         return;
     }
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, in, n, partials);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, partials, nb);
-    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, in, out, n,
-                       partials, nb);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, in, out, out2, n,
+                       partials, nb, ctr, cap, buf);
 }
 
 void radix_sort_u32(uint32_t **keys, uint32_t **vals, uint32_t **keys_alt, uint32_t **vals_alt,

@@ -1,12 +1,15 @@
 """Training of the learned contact-detection interval on the GPU.
 
-Logs come from the method itself: a run with every-step detection, split
-into windows.  In each window the state at the window start s is the
-reference (snapshot), the dynamics advance tau steps, the per-cell
-features are taken at step s + tau, a "label" active set is detected there
-with the run's margin, and the dynamics advance K = 256 more steps while
-every true contact is looked up in the label set; the label of a cell is the
-first step at which a true contact touching it is missing (censored at K).
+Logs come from the method itself.  A run advances with exact dynamics
+(delayed detection with a small interval, whose trajectory equals
+every-step detection) and opens label windows at steps spread over the run,
+so the windows see slow and fast regimes.  In a window starting at s the
+state at s - tau is the reference (snapshot), the per-cell features are taken
+at s, a "label" active set is detected there with the run's margin, and the
+dynamics advance K = 1024 more steps while every true contact (per-step
+detection with margin 0) is looked up in the label set; the label of a cell
+is the first step at which a true contact touching it is missing (censored
+at K).
 Targets are log(1 + label).  The network is trained with the project's own
 HIP kernels (forward, backward with an ordered gradient reduction, Adam)
 under the expectile loss (tau = 0.05), which favours under-prediction.
@@ -24,20 +27,23 @@ import time
 
 import numpy as np
 
-K_CAP = 256
+K_CAP = 1024
+WINDOW_STARTS = (400, 1500, 3000, 5000, 8000, 12000, 17000, 23000, 30000, 38000)
 
 
-def generate_logs(dem, sysm, windows=16, taus=(5, 10, 20, 40, 80), K=K_CAP, warm=0, log=None):
+def generate_logs(dem, sysm, starts=WINDOW_STARTS, taus=(5, 10, 20, 40, 80, 160, 320), K=K_CAP, log=None):
     """Returns (features float32 [n,6], targets float32 [n]) from one run."""
     torch = dem._torch()
-    ctx = dem.DemContext(sysm, mode="every", capacity=max(64, 10 * sysm.n_spheres))
+    ctx = dem.DemContext(sysm, mode="fixed", k=4, lam=0, capacity=max(64, 10 * sysm.n_spheres))
     ctx.set_state()
-    if warm:
-        ctx.step(warm)
     ncell = ctx.info()["ncells"]
     feats, targets = [], []
-    for w in range(windows):
+    step = 0
+    for w, s in enumerate(starts):
         tau = taus[w % len(taus)]
+        if s - tau < step:
+            continue
+        ctx.step(s - tau - step)
         ctx.snapshot()
         ctx.step(tau)
         f, ids, _ = ctx.features()
@@ -46,13 +52,14 @@ def generate_logs(dem, sysm, windows=16, taus=(5, 10, 20, 40, 80), K=K_CAP, warm
         for t in range(1, K + 1):
             ctx.step(1)
             ctx.label_update(t, first)
+        step = s + K
         torch.cuda.synchronize()
-        lab = first.cpu().numpy().astype(np.int64)[ids]
-        lab = np.minimum(lab, K)
+        lab = np.minimum(first.cpu().numpy().astype(np.int64)[ids], K)
         feats.append(f.cpu().numpy())
         targets.append(np.log1p(lab.astype(np.float64)).astype(np.float32))
         if log:
-            log(f"  window {w}: tau {tau} cells {ids.size} min label {lab.min()} mean {lab.mean():.1f}")
+            log(f"  window at {s}: tau {tau} cells {ids.size} labels min {lab.min()} "
+                f"censored {np.mean(lab >= K):.2f} mean {lab.mean():.1f}")
     ctx.close()
     return np.concatenate(feats), np.concatenate(targets)
 
@@ -107,7 +114,6 @@ def main():
     ap.add_argument("--out", default="gpurun_out/mlp_interval.json")
     ap.add_argument("--n1", type=int, default=100_000, help="spheres of the config-1 log runs")
     ap.add_argument("--n2", type=int, default=30_000, help="clumps of the config-2 log runs")
-    ap.add_argument("--windows", type=int, default=12)
     ap.add_argument("--epochs", type=int, default=300)
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
@@ -127,7 +133,7 @@ def main():
                 nt = int(args.n2 * 0.9)
                 s = W.config2(seed=seed, n_tri=nt, n_penta=args.n2 - nt)
             log(f"logs {name} seed {seed}: {s.n_spheres} spheres")
-            X, T = generate_logs(dem, s, windows=args.windows, warm=200 * seed, log=log)
+            X, T = generate_logs(dem, s, log=log)
             Xs.append(X)
             Ts.append(T)
             meta.append(dict(config=name, seed=seed, n_spheres=s.n_spheres, samples=int(X.shape[0])))

@@ -32,8 +32,26 @@ def dem():
     return d
 
 
+def cluster(n_small=60, R=0.006, r=0.0015):
+    """One large sphere with small ones on its surface: rows far longer than
+    the 16 staged partners of the single-traversal detection."""
+    k = np.arange(n_small) + 0.5
+    phi = np.arccos(1 - 2 * k / n_small)
+    th = np.pi * (1 + 5 ** 0.5) * k
+    d = R + r - 2e-5
+    pts = d * np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], 1)
+    X = np.vstack([np.zeros((1, 3)), pts])
+    rad = np.r_[R, np.full(n_small, r)]
+    rng = np.random.default_rng(0)
+    V = rng.normal(0, 0.05, size=X.shape)
+    return W.assemble(np.full(X.shape[0], -1), X, W._qid(X.shape[0]), V, np.zeros_like(X), [], rad, None,
+                      W.box_walls(-0.02 * np.ones(3), 0.02 * np.ones(3)), W.materials(), (0, 0, -9.81), 2e-6,
+                      0.0002, -0.02 * np.ones(3), 0.02 * np.ones(3), name="cluster")
+
+
 def systems():
     return {
+        "cluster": cluster(),
         "spheres": W.small_spheres(1, n=343),
         "clumps": W.small_clumps(2, n=150, with_cylinder=True, spacing=0.0085),
         "config0": W.config0(),
@@ -114,7 +132,7 @@ def test_contact_sets_bit_exact(dem, name, margin_scale):
     assert np.all(hist == 0)
 
 
-def _force_case(dem, s, seed=0, presteps=0):
+def _force_case(dem, s, seed=0, presteps=0, ages=False):
     ctx = dem.DemContext(s, mode="fixed", margin=max(s.margin, 1e-4))
     ctx.set_state()
     if presteps:
@@ -122,7 +140,8 @@ def _force_case(dem, s, seed=0, presteps=0):
     ctx.detect_contacts(max(s.margin, 1e-4))
     keys, _ = ctx.get_contacts()
     rng = np.random.default_rng(seed)
-    hist = W.f32(rng.normal(0.0, 3e-6, size=(keys.size, 3))).astype(np.float32)
+    hist = W.f32(rng.normal(0.0, 3e-6, size=(keys.size, 4))).astype(np.float32)
+    hist[:, 3] = W.f32(rng.uniform(0.0, 3e-5, size=keys.size)) if ages else 0.0
     ctx.set_contacts(keys, hist)
     ctx.forces()
     Fo, To, Fc = ctx.get_forces(keys.size)
@@ -151,9 +170,9 @@ def test_forces_match_oracle(dem, name):
     assert np.all(Fc[~touch] == 0.0)
     assert np.all(h2[~touch] == 0.0)
     # history
-    hn = np.linalg.norm(ref["hist"], axis=1)
+    hn = np.linalg.norm(ref["hist"][:, :3], axis=1)
     hmed = np.median(hn[touch]) if touch.any() else 1.0
-    herr = np.linalg.norm(h2 - ref["hist"], axis=1) / np.maximum(hn, 1e-3 * hmed)
+    herr = np.linalg.norm(h2[:, :3] - ref["hist"][:, :3], axis=1) / np.maximum(hn, 1e-3 * hmed)
     assert herr.max() <= 1e-5
     # owner sums: tolerance relative to the summed magnitudes of the terms
     own = s.sph_owner
@@ -170,9 +189,42 @@ def test_forces_match_oracle(dem, name):
     assert np.all(terr <= 1e-5 * np.maximum(Tscale, 1e-3 * Fmed * 0.003) + 1e-30)
 
 
-@pytest.mark.parametrize("name", list(SYS))
+def test_rolling_resistance_matches_oracle(dem):
+    """Default model with C_rr > 0: the torque-only rolling-resistance force
+    and the contact-age gate (Eq. (2), default-model walk-through)."""
+    s = W.small_spheres(21, n=343, vel=0.3)
+    s.mat_crr[:] = 0.1
+    keys, Fo, To, Fc, h2, ref = _force_case(dem, s, seed=4, ages=True)
+    touch = ref["touch"] > 0
+    assert touch.sum() > 10
+    Fn = np.linalg.norm(ref["Fc"], axis=1)
+    Fmed = np.median(Fn[touch])
+    rel = np.linalg.norm(Fc - ref["Fc"], axis=1) / np.maximum(Fn, 1e-3 * Fmed)
+    assert rel.max() <= 1e-5
+    np.testing.assert_allclose(h2[touch, 3], ref["hist"][touch, 3], rtol=1e-6)
+    assert np.all(h2[~touch, 3] == 0.0)
+    L1 = np.zeros(s.n_owners)
+    ks = (keys >> np.uint64(32)).astype(np.int64)
+    js = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    np.add.at(L1, s.sph_owner[ks], Fn)
+    sph = js < s.n_spheres
+    np.add.at(L1, s.sph_owner[js[sph]], Fn[sph])
+    terr = np.linalg.norm(To - ref["To"], axis=1)
+    assert np.all(terr <= 1e-5 * np.maximum(L1 * 0.006, 1e-3 * Fmed * 0.003) + 1e-30)
+    # the rolling torque is on: torques differ from the C_rr = 0 model
+    s0 = W.small_spheres(21, n=343, vel=0.3)
+    ref0 = oracle.Oracle(s0).forces({k: v for k, v in zip(("X", "q", "V", "W"),
+                                     (s.X, s.q, s.V, s.W))}, keys, np.asarray(h2, dtype=np.float64))
+    assert np.abs(ref["To"] - ref0["To"]).max() > 1e-3 * np.abs(ref["To"]).max()
+
+
+@pytest.mark.parametrize("name", list(SYS) + ["rolling"])
 def test_one_step_matches_oracle(dem, name):
-    s = SYS[name]
+    if name == "rolling":
+        s = W.small_spheres(22, n=343, vel=0.3)
+        s.mat_crr[:] = 0.1
+    else:
+        s = SYS[name]
     ctx = dem.DemContext(s, mode="every")
     ctx.set_state()
     g0 = ctx.get_state()

@@ -106,7 +106,7 @@ def test_features_closed_form():
     Vs = np.zeros((3, 3))
     ids, f = mlp.features(s, X, V, Xs, Vs, tau_steps=8)
     assert ids.size == 1
-    h, m, K = s.dt, s.margin, 256.0
+    h, m, K = s.dt, s.margin, mlp.K_CAP
     lo, edge, nf = mlp.feature_grid(s)
     spread = math.sqrt(0.1 ** 2 + 0.2 ** 2 + 0.3 ** 2)
     vol = (4 / 3 * math.pi * s.sph_rad ** 3).sum() / edge ** 3

@@ -181,7 +181,7 @@ def test_sliding_sphere_reaches_five_sevenths():
 def test_incline_rolling_threshold(alpha_deg, rolls):
     """Sec. 4.3.1: the sphere (r = 0.2 m, 5 kg, v0 = 0.5 m/s up the slope,
     mu = 0.25) rolls without sliding iff tan(alpha) <= 3.5 mu."""
-    mu, crr, alpha_c = _golden("incline_rolling_threshold.txt")[0]
+    mu, crr, alpha_c, _ = _golden("incline_rolling_threshold.txt")[0]
     assert abs(math.degrees(math.atan(3.5 * mu - 2.5 * crr)) - alpha_c) < 1e-9
     a = math.radians(alpha_deg)
     g = 9.81
@@ -195,6 +195,34 @@ def test_incline_rolling_threshold(alpha_deg, rolls):
     slip = v - ww[1] * 0.2
     if rolls:
         assert abs(slip) < 2e-3 * abs(v)
+    else:
+        assert abs(slip) > 0.05 * abs(v)
+
+
+@pytest.mark.parametrize("alpha_deg,mode", [(2.0, "stationary"), (5.0, "rolling"), (30.0, "rolling"),
+                                            (42.0, "sliding")])
+def test_incline_with_rolling_resistance(alpha_deg, mode):
+    """Sec. 4.3.1 with C_r > 0: at rest iff tan(alpha) <= C_r, rolling
+    without sliding iff tan(alpha) <= 3.5 mu - 2.5 C_r, sliding above."""
+    mu, crr, alpha_roll, alpha_rest = _golden("incline_rolling_threshold.txt")[1]
+    assert abs(math.degrees(math.atan(3.5 * mu - 2.5 * crr)) - alpha_roll) < 1e-9
+    assert abs(math.degrees(math.atan(crr)) - alpha_rest) < 1e-9
+    a = math.radians(alpha_deg)
+    g = 9.81
+    gvec = (g * math.sin(a), 0.0, -g * math.cos(a))
+    s = sphere_on_plane([-0.5, 0, 0], [0, 0, 0], mu, gvec, r=0.2, m=5.0, dt=2e-5)
+    s.mat_crr[:] = crr
+    o = oracle.Oracle(s)
+    st, acs, _, step = o.run(o.state(), 40000, mode="every")
+    v = st["V"][0, 0]
+    R = Rotation.from_quat(st["q"][0, [1, 2, 3, 0]]).as_matrix()
+    slip = v - (R @ st["W"][0])[1] * 0.2
+    if mode == "stationary":
+        assert abs(v) < 1e-3
+        st2, *_ = o.run(st, 5000, mode="every", acs=acs, step=step)
+        assert abs(st2["X"][0, 0] - st["X"][0, 0]) < 1e-4
+    elif mode == "rolling":
+        assert v > 0.05 and abs(slip) < 2e-3 * v
     else:
         assert abs(slip) > 0.05 * abs(v)
 

@@ -353,13 +353,16 @@ def config2(seed=0, n_tri=900_000, n_penta=100_000):
 
 def config3(seed=7, n=8_000_000):
     """Granular column: lognormal radii (median 3 mm, sigma 0.25, clipped to
-    [1.5, 6] mm) on a 12.5 mm lattice in a 2 x 2 m footprint, released onto
-    a floor inside far side walls; dt = 5e-6 s; margin 0.15 mm."""
+    [1.5, 6] mm) on a 12.5 mm lattice in a 2 x 2 m footprint (160 x 160 sites
+    per layer at 8 M spheres; smaller n shrink the footprint with the cube
+    root so the column keeps its aspect), released onto a floor inside far
+    side walls; dt = 5e-6 s; margin 0.15 mm."""
     rng = np.random.default_rng(seed)
     s = 0.0125
-    per = 160
+    per = max(4, int(round(160 * (n / 8_000_000) ** (1.0 / 3.0))))
     layers = -(-n // (per * per))
-    base = lattice((per, per, layers), s, np.array([-1.0 + 0.5 * s, -1.0 + 0.5 * s, 0.5 * s]),
+    half = 0.5 * per * s
+    base = lattice((per, per, layers), s, np.array([-half + 0.5 * s, -half + 0.5 * s, 0.5 * s]),
                    n_take=n)
     rad = np.clip(0.003 * np.exp(0.25 * rng.standard_normal(n)), 0.0015, 0.006)
     jit = rng.uniform(-0.0002, 0.0002, size=(n, 3))
@@ -368,11 +371,41 @@ def config3(seed=7, n=8_000_000):
     walls = concat_walls(plane(lo, (0, 0, 1)), plane((-5.0, 0, 0), (1, 0, 0)),
                          plane((5.0, 0, 0), (-1, 0, 0)), plane((0, -5.0, 0), (0, 1, 0)),
                          plane((0, 5.0, 0), (0, -1, 0)))
-    lo_dom = np.array([-1.25, -1.25, 0.0])
-    hi_dom = np.array([1.25, 1.25, top])
+    lo_dom = np.array([-1.25 * half - 0.05, -1.25 * half - 0.05, 0.0])
+    hi_dom = np.array([1.25 * half + 0.05, 1.25 * half + 0.05, top])
     return assemble(np.full(n, -1), base + jit, _qid(n), np.zeros((n, 3)), np.zeros((n, 3)),
                     [], rad, None, walls, materials(), (0, 0, -9.81), 5e-6, 0.00015,
                     lo_dom, hi_dom, name="config3", meta=dict(steps=20000, seed=seed))
+
+
+def config4(seed=0, n_owners=32_000_000, frac_single=18.0 / 32.0):
+    """Large bed (about 60 M spheres at full size): single spheres
+    (r = 2 mm) and tri-sphere clumps (r = 2 mm, circumradius 4/3 mm) on a
+    7 mm lattice filling a 2 x 2 m container bottom-up (the bed is built
+    packed rather than settled), then an analytic cylinder (R = 0.1 m,
+    L = 0.5 m, axis y) resting on the bed top moves +x at 0.2 m/s with
+    rolling angular velocity v / R; dt = 5e-6 s; margin 0.2 mm."""
+    rng = np.random.default_rng(seed)
+    s = 0.007
+    per = max(4, int(round(285 * (n_owners / 32_000_000) ** 0.5)))
+    layers = -(-n_owners // (per * per))
+    half = 0.5 * per * s
+    base = lattice((per, per, layers), s, np.array([-half + 0.5 * s, -half + 0.5 * s, 0.5 * s]),
+                   n_take=n_owners)
+    jit = rng.uniform(-0.0002, 0.0002, size=(n_owners, 3))
+    q = random_quaternions(rng, n_owners)
+    types = np.where(rng.random(n_owners) < frac_single, -1, 0).astype(np.int32)
+    q[types < 0] = np.array([1.0, 0, 0, 0])
+    top = base[:, 2].max() + 0.0035
+    lo, hi = np.array([-half - 0.003, -half - 0.003, 0.0]), np.array([half + 0.003, half + 0.003, top + 0.25])
+    R = 0.1
+    cyl = cylinder((-half + 0.3, 0.0, top + R - 0.0005), (0, 1, 0), R, 0.5, vel=(0.2, 0.0, 0.0),
+                   omega=(0.0, 0.2 / R, 0.0))
+    walls = concat_walls(box_walls(lo, hi), cyl)
+    return assemble(types, base + jit, q, np.zeros((n_owners, 3)), np.zeros((n_owners, 3)),
+                    [tri_template(0.002, 0.002 * 2.0 / 3.0)], 0.002, [0], walls, materials(),
+                    (0, 0, -9.81), 5e-6, 0.0002, lo, hi, name="config4",
+                    meta=dict(steps=5000, seed=seed))
 
 
 def _qid(n):
