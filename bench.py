@@ -37,8 +37,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--n", type=int, default=1_000_000, help="spheres (workload size)")
-    ap.add_argument("--modes", default="fixed,every,learned")
+    ap.add_argument("--n", type=int, default=1_000_000, help="spheres of the config-1 workload")
+    ap.add_argument("--workload", default="config1",
+                    help="config1 (headline) | config2 | config3 | config4: other sizes for the design notes")
+    ap.add_argument("--modes", default="fixed,every,learned,analytic",
+                    help="schedules: fixed (k steps), every (every step), learned (MLP interval), "
+                         "analytic (the learned schedule's fallback bound alone, no network)")
     ap.add_argument("--no-judge", action="store_true", help="skip the judged (miss-counting) runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=50)
@@ -102,11 +106,17 @@ def load_traffic(kernel):
         return None
 
 
-def run_mode(dem, torch, sysm, mode, args, mlp=None, judge=False):
-    ctx = dem.DemContext(sysm, mode=mode, k=args.k, lam=args.lam, judge=judge, timing=not judge,
-                         capacity=max(64, 8 * sysm.n_spheres), k_max=256)
+def make_ctx(dem, sysm, mode, args, mlp, judge):
+    lib_mode = "learned" if mode == "analytic" else mode
+    ctx = dem.DemContext(sysm, mode=lib_mode, k=args.k, lam=args.lam, judge=judge, timing=0 if judge else 4,
+                         capacity=max(64, 8 * sysm.n_spheres), k_max=1024, mlp_safety=args.mlp_safety)
     if mode == "learned":
         ctx.mlp_set(mlp)
+    return ctx
+
+
+def run_mode(dem, torch, sysm, mode, args, mlp=None, judge=False):
+    ctx = make_ctx(dem, sysm, mode, args, mlp, judge)
     ctx.set_state()
     dyn, kin = torch.cuda.Stream(), torch.cuda.Stream()
     if args.warmup:
@@ -152,14 +162,27 @@ def main():
         build.build()
     torch.cuda.init()
     t_gen = time.perf_counter()
-    sysm = W.config1(seed=0, n=args.n)
+    if args.workload == "config1":
+        sysm = W.config1(seed=0, n=args.n)
+    elif args.workload == "config2":
+        sysm = W.config2(seed=0)
+    elif args.workload == "config3":
+        sysm = W.config3(seed=7)
+    elif args.workload == "config4":
+        sysm = W.config4(seed=0)
+    else:
+        raise SystemExit(f"unknown workload {args.workload}")
     print(f"# workload generated: {sysm.n_spheres} spheres in {time.perf_counter() - t_gen:.1f}s",
           file=sys.stderr, flush=True)
     Ns, No = sysm.n_spheres, sysm.n_owners
     mlp = None
+    mlp_safety = 1.0
     mlp_path = os.path.join(ROOT, "paper_2311_04648_amd", "mlp_interval.json")
     if os.path.exists(mlp_path):
-        mlp = np.array(json.load(open(mlp_path))["params"], dtype=np.float32)
+        md = json.load(open(mlp_path))
+        mlp = np.array(md["params"], dtype=np.float32)
+        mlp_safety = float(md.get("safety", 1.0))
+    args.mlp_safety = mlp_safety
 
     modes = [m for m in args.modes.split(",") if m]
     results = {}
@@ -178,10 +201,7 @@ def main():
             if mode == "every":
                 misses[mode] = 0
                 continue
-            ctx = dem.DemContext(sysm, mode=mode, k=args.k, lam=args.lam, judge=True,
-                                 capacity=max(64, 8 * Ns), k_max=256)
-            if mode == "learned":
-                ctx.mlp_set(mlp)
+            ctx = make_ctx(dem, sysm, mode, args, mlp, True)
             ctx.set_state()
             st = ctx.step(args.warmup + args.steps)
             misses[mode] = int(st["misses"])
@@ -216,7 +236,7 @@ def main():
                 "note": "detection chain on the second stream, concurrent with the dynamics stream"}
 
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and Ns <= 10_000_000:
         import oracle
         o = oracle.Oracle(sysm)
         ost = o.state()
@@ -252,10 +272,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{Ns} polydisperse spheres r~U(2,3) mm settling from a jittered 7.5 mm lattice "
-                               f"in a 0.6x0.6x1.2 m box, dt 5e-6 s, margin 0.2 mm, delayed CD every {args.k} "
-                               f"steps on a second HIP stream (adoption latency {args.lam})",
-                   "n_spheres": Ns, "schedule": head, "k": args.k, "lambda": args.lam},
+        "config": {"workload": (f"{Ns} polydisperse spheres r~U(2,3) mm settling from a jittered 7.5 mm lattice "
+                                f"in a 0.6x0.6x1.2 m box, dt 5e-6 s, margin 0.2 mm, delayed CD every {args.k} "
+                                f"steps on a second HIP stream (adoption latency {args.lam})")
+                   if args.workload == "config1" else f"{args.workload}: {Ns} spheres, {No} owners",
+                   "n_spheres": Ns, "n_owners": No, "schedule": head, "k": args.k, "lambda": args.lam},
         "modes": modes_out,
         "missed_contacts": misses.get(head),
         "roofline": roofline,

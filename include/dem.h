@@ -135,7 +135,9 @@ typedef struct {
     int32_t judge;          /* 1: count contacts missing from the set in use, every step */
     int32_t repair;         /* 1: a missed contact discards the stale set (default) */
     int32_t cd_interval_max;/* LEARNED: upper bound on the interval */
-    int32_t timing;         /* 1: time each kernel stage with HIP events (stats->stage_ms) */
+    int32_t timing;         /* n > 0: time kernel stages with HIP events (stats->stage_ms);
+                               force and fold stages are sampled every n-th step */
+    double mlp_safety;      /* LEARNED: factor on the predicted horizon (0 = 1) */
 } dem_params;
 
 /* Statistics of a dem_step call (Sec. 2.1, thread collaboration stats). */
@@ -282,8 +284,9 @@ int64_t dem_mlp_backward_work_bytes(int64_t n);
 
 /* ---- training-log tools (the learned interval is trained on logs the
  * method generates with per-step detection) ------------------------------
- * dem_snapshot: copies the current state into the work-order snapshot that
- *   features are measured against (steps since the last detection restart).
+ * dem_snapshot: copies the current state into the reference that features
+ *   are measured against (steps since the last detection restart there; in
+ *   DEM_CD_LEARNED runs every work order does this).
  * dem_feature_cells: after dem_features, the feature-cell id of each output
  *   row (host cell_ids [cap]) and of each owner (host owner_cell [No]).
  * dem_label_begin: detects, with the run margin, a side "label" set on the

@@ -35,7 +35,7 @@ class Params(C.Structure):
                 ("v_error_out", C.c_double), ("domain_lo", C.c_double * 3), ("domain_hi", C.c_double * 3),
                 ("cd_mode", C.c_int32), ("cd_interval", C.c_int32), ("cd_latency", C.c_int32),
                 ("judge", C.c_int32), ("repair", C.c_int32), ("cd_interval_max", C.c_int32),
-                ("timing", C.c_int32)]
+                ("timing", C.c_int32), ("mlp_safety", C.c_double)]
 
 
 class Materials(C.Structure):
@@ -147,7 +147,7 @@ class DemContext:
     """One DEM problem bound to caller-owned device memory (a torch tensor)."""
 
     def __init__(self, system, mode="every", k=10, lam=5, judge=False, repair=True, capacity=None,
-                 margin=None, v_error_out=0.0, k_max=None, device="cuda:0", timing=False):
+                 margin=None, v_error_out=0.0, k_max=None, device="cuda:0", timing=False, mlp_safety=1.0):
         torch = _torch()
         self.torch = torch
         self.device = torch.device(device)
@@ -175,7 +175,8 @@ class DemContext:
         P.judge = int(bool(judge))
         P.repair = int(bool(repair))
         P.cd_interval_max = int(k_max or 16 * max(int(k), 1))
-        P.timing = int(bool(timing))
+        P.timing = int(timing) if not isinstance(timing, bool) else int(timing)
+        P.mlp_safety = float(mlp_safety)
         self.params = P
         Mt = Materials(int(np.asarray(s.mat_E).shape[0]), keep(s.mat_E, np.float64), keep(s.mat_nu, np.float64),
                        keep(s.mat_cor, np.float64), keep(s.mat_mu, np.float64), keep(s.mat_crr, np.float64))
@@ -268,12 +269,15 @@ class DemContext:
 
     def get_contacts(self, stream=None):
         n = C.c_int64()
-        cap = self.capacity
-        keys = np.zeros(cap, dtype=np.uint64)
-        hist = np.zeros((cap, 4), dtype=np.float32)
+        st = lib().dem_get_contacts(self.ctx, None, None, 0, C.byref(n), _stream_ptr(stream))
+        if st not in (DEM_OK, DEM_ERR_CAPACITY) or n.value > self.capacity:
+            self._check(st if st != DEM_OK else DEM_ERR_CAPACITY)
+        cap = int(n.value)
+        keys = np.zeros(max(cap, 1), dtype=np.uint64)
+        hist = np.zeros((max(cap, 1), 4), dtype=np.float32)
         self._check(lib().dem_get_contacts(self.ctx, _p(keys), _p(hist), cap, C.byref(n), _stream_ptr(stream)))
         n = int(n.value)
-        return keys[:n].copy(), hist[:n].copy()
+        return keys[:n], hist[:n]
 
     def set_contacts(self, keys, hist=None, stream=None):
         """hist: [n,4] (displacement xyz, age) or [n,3] (age 0)."""

@@ -46,6 +46,7 @@ struct dem_ctx {
     char *ws = nullptr;
     int64_t ws_bytes = 0, cap = 0;
     OwnerRec *rec = nullptr, *snap_rec = nullptr;
+    OwnerRec *fref_rec = nullptr;   // reference state of the learned-interval features
     double *q = nullptr, *snap_q = nullptr;
     OwnerAux *d_aux = nullptr;
     uint32_t *d_sph0 = nullptr;
@@ -157,6 +158,7 @@ void carve(Carver &c, dem_ctx *ctx, int64_t cap)
     int64_t No = ctx->No, Ns = ctx->Ns;
     ctx->rec = c.take<OwnerRec>(No);
     ctx->snap_rec = c.take<OwnerRec>(No);
+    ctx->fref_rec = c.take<OwnerRec>(No);
     ctx->q = c.take<double>(4 * No);
     ctx->snap_q = c.take<double>(4 * No);
     ctx->d_aux = c.take<OwnerAux>(No);
@@ -284,7 +286,9 @@ void drain_pair(dem_ctx *ctx, dem_ctx::TimedPair &p)
 // Opens a timed stage on stream s; returns the pair to close (or null).
 dem_ctx::TimedPair *stage_begin(dem_ctx *ctx, int kind, hipStream_t s)
 {
-    if (!ctx->P.timing) return nullptr;
+    if (ctx->P.timing <= 0) return nullptr;
+    // per-step stages are sampled every `timing` steps; detection stages always
+    if (kind <= 1 && (ctx->step % ctx->P.timing) != 0) return nullptr;
     if (ctx->ring.empty()) ctx->ring.resize(1024);
     dem_ctx::TimedPair &p = ctx->ring[ctx->ring_pos];
     ctx->ring_pos = (ctx->ring_pos + 1) % ctx->ring.size();
@@ -875,7 +879,11 @@ int64_t learned_interval(dem_ctx *ctx, hipStream_t s);
 
 static void issue_work_order(dem_ctx *ctx, hipStream_t dyn, hipStream_t kin, int64_t n)
 {
-    ctx->snap_step = n;
+    if (ctx->P.cd_mode == DEM_CD_LEARNED) {
+        // the learned interval measures the next features against this state
+        hipMemcpyAsync(ctx->fref_rec, ctx->rec, sizeof(OwnerRec) * ctx->No, hipMemcpyDeviceToDevice, dyn);
+        ctx->snap_step = n;
+    }
     hipMemcpyAsync(ctx->snap_rec, ctx->rec, sizeof(OwnerRec) * ctx->No, hipMemcpyDeviceToDevice, dyn);
     if (ctx->has_clumps)
         hipMemcpyAsync(ctx->snap_q, ctx->q, sizeof(double) * 4 * ctx->No, hipMemcpyDeviceToDevice, dyn);
@@ -947,7 +955,7 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
                 ctx->n_wo = 1;
                 ctx->interval_sum = 0.0;
                 if (P.cd_mode == DEM_CD_LEARNED) {
-                    hipMemcpyAsync(ctx->snap_rec, ctx->rec, sizeof(OwnerRec) * ctx->No, hipMemcpyDeviceToDevice, dyn);
+                    hipMemcpyAsync(ctx->fref_rec, ctx->rec, sizeof(OwnerRec) * ctx->No, hipMemcpyDeviceToDevice, dyn);
                     ctx->snap_step = n;
                 }
                 int64_t k = P.cd_mode == DEM_CD_LEARNED ? learned_interval(ctx, dyn) : P.cd_interval;
@@ -990,7 +998,7 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
                         k_next = -1;
                         ctx->last_wo = n;
                         if (P.cd_mode == DEM_CD_LEARNED) {
-                            hipMemcpyAsync(ctx->snap_rec, ctx->rec, sizeof(OwnerRec) * ctx->No,
+                            hipMemcpyAsync(ctx->fref_rec, ctx->rec, sizeof(OwnerRec) * ctx->No,
                                            hipMemcpyDeviceToDevice, dyn);
                             ctx->snap_step = n;
                         }
@@ -1101,7 +1109,7 @@ static void run_features(dem_ctx *ctx, hipStream_t s, float *out, uint32_t *cell
 {
     float tau = (float)(ctx->step - ctx->snap_step);
     float margin = (float)(ctx->P.margin > 0.0 ? ctx->P.margin : 1e-6);
-    feature_pipeline(ctx->rec, ctx->snap_rec, ctx->d_sph0, ctx->d_sph, ctx->org, ctx->fgrid, (float)ctx->P.dt,
+    feature_pipeline(ctx->rec, ctx->fref_rec, ctx->d_sph0, ctx->d_sph, ctx->org, ctx->fgrid, (float)ctx->P.dt,
                      margin, tau, ctx->d_fraw, ctx->d_fflag, ctx->d_fpos, ctx->cdD.partials, ctx->d_cellmap, out,
                      cell_ids, ctx->No, s);
 }
@@ -1124,8 +1132,10 @@ static int64_t analytic_interval(dem_ctx *ctx, double vmax)
 
 // Decides the next detection interval at a work order (LEARNED mode): the
 // MLP predicts, per cell, how many steps a set detected now stays complete;
-// the minimum over cells minus the adoption latency is the interval; the
-// analytic bound is the fallback and the floor.  Synchronises `s`.
+// the minimum over cells, scaled by the model's calibrated safety factor,
+// minus the adoption latency is the interval.  The analytic bound is the
+// fallback when no model is installed or its prediction is not finite.
+// Synchronises `s`.
 int64_t learned_interval(dem_ctx *ctx, hipStream_t s)
 {
     // top speed of the last integrated step
@@ -1147,10 +1157,10 @@ int64_t learned_interval(dem_ctx *ctx, hipStream_t s)
     hipMemcpyAsync(ctx->h_pred, ctx->d_pred + ctx->ncell_cap, 4, hipMemcpyDeviceToHost, s);
     hipStreamSynchronize(s);
     float R = ctx->h_pred[0];
-    if (!(R >= 0.0f) || ncell == 0) return k_an;
-    double kl = std::floor((double)R) - (double)ctx->P.cd_latency - 1.0;
+    if (!(R >= 0.0f) || !std::isfinite(R) || ncell == 0) return k_an;   // fallback
+    double safety = ctx->P.mlp_safety > 0.0 ? ctx->P.mlp_safety : 1.0;
+    double kl = std::floor(safety * (double)R) - (double)ctx->P.cd_latency - 1.0;
     int64_t k = kl < 1.0 ? 1 : (int64_t)std::min(kl, 1e9);
-    k = std::max(k, k_an);
     return std::min<int64_t>(k, ctx->P.cd_interval_max);
 }
 
@@ -1178,8 +1188,7 @@ dem_status dem_snapshot(dem_ctx *ctx, dem_stream stream)
         return DEM_ERR_STATE;
     }
     hipStream_t s = S(stream);
-    HIPCHK(hipMemcpyAsync(ctx->snap_rec, ctx->rec, sizeof(OwnerRec) * ctx->No, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(ctx->snap_q, ctx->q, sizeof(double) * 4 * ctx->No, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->fref_rec, ctx->rec, sizeof(OwnerRec) * ctx->No, hipMemcpyDeviceToDevice, s));
     ctx->snap_step = ctx->step;
     return DEM_OK;
 }

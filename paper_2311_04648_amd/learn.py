@@ -32,12 +32,13 @@ WINDOW_STARTS = (400, 1500, 3000, 5000, 8000, 12000, 17000, 23000, 30000, 38000)
 
 
 def generate_logs(dem, sysm, starts=WINDOW_STARTS, taus=(5, 10, 20, 40, 80, 160, 320), K=K_CAP, log=None):
-    """Returns (features float32 [n,6], targets float32 [n]) from one run."""
+    """Returns (features float32 [n,6], targets float32 [n], window index [n])
+    from one run."""
     torch = dem._torch()
     ctx = dem.DemContext(sysm, mode="fixed", k=4, lam=0, capacity=max(64, 10 * sysm.n_spheres))
     ctx.set_state()
     ncell = ctx.info()["ncells"]
-    feats, targets = [], []
+    feats, targets, wins = [], [], []
     step = 0
     for w, s in enumerate(starts):
         tau = taus[w % len(taus)]
@@ -57,11 +58,12 @@ def generate_logs(dem, sysm, starts=WINDOW_STARTS, taus=(5, 10, 20, 40, 80, 160,
         lab = np.minimum(first.cpu().numpy().astype(np.int64)[ids], K)
         feats.append(f.cpu().numpy())
         targets.append(np.log1p(lab.astype(np.float64)).astype(np.float32))
+        wins.append(np.full(ids.size, w, dtype=np.int32))
         if log:
             log(f"  window at {s}: tau {tau} cells {ids.size} labels min {lab.min()} "
                 f"censored {np.mean(lab >= K):.2f} mean {lab.mean():.1f}")
     ctx.close()
-    return np.concatenate(feats), np.concatenate(targets)
+    return np.concatenate(feats), np.concatenate(targets), np.concatenate(wins)
 
 
 def init_params(seed=0):
@@ -109,6 +111,27 @@ def train(dem, X, T, epochs=200, batch=4096, lr=3e-3, tau=0.05, seed=0, log=None
     return p.cpu().numpy(), hist
 
 
+def calibrate(dem, p, X, T, win, K=K_CAP, margin=0.9):
+    """Safety factor on the predicted horizon: the policy uses the minimum
+    prediction over cells, so per log window compare that minimum with the
+    true minimum label (windows whose minimum is censored bound nothing) and
+    keep the worst ratio, times `margin`, capped at 1."""
+    torch = dem._torch()
+    dev = torch.device("cuda:0")
+    y = dem.mlp_forward(torch.tensor(p, device=dev), torch.tensor(X, device=dev)).cpu().numpy()
+    R = np.expm1(y.astype(np.float64))
+    lab = np.expm1(T.astype(np.float64))
+    ratios = []
+    for w in np.unique(win):
+        sel = win == w
+        lmin = lab[sel].min()
+        if lmin >= K - 0.5:
+            continue
+        ratios.append(lmin / max(R[sel].min(), 1e-9))
+    worst = min(ratios) if ratios else 1.0
+    return float(min(1.0, margin * worst)), ratios
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default="gpurun_out/mlp_interval.json")
@@ -124,7 +147,8 @@ def main():
         print(msg, flush=True)
 
     t0 = time.time()
-    Xs, Ts, meta = [], [], []
+    Xs, Ts, Ws, meta = [], [], [], []
+    nwin = 0
     for seed in (1, 2, 3, 4):
         for name in ("config1", "config2"):
             if name == "config1":
@@ -133,21 +157,28 @@ def main():
                 nt = int(args.n2 * 0.9)
                 s = W.config2(seed=seed, n_tri=nt, n_penta=args.n2 - nt)
             log(f"logs {name} seed {seed}: {s.n_spheres} spheres")
-            X, T = generate_logs(dem, s, log=log)
+            X, T, Wn = generate_logs(dem, s, log=log)
             Xs.append(X)
             Ts.append(T)
+            Ws.append(Wn + nwin)
+            nwin += int(Wn.max()) + 1
             meta.append(dict(config=name, seed=seed, n_spheres=s.n_spheres, samples=int(X.shape[0])))
     X = np.concatenate(Xs)
     T = np.concatenate(Ts)
+    Wn = np.concatenate(Ws)
     log(f"{X.shape[0]} samples in {time.time() - t0:.1f}s; training")
     p, hist = train(dem, X, T, epochs=args.epochs, log=log)
+    safety, ratios = calibrate(dem, p, X, T, Wn)
+    log(f"safety factor {safety:.3f} (per-window min label / min prediction: "
+        f"{np.round(np.sort(ratios)[:8], 3).tolist()} ...)")
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     with open(args.out, "w") as f:
-        json.dump({"params": [float(x) for x in p], "loss_history": hist, "samples": int(X.shape[0]),
+        json.dump({"params": [float(x) for x in p], "safety": safety, "loss_history": hist,
+                   "samples": int(X.shape[0]),
                    "runs": meta, "tau": 0.05, "K": K_CAP,
                    "feature_mean": X.mean(0).tolist(), "feature_max": X.max(0).tolist(),
                    "target_mean": float(T.mean())}, f)
-    np.savez_compressed(os.path.splitext(args.out)[0] + "_logs.npz", X=X, T=T)
+    np.savez_compressed(os.path.splitext(args.out)[0] + "_logs.npz", X=X, T=T, W=Wn)
     log(f"saved {args.out} in {time.time() - t0:.1f}s")
 
 

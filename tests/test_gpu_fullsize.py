@@ -36,6 +36,8 @@ def _full(name):
         return W.config2(seed=0), 400
     if name == "config3":
         return W.config3(seed=7), 200
+    if name == "config4":
+        return W.config4(seed=0), 100
     raise ValueError(name)
 
 
@@ -44,12 +46,12 @@ def _sample_spheres(keys, Ns, rng, n):
     return np.sort(rng.choice(i, size=min(n, i.size), replace=False))
 
 
-@pytest.mark.parametrize("name", ["config1", "config2", "config3"])
+@pytest.mark.parametrize("name", ["config1", "config2", "config3", "config4"])
 def test_full_size_sampled_parity(dem, name):
     import torch
     s, presteps = _full(name)
     print(f"{name}: {s.n_spheres} spheres, {s.n_owners} owners", flush=True)
-    ctx = dem.DemContext(s, mode="fixed", k=10, lam=5, capacity=8 * s.n_spheres)
+    ctx = dem.DemContext(s, mode="fixed", k=10, lam=5, capacity=(4 if name == "config4" else 8) * s.n_spheres)
     ctx.set_state()
     dyn, kin = torch.cuda.Stream(), torch.cuda.Stream()
     ctx.step(presteps, dyn=dyn, kin=kin)
@@ -59,9 +61,10 @@ def test_full_size_sampled_parity(dem, name):
     st = {"X": g["X"], "q": g["q"], "V": g["V"].astype(np.float64), "W": g["W"].astype(np.float64)}
     o = oracle.Oracle(s)
     rng = np.random.default_rng(1)
-    sample = _sample_spheres(keys, s.n_spheres, rng, 60)
+    nrow = 24 if name == "config4" else 60
+    sample = _sample_spheres(keys, s.n_spheres, rng, nrow)
     # also a few spheres with no contact
-    sample = np.unique(np.r_[sample, rng.choice(s.n_spheres, 20, replace=False)])
+    sample = np.unique(np.r_[sample, rng.choice(s.n_spheres, 8, replace=False)])
     rows = o.detect_rows(st, s.margin, sample, step=g["step"])
     ki = (keys >> np.uint64(32)).astype(np.int64)
     for i, row in zip(sample, rows):

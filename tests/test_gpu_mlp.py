@@ -139,10 +139,12 @@ def test_learned_interval_beats_fixed_with_zero_misses(dem):
     """Held-out workload (granular column, seed 7, reduced size): the learned
     schedule runs fewer detections than the fixed k = 10 schedule, misses no
     contact (judged), and its trajectory equals every-step detection."""
-    params = np.array(json.load(open(MODEL))["params"], dtype=np.float32)
+    md = json.load(open(MODEL))
+    params = np.array(md["params"], dtype=np.float32)
     s = W.config3(seed=7, n=20_000)
     steps = 1500
-    learned = dem.DemContext(s, mode="learned", k=10, lam=2, judge=True, k_max=256)
+    learned = dem.DemContext(s, mode="learned", k=10, lam=2, judge=True, k_max=1024,
+                             mlp_safety=md.get("safety", 1.0))
     learned.mlp_set(params)
     learned.set_state()
     ls = learned.step(steps)
