@@ -138,6 +138,10 @@ typedef struct {
     int32_t timing;         /* n > 0: time kernel stages with HIP events (stats->stage_ms);
                                force and fold stages are sampled every n-th step */
     double mlp_safety;      /* LEARNED: factor on the predicted horizon (0 = 1) */
+    int32_t bin_sort;       /* sort of (bin, sphere id): 0 one pass over the bin histogram
+                               (default), 1 stable LSD radix sort with 8-bit digits;
+                               both give the same order */
+    int32_t pad0;
 } dem_params;
 
 /* Statistics of a dem_step call (Sec. 2.1, thread collaboration stats). */
@@ -156,9 +160,11 @@ typedef struct {
     /* with params.timing: summed device time and launch count per stage,
      * measured with HIP events on the stream the stage runs on:
      * [0] force kernel, [1] fold + integrate kernel, [2] contact detection
-     * (bin, sort, detect, B lists), [3] history remap */
-    double stage_ms[4];
-    int64_t stage_n[4];
+     * (bin, sort, detect, B lists), [3] history remap, [4] an empty
+     * one-wave kernel bracketed the same way as [0] and [1] (the fixed
+     * overhead of the event markers, to subtract from single-kernel times) */
+    double stage_ms[5];
+    int64_t stage_n[5];
     double mean_contacts;   /* mean size of the active set over the steps */
 } dem_step_stats;
 

@@ -35,7 +35,8 @@ class Params(C.Structure):
                 ("v_error_out", C.c_double), ("domain_lo", C.c_double * 3), ("domain_hi", C.c_double * 3),
                 ("cd_mode", C.c_int32), ("cd_interval", C.c_int32), ("cd_latency", C.c_int32),
                 ("judge", C.c_int32), ("repair", C.c_int32), ("cd_interval_max", C.c_int32),
-                ("timing", C.c_int32), ("mlp_safety", C.c_double)]
+                ("timing", C.c_int32), ("mlp_safety", C.c_double), ("bin_sort", C.c_int32),
+                ("pad0", C.c_int32)]
 
 
 class Materials(C.Structure):
@@ -62,7 +63,7 @@ class StepStats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("step", C.c_int64), ("cds", C.c_int64), ("swaps", C.c_int64),
                 ("misses", C.c_int64), ("repairs", C.c_int64), ("n_contacts", C.c_int64),
                 ("required_capacity", C.c_int64), ("max_speed", C.c_double), ("ms", C.c_double),
-                ("mean_interval", C.c_double), ("stage_ms", C.c_double * 4), ("stage_n", C.c_int64 * 4),
+                ("mean_interval", C.c_double), ("stage_ms", C.c_double * 5), ("stage_n", C.c_int64 * 5),
                 ("mean_contacts", C.c_double)]
 
     def as_dict(self):
@@ -147,7 +148,8 @@ class DemContext:
     """One DEM problem bound to caller-owned device memory (a torch tensor)."""
 
     def __init__(self, system, mode="every", k=10, lam=5, judge=False, repair=True, capacity=None,
-                 margin=None, v_error_out=0.0, k_max=None, device="cuda:0", timing=False, mlp_safety=1.0):
+                 margin=None, v_error_out=0.0, k_max=None, device="cuda:0", timing=False, mlp_safety=1.0,
+                 bin_sort=0):
         torch = _torch()
         self.torch = torch
         self.device = torch.device(device)
@@ -177,6 +179,7 @@ class DemContext:
         P.cd_interval_max = int(k_max or 16 * max(int(k), 1))
         P.timing = int(timing) if not isinstance(timing, bool) else int(timing)
         P.mlp_safety = float(mlp_safety)
+        P.bin_sort = int(bin_sort)
         self.params = P
         Mt = Materials(int(np.asarray(s.mat_E).shape[0]), keep(s.mat_E, np.float64), keep(s.mat_nu, np.float64),
                        keep(s.mat_cor, np.float64), keep(s.mat_mu, np.float64), keep(s.mat_crr, np.float64))

@@ -89,8 +89,8 @@ struct dem_ctx {
     };
     std::vector<TimedPair> ring;
     size_t ring_pos = 0;
-    double stage_ms[4] = {0, 0, 0, 0};
-    int64_t stage_n[4] = {0, 0, 0, 0};
+    double stage_ms[5] = {0, 0, 0, 0, 0};
+    int64_t stage_n[5] = {0, 0, 0, 0, 0};
 };
 
 #define HIPCHK(expr)                                                                   \
@@ -151,6 +151,7 @@ void carve_cd(Carver &c, const dem_ctx *ctx, CdWork &w)
     w.hist = c.take<uint32_t>(radix_hist_elems(ns));
     w.partials = c.take<uint32_t>(partial_elems(ctx));
     w.sort_bits = ctx->sort_bits;
+    w.sort_mode = ctx->P.bin_sort;
 }
 
 void carve(Carver &c, dem_ctx *ctx, int64_t cap)
@@ -284,22 +285,32 @@ void drain_pair(dem_ctx *ctx, dem_ctx::TimedPair &p)
 }
 
 // Opens a timed stage on stream s; returns the pair to close (or null).
-dem_ctx::TimedPair *stage_begin(dem_ctx *ctx, int kind, hipStream_t s)
+// A free event pair for a timed stage (or null when not timing).  Per-step
+// kernels are sampled every `timing` steps; detection chains always.
+dem_ctx::TimedPair *stage_slot(dem_ctx *ctx, int kind)
 {
     if (ctx->P.timing <= 0) return nullptr;
-    // per-step stages are sampled every `timing` steps; detection stages always
-    if (kind <= 1 && (ctx->step % ctx->P.timing) != 0) return nullptr;
+    if ((kind <= 1 || kind == 4) && (ctx->step % ctx->P.timing) != 0) return nullptr;
     if (ctx->ring.empty()) ctx->ring.resize(1024);
     dem_ctx::TimedPair &p = ctx->ring[ctx->ring_pos];
     ctx->ring_pos = (ctx->ring_pos + 1) % ctx->ring.size();
     drain_pair(ctx, p);
     if (!p.a) {
+        // no system-scope release at the stamps: they must not add a cache
+        // write-back to the kernel they bracket
         hipEventCreateWithFlags(&p.a, hipEventDisableSystemFence);
         hipEventCreateWithFlags(&p.b, hipEventDisableSystemFence);
     }
     p.kind = kind;
-    hipEventRecord(p.a, s);
     return &p;
+}
+
+// Opens a timed chain of kernels on stream s (events recorded around it).
+dem_ctx::TimedPair *stage_begin(dem_ctx *ctx, int kind, hipStream_t s)
+{
+    dem_ctx::TimedPair *p = stage_slot(ctx, kind);
+    if (p) hipEventRecord(p->a, s);
+    return p;
 }
 
 void stage_end(dem_ctx::TimedPair *p, hipStream_t s)
@@ -918,7 +929,7 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
     const int64_t step0 = ctx->step;
     dem_status result = DEM_OK;
     drain_all(ctx);
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 5; ++k) {
         ctx->stage_ms[k] = 0.0;
         ctx->stage_n[k] = 0;
     }
@@ -1021,12 +1032,19 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
             }
         }
         DynArgs a = dyn_args(ctx, n);
+        // single kernels are bracketed by marker events, which wait for the
+        // previous work on the stream; an empty kernel bracketed the same way
+        // measures the markers' own overhead
         auto *tf = stage_begin(ctx, 0, dyn);
         launch_force(a, ctx->acs[ctx->cur], ctx->sb, ctx->ctr, dyn);
         stage_end(tf, dyn);
         auto *ti = stage_begin(ctx, 1, dyn);
         launch_fold_integrate(a, ctx->acs[ctx->cur], ctx->sb, ctx->ctr, 1, dyn);
         stage_end(ti, dyn);
+        if (auto *tn = stage_begin(ctx, 4, dyn)) {
+            launch_noop(dyn, nullptr, nullptr);
+            stage_end(tn, dyn);
+        }
         ctx->step = n + 1;
     }
     {
@@ -1066,7 +1084,7 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
         stats->mean_interval = ctx->n_wo > 1 ? ctx->interval_sum / (double)(ctx->n_wo - 1)
                                              : (double)(P.cd_mode == DEM_CD_EVERY ? 1 : P.cd_interval);
         drain_all(ctx);
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 5; ++k) {
             stats->stage_ms[k] = ctx->stage_ms[k];
             stats->stage_n[k] = ctx->stage_n[k];
         }

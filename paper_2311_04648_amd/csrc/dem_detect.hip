@@ -70,6 +70,38 @@ __global__ void __launch_bounds__(TPB) k_cd_prepare(DetectArgs a, uint32_t *keys
     atomicAdd(&cell_count[key], 1u);
 }
 
+// One-pass sort of (bin key, sphere id): the per-bin counts and their scan
+// (the cell ranges) are the histogram and offsets of a single radix digit
+// as wide as the key; each sphere claims a slot of its bin with an atomic
+// cursor, and each bin then orders its few ids ascending, so the result is
+// identical to a stable sort.
+__global__ void __launch_bounds__(TPB) k_bucket_scatter(const uint32_t *keys_in, int64_t n, uint32_t *cursor,
+                                                        uint32_t *keys_out, uint32_t *vals_out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t k = keys_in[i];
+    uint32_t pos = atomicAdd(&cursor[k], 1u);
+    keys_out[pos] = k;
+    vals_out[pos] = (uint32_t)i;
+}
+
+__global__ void __launch_bounds__(TPB) k_bucket_order(const uint32_t *cell_start, int64_t nbins, uint32_t *vals)
+{
+    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbins) return;
+    uint32_t b0 = cell_start[b], b1 = cell_start[b + 1];
+    for (uint32_t t = b0 + 1; t < b1; ++t) {
+        uint32_t v = vals[t];
+        uint32_t u = t;
+        while (u > b0 && vals[u - 1] > v) {
+            vals[u] = vals[u - 1];
+            --u;
+        }
+        vals[u] = v;
+    }
+}
+
 __global__ void __launch_bounds__(TPB) k_cand_gather(const uint32_t *vals, const Cand *cand_tmp,
                                                      Cand *cand, int64_t n)
 {
@@ -124,7 +156,7 @@ __global__ void __launch_bounds__(TPB) k_detect(DetectArgs a, const uint32_t *ke
                                                 uint32_t *miss, const uint32_t *cellmap = nullptr,
                                                 uint32_t *first_miss = nullptr, uint32_t tval = 0)
 {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (p >= a.n_spheres) return;
     const Cand ci = cand[p];
     const uint32_t i = ci.id;
@@ -210,7 +242,7 @@ __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32
                                                       const uint32_t *cell_start, uint32_t *count,
                                                       uint32_t *stage, uint32_t *bcount)
 {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (p >= a.n_spheres) return;
     const Cand ci = cand[p];
     const uint32_t i = ci.id;
@@ -287,7 +319,7 @@ __global__ void __launch_bounds__(TPB) k_detect_overflow(DetectArgs a, const uin
                                                          uint32_t *out_j, int64_t cap, uint32_t *bcur,
                                                          uint32_t *bidx)
 {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (p >= a.n_spheres) return;
     const uint32_t i = cand[p].id;
     if ((int64_t)start[a.n_spheres] > cap) return;
@@ -429,11 +461,22 @@ __global__ void __launch_bounds__(TPB) k_remap(const uint32_t *os, const uint32_
 void launch_bin(const DetectArgs &a, CdWork &w, hipStream_t s)
 {
     int64_t n = a.n_spheres;
-    launch_fill_u32(w.cell_count, (int64_t)a.grid.nbins, 0u, s);
+    const int64_t nb = (int64_t)a.grid.nbins;
+    launch_fill_u32(w.cell_count, nb, 0u, s);
     hipLaunchKernelGGL(k_cd_prepare, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.vals, w.cand_tmp,
                        w.cell_count);
-    scan_exclusive_u32(w.cell_count, w.cell_start, (int64_t)a.grid.nbins, w.partials, s);
-    radix_sort_u32(&w.keys, &w.vals, &w.keys_alt, &w.vals_alt, n, w.sort_bits, w.hist, w.partials, s);
+    if (w.sort_mode == 0) {
+        // cell ranges, with a copy of the offsets as the per-bin cursor
+        scan_exclusive_u32(w.cell_count, w.cell_start, nb, w.partials, s, w.cell_count);
+        hipLaunchKernelGGL(k_bucket_scatter, dim3(nblocks(n)), dim3(TPB), 0, s, w.keys, n, w.cell_count,
+                           w.keys_alt, w.vals_alt);
+        hipLaunchKernelGGL(k_bucket_order, dim3(nblocks(nb)), dim3(TPB), 0, s, w.cell_start, nb, w.vals_alt);
+        uint32_t *t = w.keys; w.keys = w.keys_alt; w.keys_alt = t;
+        t = w.vals; w.vals = w.vals_alt; w.vals_alt = t;
+    } else {
+        scan_exclusive_u32(w.cell_count, w.cell_start, nb, w.partials, s);
+        radix_sort_u32(&w.keys, &w.vals, &w.keys_alt, &w.vals_alt, n, w.sort_bits, w.hist, w.partials, s);
+    }
     hipLaunchKernelGGL(k_cand_gather, dim3(nblocks(n)), dim3(TPB), 0, s, w.vals, w.cand_tmp, w.cand, n);
 }
 

@@ -77,6 +77,16 @@ __host__ __device__ inline void rot_apply(const Mat3d &R, double px, double py, 
     o[2] = (R.m[6] * px + R.m[7] * py) + R.m[8] * pz;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  This maps the dispatch index to a logical block so that every XCD
+// works on one contiguous range of blocks: neighbouring spheres (which share
+// neighbour rows and partner records) then meet in the same L2.
+__device__ inline uint32_t xcd_block(uint32_t b, uint32_t n)
+{
+    const uint32_t per = n >> 3, rem = n & 7u, x = b & 7u, k = b >> 3;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
 __device__ inline float3 f3(float x, float y, float z) { return make_float3(x, y, z); }
 __device__ inline float3 operator+(float3 a, float3 b) { return f3(a.x + b.x, a.y + b.y, a.z + b.z); }
 __device__ inline float3 operator-(float3 a, float3 b) { return f3(a.x - b.x, a.y - b.y, a.z - b.z); }

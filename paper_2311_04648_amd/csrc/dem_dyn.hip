@@ -22,6 +22,8 @@
 // orientation has no physical effect).
 #include "dem_device.h"
 
+#include <hip/hip_ext.h>
+
 namespace {
 
 constexpr int TPB = 256;
@@ -76,7 +78,7 @@ __global__ void __launch_bounds__(TPB) k_force(DynArgs a, const uint32_t *start,
                                                float *hx, float *hy, float *hz, float *hw, float *aF, float *aT,
                                                float *bF, float *bT, int64_t cap, const DevCounters *ctr)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= a.n_spheres) return;
     if (stopped(ctr, a.step)) return;
     const int64_t Ns = a.n_spheres, No = a.n_owners;
@@ -387,20 +389,31 @@ __global__ void __launch_bounds__(256) k_reduce_max(const float *blkmax, int64_t
     if (threadIdx.x == 0) ctr->maxv2[0] = __float_as_uint(fmaxf(fmaxf(w[0], w[1]), fmaxf(w[2], w[3])));
 }
 
+__global__ void __launch_bounds__(64) k_noop() {}
+
+void launch_noop(hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+{
+    hipExtLaunchKernelGGL(k_noop, dim3(1), dim3(64), 0, s, ev0, ev1, 0);
+}
+
 void launch_reduce_max(const DynArgs &a, DevCounters *ctr, hipStream_t s)
 {
     hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(256), 0, s, a.blkmax, (int64_t)nblocks(a.n_owners), ctr);
 }
 
-void launch_force(const DynArgs &a, AcsBuf &cur, StepBufs &sb, DevCounters *ctr, hipStream_t s)
+void launch_force(const DynArgs &a, AcsBuf &cur, StepBufs &sb, DevCounters *ctr, hipStream_t s,
+                  hipEvent_t ev0, hipEvent_t ev1)
 {
-    hipLaunchKernelGGL(k_force, dim3(nblocks(a.n_spheres)), dim3(TPB), 0, s, a, cur.start, cur.j, cur.hx,
-                       cur.hy, cur.hz, cur.hw, sb.aF, sb.aT, sb.bF, sb.bT, sb.cap, ctr);
+    hipExtLaunchKernelGGL(k_force, dim3(nblocks(a.n_spheres)), dim3(TPB), 0, s, ev0, ev1, 0, a, cur.start,
+                          (const uint32_t *)cur.j, cur.hx, cur.hy, cur.hz, cur.hw, sb.aF, sb.aT, sb.bF, sb.bT,
+                          sb.cap, (const DevCounters *)ctr);
 }
 
 void launch_fold_integrate(const DynArgs &a, const AcsBuf &cur, StepBufs &sb, DevCounters *ctr,
-                           int integrate, hipStream_t s)
+                           int integrate, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
-    hipLaunchKernelGGL(k_fold_integrate, dim3(nblocks(a.n_owners)), dim3(TPB), 0, s, a, cur.start, cur.bstart,
-                       cur.bidx, sb.aF, sb.aT, sb.bF, sb.bT, sb.cap, sb.Fo, sb.To, integrate, ctr);
+    hipExtLaunchKernelGGL(k_fold_integrate, dim3(nblocks(a.n_owners)), dim3(TPB), 0, s, ev0, ev1, 0, a,
+                          (const uint32_t *)cur.start, (const uint32_t *)cur.bstart, (const uint32_t *)cur.bidx,
+                          (const float *)sb.aF, (const float *)sb.aT, (const float *)sb.bF, (const float *)sb.bT,
+                          sb.cap, sb.Fo, sb.To, integrate, ctr);
 }

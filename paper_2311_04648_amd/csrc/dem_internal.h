@@ -138,6 +138,7 @@ struct CdWork {
     uint32_t *stage;       // [16 Ns] staged partners of the single-traversal detection
     uint32_t *hist, *partials;
     int sort_bits;
+    int sort_mode;         // 0: one-pass bin sort, 1: 8-bit LSD radix passes
 };
 
 struct AcsBuf {
@@ -190,9 +191,13 @@ struct StepBufs {
     int64_t cap;
 };
 
-void launch_force(const DynArgs &a, AcsBuf &cur, StepBufs &sb, DevCounters *ctr, hipStream_t s);
+// ev0/ev1 (may be null): events stamped by the dispatch itself around the kernel
+void launch_force(const DynArgs &a, AcsBuf &cur, StepBufs &sb, DevCounters *ctr, hipStream_t s,
+                  hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_fold_integrate(const DynArgs &a, const AcsBuf &cur, StepBufs &sb, DevCounters *ctr,
-                           int integrate, hipStream_t s);
+                           int integrate, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// an empty one-wave kernel stamped with events (overhead of the stamps)
+void launch_noop(hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 // max |v|^2 of the last integration into ctr->maxv2[0]
 void launch_reduce_max(const DynArgs &a, DevCounters *ctr, hipStream_t s);
 

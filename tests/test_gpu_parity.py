@@ -104,15 +104,25 @@ def test_state_roundtrip_exact(dem, name):
 
 
 @pytest.mark.parametrize("name", list(SYS))
-def test_binning_sort_is_stable_permutation(dem, name):
+@pytest.mark.parametrize("bin_sort", [0, 1])
+def test_binning_sort_is_stable_permutation(dem, name, bin_sort):
     s = SYS[name]
-    ctx = dem.DemContext(s, mode="every")
+    ctx = dem.DemContext(s, mode="every", bin_sort=bin_sort)
     ctx.set_state()
     keys, ids = ctx.bin()
     assert np.all(np.diff(keys.astype(np.int64)) >= 0)
     assert np.array_equal(np.sort(ids), np.arange(s.n_spheres))
     same = np.diff(keys.astype(np.int64)) == 0
     assert np.all(np.diff(ids.astype(np.int64))[same] > 0)
+    # the one-pass bin sort and the LSD radix sort give the same order,
+    # equal to numpy's stable argsort of the keys
+    other = dem.DemContext(s, mode="every", bin_sort=1 - bin_sort)
+    other.set_state()
+    k2, i2 = other.bin()
+    np.testing.assert_array_equal(keys, k2)
+    np.testing.assert_array_equal(ids, i2)
+    order = np.argsort(keys[np.argsort(ids)], kind="stable")
+    np.testing.assert_array_equal(ids, order.astype(np.uint32))
 
 
 @pytest.mark.parametrize("name", list(SYS))
