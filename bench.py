@@ -29,13 +29,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-STAGES = ["k_force", "k_fold_integrate", "detect", "k_remap"]
+STAGES = ["k_force", "k_fold_integrate", "detect", "k_remap"]   # two-kernel dynamics
+STAGES_FUSED = ["k_force", "k_step_fused", "detect", "k_remap"]  # fused dynamics (default)
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=1_000_000, help="spheres of the config-1 workload")
     ap.add_argument("--workload", default="config1",
@@ -48,22 +49,33 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=50)
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--lam", type=int, default=5)
+    ap.add_argument("--dyn-path", type=int, default=0,
+                    help="dynamics: 0 one fused kernel per step, 1 force kernel + fold/integrate kernel")
+    ap.add_argument("--timing", type=int, default=32,
+                    help="time the dynamics kernel with HIP events every n-th step")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     return ap.parse_args()
 
 
-def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes):
+def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, rolling=False):
     """Bytes one launch of a stage must move at minimum (unique data);
     `active` = spheres that appear in at least one contact:
     k_force: per sphere its row offset (4); per active sphere its record
       (16), its owner's record (48) and its A-side sums written (24); per
       contact the partner id (4), history read + write (24) and the B-side
       reaction written (24).
-    k_fold_integrate: per owner the record read + write (96), inverse inertia
-      and template (16) and sphere range (4); per sphere the row and B-list
-      offsets (8); per active sphere the A-side sums (24); per contact the
-      B-list entry (4) and the reaction (24).
+    k_step_fused: per owner the record read + write (96) and the inverse
+      inertia (4 for single-sphere systems; else 16, the sphere range 4 and
+      the quaternion read + written 64); per sphere the row and B-list
+      offsets (8); per active sphere its record (16); per contact the partner
+      id (4), the history read + written (24, 32 with contact age) and the
+      B-list entry with its source sphere (8).
+    k_fold_integrate: per owner the record read + write (96) and the inverse
+      inertia: one isotropic value (4) when every owner is a single sphere,
+      else three values and the template (16) plus the sphere range (4); per
+      sphere the row and B-list offsets (8); per active sphere the A-side sums
+      (24); per contact the B-list entry (4) and the reaction (24).
     detect: per sphere record + owner record (64), key/id (8) and candidate
       (32) written, radix passes (16 each), candidate gather (36 r + 32 w),
       one traversal reading 32 B of candidates per neighbour-row hit, row
@@ -73,8 +85,10 @@ def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes):
       (4), history read (12) and written (12)."""
     if stage == "k_force":
         return Ns * 4 + active * 88 + C * 52
+    if stage == "k_step_fused":
+        return No * (180 if clumps else 100) + Ns * 8 + active * 16 + C * (44 if rolling else 36)
     if stage == "k_fold_integrate":
-        return No * 116 + Ns * 8 + active * 24 + C * 28
+        return No * (116 if clumps else 100) + Ns * 8 + active * 24 + C * 28
     if stage == "detect":
         return Ns * (64 + 8 + 32 + 16 * passes + 68 + 32 + 8 + 16) + C * 24 + nbins * 12
     if stage == "k_remap":
@@ -113,8 +127,9 @@ def load_traffic(kernel):
 
 def make_ctx(dem, sysm, mode, args, mlp, judge):
     lib_mode = "learned" if mode == "analytic" else mode
-    ctx = dem.DemContext(sysm, mode=lib_mode, k=args.k, lam=args.lam, judge=judge, timing=0 if judge else 4,
-                         capacity=max(64, 8 * sysm.n_spheres), k_max=1024, mlp_safety=args.mlp_safety)
+    ctx = dem.DemContext(sysm, mode=lib_mode, k=args.k, lam=args.lam, judge=judge,
+                         timing=0 if judge else args.timing, capacity=max(64, 8 * sysm.n_spheres), k_max=1024,
+                         mlp_safety=args.mlp_safety, dyn_path=args.dyn_path)
     if mode == "learned":
         ctx.mlp_set(mlp)
     return ctx
@@ -217,7 +232,9 @@ def main():
     r = results[head]
     st = r["stats"]
     value = Ns * args.steps / r["seconds"]
-    # dominant single kernel of the headline run (force or fold/integrate),
+    stages = STAGES_FUSED if args.dyn_path == 0 else STAGES
+    # dominant single kernel of the headline run (the fused step, or force or
+    # fold/integrate on the two-kernel path),
     # (stage 4 is the stamp-overhead probe, not a stage of the path)
     # timed live with HIP events on its stream; the detection chain (about 20
     # kernels on the second stream) is reported separately
@@ -225,21 +242,24 @@ def main():
     dom = 0 if tot[0] >= tot[1] else 1
     n_launch = max(int(st["stage_n"][dom]), 1)
     avg_raw = tot[dom] / n_launch
-    # the event markers add a fixed overhead, measured live on the same stream
-    # with an empty one-wave kernel bracketed the same way
+    # every event pair around the dynamics kernel(s) is followed by an empty
+    # one-wave kernel bracketed the same way: its interval is the markers'
+    # own overhead, paid once per pair (the fused kernel is timed in runs of
+    # up to 8 back-to-back launches per pair)
     n_noop = max(int(st["stage_n"][4]), 1)
     stamp_ms = tot[4] / n_noop
-    avg_ms = max(avg_raw - stamp_ms, 1e-6)
+    avg_ms = max((tot[dom] - tot[4]) / n_launch, 1e-6)
     C = st["mean_contacts"]
     passes = 1   # one-pass bin sort (the LSD radix option would take (sort_bits + 7) // 8)
-    algo = algorithmic_bytes(STAGES[dom], Ns, No, C, r["active"], r["info"]["nbins"], passes)
+    algo = algorithmic_bytes(stages[dom], Ns, No, C, r["active"], r["info"]["nbins"], passes,
+                             clumps=Ns != No, rolling=bool(np.any(np.asarray(sysm.mat_crr) > 0)))
     achieved = algo / (avg_ms * 1e-3) / 1e9
-    traffic = load_traffic(STAGES[dom])
-    roofline = {"bound": "hbm", "kernel": STAGES[dom], "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+    traffic = load_traffic(stages[dom])
+    roofline = {"bound": "hbm", "kernel": stages[dom], "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes_per_launch": int(algo), "avg_launch_ms": round(avg_ms, 5),
-                "event_interval_ms": round(avg_raw, 5), "event_stamp_overhead_ms": round(stamp_ms, 5),
-                "launches": n_launch}
+                "event_interval_per_launch_ms": round(avg_raw, 5), "event_pair_overhead_ms": round(stamp_ms, 5),
+                "event_pairs": int(st["stage_n"][4]), "launches": n_launch}
     n_cd = max(int(st["stage_n"][2]), 1)
     cd_ms = tot[2] / n_cd
     cd_bytes = algorithmic_bytes("detect", Ns, No, C, r["active"], r["info"]["nbins"], passes)
@@ -261,11 +281,48 @@ def main():
                          f"(k={args.k}) from the initial state, single-threaded FP64 C oracle, {dt:.1f} s"}
         print(f"# cpu oracle: {cpu['value']:.4g} sphere-steps/s in {dt:.1f}s", file=sys.stderr, flush=True)
 
+    # measured streaming bandwidth of a plain device copy (2 x 1 GiB moved per copy)
+    nb = 1 << 28
+    src = torch.ones(nb, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(10):
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    copy_gbs = 2 * 4 * nb / (sorted(times)[len(times) // 2] * 1e-3) / 1e9
+    del src, dst
+    roofline["measured_copy_GBs"] = round(copy_gbs, 1)
+    roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    rolling = bool(np.any(np.asarray(sysm.mat_crr) > 0))
+
+    def path_bytes_per_step(rr):
+        # algorithmic bytes of one step of the whole path: the dynamics
+        # kernel(s) every step, detection and remap once per detection
+        s2 = rr["stats"]
+        Cm, act = s2["mean_contacts"], rr["active"]
+        if args.dyn_path == 0:
+            dyn_b = algorithmic_bytes("k_step_fused", Ns, No, Cm, act, 0, passes, clumps=Ns != No, rolling=rolling)
+        else:
+            dyn_b = (algorithmic_bytes("k_force", Ns, No, Cm, act, 0, passes)
+                     + algorithmic_bytes("k_fold_integrate", Ns, No, Cm, act, 0, passes, clumps=Ns != No))
+        per_cd = (algorithmic_bytes("detect", Ns, No, Cm, act, rr["info"]["nbins"], passes)
+                  + algorithmic_bytes("k_remap", Ns, No, Cm, act, 0, passes))
+        return dyn_b + per_cd * s2["cds"] / args.steps
+
     modes_out = {}
     for mode, rr in results.items():
         s2 = rr["stats"]
+        bps = path_bytes_per_step(rr)
+        gbs = bps / (rr["seconds"] / args.steps) / 1e9
         modes_out[mode] = {"value": round(Ns * args.steps / rr["seconds"], 1),
                            "ms_per_step": round(1e3 * rr["seconds"] / args.steps, 5),
+                           "algorithmic_bytes_per_step": int(bps), "achieved_GBs": round(gbs, 1),
+                           "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "copy_frac": round(gbs / copy_gbs, 4),
                            "cds": int(s2["cds"]), "mean_interval": round(s2["mean_interval"], 2),
                            "mean_contacts": round(s2["mean_contacts"], 1),
                            "missed_contacts": misses.get(mode),
@@ -288,7 +345,8 @@ def main():
                                 f"in a 0.6x0.6x1.2 m box, dt 5e-6 s, margin 0.2 mm, delayed CD every {args.k} "
                                 f"steps on a second HIP stream (adoption latency {args.lam})")
                    if args.workload == "config1" else f"{args.workload}: {Ns} spheres, {No} owners",
-                   "n_spheres": Ns, "n_owners": No, "schedule": head, "k": args.k, "lambda": args.lam},
+                   "n_spheres": Ns, "n_owners": No, "schedule": head, "k": args.k, "lambda": args.lam,
+                   "dynamics": "one fused kernel per step" if args.dyn_path == 0 else "force + fold kernels"},
         "modes": modes_out,
         "missed_contacts": misses.get(head),
         "roofline": roofline,

@@ -136,12 +136,17 @@ typedef struct {
     int32_t repair;         /* 1: a missed contact discards the stale set (default) */
     int32_t cd_interval_max;/* LEARNED: upper bound on the interval */
     int32_t timing;         /* n > 0: time kernel stages with HIP events (stats->stage_ms);
-                               force and fold stages are sampled every n-th step */
+                               the dynamics kernels are sampled every n-th step */
     double mlp_safety;      /* LEARNED: factor on the predicted horizon (0 = 1) */
     int32_t bin_sort;       /* sort of (bin, sphere id): 0 one pass over the bin histogram
                                (default), 1 stable LSD radix sort with 8-bit digits;
                                both give the same order */
-    int32_t pad0;
+    int32_t dyn_path;       /* dem_step's dynamics: 0 one fused kernel per step (default:
+                               each owner evaluates its A-row contacts and re-evaluates
+                               its B-side contacts with the same function, then
+                               integrates; state and history are double-buffered),
+                               1 two kernels (forces with per-contact reactions, then
+                               the ordered fold and integration); both give the same bits */
 } dem_params;
 
 /* Statistics of a dem_step call (Sec. 2.1, thread collaboration stats). */
@@ -159,10 +164,14 @@ typedef struct {
     double mean_interval;   /* mean steps between work orders */
     /* with params.timing: summed device time and launch count per stage,
      * measured with HIP events on the stream the stage runs on:
-     * [0] force kernel, [1] fold + integrate kernel, [2] contact detection
-     * (bin, sort, detect, B lists), [3] history remap, [4] an empty
-     * one-wave kernel bracketed the same way as [0] and [1] (the fixed
-     * overhead of the event markers, to subtract from single-kernel times) */
+     * [0] force kernel and [1] fold + integrate kernel of the two-kernel
+     * dynamics (one event pair per kernel, every `timing`-th step), or [1]
+     * the fused step kernel (runs of up to 8 back-to-back launches between
+     * one event pair, a run opened every `timing`-th step on steps with no
+     * other dynamics-stream work); [2] contact detection (bin, sort,
+     * detect, B lists); [3] history remap; [4] an empty one-wave kernel
+     * bracketed like [0]/[1] (one per event pair of [0]/[1]: the markers'
+     * own overhead, so stage_ms[1] - stage_ms[4] is kernel time) */
     double stage_ms[5];
     int64_t stage_n[5];
     double mean_contacts;   /* mean size of the active set over the steps */

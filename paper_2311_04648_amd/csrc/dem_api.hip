@@ -45,10 +45,13 @@ struct dem_ctx {
     bool bound = false;
     char *ws = nullptr;
     int64_t ws_bytes = 0, cap = 0;
-    OwnerRec *rec = nullptr, *snap_rec = nullptr;
+    OwnerRec *rec = nullptr;
+    OwnerRec *rec_alt = nullptr;    // the fused step writes here, then the two swap
+    double *q_alt = nullptr;
     OwnerRec *fref_rec = nullptr;   // reference state of the learned-interval features
-    double *q = nullptr, *snap_q = nullptr;
+    double *q = nullptr;
     OwnerAux *d_aux = nullptr;
+    float *d_inv_i = nullptr;
     uint32_t *d_sph0 = nullptr;
     SphRec *d_sph = nullptr;
     float *d_tpos = nullptr;
@@ -86,7 +89,10 @@ struct dem_ctx {
     struct TimedPair {
         hipEvent_t a = nullptr, b = nullptr;
         int kind = -1;
+        int count = 1;      // launches between the two events
     };
+    TimedPair *run = nullptr;   // open run of timed back-to-back dynamics launches
+    int run_len = 0;
     std::vector<TimedPair> ring;
     size_t ring_pos = 0;
     double stage_ms[5] = {0, 0, 0, 0, 0};
@@ -132,7 +138,7 @@ int64_t partial_elems(const dem_ctx *ctx)
 {
     int64_t n = std::max<int64_t>(ctx->Ns + 1, (int64_t)ctx->grid.nbins + 1);
     n = std::max<int64_t>(n, radix_hist_elems(ctx->Ns));
-    return scan_tmp_elems(n) + 16;
+    return 2 * scan_tmp_elems(n) + 16;
 }
 
 void carve_cd(Carver &c, const dem_ctx *ctx, CdWork &w)
@@ -158,11 +164,12 @@ void carve(Carver &c, dem_ctx *ctx, int64_t cap)
 {
     int64_t No = ctx->No, Ns = ctx->Ns;
     ctx->rec = c.take<OwnerRec>(No);
-    ctx->snap_rec = c.take<OwnerRec>(No);
+    ctx->rec_alt = c.take<OwnerRec>(No);
     ctx->fref_rec = c.take<OwnerRec>(No);
     ctx->q = c.take<double>(4 * No);
-    ctx->snap_q = c.take<double>(4 * No);
+    ctx->q_alt = c.take<double>(4 * No);
     ctx->d_aux = c.take<OwnerAux>(No);
+    ctx->d_inv_i = c.take<float>(No);
     ctx->d_sph0 = c.take<uint32_t>(No + 1);
     ctx->d_sph = c.take<SphRec>(Ns);
     ctx->d_tpos = c.take<float>(4 * std::max(ctx->ncomp, 1));
@@ -176,8 +183,13 @@ void carve(Carver &c, dem_ctx *ctx, int64_t cap)
         a.hy = c.take<float>(cap);
         a.hz = c.take<float>(cap);
         a.hw = c.take<float>(cap);
+        a.hx2 = c.take<float>(cap);
+        a.hy2 = c.take<float>(cap);
+        a.hz2 = c.take<float>(cap);
+        a.hw2 = c.take<float>(cap);
         a.bstart = c.take<uint32_t>(Ns + 1);
         a.bidx = c.take<uint32_t>(cap);
+        a.bsrc = c.take<uint32_t>(cap);
         a.bcur = c.take<uint32_t>(Ns + 1);
     }
     ctx->sb.aF = c.take<float>(3 * Ns);
@@ -204,11 +216,11 @@ void carve(Carver &c, dem_ctx *ctx, int64_t cap)
     ctx->d_lab_j = c.take<uint32_t>(cap);
 }
 
-DetectArgs detect_args(const dem_ctx *ctx, bool snapshot, double margin, int64_t step)
+DetectArgs detect_args(const dem_ctx *ctx, double margin, int64_t step)
 {
     DetectArgs a;
-    a.rec = snapshot ? ctx->snap_rec : ctx->rec;
-    a.q = snapshot ? ctx->snap_q : ctx->q;
+    a.rec = ctx->rec;
+    a.q = ctx->q;
     a.aux = ctx->d_aux;
     a.sph = ctx->d_sph;
     a.tpos = ctx->d_tpos;
@@ -229,6 +241,7 @@ DynArgs dyn_args(const dem_ctx *ctx, int64_t step)
     a.rec = ctx->rec;
     a.q = ctx->q;
     a.aux = ctx->d_aux;
+    a.inv_i = ctx->d_inv_i;
     a.own_sph0 = ctx->d_sph0;
     a.sph = ctx->d_sph;
     a.tpos = ctx->d_tpos;
@@ -279,9 +292,10 @@ void drain_pair(dem_ctx *ctx, dem_ctx::TimedPair &p)
     hipEventSynchronize(p.b);
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
         ctx->stage_ms[p.kind] += ms;
-        ctx->stage_n[p.kind] += 1;
+        ctx->stage_n[p.kind] += p.count;
     }
     p.kind = -1;
+    p.count = 1;
 }
 
 // Opens a timed stage on stream s; returns the pair to close (or null).
@@ -290,7 +304,8 @@ void drain_pair(dem_ctx *ctx, dem_ctx::TimedPair &p)
 dem_ctx::TimedPair *stage_slot(dem_ctx *ctx, int kind)
 {
     if (ctx->P.timing <= 0) return nullptr;
-    if ((kind <= 1 || kind == 4) && (ctx->step % ctx->P.timing) != 0) return nullptr;
+    if ((kind <= 1 || kind == 4) && kind != 5 && (ctx->step % ctx->P.timing) != 0) return nullptr;
+    if (kind == 5) kind = 1;   // a run of fused dynamics launches (opened by the caller's own rule)
     if (ctx->ring.empty()) ctx->ring.resize(1024);
     dem_ctx::TimedPair &p = ctx->ring[ctx->ring_pos];
     ctx->ring_pos = (ctx->ring_pos + 1) % ctx->ring.size();
@@ -316,6 +331,27 @@ dem_ctx::TimedPair *stage_begin(dem_ctx *ctx, int kind, hipStream_t s)
 void stage_end(dem_ctx::TimedPair *p, hipStream_t s)
 {
     if (p) hipEventRecord(p->b, s);
+}
+
+// Runs of up to RUN_LAUNCHES back-to-back fused dynamics launches are timed
+// with one pair of marker events (their overhead is paid once per run and
+// measured by an empty kernel bracketed the same way right after the run).
+// A run is closed before any other work is enqueued on the dynamics stream.
+constexpr int RUN_LAUNCHES = 8;
+
+void run_close(dem_ctx *ctx, hipStream_t s)
+{
+    if (!ctx->run) return;
+    ctx->run->count = ctx->run_len;
+    stage_end(ctx->run, s);
+    ctx->run = nullptr;
+    ctx->run_len = 0;
+    if (auto *tn = stage_slot(ctx, 5)) {
+        tn->kind = 4;
+        hipEventRecord(tn->a, s);
+        launch_noop(s, nullptr, nullptr);
+        hipEventRecord(tn->b, s);
+    }
 }
 
 void drain_all(dem_ctx *ctx)
@@ -352,6 +388,8 @@ dem_status dem_create(const dem_params *params, const dem_materials *mats, const
     if (!(P.dt > 0.0)) return fail("dt must be positive");
     if (!(P.margin >= 0.0)) return fail("margin must be >= 0");
     if (P.cd_mode < 0 || P.cd_mode > 2) return fail("unknown cd_mode");
+    if (P.dyn_path < 0 || P.dyn_path > 1) return fail("dyn_path must be 0 (fused) or 1 (two kernels)");
+    if (P.bin_sort < 0 || P.bin_sort > 1) return fail("bin_sort must be 0 (one pass) or 1 (radix)");
     if (P.cd_mode != DEM_CD_EVERY) {
         if (P.cd_interval < 1) return fail("cd_interval must be >= 1");
         if (P.cd_latency < 0 || P.cd_latency > P.cd_interval) return fail("need 0 <= cd_latency <= cd_interval");
@@ -555,6 +593,11 @@ dem_status dem_bind(dem_ctx *ctx, void *device_workspace, int64_t bytes, int64_t
     if (!ctx->ev_wo) HIPCHK(hipEventCreateWithFlags(&ctx->ev_wo, hipEventDisableTiming));
     if (!ctx->ev_cd) HIPCHK(hipEventCreateWithFlags(&ctx->ev_cd, hipEventDisableTiming));
     HIPCHK(hipMemcpy(ctx->d_aux, ctx->aux.data(), sizeof(OwnerAux) * ctx->No, hipMemcpyHostToDevice));
+    {
+        std::vector<float> inv_i(ctx->No);
+        for (int64_t o = 0; o < ctx->No; ++o) inv_i[o] = ctx->aux[o].inv_moi[0];
+        HIPCHK(hipMemcpy(ctx->d_inv_i, inv_i.data(), sizeof(float) * ctx->No, hipMemcpyHostToDevice));
+    }
     HIPCHK(hipMemcpy(ctx->d_sph0, ctx->sph0.data(), sizeof(uint32_t) * (ctx->No + 1), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_sph, ctx->sph.data(), sizeof(SphRec) * ctx->Ns, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_tpos, ctx->tpos.data(), sizeof(float) * ctx->tpos.size(), hipMemcpyHostToDevice));
@@ -614,6 +657,9 @@ dem_status dem_set_state(dem_ctx *ctx, const double *X, const double *q, const f
     }
     HIPCHK(hipMemcpyAsync(ctx->rec, rec.data(), sizeof(OwnerRec) * ctx->No, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(ctx->q, qd.data(), sizeof(double) * 4 * ctx->No, hipMemcpyHostToDevice, s));
+    // the fused step leaves the orientations of single-sphere systems alone,
+    // so both buffers hold them
+    HIPCHK(hipMemcpyAsync(ctx->q_alt, qd.data(), sizeof(double) * 4 * ctx->No, hipMemcpyHostToDevice, s));
     DevCounters z{};
     HIPCHK(hipMemcpyAsync(ctx->ctr, &z, sizeof(DevCounters), hipMemcpyHostToDevice, s));
     clear_set(ctx, 0, s);
@@ -662,7 +708,7 @@ dem_status dem_bin(dem_ctx *ctx, dem_stream stream, uint32_t *sorted_keys, uint3
         return DEM_ERR_STATE;
     }
     hipStream_t s = S(stream);
-    DetectArgs a = detect_args(ctx, false, ctx->P.margin, ctx->step);
+    DetectArgs a = detect_args(ctx, ctx->P.margin, ctx->step);
     launch_bin(a, ctx->cdD, s);
     HIPCHK(hipGetLastError());
     if (sorted_keys || sorted_ids) {
@@ -677,7 +723,7 @@ dem_status dem_bin(dem_ctx *ctx, dem_stream stream, uint32_t *sorted_keys, uint3
 
 static dem_status detect_now(dem_ctx *ctx, double margin, hipStream_t s, int target)
 {
-    DetectArgs a = detect_args(ctx, false, margin, ctx->step);
+    DetectArgs a = detect_args(ctx, margin, ctx->step);
     auto *tp = stage_begin(ctx, 2, s);
     launch_detect(a, ctx->cdD, ctx->acs[target], ctx->cap, ctx->ctr, target, s);
     stage_end(tp, s);
@@ -874,7 +920,7 @@ dem_status dem_count_missing(dem_ctx *ctx, dem_stream stream, int64_t *missing)
     }
     hipStream_t s = S(stream);
     launch_fill_u32(&ctx->ctr->miss, 1, 0u, s);
-    DetectArgs a = detect_args(ctx, false, 0.0, ctx->step);
+    DetectArgs a = detect_args(ctx, 0.0, ctx->step);
     launch_judge(a, ctx->cdD, ctx->acs[ctx->cur], ctx->cap, ctx->ctr, s);
     HIPCHK(hipGetLastError());
     dem_status st = read_counters(ctx, s);
@@ -895,15 +941,21 @@ static void issue_work_order(dem_ctx *ctx, hipStream_t dyn, hipStream_t kin, int
         hipMemcpyAsync(ctx->fref_rec, ctx->rec, sizeof(OwnerRec) * ctx->No, hipMemcpyDeviceToDevice, dyn);
         ctx->snap_step = n;
     }
-    hipMemcpyAsync(ctx->snap_rec, ctx->rec, sizeof(OwnerRec) * ctx->No, hipMemcpyDeviceToDevice, dyn);
-    if (ctx->has_clumps)
-        hipMemcpyAsync(ctx->snap_q, ctx->q, sizeof(double) * 4 * ctx->No, hipMemcpyDeviceToDevice, dyn);
+    // the work order: the first binning kernel reads the state of step n on
+    // the dynamics stream (centres, bin keys and candidate records are the
+    // snapshot); the rest of the detection runs on the detection stream
+    int target = 1 - ctx->cur;
+    DetectArgs a = detect_args(ctx, ctx->P.margin, n);
+    auto *tf = stage_begin(ctx, 2, dyn);
+    launch_detect_front(a, ctx->cdK, ctx->acs[target], dyn);
+    if (tf) {
+        stage_end(tf, dyn);
+        tf->count = 0;   // one detection is counted once, with its back part
+    }
     hipEventRecord(ctx->ev_wo, dyn);
     hipStreamWaitEvent(kin, ctx->ev_wo, 0);
-    int target = 1 - ctx->cur;
-    DetectArgs a = detect_args(ctx, true, ctx->P.margin, n);
     auto *tp = stage_begin(ctx, 2, kin);
-    launch_detect(a, ctx->cdK, ctx->acs[target], ctx->cap, ctx->ctr, target, kin);
+    launch_detect_back(a, ctx->cdK, ctx->acs[target], ctx->cap, ctx->ctr, target, kin);
     stage_end(tp, kin);
     hipEventRecord(ctx->ev_cd, kin);
     ctx->pending = true;
@@ -928,6 +980,12 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
     int64_t cds = 0, swaps = 0, misses = 0, repairs = 0;
     const int64_t step0 = ctx->step;
     dem_status result = DEM_OK;
+    if (ctx->run) {
+        // a run left open by a call that returned early is discarded
+        ctx->run->kind = -1;
+        ctx->run = nullptr;
+        ctx->run_len = 0;
+    }
     drain_all(ctx);
     for (int k = 0; k < 5; ++k) {
         ctx->stage_ms[k] = 0.0;
@@ -942,6 +1000,13 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
     if (ctx->n_wo == 0) ctx->interval_sum = 0.0;
     for (int64_t t = 0; t < n_steps; ++t) {
         const int64_t n = ctx->step;
+        {
+            // close a timed run before a step that enqueues other work on
+            // the dynamics stream
+            const bool busy = P.cd_mode == DEM_CD_EVERY || !ctx->sched_init || P.judge || n == ctx->next_wo ||
+                              (ctx->pending && n == ctx->pend_swap);
+            if (busy) run_close(ctx, dyn);
+        }
         if (P.cd_mode == DEM_CD_EVERY) {
             int target = 1 - ctx->cur;
             dem_status st = detect_now(ctx, 0.0, dyn, target);
@@ -983,7 +1048,7 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
                 if (P.judge) {
                     int cand = swap_due ? ctx->pend_buf : ctx->cur;
                     launch_fill_u32(&ctx->ctr->miss, 1, 0u, dyn);
-                    DetectArgs a = detect_args(ctx, false, 0.0, n);
+                    DetectArgs a = detect_args(ctx, 0.0, n);
                     launch_judge(a, ctx->cdD, ctx->acs[cand], ctx->cap, ctx->ctr, dyn);
                     dem_status st = read_counters(ctx, dyn);
                     if (st != DEM_OK) return st;
@@ -1035,18 +1100,33 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
         // single kernels are bracketed by marker events, which wait for the
         // previous work on the stream; an empty kernel bracketed the same way
         // measures the markers' own overhead
-        auto *tf = stage_begin(ctx, 0, dyn);
-        launch_force(a, ctx->acs[ctx->cur], ctx->sb, ctx->ctr, dyn);
-        stage_end(tf, dyn);
-        auto *ti = stage_begin(ctx, 1, dyn);
-        launch_fold_integrate(a, ctx->acs[ctx->cur], ctx->sb, ctx->ctr, 1, dyn);
-        stage_end(ti, dyn);
-        if (auto *tn = stage_begin(ctx, 4, dyn)) {
-            launch_noop(dyn, nullptr, nullptr);
-            stage_end(tn, dyn);
+        if (P.dyn_path == 0) {
+            if (!ctx->run && P.timing > 0 && n % P.timing == 0) {
+                ctx->run = stage_slot(ctx, 5);
+                if (ctx->run) hipEventRecord(ctx->run->a, dyn);
+            }
+            launch_step_fused(a, ctx->rec_alt, ctx->q_alt, ctx->acs[ctx->cur], ctx->cap, ctx->ctr, dyn);
+            if (ctx->run && ++ctx->run_len == RUN_LAUNCHES) run_close(ctx, dyn);
+            std::swap(ctx->rec, ctx->rec_alt);
+            std::swap(ctx->q, ctx->q_alt);
+            swap_hist(ctx->acs[ctx->cur]);
+        } else {
+            auto *tf = stage_begin(ctx, 0, dyn);
+            launch_force(a, ctx->acs[ctx->cur], ctx->sb, ctx->ctr, dyn);
+            stage_end(tf, dyn);
+            auto *ti = stage_begin(ctx, 1, dyn);
+            launch_fold_integrate(a, ctx->acs[ctx->cur], ctx->sb, ctx->ctr, 1, dyn);
+            stage_end(ti, dyn);
+        }
+        if (P.dyn_path != 0) {
+            if (auto *tn = stage_begin(ctx, 4, dyn)) {
+                launch_noop(dyn, nullptr, nullptr);
+                stage_end(tn, dyn);
+            }
         }
         ctx->step = n + 1;
     }
+    run_close(ctx, dyn);
     {
         DynArgs da = dyn_args(ctx, ctx->step);
         launch_reduce_max(da, ctx->ctr, dyn);
@@ -1265,7 +1345,7 @@ dem_status dem_label_begin(dem_ctx *ctx, dem_stream stream, int64_t *n_contacts)
         return DEM_ERR_STATE;
     }
     hipStream_t s = S(stream);
-    DetectArgs a = detect_args(ctx, false, ctx->P.margin, ctx->step);
+    DetectArgs a = detect_args(ctx, ctx->P.margin, ctx->step);
     launch_detect_plain(a, ctx->cdD, ctx->d_lab_start, ctx->d_lab_j, ctx->cap, ctx->ctr, s);
     HIPCHK(hipGetLastError());
     dem_status st = read_counters(ctx, s);
@@ -1282,7 +1362,7 @@ dem_status dem_label_update(dem_ctx *ctx, uint32_t t, uint32_t *first_miss_dev, 
         return DEM_ERR_STATE;
     }
     hipStream_t s = S(stream);
-    DetectArgs a = detect_args(ctx, false, 0.0, ctx->step);
+    DetectArgs a = detect_args(ctx, 0.0, ctx->step);
     launch_label_judge(a, ctx->cdD, ctx->d_lab_start, ctx->d_lab_j, ctx->cap, ctx->d_cellmap, first_miss_dev, t, s);
     HIPCHK(hipGetLastError());
     return DEM_OK;

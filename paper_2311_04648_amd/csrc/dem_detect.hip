@@ -235,14 +235,24 @@ __global__ void __launch_bounds__(TPB) k_detect(DetectArgs a, const uint32_t *ke
     if (MODE == MODE_JUDGE && nmiss) atomicAdd(miss, nmiss);
 }
 
-// Single traversal: stages up to STAGE_K partners of each sphere (in
-// traversal order) and counts all of them; also counts, per sphere, the
-// contacts in which it is the higher id (its B list).
+// Single traversal over the forward half of the bin stencil: each sphere
+// (thread, in bin order) tests only the candidates after itself in its own
+// bin and the 13 neighbour bins that follow its bin in key order -- bin
+// x+1, the three bins of row y+1, the nine bins of plane z+1 -- so each pair
+// of candidates is tested once.  The FP64 predicate is symmetric bit for
+// bit.  A pair found goes to the row of its lower id: the row's count is
+// claimed with an atomic and the first STAGE_K partners are staged (their
+// order is fixed later by sorting each row); the higher id's B-list count is
+// bumped.  Walls go to the sphere's own row.  `count` must be zero on entry.
+// Candidate loads are issued four at a time over the concatenation of the
+// five contiguous ranges, so each thread has several loads in flight.
+constexpr int DETECT_BATCH = 4;
+
 __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32_t *keys, const Cand *cand,
                                                       const uint32_t *cell_start, uint32_t *count,
                                                       uint32_t *stage, uint32_t *bcount)
 {
-    int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (p >= a.n_spheres) return;
     const Cand ci = cand[p];
     const uint32_t i = ci.id;
@@ -250,23 +260,52 @@ __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32
     const double xi = ci.x, yi = ci.y, zi = ci.z, ri = (double)ci.r;
     const double m = a.margin;
     const uint32_t nx = (uint32_t)a.grid.nx, nxy = (uint32_t)a.grid.nx * (uint32_t)a.grid.ny;
-    uint32_t *st = stage + (size_t)i * STAGE_K;
+    // five contiguous candidate ranges: own bin after p + bin x+1; row y+1;
+    // the rows y-1, y, y+1 of plane z+1
+    uint32_t ra[5], rl[5];
+    {
+        const uint32_t e0 = cell_start[key + 2];
+        ra[0] = (uint32_t)p + 1u;
+        rl[0] = e0 - ra[0];
+        const uint32_t r1 = key + nx;
+        ra[1] = cell_start[r1 - 1];
+        rl[1] = cell_start[r1 + 2] - ra[1];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const uint32_t row = key + nxy + (uint32_t)((int)nx * (t - 1));
+            ra[2 + t] = cell_start[row - 1];
+            rl[2 + t] = cell_start[row + 2] - ra[2 + t];
+        }
+    }
+    const uint32_t total = (rl[0] + rl[1]) + (rl[2] + rl[3] + rl[4]);
     uint32_t own_i = 0xffffffffu;
-    uint32_t n = 0;
-    for (int dz = -1; dz <= 1; ++dz) {
-        for (int dy = -1; dy <= 1; ++dy) {
-            uint32_t row = key + (uint32_t)((int)nxy * dz) + (uint32_t)((int)nx * dy);
-            uint32_t q0 = cell_start[row - 1], q1 = cell_start[row + 2];
-            for (uint32_t qq = q0; qq < q1; ++qq) {
-                const Cand cj = cand[qq];
-                if (cj.id <= i) continue;
-                if (!sphere_pair_hit(xi, yi, zi, ri, cj, m)) continue;
-                if (own_i == 0xffffffffu) own_i = a.sph[i].owner;
-                if (a.sph[cj.id].owner == own_i) continue;
-                if (n < STAGE_K) st[n] = cj.id;
-                if (bcount) atomicAdd(&bcount[cj.id], 1u);
-                ++n;
+    for (uint32_t v0 = 0; v0 < total; v0 += DETECT_BATCH) {
+        Cand cb[DETECT_BATCH];
+#pragma unroll
+        for (int u = 0; u < DETECT_BATCH; ++u) {
+            uint32_t v = v0 + (uint32_t)u;
+            if (v < total) {
+                int r = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (r == k && v >= rl[k]) {
+                        v -= rl[k];
+                        r = k + 1;
+                    }
+                cb[u] = cand[ra[r] + v];
             }
+        }
+#pragma unroll
+        for (int u = 0; u < DETECT_BATCH; ++u) {
+            if (v0 + (uint32_t)u >= total) break;
+            const Cand &cj = cb[u];
+            if (!sphere_pair_hit(xi, yi, zi, ri, cj, m)) continue;
+            if (own_i == 0xffffffffu) own_i = a.sph[i].owner;
+            if (a.sph[cj.id].owner == own_i) continue;
+            const uint32_t lo = i < cj.id ? i : cj.id, hi = i < cj.id ? cj.id : i;
+            const uint32_t slot = atomicAdd(&count[lo], 1u);
+            if (slot < (uint32_t)STAGE_K) stage[(size_t)lo * STAGE_K + slot] = hi;
+            if (bcount) atomicAdd(&bcount[hi], 1u);
         }
     }
     for (int w = 0; w < a.n_walls; ++w) {
@@ -274,75 +313,91 @@ __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32
         double pw[3];
         wall_point(wd, a.step, a.h, pw);
         if (!wall_hit(wd, pw, xi, yi, zi, ri, m)) continue;
-        if (n < STAGE_K) st[n] = (uint32_t)a.n_spheres + (uint32_t)w;
-        ++n;
+        const uint32_t slot = atomicAdd(&count[i], 1u);
+        if (slot < (uint32_t)STAGE_K) stage[(size_t)i * STAGE_K + slot] = (uint32_t)a.n_spheres + (uint32_t)w;
     }
-    count[i] = n;
+}
+
+// Appends sphere i to the B list of each sphere partner in its row.
+__device__ inline void fill_blists(const uint32_t *row, uint32_t base, uint32_t n, uint32_t i, int64_t ns,
+                                   uint32_t *bcur, uint32_t *bidx, uint32_t *bsrc)
+{
+    for (uint32_t t = 0; t < n; ++t) {
+        const uint32_t jj = row[t];
+        if ((int64_t)jj < ns) {
+            const uint32_t slot = atomicAdd(&bcur[jj], 1u);
+            bidx[slot] = base + t;
+            bsrc[slot] = i;
+        }
+    }
 }
 
 // Moves staged rows (at most STAGE_K) to their CSR place, sorted, and fills
-// the B lists (slot order is fixed later by k_blist_sort).
-__global__ void __launch_bounds__(TPB) k_compact(const uint32_t *start, const uint32_t *stage, uint32_t *out_j,
-                                                 int64_t ns, int64_t cap, uint32_t *bcur, uint32_t *bidx)
+// the B lists (slot order is fixed later by k_blist_sort).  A row longer
+// than STAGE_K is found again by a full-stencil walk for its sphere (its
+// centre from the unsorted candidate records, its bin recomputed the same
+// way as when binning), written, and sorted in place.
+__global__ void __launch_bounds__(TPB) k_compact(DetectArgs a, const Cand *cand_tmp, const Cand *cand,
+                                                 const uint32_t *cell_start, const uint32_t *start,
+                                                 const uint32_t *stage, uint32_t *out_j, int64_t cap,
+                                                 uint32_t *bcur, uint32_t *bidx, uint32_t *bsrc)
 {
+    const int64_t ns = a.n_spheres;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ns || (int64_t)start[ns] > cap) return;
     const uint32_t r0 = start[i], n = start[i + 1] - r0;
-    if (n == 0 || n > STAGE_K) return;
-    uint32_t v[STAGE_K];
-    const uint32_t *st = stage + (size_t)i * STAGE_K;
+    if (n == 0) return;
+    if (n <= STAGE_K) {
+        uint32_t v[STAGE_K];
+        const uint32_t *st = stage + (size_t)i * STAGE_K;
 #pragma unroll
-    for (int t = 0; t < STAGE_K; ++t) v[t] = (uint32_t)t < n ? st[t] : 0xffffffffu;
-    // sorting network on registers (odd-even transposition), ascending
+        for (int t = 0; t < STAGE_K; ++t) v[t] = (uint32_t)t < n ? st[t] : 0xffffffffu;
+        // sorting network on registers (odd-even transposition), ascending
 #pragma unroll
-    for (int r = 0; r < STAGE_K; ++r) {
+        for (int r = 0; r < STAGE_K; ++r) {
 #pragma unroll
-        for (int t = (r & 1); t + 1 < STAGE_K; t += 2) {
-            uint32_t lo = v[t] < v[t + 1] ? v[t] : v[t + 1];
-            uint32_t hi = v[t] < v[t + 1] ? v[t + 1] : v[t];
-            v[t] = lo;
-            v[t + 1] = hi;
+            for (int t = (r & 1); t + 1 < STAGE_K; t += 2) {
+                uint32_t lo = v[t] < v[t + 1] ? v[t] : v[t + 1];
+                uint32_t hi = v[t] < v[t + 1] ? v[t + 1] : v[t];
+                v[t] = lo;
+                v[t + 1] = hi;
+            }
         }
-    }
 #pragma unroll
-    for (int t = 0; t < STAGE_K; ++t) {
-        if ((uint32_t)t < n) {
-            out_j[r0 + t] = v[t];
-            if (bidx && (int64_t)v[t] < ns) bidx[atomicAdd(&bcur[v[t]], 1u)] = r0 + t;
+        for (int t = 0; t < STAGE_K; ++t) {
+            if ((uint32_t)t < n) {
+                out_j[r0 + t] = v[t];
+                if (bidx && (int64_t)v[t] < ns) {
+                    const uint32_t slot = atomicAdd(&bcur[v[t]], 1u);
+                    bidx[slot] = r0 + t;
+                    bsrc[slot] = (uint32_t)i;
+                }
+            }
         }
+        return;
     }
-}
-
-// Rows longer than STAGE_K: traverse again, write, sort in place, fill B lists.
-__global__ void __launch_bounds__(TPB) k_detect_overflow(DetectArgs a, const uint32_t *keys, const Cand *cand,
-                                                         const uint32_t *cell_start, const uint32_t *start,
-                                                         uint32_t *out_j, int64_t cap, uint32_t *bcur,
-                                                         uint32_t *bidx)
-{
-    int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (p >= a.n_spheres) return;
-    const uint32_t i = cand[p].id;
-    if ((int64_t)start[a.n_spheres] > cap) return;
-    const uint32_t base = start[i], total = start[i + 1] - base;
-    if (total <= STAGE_K) return;
-    const Cand ci = cand[p];
-    const uint32_t key = keys[p];
+    const Cand ci = cand_tmp[i];
     const double xi = ci.x, yi = ci.y, zi = ci.z, ri = (double)ci.r;
     const double m = a.margin;
+    const int cx = bin_coord(xi, a.grid.lo[0], a.grid.inv_b, a.grid.nx);
+    const int cy = bin_coord(yi, a.grid.lo[1], a.grid.inv_b, a.grid.ny);
+    const int cz = bin_coord(zi, a.grid.lo[2], a.grid.inv_b, a.grid.nz);
+    const uint32_t key = ((uint32_t)cz * (uint32_t)a.grid.ny + (uint32_t)cy) * (uint32_t)a.grid.nx + (uint32_t)cx;
     const uint32_t nx = (uint32_t)a.grid.nx, nxy = (uint32_t)a.grid.nx * (uint32_t)a.grid.ny;
-    uint32_t own_i = a.sph[i].owner;
-    uint32_t n = 0;
+    const uint32_t own_i = a.sph[i].owner;
+    uint32_t *row = out_j + r0;
+    uint32_t k = 0;
     for (int dz = -1; dz <= 1; ++dz) {
         for (int dy = -1; dy <= 1; ++dy) {
-            uint32_t row = key + (uint32_t)((int)nxy * dz) + (uint32_t)((int)nx * dy);
-            uint32_t q0 = cell_start[row - 1], q1 = cell_start[row + 2];
+            const uint32_t rw = key + (uint32_t)((int)nxy * dz) + (uint32_t)((int)nx * dy);
+            const uint32_t q0 = cell_start[rw - 1], q1 = cell_start[rw + 2];
             for (uint32_t qq = q0; qq < q1; ++qq) {
                 const Cand cj = cand[qq];
-                if (cj.id <= i) continue;
+                if (cj.id <= (uint32_t)i) continue;
                 if (!sphere_pair_hit(xi, yi, zi, ri, cj, m)) continue;
                 if (a.sph[cj.id].owner == own_i) continue;
-                if (n < total) out_j[base + n] = cj.id;
-                ++n;
+                if (k < n) row[k] = cj.id;
+                ++k;
             }
         }
     }
@@ -351,22 +406,20 @@ __global__ void __launch_bounds__(TPB) k_detect_overflow(DetectArgs a, const uin
         double pw[3];
         wall_point(wd, a.step, a.h, pw);
         if (!wall_hit(wd, pw, xi, yi, zi, ri, m)) continue;
-        if (n < total) out_j[base + n] = (uint32_t)a.n_spheres + (uint32_t)w;
-        ++n;
+        if (k < n) row[k] = (uint32_t)ns + (uint32_t)w;
+        ++k;
     }
-    if (n > total) n = total;
-    for (uint32_t t = 1; t < n; ++t) {
-        uint32_t v = out_j[base + t];
+    if (k > n) k = n;
+    for (uint32_t t = 1; t < k; ++t) {
+        const uint32_t v = row[t];
         uint32_t u = t;
-        while (u > 0 && out_j[base + u - 1] > v) {
-            out_j[base + u] = out_j[base + u - 1];
+        while (u > 0 && row[u - 1] > v) {
+            row[u] = row[u - 1];
             --u;
         }
-        out_j[base + u] = v;
+        row[u] = v;
     }
-    if (bidx)
-        for (uint32_t t = 0; t < n; ++t)
-            if ((int64_t)out_j[base + t] < a.n_spheres) bidx[atomicAdd(&bcur[out_j[base + t]], 1u)] = base + t;
+    if (bidx) fill_blists(row, r0, k, (uint32_t)i, ns, bcur, bidx, bsrc);
 }
 
 __global__ void k_check_capacity(const uint32_t *start, int64_t ns, int64_t cap, DevCounters *ctr,
@@ -399,30 +452,38 @@ __global__ void __launch_bounds__(TPB) k_blist_count(const uint32_t *start, cons
 }
 
 __global__ void __launch_bounds__(TPB) k_blist_fill(const uint32_t *start, const uint32_t *j,
-                                                    int64_t ns, int64_t cap, uint32_t *cursor, uint32_t *bidx)
+                                                    int64_t ns, int64_t cap, uint32_t *cursor, uint32_t *bidx,
+                                                    uint32_t *bsrc)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ns || (int64_t)start[ns] > cap) return;
     for (uint32_t c = start[i]; c < start[i + 1]; ++c) {
         uint32_t jj = j[c];
-        if ((int64_t)jj < ns) bidx[atomicAdd(&cursor[jj], 1u)] = c;
+        if ((int64_t)jj < ns) {
+            const uint32_t slot = atomicAdd(&cursor[jj], 1u);
+            bidx[slot] = c;
+            bsrc[slot] = (uint32_t)i;
+        }
     }
 }
 
+// Orders each B list by contact index (its source sphere moves along).
 __global__ void __launch_bounds__(TPB) k_blist_sort(const uint32_t *start, const uint32_t *bstart, int64_t ns,
-                                                    int64_t cap, uint32_t *bidx)
+                                                    int64_t cap, uint32_t *bidx, uint32_t *bsrc)
 {
     int64_t jv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (jv >= ns || (int64_t)start[ns] > cap) return;   // an overflowed set has no B lists
     uint32_t b0 = bstart[jv], b1 = bstart[jv + 1];
     for (uint32_t t = b0 + 1; t < b1; ++t) {
-        uint32_t v = bidx[t];
+        const uint32_t v = bidx[t], w = bsrc[t];
         uint32_t u = t;
         while (u > b0 && bidx[u - 1] > v) {
             bidx[u] = bidx[u - 1];
+            bsrc[u] = bsrc[u - 1];
             --u;
         }
         bidx[u] = v;
+        bsrc[u] = w;
     }
 }
 
@@ -458,13 +519,24 @@ __global__ void __launch_bounds__(TPB) k_remap(const uint32_t *os, const uint32_
 
 }  // namespace
 
-void launch_bin(const DetectArgs &a, CdWork &w, hipStream_t s)
+// First part of binning: zeroes the bin counts (and up to two further
+// arrays of the caller in the same launch), then sphere centres, bin keys,
+// unsorted candidate records and bin counts from the state in `a`.  After
+// it, nothing of the binning reads the owner state.
+void launch_bin_front(const DetectArgs &a, CdWork &w, hipStream_t s, uint32_t *z1, int64_t n1, uint32_t *z2,
+                      int64_t n2)
+{
+    const int64_t n = a.n_spheres;
+    launch_zero3(w.cell_count, (int64_t)a.grid.nbins, z1, n1, z2, n2, s);
+    hipLaunchKernelGGL(k_cd_prepare, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.vals, w.cand_tmp,
+                       w.cell_count);
+}
+
+// Rest of binning: cell ranges, sort of (bin, id), candidates in bin order.
+void launch_bin_back(const DetectArgs &a, CdWork &w, hipStream_t s)
 {
     int64_t n = a.n_spheres;
     const int64_t nb = (int64_t)a.grid.nbins;
-    launch_fill_u32(w.cell_count, nb, 0u, s);
-    hipLaunchKernelGGL(k_cd_prepare, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.vals, w.cand_tmp,
-                       w.cell_count);
     if (w.sort_mode == 0) {
         // cell ranges, with a copy of the offsets as the per-bin cursor
         scan_exclusive_u32(w.cell_count, w.cell_start, nb, w.partials, s, w.cell_count);
@@ -477,7 +549,16 @@ void launch_bin(const DetectArgs &a, CdWork &w, hipStream_t s)
         scan_exclusive_u32(w.cell_count, w.cell_start, nb, w.partials, s);
         radix_sort_u32(&w.keys, &w.vals, &w.keys_alt, &w.vals_alt, n, w.sort_bits, w.hist, w.partials, s);
     }
+    // candidate records in bin order (random 32-byte reads, coalesced writes;
+    // moving the records in the scatter instead costs more: random writes)
     hipLaunchKernelGGL(k_cand_gather, dim3(nblocks(n)), dim3(TPB), 0, s, w.vals, w.cand_tmp, w.cand, n);
+}
+
+void launch_bin(const DetectArgs &a, CdWork &w, hipStream_t s, uint32_t *z1, int64_t n1, uint32_t *z2,
+                int64_t n2)
+{
+    launch_bin_front(a, w, s, z1, n1, z2, n2);
+    launch_bin_back(a, w, s);
 }
 
 void launch_blists(AcsBuf &b, int64_t ns, int64_t cap, uint32_t *partials, hipStream_t s)
@@ -485,25 +566,41 @@ void launch_blists(AcsBuf &b, int64_t ns, int64_t cap, uint32_t *partials, hipSt
     launch_fill_u32(b.bcur, ns + 1, 0u, s);
     hipLaunchKernelGGL(k_blist_count, dim3(nblocks(ns)), dim3(TPB), 0, s, b.start, b.j, ns, cap, b.bcur);
     scan_exclusive_u32(b.bcur, b.bstart, ns, partials, s, b.bcur);
-    hipLaunchKernelGGL(k_blist_fill, dim3(nblocks(ns)), dim3(TPB), 0, s, b.start, b.j, ns, cap, b.bcur, b.bidx);
-    hipLaunchKernelGGL(k_blist_sort, dim3(nblocks(ns)), dim3(TPB), 0, s, b.start, b.bstart, ns, cap, b.bidx);
+    hipLaunchKernelGGL(k_blist_fill, dim3(nblocks(ns)), dim3(TPB), 0, s, b.start, b.j, ns, cap, b.bcur, b.bidx,
+                       b.bsrc);
+    hipLaunchKernelGGL(k_blist_sort, dim3(nblocks(ns)), dim3(TPB), 0, s, b.start, b.bstart, ns, cap, b.bidx,
+                       b.bsrc);
+}
+
+void launch_detect_front(const DetectArgs &a, CdWork &w, AcsBuf &out, hipStream_t s)
+{
+    const int64_t n = a.n_spheres;
+    launch_bin_front(a, w, s, out.bcur, n + 1, w.count, n + 1);
 }
 
 void launch_detect(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap, DevCounters *ctr, int buf,
                    hipStream_t s)
 {
+    launch_detect_front(a, w, out, s);
+    launch_detect_back(a, w, out, cap, ctr, buf, s);
+}
+
+void launch_detect_back(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap, DevCounters *ctr, int buf,
+                        hipStream_t s)
+{
     int64_t n = a.n_spheres;
-    launch_bin(a, w, s);
-    launch_fill_u32(out.bcur, n + 1, 0u, s);
+    launch_bin_back(a, w, s);
     hipLaunchKernelGGL(k_detect_stage, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand, w.cell_start,
                        w.count, w.stage, out.bcur);
-    scan_exclusive_u32(w.count, out.start, n, w.partials, s, nullptr, ctr, cap, buf);
-    scan_exclusive_u32(out.bcur, out.bstart, n, w.partials, s, out.bcur);
-    hipLaunchKernelGGL(k_compact, dim3(nblocks(n)), dim3(TPB), 0, s, out.start, w.stage, out.j, n, cap, out.bcur,
-                       out.bidx);
-    hipLaunchKernelGGL(k_detect_overflow, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand, w.cell_start,
-                       out.start, out.j, cap, out.bcur, out.bidx);
-    hipLaunchKernelGGL(k_blist_sort, dim3(nblocks(n)), dim3(TPB), 0, s, out.start, out.bstart, n, cap, out.bidx);
+    // row offsets (checked against the capacity) and B-list offsets (with a
+    // copy as the fill cursor) in one pair of launches
+    scan_exclusive_u32_pair(w.count, out.start, nullptr, ctr, cap, buf, out.bcur, out.bstart, out.bcur, n,
+                            w.partials, s);
+    hipLaunchKernelGGL(k_compact, dim3(nblocks(n)), dim3(TPB), 0, s, a, (const Cand *)w.cand_tmp,
+                       (const Cand *)w.cand, (const uint32_t *)w.cell_start, (const uint32_t *)out.start,
+                       (const uint32_t *)w.stage, out.j, cap, out.bcur, out.bidx, out.bsrc);
+    hipLaunchKernelGGL(k_blist_sort, dim3(nblocks(n)), dim3(TPB), 0, s, out.start, out.bstart, n, cap, out.bidx,
+                       out.bsrc);
 }
 
 void launch_judge(const DetectArgs &a, CdWork &w, const AcsBuf &cur, int64_t cap, DevCounters *ctr,
@@ -528,15 +625,15 @@ void launch_detect_plain(const DetectArgs &a, CdWork &w, uint32_t *start, uint32
                          DevCounters *ctr, hipStream_t s)
 {
     int64_t n = a.n_spheres;
-    launch_bin(a, w, s);
+    launch_bin(a, w, s, w.count, n + 1);
     hipLaunchKernelGGL(k_detect_stage, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand, w.cell_start,
                        w.count, w.stage, (uint32_t *)nullptr);
     scan_exclusive_u32(w.count, start, n, w.partials, s);
     hipLaunchKernelGGL(k_record_total, dim3(1), dim3(1), 0, s, start, n, ctr);
-    hipLaunchKernelGGL(k_compact, dim3(nblocks(n)), dim3(TPB), 0, s, start, w.stage, j, n, cap,
-                       (uint32_t *)nullptr, (uint32_t *)nullptr);
-    hipLaunchKernelGGL(k_detect_overflow, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand, w.cell_start,
-                       start, j, cap, (uint32_t *)nullptr, (uint32_t *)nullptr);
+    hipLaunchKernelGGL(k_compact, dim3(nblocks(n)), dim3(TPB), 0, s, a, (const Cand *)w.cand_tmp,
+                       (const Cand *)w.cand, (const uint32_t *)w.cell_start, (const uint32_t *)start,
+                       (const uint32_t *)w.stage, j, cap, (uint32_t *)nullptr, (uint32_t *)nullptr,
+                       (uint32_t *)nullptr);
 }
 
 void launch_label_judge(const DetectArgs &a, CdWork &w, const uint32_t *lab_start, const uint32_t *lab_j,

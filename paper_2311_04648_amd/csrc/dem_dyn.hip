@@ -74,6 +74,190 @@ __device__ inline bool stopped(const DevCounters *c, int64_t step)
     return c->stop_cd != 0u || c->div[(step + 1) & 1] != 0u;
 }
 
+// One contact evaluated from the side of sphere A (the lower id of the pair
+// or the sphere of a sphere-wall pair): overlap and normal in FP64, the
+// Hertz-Mindlin law with tangential history in FP32.  `hold` is the contact's
+// history before the step; the result holds the new one.  Both the A-side
+// sum and the B-side reaction of a contact are taken from this one function,
+// so a contact gives the same bits wherever it is evaluated.
+struct ContactOut {
+    float3 F;        // force on A (normal + tangential)
+    float3 Ft;       // F plus the rolling-resistance force (torques only)
+    float3 armA;     // contact point minus A's owner centre
+    float3 armB;     // contact point minus B's owner centre (wall: wall point)
+    float4 h;        // history after the step (xi, contact age)
+    bool touching;
+};
+
+__device__ __forceinline__ void contact_eval(const DynArgs &a, const SphRec &sA, const OwnerKin &kA,
+                                             const double *xA, uint32_t jp, float4 hold, ContactOut &out)
+{
+    const int64_t Ns = a.n_spheres;
+    const double radA = (double)sA.rad;
+    const float hf = (float)a.h;
+    double nrm[3], delta = 0.0, XB[3];
+    float Rbar = 0.f, mbar = 0.f;
+    float3 vB = f3(0.f, 0.f, 0.f), wB = f3(0.f, 0.f, 0.f);
+    uint32_t matB = 0;
+    bool touching = false;
+    if ((int64_t)jp < Ns) {
+        const SphRec sB = load_sph(a.sph + jp);
+        const OwnerRec rB = load_rec(a.rec + sB.owner);
+        OwnerKin kB;
+        double xB[3];
+        owner_kin(rB, sB, a.aux, a.q, a.tpos, a.org, kB, xB);
+        double dx = xA[0] - xB[0], dy = xA[1] - xB[1], dz = xA[2] - xB[2];
+        double d2 = (dx * dx + dy * dy) + dz * dz;
+        double radB = (double)sB.rad;
+        double T = radA + radB;
+        touching = d2 < T * T;
+        if (touching) {
+            double d = sqrt(d2);
+            nrm[0] = dx / d;
+            nrm[1] = dy / d;
+            nrm[2] = dz / d;
+            delta = T - d;
+            Rbar = (float)(radA * radB / (radA + radB));
+            mbar = kA.mass * kB.mass / (kA.mass + kB.mass);
+            matB = sB.mat;
+            XB[0] = kB.X[0];
+            XB[1] = kB.X[1];
+            XB[2] = kB.X[2];
+            vB = kB.v;
+            wB = kB.w;
+        }
+    } else {
+        const WallDev wd = a.walls[jp - (uint32_t)Ns];
+        double p[3];
+        wall_point(wd, a.step, a.h, p);
+        double rx = xA[0] - p[0], ry = xA[1] - p[1], rz = xA[2] - p[2];
+        if (wd.type == 0) {
+            double sd = (rx * wd.geom[3] + ry * wd.geom[4]) + rz * wd.geom[5];
+            touching = sd < radA;
+            if (touching) {
+                nrm[0] = wd.geom[3];
+                nrm[1] = wd.geom[4];
+                nrm[2] = wd.geom[5];
+                delta = radA - sd;
+                Rbar = (float)radA;
+            }
+        } else {
+            double ax = (rx * wd.geom[3] + ry * wd.geom[4]) + rz * wd.geom[5];
+            double hl = 0.5 * wd.geom[7];
+            double px = rx - ax * wd.geom[3], py = ry - ax * wd.geom[4], pz = rz - ax * wd.geom[5];
+            double d2 = (px * px + py * py) + pz * pz;
+            double T = wd.geom[6] + radA;
+            touching = (ax <= hl && ax >= -hl) && d2 < T * T && d2 > 0.0;
+            if (touching) {
+                double d = sqrt(d2);
+                nrm[0] = px / d;
+                nrm[1] = py / d;
+                nrm[2] = pz / d;
+                delta = T - d;
+                Rbar = (float)(radA * wd.geom[6] / (radA + wd.geom[6]));
+            }
+        }
+        if (touching) {
+            mbar = kA.mass;
+            matB = (uint32_t)wd.mat;
+            XB[0] = p[0];
+            XB[1] = p[1];
+            XB[2] = p[2];
+            vB = f3((float)wd.vel[0], (float)wd.vel[1], (float)wd.vel[2]);
+            wB = f3((float)wd.omega[0], (float)wd.omega[1], (float)wd.omega[2]);
+        }
+    }
+    out.touching = touching;
+    if (!touching) {
+        out.h = make_float4(0.f, 0.f, 0.f, 0.f);
+        return;
+    }
+    // contact point in the middle of the overlap; arms to both owner centres
+    const double sc = radA - 0.5 * delta;
+    double cp[3] = {xA[0] - sc * nrm[0], xA[1] - sc * nrm[1], xA[2] - sc * nrm[2]};
+    const float3 armA = f3((float)(cp[0] - kA.X[0]), (float)(cp[1] - kA.X[1]), (float)(cp[2] - kA.X[2]));
+    const float3 armB = f3((float)(cp[0] - XB[0]), (float)(cp[1] - XB[1]), (float)(cp[2] - XB[2]));
+    const float3 n = f3((float)nrm[0], (float)nrm[1], (float)nrm[2]);
+    const MatPair mq = a.mat[(size_t)sA.mat * (size_t)a.n_mat + matB];
+    // relative velocity of A with respect to B at the contact point
+    // (linear parts first, so their difference is exact-ish)
+    const float3 rotA = cross3(kA.w, armA), rotB = cross3(wB, armB);
+    const float3 u = (kA.v - vB) + (rotA - rotB);
+    const float pn = dot3(u, n);
+    const float3 ut = u - pn * n;
+    float3 xi = f3(hold.x, hold.y, hold.z);
+    xi = xi + hf * ut;
+    xi = xi - dot3(xi, n) * n;
+    const float df = (float)delta;
+    const float sqrtRd = sqrtf(Rbar * df);
+    const float Sn = 2.0f * mq.Estar * sqrtRd;
+    const float kn = (2.0f / 3.0f) * Sn;
+    const float c56 = 1.8257418583505538f;   // 2 sqrt(5/6)
+    const float gn = c56 * mq.beta * sqrtf(Sn * mbar);
+    float3 F = (kn * df + gn * pn) * n;
+    // rolling resistance: torque-only force C_rr |F_n| along the rolling
+    // part of the relative velocity, once the contact is older than the
+    // damped collision time of the simplified constants
+    float3 Fr = f3(0.f, 0.f, 0.f);
+    float age = 0.f;
+    if (a.rolling) {
+        age = hold.w + hf;
+        if (mq.crr > 0.0f) {
+            bool add = true;
+            const float Reff = sqrtf(Rbar);
+            const float kns = (4.0f / 3.0f) * mq.Estar * sqrtf(Reff);
+            const float gns = -2.0f * sqrtf((5.0f / 3.0f) * mbar * mq.Estar) * mq.beta * sqrtf(sqrtf(Reff));
+            const float dcf = gns / (2.0f * sqrtf(kns * mbar));
+            if (dcf < 1.0f) {
+                const float tcol = 3.14159265358979f * sqrtf(mbar / (kns * (1.0f - dcf * dcf)));
+                if (age <= tcol) add = false;
+            }
+            if (add) {
+                const float3 vr = rotB - rotA;
+                const float vrn = sqrtf(dot3(vr, vr));
+                if (vrn > 1e-12f) Fr = ((mq.crr * sqrtf(dot3(F, F))) / vrn) * vr;
+            }
+        }
+    }
+    if (mq.mu > 0.0f) {
+        const float kt = 8.0f * mq.Gstar * sqrtRd;
+        const float gt = -c56 * mq.beta * sqrtf(mbar * kt);
+        float3 ft = (-kt) * xi - gt * ut;
+        const float ftn = sqrtf(dot3(ft, ft));
+        if (ftn > 1e-12f) {
+            const float ftmax = sqrtf(dot3(F, F)) * mq.mu;
+            if (ftn > ftmax) {
+                ft = (ftmax / ftn) * ft;
+                xi = (-1.0f / kt) * (ft + gt * ut);
+            }
+        } else {
+            ft = f3(0.f, 0.f, 0.f);
+        }
+        F = F + ft;
+    }
+    out.F = F;
+    out.Ft = F + Fr;
+    out.armA = armA;
+    out.armB = armB;
+    out.h = make_float4(xi.x, xi.y, xi.z, age);
+}
+
+__device__ inline float4 load_hist(const float *hx, const float *hy, const float *hz, const float *hw,
+                                   uint32_t c, int rolling)
+{
+    return make_float4(hx[c], hy[c], hz[c], rolling ? hw[c] : 0.f);
+}
+
+__device__ inline void store_hist(float *hx, float *hy, float *hz, float *hw, uint32_t c, float4 h, int rolling)
+{
+    hx[c] = h.x;
+    hy[c] = h.y;
+    hz[c] = h.z;
+    if (rolling) hw[c] = h.w;
+}
+
+// Two-kernel path (forces without integration): A-side sums per sphere and
+// the reaction on B per contact, history updated in place.
 __global__ void __launch_bounds__(TPB) k_force(DynArgs a, const uint32_t *start, const uint32_t *jarr,
                                                float *hx, float *hy, float *hz, float *hw, float *aF, float *aT,
                                                float *bF, float *bT, int64_t cap, const DevCounters *ctr)
@@ -81,7 +265,7 @@ __global__ void __launch_bounds__(TPB) k_force(DynArgs a, const uint32_t *start,
     int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= a.n_spheres) return;
     if (stopped(ctr, a.step)) return;
-    const int64_t Ns = a.n_spheres, No = a.n_owners;
+    const int64_t Ns = a.n_spheres;
     float3 FA = f3(0.f, 0.f, 0.f), TA = f3(0.f, 0.f, 0.f);
     const uint32_t c0 = start[i], c1 = start[i + 1];
     if (c0 < c1) {
@@ -90,87 +274,11 @@ __global__ void __launch_bounds__(TPB) k_force(DynArgs a, const uint32_t *start,
         OwnerKin kA;
         double xA[3];
         owner_kin(rA, sA, a.aux, a.q, a.tpos, a.org, kA, xA);
-        const double radA = (double)sA.rad;
-        const float hf = (float)a.h;
         for (uint32_t c = c0; c < c1; ++c) {
-            const uint32_t jp = jarr[c];
-            double nrm[3], delta = 0.0, XB[3];
-            float Rbar = 0.f, mbar = 0.f;
-            float3 vB = f3(0.f, 0.f, 0.f), wB = f3(0.f, 0.f, 0.f);
-            uint32_t matB = 0;
-            bool touching = false, wall = (int64_t)jp >= Ns;
-            if (!wall) {
-                const SphRec sB = load_sph(a.sph + jp);
-                const OwnerRec rB = load_rec(a.rec + sB.owner);
-                OwnerKin kB;
-                double xB[3];
-                owner_kin(rB, sB, a.aux, a.q, a.tpos, a.org, kB, xB);
-                double dx = xA[0] - xB[0], dy = xA[1] - xB[1], dz = xA[2] - xB[2];
-                double d2 = (dx * dx + dy * dy) + dz * dz;
-                double radB = (double)sB.rad;
-                double T = radA + radB;
-                touching = d2 < T * T;
-                if (touching) {
-                    double d = sqrt(d2);
-                    nrm[0] = dx / d;
-                    nrm[1] = dy / d;
-                    nrm[2] = dz / d;
-                    delta = T - d;
-                    Rbar = (float)(radA * radB / (radA + radB));
-                    mbar = kA.mass * kB.mass / (kA.mass + kB.mass);
-                    matB = sB.mat;
-                    XB[0] = kB.X[0];
-                    XB[1] = kB.X[1];
-                    XB[2] = kB.X[2];
-                    vB = kB.v;
-                    wB = kB.w;
-                }
-            } else {
-                const WallDev wd = a.walls[jp - (uint32_t)Ns];
-                double p[3];
-                wall_point(wd, a.step, a.h, p);
-                double rx = xA[0] - p[0], ry = xA[1] - p[1], rz = xA[2] - p[2];
-                if (wd.type == 0) {
-                    double sd = (rx * wd.geom[3] + ry * wd.geom[4]) + rz * wd.geom[5];
-                    touching = sd < radA;
-                    if (touching) {
-                        nrm[0] = wd.geom[3];
-                        nrm[1] = wd.geom[4];
-                        nrm[2] = wd.geom[5];
-                        delta = radA - sd;
-                        Rbar = (float)radA;
-                    }
-                } else {
-                    double ax = (rx * wd.geom[3] + ry * wd.geom[4]) + rz * wd.geom[5];
-                    double hl = 0.5 * wd.geom[7];
-                    double px = rx - ax * wd.geom[3], py = ry - ax * wd.geom[4], pz = rz - ax * wd.geom[5];
-                    double d2 = (px * px + py * py) + pz * pz;
-                    double T = wd.geom[6] + radA;
-                    touching = (ax <= hl && ax >= -hl) && d2 < T * T && d2 > 0.0;
-                    if (touching) {
-                        double d = sqrt(d2);
-                        nrm[0] = px / d;
-                        nrm[1] = py / d;
-                        nrm[2] = pz / d;
-                        delta = T - d;
-                        Rbar = (float)(radA * wd.geom[6] / (radA + wd.geom[6]));
-                    }
-                }
-                if (touching) {
-                    mbar = kA.mass;
-                    matB = (uint32_t)wd.mat;
-                    XB[0] = p[0];
-                    XB[1] = p[1];
-                    XB[2] = p[2];
-                    vB = f3((float)wd.vel[0], (float)wd.vel[1], (float)wd.vel[2]);
-                    wB = f3((float)wd.omega[0], (float)wd.omega[1], (float)wd.omega[2]);
-                }
-            }
-            if (!touching) {
-                hx[c] = 0.f;
-                hy[c] = 0.f;
-                hz[c] = 0.f;
-                if (a.rolling) hw[c] = 0.f;
+            ContactOut co;
+            contact_eval(a, sA, kA, xA, jarr[c], load_hist(hx, hy, hz, hw, c, a.rolling), co);
+            store_hist(hx, hy, hz, hw, c, co.h, a.rolling);
+            if (!co.touching) {
                 bF[c] = 0.f;
                 bF[cap + c] = 0.f;
                 bF[2 * cap + c] = 0.f;
@@ -179,77 +287,10 @@ __global__ void __launch_bounds__(TPB) k_force(DynArgs a, const uint32_t *start,
                 bT[2 * cap + c] = 0.f;
                 continue;
             }
-            // contact point in the middle of the overlap; arms to both owner centres
-            const double sc = radA - 0.5 * delta;
-            double cp[3] = {xA[0] - sc * nrm[0], xA[1] - sc * nrm[1], xA[2] - sc * nrm[2]};
-            const float3 armA = f3((float)(cp[0] - kA.X[0]), (float)(cp[1] - kA.X[1]), (float)(cp[2] - kA.X[2]));
-            const float3 armB = f3((float)(cp[0] - XB[0]), (float)(cp[1] - XB[1]), (float)(cp[2] - XB[2]));
-            const float3 n = f3((float)nrm[0], (float)nrm[1], (float)nrm[2]);
-            const MatPair mq = a.mat[(size_t)sA.mat * (size_t)a.n_mat + matB];
-            // relative velocity of A with respect to B at the contact point
-            // (linear parts first, so their difference is exact-ish)
-            const float3 rotA = cross3(kA.w, armA), rotB = cross3(wB, armB);
-            const float3 u = (kA.v - vB) + (rotA - rotB);
-            const float pn = dot3(u, n);
-            const float3 ut = u - pn * n;
-            float3 xi = f3(hx[c], hy[c], hz[c]);
-            xi = xi + hf * ut;
-            xi = xi - dot3(xi, n) * n;
-            const float df = (float)delta;
-            const float sqrtRd = sqrtf(Rbar * df);
-            const float Sn = 2.0f * mq.Estar * sqrtRd;
-            const float kn = (2.0f / 3.0f) * Sn;
-            const float c56 = 1.8257418583505538f;   // 2 sqrt(5/6)
-            const float gn = c56 * mq.beta * sqrtf(Sn * mbar);
-            float3 F = (kn * df + gn * pn) * n;
-            // rolling resistance: torque-only force C_rr |F_n| along the rolling
-            // part of the relative velocity, once the contact is older than
-            // the damped collision time of the simplified constants
-            float3 Fr = f3(0.f, 0.f, 0.f);
-            if (a.rolling) {
-                const float age = hw[c] + hf;
-                hw[c] = age;
-                if (mq.crr > 0.0f) {
-                    bool add = true;
-                    const float Reff = sqrtf(Rbar);
-                    const float kns = (4.0f / 3.0f) * mq.Estar * sqrtf(Reff);
-                    const float gns = -2.0f * sqrtf((5.0f / 3.0f) * mbar * mq.Estar) * mq.beta * sqrtf(sqrtf(Reff));
-                    const float dcf = gns / (2.0f * sqrtf(kns * mbar));
-                    if (dcf < 1.0f) {
-                        const float tcol = 3.14159265358979f * sqrtf(mbar / (kns * (1.0f - dcf * dcf)));
-                        if (age <= tcol) add = false;
-                    }
-                    if (add) {
-                        const float3 vr = rotB - rotA;
-                        const float vrn = sqrtf(dot3(vr, vr));
-                        if (vrn > 1e-12f) Fr = ((mq.crr * sqrtf(dot3(F, F))) / vrn) * vr;
-                    }
-                }
-            }
-            if (mq.mu > 0.0f) {
-                const float kt = 8.0f * mq.Gstar * sqrtRd;
-                const float gt = -c56 * mq.beta * sqrtf(mbar * kt);
-                float3 ft = (-kt) * xi - gt * ut;
-                const float ftn = sqrtf(dot3(ft, ft));
-                if (ftn > 1e-12f) {
-                    const float ftmax = sqrtf(dot3(F, F)) * mq.mu;
-                    if (ftn > ftmax) {
-                        ft = (ftmax / ftn) * ft;
-                        xi = (-1.0f / kt) * (ft + gt * ut);
-                    }
-                } else {
-                    ft = f3(0.f, 0.f, 0.f);
-                }
-                F = F + ft;
-            }
-            hx[c] = xi.x;
-            hy[c] = xi.y;
-            hz[c] = xi.z;
-            FA = FA + F;
-            const float3 Ft = F + Fr;
-            TA = TA + cross3(armA, Ft);
-            const float3 mF = f3(-F.x, -F.y, -F.z);
-            const float3 tB = cross3(armB, f3(-Ft.x, -Ft.y, -Ft.z));
+            FA = FA + co.F;
+            TA = TA + cross3(co.armA, co.Ft);
+            const float3 mF = f3(-co.F.x, -co.F.y, -co.F.z);
+            const float3 tB = cross3(co.armB, f3(-co.Ft.x, -co.Ft.y, -co.Ft.z));
             bF[c] = mF.x;
             bF[cap + c] = mF.y;
             bF[2 * cap + c] = mF.z;
@@ -266,9 +307,88 @@ __global__ void __launch_bounds__(TPB) k_force(DynArgs a, const uint32_t *start,
         aT[Ns + i] = TA.y;
         aT[2 * Ns + i] = TA.z;
     }
-    (void)No;
 }
 
+// Semi-implicit Euler for one owner: velocity (FP32), angular velocity
+// (world frame for single spheres, body frame for clumps, whose quaternion is
+// advanced in FP64 by the exponential map and written to qout; an unrotated
+// clump copies qin there unless the two are the same), FP64 position
+// re-encoded on the 2^-38 m grid.  Flags divergence; returns |v|^2.
+__device__ __forceinline__ float advance(const DynArgs &a, OwnerRec &r, const float *inv, bool rotating, float3 F,
+                                         float3 T, const double *qin, double *qout, DevCounters *ctr)
+{
+    const float hf = (float)a.h;
+    const float m = r.mass;
+    float3 v = f3(r.v[0], r.v[1], r.v[2]);
+    v = v + hf * f3(F.x / m + a.g[0], F.y / m + a.g[1], F.z / m + a.g[2]);
+    float3 w = f3(r.w[0], r.w[1], r.w[2]);
+    if (!rotating) {
+        w = w + hf * f3(T.x * inv[0], T.y * inv[1], T.z * inv[2]);
+    } else {
+        const double4 qv = *reinterpret_cast<const double4 *>(qin);
+        Mat3d R = rot_from_q(qv.x, qv.y, qv.z, qv.w);
+        // torque into the body frame: R^T T
+        const float tbx = (float)((R.m[0] * (double)T.x + R.m[3] * (double)T.y) + R.m[6] * (double)T.z);
+        const float tby = (float)((R.m[1] * (double)T.x + R.m[4] * (double)T.y) + R.m[7] * (double)T.z);
+        const float tbz = (float)((R.m[2] * (double)T.x + R.m[5] * (double)T.y) + R.m[8] * (double)T.z);
+        w = w + hf * f3(tbx * inv[0], tby * inv[1], tbz * inv[2]);
+        // q <- normalize(q (x) exp(h w / 2)) in FP64
+        const double th0 = a.h * (double)w.x, th1 = a.h * (double)w.y, th2 = a.h * (double)w.z;
+        const double ang = sqrt((th0 * th0 + th1 * th1) + th2 * th2);
+        if (ang > 0.0) {
+            const double sh = sin(0.5 * ang) / ang, ch = cos(0.5 * ang);
+            const double b0 = ch, b1q = sh * th0, b2 = sh * th1, b3 = sh * th2;
+            double n0 = qv.x * b0 - qv.y * b1q - qv.z * b2 - qv.w * b3;
+            double n1 = qv.x * b1q + qv.y * b0 + qv.z * b3 - qv.w * b2;
+            double n2 = qv.x * b2 - qv.y * b3 + qv.z * b0 + qv.w * b1q;
+            double n3 = qv.x * b3 + qv.y * b2 - qv.z * b1q + qv.w * b0;
+            const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2 + n3 * n3);
+            *reinterpret_cast<double4 *>(qout) = make_double4(n0 / nn, n1 / nn, n2 / nn, n3 / nn);
+        } else if (qout != qin) {
+            *reinterpret_cast<double4 *>(qout) = qv;
+        }
+    }
+    // position: FP64 update, re-encoded on the 2^-38 m grid
+    uint32_t iv[3];
+    for (int k = 0; k < 3; ++k) {
+        const float vk = k == 0 ? v.x : (k == 1 ? v.y : v.z);
+        const double X = decode_axis(r.vox, r.off[k], a.org.o[k], k) + a.h * (double)vk;
+        encode_axis(X, a.org.o[k], &iv[k], &r.off[k]);
+    }
+    r.vox = pack_vox(iv[0], iv[1], iv[2]);
+    r.v[0] = v.x;
+    r.v[1] = v.y;
+    r.v[2] = v.z;
+    r.w[0] = w.x;
+    r.w[1] = w.y;
+    r.w[2] = w.z;
+    const float v2 = dot3(v, v);
+    if (!(v2 == v2) || (a.v_err2 > 0.0f && v2 > a.v_err2) || !(dot3(w, w) == dot3(w, w)))
+        ctr->div[a.step & 1] = 1u;
+    return v2;
+}
+
+// Block-wide max of |v|^2 written to the block's slot (no atomics); the
+// maximum over blocks is reduced only when it is read.
+__device__ __forceinline__ void block_max_v2(float v2, float *slot)
+{
+    __shared__ float wmax[TPB / 64];
+    if (!(v2 == v2)) v2 = 3.0e38f;
+    for (int d = 32; d > 0; d >>= 1) v2 = fmaxf(v2, __shfl_xor(v2, d, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m = wmax[0];
+        for (int k = 1; k < TPB / 64; ++k) m = fmaxf(m, wmax[k]);
+        *slot = m;
+    }
+}
+
+// SINGLES: every owner is one sphere (sphere index == owner index), so the
+// owner's sphere range and template are not read and the inverse moment of
+// inertia is one isotropic value.  The owner state is loaded before the sums
+// so its latency overlaps theirs.
+template <bool SINGLES>
 __global__ void __launch_bounds__(TPB) k_fold_integrate(DynArgs a, const uint32_t *start,
                                                         const uint32_t *bstart,
                                                         const uint32_t *bidx, const float *aF,
@@ -286,8 +406,24 @@ __global__ void __launch_bounds__(TPB) k_fold_integrate(DynArgs a, const uint32_
         ctr->contact_steps += ctr->n_contacts[a.cur];
     }
     if (valid) {
+        OwnerRec r;
+        float inv[3];
+        int32_t tmpl = -1;
+        if (integrate) {
+            r = load_rec(a.rec + o);
+            if (SINGLES) {
+                inv[0] = inv[1] = inv[2] = a.inv_i[o];
+            } else {
+                const OwnerAux ax = a.aux[o];
+                inv[0] = ax.inv_moi[0];
+                inv[1] = ax.inv_moi[1];
+                inv[2] = ax.inv_moi[2];
+                tmpl = ax.tmpl;
+            }
+        }
         float3 F = f3(0.f, 0.f, 0.f), T = f3(0.f, 0.f, 0.f);
-        const uint32_t s0 = a.own_sph0[o], s1 = a.own_sph0[o + 1];
+        const uint32_t s0 = SINGLES ? (uint32_t)o : a.own_sph0[o];
+        const uint32_t s1 = SINGLES ? (uint32_t)o + 1u : a.own_sph0[o + 1];
         for (uint32_t s = s0; s < s1; ++s) {
             if (start[s] != start[s + 1]) {
                 F = F + f3(aF[s], aF[Ns + s], aF[2 * Ns + s]);
@@ -308,72 +444,117 @@ __global__ void __launch_bounds__(TPB) k_fold_integrate(DynArgs a, const uint32_
             To[No + o] = T.y;
             To[2 * No + o] = T.z;
         } else {
-            OwnerRec r = load_rec(a.rec + o);
-            const OwnerAux ax = a.aux[o];
-            const float hf = (float)a.h;
-            const float m = r.mass;
-            float3 v = f3(r.v[0], r.v[1], r.v[2]);
-            v = v + hf * f3(F.x / m + a.g[0], F.y / m + a.g[1], F.z / m + a.g[2]);
-            float3 w = f3(r.w[0], r.w[1], r.w[2]);
-            if (ax.tmpl < 0) {
-                w = w + hf * f3(T.x * ax.inv_moi[0], T.y * ax.inv_moi[1], T.z * ax.inv_moi[2]);
-            } else {
-                double *qp = a.q + 4 * (size_t)o;
-                double4 qv = *reinterpret_cast<const double4 *>(qp);
-                Mat3d R = rot_from_q(qv.x, qv.y, qv.z, qv.w);
-                // torque into the body frame: R^T T
-                const float tbx = (float)((R.m[0] * (double)T.x + R.m[3] * (double)T.y) + R.m[6] * (double)T.z);
-                const float tby = (float)((R.m[1] * (double)T.x + R.m[4] * (double)T.y) + R.m[7] * (double)T.z);
-                const float tbz = (float)((R.m[2] * (double)T.x + R.m[5] * (double)T.y) + R.m[8] * (double)T.z);
-                w = w + hf * f3(tbx * ax.inv_moi[0], tby * ax.inv_moi[1], tbz * ax.inv_moi[2]);
-                // q <- normalize(q (x) exp(h w / 2)) in FP64
-                const double th0 = a.h * (double)w.x, th1 = a.h * (double)w.y, th2 = a.h * (double)w.z;
-                const double ang = sqrt((th0 * th0 + th1 * th1) + th2 * th2);
-                if (ang > 0.0) {
-                    const double sh = sin(0.5 * ang) / ang, ch = cos(0.5 * ang);
-                    const double b0 = ch, b1q = sh * th0, b2 = sh * th1, b3 = sh * th2;
-                    double n0 = qv.x * b0 - qv.y * b1q - qv.z * b2 - qv.w * b3;
-                    double n1 = qv.x * b1q + qv.y * b0 + qv.z * b3 - qv.w * b2;
-                    double n2 = qv.x * b2 - qv.y * b3 + qv.z * b0 + qv.w * b1q;
-                    double n3 = qv.x * b3 + qv.y * b2 - qv.z * b1q + qv.w * b0;
-                    const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2 + n3 * n3);
-                    *reinterpret_cast<double4 *>(qp) = make_double4(n0 / nn, n1 / nn, n2 / nn, n3 / nn);
-                }
-            }
-            // position: FP64 update, re-encoded on the 2^-38 m grid
-            uint32_t iv[3];
-            for (int k = 0; k < 3; ++k) {
-                const float vk = k == 0 ? v.x : (k == 1 ? v.y : v.z);
-                const double X = decode_axis(r.vox, r.off[k], a.org.o[k], k) + a.h * (double)vk;
-                encode_axis(X, a.org.o[k], &iv[k], &r.off[k]);
-            }
-            r.vox = pack_vox(iv[0], iv[1], iv[2]);
-            r.v[0] = v.x;
-            r.v[1] = v.y;
-            r.v[2] = v.z;
-            r.w[0] = w.x;
-            r.w[1] = w.y;
-            r.w[2] = w.z;
+            v2 = advance(a, r, inv, !SINGLES && tmpl >= 0, F, T, a.q + 4 * (size_t)o, a.q + 4 * (size_t)o, ctr);
             store_rec(a.rec + o, r);
-            v2 = dot3(v, v);
-            if (!(v2 == v2) || (a.v_err2 > 0.0f && v2 > a.v_err2) || !(dot3(w, w) == dot3(w, w)))
-                ctr->div[a.step & 1] = 1u;
         }
     }
-    if (integrate) {
-        // block-wide max of |v|^2 written to this block's slot (no atomics);
-        // the maximum over blocks is reduced only when it is read
-        __shared__ float wmax[TPB / 64];
-        if (!(v2 == v2)) v2 = 3.0e38f;
-        for (int d = 32; d > 0; d >>= 1) v2 = fmaxf(v2, __shfl_xor(v2, d, 64));
-        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v2;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            float m = wmax[0];
-            for (int k = 1; k < TPB / 64; ++k) m = fmaxf(m, wmax[k]);
-            a.blkmax[blockIdx.x] = m;
+    if (integrate) block_max_v2(v2, a.blkmax + blockIdx.x);
+}
+
+// One whole step per owner.  Its spheres' A rows are evaluated (history
+// written to the second buffer); each B-list entry is evaluated again from
+// its A sphere with the same function (reading the history before the step),
+// so the owner needs no reaction written by another thread.  The sums run in
+// the order of the two-kernel path -- per sphere the A-row sum, then the
+// B-side reactions by ascending contact index -- and the integration is the
+// same, so both paths give the same bits.  Reads (a.rec, a.q, history),
+// writes (rec_out, q_out, second history): no thread reads what another
+// writes.  When the step is stopped (capacity or divergence) the state and
+// history are copied unchanged.
+template <bool SINGLES>
+__global__ void __launch_bounds__(TPB) k_step_fused(DynArgs a, OwnerRec *rec_out, double *q_out,
+                                                    const uint32_t *start, const uint32_t *jarr,
+                                                    const uint32_t *bstart, const uint32_t *bidx,
+                                                    const uint32_t *bsrc, const float *hx, const float *hy,
+                                                    const float *hz, const float *hw, float *ox, float *oy,
+                                                    float *oz, float *ow, int64_t cap, DevCounters *ctr)
+{
+    const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t o = (int64_t)lb * blockDim.x + threadIdx.x;
+    const int64_t No = a.n_owners;
+    const bool valid = o < No;
+    if (stopped(ctr, a.step)) {
+        if (valid) {
+            store_rec(rec_out + o, load_rec(a.rec + o));
+            if (!SINGLES)
+                *reinterpret_cast<double4 *>(q_out + 4 * (size_t)o) =
+                    *reinterpret_cast<const double4 *>(a.q + 4 * (size_t)o);
+            // (a set that overflowed its capacity has no valid rows to copy)
+            const uint32_t s0 = SINGLES ? (uint32_t)o : a.own_sph0[o];
+            const uint32_t s1 = SINGLES ? (uint32_t)o + 1u : a.own_sph0[o + 1];
+            if ((int64_t)start[a.n_spheres] <= cap)
+                for (uint32_t c = start[s0]; c < start[s1]; ++c)
+                    store_hist(ox, oy, oz, ow, c, load_hist(hx, hy, hz, hw, c, a.rolling), a.rolling);
         }
+        return;
     }
+    if (o == 0) {
+        ctr->last_step_done = a.step + 1;
+        ctr->contact_steps += ctr->n_contacts[a.cur];
+    }
+    float v2 = 0.0f;
+    if (valid) {
+        OwnerRec r = load_rec(a.rec + o);
+        float inv[3];
+        int32_t tmpl = -1;
+        if (SINGLES) {
+            inv[0] = inv[1] = inv[2] = a.inv_i[o];
+        } else {
+            const OwnerAux ax = a.aux[o];
+            inv[0] = ax.inv_moi[0];
+            inv[1] = ax.inv_moi[1];
+            inv[2] = ax.inv_moi[2];
+            tmpl = ax.tmpl;
+        }
+        float3 F = f3(0.f, 0.f, 0.f), T = f3(0.f, 0.f, 0.f);
+        const uint32_t s0 = SINGLES ? (uint32_t)o : a.own_sph0[o];
+        const uint32_t s1 = SINGLES ? (uint32_t)o + 1u : a.own_sph0[o + 1];
+        for (uint32_t s = s0; s < s1; ++s) {
+            const uint32_t c0 = start[s], c1 = start[s + 1];
+            const uint32_t b0 = bstart[s], b1 = bstart[s + 1];
+            if (c0 < c1) {
+                const SphRec sS = load_sph(a.sph + s);
+                OwnerKin kS;
+                double xS[3];
+                owner_kin(r, sS, a.aux, a.q, a.tpos, a.org, kS, xS);
+                float3 FA = f3(0.f, 0.f, 0.f), TA = f3(0.f, 0.f, 0.f);
+                for (uint32_t c = c0; c < c1; ++c) {
+                    ContactOut co;
+                    contact_eval(a, sS, kS, xS, jarr[c], load_hist(hx, hy, hz, hw, c, a.rolling), co);
+                    store_hist(ox, oy, oz, ow, c, co.h, a.rolling);
+                    if (!co.touching) continue;
+                    FA = FA + co.F;
+                    TA = TA + cross3(co.armA, co.Ft);
+                }
+                F = F + FA;
+                T = T + TA;
+            }
+            for (uint32_t b = b0; b < b1; ++b) {
+                const uint32_t c = bidx[b], i = bsrc[b];
+                const SphRec sI = load_sph(a.sph + i);
+                const OwnerRec rI = load_rec(a.rec + sI.owner);
+                OwnerKin kI;
+                double xI[3];
+                owner_kin(rI, sI, a.aux, a.q, a.tpos, a.org, kI, xI);
+                ContactOut co;
+                contact_eval(a, sI, kI, xI, s, load_hist(hx, hy, hz, hw, c, a.rolling), co);
+                float3 mF = f3(0.f, 0.f, 0.f), tB = f3(0.f, 0.f, 0.f);
+                if (co.touching) {
+                    mF = f3(-co.F.x, -co.F.y, -co.F.z);
+                    tB = cross3(co.armB, f3(-co.Ft.x, -co.Ft.y, -co.Ft.z));
+                }
+                F = F + mF;
+                T = T + tB;
+            }
+        }
+        const bool rotating = !SINGLES && tmpl >= 0;
+        const double *qin = a.q + 4 * (size_t)o;
+        double *qo = q_out + 4 * (size_t)o;
+        v2 = advance(a, r, inv, rotating, F, T, qin, qo, ctr);
+        if (!SINGLES && !rotating) *reinterpret_cast<double4 *>(qo) = *reinterpret_cast<const double4 *>(qin);
+        store_rec(rec_out + o, r);
+    }
+    block_max_v2(v2, a.blkmax + lb);
 }
 
 }  // namespace
@@ -409,10 +590,22 @@ void launch_force(const DynArgs &a, AcsBuf &cur, StepBufs &sb, DevCounters *ctr,
                           sb.cap, (const DevCounters *)ctr);
 }
 
+void launch_step_fused(const DynArgs &a, OwnerRec *rec_out, double *q_out, const AcsBuf &cur, int64_t cap,
+                       DevCounters *ctr, hipStream_t s)
+{
+    auto kern = a.has_clumps ? k_step_fused<false> : k_step_fused<true>;
+    hipLaunchKernelGGL(kern, dim3(nblocks(a.n_owners)), dim3(TPB), 0, s, a, rec_out, q_out,
+                       (const uint32_t *)cur.start, (const uint32_t *)cur.j, (const uint32_t *)cur.bstart,
+                       (const uint32_t *)cur.bidx, (const uint32_t *)cur.bsrc, (const float *)cur.hx,
+                       (const float *)cur.hy, (const float *)cur.hz, (const float *)cur.hw, cur.hx2, cur.hy2,
+                       cur.hz2, cur.hw2, cap, ctr);
+}
+
 void launch_fold_integrate(const DynArgs &a, const AcsBuf &cur, StepBufs &sb, DevCounters *ctr,
                            int integrate, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
-    hipExtLaunchKernelGGL(k_fold_integrate, dim3(nblocks(a.n_owners)), dim3(TPB), 0, s, ev0, ev1, 0, a,
+    auto kern = a.has_clumps ? k_fold_integrate<false> : k_fold_integrate<true>;
+    hipExtLaunchKernelGGL(kern, dim3(nblocks(a.n_owners)), dim3(TPB), 0, s, ev0, ev1, 0, a,
                           (const uint32_t *)cur.start, (const uint32_t *)cur.bstart, (const uint32_t *)cur.bidx,
                           (const float *)sb.aF, (const float *)sb.aT, (const float *)sb.bF, (const float *)sb.bT,
                           sb.cap, sb.Fo, sb.To, integrate, ctr);

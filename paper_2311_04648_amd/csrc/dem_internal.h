@@ -92,7 +92,7 @@ struct DevCounters {
 };
 
 struct ScanTmp {
-    uint32_t *partials;  // >= ceil(n/4096)+1 entries
+    uint32_t *partials;  // >= 2 scan_tmp_elems(n) entries
 };
 
 // ---------------------------------------------------------------------------
@@ -107,6 +107,12 @@ void launch_copy_u32(uint32_t *dst, const uint32_t *src, int64_t n, hipStream_t 
 void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *partials,
                         hipStream_t s, uint32_t *out2 = nullptr, DevCounters *ctr = nullptr,
                         int64_t cap = 0, int buf = 0);
+// two scans of the same length in one pair of launches (partials holds
+// 2 scan_tmp_elems(n) entries); the first may check its total against cap
+void scan_exclusive_u32_pair(const uint32_t *in0, uint32_t *out0, uint32_t *out0b, DevCounters *ctr, int64_t cap,
+                             int buf, const uint32_t *in1, uint32_t *out1, uint32_t *out1b, int64_t n,
+                             uint32_t *partials, hipStream_t s);
+void launch_zero3(uint32_t *p0, int64_t n0, uint32_t *p1, int64_t n1, uint32_t *p2, int64_t n2, hipStream_t s);
 int64_t radix_hist_elems(int64_t n);
 // stable LSD radix sort of (keys, vals) on the low `bits` bits; the buffer
 // pairs are swapped as needed so the result ends in (*keys, *vals); the alt
@@ -146,15 +152,35 @@ struct AcsBuf {
     uint32_t *j;       // [cap]
     float *hx, *hy, *hz;
     float *hw;         // contact age (tracked only with rolling resistance)
+    // second history buffer: the fused step reads (hx..hw) and writes these,
+    // then the two are swapped
+    float *hx2, *hy2, *hz2, *hw2;
     uint32_t *bstart;  // [Ns+1]
-    uint32_t *bidx;    // [cap]
+    uint32_t *bidx;    // [cap] contact index of each B-list entry
+    uint32_t *bsrc;    // [cap] the A sphere of that contact
     uint32_t *bcur;    // [Ns+1] scratch cursor
 };
 
-void launch_bin(const DetectArgs &a, CdWork &w, hipStream_t s);
+inline void swap_hist(AcsBuf &b)
+{
+    float *t;
+    t = b.hx; b.hx = b.hx2; b.hx2 = t;
+    t = b.hy; b.hy = b.hy2; b.hy2 = t;
+    t = b.hz; b.hz = b.hz2; b.hz2 = t;
+    t = b.hw; b.hw = b.hw2; b.hw2 = t;
+}
+
+void launch_bin(const DetectArgs &a, CdWork &w, hipStream_t s, uint32_t *z1 = nullptr, int64_t n1 = 0,
+                uint32_t *z2 = nullptr, int64_t n2 = 0);
 // full detection into `out` (count, scan, write, sort rows, B lists)
 void launch_detect(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap, DevCounters *ctr,
                    int buf, hipStream_t s);
+// the same in two parts: the front reads the owner state (centres, bin
+// keys, candidate records, bin counts); the back reads only what the front
+// wrote, so it may run on another stream after an event
+void launch_detect_front(const DetectArgs &a, CdWork &w, AcsBuf &out, hipStream_t s);
+void launch_detect_back(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap, DevCounters *ctr,
+                        int buf, hipStream_t s);
 void launch_judge(const DetectArgs &a, CdWork &w, const AcsBuf &cur, int64_t cap, DevCounters *ctr,
                   hipStream_t s);
 void launch_blists(AcsBuf &b, int64_t n_spheres, int64_t cap, uint32_t *partials, hipStream_t s);
@@ -165,6 +191,7 @@ struct DynArgs {
     OwnerRec *rec;
     double *q;
     const OwnerAux *aux;
+    const float *inv_i;     // per owner: isotropic inverse moment of inertia (single spheres)
     const uint32_t *own_sph0;
     const SphRec *sph;
     const float *tpos;
@@ -196,6 +223,11 @@ void launch_force(const DynArgs &a, AcsBuf &cur, StepBufs &sb, DevCounters *ctr,
                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_fold_integrate(const DynArgs &a, const AcsBuf &cur, StepBufs &sb, DevCounters *ctr,
                            int integrate, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// one fused step (forces of both sides, ordered sums, integration): reads
+// a.rec / a.q and cur's history, writes rec_out / q_out and cur's second
+// history buffer; the caller swaps both afterwards
+void launch_step_fused(const DynArgs &a, OwnerRec *rec_out, double *q_out, const AcsBuf &cur, int64_t cap,
+                       DevCounters *ctr, hipStream_t s);
 // an empty one-wave kernel stamped with events (overhead of the stamps)
 void launch_noop(hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 // max |v|^2 of the last integration into ctr->maxv2[0]

@@ -1,18 +1,25 @@
 // Scan and stable LSD radix sort for gfx950 (wave64).
 //
-// Scan: three phases (tile sums, one-block scan of the tile sums, tile
-// scan + offset), deterministic.  Radix sort: 8-bit digits; per pass an
+// Scan: tile sums, then tile scan + offset, deterministic.  A tile is 1024
+// values, four per thread loaded and stored as one 16-byte vector (a wave
+// touches 1 KiB contiguously).  With few tiles each block adds up the tile
+// sums before it itself; with many, a one-block pass scans the tile sums
+// in between.  Radix sort: 8-bit digits; per pass an
 // up-sweep histogram per 2048-key tile (LDS atomics), a digit-major scan of
 // the histograms, and a down-sweep that ranks keys stably inside the tile
 // with wave64 ballots (match-by-digit from 8 ballots, popcount of the lower
 // lanes) and per-wave digit counts in LDS.
 #include "dem_internal.h"
 
+#include <algorithm>
+
 namespace {
 
 constexpr int SCAN_THREADS = 256;
-constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_ITEMS = 4;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+constexpr int64_t SCAN_DIRECT_TILES = 2048;   // up to this many tiles: no separate pass over tile sums
+constexpr int SPINE_THREADS = 1024;
 
 constexpr int RADIX_THREADS = 256;
 constexpr int RADIX_ITEMS = 8;
@@ -57,6 +64,17 @@ __global__ void __launch_bounds__(256) k_fill(uint32_t *p, int64_t n, uint32_t v
     for (; i < n; i += stride) p[i] = v;
 }
 
+// Zero-fills up to three arrays in one launch (blockIdx.y picks the array).
+__global__ void __launch_bounds__(256) k_zero3(uint32_t *p0, int64_t n0, uint32_t *p1, int64_t n1, uint32_t *p2,
+                                               int64_t n2)
+{
+    uint32_t *p = blockIdx.y == 0 ? p0 : (blockIdx.y == 1 ? p1 : p2);
+    const int64_t n = blockIdx.y == 0 ? n0 : (blockIdx.y == 1 ? n1 : n2);
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = 0u;
+}
+
 __global__ void __launch_bounds__(256) k_copy(uint32_t *d, const uint32_t *s, int64_t n)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -64,71 +82,123 @@ __global__ void __launch_bounds__(256) k_copy(uint32_t *d, const uint32_t *s, in
     for (; i < n; i += stride) d[i] = s[i];
 }
 
-__global__ void __launch_bounds__(SCAN_THREADS) k_scan_reduce(const uint32_t *in, int64_t n,
-                                                              uint32_t *partials)
+// Loads the four values at i..i+3 (i a multiple of 4, the array 16-byte
+// aligned); values at or past n read as 0.
+__device__ inline uint4 load4(const uint32_t *in, int64_t i, int64_t n)
 {
-    int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        int64_t i = base + (int64_t)k * SCAN_THREADS + threadIdx.x;
-        if (i < n) s += in[i];
-    }
-    uint32_t tot;
-    block_excl_scan(s, &tot);
-    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+    if (i + 3 < n) return *reinterpret_cast<const uint4 *>(in + i);
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (i < n) v.x = in[i];
+    if (i + 1 < n) v.y = in[i + 1];
+    if (i + 2 < n) v.z = in[i + 2];
+    return v;
 }
 
-// Tile scan + offset.  Each block adds up the sums of the tiles before it
-// (strided over its threads, then a block reduction; integer sums are exact
-// in any order), so no separate pass over the tile sums is needed.  Also
-// writes out[n] = total, an optional copy of the result, and an optional
-// capacity check of the total.
-__global__ void __launch_bounds__(SCAN_THREADS) k_scan_down(const uint32_t *in, uint32_t *out,
-                                                            uint32_t *out2, int64_t n,
-                                                            const uint32_t *partials, int64_t nb,
-                                                            DevCounters *ctr, int64_t cap, int buf)
+__device__ inline void store4(uint32_t *out, int64_t i, int64_t n, uint4 v)
+{
+    if (i + 3 < n) {
+        *reinterpret_cast<uint4 *>(out + i) = v;
+        return;
+    }
+    if (i < n) out[i] = v.x;
+    if (i + 1 < n) out[i + 1] = v.y;
+    if (i + 2 < n) out[i + 2] = v.z;
+}
+
+// One scan of a launch; a launch scans one or two arrays of the same
+// length (blockIdx.y picks the job).
+struct ScanJob {
+    const uint32_t *in;
+    uint32_t *out, *out2;    // out2: optional copy of the result
+    uint32_t *partials;      // tile sums of this job
+    DevCounters *ctr;        // optional capacity check of the total
+    int64_t cap;
+    int buf;
+};
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_reduce(ScanJob j0, ScanJob j1, int64_t n)
+{
+    const ScanJob &j = blockIdx.y == 0 ? j0 : j1;
+    const uint4 v = load4(j.in, (int64_t)blockIdx.x * SCAN_TILE + 4 * (int64_t)threadIdx.x, n);
+    uint32_t tot;
+    block_excl_scan((v.x + v.y) + (v.z + v.w), &tot);
+    if (threadIdx.x == 0) j.partials[blockIdx.x] = tot;
+}
+
+// One block per job: partials[0..nb) <- their exclusive prefix sums.
+__global__ void __launch_bounds__(SPINE_THREADS) k_scan_spine(ScanJob j0, ScanJob j1, int64_t nb)
+{
+    __shared__ uint32_t wsum[SPINE_THREADS / 64];
+    uint32_t *partials = blockIdx.y == 0 ? j0.partials : j1.partials;
+    const int64_t per = (nb + SPINE_THREADS - 1) / SPINE_THREADS;
+    const int64_t b0 = (int64_t)threadIdx.x * per;
+    uint32_t s = 0;
+    for (int64_t b = b0; b < b0 + per && b < nb; ++b) s += partials[b];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t inc = s;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t u = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += u;
+    }
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int k = 0; k < wid; ++k) off += wsum[k];
+    uint32_t run = inc - s + off;
+    for (int64_t b = b0; b < b0 + per && b < nb; ++b) {
+        const uint32_t x = partials[b];
+        partials[b] = run;
+        run += x;
+    }
+}
+
+// Tile scan + offset.  The tile is loaded first; its offset is either the
+// sum of the tile sums before it (few tiles: strided over the threads, then
+// a block reduction; integer sums are exact in any order) or, after the
+// spine pass, partials[blockIdx.x].  Also writes out[n] = total, the
+// optional copy, and the optional capacity check of the total.
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_down(ScanJob j0, ScanJob j1, int64_t n, int64_t nb,
+                                                            int spine)
 {
     __shared__ uint32_t red[SCAN_THREADS / 64];
+    const ScanJob &j = blockIdx.y == 0 ? j0 : j1;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + 4 * (int64_t)threadIdx.x;
+    const uint4 v = load4(j.in, base, n);
     uint32_t pre = 0;
-    for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += SCAN_THREADS) pre += partials[b];
-    for (int d = 32; d > 0; d >>= 1) pre += __shfl_xor(pre, d, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = pre;
-    __syncthreads();
-    pre = 0;
+    if (spine) {
+        pre = j.partials[blockIdx.x];
+    } else {
+        for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += SCAN_THREADS) pre += j.partials[b];
+        for (int d = 32; d > 0; d >>= 1) pre += __shfl_xor(pre, d, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = pre;
+        __syncthreads();
+        pre = 0;
 #pragma unroll
-    for (int k = 0; k < SCAN_THREADS / 64; ++k) pre += red[k];
-    int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
-    uint32_t v[SCAN_ITEMS];
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        int64_t i = base + k;
-        v[k] = (i < n) ? in[i] : 0u;
-        s += v[k];
+        for (int k = 0; k < SCAN_THREADS / 64; ++k) pre += red[k];
     }
+    const uint32_t s = (v.x + v.y) + (v.z + v.w);
     uint32_t tot;
-    uint32_t ex = block_excl_scan(s, &tot) + pre;
-#pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        int64_t i = base + k;
-        if (i < n) {
-            out[i] = ex;
-            if (out2) out2[i] = ex;
-        }
-        ex += v[k];
-    }
+    const uint32_t ex = block_excl_scan(s, &tot) + pre;
+    uint4 o;
+    o.x = ex;
+    o.y = o.x + v.x;
+    o.z = o.y + v.y;
+    o.w = o.z + v.z;
+    store4(j.out, base, n, o);
+    if (j.out2) store4(j.out2, base, n, o);
     if (blockIdx.x == nb - 1 && threadIdx.x == SCAN_THREADS - 1) {
-        // ex is now the grand total (last thread of the last tile)
-        out[n] = ex;
-        if (out2) out2[n] = ex;
-        if (ctr) {
-            ctr->n_contacts[buf] = ex;
-            if ((int64_t)ex > cap) {
-                ctr->overflow[buf] = 1u;
-                atomicMax(&ctr->required, ex);
+        // the last thread of the last tile (values past n read as 0)
+        const uint32_t total = ex + s;
+        j.out[n] = total;
+        if (j.out2) j.out2[n] = total;
+        if (j.ctr) {
+            j.ctr->n_contacts[j.buf] = total;
+            if ((int64_t)total > j.cap) {
+                j.ctr->overflow[j.buf] = 1u;
+                atomicMax(&j.ctr->required, total);
             } else {
-                ctr->overflow[buf] = 0u;
+                j.ctr->overflow[j.buf] = 0u;
             }
         }
     }
@@ -223,24 +293,53 @@ void launch_fill_u32(uint32_t *p, int64_t n, uint32_t value, hipStream_t s)
     hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n, value);
 }
 
+void launch_zero3(uint32_t *p0, int64_t n0, uint32_t *p1, int64_t n1, uint32_t *p2, int64_t n2, hipStream_t s)
+{
+    const int64_t m = std::max(n0, std::max(n1, n2));
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_zero3, dim3(grid_for(m, 256, 4096), 3), dim3(256), 0, s, p0, p0 ? n0 : 0, p1,
+                       p1 ? n1 : 0, p2, p2 ? n2 : 0);
+}
+
 void launch_copy_u32(uint32_t *dst, const uint32_t *src, int64_t n, hipStream_t s)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_copy, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, dst, src, n);
 }
 
+static void scan_jobs(const ScanJob &j0, const ScanJob &j1, int njobs, int64_t n, hipStream_t s)
+{
+    const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb == 0) {
+        launch_fill_u32(j0.out, 1, 0u, s);
+        if (j0.out2) launch_fill_u32(j0.out2, 1, 0u, s);
+        if (njobs > 1) {
+            launch_fill_u32(j1.out, 1, 0u, s);
+            if (j1.out2) launch_fill_u32(j1.out2, 1, 0u, s);
+        }
+        return;
+    }
+    const dim3 grid((unsigned)nb, (unsigned)njobs);
+    hipLaunchKernelGGL(k_scan_reduce, grid, dim3(SCAN_THREADS), 0, s, j0, j1, n);
+    const int spine = nb > SCAN_DIRECT_TILES ? 1 : 0;
+    if (spine) hipLaunchKernelGGL(k_scan_spine, dim3(1, (unsigned)njobs), dim3(SPINE_THREADS), 0, s, j0, j1, nb);
+    hipLaunchKernelGGL(k_scan_down, grid, dim3(SCAN_THREADS), 0, s, j0, j1, n, nb, spine);
+}
+
 void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *partials,
                         hipStream_t s, uint32_t *out2, DevCounters *ctr, int64_t cap, int buf)
 {
-    int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
-    if (nb == 0) {
-        launch_fill_u32(out, 1, 0u, s);
-        if (out2) launch_fill_u32(out2, 1, 0u, s);
-        return;
-    }
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, in, n, partials);
-    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, in, out, out2, n,
-                       partials, nb, ctr, cap, buf);
+    ScanJob j{in, out, out2, partials, ctr, cap, buf};
+    scan_jobs(j, j, 1, n, s);
+}
+
+void scan_exclusive_u32_pair(const uint32_t *in0, uint32_t *out0, uint32_t *out0b, DevCounters *ctr, int64_t cap,
+                             int buf, const uint32_t *in1, uint32_t *out1, uint32_t *out1b, int64_t n,
+                             uint32_t *partials, hipStream_t s)
+{
+    ScanJob j0{in0, out0, out0b, partials, ctr, cap, buf};
+    ScanJob j1{in1, out1, out1b, partials + scan_tmp_elems(n), nullptr, 0, 0};
+    scan_jobs(j0, j1, 2, n, s);
 }
 
 void radix_sort_u32(uint32_t **keys, uint32_t **vals, uint32_t **keys_alt, uint32_t **vals_alt,

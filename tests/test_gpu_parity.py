@@ -284,6 +284,41 @@ def test_one_step_matches_oracle(dem, name):
         assert np.all(np.linalg.norm(dq_g - dq_o, axis=1) <= tol_q)
 
 
+def _fused_case(name):
+    if name == "rolling":
+        s = W.small_spheres(23, n=512, vel=0.3)
+        s.mat_crr[:] = 0.1
+        return s
+    if name == "clumps_dense":
+        return W.small_clumps(6, n=300, vel=0.3, with_cylinder=True, spacing=0.0080)
+    return SYS[name]
+
+
+@pytest.mark.parametrize("name", ["cluster", "spheres", "clumps", "clumps_dense", "spheres_ragged", "rolling"])
+def test_fused_step_equals_two_kernel_path_bitwise(dem, name):
+    """The fused step (each owner re-evaluates its B-side contacts with the
+    same function) gives the bits of the two-kernel path (per-contact
+    reactions written, then the ordered fold): state, contact set and
+    history, over a delayed schedule on two streams."""
+    import torch
+    s = _fused_case(name)
+    out = []
+    for path in (0, 1):
+        c = dem.DemContext(s, mode="fixed", k=5, lam=2, dyn_path=path)
+        c.set_state()
+        c.step(120, dyn=torch.cuda.Stream(), kin=torch.cuda.Stream())
+        g = c.get_state()
+        keys, hist = c.get_contacts()
+        out.append((g, keys, hist))
+        c.close()
+    (ga, ka, ha), (gb, kb, hb) = out
+    assert ka.size > 0
+    for k in ("X", "V", "W", "q"):
+        np.testing.assert_array_equal(ga[k], gb[k])
+    np.testing.assert_array_equal(ka, kb)
+    np.testing.assert_array_equal(ha, hb)
+
+
 def test_delayed_equals_every_step_bitwise(dem):
     """Sec. 2.1: delayed detection with a sufficient margin reproduces the
     every-step trajectory exactly (false positives add exact zeros, the
@@ -385,9 +420,10 @@ def test_capacity_error_reports_required_size(dem):
     assert ctx.detect_contacts(0.0) == need
 
 
-def test_capacity_overflow_during_steps_stops(dem):
+@pytest.mark.parametrize("dyn_path", [0, 1])
+def test_capacity_overflow_during_steps_stops(dem, dyn_path):
     s = W.small_spheres(1, n=343)
-    ctx = dem.DemContext(s, mode="every", capacity=20)
+    ctx = dem.DemContext(s, mode="every", capacity=20, dyn_path=dyn_path)
     ctx.set_state()
     with pytest.raises(dem.DemError) as e:
         ctx.step(5)
@@ -396,9 +432,10 @@ def test_capacity_overflow_during_steps_stops(dem):
     np.testing.assert_array_equal(g["X"], s.X)
 
 
-def test_divergence_guard(dem):
+@pytest.mark.parametrize("dyn_path", [0, 1])
+def test_divergence_guard(dem, dyn_path):
     s = W.small_spheres(1, n=343, vel=0.5)
-    ctx = dem.DemContext(s, mode="every", v_error_out=0.05)
+    ctx = dem.DemContext(s, mode="every", v_error_out=0.05, dyn_path=dyn_path)
     ctx.set_state()
     with pytest.raises(dem.DemError) as e:
         ctx.step(5)
