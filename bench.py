@@ -245,7 +245,8 @@ def main():
     # every event pair around the dynamics kernel(s) is followed by an empty
     # one-wave kernel bracketed the same way: its interval is the markers'
     # own overhead, paid once per pair (the fused kernel is timed in runs of
-    # up to 8 back-to-back launches per pair)
+    # 4 back-to-back launches per pair, placed evenly over the schedule's
+    # quiet stretches)
     n_noop = max(int(st["stage_n"][4]), 1)
     stamp_ms = tot[4] / n_noop
     avg_ms = max((tot[dom] - tot[4]) / n_launch, 1e-6)

@@ -166,9 +166,9 @@ typedef struct {
      * measured with HIP events on the stream the stage runs on:
      * [0] force kernel and [1] fold + integrate kernel of the two-kernel
      * dynamics (one event pair per kernel, every `timing`-th step), or [1]
-     * the fused step kernel (runs of up to 8 back-to-back launches between
-     * one event pair, a run opened every `timing`-th step on steps with no
-     * other dynamics-stream work); [2] contact detection (bin, sort,
+     * the fused step kernel (runs of 4 back-to-back launches between one
+     * event pair, one run per `timing` steps, placed where the next 4 steps
+     * have no other dynamics-stream work); [2] contact detection (bin, sort,
      * detect, B lists); [3] history remap; [4] an empty one-wave kernel
      * bracketed like [0]/[1] (one per event pair of [0]/[1]: the markers'
      * own overhead, so stage_ms[1] - stage_ms[4] is kernel time) */

@@ -93,6 +93,7 @@ struct dem_ctx {
     };
     TimedPair *run = nullptr;   // open run of timed back-to-back dynamics launches
     int run_len = 0;
+    bool run_due = false;       // a sampling mark passed; open a run when possible
     std::vector<TimedPair> ring;
     size_t ring_pos = 0;
     double stage_ms[5] = {0, 0, 0, 0, 0};
@@ -333,11 +334,16 @@ void stage_end(dem_ctx::TimedPair *p, hipStream_t s)
     if (p) hipEventRecord(p->b, s);
 }
 
-// Runs of up to RUN_LAUNCHES back-to-back fused dynamics launches are timed
-// with one pair of marker events (their overhead is paid once per run and
+// Runs of RUN_LAUNCHES back-to-back fused dynamics launches are timed with
+// one pair of marker events (their overhead is paid once per run and
 // measured by an empty kernel bracketed the same way right after the run).
-// A run is closed before any other work is enqueued on the dynamics stream.
-constexpr int RUN_LAUNCHES = 8;
+// After each sampling mark (every `timing` steps) a run opens at the first
+// step followed by RUN_LAUNCHES - 1 steps with no other dynamics-stream work,
+// so runs cover whole quiet stretches of the schedule and sample its phases
+// evenly.  With detection on the dynamics stream every step (every-step or
+// judged runs) a run is the one launch of a sampled step.  A run is closed
+// before any other work is enqueued on the dynamics stream.
+constexpr int RUN_LAUNCHES = 4;
 
 void run_close(dem_ctx *ctx, hipStream_t s)
 {
@@ -986,6 +992,7 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
         ctx->run = nullptr;
         ctx->run_len = 0;
     }
+    ctx->run_due = false;
     drain_all(ctx);
     for (int k = 0; k < 5; ++k) {
         ctx->stage_ms[k] = 0.0;
@@ -1101,9 +1108,19 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
         // previous work on the stream; an empty kernel bracketed the same way
         // measures the markers' own overhead
         if (P.dyn_path == 0) {
-            if (!ctx->run && P.timing > 0 && n % P.timing == 0) {
-                ctx->run = stage_slot(ctx, 5);
-                if (ctx->run) hipEventRecord(ctx->run->a, dyn);
+            if (P.timing > 0 && n % P.timing == 0) ctx->run_due = true;
+            if (!ctx->run && ctx->run_due) {
+                bool open = P.cd_mode == DEM_CD_EVERY || P.judge;
+                if (!open) {
+                    int64_t next_busy = ctx->next_wo;
+                    if (ctx->pending && ctx->pend_swap < next_busy) next_busy = ctx->pend_swap;
+                    open = next_busy - n >= RUN_LAUNCHES;
+                }
+                if (open) {
+                    ctx->run = stage_slot(ctx, 5);
+                    if (ctx->run) hipEventRecord(ctx->run->a, dyn);
+                    ctx->run_due = false;
+                }
             }
             launch_step_fused(a, ctx->rec_alt, ctx->q_alt, ctx->acs[ctx->cur], ctx->cap, ctx->ctr, dyn);
             if (ctx->run && ++ctx->run_len == RUN_LAUNCHES) run_close(ctx, dyn);

@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(TPB) k_cd_prepare(DetectArgs a, uint32_t *keys
     int cz = bin_coord(x[2], a.grid.lo[2], a.grid.inv_b, a.grid.nz);
     uint32_t key = ((uint32_t)cz * (uint32_t)a.grid.ny + (uint32_t)cy) * (uint32_t)a.grid.nx + (uint32_t)cx;
     keys[i] = key;
-    vals[i] = (uint32_t)i;
+    if (vals) vals[i] = (uint32_t)i;   // ids to sort (the one-pass sort writes its own)
     Cand c;
     c.x = x[0];
     c.y = x[1];
@@ -528,8 +528,8 @@ void launch_bin_front(const DetectArgs &a, CdWork &w, hipStream_t s, uint32_t *z
 {
     const int64_t n = a.n_spheres;
     launch_zero3(w.cell_count, (int64_t)a.grid.nbins, z1, n1, z2, n2, s);
-    hipLaunchKernelGGL(k_cd_prepare, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.vals, w.cand_tmp,
-                       w.cell_count);
+    hipLaunchKernelGGL(k_cd_prepare, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys,
+                       w.sort_mode == 0 ? (uint32_t *)nullptr : w.vals, w.cand_tmp, w.cell_count);
 }
 
 // Rest of binning: cell ranges, sort of (bin, id), candidates in bin order.
