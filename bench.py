@@ -41,9 +41,10 @@ def parse():
     ap.add_argument("--n", type=int, default=1_000_000, help="spheres of the config-1 workload")
     ap.add_argument("--workload", default="config1",
                     help="config1 (headline) | config2 | config3 | config4: other sizes for the design notes")
-    ap.add_argument("--modes", default="fixed,every,learned,analytic",
+    ap.add_argument("--modes", default="fixed,every,learned,analytic,adaptive",
                     help="schedules: fixed (k steps), every (every step), learned (MLP interval), "
-                         "analytic (the learned schedule's fallback bound alone, no network)")
+                         "analytic (the learned schedule's fallback bound alone, no network), "
+                         "adaptive (work order at every adoption, latency adapted from timing, margin from n_max)")
     ap.add_argument("--no-judge", action="store_true", help="skip the judged (miss-counting) runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=50)

@@ -64,7 +64,15 @@ typedef enum {
 typedef enum {
     DEM_CD_EVERY = 0,      /* contact detection every step, margin 0 */
     DEM_CD_FIXED = 1,      /* delayed detection every cd_interval steps, Sec. 2.1 */
-    DEM_CD_LEARNED = 2     /* delayed detection, interval chosen by the MLP */
+    DEM_CD_LEARNED = 2,    /* delayed detection, interval chosen by the MLP */
+    DEM_CD_ADAPTIVE = 3    /* Sec. 2.1's own policy: a work order goes out at every
+                              adoption, so detection is always in flight; its latency
+                              lambda (steps) is adapted from the measured timing of past
+                              cycles to the smallest value at which the dynamics stream
+                              does not wait; the margin follows from n_max = 2 lambda
+                              steps, the current top speed and gravity
+                              (m = 1.1 (v t + |g| t^2 / 2), t = n_max dt), capped by
+                              params.margin (when the cap binds, lambda shrinks) */
 } dem_cd_mode;
 
 enum { DEM_WALL_PLANE = 0, DEM_WALL_CYLINDER = 1 };
@@ -131,10 +139,11 @@ typedef struct {
     double domain_hi[3];
     int32_t cd_mode;        /* dem_cd_mode */
     int32_t cd_interval;    /* k: steps between work orders (FIXED) */
-    int32_t cd_latency;     /* lambda: steps from work order to adoption, 0 <= lambda <= k */
+    int32_t cd_latency;     /* lambda: steps from work order to adoption, 0 <= lambda <= k
+                               (ADAPTIVE: the first lambda, >= 1) */
     int32_t judge;          /* 1: count contacts missing from the set in use, every step */
     int32_t repair;         /* 1: a missed contact discards the stale set (default) */
-    int32_t cd_interval_max;/* LEARNED: upper bound on the interval */
+    int32_t cd_interval_max;/* LEARNED: upper bound on the interval; ADAPTIVE: on lambda */
     int32_t timing;         /* n > 0: time kernel stages with HIP events (stats->stage_ms);
                                the dynamics kernels are sampled every n-th step */
     double mlp_safety;      /* LEARNED: factor on the predicted horizon (0 = 1) */

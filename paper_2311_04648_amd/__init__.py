@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_dem_hip.so")
 
 DEM_OK, DEM_ERR_ARG, DEM_ERR_CAPACITY, DEM_ERR_HIP, DEM_ERR_DIVERGED, DEM_ERR_MISSED, DEM_ERR_STATE = range(7)
-MODES = {"every": 0, "fixed": 1, "learned": 2}
+MODES = {"every": 0, "fixed": 1, "learned": 2, "adaptive": 3}
 MLP_NPARAM = 1313
 MLP_NFEAT = 6
 _STATUS = {0: "OK", 1: "ARG", 2: "CAPACITY", 3: "HIP", 4: "DIVERGED", 5: "MISSED", 6: "STATE"}

@@ -83,6 +83,18 @@ struct dem_ctx {
     int64_t pend_swap = 0, next_wo = 0, last_wo = 0;
     int pend_buf = 1;
     hipEvent_t ev_wo = nullptr, ev_cd = nullptr;
+    // adaptive schedule: per work-order cycle, timing events at the work
+    // order (dynamics stream), at the end of its detection (detection
+    // stream) and at its adoption step before the wait (dynamics stream)
+    struct Cycle {
+        hipEvent_t wo = nullptr, cd = nullptr, adopt = nullptr;
+        int lam = 0;
+        bool issued = false, adopted = false;
+    };
+    Cycle cyc[4];
+    int cyc_pos = 0;
+    uint32_t *h_capped = nullptr;   // pinned, one flag per cycle slot
+    int lam_cur = 1;
     int64_t n_wo = 0;
     double interval_sum = 0.0;
     // stage timing (params.timing): a ring of event pairs, drained lazily
@@ -231,6 +243,7 @@ DetectArgs detect_args(const dem_ctx *ctx, double margin, int64_t step)
     a.grid = ctx->grid;
     a.org = ctx->org;
     a.margin = margin;
+    a.margin_dev = nullptr;
     a.h = ctx->P.dt;
     a.step = step;
     return a;
@@ -393,7 +406,9 @@ dem_status dem_create(const dem_params *params, const dem_materials *mats, const
     const dem_params &P = ctx->P;
     if (!(P.dt > 0.0)) return fail("dt must be positive");
     if (!(P.margin >= 0.0)) return fail("margin must be >= 0");
-    if (P.cd_mode < 0 || P.cd_mode > 2) return fail("unknown cd_mode");
+    if (P.cd_mode < 0 || P.cd_mode > 3) return fail("unknown cd_mode");
+    if (P.cd_mode == DEM_CD_ADAPTIVE && (P.cd_latency < 1 || P.cd_interval_max < 1))
+        return fail("the adaptive schedule needs cd_latency >= 1 and cd_interval_max >= 1");
     if (P.dyn_path < 0 || P.dyn_path > 1) return fail("dyn_path must be 0 (fused) or 1 (two kernels)");
     if (P.bin_sort < 0 || P.bin_sort > 1) return fail("bin_sort must be 0 (one pass) or 1 (radix)");
     if (P.cd_mode != DEM_CD_EVERY) {
@@ -598,6 +613,12 @@ dem_status dem_bind(dem_ctx *ctx, void *device_workspace, int64_t bytes, int64_t
     if (!ctx->h_pred) HIPCHK(hipHostMalloc((void **)&ctx->h_pred, 64));
     if (!ctx->ev_wo) HIPCHK(hipEventCreateWithFlags(&ctx->ev_wo, hipEventDisableTiming));
     if (!ctx->ev_cd) HIPCHK(hipEventCreateWithFlags(&ctx->ev_cd, hipEventDisableTiming));
+    if (!ctx->h_capped) HIPCHK(hipHostMalloc((void **)&ctx->h_capped, 4 * sizeof(uint32_t)));
+    for (auto &c : ctx->cyc) {
+        if (!c.wo) HIPCHK(hipEventCreate(&c.wo));
+        if (!c.cd) HIPCHK(hipEventCreate(&c.cd));
+        if (!c.adopt) HIPCHK(hipEventCreate(&c.adopt));
+    }
     HIPCHK(hipMemcpy(ctx->d_aux, ctx->aux.data(), sizeof(OwnerAux) * ctx->No, hipMemcpyHostToDevice));
     {
         std::vector<float> inv_i(ctx->No);
@@ -940,18 +961,73 @@ dem_status dem_count_missing(dem_ctx *ctx, dem_stream stream, int64_t *missing)
 // ---------------------------------------------------------------------------
 int64_t learned_interval(dem_ctx *ctx, hipStream_t s);
 
-static void issue_work_order(dem_ctx *ctx, hipStream_t dyn, hipStream_t kin, int64_t n)
+// Adaptive schedule: the latency of the next cycle from the timing of a
+// finished one.  The detection of cycle c took d_cd from its work order; the
+// dynamics stream took d_dyn to reach the adoption step (before waiting).
+// The smallest latency at which the dynamics would not have waited is
+// lam_c d_cd / d_dyn; 10 % is added.  A cycle whose margin hit its cap
+// shrinks the latency instead (a shorter n_max needs a smaller margin).
+static void adapt_latency(dem_ctx *ctx)
 {
-    if (ctx->P.cd_mode == DEM_CD_LEARNED) {
+    const int last = ctx->cyc_pos;                 // most recent work order
+    const int prev = (last + 3) % 4, prev2 = (last + 2) % 4;
+    // bound how far the host runs ahead: the cycle two work orders back
+    // has been adopted on the device
+    if (ctx->cyc[prev2].adopted) hipEventSynchronize(ctx->cyc[prev2].adopt);
+    int use = -1;
+    if (ctx->cyc[prev].adopted && hipEventQuery(ctx->cyc[prev].adopt) == hipSuccess) use = prev;
+    else if (ctx->cyc[prev2].adopted) use = prev2;
+    if (use < 0) return;
+    dem_ctx::Cycle &c = ctx->cyc[use];
+    if (hipEventQuery(c.cd) != hipSuccess) return;
+    float d_cd = 0.f, d_dyn = 0.f;
+    if (hipEventElapsedTime(&d_cd, c.wo, c.cd) != hipSuccess) return;
+    if (hipEventElapsedTime(&d_dyn, c.wo, c.adopt) != hipSuccess || !(d_dyn > 0.f)) return;
+    int lam;
+    if (ctx->h_capped[use]) {
+        lam = c.lam - 1;
+    } else {
+        lam = (int)std::ceil((double)c.lam * (double)d_cd / (double)d_dyn * 1.1);
+    }
+    const int lmax = std::max(1, ctx->P.cd_interval_max);
+    ctx->lam_cur = std::min(std::max(lam, 1), lmax);
+}
+
+// Issues a work order at step n: the detection front on the dynamics stream
+// (it reads the state of step n), the rest on the detection stream.
+// Returns the latency (steps to adoption) of this cycle.
+static int64_t issue_work_order(dem_ctx *ctx, hipStream_t dyn, hipStream_t kin, int64_t n)
+{
+    const dem_params &P = ctx->P;
+    if (P.cd_mode == DEM_CD_LEARNED) {
         // the learned interval measures the next features against this state
         hipMemcpyAsync(ctx->fref_rec, ctx->rec, sizeof(OwnerRec) * ctx->No, hipMemcpyDeviceToDevice, dyn);
         ctx->snap_step = n;
     }
+    int64_t lam = P.cd_latency;
+    int target = 1 - ctx->cur;
+    DetectArgs a = detect_args(ctx, P.margin, n);
+    dem_ctx::Cycle *cy = nullptr;
+    if (P.cd_mode == DEM_CD_ADAPTIVE) {
+        adapt_latency(ctx);
+        lam = ctx->lam_cur;
+        const double g = std::sqrt(P.gravity[0] * P.gravity[0] + P.gravity[1] * P.gravity[1] +
+                                   P.gravity[2] * P.gravity[2]);
+        launch_reduce_max(dyn_args(ctx, n), ctx->ctr, dyn);
+        launch_adaptive_margin(ctx->ctr, 2.0 * (double)lam * P.dt, g, P.margin, dyn);
+        const int slot = (ctx->cyc_pos + 1) % 4;
+        hipMemcpyAsync(&ctx->h_capped[slot], &ctx->ctr->capped, sizeof(uint32_t), hipMemcpyDeviceToHost, dyn);
+        cy = &ctx->cyc[slot];
+        hipEventRecord(cy->wo, dyn);
+        cy->lam = (int)lam;
+        cy->issued = true;
+        cy->adopted = false;
+        ctx->cyc_pos = slot;
+        a.margin_dev = &ctx->ctr->margin;
+    }
     // the work order: the first binning kernel reads the state of step n on
     // the dynamics stream (centres, bin keys and candidate records are the
     // snapshot); the rest of the detection runs on the detection stream
-    int target = 1 - ctx->cur;
-    DetectArgs a = detect_args(ctx, ctx->P.margin, n);
     auto *tf = stage_begin(ctx, 2, dyn);
     launch_detect_front(a, ctx->cdK, ctx->acs[target], dyn);
     if (tf) {
@@ -963,13 +1039,15 @@ static void issue_work_order(dem_ctx *ctx, hipStream_t dyn, hipStream_t kin, int
     auto *tp = stage_begin(ctx, 2, kin);
     launch_detect_back(a, ctx->cdK, ctx->acs[target], ctx->cap, ctx->ctr, target, kin);
     stage_end(tp, kin);
+    if (cy) hipEventRecord(cy->cd, kin);
     hipEventRecord(ctx->ev_cd, kin);
     ctx->pending = true;
     ctx->pend_buf = target;
-    ctx->pend_swap = n + ctx->P.cd_latency;
+    ctx->pend_swap = n + lam;
     if (ctx->n_wo > 0) ctx->interval_sum += (double)(n - ctx->last_wo);
     ctx->last_wo = n;
     ctx->n_wo++;
+    return lam;
 }
 
 dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream kin_, dem_step_stats *stats)
@@ -1041,8 +1119,13 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
                     hipMemcpyAsync(ctx->fref_rec, ctx->rec, sizeof(OwnerRec) * ctx->No, hipMemcpyDeviceToDevice, dyn);
                     ctx->snap_step = n;
                 }
-                int64_t k = P.cd_mode == DEM_CD_LEARNED ? learned_interval(ctx, dyn) : P.cd_interval;
+                int64_t k = P.cd_mode == DEM_CD_LEARNED ? learned_interval(ctx, dyn)
+                                                         : (P.cd_mode == DEM_CD_ADAPTIVE ? 1 : P.cd_interval);
                 ctx->next_wo = n + k;
+                if (P.cd_mode == DEM_CD_ADAPTIVE) {
+                    ctx->lam_cur = std::max(1, P.cd_latency);
+                    for (auto &c : ctx->cyc) c.issued = c.adopted = false;
+                }
             } else {
                 int64_t k_next = -1;
                 if (P.cd_latency == 0 && n == ctx->next_wo) {
@@ -1051,6 +1134,11 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
                     ++cds;
                 }
                 bool swap_due = ctx->pending && n == ctx->pend_swap;
+                if (swap_due && P.cd_mode == DEM_CD_ADAPTIVE) {
+                    dem_ctx::Cycle &c = ctx->cyc[ctx->cyc_pos];
+                    hipEventRecord(c.adopt, dyn);
+                    c.adopted = true;
+                }
                 if (swap_due) hipStreamWaitEvent(dyn, ctx->ev_cd, 0);
                 if (P.judge) {
                     int cand = swap_due ? ctx->pend_buf : ctx->cur;
@@ -1076,7 +1164,9 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
                         ctx->pending = false;
                         swap_due = true;
                         ctx->pend_buf = target;
-                        int64_t k = P.cd_mode == DEM_CD_LEARNED ? learned_interval(ctx, dyn) : P.cd_interval;
+                        int64_t k = P.cd_mode == DEM_CD_LEARNED
+                                        ? learned_interval(ctx, dyn)
+                                        : (P.cd_mode == DEM_CD_ADAPTIVE ? ctx->lam_cur : P.cd_interval);
                         ctx->next_wo = n + k;
                         k_next = -1;
                         ctx->last_wo = n;
@@ -1095,7 +1185,8 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
                 }
                 if (P.cd_latency > 0 && n == ctx->next_wo) {
                     int64_t k = P.cd_mode == DEM_CD_LEARNED ? learned_interval(ctx, dyn) : P.cd_interval;
-                    issue_work_order(ctx, dyn, kin, n);
+                    const int64_t lam = issue_work_order(ctx, dyn, kin, n);
+                    if (P.cd_mode == DEM_CD_ADAPTIVE) k = lam;   // the next order goes out at this adoption
                     ++cds;
                     ctx->next_wo = n + k;
                 } else if (P.cd_latency == 0 && k_next > 0) {
@@ -1197,6 +1288,12 @@ void dem_destroy(dem_ctx *ctx)
     if (ctx->h_pred) hipHostFree(ctx->h_pred);
     if (ctx->ev_wo) hipEventDestroy(ctx->ev_wo);
     if (ctx->ev_cd) hipEventDestroy(ctx->ev_cd);
+    if (ctx->h_capped) hipHostFree(ctx->h_capped);
+    for (auto &c : ctx->cyc) {
+        if (c.wo) hipEventDestroy(c.wo);
+        if (c.cd) hipEventDestroy(c.cd);
+        if (c.adopt) hipEventDestroy(c.adopt);
+    }
     for (auto &p : ctx->ring) {
         if (p.a) hipEventDestroy(p.a);
         if (p.b) hipEventDestroy(p.b);

@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(TPB) k_detect(DetectArgs a, const uint32_t *ke
     const uint32_t i = ci.id;
     const uint32_t key = keys[p];
     const double xi = ci.x, yi = ci.y, zi = ci.z, ri = (double)ci.r;
-    const double m = a.margin;
+    const double m = a.margin_dev ? *a.margin_dev : a.margin;
     const uint32_t nx = (uint32_t)a.grid.nx, nxy = (uint32_t)a.grid.nx * (uint32_t)a.grid.ny;
     uint32_t own_i = 0xffffffffu;
     uint32_t base = 0;
@@ -258,7 +258,7 @@ __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32
     const uint32_t i = ci.id;
     const uint32_t key = keys[p];
     const double xi = ci.x, yi = ci.y, zi = ci.z, ri = (double)ci.r;
-    const double m = a.margin;
+    const double m = a.margin_dev ? *a.margin_dev : a.margin;
     const uint32_t nx = (uint32_t)a.grid.nx, nxy = (uint32_t)a.grid.nx * (uint32_t)a.grid.ny;
     // five contiguous candidate ranges: own bin after p + bin x+1; row y+1;
     // the rows y-1, y, y+1 of plane z+1
@@ -378,7 +378,7 @@ __global__ void __launch_bounds__(TPB) k_compact(DetectArgs a, const Cand *cand_
     }
     const Cand ci = cand_tmp[i];
     const double xi = ci.x, yi = ci.y, zi = ci.z, ri = (double)ci.r;
-    const double m = a.margin;
+    const double m = a.margin_dev ? *a.margin_dev : a.margin;
     const int cx = bin_coord(xi, a.grid.lo[0], a.grid.inv_b, a.grid.nx);
     const int cy = bin_coord(yi, a.grid.lo[1], a.grid.inv_b, a.grid.ny);
     const int cz = bin_coord(zi, a.grid.lo[2], a.grid.inv_b, a.grid.nz);

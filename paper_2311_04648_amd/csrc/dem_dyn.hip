@@ -570,11 +570,34 @@ __global__ void __launch_bounds__(256) k_reduce_max(const float *blkmax, int64_t
     if (threadIdx.x == 0) ctr->maxv2[0] = __float_as_uint(fmaxf(fmaxf(w[0], w[1]), fmaxf(w[2], w[3])));
 }
 
+// Margin of the next detection under the adaptive schedule: in t = n_max h
+// each geometry moves at most v t + |g| t^2 / 2 when nothing but gravity
+// accelerates it (v: top speed of the last step); 10 % is added.  Capped
+// by the run margin (the bins were sized for it), which is flagged.
+__global__ void __launch_bounds__(64) k_adaptive_margin(DevCounters *ctr, double t, double gmag, double cap)
+{
+    if (threadIdx.x != 0) return;
+    const double v = sqrt((double)__uint_as_float(ctr->maxv2[0]));
+    double m = 1.1 * (v * t + 0.5 * gmag * t * t);
+    uint32_t capped = 0u;
+    if (!(m <= cap)) {
+        m = cap;
+        capped = 1u;
+    }
+    ctr->margin = m;
+    ctr->capped = capped;
+}
+
 __global__ void __launch_bounds__(64) k_noop() {}
 
 void launch_noop(hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     hipExtLaunchKernelGGL(k_noop, dim3(1), dim3(64), 0, s, ev0, ev1, 0);
+}
+
+void launch_adaptive_margin(DevCounters *ctr, double t, double gmag, double cap, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adaptive_margin, dim3(1), dim3(64), 0, s, ctr, t, gmag, cap);
 }
 
 void launch_reduce_max(const DynArgs &a, DevCounters *ctr, hipStream_t s)

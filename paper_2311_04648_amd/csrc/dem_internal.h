@@ -84,11 +84,12 @@ struct DevCounters {
     uint32_t div[2];          // divergence seen by the integrator, by step parity
     uint32_t miss;            // judge: missing true contacts
     uint32_t maxv2[4];        // max |v|^2 bits per step slot
-    uint32_t pad0;
+    uint32_t capped;          // adaptive schedule: the derived margin hit its cap
     int64_t last_step_done;
     uint32_t ncell;           // feature cells in use
     uint32_t pad1;
     unsigned long long contact_steps;   // sum over integrated steps of the set size in use
+    double margin;            // adaptive schedule: margin of the next detection
 };
 
 struct ScanTmp {
@@ -132,6 +133,7 @@ struct DetectArgs {
     Grid grid;
     Origin org;
     double margin;
+    const double *margin_dev;   // if set, the margin is read from device memory
     double h;
     int64_t step;
 };
@@ -231,5 +233,8 @@ void launch_step_fused(const DynArgs &a, OwnerRec *rec_out, double *q_out, const
 // an empty one-wave kernel stamped with events (overhead of the stamps)
 void launch_noop(hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 // max |v|^2 of the last integration into ctr->maxv2[0]
+// adaptive schedule: margin of the next detection from the top speed
+// (after launch_reduce_max), into ctr->margin
+void launch_adaptive_margin(DevCounters *ctr, double t, double gmag, double cap, hipStream_t s);
 void launch_reduce_max(const DynArgs &a, DevCounters *ctr, hipStream_t s);
 

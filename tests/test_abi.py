@@ -56,6 +56,8 @@ def _create(sysm, **kw):
     P.cd_mode = kw.get("mode", 1)
     P.cd_interval = kw.get("k", 10)
     P.cd_latency = kw.get("lam", 5)
+    P.dyn_path = kw.get("dyn_path", 0)
+    P.bin_sort = kw.get("bin_sort", 0)
     keep = []
 
     def k(a, dt):
@@ -94,7 +96,7 @@ def test_create_and_workspace_size_on_host():
     dem.lib().dem_destroy(ctx)
 
 
-@pytest.mark.parametrize("bad", ["dt", "radius", "latency"])
+@pytest.mark.parametrize("bad", ["dt", "radius", "latency", "mode", "adaptive_latency", "dyn_path", "bin_sort"])
 def test_create_rejects_bad_arguments(bad):
     _ensure_built()
     s = W.small_spheres(0, n=20)
@@ -105,6 +107,14 @@ def test_create_rejects_bad_arguments(bad):
         r = s.sph_rad.copy()
         r[3] = -1.0
         kw["sph_rad"] = r
+    elif bad == "mode":
+        kw["mode"] = 4
+    elif bad == "adaptive_latency":
+        kw["mode"], kw["lam"] = 3, 0
+    elif bad == "dyn_path":
+        kw["dyn_path"] = 2
+    elif bad == "bin_sort":
+        kw["bin_sort"] = 7
     else:
         kw["lam"] = 20
     st, ctx, msg = _create(s, **kw)

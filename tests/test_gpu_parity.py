@@ -351,6 +351,45 @@ def test_delayed_two_streams_equals_every_step_bitwise(dem):
         np.testing.assert_array_equal(ga[k], gb[k])
 
 
+@pytest.mark.parametrize("streams", [1, 2])
+def test_adaptive_schedule_equals_every_step_bitwise(dem, streams):
+    """Sec. 2.1's own policy (work order at every adoption, latency adapted
+    from timing, margin from n_max = 2 lambda): judged, no contact is
+    missed, and the trajectory equals every-step detection bit for bit."""
+    import torch
+    s = W.small_spheres(5, n=512, vel=0.3)
+    a = dem.DemContext(s, mode="every")
+    a.set_state()
+    a.step(300)
+    b = dem.DemContext(s, mode="adaptive", k=10, lam=2, judge=True, k_max=64)
+    b.set_state()
+    kw = dict(dyn=torch.cuda.Stream(), kin=torch.cuda.Stream()) if streams == 2 else {}
+    stats = b.step(300, **kw)
+    assert stats["misses"] == 0
+    assert stats["cds"] > 300 // 64
+    assert 1.0 <= stats["mean_interval"] <= 64.0
+    ga, gb = a.get_state(), b.get_state()
+    for k in ("X", "V", "W", "q"):
+        np.testing.assert_array_equal(ga[k], gb[k])
+
+
+def test_adaptive_schedule_with_binding_margin_cap_stays_exact(dem):
+    """A run margin far below what n_max needs: the derived margin is capped,
+    the latency shrinks, the judge repairs what the small margin misses, and
+    the trajectory still equals every-step detection."""
+    s = W.small_spheres(6, n=343, vel=1.0)
+    a = dem.DemContext(s, mode="every")
+    a.set_state()
+    a.step(200)
+    b = dem.DemContext(s, mode="adaptive", k=10, lam=4, judge=True, margin=2e-6, k_max=64)
+    b.set_state()
+    stats = b.step(200)
+    ga, gb = a.get_state(), b.get_state()
+    for k in ("X", "V", "W"):
+        np.testing.assert_array_equal(ga[k], gb[k])
+    assert stats["cds"] >= 200 // 8
+
+
 def test_judge_counts_misses_and_repair_restores_exactness(dem):
     s = W.small_spheres(7, n=343, vel=1.0, margin=1e-6)
     a = dem.DemContext(s, mode="every")
