@@ -7,7 +7,8 @@ dt = 5e-6 s; margin 0.1 r_min = 0.2 mm; delayed contact detection every 10
 steps on a second HIP stream (the fixed-margin schedule).  One "step" is
 contact detection (amortised over its interval) + force + reduction +
 integration for all spheres.  The same workload is also timed with
-every-step detection and with the learned interval.
+every-step detection, with the learned interval, with its analytic fallback
+alone, and with the paper's timing-adaptive policy.
 
 Prints one JSON line: sphere-steps/s of the fixed-margin schedule as
 `value`, the other schedules under `modes`, the roofline of the dominant

@@ -1183,7 +1183,12 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
                     ctx->pending = false;
                     ++swaps;
                 }
-                if (P.cd_latency > 0 && n == ctx->next_wo) {
+                if (P.cd_latency > 0 && n == ctx->next_wo && ctx->pending) {
+                    // the previous detection is not adopted yet: its buffer
+                    // and workspace are in use, so the order waits for the
+                    // adoption step
+                    ctx->next_wo = ctx->pend_swap;
+                } else if (P.cd_latency > 0 && n == ctx->next_wo) {
                     int64_t k = P.cd_mode == DEM_CD_LEARNED ? learned_interval(ctx, dyn) : P.cd_interval;
                     const int64_t lam = issue_work_order(ctx, dyn, kin, n);
                     if (P.cd_mode == DEM_CD_ADAPTIVE) k = lam;   // the next order goes out at this adoption
@@ -1339,7 +1344,11 @@ static int64_t analytic_interval(dem_ctx *ctx, double vmax)
     else t = vmax > 0.0 ? m / vmax : 1e30;
     double n = std::floor(t / P.dt) - (double)P.cd_latency;
     int64_t k = n < 1.0 ? 1 : (n > 1e9 ? (int64_t)1e9 : (int64_t)n);
-    return std::min<int64_t>(k, P.cd_interval_max);
+    k = std::min<int64_t>(k, P.cd_interval_max);
+    // a work order never goes out before the previous set is adopted: with a
+    // horizon shorter than two latencies the orders follow the adoptions
+    // back to back (the judge guards what the short horizon leaves open)
+    return std::max<int64_t>(k, std::max(P.cd_latency, 1));
 }
 
 // Decides the next detection interval at a work order (LEARNED mode): the
@@ -1373,7 +1382,8 @@ int64_t learned_interval(dem_ctx *ctx, hipStream_t s)
     double safety = ctx->P.mlp_safety > 0.0 ? ctx->P.mlp_safety : 1.0;
     double kl = std::floor(safety * (double)R) - (double)ctx->P.cd_latency - 1.0;
     int64_t k = kl < 1.0 ? 1 : (int64_t)std::min(kl, 1e9);
-    return std::min<int64_t>(k, ctx->P.cd_interval_max);
+    k = std::min<int64_t>(k, ctx->P.cd_interval_max);
+    return std::max<int64_t>(k, std::max(ctx->P.cd_latency, 1));   // as in analytic_interval
 }
 
 extern "C" {

@@ -225,44 +225,93 @@ __global__ void __launch_bounds__(256) k_feat_clear(uint32_t *raw, int64_t ncell
     for (int k = 6; k < RAW; ++k) r[k] = 0u;
 }
 
+// Per-owner contributions to its feature cell.  Owners are numbered in
+// space-filling order often enough that the lanes of a wave share few cells,
+// so each wave first combines the values of its lanes per distinct cell
+// (integer max / min / sums over shuffles, order-free) and one lane per
+// cell issues the atomics.
 __global__ void __launch_bounds__(256) k_feat_accum(const OwnerRec *rec, const OwnerRec *snap, const uint32_t *own_sph0,
                                                    const SphRec *sph, Origin org, Grid fg, uint32_t *raw,
                                                    uint32_t *cellmap, int64_t No)
 {
-    int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= No) return;
-    OwnerRec r = load_rec(rec + o);
-    OwnerRec s = load_rec(snap + o);
-    double X[3], Xs[3];
-    for (int k = 0; k < 3; ++k) {
-        X[k] = decode_axis(r.vox, r.off[k], org.o[k], k);
-        Xs[k] = decode_axis(s.vox, s.off[k], org.o[k], k);
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = o < No;
+    uint32_t c = 0xffffffffu;
+    uint32_t vmax[3] = {0u, 0u, 0u}, vmin[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu};
+    uint32_t fdv = 0u, fva = 0u, fdx = 0u, cnt = 0u;
+    unsigned long long iv = 0ull;
+    if (valid) {
+        OwnerRec r = load_rec(rec + o);
+        OwnerRec s = load_rec(snap + o);
+        double X[3], Xs[3];
+        for (int k = 0; k < 3; ++k) {
+            X[k] = decode_axis(r.vox, r.off[k], org.o[k], k);
+            Xs[k] = decode_axis(s.vox, s.off[k], org.o[k], k);
+        }
+        c = fcell_of(fg, X[0], X[1], X[2]);
+        cellmap[o] = c;
+        for (int k = 0; k < 3; ++k) {
+            const uint32_t e = ord_enc(r.v[k]);
+            vmax[k] = e;
+            vmin[k] = e;
+        }
+        float dv0 = r.v[0] - s.v[0], dv1 = r.v[1] - s.v[1], dv2 = r.v[2] - s.v[2];
+        float dv = sqrtf((dv0 * dv0 + dv1 * dv1) + dv2 * dv2);
+        float va = sqrtf((r.v[0] * r.v[0] + r.v[1] * r.v[1]) + r.v[2] * r.v[2]);
+        double d0 = X[0] - Xs[0], d1 = X[1] - Xs[1], d2 = X[2] - Xs[2];
+        float dx = (float)sqrt((d0 * d0 + d1 * d1) + d2 * d2);
+        fdv = __float_as_uint(dv);
+        fva = __float_as_uint(va);
+        fdx = __float_as_uint(dx);
+        cnt = 1u;
+        double vol = 0.0;
+        for (uint32_t q = own_sph0[o]; q < own_sph0[o + 1]; ++q) {
+            double rr = (double)sph[q].rad;
+            vol += 4.18879020478639098 * rr * rr * rr;
+        }
+        // fixed-point volume in units of 1e-18 m^3
+        iv = (unsigned long long)(vol * 1e18 + 0.5);
     }
-    uint32_t c = fcell_of(fg, X[0], X[1], X[2]);
-    cellmap[o] = c;
-    uint32_t *rw = raw + (int64_t)c * RAW;
-    for (int k = 0; k < 3; ++k) {
-        uint32_t e = ord_enc(r.v[k]);
-        atomicMax(&rw[k], e);
-        atomicMin(&rw[3 + k], e);
+    const int lane = (int)(threadIdx.x & 63);
+    unsigned long long todo = __ballot(valid);
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const uint32_t cl = __shfl(c, leader, 64);
+        const bool mine = valid && c == cl;
+        const unsigned long long grp = __ballot(mine);
+        uint32_t a[11];
+        for (int k = 0; k < 3; ++k) {
+            a[k] = mine ? vmax[k] : 0u;
+            a[3 + k] = mine ? vmin[k] : 0xffffffffu;
+        }
+        a[6] = mine ? fdv : 0u;
+        a[7] = mine ? fva : 0u;
+        a[8] = mine ? fdx : 0u;
+        a[9] = mine ? cnt : 0u;
+        unsigned long long sv = mine ? iv : 0ull;
+        for (int d = 32; d > 0; d >>= 1) {
+            for (int k = 0; k < 3; ++k) {
+                a[k] = max(a[k], (uint32_t)__shfl_xor(a[k], d, 64));
+                a[3 + k] = min(a[3 + k], (uint32_t)__shfl_xor(a[3 + k], d, 64));
+            }
+            for (int k = 6; k < 9; ++k) a[k] = max(a[k], (uint32_t)__shfl_xor(a[k], d, 64));
+            a[9] += (uint32_t)__shfl_xor(a[9], d, 64);
+            sv += (unsigned long long)__shfl_xor((long long)sv, d, 64);
+        }
+        if (lane == leader) {
+            uint32_t *rw = raw + (int64_t)cl * RAW;
+            for (int k = 0; k < 3; ++k) {
+                atomicMax(&rw[k], a[k]);
+                atomicMin(&rw[3 + k], a[3 + k]);
+            }
+            atomicMax(&rw[6], a[6]);
+            atomicMax(&rw[7], a[7]);
+            atomicMax(&rw[8], a[8]);
+            atomicAdd(&rw[9], a[9]);
+            atomicAdd(reinterpret_cast<unsigned long long *>(&rw[10]), sv);
+        }
+        todo &= ~grp;
     }
-    float dv0 = r.v[0] - s.v[0], dv1 = r.v[1] - s.v[1], dv2 = r.v[2] - s.v[2];
-    float dv = sqrtf((dv0 * dv0 + dv1 * dv1) + dv2 * dv2);
-    float va = sqrtf((r.v[0] * r.v[0] + r.v[1] * r.v[1]) + r.v[2] * r.v[2]);
-    double d0 = X[0] - Xs[0], d1 = X[1] - Xs[1], d2 = X[2] - Xs[2];
-    float dx = (float)sqrt((d0 * d0 + d1 * d1) + d2 * d2);
-    atomicMax(&rw[6], __float_as_uint(dv));
-    atomicMax(&rw[7], __float_as_uint(va));
-    atomicMax(&rw[8], __float_as_uint(dx));
-    atomicAdd(&rw[9], 1u);
-    double vol = 0.0;
-    for (uint32_t q = own_sph0[o]; q < own_sph0[o + 1]; ++q) {
-        double rr = (double)sph[q].rad;
-        vol += 4.18879020478639098 * rr * rr * rr;
-    }
-    // fixed-point volume in units of 1e-18 m^3
-    unsigned long long iv = (unsigned long long)(vol * 1e18 + 0.5);
-    atomicAdd(reinterpret_cast<unsigned long long *>(&rw[10]), iv);
 }
 
 __global__ void __launch_bounds__(256) k_feat_flags(const uint32_t *raw, int64_t ncell, uint32_t *flag)

@@ -161,3 +161,26 @@ def test_learned_interval_beats_fixed_with_zero_misses(dem):
     a, b = learned.get_state(), every.get_state()
     for k in ("X", "V", "W"):
         np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_short_predicted_horizon_never_overlaps_work_orders(dem):
+    """A model that predicts a horizon shorter than two adoption latencies:
+    the interval is held at the latency, so a work order never goes out
+    while the previous detection is in flight; judged with repair, the run
+    stays equal to every-step detection bit for bit."""
+    import torch
+    s = W.small_spheres(8, n=512, vel=0.3)
+    p = np.zeros(omlp.NPARAM, dtype=np.float32)
+    p[-1] = np.log1p(3.0)          # every cell: exp(y) - 1 = 3 steps
+    lam = 4
+    c = dem.DemContext(s, mode="learned", k=10, lam=lam, judge=True, k_max=64)
+    c.mlp_set(p)
+    c.set_state()
+    st = c.step(200, dyn=torch.cuda.Stream(), kin=torch.cuda.Stream())
+    assert st["mean_interval"] >= lam
+    e = dem.DemContext(s, mode="every")
+    e.set_state()
+    e.step(200)
+    a, b = c.get_state(), e.get_state()
+    for k in ("X", "V", "W"):
+        np.testing.assert_array_equal(a[k], b[k])
