@@ -163,6 +163,7 @@ void carve_cd(Carver &c, const dem_ctx *ctx, CdWork &w)
     w.vals_alt = c.take<uint32_t>(ns);
     w.cand_tmp = c.take<Cand>(ns);
     w.cand = c.take<Cand>(ns);
+    w.candf = c.take<float4>(ns);
     w.cell_count = c.take<uint32_t>((int64_t)ctx->grid.nbins + 1);
     w.cell_start = c.take<uint32_t>((int64_t)ctx->grid.nbins + 1);
     w.count = c.take<uint32_t>(ns + 1);

@@ -102,12 +102,16 @@ __global__ void __launch_bounds__(TPB) k_bucket_order(const uint32_t *cell_start
     }
 }
 
+// Candidate records in bin order, and their 16-byte FP32 copies for the
+// prefilter of the detection walk.
 __global__ void __launch_bounds__(TPB) k_cand_gather(const uint32_t *vals, const Cand *cand_tmp,
-                                                     Cand *cand, int64_t n)
+                                                     Cand *cand, float4 *candf, Grid g, int64_t n)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    cand[p] = cand_tmp[vals[p]];
+    const Cand c = cand_tmp[vals[p]];
+    cand[p] = c;
+    candf[p] = make_float4((float)(c.x - g.lo[0]), (float)(c.y - g.lo[1]), (float)(c.z - g.lo[2]), c.r);
 }
 
 __device__ inline bool sphere_pair_hit(double xi, double yi, double zi, double ri, const Cand &cj,
@@ -249,16 +253,28 @@ __global__ void __launch_bounds__(TPB) k_detect(DetectArgs a, const uint32_t *ke
 constexpr int DETECT_BATCH = 4;
 
 __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32_t *keys, const Cand *cand,
-                                                      const uint32_t *cell_start, uint32_t *count,
-                                                      uint32_t *stage, uint32_t *bcount)
+                                                      const float4 *candf, const uint32_t *cell_start,
+                                                      uint32_t *count, uint32_t *stage, uint32_t *bcount)
 {
     const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (p >= a.n_spheres) return;
     const Cand ci = cand[p];
+    const float4 cif = candf[p];
     const uint32_t i = ci.id;
     const uint32_t key = keys[p];
     const double xi = ci.x, yi = ci.y, zi = ci.z, ri = (double)ci.r;
     const double m = a.margin_dev ? *a.margin_dev : a.margin;
+    // FP32 prefilter: a candidate is rejected only when its FP32 distance
+    // exceeds the pair threshold T by more than a bound on the rounding.
+    // Each FP32 coordinate is within 2^-24 |c| of the exact one (c: the
+    // coordinate relative to the grid origin), so each difference is within
+    // 2^-24 (M_i + M_j + |dx|) (M: largest coordinate magnitude of a sphere)
+    // and the distance within sqrt(3) times that; the squares, sums and T
+    // itself add a few 2^-24 relative.  The slack 8 2^-24 (M_i + M_j) +
+    // 16 2^-24 T + 1e-12 m exceeds all of it, so no true pair is rejected;
+    // the exact FP64 predicate decides the rest.
+    const float twom = (float)(2.0 * m);
+    const float Mi = fmaxf(fabsf(cif.x), fmaxf(fabsf(cif.y), fabsf(cif.z)));
     const uint32_t nx = (uint32_t)a.grid.nx, nxy = (uint32_t)a.grid.nx * (uint32_t)a.grid.ny;
     // five contiguous candidate ranges: own bin after p + bin x+1; row y+1;
     // the rows y-1, y, y+1 of plane z+1
@@ -280,10 +296,12 @@ __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32
     const uint32_t total = (rl[0] + rl[1]) + (rl[2] + rl[3] + rl[4]);
     uint32_t own_i = 0xffffffffu;
     for (uint32_t v0 = 0; v0 < total; v0 += DETECT_BATCH) {
-        Cand cb[DETECT_BATCH];
+        float4 cb[DETECT_BATCH];
+        uint32_t qb[DETECT_BATCH];
 #pragma unroll
         for (int u = 0; u < DETECT_BATCH; ++u) {
             uint32_t v = v0 + (uint32_t)u;
+            qb[u] = 0xffffffffu;
             if (v < total) {
                 int r = 0;
 #pragma unroll
@@ -292,13 +310,19 @@ __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32
                         v -= rl[k];
                         r = k + 1;
                     }
-                cb[u] = cand[ra[r] + v];
+                qb[u] = ra[r] + v;
+                cb[u] = candf[qb[u]];
             }
         }
 #pragma unroll
         for (int u = 0; u < DETECT_BATCH; ++u) {
-            if (v0 + (uint32_t)u >= total) break;
-            const Cand &cj = cb[u];
+            if (qb[u] == 0xffffffffu) break;
+            const float dxf = cif.x - cb[u].x, dyf = cif.y - cb[u].y, dzf = cif.z - cb[u].z;
+            const float Mj = fmaxf(fabsf(cb[u].x), fmaxf(fabsf(cb[u].y), fabsf(cb[u].z)));
+            const float T32 = (cif.w + cb[u].w) + twom;
+            const float tf = T32 + ((4.77e-7f * (Mi + Mj) + 9.54e-7f * T32) + 1e-12f);
+            if ((dxf * dxf + dyf * dyf) + dzf * dzf > tf * tf) continue;
+            const Cand cj = cand[qb[u]];
             if (!sphere_pair_hit(xi, yi, zi, ri, cj, m)) continue;
             if (own_i == 0xffffffffu) own_i = a.sph[i].owner;
             if (a.sph[cj.id].owner == own_i) continue;
@@ -532,8 +556,11 @@ void launch_bin_front(const DetectArgs &a, CdWork &w, hipStream_t s, uint32_t *z
                        w.sort_mode == 0 ? (uint32_t *)nullptr : w.vals, w.cand_tmp, w.cell_count);
 }
 
-// Rest of binning: cell ranges, sort of (bin, id), candidates in bin order.
-void launch_bin_back(const DetectArgs &a, CdWork &w, hipStream_t s)
+// Rest of binning: cell ranges, sort by bin, candidates in bin order.
+// With `order_bins` the ids inside each bin are put in ascending order (a
+// stable sort of (bin, id)); the detection does not need it: the pairs it
+// finds do not depend on the order of the candidates inside a bin.
+void launch_bin_back(const DetectArgs &a, CdWork &w, hipStream_t s, bool order_bins)
 {
     int64_t n = a.n_spheres;
     const int64_t nb = (int64_t)a.grid.nbins;
@@ -542,7 +569,8 @@ void launch_bin_back(const DetectArgs &a, CdWork &w, hipStream_t s)
         scan_exclusive_u32(w.cell_count, w.cell_start, nb, w.partials, s, w.cell_count);
         hipLaunchKernelGGL(k_bucket_scatter, dim3(nblocks(n)), dim3(TPB), 0, s, w.keys, n, w.cell_count,
                            w.keys_alt, w.vals_alt);
-        hipLaunchKernelGGL(k_bucket_order, dim3(nblocks(nb)), dim3(TPB), 0, s, w.cell_start, nb, w.vals_alt);
+        if (order_bins)
+            hipLaunchKernelGGL(k_bucket_order, dim3(nblocks(nb)), dim3(TPB), 0, s, w.cell_start, nb, w.vals_alt);
         uint32_t *t = w.keys; w.keys = w.keys_alt; w.keys_alt = t;
         t = w.vals; w.vals = w.vals_alt; w.vals_alt = t;
     } else {
@@ -551,14 +579,15 @@ void launch_bin_back(const DetectArgs &a, CdWork &w, hipStream_t s)
     }
     // candidate records in bin order (random 32-byte reads, coalesced writes;
     // moving the records in the scatter instead costs more: random writes)
-    hipLaunchKernelGGL(k_cand_gather, dim3(nblocks(n)), dim3(TPB), 0, s, w.vals, w.cand_tmp, w.cand, n);
+    hipLaunchKernelGGL(k_cand_gather, dim3(nblocks(n)), dim3(TPB), 0, s, w.vals, w.cand_tmp, w.cand, w.candf,
+                       a.grid, n);
 }
 
 void launch_bin(const DetectArgs &a, CdWork &w, hipStream_t s, uint32_t *z1, int64_t n1, uint32_t *z2,
-                int64_t n2)
+                int64_t n2, bool order_bins)
 {
     launch_bin_front(a, w, s, z1, n1, z2, n2);
-    launch_bin_back(a, w, s);
+    launch_bin_back(a, w, s, order_bins);
 }
 
 void launch_blists(AcsBuf &b, int64_t ns, int64_t cap, uint32_t *partials, hipStream_t s)
@@ -589,9 +618,9 @@ void launch_detect_back(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap
                         hipStream_t s)
 {
     int64_t n = a.n_spheres;
-    launch_bin_back(a, w, s);
-    hipLaunchKernelGGL(k_detect_stage, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand, w.cell_start,
-                       w.count, w.stage, out.bcur);
+    launch_bin_back(a, w, s, false);
+    hipLaunchKernelGGL(k_detect_stage, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,
+                       (const float4 *)w.candf, w.cell_start, w.count, w.stage, out.bcur);
     // row offsets (checked against the capacity) and B-list offsets (with a
     // copy as the fill cursor) in one pair of launches
     scan_exclusive_u32_pair(w.count, out.start, nullptr, ctr, cap, buf, out.bcur, out.bstart, out.bcur, n,
@@ -607,7 +636,7 @@ void launch_judge(const DetectArgs &a, CdWork &w, const AcsBuf &cur, int64_t cap
                   hipStream_t s)
 {
     int64_t n = a.n_spheres;
-    launch_bin(a, w, s);
+    launch_bin(a, w, s, nullptr, 0, nullptr, 0, false);
     hipLaunchKernelGGL(k_detect<MODE_JUDGE>, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,
                        w.cell_start, (uint32_t *)nullptr, (const uint32_t *)nullptr, (uint32_t *)nullptr,
                        cap, (const uint32_t *)cur.start, (const uint32_t *)cur.j, &ctr->miss,
@@ -625,9 +654,9 @@ void launch_detect_plain(const DetectArgs &a, CdWork &w, uint32_t *start, uint32
                          DevCounters *ctr, hipStream_t s)
 {
     int64_t n = a.n_spheres;
-    launch_bin(a, w, s, w.count, n + 1);
-    hipLaunchKernelGGL(k_detect_stage, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand, w.cell_start,
-                       w.count, w.stage, (uint32_t *)nullptr);
+    launch_bin(a, w, s, w.count, n + 1, nullptr, 0, false);
+    hipLaunchKernelGGL(k_detect_stage, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,
+                       (const float4 *)w.candf, w.cell_start, w.count, w.stage, (uint32_t *)nullptr);
     scan_exclusive_u32(w.count, start, n, w.partials, s);
     hipLaunchKernelGGL(k_record_total, dim3(1), dim3(1), 0, s, start, n, ctr);
     hipLaunchKernelGGL(k_compact, dim3(nblocks(n)), dim3(TPB), 0, s, a, (const Cand *)w.cand_tmp,
@@ -641,7 +670,7 @@ void launch_label_judge(const DetectArgs &a, CdWork &w, const uint32_t *lab_star
                         hipStream_t s)
 {
     int64_t n = a.n_spheres;
-    launch_bin(a, w, s);
+    launch_bin(a, w, s, nullptr, 0, nullptr, 0, false);
     hipLaunchKernelGGL(k_detect<MODE_LABEL>, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,
                        w.cell_start, (uint32_t *)nullptr, (const uint32_t *)nullptr, (uint32_t *)nullptr,
                        cap, lab_start, lab_j, (uint32_t *)nullptr, cellmap, first_miss, tval);

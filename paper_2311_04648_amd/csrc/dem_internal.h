@@ -141,6 +141,7 @@ struct DetectArgs {
 struct CdWork {
     uint32_t *keys, *vals, *keys_alt, *vals_alt;   // sorted result lands in keys/vals
     Cand *cand_tmp, *cand;
+    float4 *candf;         // [Ns] bin order: FP32 centre relative to the grid origin, radius
     uint32_t *cell_count, *cell_start;
     uint32_t *count;       // [Ns+1]
     uint32_t *stage;       // [16 Ns] staged partners of the single-traversal detection
@@ -173,7 +174,7 @@ inline void swap_hist(AcsBuf &b)
 }
 
 void launch_bin(const DetectArgs &a, CdWork &w, hipStream_t s, uint32_t *z1 = nullptr, int64_t n1 = 0,
-                uint32_t *z2 = nullptr, int64_t n2 = 0);
+                uint32_t *z2 = nullptr, int64_t n2 = 0, bool order_bins = true);
 // full detection into `out` (count, scan, write, sort rows, B lists)
 void launch_detect(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap, DevCounters *ctr,
                    int buf, hipStream_t s);
