@@ -60,19 +60,19 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, rolling=False):
+def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, rolling=False, n_clump=None):
     """Bytes one launch of a stage must move at minimum (unique data);
     `active` = spheres that appear in at least one contact:
     k_force: per sphere its row offset (4); per active sphere its record
       (16), its owner's record (48) and its A-side sums written (24); per
       contact the partner id (4), history read + write (24) and the B-side
       reaction written (24).
-    k_step_fused: per owner the record read + write (96) and the inverse
-      inertia (4 for single-sphere systems; else 16, the sphere range 4 and
-      the quaternion read + written 64); per sphere the row and B-list
-      offsets (8); per active sphere its record (16); per contact the partner
-      id (4), the history read + written (24, 32 with contact age) and the
-      B-list entry with its source sphere (8).
+    k_step_fused: per owner its contact flag (1), the record read + write
+      (96) and the inverse inertia (4 for single-sphere systems; else 16, and
+      per clump owner the quaternion read + written 64); per active sphere
+      its record, row and B-list offsets and its owner's sphere range (28);
+      per contact the partner id (4), the history read + written (24, 32
+      with contact age) and the B-list entry with its source sphere (8).
     k_fold_integrate: per owner the record read + write (96) and the inverse
       inertia: one isotropic value (4) when every owner is a single sphere,
       else three values and the template (16) plus the sphere range (4); per
@@ -88,7 +88,8 @@ def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, roll
     if stage == "k_force":
         return Ns * 4 + active * 88 + C * 52
     if stage == "k_step_fused":
-        return No * (180 if clumps else 100) + Ns * 8 + active * 16 + C * (44 if rolling else 36)
+        nc = (No if n_clump is None else n_clump) if clumps else 0
+        return No * (113 if clumps else 101) + nc * 64 + active * 28 + C * (44 if rolling else 36)
     if stage == "k_fold_integrate":
         return No * (116 if clumps else 100) + Ns * 8 + active * 24 + C * 28
     if stage == "detect":
@@ -254,8 +255,10 @@ def main():
     avg_ms = max((tot[dom] - tot[4]) / n_launch, 1e-6)
     C = st["mean_contacts"]
     passes = 1   # one-pass bin sort (the LSD radix option would take (sort_bits + 7) // 8)
+    n_clump = int(np.sum(np.asarray(sysm.own_tmpl) >= 0))
     algo = algorithmic_bytes(stages[dom], Ns, No, C, r["active"], r["info"]["nbins"], passes,
-                             clumps=Ns != No, rolling=bool(np.any(np.asarray(sysm.mat_crr) > 0)))
+                             clumps=Ns != No, rolling=bool(np.any(np.asarray(sysm.mat_crr) > 0)),
+                             n_clump=n_clump)
     achieved = algo / (avg_ms * 1e-3) / 1e9
     traffic = load_traffic(stages[dom])
     roofline = {"bound": "hbm", "kernel": stages[dom], "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
@@ -309,7 +312,8 @@ def main():
         s2 = rr["stats"]
         Cm, act = s2["mean_contacts"], rr["active"]
         if args.dyn_path == 0:
-            dyn_b = algorithmic_bytes("k_step_fused", Ns, No, Cm, act, 0, passes, clumps=Ns != No, rolling=rolling)
+            dyn_b = algorithmic_bytes("k_step_fused", Ns, No, Cm, act, 0, passes, clumps=Ns != No, rolling=rolling,
+                                      n_clump=n_clump)
         else:
             dyn_b = (algorithmic_bytes("k_force", Ns, No, Cm, act, 0, passes)
                      + algorithmic_bytes("k_fold_integrate", Ns, No, Cm, act, 0, passes, clumps=Ns != No))

@@ -205,6 +205,7 @@ void carve(Carver &c, dem_ctx *ctx, int64_t cap)
         a.bidx = c.take<uint32_t>(cap);
         a.bsrc = c.take<uint32_t>(cap);
         a.bcur = c.take<uint32_t>(Ns + 1);
+        a.oany = c.take<uint8_t>(No);
     }
     ctx->sb.aF = c.take<float>(3 * Ns);
     ctx->sb.aT = c.take<float>(3 * Ns);
@@ -245,6 +246,8 @@ DetectArgs detect_args(const dem_ctx *ctx, double margin, int64_t step)
     a.org = ctx->org;
     a.margin = margin;
     a.margin_dev = nullptr;
+    a.own_sph0 = ctx->has_clumps ? ctx->d_sph0 : nullptr;
+    a.n_owners = ctx->No;
     a.h = ctx->P.dt;
     a.step = step;
     return a;
@@ -298,6 +301,7 @@ void clear_set(dem_ctx *ctx, int b, hipStream_t s)
 {
     launch_fill_u32(ctx->acs[b].start, ctx->Ns + 1, 0u, s);
     launch_fill_u32(ctx->acs[b].bstart, ctx->Ns + 1, 0u, s);
+    launch_owner_flags(ctx->acs[b], ctx->has_clumps ? ctx->d_sph0 : nullptr, ctx->No, ctx->Ns, ctx->cap, s);
 }
 
 void drain_pair(dem_ctx *ctx, dem_ctx::TimedPair &p)
@@ -929,6 +933,7 @@ dem_status dem_set_contacts(dem_ctx *ctx, const uint64_t *keys, const float *his
         HIPCHK(hipMemcpyAsync(a.hw, h.data() + 3 * n, 4 * n, hipMemcpyHostToDevice, s));
     }
     launch_blists(a, ctx->Ns, ctx->cap, ctx->cdD.partials, s);
+    launch_owner_flags(a, ctx->has_clumps ? ctx->d_sph0 : nullptr, ctx->No, ctx->Ns, ctx->cap, s);
     HIPCHK(hipGetLastError());
     uint32_t nn = (uint32_t)n, zero = 0;
     HIPCHK(hipMemcpyAsync(&ctx->ctr->n_contacts[b], &nn, 4, hipMemcpyHostToDevice, s));
@@ -1120,8 +1125,10 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
                     hipMemcpyAsync(ctx->fref_rec, ctx->rec, sizeof(OwnerRec) * ctx->No, hipMemcpyDeviceToDevice, dyn);
                     ctx->snap_step = n;
                 }
-                int64_t k = P.cd_mode == DEM_CD_LEARNED ? learned_interval(ctx, dyn)
-                                                         : (P.cd_mode == DEM_CD_ADAPTIVE ? 1 : P.cd_interval);
+                // the first interval is the fixed one: the learned interval's
+                // features (and its analytic fallback's top speed) measure
+                // motion since the previous work order, and there is none yet
+                int64_t k = P.cd_mode == DEM_CD_ADAPTIVE ? 1 : std::min(P.cd_interval, P.cd_interval_max);
                 ctx->next_wo = n + k;
                 if (P.cd_mode == DEM_CD_ADAPTIVE) {
                     ctx->lam_cur = std::max(1, P.cd_latency);
@@ -1191,8 +1198,26 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
                     ctx->next_wo = ctx->pend_swap;
                 } else if (P.cd_latency > 0 && n == ctx->next_wo) {
                     int64_t k = P.cd_mode == DEM_CD_LEARNED ? learned_interval(ctx, dyn) : P.cd_interval;
-                    const int64_t lam = issue_work_order(ctx, dyn, kin, n);
-                    if (P.cd_mode == DEM_CD_ADAPTIVE) k = lam;   // the next order goes out at this adoption
+                    if (P.cd_mode == DEM_CD_LEARNED && k < P.cd_latency) {
+                        // the predicted horizon does not cover the latency of a
+                        // delayed detection: detect now on the dynamics stream and
+                        // use the set from this step on
+                        const int target = 1 - ctx->cur;
+                        dem_status st = detect_now(ctx, P.margin, dyn, target);
+                        if (st != DEM_OK) return st;
+                        st = adopt(ctx, target, dyn);
+                        if (st != DEM_OK) return st;
+                        hipMemcpyAsync(ctx->fref_rec, ctx->rec, sizeof(OwnerRec) * ctx->No,
+                                       hipMemcpyDeviceToDevice, dyn);
+                        ctx->snap_step = n;
+                        if (ctx->n_wo > 0) ctx->interval_sum += (double)(n - ctx->last_wo);
+                        ctx->last_wo = n;
+                        ctx->n_wo++;
+                        ++swaps;
+                    } else {
+                        const int64_t lam = issue_work_order(ctx, dyn, kin, n);
+                        if (P.cd_mode == DEM_CD_ADAPTIVE) k = lam;   // the next order goes out at this adoption
+                    }
                     ++cds;
                     ctx->next_wo = n + k;
                 } else if (P.cd_latency == 0 && k_next > 0) {
@@ -1345,11 +1370,7 @@ static int64_t analytic_interval(dem_ctx *ctx, double vmax)
     else t = vmax > 0.0 ? m / vmax : 1e30;
     double n = std::floor(t / P.dt) - (double)P.cd_latency;
     int64_t k = n < 1.0 ? 1 : (n > 1e9 ? (int64_t)1e9 : (int64_t)n);
-    k = std::min<int64_t>(k, P.cd_interval_max);
-    // a work order never goes out before the previous set is adopted: with a
-    // horizon shorter than two latencies the orders follow the adoptions
-    // back to back (the judge guards what the short horizon leaves open)
-    return std::max<int64_t>(k, std::max(P.cd_latency, 1));
+    return std::min<int64_t>(k, P.cd_interval_max);
 }
 
 // Decides the next detection interval at a work order (LEARNED mode): the
@@ -1383,8 +1404,7 @@ int64_t learned_interval(dem_ctx *ctx, hipStream_t s)
     double safety = ctx->P.mlp_safety > 0.0 ? ctx->P.mlp_safety : 1.0;
     double kl = std::floor(safety * (double)R) - (double)ctx->P.cd_latency - 1.0;
     int64_t k = kl < 1.0 ? 1 : (int64_t)std::min(kl, 1e9);
-    k = std::min<int64_t>(k, ctx->P.cd_interval_max);
-    return std::max<int64_t>(k, std::max(ctx->P.cd_latency, 1));   // as in analytic_interval
+    return std::min<int64_t>(k, ctx->P.cd_interval_max);
 }
 
 extern "C" {

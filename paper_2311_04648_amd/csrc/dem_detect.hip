@@ -511,6 +511,24 @@ __global__ void __launch_bounds__(TPB) k_blist_sort(const uint32_t *start, const
     }
 }
 
+// Per-owner contact flag of a set: 1 if any sphere of owner o has a row or
+// B-list entry (the spheres of an owner are consecutive, so their rows and
+// B lists are one range each); an overflowed set flags nothing.
+__global__ void __launch_bounds__(TPB) k_owner_flags(const uint32_t *start, const uint32_t *bstart,
+                                                     const uint32_t *own_sph0, int64_t no, int64_t ns,
+                                                     int64_t cap, uint8_t *flag)
+{
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= no) return;
+    if ((int64_t)start[ns] > cap) {
+        flag[o] = 0;
+        return;
+    }
+    const uint32_t s0 = own_sph0 ? own_sph0[o] : (uint32_t)o;
+    const uint32_t s1 = own_sph0 ? own_sph0[o + 1] : (uint32_t)o + 1u;
+    flag[o] = (start[s0] != start[s1] || bstart[s0] != bstart[s1]) ? 1 : 0;
+}
+
 __global__ void __launch_bounds__(TPB) k_remap(const uint32_t *os, const uint32_t *oj, const float *ohx,
                                                const float *ohy, const float *ohz, const float *ohw,
                                                const uint32_t *ns_, const uint32_t *nj, float *nhx, float *nhy,
@@ -607,6 +625,12 @@ void launch_detect_front(const DetectArgs &a, CdWork &w, AcsBuf &out, hipStream_
     launch_bin_front(a, w, s, out.bcur, n + 1, w.count, n + 1);
 }
 
+void launch_owner_flags(AcsBuf &b, const uint32_t *own_sph0, int64_t no, int64_t ns, int64_t cap, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_owner_flags, dim3(nblocks(no)), dim3(TPB), 0, s, (const uint32_t *)b.start,
+                       (const uint32_t *)b.bstart, own_sph0, no, ns, cap, b.oany);
+}
+
 void launch_detect(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap, DevCounters *ctr, int buf,
                    hipStream_t s)
 {
@@ -630,6 +654,7 @@ void launch_detect_back(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap
                        (const uint32_t *)w.stage, out.j, cap, out.bcur, out.bidx, out.bsrc);
     hipLaunchKernelGGL(k_blist_sort, dim3(nblocks(n)), dim3(TPB), 0, s, out.start, out.bstart, n, cap, out.bidx,
                        out.bsrc);
+    launch_owner_flags(out, a.own_sph0, a.n_owners, n, cap, s);
 }
 
 void launch_judge(const DetectArgs &a, CdWork &w, const AcsBuf &cur, int64_t cap, DevCounters *ctr,

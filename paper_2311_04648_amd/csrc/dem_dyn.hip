@@ -312,10 +312,10 @@ __global__ void __launch_bounds__(TPB) k_force(DynArgs a, const uint32_t *start,
 // Semi-implicit Euler for one owner: velocity (FP32), angular velocity
 // (world frame for single spheres, body frame for clumps, whose quaternion is
 // advanced in FP64 by the exponential map and written to qout; an unrotated
-// clump copies qin there unless the two are the same), FP64 position
+// clump writes its orientation qv there unchanged), FP64 position
 // re-encoded on the 2^-38 m grid.  Flags divergence; returns |v|^2.
 __device__ __forceinline__ float advance(const DynArgs &a, OwnerRec &r, const float *inv, bool rotating, float3 F,
-                                         float3 T, const double *qin, double *qout, DevCounters *ctr)
+                                         float3 T, const double4 qv, double *qout, DevCounters *ctr)
 {
     const float hf = (float)a.h;
     const float m = r.mass;
@@ -325,7 +325,6 @@ __device__ __forceinline__ float advance(const DynArgs &a, OwnerRec &r, const fl
     if (!rotating) {
         w = w + hf * f3(T.x * inv[0], T.y * inv[1], T.z * inv[2]);
     } else {
-        const double4 qv = *reinterpret_cast<const double4 *>(qin);
         Mat3d R = rot_from_q(qv.x, qv.y, qv.z, qv.w);
         // torque into the body frame: R^T T
         const float tbx = (float)((R.m[0] * (double)T.x + R.m[3] * (double)T.y) + R.m[6] * (double)T.z);
@@ -336,7 +335,19 @@ __device__ __forceinline__ float advance(const DynArgs &a, OwnerRec &r, const fl
         const double th0 = a.h * (double)w.x, th1 = a.h * (double)w.y, th2 = a.h * (double)w.z;
         const double ang = sqrt((th0 * th0 + th1 * th1) + th2 * th2);
         if (ang > 0.0) {
-            const double sh = sin(0.5 * ang) / ang, ch = cos(0.5 * ang);
+            // sin(x)/x and cos(x) of the half angle x; a step turns a clump by
+            // far less than 0.02 rad, where their Taylor series cut after the
+            // x^6 and x^8 terms are exact to below 2^-60 relative
+            const double x = 0.5 * ang, x2 = x * x;
+            double sinc, ch;
+            if (x < 1e-2) {
+                sinc = 1.0 - x2 * (1.0 / 6.0) * (1.0 - x2 * (1.0 / 20.0) * (1.0 - x2 * (1.0 / 42.0)));
+                ch = 1.0 - x2 * 0.5 * (1.0 - x2 * (1.0 / 12.0) * (1.0 - x2 * (1.0 / 30.0) * (1.0 - x2 * (1.0 / 56.0))));
+            } else {
+                sinc = sin(x) / x;
+                ch = cos(x);
+            }
+            const double sh = 0.5 * sinc;   // sin(ang / 2) / ang
             const double b0 = ch, b1q = sh * th0, b2 = sh * th1, b3 = sh * th2;
             double n0 = qv.x * b0 - qv.y * b1q - qv.z * b2 - qv.w * b3;
             double n1 = qv.x * b1q + qv.y * b0 + qv.z * b3 - qv.w * b2;
@@ -344,7 +355,7 @@ __device__ __forceinline__ float advance(const DynArgs &a, OwnerRec &r, const fl
             double n3 = qv.x * b3 + qv.y * b2 - qv.z * b1q + qv.w * b0;
             const double nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2 + n3 * n3);
             *reinterpret_cast<double4 *>(qout) = make_double4(n0 / nn, n1 / nn, n2 / nn, n3 / nn);
-        } else if (qout != qin) {
+        } else if (qout) {
             *reinterpret_cast<double4 *>(qout) = qv;
         }
     }
@@ -444,7 +455,11 @@ __global__ void __launch_bounds__(TPB) k_fold_integrate(DynArgs a, const uint32_
             To[No + o] = T.y;
             To[2 * No + o] = T.z;
         } else {
-            v2 = advance(a, r, inv, !SINGLES && tmpl >= 0, F, T, a.q + 4 * (size_t)o, a.q + 4 * (size_t)o, ctr);
+            // orientation updated in place
+            const bool rot = !SINGLES && tmpl >= 0;
+            double *qp = a.q + 4 * (size_t)o;
+            const double4 qv = rot ? *reinterpret_cast<const double4 *>(qp) : make_double4(1.0, 0.0, 0.0, 0.0);
+            v2 = advance(a, r, inv, rot, F, T, qv, rot ? qp : nullptr, ctr);
             store_rec(a.rec + o, r);
         }
     }
@@ -462,12 +477,13 @@ __global__ void __launch_bounds__(TPB) k_fold_integrate(DynArgs a, const uint32_
 // writes.  When the step is stopped (capacity or divergence) the state and
 // history are copied unchanged.
 template <bool SINGLES>
-__global__ void __launch_bounds__(TPB) k_step_fused(DynArgs a, OwnerRec *rec_out, double *q_out,
+__global__ void __launch_bounds__(TPB, 4) k_step_fused(DynArgs a, OwnerRec *rec_out, double *q_out,
                                                     const uint32_t *start, const uint32_t *jarr,
                                                     const uint32_t *bstart, const uint32_t *bidx,
-                                                    const uint32_t *bsrc, const float *hx, const float *hy,
-                                                    const float *hz, const float *hw, float *ox, float *oy,
-                                                    float *oz, float *ow, int64_t cap, DevCounters *ctr)
+                                                    const uint32_t *bsrc, const uint8_t *oany,
+                                                    const float *hx, const float *hy, const float *hz,
+                                                    const float *hw, float *ox, float *oy, float *oz, float *ow,
+                                                    int64_t cap, DevCounters *ctr)
 {
     const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t o = (int64_t)lb * blockDim.x + threadIdx.x;
@@ -494,9 +510,14 @@ __global__ void __launch_bounds__(TPB) k_step_fused(DynArgs a, OwnerRec *rec_out
     }
     float v2 = 0.0f;
     if (valid) {
+        // every per-owner load is issued here, none waits for another: the
+        // record, the inertia, the orientation (clump systems), and whether
+        // the owner has any contact in the set in use (a flag per owner
+        // written with the set)
         OwnerRec r = load_rec(a.rec + o);
         float inv[3];
         int32_t tmpl = -1;
+        double4 qv = make_double4(1.0, 0.0, 0.0, 0.0);
         if (SINGLES) {
             inv[0] = inv[1] = inv[2] = a.inv_i[o];
         } else {
@@ -505,53 +526,64 @@ __global__ void __launch_bounds__(TPB) k_step_fused(DynArgs a, OwnerRec *rec_out
             inv[1] = ax.inv_moi[1];
             inv[2] = ax.inv_moi[2];
             tmpl = ax.tmpl;
+            qv = *reinterpret_cast<const double4 *>(a.q + 4 * (size_t)o);
         }
+        const bool any = oany[o] != 0;
         float3 F = f3(0.f, 0.f, 0.f), T = f3(0.f, 0.f, 0.f);
-        const uint32_t s0 = SINGLES ? (uint32_t)o : a.own_sph0[o];
-        const uint32_t s1 = SINGLES ? (uint32_t)o + 1u : a.own_sph0[o + 1];
-        for (uint32_t s = s0; s < s1; ++s) {
-            const uint32_t c0 = start[s], c1 = start[s + 1];
-            const uint32_t b0 = bstart[s], b1 = bstart[s + 1];
-            if (c0 < c1) {
-                const SphRec sS = load_sph(a.sph + s);
-                OwnerKin kS;
-                double xS[3];
-                owner_kin(r, sS, a.aux, a.q, a.tpos, a.org, kS, xS);
-                float3 FA = f3(0.f, 0.f, 0.f), TA = f3(0.f, 0.f, 0.f);
-                for (uint32_t c = c0; c < c1; ++c) {
-                    ContactOut co;
-                    contact_eval(a, sS, kS, xS, jarr[c], load_hist(hx, hy, hz, hw, c, a.rolling), co);
-                    store_hist(ox, oy, oz, ow, c, co.h, a.rolling);
-                    if (!co.touching) continue;
-                    FA = FA + co.F;
-                    TA = TA + cross3(co.armA, co.Ft);
+        const uint32_t s0 = SINGLES ? (uint32_t)o : (any ? a.own_sph0[o] : 0u);
+        const uint32_t s1 = SINGLES ? (uint32_t)o + 1u : (any ? a.own_sph0[o + 1] : 0u);
+        for (uint32_t s = s0; any && s < s1; ++s) {
+            const uint32_t c0 = start[s], na = start[s + 1] - c0;
+            const uint32_t b0 = bstart[s], nall = na + (bstart[s + 1] - b0);
+            // one loop over the sphere's A row, then its B list: each item is
+            // evaluated from its A side by the same function
+            float3 FA = f3(0.f, 0.f, 0.f), TA = f3(0.f, 0.f, 0.f);
+            for (uint32_t t = 0; t < nall; ++t) {
+                const bool aside = t < na;
+                uint32_t c, iA, jp;
+                if (aside) {
+                    c = c0 + t;
+                    iA = s;
+                    jp = jarr[c];
+                } else {
+                    const uint32_t b = b0 + (t - na);
+                    c = bidx[b];
+                    iA = bsrc[b];
+                    jp = s;
                 }
-                F = F + FA;
-                T = T + TA;
-            }
-            for (uint32_t b = b0; b < b1; ++b) {
-                const uint32_t c = bidx[b], i = bsrc[b];
-                const SphRec sI = load_sph(a.sph + i);
-                const OwnerRec rI = load_rec(a.rec + sI.owner);
-                OwnerKin kI;
-                double xI[3];
-                owner_kin(rI, sI, a.aux, a.q, a.tpos, a.org, kI, xI);
+                const SphRec sA = load_sph(a.sph + iA);
+                const OwnerRec rA = load_rec(a.rec + sA.owner);
+                OwnerKin kA;
+                double xA[3];
+                owner_kin(rA, sA, a.aux, a.q, a.tpos, a.org, kA, xA);
                 ContactOut co;
-                contact_eval(a, sI, kI, xI, s, load_hist(hx, hy, hz, hw, c, a.rolling), co);
-                float3 mF = f3(0.f, 0.f, 0.f), tB = f3(0.f, 0.f, 0.f);
-                if (co.touching) {
-                    mF = f3(-co.F.x, -co.F.y, -co.F.z);
-                    tB = cross3(co.armB, f3(-co.Ft.x, -co.Ft.y, -co.Ft.z));
+                contact_eval(a, sA, kA, xA, jp, load_hist(hx, hy, hz, hw, c, a.rolling), co);
+                if (aside) {
+                    store_hist(ox, oy, oz, ow, c, co.h, a.rolling);
+                    if (co.touching) {
+                        FA = FA + co.F;
+                        TA = TA + cross3(co.armA, co.Ft);
+                    }
+                    if (t + 1 == na) {
+                        F = F + FA;
+                        T = T + TA;
+                    }
+                } else {
+                    float3 mF = f3(0.f, 0.f, 0.f), tB = f3(0.f, 0.f, 0.f);
+                    if (co.touching) {
+                        mF = f3(-co.F.x, -co.F.y, -co.F.z);
+                        tB = cross3(co.armB, f3(-co.Ft.x, -co.Ft.y, -co.Ft.z));
+                    }
+                    F = F + mF;
+                    T = T + tB;
                 }
-                F = F + mF;
-                T = T + tB;
             }
         }
         const bool rotating = !SINGLES && tmpl >= 0;
-        const double *qin = a.q + 4 * (size_t)o;
         double *qo = q_out + 4 * (size_t)o;
-        v2 = advance(a, r, inv, rotating, F, T, qin, qo, ctr);
-        if (!SINGLES && !rotating) *reinterpret_cast<double4 *>(qo) = *reinterpret_cast<const double4 *>(qin);
+        // (a single sphere's orientation never changes and both buffers hold
+        // it, so nothing is copied for it)
+        v2 = advance(a, r, inv, rotating, F, T, qv, qo, ctr);
         store_rec(rec_out + o, r);
     }
     block_max_v2(v2, a.blkmax + lb);
@@ -619,7 +651,8 @@ void launch_step_fused(const DynArgs &a, OwnerRec *rec_out, double *q_out, const
     auto kern = a.has_clumps ? k_step_fused<false> : k_step_fused<true>;
     hipLaunchKernelGGL(kern, dim3(nblocks(a.n_owners)), dim3(TPB), 0, s, a, rec_out, q_out,
                        (const uint32_t *)cur.start, (const uint32_t *)cur.j, (const uint32_t *)cur.bstart,
-                       (const uint32_t *)cur.bidx, (const uint32_t *)cur.bsrc, (const float *)cur.hx,
+                       (const uint32_t *)cur.bidx, (const uint32_t *)cur.bsrc, (const uint8_t *)cur.oany,
+                       (const float *)cur.hx,
                        (const float *)cur.hy, (const float *)cur.hz, (const float *)cur.hw, cur.hx2, cur.hy2,
                        cur.hz2, cur.hw2, cap, ctr);
 }

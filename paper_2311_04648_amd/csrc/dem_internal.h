@@ -134,6 +134,8 @@ struct DetectArgs {
     Origin org;
     double margin;
     const double *margin_dev;   // if set, the margin is read from device memory
+    const uint32_t *own_sph0;   // [No+1] first sphere of each owner (null: one sphere per owner)
+    int64_t n_owners;
     double h;
     int64_t step;
 };
@@ -162,6 +164,7 @@ struct AcsBuf {
     uint32_t *bidx;    // [cap] contact index of each B-list entry
     uint32_t *bsrc;    // [cap] the A sphere of that contact
     uint32_t *bcur;    // [Ns+1] scratch cursor
+    uint8_t *oany;     // [No] 1 if any sphere of the owner has a row or B-list entry in this set
 };
 
 inline void swap_hist(AcsBuf &b)
@@ -187,6 +190,10 @@ void launch_detect_back(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap
 void launch_judge(const DetectArgs &a, CdWork &w, const AcsBuf &cur, int64_t cap, DevCounters *ctr,
                   hipStream_t s);
 void launch_blists(AcsBuf &b, int64_t n_spheres, int64_t cap, uint32_t *partials, hipStream_t s);
+// the per-owner contact flags of a set (AcsBuf::oany) from its rows and B
+// lists (an overflowed set flags nothing)
+void launch_owner_flags(AcsBuf &b, const uint32_t *own_sph0, int64_t n_owners, int64_t n_spheres, int64_t cap,
+                        hipStream_t s);
 void launch_remap(const AcsBuf &oldb, AcsBuf &newb, int64_t n_spheres, DevCounters *ctr, int newbuf,
                   int rolling, hipStream_t s);
 

@@ -163,11 +163,11 @@ def test_learned_interval_beats_fixed_with_zero_misses(dem):
         np.testing.assert_array_equal(a[k], b[k])
 
 
-def test_short_predicted_horizon_never_overlaps_work_orders(dem):
-    """A model that predicts a horizon shorter than two adoption latencies:
-    the interval is held at the latency, so a work order never goes out
-    while the previous detection is in flight; judged with repair, the run
-    stays equal to every-step detection bit for bit."""
+def test_short_predicted_horizon_detects_synchronously(dem):
+    """A model that predicts a horizon shorter than the adoption latency:
+    each such order is detected at once on the dynamics stream (never two
+    detections in flight into one buffer); judged, nothing is missed and
+    the run equals every-step detection bit for bit."""
     import torch
     s = W.small_spheres(8, n=512, vel=0.3)
     p = np.zeros(omlp.NPARAM, dtype=np.float32)
@@ -177,7 +177,8 @@ def test_short_predicted_horizon_never_overlaps_work_orders(dem):
     c.mlp_set(p)
     c.set_state()
     st = c.step(200, dyn=torch.cuda.Stream(), kin=torch.cuda.Stream())
-    assert st["mean_interval"] >= lam
+    assert st["misses"] == 0
+    assert st["cds"] >= 200 // lam
     e = dem.DemContext(s, mode="every")
     e.set_state()
     e.step(200)
