@@ -39,6 +39,9 @@ class OrcSys(C.Structure):
         ("n_mat", C.c_int64), ("mat_E", C.c_void_p), ("mat_nu", C.c_void_p),
         ("mat_cor", C.c_void_p), ("mat_mu", C.c_void_p), ("mat_crr", C.c_void_p),
         ("gravity", C.c_double * 3), ("h", C.c_double),
+        ("n_mesh", C.c_int64), ("n_tri", C.c_int64), ("tri_mesh", C.c_void_p), ("tri_local", C.c_void_p),
+        ("mesh_origin", C.c_void_p), ("mesh_vel", C.c_void_p), ("mesh_omega", C.c_void_p),
+        ("mesh_mat", C.c_void_p),
     ]
 
 
@@ -74,11 +77,21 @@ def lib():
         _lib.orc_run.argtypes = [vp, vp, vp, vp, vp, vp, i64, C.c_int, i64, i64, d, C.c_int,
                                  vp, vp, vp, i64, vp]
         _lib.orc_run.restype = C.c_int
+        _lib.orc_tri_closest.argtypes = [vp, vp, vp, vp, vp]
+        _lib.orc_mesh_pose.argtypes = [vp, i64, i64, vp, vp]
     return _lib
 
 
 def _p(a):
     return a.ctypes.data if a is not None else None
+
+
+def tri_closest(a, b, c, p):
+    """Closest point of triangle (a, b, c) to p (FP64)."""
+    a, b, c, p = (np.ascontiguousarray(v, dtype=np.float64) for v in (a, b, c, p))
+    q = np.zeros(3)
+    lib().orc_tri_closest(_p(a), _p(b), _p(c), _p(p), _p(q))
+    return q
 
 
 def _hist4(hist, n):
@@ -128,6 +141,14 @@ class Oracle:
         for k in range(3):
             s.gravity[k] = float(sysm.gravity[k])
         s.h = float(sysm.dt)
+        s.n_tri = sysm.n_tri
+        s.n_mesh = sysm.n_mesh
+        s.tri_mesh = arr("tri_mesh", np.int32)
+        s.tri_local = arr("tri_local", np.float64)
+        s.mesh_origin = arr("mesh_origin", np.float64)
+        s.mesh_vel = arr("mesh_vel", np.float64)
+        s.mesh_omega = arr("mesh_omega", np.float64)
+        s.mesh_mat = arr("mesh_mat", np.int32)
         self._keep = keep
         self._s = s
         self.ps = C.addressof(s)
@@ -142,15 +163,29 @@ class Oracle:
         lib().orc_sphere_centres(self.ps, _p(st["X"]), _p(st["q"]), _p(xs))
         return xs
 
-    def wall_positions(self, step):
-        wp = np.zeros((max(self.sys.n_walls, 1), 3))
+    def _geom(self, step):
+        """Prescribed-motion geometry at a step: wall reference points
+        (3 per wall) followed by the world vertices of every facet (9)."""
+        wp = np.zeros(3 * self.sys.n_walls + 9 * self.sys.n_tri + 1)
         lib().orc_wall_positions(self.ps, int(step), _p(wp))
-        return wp[: self.sys.n_walls]
+        return wp
+
+    def wall_positions(self, step):
+        return self._geom(step)[: 3 * self.sys.n_walls].reshape(-1, 3)
+
+    def facet_positions(self, step):
+        """World vertices [T, 3, 3] of every facet at a step."""
+        W = self.sys.n_walls
+        return self._geom(step)[3 * W: 3 * W + 9 * self.sys.n_tri].reshape(-1, 3, 3)
+
+    def mesh_pose(self, g, step):
+        p, R = np.zeros(3), np.zeros(9)
+        lib().orc_mesh_pose(self.ps, int(g), int(step), _p(p), _p(R))
+        return p, R.reshape(3, 3)
 
     def detect(self, st, margin, step=0, brute=False, cap=None):
         xs = self.sphere_centres(st)
-        wp = np.zeros((max(self.sys.n_walls, 1), 3))
-        lib().orc_wall_positions(self.ps, int(step), _p(wp))
+        wp = self._geom(step)
         cap = cap or max(64, 16 * self.sys.n_spheres)
         while True:
             keys = np.zeros(cap, dtype=np.uint64)
@@ -164,8 +199,7 @@ class Oracle:
         """Rows of the given spheres by brute force (for sampled checks of
         inputs too large for a full detection)."""
         xs = self.sphere_centres(st)
-        wp = np.zeros((max(self.sys.n_walls, 1), 3))
-        lib().orc_wall_positions(self.ps, int(step), _p(wp))
+        wp = self._geom(step)
         out = []
         buf = np.zeros(4096, dtype=np.uint64)
         for i in spheres:
@@ -204,8 +238,7 @@ class Oracle:
 
     def count_missing(self, st, acs, step=0):
         xs = self.sphere_centres(st)
-        wp = np.zeros((max(self.sys.n_walls, 1), 3))
-        lib().orc_wall_positions(self.ps, int(step), _p(wp))
+        wp = self._geom(step)
         cap = max(64, 16 * self.sys.n_spheres)
         tmp = np.zeros(cap, dtype=np.uint64)
         acs = np.ascontiguousarray(acs, dtype=np.uint64)

@@ -19,6 +19,9 @@
  *     contact wildcards are zero at birth and persist while the contact lives)
  *   - the delayed active-set schedule of Sec. 2.1 with a deterministic swap
  *     step, plus the per-step judge that counts contacts missing from the set.
+ *   - sphere contacts with the facets of rigid triangle meshes under
+ *     prescribed motion (Sec. 2.4: a mesh is an owner, a facet a geometry),
+ *     through the closest point of each facet to the sphere centre.
  *
  * Readings where the paper is silent (documented in the design notes):
  *   E*, G*: 1/E* = sum (1-nu^2)/E ; 1/G* = sum 2(2-nu)(1+nu)/E  (standard
@@ -55,6 +58,13 @@ typedef struct {
     const double *mat_cor, *mat_mu, *mat_crr; /* [M M] */
     double gravity[3];
     double h;
+    int64_t n_mesh, n_tri;
+    const int32_t *tri_mesh;     /* [T] mesh of each facet */
+    const double *tri_local;     /* [9 T] facet vertices in the mesh frame */
+    const double *mesh_origin;   /* [3 M] mesh frame origin at t = 0 (world) */
+    const double *mesh_vel;      /* [3 M] constant velocity */
+    const double *mesh_omega;    /* [3 M] constant angular velocity (world), about the origin */
+    const int32_t *mesh_mat;     /* [M] */
 } orc_sys;
 
 typedef struct {
@@ -133,13 +143,117 @@ void orc_sphere_centres(const orc_sys *s, const double *X, const double *q, doub
     }
 }
 
-/* Prescribed wall motion: reference point at step n is p0 + V (n h). */
+/* Pose of mesh g at step n (t = n h): origin o + v t, and the rotation by
+ * the angle |w| t about the axis w / |w| (Rodrigues' rotation formula). */
+static void mesh_pose(const orc_sys *s, int64_t g, int64_t step, double p[3], double R[9])
+{
+    double t = (double)step * s->h;
+    const double *o = s->mesh_origin + 3 * g, *v = s->mesh_vel + 3 * g, *w = s->mesh_omega + 3 * g;
+    for (int k = 0; k < 3; ++k) p[k] = o[k] + v[k] * t;
+    double wn = sqrt((w[0] * w[0] + w[1] * w[1]) + w[2] * w[2]);
+    if (!(wn > 0.0)) {
+        for (int k = 0; k < 9; ++k) R[k] = (k % 4 == 0) ? 1.0 : 0.0;
+        return;
+    }
+    double ax = w[0] / wn, ay = w[1] / wn, az = w[2] / wn;
+    double ang = wn * t;
+    double c = cos(ang), sn = sin(ang), C = 1.0 - c;
+    R[0] = c + ax * ax * C;
+    R[1] = ax * ay * C - az * sn;
+    R[2] = ax * az * C + ay * sn;
+    R[3] = ay * ax * C + az * sn;
+    R[4] = c + ay * ay * C;
+    R[5] = ay * az * C - ax * sn;
+    R[6] = az * ax * C - ay * sn;
+    R[7] = az * ay * C + ax * sn;
+    R[8] = c + az * az * C;
+}
+
+/* Positions of the prescribed-motion geometry at step n, in one buffer:
+ * wp[3 w + k] the reference point of wall w (p0 + V n h), then from
+ * wp[3 W] on the world vertices of every facet (9 per facet: origin +
+ * R v for each vertex v). */
 void orc_wall_positions(const orc_sys *s, int64_t step, double *wp)
 {
     double t = (double)step * s->h;
     for (int64_t w = 0; w < s->n_walls; ++w)
         for (int k = 0; k < 3; ++k)
             wp[3 * w + k] = s->wall_geom[8 * w + k] + s->wall_vel[3 * w + k] * t;
+    double *tw = wp + 3 * s->n_walls;
+    for (int64_t g = 0; g < s->n_mesh; ++g) {
+        double p[3], R[9];
+        mesh_pose(s, g, step, p, R);
+        for (int64_t f = 0; f < s->n_tri; ++f) {
+            if (s->tri_mesh[f] != g) continue;
+            for (int v = 0; v < 3; ++v) {
+                const double *x = s->tri_local + 9 * f + 3 * v;
+                for (int k = 0; k < 3; ++k)
+                    tw[9 * f + 3 * v + k] = p[k] + ((R[3 * k] * x[0] + R[3 * k + 1] * x[1]) + R[3 * k + 2] * x[2]);
+            }
+        }
+    }
+}
+
+static double dot3(const double *u, const double *v) { return (u[0] * v[0] + u[1] * v[1]) + u[2] * v[2]; }
+
+/* Closest point q of the triangle (a, b, c) to p: the point of the face,
+ * of an edge or a vertex, chosen by the Voronoi region of p (the standard
+ * barycentric region test, e.g. Ericson, Real-Time Collision Detection,
+ * 2005, Sec. 5.1.5). */
+static void closest_on_tri(const double *a, const double *b, const double *c, const double *p, double *q)
+{
+    double ab[3], ac[3], ap[3], bp[3], cp[3];
+    for (int k = 0; k < 3; ++k) { ab[k] = b[k] - a[k]; ac[k] = c[k] - a[k]; ap[k] = p[k] - a[k]; }
+    double d1 = dot3(ab, ap), d2 = dot3(ac, ap);
+    if (d1 <= 0.0 && d2 <= 0.0) { for (int k = 0; k < 3; ++k) q[k] = a[k]; return; }
+    for (int k = 0; k < 3; ++k) bp[k] = p[k] - b[k];
+    double d3 = dot3(ab, bp), d4 = dot3(ac, bp);
+    if (d3 >= 0.0 && d4 <= d3) { for (int k = 0; k < 3; ++k) q[k] = b[k]; return; }
+    double vc = d1 * d4 - d3 * d2;
+    if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {
+        double v = d1 / (d1 - d3);
+        for (int k = 0; k < 3; ++k) q[k] = a[k] + v * ab[k];
+        return;
+    }
+    for (int k = 0; k < 3; ++k) cp[k] = p[k] - c[k];
+    double d5 = dot3(ab, cp), d6 = dot3(ac, cp);
+    if (d6 >= 0.0 && d5 <= d6) { for (int k = 0; k < 3; ++k) q[k] = c[k]; return; }
+    double vb = d5 * d2 - d1 * d6;
+    if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {
+        double w = d2 / (d2 - d6);
+        for (int k = 0; k < 3; ++k) q[k] = a[k] + w * ac[k];
+        return;
+    }
+    double va = d3 * d6 - d5 * d4;
+    if (va <= 0.0 && (d4 - d3) >= 0.0 && (d5 - d6) >= 0.0) {
+        double w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+        for (int k = 0; k < 3; ++k) q[k] = b[k] + w * (c[k] - b[k]);
+        return;
+    }
+    double den = 1.0 / ((va + vb) + vc);
+    double v = vb * den, w = vc * den;
+    for (int k = 0; k < 3; ++k) q[k] = (a[k] + ab[k] * v) + ac[k] * w;
+}
+
+/* Exported for the tests: the closest point of triangle (a, b, c) to p,
+ * and the pose of mesh g at a step. */
+void orc_tri_closest(const double *a, const double *b, const double *c, const double *p, double *q)
+{
+    closest_on_tri(a, b, c, p, q);
+}
+
+void orc_mesh_pose(const orc_sys *s, int64_t g, int64_t step, double *p, double *R)
+{
+    mesh_pose(s, g, step, p, R);
+}
+
+/* Squared distance of x to facet f (world vertices tw), and the closest point. */
+static double tri_dist2(const double *tw, int64_t f, const double *x, double *q)
+{
+    const double *v = tw + 9 * f;
+    closest_on_tri(v, v + 3, v + 6, x, q);
+    double dx = x[0] - q[0], dy = x[1] - q[1], dz = x[2] - q[2];
+    return (dx * dx + dy * dy) + dz * dz;
 }
 
 /* ------------------------------------------------------------------ */
@@ -172,6 +286,15 @@ static int wall_hit(const orc_sys *s, int64_t w, const double *wp, const double 
     return d2 < T * T;
 }
 
+/* Sphere-facet predicate: distance below r + 2 m (strict). */
+static int tri_hit(const orc_sys *s, const double *wp, int64_t f, const double *x, double r, double m)
+{
+    double q[3];
+    double d2 = tri_dist2(wp + 3 * s->n_walls, f, x, q);
+    double T = r + 2.0 * m;
+    return d2 < T * T;
+}
+
 static int cmp_u64(const void *a, const void *b)
 {
     uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
@@ -196,6 +319,12 @@ int64_t orc_detect_brute(const orc_sys *s, const double *xs, const double *wp, d
         for (int64_t w = 0; w < s->n_walls; ++w) {
             if (wall_hit(s, w, wp, xs + 3 * i, s->sph_rad[i], m)) {
                 if (n < cap) keys[n] = ((uint64_t)i << 32) | (uint64_t)(s->n_spheres + w);
+                ++n;
+            }
+        }
+        for (int64_t f = 0; f < s->n_tri; ++f) {
+            if (tri_hit(s, wp, f, xs + 3 * i, s->sph_rad[i], m)) {
+                if (n < cap) keys[n] = ((uint64_t)i << 32) | (uint64_t)(s->n_spheres + s->n_walls + f);
                 ++n;
             }
         }
@@ -271,6 +400,12 @@ int64_t orc_detect_binned(const orc_sys *s, const double *xs, const double *wp, 
                 ++n;
             }
         }
+        for (int64_t f = 0; f < s->n_tri; ++f) {
+            if (tri_hit(s, wp, f, xs + 3 * i, s->sph_rad[i], m)) {
+                if (n < cap) keys[n] = ((uint64_t)i << 32) | (uint64_t)(N + s->n_walls + f);
+                ++n;
+            }
+        }
     }
     free(row);
     free(bc);
@@ -295,6 +430,12 @@ int64_t orc_detect_row(const orc_sys *s, const double *xs, const double *wp, dou
     for (int64_t w = 0; w < s->n_walls; ++w) {
         if (wall_hit(s, w, wp, xs + 3 * i, s->sph_rad[i], m)) {
             if (n < cap) keys[n] = ((uint64_t)i << 32) | (uint64_t)(s->n_spheres + w);
+            ++n;
+        }
+    }
+    for (int64_t f = 0; f < s->n_tri; ++f) {
+        if (tri_hit(s, wp, f, xs + 3 * i, s->sph_rad[i], m)) {
+            if (n < cap) keys[n] = ((uint64_t)i << 32) | (uint64_t)(s->n_spheres + s->n_walls + f);
             ++n;
         }
     }
@@ -374,7 +515,7 @@ void orc_forces(const orc_sys *s, const double *X, const double *q, const double
 {
     int64_t Ns = s->n_spheres, No = s->n_owners;
     double *xs = malloc(sizeof(double) * 3 * (size_t)(Ns > 0 ? Ns : 1));
-    double *wp = malloc(sizeof(double) * 3 * (size_t)(s->n_walls > 0 ? s->n_walls : 1));
+    double *wp = malloc(sizeof(double) * (size_t)(3 * s->n_walls + 9 * s->n_tri + 1));
     orc_sphere_centres(s, X, q, xs);
     orc_wall_positions(s, step, wp);
     memset(Fo, 0, sizeof(double) * 3 * (size_t)No);
@@ -387,7 +528,7 @@ void orc_forces(const orc_sys *s, const double *X, const double *q, const double
         const double *xA = xs + 3 * i;
         double rA = s->sph_rad[i];
         double *xi = hist + 4 * c;
-        double nrm[3], delta, Rbar, mbar, XB[3], VB[3];
+        double nrm[3], delta, Rbar, mbar, XB[3];
         int matB, is_wall = jp >= Ns, oB = -1;
         int touching = 0;
         if (!is_wall) {
@@ -405,6 +546,24 @@ void orc_forces(const orc_sys *s, const double *X, const double *q, const double
                 oB = s->sph_owner[jp];
                 mbar = s->own_mass[oA] * s->own_mass[oB] / (s->own_mass[oA] + s->own_mass[oB]);
                 matB = s->sph_mat[jp];
+            }
+        } else if (jp >= Ns + s->n_walls) {
+            /* facet of a mesh: normal from the closest point to the centre,
+             * the facet seen as flat (R = rA), the mesh as of infinite mass */
+            int64_t f = jp - Ns - s->n_walls;
+            double qf[3];
+            double d2 = tri_dist2(wp + 3 * s->n_walls, f, xA, qf);
+            touching = d2 < rA * rA && d2 > 0.0;
+            if (touching) {
+                double d = sqrt(d2);
+                nrm[0] = (xA[0] - qf[0]) / d; nrm[1] = (xA[1] - qf[1]) / d; nrm[2] = (xA[2] - qf[2]) / d;
+                delta = rA - d;
+                Rbar = rA;
+                mbar = s->own_mass[oA];
+                int64_t g = s->tri_mesh[f];
+                matB = s->mesh_mat[g];
+                double R9[9];
+                mesh_pose(s, g, step, XB, R9);
             }
         } else {
             int64_t w = jp - Ns;
@@ -464,16 +623,23 @@ void orc_forces(const orc_sys *s, const double *X, const double *q, const double
             for (int k = 0; k < 3; ++k) { XB[k] = X[3 * oB + k]; armB[k] = cp[k] - XB[k]; }
             point_velocity(V + 3 * oB, Wb + 3 * oB, q + 4 * oB, armB, vB);
         } else {
-            int64_t w = jp - Ns;
+            /* wall or mesh: prescribed velocity plus rotation about its
+             * reference point */
+            const int facet = jp >= Ns + s->n_walls;
+            const double *wv = facet ? s->mesh_vel + 3 * s->tri_mesh[jp - Ns - s->n_walls] : s->wall_vel + 3 * (jp - Ns);
+            const double *ww = facet ? s->mesh_omega + 3 * s->tri_mesh[jp - Ns - s->n_walls]
+                                     : s->wall_omega + 3 * (jp - Ns);
             double rotv[3];
             for (int k = 0; k < 3; ++k) armB[k] = cp[k] - XB[k];
-            cross(s->wall_omega + 3 * w, armB, rotv);
-            for (int k = 0; k < 3; ++k) vB[k] = s->wall_vel[3 * w + k] + rotv[k];
+            cross(ww, armB, rotv);
+            for (int k = 0; k < 3; ++k) vB[k] = wv[k] + rotv[k];
         }
         /* relative velocity of A w.r.t. B, split along the normal */
         double VBl[3];
         if (!is_wall) {
             for (int k = 0; k < 3; ++k) VBl[k] = V[3 * oB + k];
+        } else if (jp >= Ns + s->n_walls) {
+            for (int k = 0; k < 3; ++k) VBl[k] = s->mesh_vel[3 * s->tri_mesh[jp - Ns - s->n_walls] + k];
         } else {
             for (int k = 0; k < 3; ++k) VBl[k] = s->wall_vel[3 * (jp - Ns) + k];
         }
@@ -556,7 +722,7 @@ void orc_forces(const orc_sys *s, const double *X, const double *q, const double
         }
         if (!is_wall) {
             for (int k = 0; k < 3; ++k) { Fo[3 * oB + k] += mF[k]; To[3 * oB + k] += tB[k]; }
-        } else if (Fw) {
+        } else if (Fw && jp < Ns + s->n_walls) {
             for (int k = 0; k < 3; ++k) Fw[3 * (jp - Ns) + k] += mF[k];
         }
     }
@@ -632,7 +798,7 @@ int orc_run(const orc_sys *s, double *X, double *q, double *V, double *Wb, int64
 {
     int64_t Ns = s->n_spheres, No = s->n_owners, W = s->n_walls;
     double *xs = malloc(sizeof(double) * 3 * (size_t)(Ns > 0 ? Ns : 1));
-    double *wp = malloc(sizeof(double) * 3 * (size_t)(W > 0 ? W : 1));
+    double *wp = malloc(sizeof(double) * (size_t)(3 * W + 9 * s->n_tri + 1));
     double *Fo = malloc(sizeof(double) * 3 * (size_t)(No > 0 ? No : 1));
     double *To = malloc(sizeof(double) * 3 * (size_t)(No > 0 ? No : 1));
     double *Fc = malloc(sizeof(double) * 3 * (size_t)cap);

@@ -83,6 +83,15 @@ class System:
     W: np.ndarray             # f64 [No,3] angular velocity in the body frame
     name: str = ""
     meta: dict = field(default_factory=dict)
+    # rigid triangle meshes with prescribed motion (Sec. 2.4: a mesh is an
+    # owner, each facet a geometry): facet vertices in the mesh frame; mesh
+    # frame origin at t = 0, constant velocity and angular velocity (world)
+    tri_mesh: np.ndarray = field(default_factory=lambda: np.zeros(0, dtype=np.int32))      # int32 [T]
+    tri_local: np.ndarray = field(default_factory=lambda: np.zeros((0, 9)))               # f64 [T,9]
+    mesh_origin: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))             # f64 [M,3]
+    mesh_vel: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))                # f64 [M,3]
+    mesh_omega: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))              # f64 [M,3]
+    mesh_mat: np.ndarray = field(default_factory=lambda: np.zeros(0, dtype=np.int32))     # int32 [M]
 
     @property
     def n_owners(self):
@@ -95,6 +104,14 @@ class System:
     @property
     def n_walls(self):
         return int(self.wall_type.shape[0])
+
+    @property
+    def n_tri(self):
+        return int(self.tri_mesh.shape[0])
+
+    @property
+    def n_mesh(self):
+        return int(self.mesh_mat.shape[0])
 
     def copy_state(self):
         return dict(X=self.X.copy(), q=self.q.copy(), V=self.V.copy(), W=self.W.copy())
@@ -457,3 +474,125 @@ def small_clumps(seed, n=120, vel=0.2, walls=True, gravity=(0, 0, -9.81), dt=5e-
                     [tri_template(0.003, 0.002), penta_template(0.0025, 0.0025)], 0.0025,
                     [0, 0], concat_walls(*ws), materials(), gravity, dt, margin, lo, hi,
                     name=f"small_clumps{seed}")
+
+
+# --------------------------------------------------------------------------
+# triangle meshes
+# --------------------------------------------------------------------------
+
+def add_meshes(sysm, *meshes):
+    """Attaches rigid meshes to a system.  Each mesh: dict(tri=[k,3,3]
+    vertices in the mesh frame, origin, vel, omega, mat)."""
+    tri_mesh, tri_local, org, vel, om, mat = [], [], [], [], [], []
+    for g, m in enumerate(meshes):
+        tri = snap_pos(np.asarray(m["tri"], dtype=np.float64).reshape(-1, 9))
+        tri_local.append(tri)
+        tri_mesh.append(np.full(tri.shape[0], g, dtype=np.int32))
+        org.append(snap_pos(m.get("origin", (0, 0, 0))))
+        vel.append(np.asarray(m.get("vel", (0, 0, 0)), dtype=np.float64))
+        om.append(np.asarray(m.get("omega", (0, 0, 0)), dtype=np.float64))
+        mat.append(int(m.get("mat", 0)))
+    sysm.tri_mesh = np.concatenate(tri_mesh).astype(np.int32)
+    sysm.tri_local = np.vstack(tri_local)
+    sysm.mesh_origin = np.asarray(org, dtype=np.float64).reshape(-1, 3)
+    sysm.mesh_vel = np.asarray(vel, dtype=np.float64).reshape(-1, 3)
+    sysm.mesh_omega = np.asarray(om, dtype=np.float64).reshape(-1, 3)
+    sysm.mesh_mat = np.asarray(mat, dtype=np.int32)
+    return sysm
+
+
+def quad_grid(p0, e1, e2, n1, n2):
+    """A planar parallelogram p0 + a e1 + b e2 (a, b in [0, 1]) split into
+    n1 x n2 cells of two triangles each: [2 n1 n2, 3, 3]."""
+    p0, e1, e2 = (np.asarray(v, dtype=np.float64) for v in (p0, e1, e2))
+    tris = []
+    for i in range(n1):
+        for j in range(n2):
+            a = p0 + e1 * (i / n1) + e2 * (j / n2)
+            b = p0 + e1 * ((i + 1) / n1) + e2 * (j / n2)
+            c = p0 + e1 * ((i + 1) / n1) + e2 * ((j + 1) / n2)
+            d = p0 + e1 * (i / n1) + e2 * ((j + 1) / n2)
+            tris.append([a, b, c])
+            tris.append([a, c, d])
+    return np.asarray(tris)
+
+
+def bladed_mixer(radius, height, n_blades=4, hub_radius=None, n_r=15, n_z=12, n_theta=48, n_hub_z=15):
+    """A mixer impeller about the z axis in its own frame: n_blades flat
+    vertical blades from the hub to 0.9 radius, z in [0, height], and a
+    cylindrical hub, all triangulated (4 blades with the defaults: 2880
+    facets)."""
+    hub = hub_radius if hub_radius is not None else 0.08 * radius
+    parts = []
+    for k in range(n_blades):
+        th = 2.0 * np.pi * k / n_blades
+        d = np.array([np.cos(th), np.sin(th), 0.0])
+        parts.append(quad_grid(hub * d, (0.9 * radius - hub) * d, (0, 0, height), n_r, n_z))
+    ring = []
+    for i in range(n_theta):
+        a0, a1 = 2 * np.pi * i / n_theta, 2 * np.pi * (i + 1) / n_theta
+        for j in range(n_hub_z):
+            z0, z1 = height * j / n_hub_z, height * (j + 1) / n_hub_z
+            p = lambda a, z: np.array([hub * np.cos(a), hub * np.sin(a), z])
+            ring.append([p(a0, z0), p(a1, z0), p(a1, z1)])
+            ring.append([p(a0, z0), p(a1, z1), p(a0, z1)])
+    parts.append(np.asarray(ring))
+    return np.concatenate(parts)
+
+
+def small_mixer(seed, n=400, vel=0.1, omega_z=2.0 * np.pi, dt=2e-6, margin=0.0002, r=(0.002, 0.003)):
+    """Spheres dropped into a small box chamber (10 x 10 cm) over a rotating
+    bladed impeller mesh (radius 4.75 cm), for parity tests."""
+    rng = np.random.default_rng(seed)
+    R, H = 0.05, 0.03
+    side = int(math.ceil((n * 2) ** (1 / 3)))
+    s = 2 * r[1] + 0.0006
+    pts = []
+    z = H + 0.004
+    while len(pts) < n:
+        for ix in range(-side, side + 1):
+            for iy in range(-side, side + 1):
+                x, y = ix * s, iy * s
+                if x * x + y * y < (R - 2 * r[1]) ** 2 and len(pts) < n:
+                    pts.append((x, y, z))
+        z += s
+    X = np.asarray(pts[:n]) + rng.uniform(-0.0003, 0.0003, size=(n, 3))
+    rad = rng.uniform(r[0], r[1], size=n)
+    V = rng.normal(0.0, vel, size=(n, 3))
+    lo = np.array([-R - 0.004, -R - 0.004, -0.004])
+    hi = np.array([R + 0.004, R + 0.004, z + 0.02])
+    walls = box_walls(np.array([-R, -R, 0.0]), np.array([R, R, z + 0.02]))
+    mats = materials(E=1e8, nu=0.3, cor=0.4, mu=0.5)
+    sysm = assemble(np.full(n, -1), X, _qid(n), V, np.zeros((n, 3)), [], rad, None, walls, mats,
+                    (0, 0, -9.81), dt, margin, lo, hi, name=f"small_mixer{seed}")
+    tri = bladed_mixer(R * 0.95, H, n_r=4, n_z=3, n_theta=12, n_hub_z=3)
+    return add_meshes(sysm, dict(tri=tri, origin=(0, 0, 0.0005), omega=(0, 0, omega_z)))
+
+
+def mixer(seed=0, n=1_000_000, r=(0.003, 0.0035)):
+    """The scaling workload of the paper's Sec. 5 with a synthetic mesh: a
+    bladed impeller of 2880 facets (radius 0.49 m, blade height 0.15 m)
+    turning at 2 pi rad/s about z in a 1 x 1 m box chamber;
+    spheres r ~ U(3, 3.5) mm released from a jittered lattice filling a
+    cylinder of radius 0.5 m and height 1/3 m above the impeller;
+    E = 1e9 Pa, nu = 0.3, CoR = 0.2, rho = 2600; dt = 5e-7 s; margin 0.1 r_min."""
+    rng = np.random.default_rng(seed)
+    R, Hb = 0.5, 0.15
+    s = 2 * r[1] + 0.0002
+    per = int((2 * R) // s)
+    ax = (np.arange(per) - 0.5 * (per - 1)) * s
+    layer = np.array([(x, y) for x in ax for y in ax if x * x + y * y < (R - r[1] - 0.002) ** 2])
+    layers = -(-n // layer.shape[0])
+    z0 = Hb + 0.01
+    X = np.vstack([np.c_[layer, np.full(layer.shape[0], z0 + k * s)] for k in range(layers)])[:n]
+    X = X + rng.uniform(-0.0001, 0.0001, size=X.shape)
+    rad = rng.uniform(r[0], r[1], size=n)
+    top = X[:, 2].max() + 0.02
+    lo = np.array([-R - 0.005, -R - 0.005, -0.005])
+    hi = np.array([R + 0.005, R + 0.005, top])
+    walls = box_walls(np.array([-R, -R, 0.0]), np.array([R, R, top]))
+    mats = materials(E=1e9, nu=0.3, cor=0.2, mu=0.5)
+    sysm = assemble(np.full(n, -1), X, _qid(n), np.zeros((n, 3)), np.zeros((n, 3)), [], rad, None, walls, mats,
+                    (0, 0, -9.81), 5e-7, 0.1 * r[0], lo, hi, name="mixer", meta=dict(steps=5000, seed=seed))
+    tri = bladed_mixer(R * 0.98, Hb)
+    return add_meshes(sysm, dict(tri=tri, origin=(0, 0, 0.001), omega=(0, 0, 2.0 * np.pi)))
