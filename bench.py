@@ -41,7 +41,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=1_000_000, help="spheres of the config-1 workload")
     ap.add_argument("--workload", default="config1",
-                    help="config1 (headline) | config2 | config3 | config4: other sizes for the design notes")
+                    help="config1 (headline) | config2 | config3 | config4: other sizes for the design notes | "
+                         "mixer: the bladed-mixer bed with a 2880-facet impeller")
     ap.add_argument("--modes", default="fixed,every,learned,analytic,adaptive",
                     help="schedules: fixed (k steps), every (every step), learned (MLP interval), "
                          "analytic (the learned schedule's fallback bound alone, no network), "
@@ -193,6 +194,8 @@ def main():
         sysm = W.config3(seed=7)
     elif args.workload == "config4":
         sysm = W.config4(seed=0)
+    elif args.workload == "mixer":
+        sysm = W.mixer(seed=0)
     else:
         raise SystemExit(f"unknown workload {args.workload}")
     print(f"# workload generated: {sysm.n_spheres} spheres in {time.perf_counter() - t_gen:.1f}s",
@@ -274,7 +277,8 @@ def main():
                 "note": "detection chain on the second stream, concurrent with the dynamics stream"}
 
     cpu = None
-    if not args.no_cpu and Ns <= 10_000_000:
+    n_tri = int(getattr(sysm, "n_tri", 0))
+    if not args.no_cpu and Ns <= 10_000_000 and n_tri == 0:
         import oracle
         o = oracle.Oracle(sysm)
         ost = o.state()
@@ -351,7 +355,11 @@ def main():
         "config": {"workload": (f"{Ns} polydisperse spheres r~U(2,3) mm settling from a jittered 7.5 mm lattice "
                                 f"in a 0.6x0.6x1.2 m box, dt 5e-6 s, margin 0.2 mm, delayed CD every {args.k} "
                                 f"steps on a second HIP stream (adoption latency {args.lam})")
-                   if args.workload == "config1" else f"{args.workload}: {Ns} spheres, {No} owners",
+                   if args.workload == "config1" else
+                   (f"{Ns} spheres r~U(3,3.5) mm in a bed around a {n_tri}-facet bladed impeller (radius 0.49 m) "
+                    f"turning at 2 pi rad/s in a 1x1 m box chamber, dt 5e-7 s, margin 0.3 mm, delayed CD every "
+                    f"{args.k} steps on a second HIP stream (adoption latency {args.lam})")
+                   if args.workload == "mixer" else f"{args.workload}: {Ns} spheres, {No} owners",
                    "n_spheres": Ns, "n_owners": No, "schedule": head, "k": args.k, "lambda": args.lam,
                    "dynamics": "one fused kernel per step" if args.dyn_path == 0 else "force + fold kernels"},
         "modes": modes_out,
@@ -360,6 +368,13 @@ def main():
         "cd_chain": cd_chain,
         "cpu_baseline": cpu,
     }
+    if n_tri:
+        out["config"]["n_facets"] = n_tri
+        # the paper's own mixer figure, for context only (2 A100s, its own
+        # 2892-facet mesh after 1 s of mixing): 0.546 h per 1e6 steps per 1e6 spheres
+        out["paper_mixer_sphere_steps_per_s"] = 5.09e8
+        out["cpu_baseline_note"] = ("not run for this workload: the oracle tests every facet against every "
+                                    "sphere (about 3e9 closest-point tests per detection at this size)")
     print(json.dumps(out), flush=True)
 
 

@@ -27,7 +27,8 @@
  *     one buffer of at least that size (256-byte aligned) and hands it to
  *     dem_bind.  The library never frees caller memory.  The library itself
  *     allocates only its opaque host context, a few bytes of pinned host
- *     memory for read-backs, HIP events, and nothing else.
+ *     memory for read-backs, HIP events, and, with meshes, pinned staging
+ *     for the per-step mesh poses (64 KiB per mesh), and nothing else.
  *   - Host arrays (const double*, float* ...) are plain host pointers; they
  *     are read or written before the call returns.
  *   - Streams: dem_stream is a hipStream_t passed as void* (NULL = the
@@ -111,6 +112,28 @@ typedef struct {
     const int32_t *mat;         /* [n] */
 } dem_walls;
 
+/* Rigid triangle meshes with prescribed motion (Sec. 2.4: a mesh is an owner
+ * whose geometries are triangle facets; Sec. 5 drives a bladed mixer at a
+ * constant angular velocity).  Facet f belongs to mesh tri_mesh[f]; its three
+ * vertices tri_local[9*f .. 9*f+8] (x,y,z each) are given in the mesh frame.
+ * At step n (t = n dt) mesh g is the rotation by the angle |omega_g| t about
+ * the axis omega_g / |omega_g| (Rodrigues' formula, evaluated on the host in
+ * FP64), followed by the translation origin_g + vel_g t; its surface moves
+ * with vel_g + omega_g x (x - p_g(t)).  A facet acts on a sphere like a flat
+ * wall of infinite mass (Sec. 4.2.1 with R = r and m = m_sphere) along the
+ * line from the closest point of the facet to the sphere centre. */
+#define DEM_MAX_MESHES 4
+typedef struct {
+    int32_t n_mesh;             /* 0 .. DEM_MAX_MESHES */
+    int64_t n_tri;              /* facets */
+    const int32_t *tri_mesh;    /* [n_tri] */
+    const double *tri_local;    /* [9*n_tri] */
+    const double *origin;       /* [3*n_mesh] reference point at step 0 */
+    const double *vel;          /* [3*n_mesh] */
+    const double *omega;        /* [3*n_mesh] rad/s, world frame, about the reference point */
+    const int32_t *mat;         /* [n_mesh] */
+} dem_meshes;
+
 /* Owners (clumps or single spheres) and their spheres (Sec. 2.4).  Spheres are
  * numbered owner-major: owner o has spheres own_sph0[o] .. own_sph0[o+1]-1.
  * own_tmpl[o] = -1 marks a single sphere at the owner's centre (isotropic
@@ -192,6 +215,16 @@ dem_status dem_create(const dem_params *params, const dem_materials *mats,
                       const dem_templates *tmpls, const dem_walls *walls,
                       const dem_bodies *bodies, dem_ctx **out);
 
+/* Installs the meshes of a context (Sec. 2.4, Sec. 5); call between
+ * dem_create and dem_bind (the workspace holds per-facet buffers).  Copies
+ * the arrays; replaces earlier meshes; NULL or n_mesh = 0 removes them.
+ * Contact partners of a sphere then include facets, with keys
+ * j' = n_spheres + n_walls + f.
+ * Errors: DEM_ERR_STATE after dem_bind; DEM_ERR_ARG on counts out of range,
+ * a facet of an unknown mesh, a material out of range or a non-finite
+ * value. */
+dem_status dem_set_meshes(dem_ctx *ctx, const dem_meshes *meshes);
+
 /* Device bytes one binding needs for a contact array of contact_capacity
  * entries (per active-set buffer). */
 dem_status dem_workspace_size(const dem_ctx *ctx, int64_t contact_capacity, int64_t *bytes);
@@ -224,8 +257,10 @@ dem_status dem_bin(dem_ctx *ctx, dem_stream stream, uint32_t *sorted_keys, uint3
 
 /* Contact detection on the current state with margin m (0 <= m <= params
  * margin) (Sec. 2.1): every sphere pair of different owners with
- * |xi - xj|^2 < ((ri + rj) + 2m)^2 and every sphere-wall pair with gap < 2m,
- * as sorted keys (i << 32) | j' (j' = j, or n_spheres + wall index).  The
+ * |xi - xj|^2 < ((ri + rj) + 2m)^2, every sphere-wall pair with gap < 2m
+ * and every sphere-facet pair with |xi - closest point|^2 < (ri + 2m)^2, as
+ * sorted keys (i << 32) | j' (j' = j, n_spheres + wall index, or
+ * n_spheres + n_walls + facet index).  The
  * new set replaces the current one; contact history of pairs present in both
  * is carried over, new pairs start from zero (Sec. 4.2).  If n_contacts is
  * not NULL the stream is synchronised and the set size written there.

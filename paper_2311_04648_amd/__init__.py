@@ -53,6 +53,11 @@ class Walls(C.Structure):
                 ("omega", C.c_void_p), ("mat", C.c_void_p)]
 
 
+class Meshes(C.Structure):
+    _fields_ = [("n_mesh", C.c_int32), ("n_tri", C.c_int64), ("tri_mesh", C.c_void_p), ("tri_local", C.c_void_p),
+                ("origin", C.c_void_p), ("vel", C.c_void_p), ("omega", C.c_void_p), ("mat", C.c_void_p)]
+
+
 class Bodies(C.Structure):
     _fields_ = [("n_owners", C.c_int64), ("n_spheres", C.c_int64), ("own_sph0", C.c_void_p),
                 ("own_tmpl", C.c_void_p), ("own_mass", C.c_void_p), ("own_moi", C.c_void_p),
@@ -86,6 +91,7 @@ def lib():
         vp, i64, i32, d, f = C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_float
         sig = {
             "dem_create": [vp, vp, vp, vp, vp, vp],
+            "dem_set_meshes": [vp, vp],
             "dem_workspace_size": [vp, i64, vp],
             "dem_bind": [vp, vp, i64, i64],
             "dem_set_state": [vp, vp, vp, vp, vp, i64, vp],
@@ -199,6 +205,17 @@ class DemContext:
                 L.dem_destroy(ctx)
             self.ctx = None
             raise DemError(st, msg)
+        n_mesh = int(getattr(s, "n_mesh", 0))
+        if n_mesh > 0:
+            Ms = Meshes(n_mesh, int(s.n_tri), keep(s.tri_mesh, np.int32), keep(s.tri_local, np.float64),
+                        keep(s.mesh_origin, np.float64), keep(s.mesh_vel, np.float64),
+                        keep(s.mesh_omega, np.float64), keep(s.mesh_mat, np.int32))
+            st = L.dem_set_meshes(ctx, C.byref(Ms))
+            if st != DEM_OK:
+                msg = L.dem_last_error(ctx).decode()
+                L.dem_destroy(ctx)
+                self.ctx = None
+                raise DemError(st, msg)
         self._keep.clear()
         self.No = int(s.own_tmpl.shape[0])
         self.Ns = int(s.sph_rad.shape[0])

@@ -20,6 +20,8 @@
 #include <string>
 #include <vector>
 
+constexpr int64_t POSE_RING = 512, POSE_CHUNK = 256;
+
 struct dem_ctx {
     std::string err;
     dem_params P;
@@ -36,6 +38,21 @@ struct dem_ctx {
     std::vector<float> mass;
     std::vector<int32_t> tmpl;
     double rmax = 0.0;
+    // meshes (host copies; poses are evaluated per step on the host)
+    int32_t NM = 0, NF = 0;
+    std::vector<TriDev> tri;
+    std::vector<double> mesh_origin, mesh_vel, mesh_omega;
+    std::vector<int32_t> mesh_mat;
+    double vmesh = 0.0;          // fastest point of any mesh (m/s)
+    TriDev *d_tri = nullptr;
+    // mesh poses of the dynamics: a device ring of POSE_RING steps, filled
+    // POSE_CHUNK steps at a time from pinned staging (two halves, each reused
+    // after its previous copy has completed)
+    MeshPose *d_pose_ring = nullptr;    // [POSE_RING * NM]
+    MeshPose *h_pose_stage = nullptr;   // pinned [2 * POSE_CHUNK * NM]
+    hipEvent_t ev_pose[2] = {nullptr, nullptr};
+    int64_t pose_lo = 0, pose_hi = 0;   // steps whose poses the ring holds (the last chunk)
+    int pose_half = 0;
     Grid grid{};
     Grid fgrid{};
     Origin org{};
@@ -170,6 +187,8 @@ void carve_cd(Carver &c, const dem_ctx *ctx, CdWork &w)
     w.stage = c.take<uint32_t>(16 * ns);
     w.hist = c.take<uint32_t>(radix_hist_elems(ns));
     w.partials = c.take<uint32_t>(partial_elems(ctx));
+    w.fac = c.take<FacetDev>(ctx->NF);
+    w.frow = c.take<uint32_t>((int64_t)ctx->NF + 1);
     w.sort_bits = ctx->sort_bits;
     w.sort_mode = ctx->P.bin_sort;
 }
@@ -188,6 +207,8 @@ void carve(Carver &c, dem_ctx *ctx, int64_t cap)
     ctx->d_sph = c.take<SphRec>(Ns);
     ctx->d_tpos = c.take<float>(4 * std::max(ctx->ncomp, 1));
     ctx->d_walls = c.take<WallDev>(std::max(ctx->W, 1));
+    ctx->d_tri = c.take<TriDev>(ctx->NF);
+    ctx->d_pose_ring = c.take<MeshPose>(POSE_RING * ctx->NM);
     ctx->d_mat = c.take<MatPair>((int64_t)ctx->nmat * ctx->nmat);
     for (int b = 0; b < 2; ++b) {
         AcsBuf &a = ctx->acs[b];
@@ -231,6 +252,47 @@ void carve(Carver &c, dem_ctx *ctx, int64_t cap)
     ctx->d_lab_j = c.take<uint32_t>(cap);
 }
 
+// Pose of mesh g at step n (t = n dt): reference point origin + vel t, and
+// the rotation by the angle |omega| t about omega / |omega| (Rodrigues'
+// formula), in FP64 on the host.
+void mesh_pose(const dem_ctx *ctx, int g, int64_t step, MeshPose &P)
+{
+    const double t = (double)step * ctx->P.dt;
+    const double *o = &ctx->mesh_origin[3 * g], *v = &ctx->mesh_vel[3 * g], *w = &ctx->mesh_omega[3 * g];
+    for (int k = 0; k < 3; ++k) {
+        P.p[k] = o[k] + v[k] * t;
+        P.vel[k] = (float)v[k];
+        P.omega[k] = (float)w[k];
+    }
+    P.mat = ctx->mesh_mat[g];
+    P.pad = 0;
+    const double wn = std::sqrt((w[0] * w[0] + w[1] * w[1]) + w[2] * w[2]);
+    if (!(wn > 0.0)) {
+        for (int k = 0; k < 9; ++k) P.R[k] = (k % 4 == 0) ? 1.0 : 0.0;
+        return;
+    }
+    const double ux = w[0] / wn, uy = w[1] / wn, uz = w[2] / wn;
+    const double ang = wn * t;
+    const double c = std::cos(ang), sn = std::sin(ang), C = 1.0 - c;
+    P.R[0] = c + ux * ux * C;
+    P.R[1] = ux * uy * C - uz * sn;
+    P.R[2] = ux * uz * C + uy * sn;
+    P.R[3] = uy * ux * C + uz * sn;
+    P.R[4] = c + uy * uy * C;
+    P.R[5] = uy * uz * C - ux * sn;
+    P.R[6] = uz * ux * C - uy * sn;
+    P.R[7] = uz * uy * C + ux * sn;
+    P.R[8] = c + uz * uz * C;
+}
+
+MeshPoses mesh_poses(const dem_ctx *ctx, int64_t step)
+{
+    MeshPoses M;
+    std::memset(&M, 0, sizeof(M));
+    for (int g = 0; g < ctx->NM; ++g) mesh_pose(ctx, g, step, M.m[g]);
+    return M;
+}
+
 DetectArgs detect_args(const dem_ctx *ctx, double margin, int64_t step)
 {
     DetectArgs a;
@@ -250,6 +312,10 @@ DetectArgs detect_args(const dem_ctx *ctx, double margin, int64_t step)
     a.n_owners = ctx->No;
     a.h = ctx->P.dt;
     a.step = step;
+    a.rmax = ctx->rmax;
+    a.tri = ctx->d_tri;
+    a.n_tri = ctx->NF;
+    a.poses = mesh_poses(ctx, step);
     return a;
 }
 
@@ -278,10 +344,43 @@ DynArgs dyn_args(const dem_ctx *ctx, int64_t step)
     a.rolling = ctx->rolling ? 1 : 0;
     a.cur = ctx->cur;
     a.blkmax = ctx->d_blkmax;
+    a.tri = ctx->d_tri;
+    a.n_tri = ctx->NF;
+    a.poses = nullptr;
     return a;
 }
 
 inline hipStream_t S(dem_stream s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Device address of the mesh poses of step n, for dynamics kernels enqueued
+// on stream s after this call.  A step outside the last chunk refills the
+// ring with the POSE_CHUNK steps from n on: poses computed on the host into
+// a staging half, copied to ring slots (n + i) mod POSE_RING on s (so after
+// every earlier kernel on s that read those slots).  Null without meshes.
+const MeshPose *dyn_poses(dem_ctx *ctx, int64_t n, hipStream_t s)
+{
+    const int64_t nm = ctx->NM;
+    if (nm == 0) return nullptr;
+    if (!(n >= ctx->pose_lo && n < ctx->pose_hi)) {
+        const int h = ctx->pose_half;
+        ctx->pose_half ^= 1;
+        hipEventSynchronize(ctx->ev_pose[h]);
+        MeshPose *st = ctx->h_pose_stage + (size_t)h * POSE_CHUNK * nm;
+        for (int64_t i = 0; i < POSE_CHUNK; ++i)
+            for (int g = 0; g < (int)nm; ++g) mesh_pose(ctx, g, n + i, st[i * nm + g]);
+        const int64_t slot = ((n % POSE_RING) + POSE_RING) % POSE_RING;
+        const int64_t first = std::min<int64_t>(POSE_CHUNK, POSE_RING - slot);
+        hipMemcpyAsync(ctx->d_pose_ring + slot * nm, st, sizeof(MeshPose) * first * nm, hipMemcpyHostToDevice, s);
+        if (first < POSE_CHUNK)
+            hipMemcpyAsync(ctx->d_pose_ring, st + first * nm, sizeof(MeshPose) * (POSE_CHUNK - first) * nm,
+                           hipMemcpyHostToDevice, s);
+        hipEventRecord(ctx->ev_pose[h], s);
+        ctx->pose_lo = n;
+        ctx->pose_hi = n + POSE_CHUNK;
+    }
+    const int64_t slot = ((n % POSE_RING) + POSE_RING) % POSE_RING;
+    return ctx->d_pose_ring + slot * nm;
+}
 
 dem_status read_counters(dem_ctx *ctx, hipStream_t s)
 {
@@ -588,6 +687,71 @@ dem_status dem_create(const dem_params *params, const dem_materials *mats, const
     return DEM_OK;
 }
 
+dem_status dem_set_meshes(dem_ctx *ctx, const dem_meshes *meshes)
+{
+    if (!ctx) return DEM_ERR_ARG;
+    if (ctx->bound) {
+        ctx->err = "dem_set_meshes after dem_bind (the workspace holds per-facet buffers)";
+        return DEM_ERR_STATE;
+    }
+    const int32_t nm = meshes ? meshes->n_mesh : 0;
+    const int64_t nf = meshes && nm > 0 ? meshes->n_tri : 0;
+    ARGCHK(nm >= 0 && nm <= DEM_MAX_MESHES, "n_mesh must be 0..DEM_MAX_MESHES");
+    ARGCHK(nf >= 0, "n_tri must be >= 0");
+    ARGCHK(ctx->Ns + ctx->W + nf < (int64_t)0xfffffff0, "too many geometries for 32-bit partner ids");
+    // the facet walk numbers (facet, bin row) pairs with 32-bit integers
+    ARGCHK((uint64_t)nf * (uint64_t)ctx->grid.ny * (uint64_t)ctx->grid.nz < 0x7fffffffull,
+           "too many facets for the bin grid");
+    std::vector<TriDev> tri((size_t)nf);
+    std::vector<double> org(3 * (size_t)nm), vel(3 * (size_t)nm), om(3 * (size_t)nm);
+    std::vector<int32_t> mat((size_t)nm);
+    if (nm > 0) {
+        ARGCHK(meshes->origin && meshes->vel && meshes->omega && meshes->mat, "mesh origin, vel, omega, mat are required");
+        ARGCHK(nf == 0 || (meshes->tri_mesh && meshes->tri_local), "tri_mesh and tri_local are required");
+    }
+    for (int32_t g = 0; g < nm; ++g) {
+        for (int k = 0; k < 3; ++k) {
+            org[3 * g + k] = meshes->origin[3 * g + k];
+            vel[3 * g + k] = meshes->vel[3 * g + k];
+            om[3 * g + k] = meshes->omega[3 * g + k];
+            ARGCHK(std::isfinite(org[3 * g + k]) && std::isfinite(vel[3 * g + k]) && std::isfinite(om[3 * g + k]),
+                   "mesh origin, vel and omega must be finite");
+        }
+        mat[g] = meshes->mat[g];
+        ARGCHK(mat[g] >= 0 && mat[g] < ctx->nmat, "mesh material out of range");
+    }
+    std::vector<double> reach((size_t)nm, 0.0);   // largest vertex distance from the reference point
+    for (int64_t f = 0; f < nf; ++f) {
+        TriDev t{};
+        t.mesh = meshes->tri_mesh[f];
+        ARGCHK(t.mesh >= 0 && t.mesh < nm, "facet of an unknown mesh");
+        for (int k = 0; k < 9; ++k) {
+            t.v[k] = meshes->tri_local[9 * f + k];
+            ARGCHK(std::isfinite(t.v[k]), "facet vertices must be finite");
+        }
+        for (int v = 0; v < 3; ++v) {
+            const double *x = t.v + 3 * v;
+            reach[t.mesh] = std::max(reach[t.mesh], std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]));
+        }
+        tri[(size_t)f] = t;
+    }
+    double vm = 0.0;
+    for (int32_t g = 0; g < nm; ++g) {
+        const double *v = &vel[3 * g], *w = &om[3 * g];
+        vm = std::max(vm, std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) +
+                              std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]) * reach[g]);
+    }
+    ctx->NM = nm;
+    ctx->NF = (int32_t)nf;
+    ctx->tri.swap(tri);
+    ctx->mesh_origin.swap(org);
+    ctx->mesh_vel.swap(vel);
+    ctx->mesh_omega.swap(om);
+    ctx->mesh_mat.swap(mat);
+    ctx->vmesh = vm;
+    return DEM_OK;
+}
+
 dem_status dem_workspace_size(const dem_ctx *cctx, int64_t contact_capacity, int64_t *bytes)
 {
     dem_ctx *ctx = const_cast<dem_ctx *>(cctx);
@@ -619,6 +783,14 @@ dem_status dem_bind(dem_ctx *ctx, void *device_workspace, int64_t bytes, int64_t
     if (!ctx->ev_wo) HIPCHK(hipEventCreateWithFlags(&ctx->ev_wo, hipEventDisableTiming));
     if (!ctx->ev_cd) HIPCHK(hipEventCreateWithFlags(&ctx->ev_cd, hipEventDisableTiming));
     if (!ctx->h_capped) HIPCHK(hipHostMalloc((void **)&ctx->h_capped, 4 * sizeof(uint32_t)));
+    if (ctx->NM > 0) {
+        if (ctx->h_pose_stage) HIPCHK(hipHostFree(ctx->h_pose_stage));
+        ctx->h_pose_stage = nullptr;
+        HIPCHK(hipHostMalloc((void **)&ctx->h_pose_stage, sizeof(MeshPose) * 2 * POSE_CHUNK * ctx->NM));
+        for (auto &e : ctx->ev_pose)
+            if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    ctx->pose_lo = ctx->pose_hi = 0;
     for (auto &c : ctx->cyc) {
         if (!c.wo) HIPCHK(hipEventCreate(&c.wo));
         if (!c.cd) HIPCHK(hipEventCreate(&c.cd));
@@ -634,6 +806,8 @@ dem_status dem_bind(dem_ctx *ctx, void *device_workspace, int64_t bytes, int64_t
     HIPCHK(hipMemcpy(ctx->d_sph, ctx->sph.data(), sizeof(SphRec) * ctx->Ns, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_tpos, ctx->tpos.data(), sizeof(float) * ctx->tpos.size(), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_walls, ctx->walls.data(), sizeof(WallDev) * ctx->walls.size(), hipMemcpyHostToDevice));
+    if (ctx->NF > 0)
+        HIPCHK(hipMemcpy(ctx->d_tri, ctx->tri.data(), sizeof(TriDev) * ctx->NF, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_mat, ctx->mat.data(), sizeof(MatPair) * ctx->mat.size(), hipMemcpyHostToDevice));
     DevCounters z{};
     HIPCHK(hipMemcpy(ctx->ctr, &z, sizeof(DevCounters), hipMemcpyHostToDevice));
@@ -811,6 +985,7 @@ dem_status dem_forces(dem_ctx *ctx, dem_stream stream)
     }
     hipStream_t s = S(stream);
     DynArgs a = dyn_args(ctx, ctx->step);
+    a.poses = dyn_poses(ctx, ctx->step, s);
     launch_force(a, ctx->acs[ctx->cur], ctx->sb, ctx->ctr, s);
     launch_fold_integrate(a, ctx->acs[ctx->cur], ctx->sb, ctx->ctr, 0, s);
     HIPCHK(hipGetLastError());
@@ -915,7 +1090,8 @@ dem_status dem_set_contacts(dem_ctx *ctx, const uint64_t *keys, const float *his
         int64_t i = (int64_t)(key >> 32), jj = (int64_t)(key & 0xffffffffu);
         ARGCHK(c == 0 || keys[c - 1] < key, "keys must be strictly ascending");
         ARGCHK(i < ctx->Ns, "key sphere id out of range");
-        ARGCHK((jj > i && jj < ctx->Ns) || (jj >= ctx->Ns && jj < ctx->Ns + ctx->W), "key partner out of range");
+        ARGCHK((jj > i && jj < ctx->Ns) || (jj >= ctx->Ns && jj < ctx->Ns + ctx->W + ctx->NF),
+               "key partner out of range");
         start[i + 1]++;
         j[c] = (uint32_t)jj;
         if (hist)
@@ -1020,7 +1196,7 @@ static int64_t issue_work_order(dem_ctx *ctx, hipStream_t dyn, hipStream_t kin, 
         const double g = std::sqrt(P.gravity[0] * P.gravity[0] + P.gravity[1] * P.gravity[1] +
                                    P.gravity[2] * P.gravity[2]);
         launch_reduce_max(dyn_args(ctx, n), ctx->ctr, dyn);
-        launch_adaptive_margin(ctx->ctr, 2.0 * (double)lam * P.dt, g, P.margin, dyn);
+        launch_adaptive_margin(ctx->ctr, 2.0 * (double)lam * P.dt, g, P.margin, ctx->vmesh, dyn);
         const int slot = (ctx->cyc_pos + 1) % 4;
         hipMemcpyAsync(&ctx->h_capped[slot], &ctx->ctr->capped, sizeof(uint32_t), hipMemcpyDeviceToHost, dyn);
         cy = &ctx->cyc[slot];
@@ -1226,6 +1402,11 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
             }
         }
         DynArgs a = dyn_args(ctx, n);
+        if (ctx->NM > 0) {
+            // a refill of the pose ring is dynamics-stream work: no timed run spans it
+            if (ctx->run && !(n >= ctx->pose_lo && n < ctx->pose_hi)) run_close(ctx, dyn);
+            a.poses = dyn_poses(ctx, n, dyn);
+        }
         // single kernels are bracketed by marker events, which wait for the
         // previous work on the stream; an empty kernel bracketed the same way
         // measures the markers' own overhead
@@ -1329,6 +1510,12 @@ void dem_destroy(dem_ctx *ctx)
         if (p.a) hipEventDestroy(p.a);
         if (p.b) hipEventDestroy(p.b);
     }
+    // the staging may still feed a pending copy
+    for (auto &e : ctx->ev_pose)
+        if (e) hipEventSynchronize(e);
+    if (ctx->h_pose_stage) hipHostFree(ctx->h_pose_stage);
+    for (auto &e : ctx->ev_pose)
+        if (e) hipEventDestroy(e);
     delete ctx;
 }
 
@@ -1389,7 +1576,9 @@ int64_t learned_interval(dem_ctx *ctx, hipStream_t s)
     uint32_t bits = ctx->h_ctr->maxv2[0];
     std::memcpy(&v2, &bits, 4);
     double vmax = ctx->step > 0 && v2 == v2 ? std::sqrt((double)v2) : 0.0;
-    int64_t k_an = analytic_interval(ctx, vmax);
+    // a facet closes a gap at the speed of its mesh: the bound takes the
+    // faster of the spheres and the meshes
+    int64_t k_an = analytic_interval(ctx, std::max(vmax, ctx->vmesh));
     if (!ctx->mlp_set) return k_an;
     run_features(ctx, s, ctx->d_feat, nullptr);
     uint32_t ncell = 0;
@@ -1404,6 +1593,8 @@ int64_t learned_interval(dem_ctx *ctx, hipStream_t s)
     double safety = ctx->P.mlp_safety > 0.0 ? ctx->P.mlp_safety : 1.0;
     double kl = std::floor(safety * (double)R) - (double)ctx->P.cd_latency - 1.0;
     int64_t k = kl < 1.0 ? 1 : (int64_t)std::min(kl, 1e9);
+    // the features see only the spheres: mesh motion is bounded analytically
+    if (ctx->NM > 0) k = std::min(k, analytic_interval(ctx, ctx->vmesh));
     return std::min<int64_t>(k, ctx->P.cd_interval_max);
 }
 

@@ -3,22 +3,28 @@
 //
 //   bin:     sphere centres (exact FP64) -> bin key (uniform grid of cubic
 //            bins of edge >= 2 (r_max + m), padded by one bin per side),
-//            per-bin counts -> exclusive scan -> cell_start, and a stable
-//            LSD radix sort of (key, sphere id); candidate records are then
-//            gathered into bin order so neighbour rows are contiguous.
-//   detect:  one thread per sphere in bin order walks the 9 neighbour rows
-//            (3 bins each, contiguous in the sorted order) and tests every
-//            candidate j > i of another owner with the FP64 predicate
-//            |xi - xj|^2 < ((ri + rj) + 2m)^2, then the walls.  A count pass,
-//            an exclusive scan (CSR offsets by sphere id) and a write pass
-//            that insertion-sorts each row give the set as ascending keys.
+//            per-bin counts -> exclusive scan -> cell_start, and a sort of
+//            (key, sphere id) by bin; candidate records are then gathered
+//            into bin order so neighbour rows are contiguous.
+//   detect:  one thread per sphere in bin order walks the forward half of
+//            its 27-bin stencil and tests each candidate pair once with the
+//            FP64 predicate |xi - xj|^2 < ((ri + rj) + 2m)^2 (after a
+//            conservative FP32 prefilter), then the walls; a pair is staged
+//            in the row of its lower id.  Facets of rigid meshes are walked
+//            per facet over the bins near it (Sec. 2.4: a facet is one more
+//            geometry) and staged in the sphere's row.  A scan of the row
+//            counts gives the CSR offsets; each row is then sorted, so the
+//            set is a list of ascending keys.
 //   B lists: for every sphere, the contacts in which it is the higher id,
 //            ascending; used by the ordered per-owner reduction.
 //   remap:   per sphere, a merge of the old and the new row carries the
 //            tangential history of surviving pairs; new pairs start at zero.
-//   judge:   the same walk with m = 0 looks every true contact up in the
-//            row of the set in use and counts the missing ones.
+//   judge:   the full-stencil walk (and the facet walk) with m = 0 looks
+//            every true contact up in the row of the set in use and counts
+//            the missing ones.
 #include "dem_device.h"
+
+#include <algorithm>
 
 namespace {
 
@@ -150,6 +156,153 @@ __device__ inline bool row_contains(const uint32_t *row_j, uint32_t lo, uint32_t
         else b = mid;
     }
     return a < hi && row_j[a] == j;
+}
+
+// ---------------------------------------------------------------------------
+// sphere-facet pairs
+// ---------------------------------------------------------------------------
+// Facets at the pose of one detection: world vertices, box, and the range of
+// bins that holds every sphere centre within r_max + 2m of the box (grown by
+// a rounding slack; bin_coord is monotone, so the clamped range is exact);
+// frow[f] = the number of (y, z) bin rows of that range.
+__global__ void __launch_bounds__(TPB) k_facet_prepare(DetectArgs a, FacetDev *fac, uint32_t *frow)
+{
+    const int32_t f = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (f >= a.n_tri) return;
+    const TriDev t = a.tri[f];
+    const MeshPose P = pose_of(a.poses, t.mesh);
+    FacetDev d;
+    facet_world(t, P, d.v);
+    const double m = a.margin_dev ? *a.margin_dev : a.margin;
+    const double e = (a.rmax + 2.0 * m) * (1.0 + 1e-9) + 1e-12;
+    const int32_t nn[3] = {a.grid.nx, a.grid.ny, a.grid.nz};
+    int c0[3], c1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double lo = fmin(d.v[k], fmin(d.v[3 + k], d.v[6 + k]));
+        const double hi = fmax(d.v[k], fmax(d.v[3 + k], d.v[6 + k]));
+        d.lo[k] = lo;
+        d.hi[k] = hi;
+        c0[k] = bin_coord(lo - e, a.grid.lo[k], a.grid.inv_b, nn[k]);
+        c1[k] = bin_coord(hi + e, a.grid.lo[k], a.grid.inv_b, nn[k]);
+        if (c1[k] < c0[k]) c1[k] = c0[k];   // NaN vertices: one bin, no pair passes the predicate
+    }
+    d.cx0 = c0[0];
+    d.ncx = c1[0] - c0[0] + 1;
+    d.cy0 = c0[1];
+    d.ncy = c1[1] - c0[1] + 1;
+    d.cz0 = c0[2];
+    d.ncz = c1[2] - c0[2] + 1;
+    fac[f] = d;
+    frow[f] = (uint32_t)d.ncy * (uint32_t)d.ncz;
+}
+
+// Box test before the exact predicate: rejects a centre farther than T (with
+// slack) from the facet's box along one axis, which the exact predicate
+// would reject too.
+__device__ inline bool facet_box_near(const FacetDev &d, double x, double y, double z, double T)
+{
+    const double ts = T * (1.0 + 1e-9) + 1e-12;
+    return !(x < d.lo[0] - ts || x > d.hi[0] + ts || y < d.lo[1] - ts || y > d.hi[1] + ts || z < d.lo[2] - ts ||
+             z > d.hi[2] + ts);
+}
+
+// Sphere-facet predicate: |x - closest point|^2 < (r + 2m)^2 (strict).
+__device__ inline bool facet_hit(const FacetDev &d, double x, double y, double z, double r, double m)
+{
+    const double T = r + 2.0 * m;
+    if (!facet_box_near(d, x, y, z, T)) return false;
+    const double p[3] = {x, y, z};
+    double q[3];
+    return facet_dist2(d.v, p, q) < T * T;
+}
+
+enum { FMODE_STAGE = 0, FMODE_JUDGE = 1, FMODE_LABEL = 2 };
+
+// Sphere-facet pairs of one detection.  The (facet, bin row) pairs are
+// numbered through the scanned frow; a wave takes 64 of them at a time (one
+// per lane), concatenates the candidate ranges of its 64 rows with a wave
+// prefix sum and tests the concatenation 64 candidates at a time (a lane
+// finds the row of its candidate by a binary search over the lanes' running
+// sums), so long and short rows, and large and small facets, spread evenly.
+//   FMODE_STAGE: each pair joins the sphere's row like a wall (a slot of
+//                `count` is claimed; the first STAGE_K are staged);
+//   FMODE_JUDGE: each pair (m = 0) absent from the sphere's row of the set
+//                in use adds one to *miss;
+//   FMODE_LABEL: each such pair lowers first_miss of the sphere owner's cell
+//                to tval.
+template <int MODE>
+__global__ void __launch_bounds__(TPB) k_facet_walk(DetectArgs a, const FacetDev *fac, const uint32_t *frow,
+                                                    const Cand *cand, const uint32_t *cell_start, uint32_t *count,
+                                                    uint32_t *stage, const uint32_t *cur_start,
+                                                    const uint32_t *cur_j, int64_t cap, uint32_t *miss,
+                                                    const uint32_t *cellmap, uint32_t *first_miss, uint32_t tval)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    const uint32_t nt = (uint32_t)a.n_tri;
+    const uint32_t total = frow[nt];
+    const double m = a.margin_dev ? *a.margin_dev : a.margin;
+    const uint32_t nx = (uint32_t)a.grid.nx, ny = (uint32_t)a.grid.ny;
+    const uint32_t jbase = (uint32_t)a.n_spheres + (uint32_t)a.n_walls;
+    // rows of a set in use that overflowed its capacity are not valid
+    const bool cur_ok = MODE != FMODE_STAGE && (int64_t)cur_start[a.n_spheres] <= cap;
+    for (uint32_t r0 = wave * 64u; r0 < total; r0 += nwaves * 64u) {
+        const uint32_t r = r0 + lane;
+        uint32_t f = 0, s0 = 0, len = 0;
+        if (r < total) {
+            // the facet of row r: frow[f] <= r < frow[f + 1]
+            uint32_t lo = 0, hi = nt;
+            while (hi - lo > 1u) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (frow[mid] <= r) lo = mid;
+                else hi = mid;
+            }
+            f = lo;
+            const FacetDev &d = fac[f];
+            const uint32_t loc = r - frow[f];
+            const uint32_t cy = (uint32_t)d.cy0 + loc % (uint32_t)d.ncy;
+            const uint32_t cz = (uint32_t)d.cz0 + loc / (uint32_t)d.ncy;
+            const uint32_t k0 = (cz * ny + cy) * nx + (uint32_t)d.cx0;
+            s0 = cell_start[k0];
+            len = cell_start[k0 + (uint32_t)d.ncx] - s0;
+        }
+        uint32_t inc = len;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(inc, o, 64);
+            if (lane >= (uint32_t)o) inc += t;
+        }
+        const uint32_t tot = __shfl(inc, 63, 64);
+        const uint32_t exc = inc - len;
+        for (uint32_t vb = 0; vb < tot; vb += 64u) {
+            const uint32_t v = vb + lane;
+            // the lane whose range holds v: the number of lanes with inc <= v
+            uint32_t k = 0;
+#pragma unroll
+            for (int st = 32; st >= 1; st >>= 1) {
+                const uint32_t t = __shfl(inc, (int)(k + (uint32_t)st - 1u), 64);
+                if (t <= v) k += (uint32_t)st;
+            }
+            const uint32_t fk = __shfl(f, (int)k, 64);
+            const uint32_t sk = __shfl(s0, (int)k, 64);
+            const uint32_t ek = __shfl(exc, (int)k, 64);
+            if (v >= tot) continue;
+            const Cand c = cand[sk + (v - ek)];
+            if (!facet_hit(fac[fk], c.x, c.y, c.z, (double)c.r, m)) continue;
+            const uint32_t jp = jbase + fk;
+            if (MODE == FMODE_STAGE) {
+                const uint32_t slot = atomicAdd(&count[c.id], 1u);
+                if (slot < (uint32_t)STAGE_K) stage[(size_t)c.id * STAGE_K + slot] = jp;
+            } else {
+                const uint32_t lo_row = cur_ok ? cur_start[c.id] : 0u, hi_row = cur_ok ? cur_start[c.id + 1] : 0u;
+                if (row_contains(cur_j, lo_row, hi_row, jp)) continue;
+                if (MODE == FMODE_JUDGE) atomicAdd(miss, 1u);
+                else atomicMin(&first_miss[cellmap[a.sph[c.id].owner]], tval);
+            }
+        }
+    }
 }
 
 template <int MODE>
@@ -364,7 +517,8 @@ __device__ inline void fill_blists(const uint32_t *row, uint32_t base, uint32_t 
 __global__ void __launch_bounds__(TPB) k_compact(DetectArgs a, const Cand *cand_tmp, const Cand *cand,
                                                  const uint32_t *cell_start, const uint32_t *start,
                                                  const uint32_t *stage, uint32_t *out_j, int64_t cap,
-                                                 uint32_t *bcur, uint32_t *bidx, uint32_t *bsrc)
+                                                 uint32_t *bcur, uint32_t *bidx, uint32_t *bsrc,
+                                                 const FacetDev *fac)
 {
     const int64_t ns = a.n_spheres;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -431,6 +585,13 @@ __global__ void __launch_bounds__(TPB) k_compact(DetectArgs a, const Cand *cand_
         wall_point(wd, a.step, a.h, pw);
         if (!wall_hit(wd, pw, xi, yi, zi, ri, m)) continue;
         if (k < n) row[k] = (uint32_t)ns + (uint32_t)w;
+        ++k;
+    }
+    // facets: every facet's box, then the exact predicate (overflowing rows
+    // are rare; the facet walk found the same pairs)
+    for (int32_t f = 0; f < a.n_tri; ++f) {
+        if (!facet_hit(fac[f], xi, yi, zi, ri, m)) continue;
+        if (k < n) row[k] = (uint32_t)ns + (uint32_t)a.n_walls + (uint32_t)f;
         ++k;
     }
     if (k > n) k = n;
@@ -619,6 +780,19 @@ void launch_blists(AcsBuf &b, int64_t ns, int64_t cap, uint32_t *partials, hipSt
                        b.bsrc);
 }
 
+// Facets at the pose of the detection and the offsets of their bin rows.
+void launch_facet_prepare(const DetectArgs &a, CdWork &w, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_facet_prepare, dim3(nblocks(a.n_tri)), dim3(TPB), 0, s, a, w.fac, w.frow);
+    scan_exclusive_u32(w.frow, w.frow, a.n_tri, w.partials, s);
+}
+
+// The facet walk runs a fixed number of waves that stride over the rows.
+inline unsigned facet_walk_blocks(const DetectArgs &a)
+{
+    return (unsigned)std::min<int64_t>(1024, std::max<int64_t>(64, ((int64_t)a.n_tri + 3) / 4));
+}
+
 void launch_detect_front(const DetectArgs &a, CdWork &w, AcsBuf &out, hipStream_t s)
 {
     const int64_t n = a.n_spheres;
@@ -645,13 +819,22 @@ void launch_detect_back(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap
     launch_bin_back(a, w, s, false);
     hipLaunchKernelGGL(k_detect_stage, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,
                        (const float4 *)w.candf, w.cell_start, w.count, w.stage, out.bcur);
+    if (a.n_tri > 0) {
+        launch_facet_prepare(a, w, s);
+        hipLaunchKernelGGL(k_facet_walk<FMODE_STAGE>, dim3(facet_walk_blocks(a)), dim3(TPB), 0, s, a,
+                           (const FacetDev *)w.fac, (const uint32_t *)w.frow, (const Cand *)w.cand,
+                           (const uint32_t *)w.cell_start, w.count, w.stage, (const uint32_t *)nullptr,
+                           (const uint32_t *)nullptr, cap, (uint32_t *)nullptr, (const uint32_t *)nullptr,
+                           (uint32_t *)nullptr, 0u);
+    }
     // row offsets (checked against the capacity) and B-list offsets (with a
     // copy as the fill cursor) in one pair of launches
     scan_exclusive_u32_pair(w.count, out.start, nullptr, ctr, cap, buf, out.bcur, out.bstart, out.bcur, n,
                             w.partials, s);
     hipLaunchKernelGGL(k_compact, dim3(nblocks(n)), dim3(TPB), 0, s, a, (const Cand *)w.cand_tmp,
                        (const Cand *)w.cand, (const uint32_t *)w.cell_start, (const uint32_t *)out.start,
-                       (const uint32_t *)w.stage, out.j, cap, out.bcur, out.bidx, out.bsrc);
+                       (const uint32_t *)w.stage, out.j, cap, out.bcur, out.bidx, out.bsrc,
+                       (const FacetDev *)w.fac);
     hipLaunchKernelGGL(k_blist_sort, dim3(nblocks(n)), dim3(TPB), 0, s, out.start, out.bstart, n, cap, out.bidx,
                        out.bsrc);
     launch_owner_flags(out, a.own_sph0, a.n_owners, n, cap, s);
@@ -666,6 +849,14 @@ void launch_judge(const DetectArgs &a, CdWork &w, const AcsBuf &cur, int64_t cap
                        w.cell_start, (uint32_t *)nullptr, (const uint32_t *)nullptr, (uint32_t *)nullptr,
                        cap, (const uint32_t *)cur.start, (const uint32_t *)cur.j, &ctr->miss,
                        (const uint32_t *)nullptr, (uint32_t *)nullptr, 0u);
+    if (a.n_tri > 0) {
+        launch_facet_prepare(a, w, s);
+        hipLaunchKernelGGL(k_facet_walk<FMODE_JUDGE>, dim3(facet_walk_blocks(a)), dim3(TPB), 0, s, a,
+                           (const FacetDev *)w.fac, (const uint32_t *)w.frow, (const Cand *)w.cand,
+                           (const uint32_t *)w.cell_start, (uint32_t *)nullptr, (uint32_t *)nullptr,
+                           (const uint32_t *)cur.start, (const uint32_t *)cur.j, cap, &ctr->miss,
+                           (const uint32_t *)nullptr, (uint32_t *)nullptr, 0u);
+    }
 }
 
 void launch_remap(const AcsBuf &o, AcsBuf &nb, int64_t ns, DevCounters *ctr, int newbuf, int rolling,
@@ -682,12 +873,20 @@ void launch_detect_plain(const DetectArgs &a, CdWork &w, uint32_t *start, uint32
     launch_bin(a, w, s, w.count, n + 1, nullptr, 0, false);
     hipLaunchKernelGGL(k_detect_stage, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,
                        (const float4 *)w.candf, w.cell_start, w.count, w.stage, (uint32_t *)nullptr);
+    if (a.n_tri > 0) {
+        launch_facet_prepare(a, w, s);
+        hipLaunchKernelGGL(k_facet_walk<FMODE_STAGE>, dim3(facet_walk_blocks(a)), dim3(TPB), 0, s, a,
+                           (const FacetDev *)w.fac, (const uint32_t *)w.frow, (const Cand *)w.cand,
+                           (const uint32_t *)w.cell_start, w.count, w.stage, (const uint32_t *)nullptr,
+                           (const uint32_t *)nullptr, cap, (uint32_t *)nullptr, (const uint32_t *)nullptr,
+                           (uint32_t *)nullptr, 0u);
+    }
     scan_exclusive_u32(w.count, start, n, w.partials, s);
     hipLaunchKernelGGL(k_record_total, dim3(1), dim3(1), 0, s, start, n, ctr);
     hipLaunchKernelGGL(k_compact, dim3(nblocks(n)), dim3(TPB), 0, s, a, (const Cand *)w.cand_tmp,
                        (const Cand *)w.cand, (const uint32_t *)w.cell_start, (const uint32_t *)start,
                        (const uint32_t *)w.stage, j, cap, (uint32_t *)nullptr, (uint32_t *)nullptr,
-                       (uint32_t *)nullptr);
+                       (uint32_t *)nullptr, (const FacetDev *)w.fac);
 }
 
 void launch_label_judge(const DetectArgs &a, CdWork &w, const uint32_t *lab_start, const uint32_t *lab_j,
@@ -699,4 +898,11 @@ void launch_label_judge(const DetectArgs &a, CdWork &w, const uint32_t *lab_star
     hipLaunchKernelGGL(k_detect<MODE_LABEL>, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,
                        w.cell_start, (uint32_t *)nullptr, (const uint32_t *)nullptr, (uint32_t *)nullptr,
                        cap, lab_start, lab_j, (uint32_t *)nullptr, cellmap, first_miss, tval);
+    if (a.n_tri > 0) {
+        launch_facet_prepare(a, w, s);
+        hipLaunchKernelGGL(k_facet_walk<FMODE_LABEL>, dim3(facet_walk_blocks(a)), dim3(TPB), 0, s, a,
+                           (const FacetDev *)w.fac, (const uint32_t *)w.frow, (const Cand *)w.cand,
+                           (const uint32_t *)w.cell_start, (uint32_t *)nullptr, (uint32_t *)nullptr, lab_start,
+                           lab_j, cap, (uint32_t *)nullptr, cellmap, first_miss, tval);
+    }
 }

@@ -170,3 +170,93 @@ __device__ inline void wall_point(const WallDev &w, int64_t step, double h, doub
     p[1] = w.geom[1] + w.vel[1] * t;
     p[2] = w.geom[2] + w.vel[2] * t;
 }
+
+// ---------------------------------------------------------------------------
+// triangle facets of rigid meshes
+// ---------------------------------------------------------------------------
+// The pose of mesh g among the (at most MAX_MESHES) poses passed by value:
+// selected with constant indices so the kernel arguments are never copied
+// to private memory.
+__device__ inline MeshPose pose_of(const MeshPoses &P, int32_t g)
+{
+    MeshPose r = P.m[0];
+#pragma unroll
+    for (int k = 1; k < MAX_MESHES; ++k)
+        if (g == k) r = P.m[k];
+    return r;
+}
+
+// World vertices of a facet: p + R v for each vertex v.
+__device__ inline void facet_world(const TriDev &t, const MeshPose &P, double *w)
+{
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        const double x0 = t.v[3 * v], x1 = t.v[3 * v + 1], x2 = t.v[3 * v + 2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            w[3 * v + k] = P.p[k] + ((P.R[3 * k] * x0 + P.R[3 * k + 1] * x1) + P.R[3 * k + 2] * x2);
+    }
+}
+
+__device__ inline double dot3d(const double *u, const double *v) { return (u[0] * v[0] + u[1] * v[1]) + u[2] * v[2]; }
+
+// Closest point q of the triangle (a, b, c) to p by the Voronoi-region test
+// on barycentric quantities (Ericson, Real-Time Collision Detection, 2005,
+// Sec. 5.1.5): a vertex, a point of an edge, or the projection onto the face.
+__device__ inline void tri_closest(const double *a, const double *b, const double *c, const double *p, double *q)
+{
+    double e1[3], e2[3], r[3];
+    for (int k = 0; k < 3; ++k) {
+        e1[k] = b[k] - a[k];
+        e2[k] = c[k] - a[k];
+        r[k] = p[k] - a[k];
+    }
+    const double s1 = dot3d(e1, r), s2 = dot3d(e2, r);
+    if (s1 <= 0.0 && s2 <= 0.0) {
+        for (int k = 0; k < 3; ++k) q[k] = a[k];
+        return;
+    }
+    for (int k = 0; k < 3; ++k) r[k] = p[k] - b[k];
+    const double s3 = dot3d(e1, r), s4 = dot3d(e2, r);
+    if (s3 >= 0.0 && s4 <= s3) {
+        for (int k = 0; k < 3; ++k) q[k] = b[k];
+        return;
+    }
+    const double uc = s1 * s4 - s3 * s2;
+    if (uc <= 0.0 && s1 >= 0.0 && s3 <= 0.0) {
+        const double t = s1 / (s1 - s3);
+        for (int k = 0; k < 3; ++k) q[k] = a[k] + t * e1[k];
+        return;
+    }
+    for (int k = 0; k < 3; ++k) r[k] = p[k] - c[k];
+    const double s5 = dot3d(e1, r), s6 = dot3d(e2, r);
+    if (s6 >= 0.0 && s5 <= s6) {
+        for (int k = 0; k < 3; ++k) q[k] = c[k];
+        return;
+    }
+    const double ub = s5 * s2 - s1 * s6;
+    if (ub <= 0.0 && s2 >= 0.0 && s6 <= 0.0) {
+        const double t = s2 / (s2 - s6);
+        for (int k = 0; k < 3; ++k) q[k] = a[k] + t * e2[k];
+        return;
+    }
+    const double ua = s3 * s6 - s5 * s4;
+    const double g43 = s4 - s3, g56 = s5 - s6;
+    if (ua <= 0.0 && g43 >= 0.0 && g56 >= 0.0) {
+        const double t = g43 / (g43 + g56);
+        for (int k = 0; k < 3; ++k) q[k] = b[k] + t * (c[k] - b[k]);
+        return;
+    }
+    const double inv = 1.0 / ((ua + ub) + uc);
+    const double tv = ub * inv, tw = uc * inv;
+    for (int k = 0; k < 3; ++k) q[k] = (a[k] + e1[k] * tv) + e2[k] * tw;
+}
+
+// Squared distance of x to the facet with world vertices w[9], and the
+// closest point.
+__device__ inline double facet_dist2(const double *w, const double *x, double *q)
+{
+    tri_closest(w, w + 3, w + 6, x, q);
+    const double dx = x[0] - q[0], dy = x[1] - q[1], dz = x[2] - q[2];
+    return (dx * dx + dy * dy) + dz * dz;
+}

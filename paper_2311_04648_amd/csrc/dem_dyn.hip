@@ -84,11 +84,15 @@ struct ContactOut {
     float3 F;        // force on A (normal + tangential)
     float3 Ft;       // F plus the rolling-resistance force (torques only)
     float3 armA;     // contact point minus A's owner centre
-    float3 armB;     // contact point minus B's owner centre (wall: wall point)
+    float3 armB;     // contact point minus B's owner centre (wall: wall point; facet: mesh reference point)
     float4 h;        // history after the step (xi, contact age)
     bool touching;
 };
 
+// FACETS: the set may hold sphere-facet contacts (systems with meshes; the
+// FP64 closest-point code raises the register demand, so systems without
+// meshes use the variant without it).
+template <bool FACETS>
 __device__ __forceinline__ void contact_eval(const DynArgs &a, const SphRec &sA, const OwnerKin &kA,
                                              const double *xA, uint32_t jp, float4 hold, ContactOut &out)
 {
@@ -125,6 +129,31 @@ __device__ __forceinline__ void contact_eval(const DynArgs &a, const SphRec &sA,
             XB[2] = kB.X[2];
             vB = kB.v;
             wB = kB.w;
+        }
+    } else if (FACETS && jp >= (uint32_t)Ns + (uint32_t)a.n_walls) {
+        // facet of a rigid mesh: normal from the closest point of the facet
+        // to the centre; the facet acts as a flat surface (R = r_A) of
+        // infinite mass moving with the mesh
+        const TriDev t = a.tri[jp - (uint32_t)Ns - (uint32_t)a.n_walls];
+        const MeshPose P = a.poses[t.mesh];
+        double w[9], q[3];
+        facet_world(t, P, w);
+        const double d2 = facet_dist2(w, xA, q);
+        touching = d2 < radA * radA && d2 > 0.0;
+        if (touching) {
+            const double d = sqrt(d2);
+            nrm[0] = (xA[0] - q[0]) / d;
+            nrm[1] = (xA[1] - q[1]) / d;
+            nrm[2] = (xA[2] - q[2]) / d;
+            delta = radA - d;
+            Rbar = (float)radA;
+            mbar = kA.mass;
+            matB = (uint32_t)P.mat;
+            XB[0] = P.p[0];
+            XB[1] = P.p[1];
+            XB[2] = P.p[2];
+            vB = f3(P.vel[0], P.vel[1], P.vel[2]);
+            wB = f3(P.omega[0], P.omega[1], P.omega[2]);
         }
     } else {
         const WallDev wd = a.walls[jp - (uint32_t)Ns];
@@ -258,6 +287,7 @@ __device__ inline void store_hist(float *hx, float *hy, float *hz, float *hw, ui
 
 // Two-kernel path (forces without integration): A-side sums per sphere and
 // the reaction on B per contact, history updated in place.
+template <bool FACETS>
 __global__ void __launch_bounds__(TPB) k_force(DynArgs a, const uint32_t *start, const uint32_t *jarr,
                                                float *hx, float *hy, float *hz, float *hw, float *aF, float *aT,
                                                float *bF, float *bT, int64_t cap, const DevCounters *ctr)
@@ -276,7 +306,7 @@ __global__ void __launch_bounds__(TPB) k_force(DynArgs a, const uint32_t *start,
         owner_kin(rA, sA, a.aux, a.q, a.tpos, a.org, kA, xA);
         for (uint32_t c = c0; c < c1; ++c) {
             ContactOut co;
-            contact_eval(a, sA, kA, xA, jarr[c], load_hist(hx, hy, hz, hw, c, a.rolling), co);
+            contact_eval<FACETS>(a, sA, kA, xA, jarr[c], load_hist(hx, hy, hz, hw, c, a.rolling), co);
             store_hist(hx, hy, hz, hw, c, co.h, a.rolling);
             if (!co.touching) {
                 bF[c] = 0.f;
@@ -476,7 +506,7 @@ __global__ void __launch_bounds__(TPB) k_fold_integrate(DynArgs a, const uint32_
 // writes (rec_out, q_out, second history): no thread reads what another
 // writes.  When the step is stopped (capacity or divergence) the state and
 // history are copied unchanged.
-template <bool SINGLES>
+template <bool SINGLES, bool FACETS>
 __global__ void __launch_bounds__(TPB, 4) k_step_fused(DynArgs a, OwnerRec *rec_out, double *q_out,
                                                     const uint32_t *start, const uint32_t *jarr,
                                                     const uint32_t *bstart, const uint32_t *bidx,
@@ -557,7 +587,7 @@ __global__ void __launch_bounds__(TPB, 4) k_step_fused(DynArgs a, OwnerRec *rec_
                 double xA[3];
                 owner_kin(rA, sA, a.aux, a.q, a.tpos, a.org, kA, xA);
                 ContactOut co;
-                contact_eval(a, sA, kA, xA, jp, load_hist(hx, hy, hz, hw, c, a.rolling), co);
+                contact_eval<FACETS>(a, sA, kA, xA, jp, load_hist(hx, hy, hz, hw, c, a.rolling), co);
                 if (aside) {
                     store_hist(ox, oy, oz, ow, c, co.h, a.rolling);
                     if (co.touching) {
@@ -606,10 +636,12 @@ __global__ void __launch_bounds__(256) k_reduce_max(const float *blkmax, int64_t
 // each geometry moves at most v t + |g| t^2 / 2 when nothing but gravity
 // accelerates it (v: top speed of the last step); 10 % is added.  Capped
 // by the run margin (the bins were sized for it), which is flagged.
-__global__ void __launch_bounds__(64) k_adaptive_margin(DevCounters *ctr, double t, double gmag, double cap)
+__global__ void __launch_bounds__(64) k_adaptive_margin(DevCounters *ctr, double t, double gmag, double cap,
+                                                         double vfloor)
 {
     if (threadIdx.x != 0) return;
-    const double v = sqrt((double)__uint_as_float(ctr->maxv2[0]));
+    // top sphere speed, or the fastest point of a mesh if that is faster
+    const double v = fmax(sqrt((double)__uint_as_float(ctr->maxv2[0])), vfloor);
     double m = 1.1 * (v * t + 0.5 * gmag * t * t);
     uint32_t capped = 0u;
     if (!(m <= cap)) {
@@ -627,9 +659,9 @@ void launch_noop(hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
     hipExtLaunchKernelGGL(k_noop, dim3(1), dim3(64), 0, s, ev0, ev1, 0);
 }
 
-void launch_adaptive_margin(DevCounters *ctr, double t, double gmag, double cap, hipStream_t s)
+void launch_adaptive_margin(DevCounters *ctr, double t, double gmag, double cap, double vfloor, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_adaptive_margin, dim3(1), dim3(64), 0, s, ctr, t, gmag, cap);
+    hipLaunchKernelGGL(k_adaptive_margin, dim3(1), dim3(64), 0, s, ctr, t, gmag, cap, vfloor);
 }
 
 void launch_reduce_max(const DynArgs &a, DevCounters *ctr, hipStream_t s)
@@ -640,7 +672,8 @@ void launch_reduce_max(const DynArgs &a, DevCounters *ctr, hipStream_t s)
 void launch_force(const DynArgs &a, AcsBuf &cur, StepBufs &sb, DevCounters *ctr, hipStream_t s,
                   hipEvent_t ev0, hipEvent_t ev1)
 {
-    hipExtLaunchKernelGGL(k_force, dim3(nblocks(a.n_spheres)), dim3(TPB), 0, s, ev0, ev1, 0, a, cur.start,
+    auto kern = a.n_tri > 0 ? k_force<true> : k_force<false>;
+    hipExtLaunchKernelGGL(kern, dim3(nblocks(a.n_spheres)), dim3(TPB), 0, s, ev0, ev1, 0, a, cur.start,
                           (const uint32_t *)cur.j, cur.hx, cur.hy, cur.hz, cur.hw, sb.aF, sb.aT, sb.bF, sb.bT,
                           sb.cap, (const DevCounters *)ctr);
 }
@@ -648,7 +681,8 @@ void launch_force(const DynArgs &a, AcsBuf &cur, StepBufs &sb, DevCounters *ctr,
 void launch_step_fused(const DynArgs &a, OwnerRec *rec_out, double *q_out, const AcsBuf &cur, int64_t cap,
                        DevCounters *ctr, hipStream_t s)
 {
-    auto kern = a.has_clumps ? k_step_fused<false> : k_step_fused<true>;
+    auto kern = a.n_tri > 0 ? (a.has_clumps ? k_step_fused<false, true> : k_step_fused<true, true>)
+                            : (a.has_clumps ? k_step_fused<false, false> : k_step_fused<true, false>);
     hipLaunchKernelGGL(kern, dim3(nblocks(a.n_owners)), dim3(TPB), 0, s, a, rec_out, q_out,
                        (const uint32_t *)cur.start, (const uint32_t *)cur.j, (const uint32_t *)cur.bstart,
                        (const uint32_t *)cur.bidx, (const uint32_t *)cur.bsrc, (const uint8_t *)cur.oany,

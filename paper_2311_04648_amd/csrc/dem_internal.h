@@ -5,7 +5,7 @@
 //            OwnerAux[No] (inverse inertia + template), double4 q[No]
 //   spheres  SphRec[Ns] (owner, radius, material, template component)
 //   contacts per active-set buffer: acs_start[Ns+1] (CSR by lower sphere
-//            id), acs_j[cap] (partner: sphere id, or Ns + wall index),
+//            id), acs_j[cap] (partner: sphere id, Ns + wall index, or Ns + W + facet),
 //            hist x/y/z [cap] (SoA float), B-side lists bstart/bidx
 #pragma once
 
@@ -55,6 +55,37 @@ struct __align__(16) WallDev {
     double omega[3];
     int32_t type;
     int32_t mat;
+};
+
+// A facet of a rigid mesh: vertices in the mesh frame, mesh index.
+struct __align__(16) TriDev {
+    double v[9];
+    int32_t mesh;
+    int32_t pad;
+};
+
+// Pose of a mesh at one step (computed on the host) and its rigid motion.
+struct MeshPose {
+    double p[3];       // reference point
+    double R[9];       // rotation, row-major
+    float vel[3];      // velocity of the reference point
+    float omega[3];    // angular velocity (world)
+    int32_t mat;
+    int32_t pad;
+};
+
+constexpr int MAX_MESHES = 4;
+
+struct MeshPoses {
+    MeshPose m[MAX_MESHES];
+};
+
+// A facet at the pose of one detection: world vertices, their box, and the
+// range of bins whose spheres may touch it (bins cx0 .. cx0 + ncx - 1, etc.).
+struct __align__(16) FacetDev {
+    double v[9];
+    double lo[3], hi[3];
+    int32_t cx0, ncx, cy0, ncy, cz0, ncz;
 };
 
 // Candidate record in bin-sorted order: exact FP64 centre, radius, sphere id.
@@ -138,6 +169,10 @@ struct DetectArgs {
     int64_t n_owners;
     double h;
     int64_t step;
+    double rmax;            // largest sphere radius
+    const TriDev *tri;      // [n_tri] facets of the meshes
+    int32_t n_tri;
+    MeshPoses poses;        // mesh poses at `step`
 };
 
 struct CdWork {
@@ -148,6 +183,8 @@ struct CdWork {
     uint32_t *count;       // [Ns+1]
     uint32_t *stage;       // [16 Ns] staged partners of the single-traversal detection
     uint32_t *hist, *partials;
+    FacetDev *fac;         // [n_tri] facets at the pose of the detection
+    uint32_t *frow;        // [n_tri + 1] bin rows per facet, then their offsets
     int sort_bits;
     int sort_mode;         // 0: one-pass bin sort, 1: 8-bit LSD radix passes
 };
@@ -219,6 +256,9 @@ struct DynArgs {
     int32_t rolling;        // some material pair has rolling resistance
     int32_t cur;            // active-set buffer in use (for statistics)
     float *blkmax;          // per-block max |v|^2 of the last integration [ceil(No/256)]
+    const TriDev *tri;      // [n_tri] facets of the meshes
+    int32_t n_tri;
+    const MeshPose *poses;  // [MAX_MESHES] mesh poses at `step` (device memory; null without meshes)
 };
 
 struct StepBufs {
@@ -243,6 +283,6 @@ void launch_noop(hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 // max |v|^2 of the last integration into ctr->maxv2[0]
 // adaptive schedule: margin of the next detection from the top speed
 // (after launch_reduce_max), into ctr->margin
-void launch_adaptive_margin(DevCounters *ctr, double t, double gmag, double cap, hipStream_t s);
+void launch_adaptive_margin(DevCounters *ctr, double t, double gmag, double cap, double vfloor, hipStream_t s);
 void launch_reduce_max(const DynArgs &a, DevCounters *ctr, hipStream_t s);
 

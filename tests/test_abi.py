@@ -133,3 +133,44 @@ def test_calls_before_bind_report_state_error():
     assert dem.lib().dem_step(ctx, 1, None, None, C.byref(stats)) == dem.DEM_ERR_STATE
     assert b"before dem_bind" in dem.lib().dem_last_error(ctx)
     dem.lib().dem_destroy(ctx)
+
+
+def _set_meshes(ctx, sysm, **over):
+    d = dict(n_mesh=sysm.n_mesh, n_tri=sysm.n_tri, tri_mesh=sysm.tri_mesh, tri_local=sysm.tri_local,
+             origin=sysm.mesh_origin, vel=sysm.mesh_vel, omega=sysm.mesh_omega, mat=sysm.mesh_mat)
+    d.update(over)
+    keep = [np.ascontiguousarray(d[k], dtype=np.int32 if k in ("tri_mesh", "mat") else np.float64)
+            for k in ("tri_mesh", "tri_local", "origin", "vel", "omega", "mat")]
+    M = dem.Meshes(int(d["n_mesh"]), int(d["n_tri"]), *[C.c_void_p(a.ctypes.data) for a in keep])
+    st = dem.lib().dem_set_meshes(ctx, C.byref(M))
+    return st, dem.lib().dem_last_error(ctx).decode()
+
+
+def test_meshes_grow_the_workspace_and_are_validated():
+    _ensure_built()
+    s = W.small_mixer(0, n=60)
+    st, ctx, msg = _create(s)
+    assert st == dem.DEM_OK, msg
+    nb0 = C.c_int64()
+    assert dem.lib().dem_workspace_size(ctx, 1000, C.byref(nb0)) == dem.DEM_OK
+    st, msg = _set_meshes(ctx, s)
+    assert st == dem.DEM_OK, msg
+    nb1 = C.c_int64()
+    assert dem.lib().dem_workspace_size(ctx, 1000, C.byref(nb1)) == dem.DEM_OK
+    # per-facet buffers (two detection workspaces), facet table, pose ring
+    assert nb1.value >= nb0.value + s.n_tri * (2 * 144 + 80)
+    bad_mesh = s.tri_mesh.copy()
+    bad_mesh[5] = 1
+    nan_tri = s.tri_local.copy()
+    nan_tri[3, 4] = np.nan
+    for over, what in [(dict(n_mesh=5), "n_mesh"), (dict(tri_mesh=bad_mesh), "unknown mesh"),
+                       (dict(mat=np.array([7])), "material"), (dict(tri_local=nan_tri), "finite"),
+                       (dict(omega=np.array([[0.0, np.inf, 0.0]])), "finite")]:
+        st, msg = _set_meshes(ctx, s, **over)
+        assert st == dem.DEM_ERR_ARG and what in msg, (over.keys(), msg)
+    # removing the meshes restores the workspace size
+    assert dem.lib().dem_set_meshes(ctx, None) == dem.DEM_OK
+    nb2 = C.c_int64()
+    assert dem.lib().dem_workspace_size(ctx, 1000, C.byref(nb2)) == dem.DEM_OK
+    assert nb2.value == nb0.value
+    dem.lib().dem_destroy(ctx)

@@ -38,6 +38,8 @@ def _full(name):
         return W.config3(seed=7), 200
     if name == "config4":
         return W.config4(seed=0), 100
+    if name == "mixer":
+        return W.mixer(seed=0), 400
     raise ValueError(name)
 
 
@@ -46,7 +48,7 @@ def _sample_spheres(keys, Ns, rng, n):
     return np.sort(rng.choice(i, size=min(n, i.size), replace=False))
 
 
-@pytest.mark.parametrize("name", ["config1", "config2", "config3", "config4"])
+@pytest.mark.parametrize("name", ["config1", "config2", "config3", "config4", "mixer"])
 def test_full_size_sampled_parity(dem, name):
     import torch
     s, presteps = _full(name)
@@ -65,6 +67,13 @@ def test_full_size_sampled_parity(dem, name):
     sample = _sample_spheres(keys, s.n_spheres, rng, nrow)
     # also a few spheres with no contact
     sample = np.unique(np.r_[sample, rng.choice(s.n_spheres, 8, replace=False)])
+    if s.n_tri > 0:
+        # and spheres touching the impeller's facets
+        kj0 = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
+        fi = np.unique((keys >> np.uint64(32)).astype(np.int64)[kj0 >= s.n_spheres + s.n_walls])
+        print(f"{name}: {fi.size} spheres with facet contacts", flush=True)
+        assert fi.size > 0
+        sample = np.unique(np.r_[sample, rng.choice(fi, size=min(24, fi.size), replace=False)])
     rows = o.detect_rows(st, s.margin, sample, step=g["step"])
     ki = (keys >> np.uint64(32)).astype(np.int64)
     for i, row in zip(sample, rows):

@@ -517,15 +517,15 @@ def quad_grid(p0, e1, e2, n1, n2):
     return np.asarray(tris)
 
 
-def bladed_mixer(radius, height, n_blades=4, hub_radius=None, n_r=15, n_z=12, n_theta=48, n_hub_z=15):
+def bladed_mixer(radius, height, n_blades=4, hub_radius=None, n_r=15, n_z=12, n_theta=48, n_hub_z=15, phase=0.0):
     """A mixer impeller about the z axis in its own frame: n_blades flat
-    vertical blades from the hub to 0.9 radius, z in [0, height], and a
-    cylindrical hub, all triangulated (4 blades with the defaults: 2880
-    facets)."""
+    vertical blades from the hub to 0.9 radius at the angles
+    phase + 2 pi k / n_blades, z in [0, height], and a cylindrical hub, all
+    triangulated (4 blades with the defaults: 2880 facets)."""
     hub = hub_radius if hub_radius is not None else 0.08 * radius
     parts = []
     for k in range(n_blades):
-        th = 2.0 * np.pi * k / n_blades
+        th = phase + 2.0 * np.pi * k / n_blades
         d = np.array([np.cos(th), np.sin(th), 0.0])
         parts.append(quad_grid(hub * d, (0.9 * radius - hub) * d, (0, 0, height), n_r, n_z))
     ring = []
@@ -569,30 +569,82 @@ def small_mixer(seed, n=400, vel=0.1, omega_z=2.0 * np.pi, dt=2e-6, margin=0.000
     return add_meshes(sysm, dict(tri=tri, origin=(0, 0, 0.0005), omega=(0, 0, omega_z)))
 
 
-def mixer(seed=0, n=1_000_000, r=(0.003, 0.0035)):
-    """The scaling workload of the paper's Sec. 5 with a synthetic mesh: a
-    bladed impeller of 2880 facets (radius 0.49 m, blade height 0.15 m)
-    turning at 2 pi rad/s about z in a 1 x 1 m box chamber;
-    spheres r ~ U(3, 3.5) mm released from a jittered lattice filling a
-    cylinder of radius 0.5 m and height 1/3 m above the impeller;
-    E = 1e9 Pa, nu = 0.3, CoR = 0.2, rho = 2600; dt = 5e-7 s; margin 0.1 r_min."""
+def _blade_clearance(X, radius, height, n_blades, hub, origin, phase):
+    """Distance of points X [n,3] to the impeller of bladed_mixer (blades as
+    flat rectangles, hub as a cylinder side), for placing spheres clear of it."""
+    P = X - np.asarray(origin, dtype=np.float64)[None]
+    best = np.full(X.shape[0], np.inf)
+    for k in range(n_blades):
+        th = phase + 2.0 * np.pi * k / n_blades
+        d = np.array([np.cos(th), np.sin(th), 0.0])
+        a = np.clip(P @ d, hub, 0.9 * radius)
+        z = np.clip(P[:, 2], 0.0, height)
+        q = a[:, None] * d[None] + z[:, None] * np.array([0.0, 0.0, 1.0])[None]
+        best = np.minimum(best, np.linalg.norm(P - q, axis=1))
+    rho = np.hypot(P[:, 0], P[:, 1])
+    dz = np.maximum(np.maximum(-P[:, 2], P[:, 2] - height), 0.0)
+    best = np.minimum(best, np.hypot(np.abs(rho - hub), dz))
+    return best
+
+
+def mixer_bed(seed, n, R, Hb, r, E, cor, dt, margin, omega_z, mesh_res, vel=0.0, name="mixer"):
+    """Spheres r ~ U(r) on a jittered lattice filling, from the floor up, the
+    cylinder of radius R inside a 2R x 2R box chamber, around a bladed
+    impeller (radius 0.98 R, blade height Hb, turning at omega_z about z):
+    lattice sites closer than r_max + 0.3 mm to the impeller are left empty,
+    so the blades start inside the bed and sweep it from the first step (the
+    blades are turned by 0.3 rad against the lattice rows, so the gaps in
+    front of them spread from 0.3 mm to one lattice spacing)."""
     rng = np.random.default_rng(seed)
-    R, Hb = 0.5, 0.15
     s = 2 * r[1] + 0.0002
     per = int((2 * R) // s)
     ax = (np.arange(per) - 0.5 * (per - 1)) * s
     layer = np.array([(x, y) for x in ax for y in ax if x * x + y * y < (R - r[1] - 0.002) ** 2])
-    layers = -(-n // layer.shape[0])
-    z0 = Hb + 0.01
-    X = np.vstack([np.c_[layer, np.full(layer.shape[0], z0 + k * s)] for k in range(layers)])[:n]
+    Ri = 0.98 * R
+    hub = 0.08 * Ri
+    origin = (0.0, 0.0, 0.001)
+    phase = 0.3
+    pts, k = [], 0
+    total = 0
+    while total < n:
+        Xl = np.c_[layer, np.full(layer.shape[0], r[1] + 0.0001 + k * s)]
+        keep = _blade_clearance(Xl, Ri, Hb, 4, hub, origin, phase) > r[1] + 0.0003
+        pts.append(Xl[keep])
+        total += int(keep.sum())
+        k += 1
+    X = np.vstack(pts)[:n]
     X = X + rng.uniform(-0.0001, 0.0001, size=X.shape)
     rad = rng.uniform(r[0], r[1], size=n)
+    V = rng.normal(0.0, vel, size=(n, 3)) if vel > 0 else np.zeros((n, 3))
     top = X[:, 2].max() + 0.02
     lo = np.array([-R - 0.005, -R - 0.005, -0.005])
     hi = np.array([R + 0.005, R + 0.005, top])
     walls = box_walls(np.array([-R, -R, 0.0]), np.array([R, R, top]))
-    mats = materials(E=1e9, nu=0.3, cor=0.2, mu=0.5)
-    sysm = assemble(np.full(n, -1), X, _qid(n), np.zeros((n, 3)), np.zeros((n, 3)), [], rad, None, walls, mats,
-                    (0, 0, -9.81), 5e-7, 0.1 * r[0], lo, hi, name="mixer", meta=dict(steps=5000, seed=seed))
-    tri = bladed_mixer(R * 0.98, Hb)
-    return add_meshes(sysm, dict(tri=tri, origin=(0, 0, 0.001), omega=(0, 0, 2.0 * np.pi)))
+    mats = materials(E=E, nu=0.3, cor=cor, mu=0.5)
+    sysm = assemble(np.full(n, -1), X, _qid(n), V, np.zeros((n, 3)), [], rad, None, walls, mats,
+                    (0, 0, -9.81), dt, margin, lo, hi, name=name, meta=dict(seed=seed))
+    tri = bladed_mixer(Ri, Hb, phase=phase, **mesh_res)
+    return add_meshes(sysm, dict(tri=tri, origin=origin, omega=(0, 0, omega_z)))
+
+
+def small_mixer_bed(seed, n=500, omega_z=20.0 * np.pi, vel=0.05):
+    """A small mixer bed for parity tests: 10 x 10 cm chamber, impeller of
+    radius 4.9 cm and blade height 2 cm (168 facets) turning at 10 rev/s (tip
+    speed 2.8 m/s, as in the full-size mixer),
+    r ~ U(2, 3) mm, E = 1e8 Pa, dt = 2e-6 s, margin 0.2 mm."""
+    return mixer_bed(seed, n, 0.05, 0.02, (0.002, 0.003), 1e8, 0.4, 2e-6, 0.0002, omega_z,
+                     dict(n_r=4, n_z=3, n_theta=12, n_hub_z=3), vel=vel, name=f"small_mixer_bed{seed}")
+
+
+def mixer(seed=0, n=1_000_000, r=(0.003, 0.0035)):
+    """The scaling workload of the paper's Sec. 5 with a synthetic mesh: a
+    bladed impeller of 2880 facets (radius 0.49 m, blade height 0.15 m)
+    turning at 2 pi rad/s about z in a 1 x 1 m box chamber, inside a bed of
+    spheres r ~ U(3, 3.5) mm filling the cylinder of radius 0.5 m from the
+    floor up (about 0.48 m for 1M spheres; the paper's run is timed in the
+    mixing state after the release has settled, which this bed stands in
+    for); E = 1e9 Pa, nu = 0.3, CoR = 0.2, rho = 2600; dt = 5e-7 s; margin
+    0.1 r_min."""
+    sysm = mixer_bed(seed, n, 0.5, 0.15, r, 1e9, 0.2, 5e-7, 0.1 * r[0], 2.0 * np.pi, {}, name="mixer")
+    sysm.meta["steps"] = 5000
+    return sysm
