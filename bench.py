@@ -61,7 +61,7 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, rolling=False, n_clump=None):
+def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, rolling=False, n_clump=None, n_tri=0):
     """Bytes one launch of a stage must move at minimum (unique data);
     `active` = spheres that appear in at least one contact:
     k_force: per sphere its row offset (4); per active sphere its record
@@ -73,7 +73,8 @@ def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, roll
       per clump owner the quaternion read + written 64); per active sphere
       its record, row and B-list offsets and its owner's sphere range (28);
       per contact the partner id (4), the history read + written (24, 32
-      with contact age) and the B-list entry with its source sphere (8).
+      with contact age) and the B-list entry with its source sphere (8);
+      with meshes, each facet's vertices and mesh index (80).
     k_fold_integrate: per owner the record read + write (96) and the inverse
       inertia: one isotropic value (4) when every owner is a single sphere,
       else three values and the template (16) plus the sphere range (4); per
@@ -83,18 +84,20 @@ def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, roll
       (32) written, radix passes (16 each), candidate gather (36 r + 32 w),
       one traversal reading 32 B of candidates per neighbour-row hit, row
       count and offsets (8), staging (4 per partner), B lists (16); per
-      contact partner id (4) and B-list bytes (16); the bin table (12 per bin).
+      contact partner id (4) and B-list bytes (16); the bin table (12 per bin);
+      with meshes, per facet its vertices read (80), its world vertices, box
+      and bin range written (144) and its row count and offset (8).
     k_remap: per sphere both row offsets (16); per contact new id (4), old id
       (4), history read (12) and written (12)."""
     if stage == "k_force":
         return Ns * 4 + active * 88 + C * 52
     if stage == "k_step_fused":
         nc = (No if n_clump is None else n_clump) if clumps else 0
-        return No * (113 if clumps else 101) + nc * 64 + active * 28 + C * (44 if rolling else 36)
+        return No * (113 if clumps else 101) + nc * 64 + active * 28 + C * (44 if rolling else 36) + n_tri * 80
     if stage == "k_fold_integrate":
         return No * (116 if clumps else 100) + Ns * 8 + active * 24 + C * 28
     if stage == "detect":
-        return Ns * (64 + 8 + 32 + 16 * passes + 68 + 32 + 8 + 16) + C * 24 + nbins * 12
+        return Ns * (64 + 8 + 32 + 16 * passes + 68 + 32 + 8 + 16) + C * 24 + nbins * 12 + n_tri * 232
     if stage == "k_remap":
         return Ns * 16 + C * 32
     raise ValueError(stage)
@@ -110,10 +113,10 @@ def kernel_sha(path, kernel):
     return hashlib.sha256("\n".join(lines[start:end + 1]).encode()).hexdigest()[:16]
 
 
-def load_traffic(kernel):
-    """HBM bytes per launch from committed rocprofv3 PMC summaries, if they
-    were taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", "traffic_config1.json")
+def load_traffic(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 PMC summaries of this
+    workload, if they were taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(p):
         return None
     try:
@@ -259,11 +262,12 @@ def main():
     C = st["mean_contacts"]
     passes = 1   # one-pass bin sort (the LSD radix option would take (sort_bits + 7) // 8)
     n_clump = int(np.sum(np.asarray(sysm.own_tmpl) >= 0))
+    n_tri = int(getattr(sysm, "n_tri", 0))
     algo = algorithmic_bytes(stages[dom], Ns, No, C, r["active"], r["info"]["nbins"], passes,
                              clumps=Ns != No, rolling=bool(np.any(np.asarray(sysm.mat_crr) > 0)),
-                             n_clump=n_clump)
+                             n_clump=n_clump, n_tri=n_tri)
     achieved = algo / (avg_ms * 1e-3) / 1e9
-    traffic = load_traffic(stages[dom])
+    traffic = load_traffic(stages[dom], args.workload)
     roofline = {"bound": "hbm", "kernel": stages[dom], "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes_per_launch": int(algo), "avg_launch_ms": round(avg_ms, 5),
@@ -271,13 +275,12 @@ def main():
                 "event_pairs": int(st["stage_n"][4]), "launches": n_launch}
     n_cd = max(int(st["stage_n"][2]), 1)
     cd_ms = tot[2] / n_cd
-    cd_bytes = algorithmic_bytes("detect", Ns, No, C, r["active"], r["info"]["nbins"], passes)
+    cd_bytes = algorithmic_bytes("detect", Ns, No, C, r["active"], r["info"]["nbins"], passes, n_tri=n_tri)
     cd_chain = {"avg_ms": round(cd_ms, 4), "launches": n_cd, "algorithmic_bytes": int(cd_bytes),
                 "achieved_GBs": round(cd_bytes / (cd_ms * 1e-3) / 1e9, 1),
                 "note": "detection chain on the second stream, concurrent with the dynamics stream"}
 
     cpu = None
-    n_tri = int(getattr(sysm, "n_tri", 0))
     if not args.no_cpu and Ns <= 10_000_000 and n_tri == 0:
         import oracle
         o = oracle.Oracle(sysm)
@@ -317,11 +320,11 @@ def main():
         Cm, act = s2["mean_contacts"], rr["active"]
         if args.dyn_path == 0:
             dyn_b = algorithmic_bytes("k_step_fused", Ns, No, Cm, act, 0, passes, clumps=Ns != No, rolling=rolling,
-                                      n_clump=n_clump)
+                                      n_clump=n_clump, n_tri=n_tri)
         else:
             dyn_b = (algorithmic_bytes("k_force", Ns, No, Cm, act, 0, passes)
                      + algorithmic_bytes("k_fold_integrate", Ns, No, Cm, act, 0, passes, clumps=Ns != No))
-        per_cd = (algorithmic_bytes("detect", Ns, No, Cm, act, rr["info"]["nbins"], passes)
+        per_cd = (algorithmic_bytes("detect", Ns, No, Cm, act, rr["info"]["nbins"], passes, n_tri=n_tri)
                   + algorithmic_bytes("k_remap", Ns, No, Cm, act, 0, passes))
         return dyn_b + per_cd * s2["cds"] / args.steps
 

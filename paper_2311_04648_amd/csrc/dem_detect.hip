@@ -55,7 +55,8 @@ __global__ void __launch_bounds__(TPB) k_cd_prepare(DetectArgs a, uint32_t *keys
                                                     Cand *cand_tmp, uint32_t *cell_count)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n_spheres) return;
+    const bool active = i < a.n_spheres;
+    if (!active) i = a.n_spheres - 1;   // the tail lanes take part in the wave's run claim only
     SphRec s = load_sph(a.sph + i);
     OwnerRec r = load_rec(a.rec + s.owner);
     double x[3];
@@ -64,6 +65,8 @@ __global__ void __launch_bounds__(TPB) k_cd_prepare(DetectArgs a, uint32_t *keys
     int cy = bin_coord(x[1], a.grid.lo[1], a.grid.inv_b, a.grid.ny);
     int cz = bin_coord(x[2], a.grid.lo[2], a.grid.inv_b, a.grid.nz);
     uint32_t key = ((uint32_t)cz * (uint32_t)a.grid.ny + (uint32_t)cy) * (uint32_t)a.grid.nx + (uint32_t)cx;
+    wave_run_claim(cell_count, key, active);
+    if (!active) return;
     keys[i] = key;
     if (vals) vals[i] = (uint32_t)i;   // ids to sort (the one-pass sort writes its own)
     Cand c;
@@ -73,21 +76,22 @@ __global__ void __launch_bounds__(TPB) k_cd_prepare(DetectArgs a, uint32_t *keys
     c.r = s.rad;
     c.id = (uint32_t)i;
     cand_tmp[i] = c;
-    atomicAdd(&cell_count[key], 1u);
 }
 
 // One-pass sort of (bin key, sphere id): the per-bin counts and their scan
 // (the cell ranges) are the histogram and offsets of a single radix digit
 // as wide as the key; each sphere claims a slot of its bin with an atomic
-// cursor, and each bin then orders its few ids ascending, so the result is
-// identical to a stable sort.
+// cursor (one atomic per run of equal keys in a wave), and when asked each
+// bin then orders its few ids ascending, so the result is identical to a
+// stable sort.
 __global__ void __launch_bounds__(TPB) k_bucket_scatter(const uint32_t *keys_in, int64_t n, uint32_t *cursor,
                                                         uint32_t *keys_out, uint32_t *vals_out)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint32_t k = keys_in[i];
-    uint32_t pos = atomicAdd(&cursor[k], 1u);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = i < n;
+    const uint32_t k = keys_in[active ? i : n - 1];
+    const uint32_t pos = wave_run_claim(cursor, k, active);
+    if (!active) return;
     keys_out[pos] = k;
     vals_out[pos] = (uint32_t)i;
 }

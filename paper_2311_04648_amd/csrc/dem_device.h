@@ -87,6 +87,31 @@ __device__ inline uint32_t xcd_block(uint32_t b, uint32_t n)
     return x * per + (x < rem ? x : rem) + k;
 }
 
+// Claims one slot of counter[key] per active lane (active lanes form a
+// prefix of the wave): lanes of a run of equal keys in consecutive lanes
+// share one atomic, issued by the run's first lane with the run's length;
+// returns each lane's slot (the counter's old value plus its rank in the
+// run).  Spheres numbered in space-filling order put runs of neighbours in
+// one bin, whose atomics would otherwise serialise on one address.
+__device__ inline uint32_t wave_run_claim(uint32_t *counter, uint32_t key, bool active)
+{
+    const int lane = (int)(threadIdx.x & 63u);
+    const uint32_t prev = __shfl_up(key, 1, 64);
+    const bool head = active && (lane == 0 || prev != key);
+    const unsigned long long heads = __ballot(head), act = __ballot(active);
+    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);   // lanes 0 .. lane
+    const unsigned long long hb = heads & upto;
+    const int h = hb ? 63 - __clzll((long long)hb) : 0;
+    uint32_t base = 0;
+    if (head) {
+        const unsigned long long above = (heads | ~act) & ~upto;   // next head or first inactive lane
+        const int next = above ? __ffsll((long long)above) - 1 : 64;
+        base = atomicAdd(&counter[key], (uint32_t)(next - lane));
+    }
+    base = __shfl(base, h, 64);
+    return base + (uint32_t)(lane - h);
+}
+
 __device__ inline float3 f3(float x, float y, float z) { return make_float3(x, y, z); }
 __device__ inline float3 operator+(float3 a, float3 b) { return f3(a.x + b.x, a.y + b.y, a.z + b.z); }
 __device__ inline float3 operator-(float3 a, float3 b) { return f3(a.x - b.x, a.y - b.y, a.z - b.z); }

@@ -92,9 +92,14 @@ struct ContactOut {
 // FACETS: the set may hold sphere-facet contacts (systems with meshes; the
 // FP64 closest-point code raises the register demand, so systems without
 // meshes use the variant without it).
-template <bool FACETS>
+// KNOWN_B: B is a sphere whose record and kinematics the caller already
+// holds (sBk, kBk, xBk; the fused step evaluates its B-list entries with
+// its own sphere as B); otherwise B is loaded from jp.
+template <bool FACETS, bool KNOWN_B = false>
 __device__ __forceinline__ void contact_eval(const DynArgs &a, const SphRec &sA, const OwnerKin &kA,
-                                             const double *xA, uint32_t jp, float4 hold, ContactOut &out)
+                                             const double *xA, uint32_t jp, float4 hold, ContactOut &out,
+                                             const SphRec *sBk = nullptr, const OwnerKin *kBk = nullptr,
+                                             const double *xBk = nullptr)
 {
     const int64_t Ns = a.n_spheres;
     const double radA = (double)sA.rad;
@@ -104,12 +109,21 @@ __device__ __forceinline__ void contact_eval(const DynArgs &a, const SphRec &sA,
     float3 vB = f3(0.f, 0.f, 0.f), wB = f3(0.f, 0.f, 0.f);
     uint32_t matB = 0;
     bool touching = false;
-    if ((int64_t)jp < Ns) {
-        const SphRec sB = load_sph(a.sph + jp);
-        const OwnerRec rB = load_rec(a.rec + sB.owner);
+    if (KNOWN_B || (int64_t)jp < Ns) {
+        SphRec sB;
         OwnerKin kB;
         double xB[3];
-        owner_kin(rB, sB, a.aux, a.q, a.tpos, a.org, kB, xB);
+        if (KNOWN_B) {
+            sB = *sBk;
+            kB = *kBk;
+            xB[0] = xBk[0];
+            xB[1] = xBk[1];
+            xB[2] = xBk[2];
+        } else {
+            sB = load_sph(a.sph + jp);
+            const OwnerRec rB = load_rec(a.rec + sB.owner);
+            owner_kin(rB, sB, a.aux, a.q, a.tpos, a.org, kB, xB);
+        }
         double dx = xA[0] - xB[0], dy = xA[1] - xB[1], dz = xA[2] - xB[2];
         double d2 = (dx * dx + dy * dy) + dz * dz;
         double radB = (double)sB.rad;
@@ -505,9 +519,13 @@ __global__ void __launch_bounds__(TPB) k_fold_integrate(DynArgs a, const uint32_
 // same, so both paths give the same bits.  Reads (a.rec, a.q, history),
 // writes (rec_out, q_out, second history): no thread reads what another
 // writes.  When the step is stopped (capacity or divergence) the state and
-// history are copied unchanged.
+// history are copied unchanged.  SINGLES: every owner is one sphere; FACETS:
+// the set may hold sphere-facet contacts.  Systems with clumps or meshes get
+// 3 waves per SIMD: the clump rotation and the FP64 closest point would
+// otherwise spill registers to scratch inside the contact loop, which costs
+// more than the lost occupancy.
 template <bool SINGLES, bool FACETS>
-__global__ void __launch_bounds__(TPB, 4) k_step_fused(DynArgs a, OwnerRec *rec_out, double *q_out,
+__global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fused(DynArgs a, OwnerRec *rec_out, double *q_out,
                                                     const uint32_t *start, const uint32_t *jarr,
                                                     const uint32_t *bstart, const uint32_t *bidx,
                                                     const uint32_t *bsrc, const uint8_t *oany,
@@ -565,29 +583,58 @@ __global__ void __launch_bounds__(TPB, 4) k_step_fused(DynArgs a, OwnerRec *rec_
         for (uint32_t s = s0; any && s < s1; ++s) {
             const uint32_t c0 = start[s], na = start[s + 1] - c0;
             const uint32_t b0 = bstart[s], nall = na + (bstart[s + 1] - b0);
+            // single spheres: the sphere's own record and kinematics come
+            // from the owner record already loaded, once, as geometry A of
+            // its row and geometry B of its B list (for clumps, whose
+            // kinematics hold more registers, they are loaded per item)
+            SphRec sS{};
+            OwnerKin kS{};
+            double xS[3] = {0.0, 0.0, 0.0};
+            if constexpr (SINGLES) {
+                sS = load_sph(a.sph + s);
+                owner_kin(r, sS, a.aux, a.q, a.tpos, a.org, kS, xS);
+            }
             // one loop over the sphere's A row, then its B list: each item is
             // evaluated from its A side by the same function
             float3 FA = f3(0.f, 0.f, 0.f), TA = f3(0.f, 0.f, 0.f);
             for (uint32_t t = 0; t < nall; ++t) {
                 const bool aside = t < na;
-                uint32_t c, iA, jp;
-                if (aside) {
-                    c = c0 + t;
-                    iA = s;
-                    jp = jarr[c];
-                } else {
-                    const uint32_t b = b0 + (t - na);
-                    c = bidx[b];
-                    iA = bsrc[b];
-                    jp = s;
-                }
-                const SphRec sA = load_sph(a.sph + iA);
-                const OwnerRec rA = load_rec(a.rec + sA.owner);
-                OwnerKin kA;
-                double xA[3];
-                owner_kin(rA, sA, a.aux, a.q, a.tpos, a.org, kA, xA);
                 ContactOut co;
-                contact_eval<FACETS>(a, sA, kA, xA, jp, load_hist(hx, hy, hz, hw, c, a.rolling), co);
+                uint32_t c;
+                if constexpr (SINGLES) {
+                    if (aside) {
+                        c = c0 + t;
+                        contact_eval<FACETS>(a, sS, kS, xS, jarr[c], load_hist(hx, hy, hz, hw, c, a.rolling), co);
+                    } else {
+                        const uint32_t b = b0 + (t - na);
+                        c = bidx[b];
+                        const SphRec sA = load_sph(a.sph + bsrc[b]);
+                        const OwnerRec rA = load_rec(a.rec + sA.owner);
+                        OwnerKin kA;
+                        double xA[3];
+                        owner_kin(rA, sA, a.aux, a.q, a.tpos, a.org, kA, xA);
+                        contact_eval<false, true>(a, sA, kA, xA, s, load_hist(hx, hy, hz, hw, c, a.rolling), co,
+                                                  &sS, &kS, xS);
+                    }
+                } else {
+                    uint32_t iA, jp;
+                    if (aside) {
+                        c = c0 + t;
+                        iA = s;
+                        jp = jarr[c];
+                    } else {
+                        const uint32_t b = b0 + (t - na);
+                        c = bidx[b];
+                        iA = bsrc[b];
+                        jp = s;
+                    }
+                    const SphRec sA = load_sph(a.sph + iA);
+                    const OwnerRec rA = load_rec(a.rec + sA.owner);
+                    OwnerKin kA;
+                    double xA[3];
+                    owner_kin(rA, sA, a.aux, a.q, a.tpos, a.org, kA, xA);
+                    contact_eval<FACETS>(a, sA, kA, xA, jp, load_hist(hx, hy, hz, hw, c, a.rolling), co);
+                }
                 if (aside) {
                     store_hist(ox, oy, oz, ow, c, co.h, a.rolling);
                     if (co.touching) {

@@ -278,3 +278,47 @@ def test_mesh_judge_counts_missing_like_oracle(dem):
     print(f"set {keys.size} missing {miss} oracle {ref}")
     assert ref > 0
     assert miss == ref
+
+
+def clumps_on_mesh_floor(seed=2, n=150):
+    """Tri- and five-sphere clumps and single spheres thrown down at 2 m/s
+    onto a facet floor 0.3 mm below the lowest sphere, the floor spinning at
+    5 rad/s about z (friction drags the clumps round)."""
+    s = W.small_clumps(seed, n=n, vel=0.3)
+    s.V[:, 2] = -2.0
+    o = oracle.Oracle(s)
+    xs = o.sphere_centres(o.state())
+    zf = float((xs[:, 2] - s.sph_rad).min()) - 0.0003
+    L = float(s.domain_hi[0] - s.domain_lo[0]) - 0.004
+    tri = W.quad_grid((-0.5 * L, -0.5 * L, 0.0), (L, 0, 0), (0, L, 0), 8, 8)
+    return W.add_meshes(s, dict(tri=tri, origin=(0.0, 0.0, zf), omega=(0.0, 0.0, 5.0)))
+
+
+def test_clumps_on_a_mesh_floor(dem):
+    """Clump systems with facets: delayed detection on two streams equals
+    every-step detection bit for bit; after the run the contact set equals
+    the oracle's and the forces agree within 1e-5."""
+    s = clumps_on_mesh_floor()
+    _, ga, ka, _ = _run(dem, s, 300, mode="every")
+    st_f, gb, _, _ = _run(dem, s, 300, mode="fixed", k=6, lam=3, judge=True, two_streams=True)
+    assert st_f["misses"] == 0
+    for k in ("X", "V", "W", "q"):
+        np.testing.assert_array_equal(ga[k], gb[k])
+    ctx = dem.DemContext(s, mode="fixed", margin=s.margin, capacity=64 * s.n_spheres)
+    ctx.set_state(X=ga["X"], q=ga["q"], V=ga["V"], W=ga["W"], step=ga["step"])
+    ctx.detect_contacts(s.margin)
+    keys, _ = ctx.get_contacts()
+    g = ctx.get_state()
+    st = {"X": g["X"].copy(), "q": g["q"].copy(), "V": g["V"].astype(np.float64), "W": g["W"].astype(np.float64)}
+    o = oracle.Oracle(s)
+    np.testing.assert_array_equal(keys, o.detect(st, s.margin, step=g["step"]))
+    fac = _keys_split(s, keys)
+    ctx.forces()
+    _, _, Fc = ctx.get_forces(keys.size)
+    ref = o.forces(st, keys, np.zeros((keys.size, 4)), step=g["step"])
+    touch = ref["touch"] > 0
+    print(f"contacts {keys.size} facet {fac.sum()} touching facet {(touch & fac).sum()}")
+    assert (touch & fac).sum() > 5
+    Fn = np.linalg.norm(ref["Fc"], axis=1)
+    rel = np.linalg.norm(Fc - ref["Fc"], axis=1) / np.maximum(Fn, 1e-3 * np.median(Fn[touch]))
+    assert rel.max() <= 1e-5

@@ -587,19 +587,31 @@ def _blade_clearance(X, radius, height, n_blades, hub, origin, phase):
     return best
 
 
-def mixer_bed(seed, n, R, Hb, r, E, cor, dt, margin, omega_z, mesh_res, vel=0.0, name="mixer"):
+def mixer_bed(seed, n, R, Hb, r, E, cor, dt, margin, omega_z, mesh_res, vel=0.0, name="mixer", packing="cubic",
+              gap=0.0002, jitter=0.0001):
     """Spheres r ~ U(r) on a jittered lattice filling, from the floor up, the
     cylinder of radius R inside a 2R x 2R box chamber, around a bladed
     impeller (radius 0.98 R, blade height Hb, turning at omega_z about z):
     lattice sites closer than r_max + 0.3 mm to the impeller are left empty,
     so the blades start inside the bed and sweep it from the first step (the
     blades are turned by 0.3 rad against the lattice rows, so the gaps in
-    front of them spread from 0.3 mm to one lattice spacing)."""
+    front of them spread from 0.3 mm to one lattice spacing).  The lattice is
+    simple cubic or face-centred cubic with nearest-neighbour distance
+    2 r_max + gap, each site jittered by U(-jitter, jitter) per axis."""
     rng = np.random.default_rng(seed)
-    s = 2 * r[1] + 0.0002
-    per = int((2 * R) // s)
-    ax = (np.arange(per) - 0.5 * (per - 1)) * s
-    layer = np.array([(x, y) for x in ax for y in ax if x * x + y * y < (R - r[1] - 0.002) ** 2])
+    s = 2 * r[1] + gap
+    if packing == "fcc":
+        h = s / np.sqrt(2.0)     # half the cubic cell: the layer spacing and the in-layer grid step
+    else:
+        h = s
+    per = int((2 * R) // h)
+    ax = (np.arange(per) - 0.5 * (per - 1)) * h
+    # x fastest inside a layer: consecutive ids are neighbours along x, so
+    # the bins of a wave of consecutive spheres are consecutive too
+    I, J = np.meshgrid(np.arange(per), np.arange(per), indexing="xy")
+    XY = np.c_[ax[I.ravel()], ax[J.ravel()]]
+    parity = (I.ravel() + J.ravel()) & 1
+    inside = (XY ** 2).sum(1) < (R - r[1] - 0.002) ** 2
     Ri = 0.98 * R
     hub = 0.08 * Ri
     origin = (0.0, 0.0, 0.001)
@@ -607,13 +619,15 @@ def mixer_bed(seed, n, R, Hb, r, E, cor, dt, margin, omega_z, mesh_res, vel=0.0,
     pts, k = [], 0
     total = 0
     while total < n:
-        Xl = np.c_[layer, np.full(layer.shape[0], r[1] + 0.0001 + k * s)]
+        sel = inside & (parity == (k & 1)) if packing == "fcc" else inside
+        layer = XY[sel]
+        Xl = np.c_[layer, np.full(layer.shape[0], r[1] + 0.0001 + k * h)]
         keep = _blade_clearance(Xl, Ri, Hb, 4, hub, origin, phase) > r[1] + 0.0003
         pts.append(Xl[keep])
         total += int(keep.sum())
         k += 1
     X = np.vstack(pts)[:n]
-    X = X + rng.uniform(-0.0001, 0.0001, size=X.shape)
+    X = X + rng.uniform(-jitter, jitter, size=X.shape)
     rad = rng.uniform(r[0], r[1], size=n)
     V = rng.normal(0.0, vel, size=(n, 3)) if vel > 0 else np.zeros((n, 3))
     top = X[:, 2].max() + 0.02
@@ -639,12 +653,15 @@ def small_mixer_bed(seed, n=500, omega_z=20.0 * np.pi, vel=0.05):
 def mixer(seed=0, n=1_000_000, r=(0.003, 0.0035)):
     """The scaling workload of the paper's Sec. 5 with a synthetic mesh: a
     bladed impeller of 2880 facets (radius 0.49 m, blade height 0.15 m)
-    turning at 2 pi rad/s about z in a 1 x 1 m box chamber, inside a bed of
-    spheres r ~ U(3, 3.5) mm filling the cylinder of radius 0.5 m from the
-    floor up (about 0.48 m for 1M spheres; the paper's run is timed in the
-    mixing state after the release has settled, which this bed stands in
-    for); E = 1e9 Pa, nu = 0.3, CoR = 0.2, rho = 2600; dt = 5e-7 s; margin
-    0.1 r_min."""
-    sysm = mixer_bed(seed, n, 0.5, 0.15, r, 1e9, 0.2, 5e-7, 0.1 * r[0], 2.0 * np.pi, {}, name="mixer")
+    turning at 2 pi rad/s about z in a 1 x 1 m box chamber, inside a dense
+    bed of spheres r ~ U(3, 3.5) mm on a face-centred cubic lattice (nearest
+    neighbours 7.05 mm apart, jittered by 0.01 mm, so gaps of about 0.02 to
+    1.05 mm) filling the
+    cylinder of radius 0.5 m from the floor up (about 0.32 m for 1M spheres,
+    the paper's 1/3 m; the paper's run is timed in the mixing state after the
+    release has settled, which this packed bed stands in for); E = 1e9 Pa,
+    nu = 0.3, CoR = 0.2, rho = 2600; dt = 5e-7 s; margin 0.1 r_min."""
+    sysm = mixer_bed(seed, n, 0.5, 0.15, r, 1e9, 0.2, 5e-7, 0.1 * r[0], 2.0 * np.pi, {}, name="mixer",
+                     packing="fcc", gap=0.00005, jitter=0.00001)
     sysm.meta["steps"] = 5000
     return sysm
