@@ -42,6 +42,8 @@ class OrcSys(C.Structure):
         ("n_mesh", C.c_int64), ("n_tri", C.c_int64), ("tri_mesh", C.c_void_p), ("tri_local", C.c_void_p),
         ("mesh_origin", C.c_void_p), ("mesh_vel", C.c_void_p), ("mesh_omega", C.c_void_p),
         ("mesh_mat", C.c_void_p),
+        ("owner_family", C.c_void_p), ("wall_family", C.c_void_p), ("mesh_family", C.c_void_p),
+        ("pair_off", C.c_void_p), ("fixed", C.c_void_p),
     ]
 
 
@@ -116,6 +118,11 @@ class Oracle:
             keep[name] = a
             return a.ctypes.data
 
+        def arr_u8(a):
+            a = np.ascontiguousarray(a, dtype=np.uint8)
+            keep[id(a)] = a
+            return a.ctypes.data
+
         s = OrcSys()
         s.n_owners = sysm.n_owners
         s.n_spheres = sysm.n_spheres
@@ -149,6 +156,11 @@ class Oracle:
         s.mesh_vel = arr("mesh_vel", np.float64)
         s.mesh_omega = arr("mesh_omega", np.float64)
         s.mesh_mat = arr("mesh_mat", np.int32)
+        # family tags: an empty array means the default (NULL)
+        for name in ("owner_family", "wall_family", "mesh_family", "pair_off", "fixed"):
+            a = np.asarray(getattr(sysm, "fam_" + name if name in ("pair_off", "fixed") else name,
+                                   np.zeros(0)), dtype=np.uint8)
+            setattr(s, name, arr_u8(a) if a.size else None)
         self._keep = keep
         self._s = s
         self.ps = C.addressof(s)

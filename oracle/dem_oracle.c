@@ -22,6 +22,9 @@
  *   - sphere contacts with the facets of rigid triangle meshes under
  *     prescribed motion (Sec. 2.4: a mesh is an owner, a facet a geometry),
  *     through the closest point of each facet to the sphere centre.
+ *   - family tags (Sec. 2.2.2): contacts between chosen pairs of families
+ *     are never listed; owners of fixed families keep their state (the
+ *     dormant elements of the active-box scheme, Sec. 6.4).
  *
  * Readings where the paper is silent (documented in the design notes):
  *   E*, G*: 1/E* = sum (1-nu^2)/E ; 1/G* = sum 2(2-nu)(1+nu)/E  (standard
@@ -65,7 +68,22 @@ typedef struct {
     const double *mesh_vel;      /* [3 M] constant velocity */
     const double *mesh_omega;    /* [3 M] constant angular velocity (world), about the origin */
     const int32_t *mesh_mat;     /* [M] */
+    /* family tags (each may be NULL: every family 0, nothing switched off) */
+    const uint8_t *owner_family; /* [No] */
+    const uint8_t *wall_family;  /* [W] */
+    const uint8_t *mesh_family;  /* [M] */
+    const uint8_t *pair_off;     /* [256 * 256] 1: no contact between families a and b */
+    const uint8_t *fixed;        /* [256] 1: owners of this family are not integrated */
 } orc_sys;
+
+static int fam_owner(const orc_sys *s, int64_t o) { return s->owner_family ? s->owner_family[o] : 0; }
+static int fam_wall(const orc_sys *s, int64_t w) { return s->wall_family ? s->wall_family[w] : 0; }
+static int fam_facet(const orc_sys *s, int64_t f)
+{
+    return s->mesh_family ? s->mesh_family[s->tri_mesh[f]] : 0;
+}
+/* Whether contacts between families a and b are resolved. */
+static int fam_on(const orc_sys *s, int a, int b) { return !(s->pair_off && s->pair_off[256 * a + b]); }
 
 typedef struct {
     int64_t cds;        /* contact detections run (margin > 0 or every-step) */
@@ -309,20 +327,24 @@ int64_t orc_detect_brute(const orc_sys *s, const double *xs, const double *wp, d
 {
     int64_t n = 0;
     for (int64_t i = 0; i < s->n_spheres; ++i) {
+        int fi = fam_owner(s, s->sph_owner[i]);
         for (int64_t j = i + 1; j < s->n_spheres; ++j) {
             if (s->sph_owner[i] == s->sph_owner[j]) continue;
+            if (!fam_on(s, fi, fam_owner(s, s->sph_owner[j]))) continue;
             if (pair_hit(xs + 3 * i, xs + 3 * j, s->sph_rad[i], s->sph_rad[j], m)) {
                 if (n < cap) keys[n] = ((uint64_t)i << 32) | (uint64_t)j;
                 ++n;
             }
         }
         for (int64_t w = 0; w < s->n_walls; ++w) {
+            if (!fam_on(s, fi, fam_wall(s, w))) continue;
             if (wall_hit(s, w, wp, xs + 3 * i, s->sph_rad[i], m)) {
                 if (n < cap) keys[n] = ((uint64_t)i << 32) | (uint64_t)(s->n_spheres + w);
                 ++n;
             }
         }
         for (int64_t f = 0; f < s->n_tri; ++f) {
+            if (!fam_on(s, fi, fam_facet(s, f))) continue;
             if (tri_hit(s, wp, f, xs + 3 * i, s->sph_rad[i], m)) {
                 if (n < cap) keys[n] = ((uint64_t)i << 32) | (uint64_t)(s->n_spheres + s->n_walls + f);
                 ++n;
@@ -371,6 +393,7 @@ int64_t orc_detect_binned(const orc_sys *s, const double *xs, const double *wp, 
     int64_t rowcap = 4096;
     for (int64_t i = 0; i < N; ++i) {
         int64_t nr = 0;
+        int fi = fam_owner(s, s->sph_owner[i]);
         for (int dz = -1; dz <= 1; ++dz)
             for (int dy = -1; dy <= 1; ++dy)
                 for (int dx = -1; dx <= 1; ++dx) {
@@ -383,6 +406,7 @@ int64_t orc_detect_binned(const orc_sys *s, const double *xs, const double *wp, 
                     for (int64_t p = lo; p < N && br[p].key == key; ++p) {
                         int64_t j = br[p].id;
                         if (j <= i || s->sph_owner[j] == s->sph_owner[i]) continue;
+                        if (!fam_on(s, fi, fam_owner(s, s->sph_owner[j]))) continue;
                         if (pair_hit(xs + 3 * i, xs + 3 * j, s->sph_rad[i], s->sph_rad[j], m)) {
                             if (nr == rowcap) { rowcap *= 2; row = realloc(row, sizeof(uint64_t) * (size_t)rowcap); }
                             row[nr++] = ((uint64_t)i << 32) | (uint64_t)j;
@@ -395,12 +419,14 @@ int64_t orc_detect_binned(const orc_sys *s, const double *xs, const double *wp, 
             ++n;
         }
         for (int64_t w = 0; w < s->n_walls; ++w) {
+            if (!fam_on(s, fi, fam_wall(s, w))) continue;
             if (wall_hit(s, w, wp, xs + 3 * i, s->sph_rad[i], m)) {
                 if (n < cap) keys[n] = ((uint64_t)i << 32) | (uint64_t)(N + w);
                 ++n;
             }
         }
         for (int64_t f = 0; f < s->n_tri; ++f) {
+            if (!fam_on(s, fi, fam_facet(s, f))) continue;
             if (tri_hit(s, wp, f, xs + 3 * i, s->sph_rad[i], m)) {
                 if (n < cap) keys[n] = ((uint64_t)i << 32) | (uint64_t)(N + s->n_walls + f);
                 ++n;
@@ -420,20 +446,24 @@ int64_t orc_detect_row(const orc_sys *s, const double *xs, const double *wp, dou
                        uint64_t *keys, int64_t cap)
 {
     int64_t n = 0;
+    int fi = fam_owner(s, s->sph_owner[i]);
     for (int64_t j = i + 1; j < s->n_spheres; ++j) {
         if (s->sph_owner[i] == s->sph_owner[j]) continue;
+        if (!fam_on(s, fi, fam_owner(s, s->sph_owner[j]))) continue;
         if (pair_hit(xs + 3 * i, xs + 3 * j, s->sph_rad[i], s->sph_rad[j], m)) {
             if (n < cap) keys[n] = ((uint64_t)i << 32) | (uint64_t)j;
             ++n;
         }
     }
     for (int64_t w = 0; w < s->n_walls; ++w) {
+        if (!fam_on(s, fi, fam_wall(s, w))) continue;
         if (wall_hit(s, w, wp, xs + 3 * i, s->sph_rad[i], m)) {
             if (n < cap) keys[n] = ((uint64_t)i << 32) | (uint64_t)(s->n_spheres + w);
             ++n;
         }
     }
     for (int64_t f = 0; f < s->n_tri; ++f) {
+        if (!fam_on(s, fi, fam_facet(s, f))) continue;
         if (tri_hit(s, wp, f, xs + 3 * i, s->sph_rad[i], m)) {
             if (n < cap) keys[n] = ((uint64_t)i << 32) | (uint64_t)(s->n_spheres + s->n_walls + f);
             ++n;
@@ -743,12 +773,14 @@ static void quat_mul(const double *a, const double *b, double *o)
 }
 
 /* Semi-implicit Euler: velocities first, then positions with the new
- * velocities; orientation by the exponential map of h * w_body. */
+ * velocities; orientation by the exponential map of h * w_body.  Owners of
+ * fixed families keep their state. */
 void orc_integrate(const orc_sys *s, double *X, double *q, double *V, double *Wb,
                    const double *Fo, const double *To)
 {
     const double h = s->h;
     for (int64_t o = 0; o < s->n_owners; ++o) {
+        if (s->fixed && s->fixed[fam_owner(s, o)]) continue;
         double m = s->own_mass[o];
         for (int k = 0; k < 3; ++k) V[3 * o + k] += h * (Fo[3 * o + k] / m + s->gravity[k]);
         double R[9], tb[3];

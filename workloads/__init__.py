@@ -92,6 +92,15 @@ class System:
     mesh_vel: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))                # f64 [M,3]
     mesh_omega: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))              # f64 [M,3]
     mesh_mat: np.ndarray = field(default_factory=lambda: np.zeros(0, dtype=np.int32))     # int32 [M]
+    # family tags (Sec. 2.2.2; empty = every family 0, nothing switched off):
+    # per owner / wall / mesh a family 0..255; fam_pair_off[256 a + b] = 1
+    # switches contacts between families a and b off; fam_fixed[a] = 1 keeps
+    # the owners of family a in place
+    owner_family: np.ndarray = field(default_factory=lambda: np.zeros(0, dtype=np.uint8))  # u8 [No]
+    wall_family: np.ndarray = field(default_factory=lambda: np.zeros(0, dtype=np.uint8))   # u8 [W]
+    mesh_family: np.ndarray = field(default_factory=lambda: np.zeros(0, dtype=np.uint8))   # u8 [M]
+    fam_pair_off: np.ndarray = field(default_factory=lambda: np.zeros(0, dtype=np.uint8))  # u8 [65536]
+    fam_fixed: np.ndarray = field(default_factory=lambda: np.zeros(0, dtype=np.uint8))     # u8 [256]
 
     @property
     def n_owners(self):
@@ -585,6 +594,40 @@ def _blade_clearance(X, radius, height, n_blades, hub, origin, phase):
     dz = np.maximum(np.maximum(-P[:, 2], P[:, 2] - height), 0.0)
     best = np.minimum(best, np.hypot(np.abs(rho - hub), dz))
     return best
+
+
+def set_families(sysm, owner_family=None, pair_off=(), fixed=(), wall_family=None, mesh_family=None):
+    """Family tags (the paper's Sec. 2.2.2): a family 0..255 per owner, wall
+    and mesh; `pair_off` lists family pairs (a, b) whose contacts are never
+    resolved (both orders); `fixed` lists families whose owners stay in
+    place (their velocities are zeroed here)."""
+    No = sysm.n_owners
+    sysm.owner_family = np.asarray(owner_family if owner_family is not None else np.zeros(No), dtype=np.uint8)
+    sysm.wall_family = np.asarray(wall_family if wall_family is not None else np.zeros(sysm.n_walls), dtype=np.uint8)
+    sysm.mesh_family = np.asarray(mesh_family if mesh_family is not None else np.zeros(sysm.n_mesh), dtype=np.uint8)
+    off = np.zeros((256, 256), dtype=np.uint8)
+    for a, b in pair_off:
+        off[a, b] = off[b, a] = 1
+    sysm.fam_pair_off = off.reshape(-1)
+    fx = np.zeros(256, dtype=np.uint8)
+    fx[list(fixed)] = 1
+    sysm.fam_fixed = fx
+    still = fx[sysm.owner_family] > 0
+    sysm.V = sysm.V.copy()
+    sysm.W = sysm.W.copy()
+    sysm.V[still] = 0.0
+    sysm.W[still] = 0.0
+    return sysm
+
+
+def active_box(sysm, lo, hi, active=0, dormant=1):
+    """The active-box scheme of the paper's rover test (Sec. 6.4): owners
+    whose centre lies outside the box [lo, hi] go to family `dormant`, which
+    is fixed and has its contacts with itself switched off, so only pairs
+    with an active owner are listed; owners inside go to family `active`."""
+    inside = np.all((sysm.X >= np.asarray(lo)) & (sysm.X <= np.asarray(hi)), axis=1)
+    fam = np.where(inside, active, dormant).astype(np.uint8)
+    return set_families(sysm, fam, pair_off=[(dormant, dormant)], fixed=[dormant])
 
 
 def mixer_bed(seed, n, R, Hb, r, E, cor, dt, margin, omega_z, mesh_res, vel=0.0, name="mixer", packing="cubic",
