@@ -225,6 +225,34 @@ dem_status dem_create(const dem_params *params, const dem_materials *mats,
  * value. */
 dem_status dem_set_meshes(dem_ctx *ctx, const dem_meshes *meshes);
 
+/* Family tags (Sec. 2.2.2) and the active-box scheme built on them
+ * (Sec. 6.4).  Every owner, wall and mesh carries a family 0..255.
+ * Contacts between the families of a switched-off pair are never listed
+ * (detection, judge).  Owners of fixed families are never integrated and
+ * keep zero velocity (this call and dem_set_state set their v and w to 0);
+ * they still touch the owners of other families, as static bodies.  The
+ * active box of the paper: the owners outside the box go to a fixed family
+ * whose pair with itself is switched off.  Arrays (each may be NULL: all 0):
+ * owner_family [n_owners], wall_family [n_walls], mesh_family [n_mesh],
+ * pair_off [256*256] (1 switches the pair (a, b) off; must be symmetric),
+ * fixed [256] (1 fixes a family). */
+typedef struct {
+    const uint8_t *owner_family;
+    const uint8_t *wall_family;
+    const uint8_t *mesh_family;
+    const uint8_t *pair_off;
+    const uint8_t *fixed;
+} dem_families;
+
+/* Installs family tags (after dem_bind; call again to move an active box).
+ * If a state is set, the fixed owners' velocities are zeroed and the
+ * current set is rebuilt at once with the run margin (the history of pairs
+ * still listed is carried over; a pending delayed detection is dropped).
+ * Synchronises the stream.
+ * Errors: DEM_ERR_STATE before dem_bind; DEM_ERR_ARG on an asymmetric or
+ * non-0/1 pair table; DEM_ERR_CAPACITY if the rebuilt set does not fit. */
+dem_status dem_set_families(dem_ctx *ctx, const dem_families *fam, dem_stream stream);
+
 /* Device bytes one binding needs for a contact array of contact_capacity
  * entries (per active-set buffer). */
 dem_status dem_workspace_size(const dem_ctx *ctx, int64_t contact_capacity, int64_t *bytes);

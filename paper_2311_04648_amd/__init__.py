@@ -58,6 +58,11 @@ class Meshes(C.Structure):
                 ("origin", C.c_void_p), ("vel", C.c_void_p), ("omega", C.c_void_p), ("mat", C.c_void_p)]
 
 
+class Families(C.Structure):
+    _fields_ = [("owner_family", C.c_void_p), ("wall_family", C.c_void_p), ("mesh_family", C.c_void_p),
+                ("pair_off", C.c_void_p), ("fixed", C.c_void_p)]
+
+
 class Bodies(C.Structure):
     _fields_ = [("n_owners", C.c_int64), ("n_spheres", C.c_int64), ("own_sph0", C.c_void_p),
                 ("own_tmpl", C.c_void_p), ("own_mass", C.c_void_p), ("own_moi", C.c_void_p),
@@ -92,6 +97,7 @@ def lib():
         sig = {
             "dem_create": [vp, vp, vp, vp, vp, vp],
             "dem_set_meshes": [vp, vp],
+            "dem_set_families": [vp, vp, vp],
             "dem_workspace_size": [vp, i64, vp],
             "dem_bind": [vp, vp, i64, i64],
             "dem_set_state": [vp, vp, vp, vp, vp, i64, vp],
@@ -221,6 +227,8 @@ class DemContext:
         self.Ns = int(s.sph_rad.shape[0])
         self.capacity = int(capacity or max(64, 12 * self.Ns))
         self.bind(self.capacity)
+        if np.asarray(getattr(s, "owner_family", np.zeros(0))).size:
+            self.set_families(s.owner_family, s.wall_family, s.mesh_family, s.fam_pair_off, s.fam_fixed)
 
     # ------------------------------------------------------------------ core
     def _check(self, st, required=None):
@@ -247,6 +255,27 @@ class DemContext:
             self.close()
         except Exception:
             pass
+
+    def set_families(self, owner_family=None, wall_family=None, mesh_family=None, pair_off=None, fixed=None,
+                     stream=None):
+        """Family tags: owner_family [No], wall_family [W], mesh_family [M],
+        pair_off [256*256] (1 = no contact between the two families), fixed
+        [256]; None = all 0.  With a state set, the set is rebuilt at once."""
+        keep = []
+
+        def u8(a, n):
+            if a is None or np.asarray(a).size == 0:
+                return None
+            a = np.ascontiguousarray(a, dtype=np.uint8).reshape(-1)
+            if a.size != n:
+                raise ValueError(f"family array of {a.size} entries, expected {n}")
+            keep.append(a)
+            return a.ctypes.data
+
+        s = self.sys
+        F = Families(u8(owner_family, self.No), u8(wall_family, int(s.wall_type.shape[0])),
+                     u8(mesh_family, int(getattr(s, "n_mesh", 0))), u8(pair_off, 65536), u8(fixed, 256))
+        self._check(lib().dem_set_families(self.ctx, C.byref(F), _stream_ptr(stream)))
 
     def set_state(self, X=None, q=None, V=None, W=None, step=0, stream=None):
         s = self.sys

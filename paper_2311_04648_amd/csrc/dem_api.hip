@@ -53,6 +53,11 @@ struct dem_ctx {
     hipEvent_t ev_pose[2] = {nullptr, nullptr};
     int64_t pose_lo = 0, pose_hi = 0;   // steps whose poses the ring holds (the last chunk)
     int pose_half = 0;
+    // family tags: per owner, per mesh (walls keep theirs in WallDev), the
+    // switched-off family pairs and the fixed families
+    std::vector<uint8_t> ofam, mesh_family, pairoff, famfixed;
+    bool has_pairoff = false, has_fixed = false, has_state = false;
+    uint8_t *d_ofam = nullptr, *d_pairoff = nullptr, *d_famfixed = nullptr;
     Grid grid{};
     Grid fgrid{};
     Origin org{};
@@ -208,6 +213,9 @@ void carve(Carver &c, dem_ctx *ctx, int64_t cap)
     ctx->d_tpos = c.take<float>(4 * std::max(ctx->ncomp, 1));
     ctx->d_walls = c.take<WallDev>(std::max(ctx->W, 1));
     ctx->d_tri = c.take<TriDev>(ctx->NF);
+    ctx->d_ofam = c.take<uint8_t>(No);
+    ctx->d_pairoff = c.take<uint8_t>(256 * 256);
+    ctx->d_famfixed = c.take<uint8_t>(256);
     ctx->d_pose_ring = c.take<MeshPose>(POSE_RING * ctx->NM);
     ctx->d_mat = c.take<MatPair>((int64_t)ctx->nmat * ctx->nmat);
     for (int b = 0; b < 2; ++b) {
@@ -265,7 +273,7 @@ void mesh_pose(const dem_ctx *ctx, int g, int64_t step, MeshPose &P)
         P.omega[k] = (float)w[k];
     }
     P.mat = ctx->mesh_mat[g];
-    P.pad = 0;
+    P.family = ctx->mesh_family.empty() ? 0 : ctx->mesh_family[g];
     const double wn = std::sqrt((w[0] * w[0] + w[1] * w[1]) + w[2] * w[2]);
     if (!(wn > 0.0)) {
         for (int k = 0; k < 9; ++k) P.R[k] = (k % 4 == 0) ? 1.0 : 0.0;
@@ -316,6 +324,9 @@ DetectArgs detect_args(const dem_ctx *ctx, double margin, int64_t step)
     a.tri = ctx->d_tri;
     a.n_tri = ctx->NF;
     a.poses = mesh_poses(ctx, step);
+    a.ofam = ctx->d_ofam;
+    a.pairoff = ctx->has_pairoff ? ctx->d_pairoff : nullptr;
+    a.famfixed = ctx->has_fixed ? ctx->d_famfixed : nullptr;
     return a;
 }
 
@@ -347,6 +358,7 @@ DynArgs dyn_args(const dem_ctx *ctx, int64_t step)
     a.tri = ctx->d_tri;
     a.n_tri = ctx->NF;
     a.poses = nullptr;
+    a.has_fixed = ctx->has_fixed ? 1 : 0;
     return a;
 }
 
@@ -400,7 +412,8 @@ void clear_set(dem_ctx *ctx, int b, hipStream_t s)
 {
     launch_fill_u32(ctx->acs[b].start, ctx->Ns + 1, 0u, s);
     launch_fill_u32(ctx->acs[b].bstart, ctx->Ns + 1, 0u, s);
-    launch_owner_flags(ctx->acs[b], ctx->has_clumps ? ctx->d_sph0 : nullptr, ctx->No, ctx->Ns, ctx->cap, s);
+    launch_owner_flags(ctx->acs[b], ctx->has_clumps ? ctx->d_sph0 : nullptr, ctx->No, ctx->Ns, ctx->cap, ctx->d_ofam,
+                       ctx->has_fixed ? ctx->d_famfixed : nullptr, s);
 }
 
 void drain_pair(dem_ctx *ctx, dem_ctx::TimedPair &p)
@@ -808,6 +821,13 @@ dem_status dem_bind(dem_ctx *ctx, void *device_workspace, int64_t bytes, int64_t
     HIPCHK(hipMemcpy(ctx->d_walls, ctx->walls.data(), sizeof(WallDev) * ctx->walls.size(), hipMemcpyHostToDevice));
     if (ctx->NF > 0)
         HIPCHK(hipMemcpy(ctx->d_tri, ctx->tri.data(), sizeof(TriDev) * ctx->NF, hipMemcpyHostToDevice));
+    if (ctx->ofam.size() != (size_t)ctx->No) ctx->ofam.assign(ctx->No, 0);
+    if (ctx->pairoff.size() != 65536) ctx->pairoff.assign(65536, 0);
+    if (ctx->famfixed.size() != 256) ctx->famfixed.assign(256, 0);
+    HIPCHK(hipMemcpy(ctx->d_ofam, ctx->ofam.data(), ctx->No, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_pairoff, ctx->pairoff.data(), 65536, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_famfixed, ctx->famfixed.data(), 256, hipMemcpyHostToDevice));
+    ctx->has_state = false;
     HIPCHK(hipMemcpy(ctx->d_mat, ctx->mat.data(), sizeof(MatPair) * ctx->mat.size(), hipMemcpyHostToDevice));
     DevCounters z{};
     HIPCHK(hipMemcpy(ctx->ctr, &z, sizeof(DevCounters), hipMemcpyHostToDevice));
@@ -859,9 +879,16 @@ dem_status dem_set_state(dem_ctx *ctx, const double *X, const double *q, const f
             for (int k = 0; k < 4; ++k) qd[4 * o + k] = qq[k];
         }
         r.mass = ctx->mass[o];
+        if (ctx->famfixed[ctx->ofam[o]]) {
+            // owners of fixed families keep zero velocity
+            for (int k = 0; k < 3; ++k) r.v[k] = r.w[k] = 0.0f;
+        }
         rec[o] = r;
     }
     HIPCHK(hipMemcpyAsync(ctx->rec, rec.data(), sizeof(OwnerRec) * ctx->No, hipMemcpyHostToDevice, s));
+    // the fused step does not rewrite the records of fixed owners: both
+    // buffers start equal
+    HIPCHK(hipMemcpyAsync(ctx->rec_alt, rec.data(), sizeof(OwnerRec) * ctx->No, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(ctx->q, qd.data(), sizeof(double) * 4 * ctx->No, hipMemcpyHostToDevice, s));
     // the fused step leaves the orientations of single-sphere systems alone,
     // so both buffers hold them
@@ -872,6 +899,7 @@ dem_status dem_set_state(dem_ctx *ctx, const double *X, const double *q, const f
     clear_set(ctx, 1, s);
     HIPCHK(hipStreamSynchronize(s));
     ctx->step = step;
+    ctx->has_state = true;
     ctx->cur = 0;
     ctx->sched_init = false;
     ctx->pending = false;
@@ -973,6 +1001,56 @@ dem_status dem_detect_contacts(dem_ctx *ctx, double margin, dem_stream stream, i
         }
         *n_contacts = ctx->h_ctr->n_contacts[target];
     }
+    return DEM_OK;
+}
+
+dem_status dem_set_families(dem_ctx *ctx, const dem_families *fam, dem_stream stream)
+{
+    if (!ctx) return DEM_ERR_ARG;
+    if (!ctx->bound) {
+        ctx->err = "dem_set_families before dem_bind";
+        return DEM_ERR_STATE;
+    }
+    std::vector<uint8_t> off(65536, 0), fx(256, 0), of(ctx->No, 0), mf(ctx->NM, 0);
+    if (fam && fam->pair_off) {
+        for (int a = 0; a < 256; ++a)
+            for (int b = 0; b < 256; ++b) {
+                const uint8_t v = fam->pair_off[256 * a + b];
+                ARGCHK(v <= 1, "pair_off entries must be 0 or 1");
+                ARGCHK(v == fam->pair_off[256 * b + a], "pair_off must be symmetric");
+                off[256 * a + b] = v;
+            }
+    }
+    if (fam && fam->fixed)
+        for (int a = 0; a < 256; ++a) fx[a] = fam->fixed[a] ? 1 : 0;
+    if (fam && fam->owner_family) std::copy(fam->owner_family, fam->owner_family + ctx->No, of.begin());
+    if (fam && fam->mesh_family) std::copy(fam->mesh_family, fam->mesh_family + ctx->NM, mf.begin());
+    for (int w = 0; w < ctx->W; ++w) ctx->walls[w].family = (fam && fam->wall_family) ? fam->wall_family[w] : 0;
+    ctx->pairoff.swap(off);
+    ctx->famfixed.swap(fx);
+    ctx->ofam.swap(of);
+    ctx->mesh_family.swap(mf);
+    ctx->has_pairoff = std::any_of(ctx->pairoff.begin(), ctx->pairoff.end(), [](uint8_t v) { return v != 0; });
+    ctx->has_fixed = false;
+    for (int64_t o = 0; o < ctx->No; ++o) ctx->has_fixed = ctx->has_fixed || ctx->famfixed[ctx->ofam[o]];
+    hipStream_t s = S(stream);
+    HIPCHK(hipMemcpyAsync(ctx->d_ofam, ctx->ofam.data(), ctx->No, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->d_pairoff, ctx->pairoff.data(), 65536, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->d_famfixed, ctx->famfixed.data(), 256, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->d_walls, ctx->walls.data(), sizeof(WallDev) * ctx->walls.size(), hipMemcpyHostToDevice,
+                          s));
+    if (!ctx->has_state) {
+        HIPCHK(hipStreamSynchronize(s));
+        return DEM_OK;
+    }
+    if (ctx->has_fixed)
+        launch_fix_owners(ctx->rec, ctx->rec_alt, ctx->q, ctx->q_alt, ctx->d_ofam, ctx->d_famfixed, ctx->No, s);
+    // the set in use was built under the old tags: rebuild it from the
+    // current state (history of the pairs still listed carried over)
+    int64_t n = 0;
+    dem_status st = dem_detect_contacts(ctx, ctx->P.margin, stream, &n);
+    if (st != DEM_OK) return st;
+    HIPCHK(hipStreamSynchronize(s));
     return DEM_OK;
 }
 
@@ -1109,7 +1187,8 @@ dem_status dem_set_contacts(dem_ctx *ctx, const uint64_t *keys, const float *his
         HIPCHK(hipMemcpyAsync(a.hw, h.data() + 3 * n, 4 * n, hipMemcpyHostToDevice, s));
     }
     launch_blists(a, ctx->Ns, ctx->cap, ctx->cdD.partials, s);
-    launch_owner_flags(a, ctx->has_clumps ? ctx->d_sph0 : nullptr, ctx->No, ctx->Ns, ctx->cap, s);
+    launch_owner_flags(a, ctx->has_clumps ? ctx->d_sph0 : nullptr, ctx->No, ctx->Ns, ctx->cap, ctx->d_ofam,
+                       ctx->has_fixed ? ctx->d_famfixed : nullptr, s);
     HIPCHK(hipGetLastError());
     uint32_t nn = (uint32_t)n, zero = 0;
     HIPCHK(hipMemcpyAsync(&ctx->ctr->n_contacts[b], &nn, 4, hipMemcpyHostToDevice, s));

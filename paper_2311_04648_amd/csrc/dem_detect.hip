@@ -150,6 +150,13 @@ __device__ inline bool wall_hit(const WallDev &w, const double *p, double x, dou
     return d2 < T * T;
 }
 
+// Whether contacts between the families of owners (or walls, meshes) fa and
+// fb are listed.
+__device__ inline bool fam_on(const DetectArgs &a, uint32_t fa, uint32_t fb)
+{
+    return !(a.pairoff && a.pairoff[256u * fa + fb]);
+}
+
 // Binary search of j in the ascending row [lo, hi) of a set.
 __device__ inline bool row_contains(const uint32_t *row_j, uint32_t lo, uint32_t hi, uint32_t j)
 {
@@ -197,6 +204,8 @@ __global__ void __launch_bounds__(TPB) k_facet_prepare(DetectArgs a, FacetDev *f
     d.ncy = c1[1] - c0[1] + 1;
     d.cz0 = c0[2];
     d.ncz = c1[2] - c0[2] + 1;
+    d.family = P.family;
+    d.pad[0] = d.pad[1] = d.pad[2] = 0;
     fac[f] = d;
     frow[f] = (uint32_t)d.ncy * (uint32_t)d.ncz;
 }
@@ -295,6 +304,7 @@ __global__ void __launch_bounds__(TPB) k_facet_walk(DetectArgs a, const FacetDev
             if (v >= tot) continue;
             const Cand c = cand[sk + (v - ek)];
             if (!facet_hit(fac[fk], c.x, c.y, c.z, (double)c.r, m)) continue;
+            if (a.pairoff && !fam_on(a, a.ofam[a.sph[c.id].owner], (uint32_t)fac[fk].family)) continue;
             const uint32_t jp = jbase + fk;
             if (MODE == FMODE_STAGE) {
                 const uint32_t slot = atomicAdd(&count[c.id], 1u);
@@ -350,7 +360,9 @@ __global__ void __launch_bounds__(TPB) k_detect(DetectArgs a, const uint32_t *ke
                 if (cj.id <= i) continue;
                 if (!sphere_pair_hit(xi, yi, zi, ri, cj, m)) continue;
                 if (own_i == 0xffffffffu) own_i = a.sph[i].owner;
-                if (a.sph[cj.id].owner == own_i) continue;
+                const uint32_t own_j = a.sph[cj.id].owner;
+                if (own_j == own_i) continue;
+                if (a.pairoff && !fam_on(a, a.ofam[own_i], a.ofam[own_j])) continue;
                 if (MODE == MODE_WRITE) {
                     if (can_write) out_j[base + n] = cj.id;
                 } else if (MODE == MODE_JUDGE) {
@@ -382,6 +394,7 @@ __global__ void __launch_bounds__(TPB) k_detect(DetectArgs a, const uint32_t *ke
         double pw[3];
         wall_point(wd, a.step, a.h, pw);
         if (!wall_hit(wd, pw, xi, yi, zi, ri, m)) continue;
+        if (a.pairoff && !fam_on(a, a.ofam[a.sph[i].owner], (uint32_t)wd.family)) continue;
         uint32_t jp = (uint32_t)a.n_spheres + (uint32_t)w;
         if (MODE == MODE_WRITE) {
             if (can_write) out_j[base + n] = jp;
@@ -482,7 +495,9 @@ __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32
             const Cand cj = cand[qb[u]];
             if (!sphere_pair_hit(xi, yi, zi, ri, cj, m)) continue;
             if (own_i == 0xffffffffu) own_i = a.sph[i].owner;
-            if (a.sph[cj.id].owner == own_i) continue;
+            const uint32_t own_j = a.sph[cj.id].owner;
+            if (own_j == own_i) continue;
+            if (a.pairoff && !fam_on(a, a.ofam[own_i], a.ofam[own_j])) continue;
             const uint32_t lo = i < cj.id ? i : cj.id, hi = i < cj.id ? cj.id : i;
             const uint32_t slot = atomicAdd(&count[lo], 1u);
             if (slot < (uint32_t)STAGE_K) stage[(size_t)lo * STAGE_K + slot] = hi;
@@ -494,6 +509,7 @@ __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32
         double pw[3];
         wall_point(wd, a.step, a.h, pw);
         if (!wall_hit(wd, pw, xi, yi, zi, ri, m)) continue;
+        if (a.pairoff && !fam_on(a, a.ofam[a.sph[i].owner], (uint32_t)wd.family)) continue;
         const uint32_t slot = atomicAdd(&count[i], 1u);
         if (slot < (uint32_t)STAGE_K) stage[(size_t)i * STAGE_K + slot] = (uint32_t)a.n_spheres + (uint32_t)w;
     }
@@ -577,7 +593,9 @@ __global__ void __launch_bounds__(TPB) k_compact(DetectArgs a, const Cand *cand_
                 const Cand cj = cand[qq];
                 if (cj.id <= (uint32_t)i) continue;
                 if (!sphere_pair_hit(xi, yi, zi, ri, cj, m)) continue;
-                if (a.sph[cj.id].owner == own_i) continue;
+                const uint32_t own_j = a.sph[cj.id].owner;
+                if (own_j == own_i) continue;
+                if (a.pairoff && !fam_on(a, a.ofam[own_i], a.ofam[own_j])) continue;
                 if (k < n) row[k] = cj.id;
                 ++k;
             }
@@ -588,6 +606,7 @@ __global__ void __launch_bounds__(TPB) k_compact(DetectArgs a, const Cand *cand_
         double pw[3];
         wall_point(wd, a.step, a.h, pw);
         if (!wall_hit(wd, pw, xi, yi, zi, ri, m)) continue;
+        if (a.pairoff && !fam_on(a, a.ofam[own_i], (uint32_t)wd.family)) continue;
         if (k < n) row[k] = (uint32_t)ns + (uint32_t)w;
         ++k;
     }
@@ -595,6 +614,7 @@ __global__ void __launch_bounds__(TPB) k_compact(DetectArgs a, const Cand *cand_
     // are rare; the facet walk found the same pairs)
     for (int32_t f = 0; f < a.n_tri; ++f) {
         if (!facet_hit(fac[f], xi, yi, zi, ri, m)) continue;
+        if (a.pairoff && !fam_on(a, a.ofam[own_i], (uint32_t)fac[f].family)) continue;
         if (k < n) row[k] = (uint32_t)ns + (uint32_t)a.n_walls + (uint32_t)f;
         ++k;
     }
@@ -681,17 +701,19 @@ __global__ void __launch_bounds__(TPB) k_blist_sort(const uint32_t *start, const
 // B lists are one range each); an overflowed set flags nothing.
 __global__ void __launch_bounds__(TPB) k_owner_flags(const uint32_t *start, const uint32_t *bstart,
                                                      const uint32_t *own_sph0, int64_t no, int64_t ns,
-                                                     int64_t cap, uint8_t *flag)
+                                                     int64_t cap, const uint8_t *ofam, const uint8_t *fixed,
+                                                     uint8_t *flag)
 {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= no) return;
+    const uint8_t fx = (fixed && fixed[ofam[o]]) ? 2 : 0;
     if ((int64_t)start[ns] > cap) {
-        flag[o] = 0;
+        flag[o] = fx;
         return;
     }
     const uint32_t s0 = own_sph0 ? own_sph0[o] : (uint32_t)o;
     const uint32_t s1 = own_sph0 ? own_sph0[o + 1] : (uint32_t)o + 1u;
-    flag[o] = (start[s0] != start[s1] || bstart[s0] != bstart[s1]) ? 1 : 0;
+    flag[o] = (uint8_t)(((start[s0] != start[s1] || bstart[s0] != bstart[s1]) ? 1 : 0) | fx);
 }
 
 __global__ void __launch_bounds__(TPB) k_remap(const uint32_t *os, const uint32_t *oj, const float *ohx,
@@ -803,10 +825,11 @@ void launch_detect_front(const DetectArgs &a, CdWork &w, AcsBuf &out, hipStream_
     launch_bin_front(a, w, s, out.bcur, n + 1, w.count, n + 1);
 }
 
-void launch_owner_flags(AcsBuf &b, const uint32_t *own_sph0, int64_t no, int64_t ns, int64_t cap, hipStream_t s)
+void launch_owner_flags(AcsBuf &b, const uint32_t *own_sph0, int64_t no, int64_t ns, int64_t cap,
+                        const uint8_t *ofam, const uint8_t *fixed, hipStream_t s)
 {
     hipLaunchKernelGGL(k_owner_flags, dim3(nblocks(no)), dim3(TPB), 0, s, (const uint32_t *)b.start,
-                       (const uint32_t *)b.bstart, own_sph0, no, ns, cap, b.oany);
+                       (const uint32_t *)b.bstart, own_sph0, no, ns, cap, ofam, fixed, b.oany);
 }
 
 void launch_detect(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap, DevCounters *ctr, int buf,
@@ -841,7 +864,7 @@ void launch_detect_back(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap
                        (const FacetDev *)w.fac);
     hipLaunchKernelGGL(k_blist_sort, dim3(nblocks(n)), dim3(TPB), 0, s, out.start, out.bstart, n, cap, out.bidx,
                        out.bsrc);
-    launch_owner_flags(out, a.own_sph0, a.n_owners, n, cap, s);
+    launch_owner_flags(out, a.own_sph0, a.n_owners, n, cap, a.ofam, a.famfixed, s);
 }
 
 void launch_judge(const DetectArgs &a, CdWork &w, const AcsBuf &cur, int64_t cap, DevCounters *ctr,

@@ -449,7 +449,8 @@ __global__ void __launch_bounds__(TPB) k_fold_integrate(DynArgs a, const uint32_
                                                         const uint32_t *bidx, const float *aF,
                                                         const float *aT, const float *bF,
                                                         const float *bT, int64_t cap, float *Fo,
-                                                        float *To, int integrate, DevCounters *ctr)
+                                                        float *To, int integrate, const uint8_t *oany,
+                                                        DevCounters *ctr)
 {
     if (stopped(ctr, a.step)) return;
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -498,8 +499,8 @@ __global__ void __launch_bounds__(TPB) k_fold_integrate(DynArgs a, const uint32_
             To[o] = T.x;
             To[No + o] = T.y;
             To[2 * No + o] = T.z;
-        } else {
-            // orientation updated in place
+        } else if (!(a.has_fixed && (oany[o] & 2u))) {
+            // orientation updated in place (owners of fixed families keep their state)
             const bool rot = !SINGLES && tmpl >= 0;
             double *qp = a.q + 4 * (size_t)o;
             const double4 qv = rot ? *reinterpret_cast<const double4 *>(qp) : make_double4(1.0, 0.0, 0.0, 0.0);
@@ -557,7 +558,11 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
         ctr->contact_steps += ctr->n_contacts[a.cur];
     }
     float v2 = 0.0f;
-    if (valid) {
+    // owners of fixed families (the flag's bit 1) keep their state, which
+    // both state buffers hold: without contacts there is nothing to do; with
+    // contacts only their A rows are evaluated, for the history
+    const uint8_t fl = (valid && a.has_fixed) ? oany[o] : (uint8_t)0;
+    if (valid && (fl & 3u) != 2u) {
         // every per-owner load is issued here, none waits for another: the
         // record, the inertia, the orientation (clump systems), and whether
         // the owner has any contact in the set in use (a flag per owner
@@ -576,13 +581,14 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
             tmpl = ax.tmpl;
             qv = *reinterpret_cast<const double4 *>(a.q + 4 * (size_t)o);
         }
-        const bool any = oany[o] != 0;
+        const bool any = (oany[o] & 1u) != 0;
+        const bool fixed = (fl & 2u) != 0;
         float3 F = f3(0.f, 0.f, 0.f), T = f3(0.f, 0.f, 0.f);
         const uint32_t s0 = SINGLES ? (uint32_t)o : (any ? a.own_sph0[o] : 0u);
         const uint32_t s1 = SINGLES ? (uint32_t)o + 1u : (any ? a.own_sph0[o + 1] : 0u);
         for (uint32_t s = s0; any && s < s1; ++s) {
             const uint32_t c0 = start[s], na = start[s + 1] - c0;
-            const uint32_t b0 = bstart[s], nall = na + (bstart[s + 1] - b0);
+            const uint32_t b0 = bstart[s], nall = fixed ? na : na + (bstart[s + 1] - b0);
             // single spheres: the sphere's own record and kinematics come
             // from the owner record already loaded, once, as geometry A of
             // its row and geometry B of its B list (for clumps, whose
@@ -656,12 +662,14 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
                 }
             }
         }
-        const bool rotating = !SINGLES && tmpl >= 0;
-        double *qo = q_out + 4 * (size_t)o;
-        // (a single sphere's orientation never changes and both buffers hold
-        // it, so nothing is copied for it)
-        v2 = advance(a, r, inv, rotating, F, T, qv, qo, ctr);
-        store_rec(rec_out + o, r);
+        if (!fixed) {
+            const bool rotating = !SINGLES && tmpl >= 0;
+            double *qo = q_out + 4 * (size_t)o;
+            // (a single sphere's orientation never changes and both buffers
+            // hold it, so nothing is copied for it)
+            v2 = advance(a, r, inv, rotating, F, T, qv, qo, ctr);
+            store_rec(rec_out + o, r);
+        }
     }
     block_max_v2(v2, a.blkmax + lb);
 }
@@ -700,6 +708,29 @@ __global__ void __launch_bounds__(64) k_adaptive_margin(DevCounters *ctr, double
 }
 
 __global__ void __launch_bounds__(64) k_noop() {}
+
+// Owners of fixed families: zero velocity and angular velocity, the same
+// record (and orientation) in both state buffers.
+__global__ void __launch_bounds__(256) k_fix_owners(OwnerRec *rec, OwnerRec *rec_alt, const double *q, double *q_alt,
+                                                    const uint8_t *ofam, const uint8_t *fixed, int64_t n)
+{
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= n || !fixed[ofam[o]]) return;
+    OwnerRec r = load_rec(rec + o);
+    for (int k = 0; k < 3; ++k) {
+        r.v[k] = 0.0f;
+        r.w[k] = 0.0f;
+    }
+    store_rec(rec + o, r);
+    store_rec(rec_alt + o, r);
+    *reinterpret_cast<double4 *>(q_alt + 4 * (size_t)o) = *reinterpret_cast<const double4 *>(q + 4 * (size_t)o);
+}
+
+void launch_fix_owners(OwnerRec *rec, OwnerRec *rec_alt, const double *q, double *q_alt, const uint8_t *ofam,
+                       const uint8_t *fixed, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fix_owners, dim3(nblocks(n)), dim3(256), 0, s, rec, rec_alt, q, q_alt, ofam, fixed, n);
+}
 
 void launch_noop(hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
@@ -745,5 +776,5 @@ void launch_fold_integrate(const DynArgs &a, const AcsBuf &cur, StepBufs &sb, De
     hipExtLaunchKernelGGL(kern, dim3(nblocks(a.n_owners)), dim3(TPB), 0, s, ev0, ev1, 0, a,
                           (const uint32_t *)cur.start, (const uint32_t *)cur.bstart, (const uint32_t *)cur.bidx,
                           (const float *)sb.aF, (const float *)sb.aT, (const float *)sb.bF, (const float *)sb.bT,
-                          sb.cap, sb.Fo, sb.To, integrate, ctr);
+                          sb.cap, sb.Fo, sb.To, integrate, (const uint8_t *)cur.oany, ctr);
 }

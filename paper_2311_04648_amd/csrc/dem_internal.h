@@ -55,6 +55,7 @@ struct __align__(16) WallDev {
     double omega[3];
     int32_t type;
     int32_t mat;
+    int32_t family;
 };
 
 // A facet of a rigid mesh: vertices in the mesh frame, mesh index.
@@ -71,7 +72,7 @@ struct MeshPose {
     float vel[3];      // velocity of the reference point
     float omega[3];    // angular velocity (world)
     int32_t mat;
-    int32_t pad;
+    int32_t family;
 };
 
 constexpr int MAX_MESHES = 4;
@@ -86,6 +87,7 @@ struct __align__(16) FacetDev {
     double v[9];
     double lo[3], hi[3];
     int32_t cx0, ncx, cy0, ncy, cz0, ncz;
+    int32_t family, pad[3];
 };
 
 // Candidate record in bin-sorted order: exact FP64 centre, radius, sphere id.
@@ -173,6 +175,9 @@ struct DetectArgs {
     const TriDev *tri;      // [n_tri] facets of the meshes
     int32_t n_tri;
     MeshPoses poses;        // mesh poses at `step`
+    const uint8_t *ofam;    // [No] family of each owner
+    const uint8_t *pairoff; // [256*256] 1: contacts between the two families are not listed (null: none)
+    const uint8_t *famfixed;// [256] 1: owners of the family are fixed
 };
 
 struct CdWork {
@@ -201,7 +206,8 @@ struct AcsBuf {
     uint32_t *bidx;    // [cap] contact index of each B-list entry
     uint32_t *bsrc;    // [cap] the A sphere of that contact
     uint32_t *bcur;    // [Ns+1] scratch cursor
-    uint8_t *oany;     // [No] 1 if any sphere of the owner has a row or B-list entry in this set
+    uint8_t *oany;     // [No] bit 0: any sphere of the owner has a row or B-list entry in this set;
+                       // bit 1: the owner is in a fixed family
 };
 
 inline void swap_hist(AcsBuf &b)
@@ -230,7 +236,7 @@ void launch_blists(AcsBuf &b, int64_t n_spheres, int64_t cap, uint32_t *partials
 // the per-owner contact flags of a set (AcsBuf::oany) from its rows and B
 // lists (an overflowed set flags nothing)
 void launch_owner_flags(AcsBuf &b, const uint32_t *own_sph0, int64_t n_owners, int64_t n_spheres, int64_t cap,
-                        hipStream_t s);
+                        const uint8_t *ofam, const uint8_t *fixed, hipStream_t s);
 void launch_remap(const AcsBuf &oldb, AcsBuf &newb, int64_t n_spheres, DevCounters *ctr, int newbuf,
                   int rolling, hipStream_t s);
 
@@ -259,6 +265,7 @@ struct DynArgs {
     const TriDev *tri;      // [n_tri] facets of the meshes
     int32_t n_tri;
     const MeshPose *poses;  // [MAX_MESHES] mesh poses at `step` (device memory; null without meshes)
+    int32_t has_fixed;      // some owner is in a fixed family (its flag in AcsBuf::oany, bit 1)
 };
 
 struct StepBufs {
@@ -283,6 +290,9 @@ void launch_noop(hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 // max |v|^2 of the last integration into ctr->maxv2[0]
 // adaptive schedule: margin of the next detection from the top speed
 // (after launch_reduce_max), into ctr->margin
+// owners of fixed families: v = w = 0 in `rec`, and both state buffers equal
+void launch_fix_owners(OwnerRec *rec, OwnerRec *rec_alt, const double *q, double *q_alt, const uint8_t *ofam,
+                       const uint8_t *fixed, int64_t n_owners, hipStream_t s);
 void launch_adaptive_margin(DevCounters *ctr, double t, double gmag, double cap, double vfloor, hipStream_t s);
 void launch_reduce_max(const DynArgs &a, DevCounters *ctr, hipStream_t s);
 

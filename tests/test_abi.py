@@ -132,6 +132,9 @@ def test_calls_before_bind_report_state_error():
     stats = dem.StepStats()
     assert dem.lib().dem_step(ctx, 1, None, None, C.byref(stats)) == dem.DEM_ERR_STATE
     assert b"before dem_bind" in dem.lib().dem_last_error(ctx)
+    F = dem.Families(None, None, None, None, None)
+    assert dem.lib().dem_set_families(ctx, C.byref(F), None) == dem.DEM_ERR_STATE
+    assert b"before dem_bind" in dem.lib().dem_last_error(ctx)
     dem.lib().dem_destroy(ctx)
 
 
