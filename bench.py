@@ -42,7 +42,8 @@ def parse():
     ap.add_argument("--n", type=int, default=1_000_000, help="spheres of the config-1 workload")
     ap.add_argument("--workload", default="config1",
                     help="config1 (headline) | config2 | config3 | config4: other sizes for the design notes | "
-                         "mixer: the bladed-mixer bed with a 2880-facet impeller")
+                         "mixer: the bladed-mixer bed with a 2880-facet impeller | "
+                         "activebox: the config-4 bed (quarter size) with an active box around the cylinder")
     ap.add_argument("--modes", default="fixed,every,learned,analytic,adaptive",
                     help="schedules: fixed (k steps), every (every step), learned (MLP interval), "
                          "analytic (the learned schedule's fallback bound alone, no network), "
@@ -61,7 +62,8 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, rolling=False, n_clump=None, n_tri=0):
+def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, rolling=False, n_clump=None, n_tri=0,
+                      n_dormant=0, n_dormant_clump=0):
     """Bytes one launch of a stage must move at minimum (unique data);
     `active` = spheres that appear in at least one contact:
     k_force: per sphere its row offset (4); per active sphere its record
@@ -74,7 +76,8 @@ def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, roll
       its record, row and B-list offsets and its owner's sphere range (28);
       per contact the partner id (4), the history read + written (24, 32
       with contact age) and the B-list entry with its source sphere (8);
-      with meshes, each facet's vertices and mesh index (80).
+      with meshes, each facet's vertices and mesh index (80).  An owner of a
+      fixed family without contacts reads its flag only (1).
     k_fold_integrate: per owner the record read + write (96) and the inverse
       inertia: one isotropic value (4) when every owner is a single sphere,
       else three values and the template (16) plus the sphere range (4); per
@@ -93,7 +96,9 @@ def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, roll
         return Ns * 4 + active * 88 + C * 52
     if stage == "k_step_fused":
         nc = (No if n_clump is None else n_clump) if clumps else 0
-        return No * (113 if clumps else 101) + nc * 64 + active * 28 + C * (44 if rolling else 36) + n_tri * 80
+        nc -= n_dormant_clump if clumps else 0
+        return ((No - n_dormant) * (113 if clumps else 101) + n_dormant + nc * 64 + active * 28
+                + C * (44 if rolling else 36) + n_tri * 80)
     if stage == "k_fold_integrate":
         return No * (116 if clumps else 100) + Ns * 8 + active * 24 + C * 28
     if stage == "detect":
@@ -199,6 +204,8 @@ def main():
         sysm = W.config4(seed=0)
     elif args.workload == "mixer":
         sysm = W.mixer(seed=0)
+    elif args.workload == "activebox":
+        sysm = W.activebox(seed=0)
     else:
         raise SystemExit(f"unknown workload {args.workload}")
     print(f"# workload generated: {sysm.n_spheres} spheres in {time.perf_counter() - t_gen:.1f}s",
@@ -263,9 +270,13 @@ def main():
     passes = 1   # one-pass bin sort (the LSD radix option would take (sort_bits + 7) // 8)
     n_clump = int(np.sum(np.asarray(sysm.own_tmpl) >= 0))
     n_tri = int(getattr(sysm, "n_tri", 0))
+    fam = np.asarray(getattr(sysm, "owner_family", np.zeros(0)))
+    dormant = (np.asarray(sysm.fam_fixed)[fam] > 0) if fam.size else np.zeros(No, dtype=bool)
+    n_dormant = int(dormant.sum())
+    n_dormant_clump = int(np.sum(dormant & (np.asarray(sysm.own_tmpl) >= 0)))
     algo = algorithmic_bytes(stages[dom], Ns, No, C, r["active"], r["info"]["nbins"], passes,
                              clumps=Ns != No, rolling=bool(np.any(np.asarray(sysm.mat_crr) > 0)),
-                             n_clump=n_clump, n_tri=n_tri)
+                             n_clump=n_clump, n_tri=n_tri, n_dormant=n_dormant, n_dormant_clump=n_dormant_clump)
     achieved = algo / (avg_ms * 1e-3) / 1e9
     traffic = load_traffic(stages[dom], args.workload)
     roofline = {"bound": "hbm", "kernel": stages[dom], "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
@@ -281,7 +292,7 @@ def main():
                 "note": "detection chain on the second stream, concurrent with the dynamics stream"}
 
     cpu = None
-    if not args.no_cpu and Ns <= 10_000_000 and n_tri == 0:
+    if not args.no_cpu and Ns <= 10_000_000 and n_tri == 0 and n_dormant == 0:
         import oracle
         o = oracle.Oracle(sysm)
         ost = o.state()
@@ -320,7 +331,8 @@ def main():
         Cm, act = s2["mean_contacts"], rr["active"]
         if args.dyn_path == 0:
             dyn_b = algorithmic_bytes("k_step_fused", Ns, No, Cm, act, 0, passes, clumps=Ns != No, rolling=rolling,
-                                      n_clump=n_clump, n_tri=n_tri)
+                                      n_clump=n_clump, n_tri=n_tri, n_dormant=n_dormant,
+                                      n_dormant_clump=n_dormant_clump)
         else:
             dyn_b = (algorithmic_bytes("k_force", Ns, No, Cm, act, 0, passes)
                      + algorithmic_bytes("k_fold_integrate", Ns, No, Cm, act, 0, passes, clumps=Ns != No))
@@ -362,7 +374,12 @@ def main():
                    (f"{Ns} spheres r~U(3,3.5) mm in a bed around a {n_tri}-facet bladed impeller (radius 0.49 m) "
                     f"turning at 2 pi rad/s in a 1x1 m box chamber, dt 5e-7 s, margin 0.3 mm, delayed CD every "
                     f"{args.k} steps on a second HIP stream (adoption latency {args.lam})")
-                   if args.workload == "mixer" else f"{args.workload}: {Ns} spheres, {No} owners",
+                   if args.workload == "mixer" else
+                   (f"{Ns} spheres in {No} owners (45 % single r = 2 mm, the rest tri-sphere clumps) on a 7 mm "
+                    f"lattice in a 1 x 1 m bed, an analytic cylinder rolling on top at 0.2 m/s, dt 5e-6 s, margin "
+                    f"0.2 mm; active box of 0.5 x 0.6 x 0.1 m around the cylinder ({No - n_dormant} active "
+                    f"owners), the rest dormant; delayed CD every {args.k} steps on a second HIP stream")
+                   if args.workload == "activebox" else f"{args.workload}: {Ns} spheres, {No} owners",
                    "n_spheres": Ns, "n_owners": No, "schedule": head, "k": args.k, "lambda": args.lam,
                    "dynamics": "one fused kernel per step" if args.dyn_path == 0 else "force + fold kernels"},
         "modes": modes_out,
@@ -371,6 +388,26 @@ def main():
         "cd_chain": cd_chain,
         "cpu_baseline": cpu,
     }
+    if n_dormant:
+        act_sph = int(np.sum(~dormant[np.asarray(sysm.sph_owner)]))
+        out["config"]["active_owners"] = No - n_dormant
+        out["config"]["active_spheres"] = act_sph
+        out["active_sphere_steps_per_s"] = round(act_sph * args.steps / r["seconds"], 1)
+        out["value_note"] = "nominal: all spheres counted, the dormant ones included (as the paper counts its rover run)"
+        # the same bed and schedule with every owner active, for comparison
+        import copy
+        full = copy.copy(sysm)
+        full.owner_family = np.zeros(0, dtype=np.uint8)
+        full.fam_pair_off = np.zeros(0, dtype=np.uint8)
+        full.fam_fixed = np.zeros(0, dtype=np.uint8)
+        full.V = np.zeros_like(sysm.V)
+        full.W = np.zeros_like(sysm.W)
+        rf = run_mode(dem, torch, full, head, args, mlp=mlp)
+        out["full_domain"] = {"value": round(Ns * args.steps / rf["seconds"], 1),
+                              "ms_per_step": round(1e3 * rf["seconds"] / args.steps, 5),
+                              "mean_contacts": round(rf["stats"]["mean_contacts"], 1)}
+        print(f"# full domain ({head}): {Ns * args.steps / rf['seconds']:.4g} sphere-steps/s", file=sys.stderr,
+              flush=True)
     if n_tri:
         out["config"]["n_facets"] = n_tri
         # the paper's own mixer figure, for context only (2 A100s, its own

@@ -521,11 +521,12 @@ __global__ void __launch_bounds__(TPB) k_fold_integrate(DynArgs a, const uint32_
 // writes (rec_out, q_out, second history): no thread reads what another
 // writes.  When the step is stopped (capacity or divergence) the state and
 // history are copied unchanged.  SINGLES: every owner is one sphere; FACETS:
-// the set may hold sphere-facet contacts.  Systems with clumps or meshes get
+// the set may hold sphere-facet contacts; FIXED: some owner is in a fixed
+// family.  Systems with clumps or meshes get
 // 3 waves per SIMD: the clump rotation and the FP64 closest point would
 // otherwise spill registers to scratch inside the contact loop, which costs
 // more than the lost occupancy.
-template <bool SINGLES, bool FACETS>
+template <bool SINGLES, bool FACETS, bool FIXED>
 __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fused(DynArgs a, OwnerRec *rec_out, double *q_out,
                                                     const uint32_t *start, const uint32_t *jarr,
                                                     const uint32_t *bstart, const uint32_t *bidx,
@@ -561,7 +562,7 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
     // owners of fixed families (the flag's bit 1) keep their state, which
     // both state buffers hold: without contacts there is nothing to do; with
     // contacts only their A rows are evaluated, for the history
-    const uint8_t fl = (valid && a.has_fixed) ? oany[o] : (uint8_t)0;
+    const uint8_t fl = (FIXED && valid) ? oany[o] : (uint8_t)0;
     if (valid && (fl & 3u) != 2u) {
         // every per-owner load is issued here, none waits for another: the
         // record, the inertia, the orientation (clump systems), and whether
@@ -582,7 +583,7 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
             qv = *reinterpret_cast<const double4 *>(a.q + 4 * (size_t)o);
         }
         const bool any = (oany[o] & 1u) != 0;
-        const bool fixed = (fl & 2u) != 0;
+        const bool fixed = FIXED && (fl & 2u) != 0;
         float3 F = f3(0.f, 0.f, 0.f), T = f3(0.f, 0.f, 0.f);
         const uint32_t s0 = SINGLES ? (uint32_t)o : (any ? a.own_sph0[o] : 0u);
         const uint32_t s1 = SINGLES ? (uint32_t)o + 1u : (any ? a.own_sph0[o + 1] : 0u);
@@ -759,8 +760,12 @@ void launch_force(const DynArgs &a, AcsBuf &cur, StepBufs &sb, DevCounters *ctr,
 void launch_step_fused(const DynArgs &a, OwnerRec *rec_out, double *q_out, const AcsBuf &cur, int64_t cap,
                        DevCounters *ctr, hipStream_t s)
 {
-    auto kern = a.n_tri > 0 ? (a.has_clumps ? k_step_fused<false, true> : k_step_fused<true, true>)
-                            : (a.has_clumps ? k_step_fused<false, false> : k_step_fused<true, false>);
+    auto kern = a.has_fixed
+                    ? (a.n_tri > 0 ? (a.has_clumps ? k_step_fused<false, true, true> : k_step_fused<true, true, true>)
+                                   : (a.has_clumps ? k_step_fused<false, false, true> : k_step_fused<true, false, true>))
+                    : (a.n_tri > 0 ? (a.has_clumps ? k_step_fused<false, true, false> : k_step_fused<true, true, false>)
+                                   : (a.has_clumps ? k_step_fused<false, false, false>
+                                                   : k_step_fused<true, false, false>));
     hipLaunchKernelGGL(kern, dim3(nblocks(a.n_owners)), dim3(TPB), 0, s, a, rec_out, q_out,
                        (const uint32_t *)cur.start, (const uint32_t *)cur.j, (const uint32_t *)cur.bstart,
                        (const uint32_t *)cur.bidx, (const uint32_t *)cur.bsrc, (const uint8_t *)cur.oany,

@@ -434,6 +434,22 @@ def config4(seed=0, n_owners=32_000_000, frac_single=18.0 / 32.0):
                     meta=dict(steps=5000, seed=seed))
 
 
+def activebox(seed=0, n_owners=4_000_000):
+    """The active-box scheme of the paper's rover test (Sec. 6.4) on the
+    config-4 bed at a quarter of its size (about 7.5 M spheres in 4 M owners,
+    1 m wide): the owners within 0.25 m along x, 0.3 m along y and 0.1 m in
+    depth of the rolling cylinder's start are active, the rest dormant
+    (fixed, no contacts among themselves)."""
+    s = config4(seed=seed, n_owners=n_owners)
+    cyl = s.wall_geom[-1]
+    top = s.X[:, 2].max()
+    lo = np.array([cyl[0] - 0.25, -0.3, top - 0.1])
+    hi = np.array([cyl[0] + 0.25, 0.3, top + 1.0])
+    s = active_box(s, lo, hi)
+    s.name = "activebox"
+    return s
+
+
 def _qid(n):
     q = np.zeros((n, 4))
     q[:, 0] = 1.0
