@@ -55,9 +55,13 @@ struct dem_ctx {
     int pose_half = 0;
     // family tags: per owner, per mesh (walls keep theirs in WallDev), the
     // switched-off family pairs and the fixed families
-    std::vector<uint8_t> ofam, mesh_family, pairoff, famfixed;
-    bool has_pairoff = false, has_fixed = false, has_state = false;
-    uint8_t *d_ofam = nullptr, *d_pairoff = nullptr, *d_famfixed = nullptr;
+    std::vector<uint8_t> ofam, mesh_family, pairoff, famfixed, famdormant;
+    bool has_pairoff = false, has_fixed = false, has_state = false, has_dormant = false;
+    uint8_t *d_ofam = nullptr, *d_pairoff = nullptr, *d_famfixed = nullptr, *d_famdormant = nullptr;
+    // static index of the dormant spheres (rebuilt when the tags or the state are set)
+    uint32_t *d_dcell_start = nullptr;
+    Cand *d_dcand = nullptr;
+    float4 *d_dcandf = nullptr;
     Grid grid{};
     Grid fgrid{};
     Origin org{};
@@ -216,6 +220,10 @@ void carve(Carver &c, dem_ctx *ctx, int64_t cap)
     ctx->d_ofam = c.take<uint8_t>(No);
     ctx->d_pairoff = c.take<uint8_t>(256 * 256);
     ctx->d_famfixed = c.take<uint8_t>(256);
+    ctx->d_famdormant = c.take<uint8_t>(256);
+    ctx->d_dcell_start = c.take<uint32_t>((int64_t)ctx->grid.nbins + 1);
+    ctx->d_dcand = c.take<Cand>(Ns);
+    ctx->d_dcandf = c.take<float4>(Ns);
     ctx->d_pose_ring = c.take<MeshPose>(POSE_RING * ctx->NM);
     ctx->d_mat = c.take<MatPair>((int64_t)ctx->nmat * ctx->nmat);
     for (int b = 0; b < 2; ++b) {
@@ -327,6 +335,10 @@ DetectArgs detect_args(const dem_ctx *ctx, double margin, int64_t step)
     a.ofam = ctx->d_ofam;
     a.pairoff = ctx->has_pairoff ? ctx->d_pairoff : nullptr;
     a.famfixed = ctx->has_fixed ? ctx->d_famfixed : nullptr;
+    a.famdormant = ctx->has_dormant ? ctx->d_famdormant : nullptr;
+    a.dcell_start = ctx->d_dcell_start;
+    a.dcand = ctx->d_dcand;
+    a.dcandf = ctx->d_dcandf;
     return a;
 }
 
@@ -359,6 +371,7 @@ DynArgs dyn_args(const dem_ctx *ctx, int64_t step)
     a.n_tri = ctx->NF;
     a.poses = nullptr;
     a.has_fixed = ctx->has_fixed ? 1 : 0;
+    a.two_kernel = ctx->P.dyn_path == 1 ? 1 : 0;
     return a;
 }
 
@@ -673,7 +686,7 @@ dem_status dem_create(const dem_params *params, const dem_materials *mats, const
     ctx->grid.nbins = (uint32_t)nb;
     ctx->grid.inv_b = 1.0 / b;
     int bits = 1;
-    while (bits < 32 && (1ull << bits) < nb) ++bits;
+    while (bits < 32 && (1ull << bits) <= nb) ++bits;   // keys 0 .. nb (nb: a sphere left out of the bins)
     ctx->sort_bits = bits;
     // feature cells for the learned interval: cubes of 4 bins
     ctx->fgrid = ctx->grid;
@@ -827,6 +840,8 @@ dem_status dem_bind(dem_ctx *ctx, void *device_workspace, int64_t bytes, int64_t
     HIPCHK(hipMemcpy(ctx->d_ofam, ctx->ofam.data(), ctx->No, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_pairoff, ctx->pairoff.data(), 65536, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_famfixed, ctx->famfixed.data(), 256, hipMemcpyHostToDevice));
+    if (ctx->famdormant.size() != 256) ctx->famdormant.assign(256, 0);
+    HIPCHK(hipMemcpy(ctx->d_famdormant, ctx->famdormant.data(), 256, hipMemcpyHostToDevice));
     ctx->has_state = false;
     HIPCHK(hipMemcpy(ctx->d_mat, ctx->mat.data(), sizeof(MatPair) * ctx->mat.size(), hipMemcpyHostToDevice));
     DevCounters z{};
@@ -842,6 +857,8 @@ dem_status dem_bind(dem_ctx *ctx, void *device_workspace, int64_t bytes, int64_t
     ctx->bound = true;
     return DEM_OK;
 }
+
+static void rebuild_dormant_index(dem_ctx *ctx, hipStream_t s);
 
 dem_status dem_set_state(dem_ctx *ctx, const double *X, const double *q, const float *v, const float *w,
                          int64_t step, dem_stream stream)
@@ -897,8 +914,9 @@ dem_status dem_set_state(dem_ctx *ctx, const double *X, const double *q, const f
     HIPCHK(hipMemcpyAsync(ctx->ctr, &z, sizeof(DevCounters), hipMemcpyHostToDevice, s));
     clear_set(ctx, 0, s);
     clear_set(ctx, 1, s);
-    HIPCHK(hipStreamSynchronize(s));
     ctx->step = step;
+    rebuild_dormant_index(ctx, s);
+    HIPCHK(hipStreamSynchronize(s));
     ctx->has_state = true;
     ctx->cur = 0;
     ctx->sched_init = false;
@@ -943,6 +961,7 @@ dem_status dem_bin(dem_ctx *ctx, dem_stream stream, uint32_t *sorted_keys, uint3
     }
     hipStream_t s = S(stream);
     DetectArgs a = detect_args(ctx, ctx->P.margin, ctx->step);
+    a.famdormant = nullptr;   // every sphere binned
     launch_bin(a, ctx->cdD, s);
     HIPCHK(hipGetLastError());
     if (sorted_keys || sorted_ids) {
@@ -1004,6 +1023,15 @@ dem_status dem_detect_contacts(dem_ctx *ctx, double margin, dem_stream stream, i
     return DEM_OK;
 }
 
+// The static index of the dormant spheres from the current state (their
+// records do not change while the tags stay).
+static void rebuild_dormant_index(dem_ctx *ctx, hipStream_t s)
+{
+    if (!ctx->has_dormant) return;
+    DetectArgs a = detect_args(ctx, ctx->P.margin, ctx->step);
+    launch_dormant_index(a, ctx->cdD, ctx->d_dcell_start, ctx->d_dcand, ctx->d_dcandf, s);
+}
+
 dem_status dem_set_families(dem_ctx *ctx, const dem_families *fam, dem_stream stream)
 {
     if (!ctx) return DEM_ERR_ARG;
@@ -1032,11 +1060,33 @@ dem_status dem_set_families(dem_ctx *ctx, const dem_families *fam, dem_stream st
     ctx->mesh_family.swap(mf);
     ctx->has_pairoff = std::any_of(ctx->pairoff.begin(), ctx->pairoff.end(), [](uint8_t v) { return v != 0; });
     ctx->has_fixed = false;
-    for (int64_t o = 0; o < ctx->No; ++o) ctx->has_fixed = ctx->has_fixed || ctx->famfixed[ctx->ofam[o]];
+    std::vector<uint8_t> used(256, 0);
+    for (int64_t o = 0; o < ctx->No; ++o) {
+        ctx->has_fixed = ctx->has_fixed || ctx->famfixed[ctx->ofam[o]];
+        used[ctx->ofam[o]] = 1;
+    }
+    // dormant families: fixed, and switched off with every fixed family in
+    // use and with every wall and mesh family -- their spheres can only touch
+    // owners of the other families, which find them in the dormant index
+    std::vector<uint8_t> other(256, 0);
+    for (int w = 0; w < ctx->W; ++w) other[ctx->walls[w].family] = 1;
+    for (uint8_t f : ctx->mesh_family) other[f] = 1;
+    ctx->famdormant.assign(256, 0);
+    ctx->has_dormant = false;
+    for (int f = 0; f < 256; ++f) {
+        if (!ctx->famfixed[f]) continue;
+        bool d = true;
+        for (int g = 0; g < 256 && d; ++g) {
+            if ((used[g] && ctx->famfixed[g]) || other[g]) d = ctx->pairoff[256 * f + g] != 0;
+        }
+        ctx->famdormant[f] = d ? 1 : 0;
+        ctx->has_dormant = ctx->has_dormant || (d && used[f]);
+    }
     hipStream_t s = S(stream);
     HIPCHK(hipMemcpyAsync(ctx->d_ofam, ctx->ofam.data(), ctx->No, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(ctx->d_pairoff, ctx->pairoff.data(), 65536, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(ctx->d_famfixed, ctx->famfixed.data(), 256, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->d_famdormant, ctx->famdormant.data(), 256, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(ctx->d_walls, ctx->walls.data(), sizeof(WallDev) * ctx->walls.size(), hipMemcpyHostToDevice,
                           s));
     if (!ctx->has_state) {
@@ -1045,6 +1095,7 @@ dem_status dem_set_families(dem_ctx *ctx, const dem_families *fam, dem_stream st
     }
     if (ctx->has_fixed)
         launch_fix_owners(ctx->rec, ctx->rec_alt, ctx->q, ctx->q_alt, ctx->d_ofam, ctx->d_famfixed, ctx->No, s);
+    rebuild_dormant_index(ctx, s);
     // the set in use was built under the old tags: rebuild it from the
     // current state (history of the pairs still listed carried over)
     int64_t n = 0;

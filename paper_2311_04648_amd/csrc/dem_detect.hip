@@ -58,17 +58,24 @@ __global__ void __launch_bounds__(TPB) k_cd_prepare(DetectArgs a, uint32_t *keys
     const bool active = i < a.n_spheres;
     if (!active) i = a.n_spheres - 1;   // the tail lanes take part in the wave's run claim only
     SphRec s = load_sph(a.sph + i);
-    OwnerRec r = load_rec(a.rec + s.owner);
-    double x[3];
-    sphere_centre(r, s, a.q, a.tpos, a.org, x);
-    int cx = bin_coord(x[0], a.grid.lo[0], a.grid.inv_b, a.grid.nx);
-    int cy = bin_coord(x[1], a.grid.lo[1], a.grid.inv_b, a.grid.ny);
-    int cz = bin_coord(x[2], a.grid.lo[2], a.grid.inv_b, a.grid.nz);
-    uint32_t key = ((uint32_t)cz * (uint32_t)a.grid.ny + (uint32_t)cy) * (uint32_t)a.grid.nx + (uint32_t)cx;
-    wave_run_claim(cell_count, key, active);
+    // a dormant sphere is not binned (it is found through the dormant
+    // index): key nbins, no count, no slot in the sorted arrays
+    const bool dorm = a.famdormant && a.famdormant[a.ofam[s.owner]];
+    uint32_t key = a.grid.nbins;
+    double x[3] = {0.0, 0.0, 0.0};
+    if (!dorm) {
+        OwnerRec r = load_rec(a.rec + s.owner);
+        sphere_centre(r, s, a.q, a.tpos, a.org, x);
+        int cx = bin_coord(x[0], a.grid.lo[0], a.grid.inv_b, a.grid.nx);
+        int cy = bin_coord(x[1], a.grid.lo[1], a.grid.inv_b, a.grid.ny);
+        int cz = bin_coord(x[2], a.grid.lo[2], a.grid.inv_b, a.grid.nz);
+        key = ((uint32_t)cz * (uint32_t)a.grid.ny + (uint32_t)cy) * (uint32_t)a.grid.nx + (uint32_t)cx;
+    }
+    wave_run_claim(cell_count, key, active && !dorm);
     if (!active) return;
     keys[i] = key;
     if (vals) vals[i] = (uint32_t)i;   // ids to sort (the one-pass sort writes its own)
+    if (dorm) return;
     Cand c;
     c.x = x[0];
     c.y = x[1];
@@ -84,12 +91,12 @@ __global__ void __launch_bounds__(TPB) k_cd_prepare(DetectArgs a, uint32_t *keys
 // cursor (one atomic per run of equal keys in a wave), and when asked each
 // bin then orders its few ids ascending, so the result is identical to a
 // stable sort.
-__global__ void __launch_bounds__(TPB) k_bucket_scatter(const uint32_t *keys_in, int64_t n, uint32_t *cursor,
-                                                        uint32_t *keys_out, uint32_t *vals_out)
+__global__ void __launch_bounds__(TPB) k_bucket_scatter(const uint32_t *keys_in, int64_t n, uint32_t nbins,
+                                                        uint32_t *cursor, uint32_t *keys_out, uint32_t *vals_out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = i < n;
-    const uint32_t k = keys_in[active ? i : n - 1];
+    const uint32_t k = keys_in[i < n ? i : n - 1];
+    const bool active = i < n && k < nbins;   // (key nbins: a dormant sphere, not binned)
     const uint32_t pos = wave_run_claim(cursor, k, active);
     if (!active) return;
     keys_out[pos] = k;
@@ -115,10 +122,11 @@ __global__ void __launch_bounds__(TPB) k_bucket_order(const uint32_t *cell_start
 // Candidate records in bin order, and their 16-byte FP32 copies for the
 // prefilter of the detection walk.
 __global__ void __launch_bounds__(TPB) k_cand_gather(const uint32_t *vals, const Cand *cand_tmp,
-                                                     Cand *cand, float4 *candf, Grid g, int64_t n)
+                                                     Cand *cand, float4 *candf, Grid g, int64_t n,
+                                                     const uint32_t *cell_start)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
+    if (p >= n || p >= (int64_t)cell_start[g.nbins]) return;   // (dormant spheres sit after the binned ones)
     const Cand c = cand_tmp[vals[p]];
     cand[p] = c;
     candf[p] = make_float4((float)(c.x - g.lo[0]), (float)(c.y - g.lo[1]), (float)(c.z - g.lo[2]), c.r);
@@ -422,12 +430,51 @@ __global__ void __launch_bounds__(TPB) k_detect(DetectArgs a, const uint32_t *ke
 // five contiguous ranges, so each thread has several loads in flight.
 constexpr int DETECT_BATCH = 4;
 
+// The FP32 prefilter of the detection walk (bound derived in
+// k_detect_stage): true when candidate cj is farther from ci than the pair
+// threshold by more than the rounding can account for.
+__device__ inline bool prefilter_far(const float4 &ci, const float4 &cj, float Mi, float twom)
+{
+    const float dxf = ci.x - cj.x, dyf = ci.y - cj.y, dzf = ci.z - cj.z;
+    const float Mj = fmaxf(fabsf(cj.x), fmaxf(fabsf(cj.y), fabsf(cj.z)));
+    const float T32 = (ci.w + cj.w) + twom;
+    const float tf = T32 + ((4.77e-7f * (Mi + Mj) + 9.54e-7f * T32) + 1e-12f);
+    return (dxf * dxf + dyf * dyf) + dzf * dzf > tf * tf;
+}
+
+// Pairs of a binned sphere (bin `key`, FP32 copy cif, exact centre x, family
+// fam_i) with the dormant spheres of the 27 bins around it, from the static
+// dormant index; each pair that passes the exact predicate and is not
+// switched off goes to f(dormant id).  A dormant sphere has no thread, so
+// all its pairs with binned spheres are found here, whichever id is lower.
+template <typename F>
+__device__ inline void dormant_walk(const DetectArgs &a, uint32_t key, const float4 &cif, double xi, double yi,
+                                    double zi, double ri, double m, uint32_t fam_i, F &&f)
+{
+    const float twom = (float)(2.0 * m);
+    const float Mi = fmaxf(fabsf(cif.x), fmaxf(fabsf(cif.y), fabsf(cif.z)));
+    const uint32_t nx = (uint32_t)a.grid.nx, nxy = (uint32_t)a.grid.nx * (uint32_t)a.grid.ny;
+    for (int dz = -1; dz <= 1; ++dz) {
+        for (int dy = -1; dy <= 1; ++dy) {
+            const uint32_t row = key + (uint32_t)((int)nxy * dz) + (uint32_t)((int)nx * dy);
+            const uint32_t q1 = a.dcell_start[row + 2];
+            for (uint32_t qq = a.dcell_start[row - 1]; qq < q1; ++qq) {
+                if (prefilter_far(cif, a.dcandf[qq], Mi, twom)) continue;
+                const Cand cj = a.dcand[qq];
+                if (!sphere_pair_hit(xi, yi, zi, ri, cj, m)) continue;
+                if (!fam_on(a, fam_i, a.ofam[a.sph[cj.id].owner])) continue;
+                f(cj.id);
+            }
+        }
+    }
+}
+
 __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32_t *keys, const Cand *cand,
                                                       const float4 *candf, const uint32_t *cell_start,
                                                       uint32_t *count, uint32_t *stage, uint32_t *bcount)
 {
     const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (p >= a.n_spheres) return;
+    if (p >= a.n_spheres || p >= (int64_t)cell_start[a.grid.nbins]) return;   // (dormant spheres are not binned)
     const Cand ci = cand[p];
     const float4 cif = candf[p];
     const uint32_t i = ci.id;
@@ -504,6 +551,15 @@ __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32
             if (bcount) atomicAdd(&bcount[hi], 1u);
         }
     }
+    if (a.famdormant) {
+        if (own_i == 0xffffffffu) own_i = a.sph[i].owner;
+        dormant_walk(a, key, cif, xi, yi, zi, ri, m, a.ofam[own_i], [&](uint32_t j) {
+            const uint32_t lo = i < j ? i : j, hi = i < j ? j : i;
+            const uint32_t slot = atomicAdd(&count[lo], 1u);
+            if (slot < (uint32_t)STAGE_K) stage[(size_t)lo * STAGE_K + slot] = hi;
+            if (bcount) atomicAdd(&bcount[hi], 1u);
+        });
+    }
     for (int w = 0; w < a.n_walls; ++w) {
         WallDev wd = a.walls[w];
         double pw[3];
@@ -574,15 +630,32 @@ __global__ void __launch_bounds__(TPB) k_compact(DetectArgs a, const Cand *cand_
         }
         return;
     }
-    const Cand ci = cand_tmp[i];
-    const double xi = ci.x, yi = ci.y, zi = ci.z, ri = (double)ci.r;
+    // the centre of sphere i: its candidate record, or for a dormant sphere
+    // (not binned) its owner record, which does not change
+    const uint32_t own_i = a.sph[i].owner;
+    const bool dorm_i = a.famdormant && a.famdormant[a.ofam[own_i]];
+    double xi, yi, zi, ri;
+    if (dorm_i) {
+        const SphRec si = load_sph(a.sph + i);
+        double x[3];
+        sphere_centre(load_rec(a.rec + own_i), si, a.q, a.tpos, a.org, x);
+        xi = x[0];
+        yi = x[1];
+        zi = x[2];
+        ri = (double)si.rad;
+    } else {
+        const Cand ci = cand_tmp[i];
+        xi = ci.x;
+        yi = ci.y;
+        zi = ci.z;
+        ri = (double)ci.r;
+    }
     const double m = a.margin_dev ? *a.margin_dev : a.margin;
     const int cx = bin_coord(xi, a.grid.lo[0], a.grid.inv_b, a.grid.nx);
     const int cy = bin_coord(yi, a.grid.lo[1], a.grid.inv_b, a.grid.ny);
     const int cz = bin_coord(zi, a.grid.lo[2], a.grid.inv_b, a.grid.nz);
     const uint32_t key = ((uint32_t)cz * (uint32_t)a.grid.ny + (uint32_t)cy) * (uint32_t)a.grid.nx + (uint32_t)cx;
     const uint32_t nx = (uint32_t)a.grid.nx, nxy = (uint32_t)a.grid.nx * (uint32_t)a.grid.ny;
-    const uint32_t own_i = a.sph[i].owner;
     uint32_t *row = out_j + r0;
     uint32_t k = 0;
     for (int dz = -1; dz <= 1; ++dz) {
@@ -600,6 +673,15 @@ __global__ void __launch_bounds__(TPB) k_compact(DetectArgs a, const Cand *cand_
                 ++k;
             }
         }
+    }
+    if (a.famdormant && !dorm_i) {
+        const float4 cif = make_float4((float)(xi - a.grid.lo[0]), (float)(yi - a.grid.lo[1]),
+                                       (float)(zi - a.grid.lo[2]), (float)ri);
+        dormant_walk(a, key, cif, xi, yi, zi, ri, m, a.ofam[own_i], [&](uint32_t j) {
+            if (j <= (uint32_t)i) return;
+            if (k < n) row[k] = j;
+            ++k;
+        });
     }
     for (int w = 0; w < a.n_walls; ++w) {
         WallDev wd = a.walls[w];
@@ -746,7 +828,66 @@ __global__ void __launch_bounds__(TPB) k_remap(const uint32_t *os, const uint32_
     }
 }
 
+// Static index of the dormant spheres: bin counts ...
+__global__ void __launch_bounds__(TPB) k_dorm_count(DetectArgs a, uint32_t *dkey, uint32_t *dcount)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = i < a.n_spheres;
+    if (!in) i = a.n_spheres - 1;
+    const SphRec s = load_sph(a.sph + i);
+    const bool dorm = in && a.famdormant[a.ofam[s.owner]];
+    uint32_t key = 0;
+    if (dorm) {
+        double x[3];
+        sphere_centre(load_rec(a.rec + s.owner), s, a.q, a.tpos, a.org, x);
+        const int cx = bin_coord(x[0], a.grid.lo[0], a.grid.inv_b, a.grid.nx);
+        const int cy = bin_coord(x[1], a.grid.lo[1], a.grid.inv_b, a.grid.ny);
+        const int cz = bin_coord(x[2], a.grid.lo[2], a.grid.inv_b, a.grid.nz);
+        key = ((uint32_t)cz * (uint32_t)a.grid.ny + (uint32_t)cy) * (uint32_t)a.grid.nx + (uint32_t)cx;
+        dkey[i] = key;
+    }
+    wave_run_claim(dcount, key, dorm);
+}
+
+// ... then the candidates, placed by a cursor per bin (order inside a bin
+// is free: the pairs found do not depend on it).
+__global__ void __launch_bounds__(TPB) k_dorm_fill(DetectArgs a, const uint32_t *dkey, uint32_t *dcursor, Cand *dcand,
+                                                   float4 *dcandf)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = i < a.n_spheres;
+    if (!in) i = a.n_spheres - 1;
+    const SphRec s = load_sph(a.sph + i);
+    const bool dorm = in && a.famdormant[a.ofam[s.owner]];
+    const uint32_t key = dorm ? dkey[i] : 0u;
+    const uint32_t pos = wave_run_claim(dcursor, key, dorm);
+    if (!dorm) return;
+    double x[3];
+    sphere_centre(load_rec(a.rec + s.owner), s, a.q, a.tpos, a.org, x);
+    Cand c;
+    c.x = x[0];
+    c.y = x[1];
+    c.z = x[2];
+    c.r = s.rad;
+    c.id = (uint32_t)i;
+    dcand[pos] = c;
+    dcandf[pos] = make_float4((float)(c.x - a.grid.lo[0]), (float)(c.y - a.grid.lo[1]), (float)(c.z - a.grid.lo[2]),
+                              c.r);
+}
+
 }  // namespace
+
+void launch_dormant_index(const DetectArgs &a, CdWork &w, uint32_t *dcell_start, Cand *dcand, float4 *dcandf,
+                          hipStream_t s)
+{
+    const int64_t n = a.n_spheres, nb = (int64_t)a.grid.nbins;
+    launch_zero3(w.cell_count, nb + 1, nullptr, 0, nullptr, 0, s);
+    hipLaunchKernelGGL(k_dorm_count, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cell_count);
+    // bin ranges, with a copy as the fill cursor
+    scan_exclusive_u32(w.cell_count, dcell_start, nb, w.partials, s, w.cell_count);
+    hipLaunchKernelGGL(k_dorm_fill, dim3(nblocks(n)), dim3(TPB), 0, s, a, (const uint32_t *)w.keys, w.cell_count,
+                       dcand, dcandf);
+}
 
 // First part of binning: zeroes the bin counts (and up to two further
 // arrays of the caller in the same launch), then sphere centres, bin keys,
@@ -756,7 +897,7 @@ void launch_bin_front(const DetectArgs &a, CdWork &w, hipStream_t s, uint32_t *z
                       int64_t n2)
 {
     const int64_t n = a.n_spheres;
-    launch_zero3(w.cell_count, (int64_t)a.grid.nbins, z1, n1, z2, n2, s);
+    launch_zero3(w.cell_count, (int64_t)a.grid.nbins + 1, z1, n1, z2, n2, s);
     hipLaunchKernelGGL(k_cd_prepare, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys,
                        w.sort_mode == 0 ? (uint32_t *)nullptr : w.vals, w.cand_tmp, w.cell_count);
 }
@@ -772,8 +913,8 @@ void launch_bin_back(const DetectArgs &a, CdWork &w, hipStream_t s, bool order_b
     if (w.sort_mode == 0) {
         // cell ranges, with a copy of the offsets as the per-bin cursor
         scan_exclusive_u32(w.cell_count, w.cell_start, nb, w.partials, s, w.cell_count);
-        hipLaunchKernelGGL(k_bucket_scatter, dim3(nblocks(n)), dim3(TPB), 0, s, w.keys, n, w.cell_count,
-                           w.keys_alt, w.vals_alt);
+        hipLaunchKernelGGL(k_bucket_scatter, dim3(nblocks(n)), dim3(TPB), 0, s, w.keys, n, a.grid.nbins,
+                           w.cell_count, w.keys_alt, w.vals_alt);
         if (order_bins)
             hipLaunchKernelGGL(k_bucket_order, dim3(nblocks(nb)), dim3(TPB), 0, s, w.cell_start, nb, w.vals_alt);
         uint32_t *t = w.keys; w.keys = w.keys_alt; w.keys_alt = t;
@@ -785,7 +926,7 @@ void launch_bin_back(const DetectArgs &a, CdWork &w, hipStream_t s, bool order_b
     // candidate records in bin order (random 32-byte reads, coalesced writes;
     // moving the records in the scatter instead costs more: random writes)
     hipLaunchKernelGGL(k_cand_gather, dim3(nblocks(n)), dim3(TPB), 0, s, w.vals, w.cand_tmp, w.cand, w.candf,
-                       a.grid, n);
+                       a.grid, n, (const uint32_t *)w.cell_start);
 }
 
 void launch_bin(const DetectArgs &a, CdWork &w, hipStream_t s, uint32_t *z1, int64_t n1, uint32_t *z2,
@@ -867,9 +1008,12 @@ void launch_detect_back(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap
     launch_owner_flags(out, a.own_sph0, a.n_owners, n, cap, a.ofam, a.famfixed, s);
 }
 
-void launch_judge(const DetectArgs &a, CdWork &w, const AcsBuf &cur, int64_t cap, DevCounters *ctr,
+void launch_judge(const DetectArgs &a_in, CdWork &w, const AcsBuf &cur, int64_t cap, DevCounters *ctr,
                   hipStream_t s)
 {
+    // every sphere binned: the judge's full-stencil walk finds each pair from its lower id
+    DetectArgs a = a_in;
+    a.famdormant = nullptr;
     int64_t n = a.n_spheres;
     launch_bin(a, w, s, nullptr, 0, nullptr, 0, false);
     hipLaunchKernelGGL(k_detect<MODE_JUDGE>, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,
@@ -893,9 +1037,11 @@ void launch_remap(const AcsBuf &o, AcsBuf &nb, int64_t ns, DevCounters *ctr, int
                        nb.start, nb.j, nb.hx, nb.hy, nb.hz, nb.hw, ns, ctr, newbuf, rolling);
 }
 
-void launch_detect_plain(const DetectArgs &a, CdWork &w, uint32_t *start, uint32_t *j, int64_t cap,
+void launch_detect_plain(const DetectArgs &a_in, CdWork &w, uint32_t *start, uint32_t *j, int64_t cap,
                          DevCounters *ctr, hipStream_t s)
 {
+    DetectArgs a = a_in;
+    a.famdormant = nullptr;
     int64_t n = a.n_spheres;
     launch_bin(a, w, s, w.count, n + 1, nullptr, 0, false);
     hipLaunchKernelGGL(k_detect_stage, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,
@@ -916,10 +1062,12 @@ void launch_detect_plain(const DetectArgs &a, CdWork &w, uint32_t *start, uint32
                        (uint32_t *)nullptr, (const FacetDev *)w.fac);
 }
 
-void launch_label_judge(const DetectArgs &a, CdWork &w, const uint32_t *lab_start, const uint32_t *lab_j,
+void launch_label_judge(const DetectArgs &a_in, CdWork &w, const uint32_t *lab_start, const uint32_t *lab_j,
                         int64_t cap, const uint32_t *cellmap, uint32_t *first_miss, uint32_t tval,
                         hipStream_t s)
 {
+    DetectArgs a = a_in;
+    a.famdormant = nullptr;
     int64_t n = a.n_spheres;
     launch_bin(a, w, s, nullptr, 0, nullptr, 0, false);
     hipLaunchKernelGGL(k_detect<MODE_LABEL>, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,

@@ -87,15 +87,16 @@ __device__ inline uint32_t xcd_block(uint32_t b, uint32_t n)
     return x * per + (x < rem ? x : rem) + k;
 }
 
-// Claims one slot of counter[key] per active lane (active lanes form a
-// prefix of the wave): lanes of a run of equal keys in consecutive lanes
-// share one atomic, issued by the run's first lane with the run's length;
-// returns each lane's slot (the counter's old value plus its rank in the
-// run).  Spheres numbered in space-filling order put runs of neighbours in
-// one bin, whose atomics would otherwise serialise on one address.
-__device__ inline uint32_t wave_run_claim(uint32_t *counter, uint32_t key, bool active)
+// Claims one slot of counter[key] per active lane (key < 2^32 - 1): lanes
+// of a run of equal keys in consecutive active lanes share one atomic,
+// issued by the run's first lane with the run's length; returns each
+// lane's slot (the counter's old value plus its rank in the run).  Spheres
+// numbered in space-filling order put runs of neighbours in one bin, whose
+// atomics would otherwise serialise on one address.
+__device__ inline uint32_t wave_run_claim(uint32_t *counter, uint32_t key_in, bool active)
 {
     const int lane = (int)(threadIdx.x & 63u);
+    const uint32_t key = active ? key_in : 0xffffffffu;   // an inactive lane ends a run
     const uint32_t prev = __shfl_up(key, 1, 64);
     const bool head = active && (lane == 0 || prev != key);
     const unsigned long long heads = __ballot(head), act = __ballot(active);

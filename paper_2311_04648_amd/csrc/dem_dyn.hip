@@ -34,6 +34,16 @@ inline unsigned nblocks(int64_t n, int t = TPB)
     return (unsigned)(g < 1 ? 1 : g);
 }
 
+// Blocks of the fused step (one per 256 owners; with fixed families at most
+// FIXED_BLOCKS, each thread taking several owners).  The per-block speed
+// maxima of the last step are in blkmax[0 .. step_blocks).
+constexpr unsigned FIXED_BLOCKS = 2048;
+inline unsigned step_blocks(const DynArgs &a)
+{
+    const unsigned b = nblocks(a.n_owners);
+    return a.has_fixed && !a.two_kernel && b > FIXED_BLOCKS ? FIXED_BLOCKS : b;
+}
+
 struct OwnerKin {
     double X[3];     // owner centre (exact)
     float3 v;        // velocity
@@ -526,44 +536,19 @@ __global__ void __launch_bounds__(TPB) k_fold_integrate(DynArgs a, const uint32_
 // 3 waves per SIMD: the clump rotation and the FP64 closest point would
 // otherwise spill registers to scratch inside the contact loop, which costs
 // more than the lost occupancy.
+// The step of one owner (see k_step_fused); returns its |v|^2.
 template <bool SINGLES, bool FACETS, bool FIXED>
-__global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fused(DynArgs a, OwnerRec *rec_out, double *q_out,
-                                                    const uint32_t *start, const uint32_t *jarr,
-                                                    const uint32_t *bstart, const uint32_t *bidx,
-                                                    const uint32_t *bsrc, const uint8_t *oany,
-                                                    const float *hx, const float *hy, const float *hz,
-                                                    const float *hw, float *ox, float *oy, float *oz, float *ow,
-                                                    int64_t cap, DevCounters *ctr)
+__device__ __forceinline__ float step_owner(const DynArgs &a, const int64_t o, OwnerRec *rec_out, double *q_out, const uint32_t *start,
+    const uint32_t *jarr, const uint32_t *bstart, const uint32_t *bidx, const uint32_t *bsrc, const uint8_t *oany,
+    const float *hx, const float *hy, const float *hz, const float *hw, float *ox, float *oy, float *oz, float *ow,
+    int64_t cap, DevCounters *ctr)
 {
-    const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t o = (int64_t)lb * blockDim.x + threadIdx.x;
-    const int64_t No = a.n_owners;
-    const bool valid = o < No;
-    if (stopped(ctr, a.step)) {
-        if (valid) {
-            store_rec(rec_out + o, load_rec(a.rec + o));
-            if (!SINGLES)
-                *reinterpret_cast<double4 *>(q_out + 4 * (size_t)o) =
-                    *reinterpret_cast<const double4 *>(a.q + 4 * (size_t)o);
-            // (a set that overflowed its capacity has no valid rows to copy)
-            const uint32_t s0 = SINGLES ? (uint32_t)o : a.own_sph0[o];
-            const uint32_t s1 = SINGLES ? (uint32_t)o + 1u : a.own_sph0[o + 1];
-            if ((int64_t)start[a.n_spheres] <= cap)
-                for (uint32_t c = start[s0]; c < start[s1]; ++c)
-                    store_hist(ox, oy, oz, ow, c, load_hist(hx, hy, hz, hw, c, a.rolling), a.rolling);
-        }
-        return;
-    }
-    if (o == 0) {
-        ctr->last_step_done = a.step + 1;
-        ctr->contact_steps += ctr->n_contacts[a.cur];
-    }
     float v2 = 0.0f;
     // owners of fixed families (the flag's bit 1) keep their state, which
     // both state buffers hold: without contacts there is nothing to do; with
     // contacts only their A rows are evaluated, for the history
-    const uint8_t fl = (FIXED && valid) ? oany[o] : (uint8_t)0;
-    if (valid && (fl & 3u) != 2u) {
+    const uint8_t fl = FIXED ? oany[o] : (uint8_t)0;
+    if ((fl & 3u) != 2u) {
         // every per-owner load is issued here, none waits for another: the
         // record, the inertia, the orientation (clump systems), and whether
         // the owner has any contact in the set in use (a flag per owner
@@ -672,6 +657,64 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
             store_rec(rec_out + o, r);
         }
     }
+    return v2;
+}
+
+// A stopped step: the owner's state and history are copied unchanged.
+template <bool SINGLES>
+__device__ __forceinline__ void halt_owner(const DynArgs &a, const int64_t o, OwnerRec *rec_out, double *q_out, const uint32_t *start,
+    const uint32_t *jarr, const uint32_t *bstart, const uint32_t *bidx, const uint32_t *bsrc, const uint8_t *oany,
+    const float *hx, const float *hy, const float *hz, const float *hw, float *ox, float *oy, float *oz, float *ow,
+    int64_t cap, DevCounters *ctr)
+{
+        store_rec(rec_out + o, load_rec(a.rec + o));
+        if (!SINGLES)
+            *reinterpret_cast<double4 *>(q_out + 4 * (size_t)o) =
+                *reinterpret_cast<const double4 *>(a.q + 4 * (size_t)o);
+        // (a set that overflowed its capacity has no valid rows to copy)
+        const uint32_t s0 = SINGLES ? (uint32_t)o : a.own_sph0[o];
+        const uint32_t s1 = SINGLES ? (uint32_t)o + 1u : a.own_sph0[o + 1];
+        if ((int64_t)start[a.n_spheres] <= cap)
+            for (uint32_t c = start[s0]; c < start[s1]; ++c)
+                store_hist(ox, oy, oz, ow, c, load_hist(hx, hy, hz, hw, c, a.rolling), a.rolling);
+}
+
+template <bool SINGLES, bool FACETS, bool FIXED>
+__global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fused(DynArgs a, OwnerRec *rec_out, double *q_out,
+                                                    const uint32_t *start, const uint32_t *jarr,
+                                                    const uint32_t *bstart, const uint32_t *bidx,
+                                                    const uint32_t *bsrc, const uint8_t *oany,
+                                                    const float *hx, const float *hy, const float *hz,
+                                                    const float *hw, float *ox, float *oy, float *oz, float *ow,
+                                                    int64_t cap, DevCounters *ctr)
+{
+    const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t o0 = (int64_t)lb * blockDim.x + threadIdx.x;
+    const int64_t No = a.n_owners;
+    // with fixed families most owners may be dormant: each thread then takes
+    // every (grid size)-th owner, so dormant owners cost their flag byte and
+    // not a thread each
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (stopped(ctr, a.step)) {
+        if constexpr (FIXED) {
+            for (int64_t o = o0; o < No; o += stride) halt_owner<SINGLES>(a, o, rec_out, q_out, start, jarr, bstart, bidx, bsrc, oany, hx, hy, hz, hw, ox, oy, oz, ow, cap, ctr);
+        } else if (o0 < No) {
+            const int64_t o = o0;
+            halt_owner<SINGLES>(a, o, rec_out, q_out, start, jarr, bstart, bidx, bsrc, oany, hx, hy, hz, hw, ox, oy, oz, ow, cap, ctr);
+        }
+        return;
+    }
+    if (o0 == 0) {
+        ctr->last_step_done = a.step + 1;
+        ctr->contact_steps += ctr->n_contacts[a.cur];
+    }
+    float v2 = 0.0f;
+    if constexpr (FIXED) {
+        for (int64_t o = o0; o < No; o += stride) v2 = fmaxf(v2, step_owner<SINGLES, FACETS, FIXED>(a, o, rec_out, q_out, start, jarr, bstart, bidx, bsrc, oany, hx, hy, hz, hw, ox, oy, oz, ow, cap, ctr));
+    } else if (o0 < No) {
+        const int64_t o = o0;
+        v2 = step_owner<SINGLES, FACETS, FIXED>(a, o, rec_out, q_out, start, jarr, bstart, bidx, bsrc, oany, hx, hy, hz, hw, ox, oy, oz, ow, cap, ctr);
+    }
     block_max_v2(v2, a.blkmax + lb);
 }
 
@@ -745,7 +788,7 @@ void launch_adaptive_margin(DevCounters *ctr, double t, double gmag, double cap,
 
 void launch_reduce_max(const DynArgs &a, DevCounters *ctr, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(256), 0, s, a.blkmax, (int64_t)nblocks(a.n_owners), ctr);
+    hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(256), 0, s, a.blkmax, (int64_t)step_blocks(a), ctr);
 }
 
 void launch_force(const DynArgs &a, AcsBuf &cur, StepBufs &sb, DevCounters *ctr, hipStream_t s,
@@ -766,7 +809,7 @@ void launch_step_fused(const DynArgs &a, OwnerRec *rec_out, double *q_out, const
                     : (a.n_tri > 0 ? (a.has_clumps ? k_step_fused<false, true, false> : k_step_fused<true, true, false>)
                                    : (a.has_clumps ? k_step_fused<false, false, false>
                                                    : k_step_fused<true, false, false>));
-    hipLaunchKernelGGL(kern, dim3(nblocks(a.n_owners)), dim3(TPB), 0, s, a, rec_out, q_out,
+    hipLaunchKernelGGL(kern, dim3(step_blocks(a)), dim3(TPB), 0, s, a, rec_out, q_out,
                        (const uint32_t *)cur.start, (const uint32_t *)cur.j, (const uint32_t *)cur.bstart,
                        (const uint32_t *)cur.bidx, (const uint32_t *)cur.bsrc, (const uint8_t *)cur.oany,
                        (const float *)cur.hx,

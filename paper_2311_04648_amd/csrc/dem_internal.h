@@ -178,6 +178,14 @@ struct DetectArgs {
     const uint8_t *ofam;    // [No] family of each owner
     const uint8_t *pairoff; // [256*256] 1: contacts between the two families are not listed (null: none)
     const uint8_t *famfixed;// [256] 1: owners of the family are fixed
+    // dormant families (fixed, and switched off with every fixed family and
+    // every wall and mesh family): their spheres are left out of the binning
+    // of each detection; the active spheres find them in a static index
+    // built when the tags or the state are set (null: none)
+    const uint8_t *famdormant;      // [256]
+    const uint32_t *dcell_start;    // [nbins+1] bin ranges of the dormant index
+    const Cand *dcand;              // dormant candidates in bin order
+    const float4 *dcandf;           // their FP32 copies for the prefilter
 };
 
 struct CdWork {
@@ -232,6 +240,11 @@ void launch_detect_back(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap
                         int buf, hipStream_t s);
 void launch_judge(const DetectArgs &a, CdWork &w, const AcsBuf &cur, int64_t cap, DevCounters *ctr,
                   hipStream_t s);
+// the static index of the dormant spheres (a.famdormant must be set):
+// cell ranges into dcell_start, candidates into dcand / dcandf; w supplies
+// scratch (keys, cell_count, partials)
+void launch_dormant_index(const DetectArgs &a, CdWork &w, uint32_t *dcell_start, Cand *dcand, float4 *dcandf,
+                          hipStream_t s);
 void launch_blists(AcsBuf &b, int64_t n_spheres, int64_t cap, uint32_t *partials, hipStream_t s);
 // the per-owner contact flags of a set (AcsBuf::oany) from its rows and B
 // lists (an overflowed set flags nothing)
@@ -266,6 +279,7 @@ struct DynArgs {
     int32_t n_tri;
     const MeshPose *poses;  // [MAX_MESHES] mesh poses at `step` (device memory; null without meshes)
     int32_t has_fixed;      // some owner is in a fixed family (its flag in AcsBuf::oany, bit 1)
+    int32_t two_kernel;     // the step runs as force + fold kernels (one block per 256 owners)
 };
 
 struct StepBufs {

@@ -81,15 +81,21 @@ def test_judge_counts_switched_off_pairs_like_oracle(dem):
     assert ref > 10 and miss == ref
 
 
-def fixed_spheres(seed=7, n=512):
+def fixed_spheres(seed=7, n=512, dormant=False):
+    """Every third owner fixed; `dormant`: also switched off with the walls
+    (family 2), so the fixed spheres leave the binning (dormant index)."""
     s = W.small_spheres(seed, n=n, vel=0.3)
     fam = (np.arange(s.n_owners) % 3 == 0).astype(np.uint8)
+    if dormant:
+        return W.set_families(s, fam, pair_off=[(1, 1), (1, 2)], fixed=[1], wall_family=np.full(s.n_walls, 2))
     return W.set_families(s, fam, pair_off=[(1, 1)], fixed=[1])
 
 
-def fixed_clumps(seed=6, n=300):
+def fixed_clumps(seed=6, n=300, dormant=False):
     s = W.small_clumps(seed, n=n, vel=0.3, spacing=0.0080)
     fam = (np.arange(s.n_owners) % 4 == 1).astype(np.uint8)
+    if dormant:
+        return W.set_families(s, fam, pair_off=[(1, 1), (1, 2)], fixed=[1], wall_family=np.full(s.n_walls, 2))
     return W.set_families(s, fam, pair_off=[(1, 1)], fixed=[1])
 
 
@@ -105,9 +111,10 @@ def _run(dem, s, n, **kw):
     return st, g, keys, hist
 
 
-@pytest.mark.parametrize("name", ["spheres", "clumps"])
+@pytest.mark.parametrize("name", ["spheres", "clumps", "spheres_dormant", "clumps_dormant"])
 def test_fixed_families_schedules_bitwise(dem, name):
-    s = fixed_spheres() if name == "spheres" else fixed_clumps()
+    dorm = name.endswith("dormant")
+    s = fixed_spheres(dormant=dorm) if name.startswith("spheres") else fixed_clumps(dormant=dorm)
     fx = s.fam_fixed[s.owner_family] > 0
     _, ga, ka, ha = _run(dem, s, 300, mode="every")
     st_f, gb, _, _ = _run(dem, s, 300, mode="fixed", k=10, lam=5, judge=True, two_streams=True)
@@ -132,6 +139,43 @@ def test_fixed_families_schedules_bitwise(dem, name):
     fi = fx[s.sph_owner[i]]
     fj = fx[s.sph_owner[np.where(sph, j, 0)]] & sph
     assert np.any(fi != fj) and not np.any(fi & fj)
+
+
+@pytest.mark.parametrize("dormant", [False, True])
+@pytest.mark.parametrize("m", [0.0, 0.0002])
+def test_fixed_contact_sets_bit_exact(dem, dormant, m):
+    """With fixed families, and with dormant ones (left out of the binning,
+    found through their static index), the sets equal the oracle's."""
+    for s in (fixed_spheres(12, n=729, dormant=dormant), fixed_clumps(13, n=216, dormant=dormant)):
+        ctx = dem.DemContext(s, mode="fixed", margin=0.0002, capacity=32 * s.n_spheres)
+        ctx.set_state()
+        ctx.detect_contacts(m)
+        keys, _ = ctx.get_contacts()
+        o = oracle.Oracle(s)
+        ref = o.detect(o.state(), m)
+        assert ref.size > 50
+        np.testing.assert_array_equal(keys, ref)
+        ctx.close()
+
+
+def test_dormant_rows_longer_than_the_stage(dem):
+    """A large active sphere covered by 60 small dormant ones: its row (60
+    dormant partners) goes through the overflow path of the compaction,
+    which finds dormant partners through the index too."""
+    import test_gpu_parity as P
+    s = P.cluster()
+    fam = np.ones(s.n_owners, dtype=np.uint8)
+    fam[0] = 0
+    W.set_families(s, fam, pair_off=[(1, 1), (1, 2)], fixed=[1], wall_family=np.full(s.n_walls, 2))
+    ctx = dem.DemContext(s, mode="fixed", margin=s.margin, capacity=64 * s.n_spheres)
+    ctx.set_state()
+    for m in (0.0, s.margin):
+        ctx.detect_contacts(m)
+        keys, _ = ctx.get_contacts()
+        o = oracle.Oracle(s)
+        ref = o.detect(o.state(), m)
+        assert (ref >> np.uint64(32) == 0).sum() > 16
+        np.testing.assert_array_equal(keys, ref)
 
 
 def test_fixed_one_step_matches_oracle(dem):

@@ -439,7 +439,7 @@ def activebox(seed=0, n_owners=4_000_000):
     config-4 bed at a quarter of its size (about 7.5 M spheres in 4 M owners,
     1 m wide): the owners within 0.25 m along x, 0.3 m along y and 0.1 m in
     depth of the rolling cylinder's start are active, the rest dormant
-    (fixed, no contacts among themselves)."""
+    (fixed, touching only active owners)."""
     s = config4(seed=seed, n_owners=n_owners)
     cyl = s.wall_geom[-1]
     top = s.X[:, 2].max()
@@ -636,14 +636,18 @@ def set_families(sysm, owner_family=None, pair_off=(), fixed=(), wall_family=Non
     return sysm
 
 
-def active_box(sysm, lo, hi, active=0, dormant=1):
+def active_box(sysm, lo, hi, active=0, dormant=1, walls=2, meshes=3):
     """The active-box scheme of the paper's rover test (Sec. 6.4): owners
     whose centre lies outside the box [lo, hi] go to family `dormant`, which
-    is fixed and has its contacts with itself switched off, so only pairs
-    with an active owner are listed; owners inside go to family `active`."""
+    is fixed and has its contacts with itself, with the walls (family
+    `walls`) and with the meshes (family `meshes`) switched off, so the
+    dormant owners touch only active ones; owners inside go to family
+    `active`."""
     inside = np.all((sysm.X >= np.asarray(lo)) & (sysm.X <= np.asarray(hi)), axis=1)
     fam = np.where(inside, active, dormant).astype(np.uint8)
-    return set_families(sysm, fam, pair_off=[(dormant, dormant)], fixed=[dormant])
+    return set_families(sysm, fam, pair_off=[(dormant, dormant), (dormant, walls), (dormant, meshes)],
+                        fixed=[dormant], wall_family=np.full(sysm.n_walls, walls),
+                        mesh_family=np.full(sysm.n_mesh, meshes))
 
 
 def mixer_bed(seed, n, R, Hb, r, E, cor, dt, margin, omega_z, mesh_res, vel=0.0, name="mixer", packing="cubic",
