@@ -84,10 +84,23 @@ __device__ inline bool stopped(const DevCounters *c, int64_t step)
     return c->stop_cd != 0u || c->div[(step + 1) & 1] != 0u;
 }
 
+__device__ inline float4 load_hist(const float *hx, const float *hy, const float *hz, const float *hw,
+                                   uint32_t c, int rolling)
+{
+    return make_float4(hx[c], hy[c], hz[c], rolling ? hw[c] : 0.f);
+}
+
+// History arrays of a set and the contact's index in them.
+struct HistIn {
+    const float *x, *y, *z, *w;
+    uint32_t c;
+};
+
 // One contact evaluated from the side of sphere A (the lower id of the pair
 // or the sphere of a sphere-wall pair): overlap and normal in FP64, the
 // Hertz-Mindlin law with tangential history in FP32.  `hold` is the contact's
-// history before the step; the result holds the new one.  Both the A-side
+// history before the step (read only once the pair is found touching: most
+// pairs of a margin set are not); the result holds the new one.  Both the A-side
 // sum and the B-side reaction of a contact are taken from this one function,
 // so a contact gives the same bits wherever it is evaluated.
 struct ContactOut {
@@ -104,10 +117,12 @@ struct ContactOut {
 // meshes use the variant without it).
 // KNOWN_B: B is a sphere whose record and kinematics the caller already
 // holds (sBk, kBk, xBk; the fused step evaluates its B-list entries with
-// its own sphere as B); otherwise B is loaded from jp.
-template <bool FACETS, bool KNOWN_B = false>
+// its own sphere as B); otherwise B is loaded from jp.  SINGLES: every owner
+// is one sphere, so B's owner record is at jp and is loaded with its sphere
+// record rather than after it.
+template <bool FACETS, bool KNOWN_B = false, bool SINGLES = false>
 __device__ __forceinline__ void contact_eval(const DynArgs &a, const SphRec &sA, const OwnerKin &kA,
-                                             const double *xA, uint32_t jp, float4 hold, ContactOut &out,
+                                             const double *xA, uint32_t jp, const HistIn &hin, ContactOut &out,
                                              const SphRec *sBk = nullptr, const OwnerKin *kBk = nullptr,
                                              const double *xBk = nullptr)
 {
@@ -131,7 +146,7 @@ __device__ __forceinline__ void contact_eval(const DynArgs &a, const SphRec &sA,
             xB[2] = xBk[2];
         } else {
             sB = load_sph(a.sph + jp);
-            const OwnerRec rB = load_rec(a.rec + sB.owner);
+            const OwnerRec rB = load_rec(a.rec + (SINGLES ? jp : sB.owner));
             owner_kin(rB, sB, a.aux, a.q, a.tpos, a.org, kB, xB);
         }
         double dx = xA[0] - xB[0], dy = xA[1] - xB[1], dz = xA[2] - xB[2];
@@ -225,6 +240,7 @@ __device__ __forceinline__ void contact_eval(const DynArgs &a, const SphRec &sA,
         out.h = make_float4(0.f, 0.f, 0.f, 0.f);
         return;
     }
+    const float4 hold = load_hist(hin.x, hin.y, hin.z, hin.w, hin.c, a.rolling);
     // contact point in the middle of the overlap; arms to both owner centres
     const double sc = radA - 0.5 * delta;
     double cp[3] = {xA[0] - sc * nrm[0], xA[1] - sc * nrm[1], xA[2] - sc * nrm[2]};
@@ -295,12 +311,6 @@ __device__ __forceinline__ void contact_eval(const DynArgs &a, const SphRec &sA,
     out.h = make_float4(xi.x, xi.y, xi.z, age);
 }
 
-__device__ inline float4 load_hist(const float *hx, const float *hy, const float *hz, const float *hw,
-                                   uint32_t c, int rolling)
-{
-    return make_float4(hx[c], hy[c], hz[c], rolling ? hw[c] : 0.f);
-}
-
 __device__ inline void store_hist(float *hx, float *hy, float *hz, float *hw, uint32_t c, float4 h, int rolling)
 {
     hx[c] = h.x;
@@ -330,7 +340,7 @@ __global__ void __launch_bounds__(TPB) k_force(DynArgs a, const uint32_t *start,
         owner_kin(rA, sA, a.aux, a.q, a.tpos, a.org, kA, xA);
         for (uint32_t c = c0; c < c1; ++c) {
             ContactOut co;
-            contact_eval<FACETS>(a, sA, kA, xA, jarr[c], load_hist(hx, hy, hz, hw, c, a.rolling), co);
+            contact_eval<FACETS>(a, sA, kA, xA, jarr[c], HistIn{hx, hy, hz, hw, c}, co);
             store_hist(hx, hy, hz, hw, c, co.h, a.rolling);
             if (!co.touching) {
                 bF[c] = 0.f;
@@ -596,16 +606,18 @@ __device__ __forceinline__ float step_owner(const DynArgs &a, const int64_t o, O
                 if constexpr (SINGLES) {
                     if (aside) {
                         c = c0 + t;
-                        contact_eval<FACETS>(a, sS, kS, xS, jarr[c], load_hist(hx, hy, hz, hw, c, a.rolling), co);
+                        contact_eval<FACETS, false, true>(a, sS, kS, xS, jarr[c], HistIn{hx, hy, hz, hw, c}, co);
                     } else {
                         const uint32_t b = b0 + (t - na);
                         c = bidx[b];
-                        const SphRec sA = load_sph(a.sph + bsrc[b]);
-                        const OwnerRec rA = load_rec(a.rec + sA.owner);
+                        const uint32_t iA = bsrc[b];
+                        // (owner index == sphere index: both loads at once)
+                        const SphRec sA = load_sph(a.sph + iA);
+                        const OwnerRec rA = load_rec(a.rec + iA);
                         OwnerKin kA;
                         double xA[3];
                         owner_kin(rA, sA, a.aux, a.q, a.tpos, a.org, kA, xA);
-                        contact_eval<false, true>(a, sA, kA, xA, s, load_hist(hx, hy, hz, hw, c, a.rolling), co,
+                        contact_eval<false, true>(a, sA, kA, xA, s, HistIn{hx, hy, hz, hw, c}, co,
                                                   &sS, &kS, xS);
                     }
                 } else {
@@ -625,7 +637,7 @@ __device__ __forceinline__ float step_owner(const DynArgs &a, const int64_t o, O
                     OwnerKin kA;
                     double xA[3];
                     owner_kin(rA, sA, a.aux, a.q, a.tpos, a.org, kA, xA);
-                    contact_eval<FACETS>(a, sA, kA, xA, jp, load_hist(hx, hy, hz, hw, c, a.rolling), co);
+                    contact_eval<FACETS>(a, sA, kA, xA, jp, HistIn{hx, hy, hz, hw, c}, co);
                 }
                 if (aside) {
                     store_hist(ox, oy, oz, ow, c, co.h, a.rolling);
