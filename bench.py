@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--lam", type=int, default=5)
     ap.add_argument("--dyn-path", type=int, default=0,
-                    help="dynamics: 0 one fused kernel per step, 1 force kernel + fold/integrate kernel")
+                    help="dynamics: 0 one fused kernel per step, 1 force kernel + fold/integrate kernel, 2/3 fused with the history always/never staged in LDS")
     ap.add_argument("--timing", type=int, default=32,
                     help="time the dynamics kernel with HIP events every n-th step")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -74,8 +74,10 @@ def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, roll
       (96) and the inverse inertia (4 for single-sphere systems; else 16, and
       per clump owner the quaternion read + written 64); per active sphere
       its record, row and B-list offsets and its owner's sphere range (28);
-      per contact the partner id (4), the history read + written (24, 32
-      with contact age) and the B-list entry with its source sphere (8);
+      per contact the partner id (4), the new history written (12, 16 with
+      contact age) and the B-list entry with its source sphere (8); the old
+      history is read only for pairs that touch and is not counted (so the
+      figure is a lower bound);
       with meshes, each facet's vertices and mesh index (80).  An owner of a
       fixed family without contacts reads its flag only (1).
     k_fold_integrate: per owner the record read + write (96) and the inverse
@@ -98,7 +100,7 @@ def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, roll
         nc = (No if n_clump is None else n_clump) if clumps else 0
         nc -= n_dormant_clump if clumps else 0
         return ((No - n_dormant) * (113 if clumps else 101) + n_dormant + nc * 64 + active * 28
-                + C * (44 if rolling else 36) + n_tri * 80)
+                + C * (28 if rolling else 24) + n_tri * 80)
     if stage == "k_fold_integrate":
         return No * (116 if clumps else 100) + Ns * 8 + active * 24 + C * 28
     if stage == "detect":
@@ -248,7 +250,7 @@ def main():
     r = results[head]
     st = r["stats"]
     value = Ns * args.steps / r["seconds"]
-    stages = STAGES_FUSED if args.dyn_path == 0 else STAGES
+    stages = STAGES_FUSED if args.dyn_path != 1 else STAGES
     # dominant single kernel of the headline run (the fused step, or force or
     # fold/integrate on the two-kernel path),
     # (stage 4 is the stamp-overhead probe, not a stage of the path)
@@ -329,7 +331,7 @@ def main():
         # kernel(s) every step, detection and remap once per detection
         s2 = rr["stats"]
         Cm, act = s2["mean_contacts"], rr["active"]
-        if args.dyn_path == 0:
+        if args.dyn_path != 1:
             dyn_b = algorithmic_bytes("k_step_fused", Ns, No, Cm, act, 0, passes, clumps=Ns != No, rolling=rolling,
                                       n_clump=n_clump, n_tri=n_tri, n_dormant=n_dormant,
                                       n_dormant_clump=n_dormant_clump)
@@ -381,7 +383,7 @@ def main():
                     f"owners), the rest dormant; delayed CD every {args.k} steps on a second HIP stream")
                    if args.workload == "activebox" else f"{args.workload}: {Ns} spheres, {No} owners",
                    "n_spheres": Ns, "n_owners": No, "schedule": head, "k": args.k, "lambda": args.lam,
-                   "dynamics": "one fused kernel per step" if args.dyn_path == 0 else "force + fold kernels"},
+                   "dynamics": "one fused kernel per step" if args.dyn_path != 1 else "force + fold kernels"},
         "modes": modes_out,
         "missed_contacts": misses.get(head),
         "roofline": roofline,

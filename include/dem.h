@@ -178,7 +178,11 @@ typedef struct {
                                its B-side contacts with the same function, then
                                integrates; state and history are double-buffered),
                                1 two kernels (forces with per-contact reactions, then
-                               the ordered fold and integration); both give the same bits */
+                               the ordered fold and integration); 2 and 3 the fused
+                               kernel with its history writes always (2) or never (3)
+                               gathered per wave in LDS, which 0 decides from the last
+                               contact count read back (at least one per two spheres:
+                               gathered); all give the same bits */
 } dem_params;
 
 /* Statistics of a dem_step call (Sec. 2.1, thread collaboration stats). */

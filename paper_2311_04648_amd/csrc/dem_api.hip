@@ -372,6 +372,13 @@ DynArgs dyn_args(const dem_ctx *ctx, int64_t step)
     a.poses = nullptr;
     a.has_fixed = ctx->has_fixed ? 1 : 0;
     a.two_kernel = ctx->P.dyn_path == 1 ? 1 : 0;
+    a.dense_rows = 0;
+    if (ctx->P.dyn_path == 2) {
+        a.dense_rows = 1;
+    } else if (ctx->P.dyn_path == 0 && ctx->h_ctr) {
+        const int64_t nc = std::max(ctx->h_ctr->n_contacts[0], ctx->h_ctr->n_contacts[1]);
+        a.dense_rows = 2 * nc >= ctx->Ns ? 1 : 0;
+    }
     return a;
 }
 
@@ -539,7 +546,8 @@ dem_status dem_create(const dem_params *params, const dem_materials *mats, const
     if (P.cd_mode < 0 || P.cd_mode > 3) return fail("unknown cd_mode");
     if (P.cd_mode == DEM_CD_ADAPTIVE && (P.cd_latency < 1 || P.cd_interval_max < 1))
         return fail("the adaptive schedule needs cd_latency >= 1 and cd_interval_max >= 1");
-    if (P.dyn_path < 0 || P.dyn_path > 1) return fail("dyn_path must be 0 (fused) or 1 (two kernels)");
+    if (P.dyn_path < 0 || P.dyn_path > 3)
+        return fail("dyn_path must be 0 (fused), 1 (two kernels), 2 or 3 (fused, history staged or not)");
     if (P.bin_sort < 0 || P.bin_sort > 1) return fail("bin_sort must be 0 (one pass) or 1 (radix)");
     if (P.cd_mode != DEM_CD_EVERY) {
         if (P.cd_interval < 1) return fail("cd_interval must be >= 1");
@@ -804,7 +812,10 @@ dem_status dem_bind(dem_ctx *ctx, void *device_workspace, int64_t bytes, int64_t
     ctx->cap = contact_capacity;
     Carver c(ctx->ws);
     carve(c, ctx, contact_capacity);
-    if (!ctx->h_ctr) HIPCHK(hipHostMalloc((void **)&ctx->h_ctr, sizeof(DevCounters)));
+    if (!ctx->h_ctr) {
+        HIPCHK(hipHostMalloc((void **)&ctx->h_ctr, sizeof(DevCounters)));
+        memset(ctx->h_ctr, 0, sizeof(DevCounters));
+    }
     if (!ctx->h_pred) HIPCHK(hipHostMalloc((void **)&ctx->h_pred, 64));
     if (!ctx->ev_wo) HIPCHK(hipEventCreateWithFlags(&ctx->ev_wo, hipEventDisableTiming));
     if (!ctx->ev_cd) HIPCHK(hipEventCreateWithFlags(&ctx->ev_cd, hipEventDisableTiming));
@@ -1540,7 +1551,7 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
         // single kernels are bracketed by marker events, which wait for the
         // previous work on the stream; an empty kernel bracketed the same way
         // measures the markers' own overhead
-        if (P.dyn_path == 0) {
+        if (P.dyn_path != 1) {
             if (P.timing > 0 && n % P.timing == 0) ctx->run_due = true;
             if (!ctx->run && ctx->run_due) {
                 bool open = P.cd_mode == DEM_CD_EVERY || P.judge;
@@ -1568,7 +1579,7 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
             launch_fold_integrate(a, ctx->acs[ctx->cur], ctx->sb, ctx->ctr, 1, dyn);
             stage_end(ti, dyn);
         }
-        if (P.dyn_path != 0) {
+        if (P.dyn_path == 1) {
             if (auto *tn = stage_begin(ctx, 4, dyn)) {
                 launch_noop(dyn, nullptr, nullptr);
                 stage_end(tn, dyn);

@@ -319,6 +319,35 @@ __device__ inline void store_hist(float *hx, float *hy, float *hz, float *hw, ui
     if (rolling) hw[c] = h.w;
 }
 
+// Where the fused step puts the new history of a wave's A rows.  Rows of
+// consecutive owners are consecutive, so a wave's rows are one range
+// [c0, c0 + n) of the set.  Its first HIST_STAGE entries are put in the
+// wave's LDS slice and written out together, in whole lines, once the
+// wave's owners are done (the rest go straight to memory); written per
+// lane, each store would fill a few bytes of lines spread over the range
+// while they wait for their other entries, and the L2 writes such lines
+// back several times.
+constexpr uint32_t HIST_STAGE = 512;   // entries per wave (4 components: 8 KiB)
+
+struct HistOut {
+    float *x, *y, *z, *w;
+    float *lds;      // the wave's slice, component k at k * HIST_STAGE; nullptr: write to x..w directly
+    uint32_t c0;     // the range's first entry
+};
+
+__device__ inline void put_hist(const HistOut &ho, uint32_t c, float4 h, int rolling)
+{
+    const uint32_t k = c - ho.c0;
+    if (ho.lds && k < HIST_STAGE) {
+        ho.lds[k] = h.x;
+        ho.lds[HIST_STAGE + k] = h.y;
+        ho.lds[2 * HIST_STAGE + k] = h.z;
+        if (rolling) ho.lds[3 * HIST_STAGE + k] = h.w;
+    } else {
+        store_hist(ho.x, ho.y, ho.z, ho.w, c, h, rolling);
+    }
+}
+
 // Two-kernel path (forces without integration): A-side sums per sphere and
 // the reaction on B per contact, history updated in place.
 template <bool FACETS>
@@ -542,42 +571,57 @@ __global__ void __launch_bounds__(TPB) k_fold_integrate(DynArgs a, const uint32_
 // writes.  When the step is stopped (capacity or divergence) the state and
 // history are copied unchanged.  SINGLES: every owner is one sphere; FACETS:
 // the set may hold sphere-facet contacts; FIXED: some owner is in a fixed
-// family.  Systems with clumps or meshes get
+// family; STAGE: the history of a wave's rows goes through LDS (sets with
+// many contacts per sphere; with few, looking up each wave's range costs
+// more than it saves).  Systems with clumps or meshes get
 // 3 waves per SIMD: the clump rotation and the FP64 closest point would
 // otherwise spill registers to scratch inside the contact loop, which costs
 // more than the lost occupancy.
-// The step of one owner (see k_step_fused); returns its |v|^2.
+// What the contact part of an owner's step hands to its integration.
+struct OwnerStep {
+    OwnerRec r;
+    float inv[3];
+    int32_t tmpl;
+    double4 qv;
+    float3 F, T;
+    bool advance;    // the owner is integrated (not in a fixed family)
+};
+
+// The contact part of one owner's step (see k_step_fused): the sums F, T of
+// the forces and torques on it, its rows' new history put through ho.
 template <bool SINGLES, bool FACETS, bool FIXED>
-__device__ __forceinline__ float step_owner(const DynArgs &a, const int64_t o, OwnerRec *rec_out, double *q_out, const uint32_t *start,
+__device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, const uint32_t *start,
     const uint32_t *jarr, const uint32_t *bstart, const uint32_t *bidx, const uint32_t *bsrc, const uint8_t *oany,
-    const float *hx, const float *hy, const float *hz, const float *hw, float *ox, float *oy, float *oz, float *ow,
-    int64_t cap, DevCounters *ctr)
+    const uint8_t fl_fixed, const float *hx, const float *hy, const float *hz, const float *hw, const HistOut &ho,
+    OwnerStep &st)
 {
-    float v2 = 0.0f;
-    // owners of fixed families (the flag's bit 1) keep their state, which
-    // both state buffers hold: without contacts there is nothing to do; with
-    // contacts only their A rows are evaluated, for the history
-    const uint8_t fl = FIXED ? oany[o] : (uint8_t)0;
-    if ((fl & 3u) != 2u) {
+    st.advance = false;
+    // The owner's flag byte, written with the set (bit 0: the owner has a
+    // contact in it; bit 1: the owner is in a fixed family), read by the
+    // caller when FIXED (fl_fixed).  Owners of fixed families keep their
+    // state, which both state buffers hold: without contacts there is
+    // nothing to do; with contacts only their A rows are evaluated, for the
+    // history
+    if (!FIXED || (fl_fixed & 3u) != 2u) {
         // every per-owner load is issued here, none waits for another: the
-        // record, the inertia, the orientation (clump systems), and whether
-        // the owner has any contact in the set in use (a flag per owner
-        // written with the set)
-        OwnerRec r = load_rec(a.rec + o);
-        float inv[3];
-        int32_t tmpl = -1;
-        double4 qv = make_double4(1.0, 0.0, 0.0, 0.0);
+        // record, the inertia, the orientation (clump systems) and (without
+        // fixed families) the flag
+        OwnerRec &r = st.r;
+        r = load_rec(a.rec + o);
+        st.tmpl = -1;
+        st.qv = make_double4(1.0, 0.0, 0.0, 0.0);
         if (SINGLES) {
-            inv[0] = inv[1] = inv[2] = a.inv_i[o];
+            st.inv[0] = st.inv[1] = st.inv[2] = a.inv_i[o];
         } else {
             const OwnerAux ax = a.aux[o];
-            inv[0] = ax.inv_moi[0];
-            inv[1] = ax.inv_moi[1];
-            inv[2] = ax.inv_moi[2];
-            tmpl = ax.tmpl;
-            qv = *reinterpret_cast<const double4 *>(a.q + 4 * (size_t)o);
+            st.inv[0] = ax.inv_moi[0];
+            st.inv[1] = ax.inv_moi[1];
+            st.inv[2] = ax.inv_moi[2];
+            st.tmpl = ax.tmpl;
+            st.qv = *reinterpret_cast<const double4 *>(a.q + 4 * (size_t)o);
         }
-        const bool any = (oany[o] & 1u) != 0;
+        const uint8_t fl = FIXED ? fl_fixed : oany[o];
+        const bool any = (fl & 1u) != 0;
         const bool fixed = FIXED && (fl & 2u) != 0;
         float3 F = f3(0.f, 0.f, 0.f), T = f3(0.f, 0.f, 0.f);
         const uint32_t s0 = SINGLES ? (uint32_t)o : (any ? a.own_sph0[o] : 0u);
@@ -640,7 +684,7 @@ __device__ __forceinline__ float step_owner(const DynArgs &a, const int64_t o, O
                     contact_eval<FACETS>(a, sA, kA, xA, jp, HistIn{hx, hy, hz, hw, c}, co);
                 }
                 if (aside) {
-                    store_hist(ox, oy, oz, ow, c, co.h, a.rolling);
+                    put_hist(ho, c, co.h, a.rolling);
                     if (co.touching) {
                         FA = FA + co.F;
                         TA = TA + cross3(co.armA, co.Ft);
@@ -660,15 +704,23 @@ __device__ __forceinline__ float step_owner(const DynArgs &a, const int64_t o, O
                 }
             }
         }
-        if (!fixed) {
-            const bool rotating = !SINGLES && tmpl >= 0;
-            double *qo = q_out + 4 * (size_t)o;
-            // (a single sphere's orientation never changes and both buffers
-            // hold it, so nothing is copied for it)
-            v2 = advance(a, r, inv, rotating, F, T, qv, qo, ctr);
-            store_rec(rec_out + o, r);
-        }
+        st.F = F;
+        st.T = T;
+        st.advance = !fixed;
     }
+}
+
+// The integration part of an owner's step; returns its |v|^2.
+template <bool SINGLES>
+__device__ __forceinline__ float owner_advance(const DynArgs &a, const int64_t o, OwnerStep &st, OwnerRec *rec_out,
+                                               double *q_out, DevCounters *ctr)
+{
+    const bool rotating = !SINGLES && st.tmpl >= 0;
+    double *qo = q_out + 4 * (size_t)o;
+    // (a single sphere's orientation never changes and both buffers hold
+    // it, so nothing is copied for it)
+    const float v2 = advance(a, st.r, st.inv, rotating, st.F, st.T, st.qv, qo, ctr);
+    store_rec(rec_out + o, st.r);
     return v2;
 }
 
@@ -691,7 +743,57 @@ __device__ __forceinline__ void halt_owner(const DynArgs &a, const int64_t o, Ow
                 store_hist(ox, oy, oz, ow, c, load_hist(hx, hy, hz, hw, c, a.rolling), a.rolling);
 }
 
-template <bool SINGLES, bool FACETS, bool FIXED>
+// The step of the (up to) 64 consecutive owners from ow of one wave (runs
+// without fixed families); every
+// lane of the wave takes part (the history range is written out by all of
+// them, before the owner records, so that the wait for the range's bounds
+// is not a wait for those stores).  Returns the lane's |v|^2.
+template <bool SINGLES, bool FACETS, bool FIXED, bool STAGE>
+__device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, float *lds, OwnerRec *rec_out, double *q_out,
+    const uint32_t *start, const uint32_t *jarr, const uint32_t *bstart, const uint32_t *bidx, const uint32_t *bsrc,
+    const uint8_t *oany, const float *hx, const float *hy, const float *hz, const float *hw, float *ox, float *oy,
+    float *oz, float *ohw, int64_t cap, DevCounters *ctr)
+{
+    const int64_t No = a.n_owners;
+    const uint32_t lane = threadIdx.x & 63u;
+    const int64_t o = ow + lane;
+    const bool valid = o < No;
+    // the range of the wave's rows, read here and used only once the rows
+    // are evaluated (its loads overlap the owners')
+    HistOut ho{ox, oy, oz, ohw, nullptr, 0u};
+    uint32_t c_end = 0;
+    if constexpr (STAGE) {
+        const int64_t oe = ow + 64 < No ? ow + 64 : No;
+        const uint32_t sb = SINGLES ? (uint32_t)ow : a.own_sph0[ow];
+        const uint32_t se = SINGLES ? (uint32_t)oe : a.own_sph0[oe];
+        ho.lds = lds;
+        ho.c0 = start[sb];
+        c_end = start[se];
+    }
+    OwnerStep st;
+    st.advance = false;
+    if (valid)
+        owner_forces<SINGLES, FACETS, FIXED>(a, o, start, jarr, bstart, bidx, bsrc, oany, 0, hx, hy, hz, hw, ho, st);
+    const uint32_t n = c_end - ho.c0 < HIST_STAGE ? c_end - ho.c0 : HIST_STAGE;
+    if (STAGE && n > 0) {
+        // every staged entry was put by some lane of this wave.  The LDS
+        // operations of a wave are performed in the order it issues them,
+        // so wavefront-scope ordering is enough.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t wc0 = ho.c0;
+        for (uint32_t k = lane; k < n; k += 64u) {
+            ox[wc0 + k] = lds[k];
+            oy[wc0 + k] = lds[HIST_STAGE + k];
+            oz[wc0 + k] = lds[2 * HIST_STAGE + k];
+            if (a.rolling) ohw[wc0 + k] = lds[3 * HIST_STAGE + k];
+        }
+    }
+    return st.advance ? owner_advance<SINGLES>(a, o, st, rec_out, q_out, ctr) : 0.0f;
+}
+
+template <bool SINGLES, bool FACETS, bool FIXED, bool STAGE>
 __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fused(DynArgs a, OwnerRec *rec_out, double *q_out,
                                                     const uint32_t *start, const uint32_t *jarr,
                                                     const uint32_t *bstart, const uint32_t *bidx,
@@ -700,6 +802,8 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
                                                     const float *hw, float *ox, float *oy, float *oz, float *ow,
                                                     int64_t cap, DevCounters *ctr)
 {
+    static_assert(!(FIXED && STAGE), "runs with fixed families do not stage");
+    __shared__ float hst[STAGE ? TPB / 64 : 1][STAGE ? 4 * HIST_STAGE : 1];
     const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t o0 = (int64_t)lb * blockDim.x + threadIdx.x;
     const int64_t No = a.n_owners;
@@ -721,11 +825,21 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
         ctr->contact_steps += ctr->n_contacts[a.cur];
     }
     float v2 = 0.0f;
+    // the wave's index in the block, as a wave-uniform (scalar) value
+    const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    float *lds = STAGE ? hst[wv] : nullptr;
+    const int64_t w0 = (int64_t)lb * blockDim.x + 64 * wv;
     if constexpr (FIXED) {
-        for (int64_t o = o0; o < No; o += stride) v2 = fmaxf(v2, step_owner<SINGLES, FACETS, FIXED>(a, o, rec_out, q_out, start, jarr, bstart, bidx, bsrc, oany, hx, hy, hz, hw, ox, oy, oz, ow, cap, ctr));
-    } else if (o0 < No) {
-        const int64_t o = o0;
-        v2 = step_owner<SINGLES, FACETS, FIXED>(a, o, rec_out, q_out, start, jarr, bstart, bidx, bsrc, oany, hx, hy, hz, hw, ox, oy, oz, ow, cap, ctr);
+        // (no staging: the owners of a thread are not those of one wave)
+        const HistOut ho{ox, oy, oz, ow, nullptr, 0u};
+        for (int64_t o = o0; o < No; o += stride) {
+            OwnerStep st;
+            owner_forces<SINGLES, FACETS, FIXED>(a, o, start, jarr, bstart, bidx, bsrc, oany, oany[o], hx, hy, hz,
+                                                 hw, ho, st);
+            if (st.advance) v2 = fmaxf(v2, owner_advance<SINGLES>(a, o, st, rec_out, q_out, ctr));
+        }
+    } else if (w0 < No) {
+        v2 = step_wave<SINGLES, FACETS, FIXED, STAGE>(a, w0, lds, rec_out, q_out, start, jarr, bstart, bidx, bsrc, oany, hx, hy, hz, hw, ox, oy, oz, ow, cap, ctr);
     }
     block_max_v2(v2, a.blkmax + lb);
 }
@@ -815,12 +929,17 @@ void launch_force(const DynArgs &a, AcsBuf &cur, StepBufs &sb, DevCounters *ctr,
 void launch_step_fused(const DynArgs &a, OwnerRec *rec_out, double *q_out, const AcsBuf &cur, int64_t cap,
                        DevCounters *ctr, hipStream_t s)
 {
-    auto kern = a.has_fixed
-                    ? (a.n_tri > 0 ? (a.has_clumps ? k_step_fused<false, true, true> : k_step_fused<true, true, true>)
-                                   : (a.has_clumps ? k_step_fused<false, false, true> : k_step_fused<true, false, true>))
-                    : (a.n_tri > 0 ? (a.has_clumps ? k_step_fused<false, true, false> : k_step_fused<true, true, false>)
-                                   : (a.has_clumps ? k_step_fused<false, false, false>
-                                                   : k_step_fused<true, false, false>));
+    // runs with fixed families (mostly dormant waves) never stage
+    decltype(&k_step_fused<true, false, false, false>) kern;
+    if (a.has_fixed)
+        kern = a.n_tri > 0 ? (a.has_clumps ? k_step_fused<false, true, true, false> : k_step_fused<true, true, true, false>)
+                           : (a.has_clumps ? k_step_fused<false, false, true, false> : k_step_fused<true, false, true, false>);
+    else if (a.dense_rows)
+        kern = a.n_tri > 0 ? (a.has_clumps ? k_step_fused<false, true, false, true> : k_step_fused<true, true, false, true>)
+                           : (a.has_clumps ? k_step_fused<false, false, false, true> : k_step_fused<true, false, false, true>);
+    else
+        kern = a.n_tri > 0 ? (a.has_clumps ? k_step_fused<false, true, false, false> : k_step_fused<true, true, false, false>)
+                           : (a.has_clumps ? k_step_fused<false, false, false, false> : k_step_fused<true, false, false, false>);
     hipLaunchKernelGGL(kern, dim3(step_blocks(a)), dim3(TPB), 0, s, a, rec_out, q_out,
                        (const uint32_t *)cur.start, (const uint32_t *)cur.j, (const uint32_t *)cur.bstart,
                        (const uint32_t *)cur.bidx, (const uint32_t *)cur.bsrc, (const uint8_t *)cur.oany,

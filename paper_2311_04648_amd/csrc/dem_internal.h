@@ -280,6 +280,9 @@ struct DynArgs {
     const MeshPose *poses;  // [MAX_MESHES] mesh poses at `step` (device memory; null without meshes)
     int32_t has_fixed;      // some owner is in a fixed family (its flag in AcsBuf::oany, bit 1)
     int32_t two_kernel;     // the step runs as force + fold kernels (one block per 256 owners)
+    int32_t dense_rows;     // the last contact count read back was at least one per two spheres: the
+                            // fused step stages its history writes in LDS (a choice of speed only:
+                            // both variants give the same bits)
 };
 
 struct StepBufs {

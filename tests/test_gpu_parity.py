@@ -291,32 +291,57 @@ def _fused_case(name):
         return s
     if name == "clumps_dense":
         return W.small_clumps(6, n=300, vel=0.3, with_cylinder=True, spacing=0.0080)
+    if name == "wide_margin":
+        return wide_margin_lattice()
     return SYS[name]
 
 
-@pytest.mark.parametrize("name", ["cluster", "spheres", "clumps", "clumps_dense", "spheres_ragged", "rolling"])
+def wide_margin_lattice(m=10, r=0.001, gap=5e-5, margin=0.0015):
+    """A cubic lattice of nearly touching spheres with a margin of 1.5
+    radii: about 20 pairs per sphere in the set, so the rows of 64
+    consecutive spheres hold far more than one wave's LDS slice of
+    history (512 entries) and the fused step stages part of them."""
+    g = np.arange(m) * (2 * r + gap)
+    X = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)[:, ::-1].copy()
+    X -= X.mean(0)
+    n = X.shape[0]
+    rng = np.random.default_rng(4)
+    V = rng.normal(0, 0.05, size=X.shape)
+    L = 0.02
+    return W.assemble(np.full(n, -1), X, W._qid(n), V, np.zeros_like(X), [], r, None,
+                      W.box_walls(-L * np.ones(3), L * np.ones(3)), W.materials(), (0, 0, -9.81), 2e-6,
+                      margin, -L * np.ones(3), L * np.ones(3), name="wide_margin")
+
+
+@pytest.mark.parametrize("name", ["cluster", "spheres", "clumps", "clumps_dense", "spheres_ragged", "rolling",
+                                  "wide_margin"])
 def test_fused_step_equals_two_kernel_path_bitwise(dem, name):
     """The fused step (each owner re-evaluates its B-side contacts with the
     same function) gives the bits of the two-kernel path (per-contact
     reactions written, then the ordered fold): state, contact set and
-    history, over a delayed schedule on two streams."""
+    history, over a delayed schedule on two streams; with its history
+    writes staged per wave in LDS (path 2), not staged (3) and staged as
+    the last contact count says (0)."""
     import torch
     s = _fused_case(name)
     out = []
-    for path in (0, 1):
-        c = dem.DemContext(s, mode="fixed", k=5, lam=2, dyn_path=path)
+    for path in (1, 0, 2, 3):
+        c = dem.DemContext(s, mode="fixed", k=5, lam=2, dyn_path=path, capacity=64 * s.n_spheres)
         c.set_state()
         c.step(120, dyn=torch.cuda.Stream(), kin=torch.cuda.Stream())
         g = c.get_state()
         keys, hist = c.get_contacts()
         out.append((g, keys, hist))
         c.close()
-    (ga, ka, ha), (gb, kb, hb) = out
+    ga, ka, ha = out[0]
     assert ka.size > 0
-    for k in ("X", "V", "W", "q"):
-        np.testing.assert_array_equal(ga[k], gb[k])
-    np.testing.assert_array_equal(ka, kb)
-    np.testing.assert_array_equal(ha, hb)
+    if name == "wide_margin":
+        assert ka.size > 15 * s.n_spheres
+    for gb, kb, hb in out[1:]:
+        for k in ("X", "V", "W", "q"):
+            np.testing.assert_array_equal(ga[k], gb[k])
+        np.testing.assert_array_equal(ka, kb)
+        np.testing.assert_array_equal(ha, hb)
 
 
 def test_delayed_equals_every_step_bitwise(dem):
