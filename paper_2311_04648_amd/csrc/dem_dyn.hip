@@ -589,7 +589,7 @@ struct OwnerStep {
 
 // The contact part of one owner's step (see k_step_fused): the sums F, T of
 // the forces and torques on it, its rows' new history put through ho.
-template <bool SINGLES, bool FACETS, bool FIXED>
+template <bool SINGLES, bool FACETS, bool FIXED, bool AHEAD>
 __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, const uint32_t *start,
     const uint32_t *jarr, const uint32_t *bstart, const uint32_t *bidx, const uint32_t *bsrc, const uint8_t *oany,
     const uint8_t fl_fixed, const float *hx, const float *hy, const float *hz, const float *hw, const HistOut &ho,
@@ -641,20 +641,37 @@ __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, 
                 owner_kin(r, sS, a.aux, a.q, a.tpos, a.org, kS, xS);
             }
             // one loop over the sphere's A row, then its B list: each item is
-            // evaluated from its A side by the same function
+            // evaluated from its A side by the same function.  An item's
+            // indices (contact index; partner on the A side, source sphere on
+            // the B side) are loaded one item ahead (AHEAD), so that an item
+            // waits for one round trip to memory (its other sphere's records),
+            // not two; the variant for sparse sets of single spheres, whose
+            // registers are at the limit of 4 waves per SIMD, loads them when
+            // it reaches the item.
             float3 FA = f3(0.f, 0.f, 0.f), TA = f3(0.f, 0.f, 0.f);
+            uint32_t nj = 0, nc = 0;
+            auto fetch = [&](uint32_t t) {
+                if (t < na) {
+                    nc = c0 + t;
+                    nj = jarr[nc];
+                } else {
+                    const uint32_t b = b0 + (t - na);
+                    nc = bidx[b];
+                    nj = bsrc[b];
+                }
+            };
+            if (AHEAD && nall > 0) fetch(0);
             for (uint32_t t = 0; t < nall; ++t) {
                 const bool aside = t < na;
+                if (!AHEAD) fetch(t);
+                const uint32_t c = nc, jt = nj;
+                if (AHEAD && t + 1 < nall) fetch(t + 1);
                 ContactOut co;
-                uint32_t c;
                 if constexpr (SINGLES) {
                     if (aside) {
-                        c = c0 + t;
-                        contact_eval<FACETS, false, true>(a, sS, kS, xS, jarr[c], HistIn{hx, hy, hz, hw, c}, co);
+                        contact_eval<FACETS, false, true>(a, sS, kS, xS, jt, HistIn{hx, hy, hz, hw, c}, co);
                     } else {
-                        const uint32_t b = b0 + (t - na);
-                        c = bidx[b];
-                        const uint32_t iA = bsrc[b];
+                        const uint32_t iA = jt;
                         // (owner index == sphere index: both loads at once)
                         const SphRec sA = load_sph(a.sph + iA);
                         const OwnerRec rA = load_rec(a.rec + iA);
@@ -665,17 +682,7 @@ __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, 
                                                   &sS, &kS, xS);
                     }
                 } else {
-                    uint32_t iA, jp;
-                    if (aside) {
-                        c = c0 + t;
-                        iA = s;
-                        jp = jarr[c];
-                    } else {
-                        const uint32_t b = b0 + (t - na);
-                        c = bidx[b];
-                        iA = bsrc[b];
-                        jp = s;
-                    }
+                    const uint32_t iA = aside ? s : jt, jp = aside ? jt : s;
                     const SphRec sA = load_sph(a.sph + iA);
                     const OwnerRec rA = load_rec(a.rec + sA.owner);
                     OwnerKin kA;
@@ -773,7 +780,7 @@ __device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, f
     OwnerStep st;
     st.advance = false;
     if (valid)
-        owner_forces<SINGLES, FACETS, FIXED>(a, o, start, jarr, bstart, bidx, bsrc, oany, 0, hx, hy, hz, hw, ho, st);
+        owner_forces<SINGLES, FACETS, FIXED, STAGE || FACETS || !SINGLES>(a, o, start, jarr, bstart, bidx, bsrc, oany, 0, hx, hy, hz, hw, ho, st);
     const uint32_t n = c_end - ho.c0 < HIST_STAGE ? c_end - ho.c0 : HIST_STAGE;
     if (STAGE && n > 0) {
         // every staged entry was put by some lane of this wave.  The LDS
@@ -834,7 +841,7 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
         const HistOut ho{ox, oy, oz, ow, nullptr, 0u};
         for (int64_t o = o0; o < No; o += stride) {
             OwnerStep st;
-            owner_forces<SINGLES, FACETS, FIXED>(a, o, start, jarr, bstart, bidx, bsrc, oany, oany[o], hx, hy, hz,
+            owner_forces<SINGLES, FACETS, FIXED, STAGE || FACETS || !SINGLES>(a, o, start, jarr, bstart, bidx, bsrc, oany, oany[o], hx, hy, hz,
                                                  hw, ho, st);
             if (st.advance) v2 = fmaxf(v2, owner_advance<SINGLES>(a, o, st, rec_out, q_out, ctr));
         }
