@@ -15,12 +15,51 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
+#include <functional>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 constexpr int64_t POSE_RING = 512, POSE_CHUNK = 256;
+
+// A host thread that enqueues the detection-stream part of each work order
+// (its wait for the work-order event and a dozen launches), so that the
+// thread driving the dynamics stream keeps that stream fed meanwhile: the
+// paper, too, drives its kinematic and dynamic parts from separate host
+// threads (Sec. 2.1).  One job at a time; the dynamics thread waits for the
+// job to be enqueued (kin_join) before anything that depends on it.
+struct KinWorker {
+    std::thread th;
+    std::mutex m;
+    std::condition_variable cv;
+    std::function<void()> job;
+    bool busy = false, quit = false;
+    hipError_t err = hipSuccess;   // first launch error of a job since the last join
+    int device = 0;
+};
+
+static void kin_loop(KinWorker *w)
+{
+    hipSetDevice(w->device);
+    std::unique_lock<std::mutex> lk(w->m);
+    for (;;) {
+        w->cv.wait(lk, [w] { return w->quit || static_cast<bool>(w->job); });
+        if (!w->job) return;
+        std::function<void()> job = std::move(w->job);
+        w->job = nullptr;
+        lk.unlock();
+        job();
+        const hipError_t e = hipGetLastError();
+        lk.lock();
+        if (e != hipSuccess && w->err == hipSuccess) w->err = e;
+        w->busy = false;
+        w->cv.notify_all();
+    }
+}
 
 struct dem_ctx {
     std::string err;
@@ -109,6 +148,8 @@ struct dem_ctx {
     int64_t pend_swap = 0, next_wo = 0, last_wo = 0;
     int pend_buf = 1;
     hipEvent_t ev_wo = nullptr, ev_cd = nullptr;
+    KinWorker *kw = nullptr;   // started at the first work order on a separate detection stream
+    bool cdk_zeroed = false;   // cdK's bin counts hold zeros (each work order's back part leaves them so)
     // adaptive schedule: per work-order cycle, timing events at the work
     // order (dynamics stream), at the end of its detection (detection
     // stream) and at its adoption step before the wait (dynamics stream)
@@ -253,6 +294,7 @@ void carve(Carver &c, dem_ctx *ctx, int64_t cap)
     ctx->sb.cap = cap;
     ctx->d_blkmax = c.take<float>((No + 255) / 256 + 1);
     carve_cd(c, ctx, ctx->cdK);
+    ctx->cdk_zeroed = false;
     carve_cd(c, ctx, ctx->cdD);
     ctx->ctr = c.take<DevCounters>(1);
     ctx->ncell_cap = (int64_t)ctx->fgrid.nbins;
@@ -514,6 +556,53 @@ void drain_all(dem_ctx *ctx)
 {
     for (auto &p : ctx->ring) drain_pair(ctx, p);
 }
+
+// Hands a job to the detection-stream thread (started on first use, with
+// the caller's current device).  The previous job must have been joined.
+void kin_post(dem_ctx *ctx, std::function<void()> job)
+{
+    if (!ctx->kw) {
+        ctx->kw = new KinWorker;
+        hipGetDevice(&ctx->kw->device);
+        ctx->kw->th = std::thread(kin_loop, ctx->kw);
+    }
+    std::lock_guard<std::mutex> lk(ctx->kw->m);
+    ctx->kw->job = std::move(job);
+    ctx->kw->busy = true;
+    ctx->kw->cv.notify_all();
+}
+
+// Waits until the posted job, if any, has been enqueued; returns the first
+// launch error of the jobs since the last join.
+hipError_t kin_join(dem_ctx *ctx)
+{
+    if (!ctx->kw) return hipSuccess;
+    std::unique_lock<std::mutex> lk(ctx->kw->m);
+    ctx->kw->cv.wait(lk, [ctx] { return !ctx->kw->busy; });
+    const hipError_t e = ctx->kw->err;
+    ctx->kw->err = hipSuccess;
+    return e;
+}
+
+void kin_stop(dem_ctx *ctx)
+{
+    if (!ctx->kw) return;
+    kin_join(ctx);
+    {
+        std::lock_guard<std::mutex> lk(ctx->kw->m);
+        ctx->kw->quit = true;
+        ctx->kw->cv.notify_all();
+    }
+    ctx->kw->th.join();
+    delete ctx->kw;
+    ctx->kw = nullptr;
+}
+
+// Joins the detection-stream thread when dem_step returns, by any path.
+struct KinJoinGuard {
+    dem_ctx *ctx;
+    ~KinJoinGuard() { kin_join(ctx); }
+};
 
 }  // namespace
 
@@ -817,8 +906,10 @@ dem_status dem_bind(dem_ctx *ctx, void *device_workspace, int64_t bytes, int64_t
         memset(ctx->h_ctr, 0, sizeof(DevCounters));
     }
     if (!ctx->h_pred) HIPCHK(hipHostMalloc((void **)&ctx->h_pred, 64));
-    if (!ctx->ev_wo) HIPCHK(hipEventCreateWithFlags(&ctx->ev_wo, hipEventDisableTiming));
-    if (!ctx->ev_cd) HIPCHK(hipEventCreateWithFlags(&ctx->ev_cd, hipEventDisableTiming));
+    // (the work-order events order two streams of one device: no
+    // system-scope release is needed at their records)
+    if (!ctx->ev_wo) HIPCHK(hipEventCreateWithFlags(&ctx->ev_wo, hipEventDisableTiming | hipEventDisableSystemFence));
+    if (!ctx->ev_cd) HIPCHK(hipEventCreateWithFlags(&ctx->ev_cd, hipEventDisableTiming | hipEventDisableSystemFence));
     if (!ctx->h_capped) HIPCHK(hipHostMalloc((void **)&ctx->h_capped, 4 * sizeof(uint32_t)));
     if (ctx->NM > 0) {
         if (ctx->h_pose_stage) HIPCHK(hipHostFree(ctx->h_pose_stage));
@@ -1322,6 +1413,9 @@ static void adapt_latency(dem_ctx *ctx)
 static int64_t issue_work_order(dem_ctx *ctx, hipStream_t dyn, hipStream_t kin, int64_t n)
 {
     const dem_params &P = ctx->P;
+    // the previous order's detection-stream part is enqueued (its workspace
+    // and events are reused here)
+    kin_join(ctx);
     if (P.cd_mode == DEM_CD_LEARNED) {
         // the learned interval measures the next features against this state
         hipMemcpyAsync(ctx->fref_rec, ctx->rec, sizeof(OwnerRec) * ctx->No, hipMemcpyDeviceToDevice, dyn);
@@ -1351,6 +1445,10 @@ static int64_t issue_work_order(dem_ctx *ctx, hipStream_t dyn, hipStream_t kin, 
     // the work order: the first binning kernel reads the state of step n on
     // the dynamics stream (centres, bin keys and candidate records are the
     // snapshot); the rest of the detection runs on the detection stream
+    if (!ctx->cdk_zeroed) {
+        launch_zero3(ctx->cdK.cell_count, (int64_t)ctx->grid.nbins + 1, nullptr, 0, nullptr, 0, dyn);
+        ctx->cdk_zeroed = true;
+    }
     auto *tf = stage_begin(ctx, 2, dyn);
     launch_detect_front(a, ctx->cdK, ctx->acs[target], dyn);
     if (tf) {
@@ -1358,12 +1456,21 @@ static int64_t issue_work_order(dem_ctx *ctx, hipStream_t dyn, hipStream_t kin, 
         tf->count = 0;   // one detection is counted once, with its back part
     }
     hipEventRecord(ctx->ev_wo, dyn);
-    hipStreamWaitEvent(kin, ctx->ev_wo, 0);
-    auto *tp = stage_begin(ctx, 2, kin);
-    launch_detect_back(a, ctx->cdK, ctx->acs[target], ctx->cap, ctx->ctr, target, kin);
-    stage_end(tp, kin);
-    if (cy) hipEventRecord(cy->cd, kin);
-    hipEventRecord(ctx->ev_cd, kin);
+    auto *tp = stage_slot(ctx, 2);
+    auto back = [ctx, a, target, kin, tp, cy]() {
+        hipStreamWaitEvent(kin, ctx->ev_wo, 0);
+        if (tp) hipEventRecord(tp->a, kin);
+        launch_detect_back(a, ctx->cdK, ctx->acs[target], ctx->cap, ctx->ctr, target, kin);
+        if (tp) hipEventRecord(tp->b, kin);
+        if (cy) hipEventRecord(cy->cd, kin);
+        hipEventRecord(ctx->ev_cd, kin);
+    };
+    // on a separate detection stream the launches go out from the other
+    // host thread; on one stream they must keep their place in its order
+    if (kin != dyn)
+        kin_post(ctx, back);
+    else
+        back();
     ctx->pending = true;
     ctx->pend_buf = target;
     ctx->pend_swap = n + lam;
@@ -1382,6 +1489,7 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
     }
     ARGCHK(n_steps >= 0, "n_steps must be >= 0");
     hipStream_t dyn = S(dyn_), kin = kin_ ? S(kin_) : dyn;
+    KinJoinGuard kin_guard{ctx};
     auto t0 = std::chrono::steady_clock::now();
     const dem_params &P = ctx->P;
     int64_t cds = 0, swaps = 0, misses = 0, repairs = 0;
@@ -1425,7 +1533,10 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
             ++swaps;
         } else {
             if (!ctx->sched_init) {
-                if (ctx->pending) hipStreamWaitEvent(dyn, ctx->ev_cd, 0);
+                if (ctx->pending) {
+                    kin_join(ctx);
+                    hipStreamWaitEvent(dyn, ctx->ev_cd, 0);
+                }
                 int target = 1 - ctx->cur;
                 dem_status st = detect_now(ctx, P.margin, dyn, target);
                 if (st != DEM_OK) return st;
@@ -1464,7 +1575,10 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
                     hipEventRecord(c.adopt, dyn);
                     c.adopted = true;
                 }
-                if (swap_due) hipStreamWaitEvent(dyn, ctx->ev_cd, 0);
+                if (swap_due) {
+                    kin_join(ctx);
+                    hipStreamWaitEvent(dyn, ctx->ev_cd, 0);
+                }
                 if (P.judge) {
                     int cand = swap_due ? ctx->pend_buf : ctx->cur;
                     launch_fill_u32(&ctx->ctr->miss, 1, 0u, dyn);
@@ -1481,7 +1595,10 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
                             result = DEM_ERR_MISSED;
                             break;
                         }
-                        if (ctx->pending && !swap_due) hipStreamWaitEvent(dyn, ctx->ev_cd, 0);
+                        if (ctx->pending && !swap_due) {
+                            kin_join(ctx);
+                            hipStreamWaitEvent(dyn, ctx->ev_cd, 0);
+                        }
                         int target = 1 - ctx->cur;
                         st = detect_now(ctx, P.margin, dyn, target);
                         if (st != DEM_OK) return st;
@@ -1593,6 +1710,7 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
         launch_reduce_max(da, ctx->ctr, dyn);
     }
     HIPCHK(hipGetLastError());
+    HIPCHK(kin_join(ctx));
     if (kin != dyn) HIPCHK(hipStreamSynchronize(kin));
     dem_status st = read_counters(ctx, dyn);
     if (st != DEM_OK) return st;
@@ -1637,6 +1755,7 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
 void dem_destroy(dem_ctx *ctx)
 {
     if (!ctx) return;
+    kin_stop(ctx);
     if (ctx->h_ctr) hipHostFree(ctx->h_ctr);
     if (ctx->h_pred) hipHostFree(ctx->h_pred);
     if (ctx->ev_wo) hipEventDestroy(ctx->ev_wo);

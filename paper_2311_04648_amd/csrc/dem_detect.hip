@@ -960,10 +960,13 @@ inline unsigned facet_walk_blocks(const DetectArgs &a)
     return (unsigned)std::min<int64_t>(1024, std::max<int64_t>(64, ((int64_t)a.n_tri + 3) / 4));
 }
 
+// One kernel: the bin counts are zero on entry (left so by the back part),
+// and the per-sphere counters are zeroed by the back part on its own
+// stream, so the stream that owns the state runs no more than it must.
 void launch_detect_front(const DetectArgs &a, CdWork &w, AcsBuf &out, hipStream_t s)
 {
-    const int64_t n = a.n_spheres;
-    launch_bin_front(a, w, s, out.bcur, n + 1, w.count, n + 1);
+    hipLaunchKernelGGL(k_cd_prepare, dim3(nblocks(a.n_spheres)), dim3(TPB), 0, s, a, w.keys,
+                       w.sort_mode == 0 ? (uint32_t *)nullptr : w.vals, w.cand_tmp, w.cell_count);
 }
 
 void launch_owner_flags(AcsBuf &b, const uint32_t *own_sph0, int64_t no, int64_t ns, int64_t cap,
@@ -976,6 +979,8 @@ void launch_owner_flags(AcsBuf &b, const uint32_t *own_sph0, int64_t no, int64_t
 void launch_detect(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap, DevCounters *ctr, int buf,
                    hipStream_t s)
 {
+    // (w may come from other uses that leave the bin counts set)
+    launch_zero3(w.cell_count, (int64_t)a.grid.nbins + 1, nullptr, 0, nullptr, 0, s);
     launch_detect_front(a, w, out, s);
     launch_detect_back(a, w, out, cap, ctr, buf, s);
 }
@@ -984,6 +989,7 @@ void launch_detect_back(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap
                         hipStream_t s)
 {
     int64_t n = a.n_spheres;
+    launch_zero3(out.bcur, n + 1, w.count, n + 1, nullptr, 0, s);
     launch_bin_back(a, w, s, false);
     hipLaunchKernelGGL(k_detect_stage, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,
                        (const float4 *)w.candf, w.cell_start, w.count, w.stage, out.bcur);
@@ -1006,6 +1012,8 @@ void launch_detect_back(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap
     hipLaunchKernelGGL(k_blist_sort, dim3(nblocks(n)), dim3(TPB), 0, s, out.start, out.bstart, n, cap, out.bidx,
                        out.bsrc);
     launch_owner_flags(out, a.own_sph0, a.n_owners, n, cap, a.ofam, a.famfixed, s);
+    // the bin counts (dead since the scatter) zeroed for the next front
+    launch_zero3(w.cell_count, (int64_t)a.grid.nbins + 1, nullptr, 0, nullptr, 0, s);
 }
 
 void launch_judge(const DetectArgs &a_in, CdWork &w, const AcsBuf &cur, int64_t cap, DevCounters *ctr,

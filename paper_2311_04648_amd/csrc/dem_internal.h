@@ -233,8 +233,9 @@ void launch_bin(const DetectArgs &a, CdWork &w, hipStream_t s, uint32_t *z1 = nu
 void launch_detect(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap, DevCounters *ctr,
                    int buf, hipStream_t s);
 // the same in two parts: the front reads the owner state (centres, bin
-// keys, candidate records, bin counts); the back reads only what the front
-// wrote, so it may run on another stream after an event
+// keys, candidate records, bin counts; w.cell_count must hold zeros, as the
+// back leaves it); the back reads only what the front wrote, so it may run
+// on another stream after an event
 void launch_detect_front(const DetectArgs &a, CdWork &w, AcsBuf &out, hipStream_t s);
 void launch_detect_back(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap, DevCounters *ctr,
                         int buf, hipStream_t s);
