@@ -121,11 +121,21 @@ __global__ void __launch_bounds__(TPB) k_bucket_order(const uint32_t *cell_start
 
 // Candidate records in bin order, and their 16-byte FP32 copies for the
 // prefilter of the detection walk.
+// (z1, z2: optional per-sphere counters of the detection that follows,
+// n + 1 entries each, zeroed here rather than by a launch of their own)
 __global__ void __launch_bounds__(TPB) k_cand_gather(const uint32_t *vals, const Cand *cand_tmp,
                                                      Cand *cand, float4 *candf, Grid g, int64_t n,
-                                                     const uint32_t *cell_start)
+                                                     const uint32_t *cell_start, uint32_t *z1, uint32_t *z2)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (z1 && p < n) {
+        z1[p] = 0u;
+        z2[p] = 0u;
+        if (p == 0) {
+            z1[n] = 0u;
+            z2[n] = 0u;
+        }
+    }
     if (p >= n || p >= (int64_t)cell_start[g.nbins]) return;   // (dormant spheres sit after the binned ones)
     const Cand c = cand_tmp[vals[p]];
     cand[p] = c;
@@ -778,6 +788,45 @@ __global__ void __launch_bounds__(TPB) k_blist_sort(const uint32_t *start, const
     }
 }
 
+// The last kernel of a detection: the B lists of sphere t sorted (as
+// k_blist_sort), the flag of owner t (as k_owner_flags) and, striding over
+// the bins, the bin counts zeroed for the next detection's front.
+__global__ void __launch_bounds__(TPB) k_blist_finish(const uint32_t *start, const uint32_t *bstart, int64_t ns,
+                                                      int64_t cap, uint32_t *bidx, uint32_t *bsrc,
+                                                      const uint32_t *own_sph0, int64_t no, const uint8_t *ofam,
+                                                      const uint8_t *fixed, uint8_t *flag, uint32_t *cell_count,
+                                                      int64_t nz)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = t; k < nz; k += nthreads) cell_count[k] = 0u;
+    const bool over = (int64_t)start[ns] > cap;
+    if (t < ns && !over) {
+        const uint32_t b0 = bstart[t], b1 = bstart[t + 1];
+        for (uint32_t u0 = b0 + 1; u0 < b1; ++u0) {
+            const uint32_t v = bidx[u0], w = bsrc[u0];
+            uint32_t u = u0;
+            while (u > b0 && bidx[u - 1] > v) {
+                bidx[u] = bidx[u - 1];
+                bsrc[u] = bsrc[u - 1];
+                --u;
+            }
+            bidx[u] = v;
+            bsrc[u] = w;
+        }
+    }
+    if (t < no) {
+        const uint8_t fx = (fixed && fixed[ofam[t]]) ? 2 : 0;
+        if (over) {
+            flag[t] = fx;
+        } else {
+            const uint32_t s0 = own_sph0 ? own_sph0[t] : (uint32_t)t;
+            const uint32_t s1 = own_sph0 ? own_sph0[t + 1] : (uint32_t)t + 1u;
+            flag[t] = (uint8_t)(((start[s0] != start[s1] || bstart[s0] != bstart[s1]) ? 1 : 0) | fx);
+        }
+    }
+}
+
 // Per-owner contact flag of a set: 1 if any sphere of owner o has a row or
 // B-list entry (the spheres of an owner are consecutive, so their rows and
 // B lists are one range each); an overflowed set flags nothing.
@@ -906,7 +955,8 @@ void launch_bin_front(const DetectArgs &a, CdWork &w, hipStream_t s, uint32_t *z
 // With `order_bins` the ids inside each bin are put in ascending order (a
 // stable sort of (bin, id)); the detection does not need it: the pairs it
 // finds do not depend on the order of the candidates inside a bin.
-void launch_bin_back(const DetectArgs &a, CdWork &w, hipStream_t s, bool order_bins)
+void launch_bin_back(const DetectArgs &a, CdWork &w, hipStream_t s, bool order_bins, uint32_t *z1 = nullptr,
+                     uint32_t *z2 = nullptr)
 {
     int64_t n = a.n_spheres;
     const int64_t nb = (int64_t)a.grid.nbins;
@@ -926,7 +976,7 @@ void launch_bin_back(const DetectArgs &a, CdWork &w, hipStream_t s, bool order_b
     // candidate records in bin order (random 32-byte reads, coalesced writes;
     // moving the records in the scatter instead costs more: random writes)
     hipLaunchKernelGGL(k_cand_gather, dim3(nblocks(n)), dim3(TPB), 0, s, w.vals, w.cand_tmp, w.cand, w.candf,
-                       a.grid, n, (const uint32_t *)w.cell_start);
+                       a.grid, n, (const uint32_t *)w.cell_start, z1, z2);
 }
 
 void launch_bin(const DetectArgs &a, CdWork &w, hipStream_t s, uint32_t *z1, int64_t n1, uint32_t *z2,
@@ -989,8 +1039,8 @@ void launch_detect_back(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap
                         hipStream_t s)
 {
     int64_t n = a.n_spheres;
-    launch_zero3(out.bcur, n + 1, w.count, n + 1, nullptr, 0, s);
-    launch_bin_back(a, w, s, false);
+    // (the per-sphere counters out.bcur and w.count zeroed by the gather)
+    launch_bin_back(a, w, s, false, out.bcur, w.count);
     hipLaunchKernelGGL(k_detect_stage, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,
                        (const float4 *)w.candf, w.cell_start, w.count, w.stage, out.bcur);
     if (a.n_tri > 0) {
@@ -1009,11 +1059,11 @@ void launch_detect_back(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap
                        (const Cand *)w.cand, (const uint32_t *)w.cell_start, (const uint32_t *)out.start,
                        (const uint32_t *)w.stage, out.j, cap, out.bcur, out.bidx, out.bsrc,
                        (const FacetDev *)w.fac);
-    hipLaunchKernelGGL(k_blist_sort, dim3(nblocks(n)), dim3(TPB), 0, s, out.start, out.bstart, n, cap, out.bidx,
-                       out.bsrc);
-    launch_owner_flags(out, a.own_sph0, a.n_owners, n, cap, a.ofam, a.famfixed, s);
-    // the bin counts (dead since the scatter) zeroed for the next front
-    launch_zero3(w.cell_count, (int64_t)a.grid.nbins + 1, nullptr, 0, nullptr, 0, s);
+    // B lists sorted, owner flags, and the bin counts (dead since the
+    // scatter) zeroed for the next front, in one launch
+    hipLaunchKernelGGL(k_blist_finish, dim3(nblocks(std::max(n, a.n_owners))), dim3(TPB), 0, s, out.start,
+                       out.bstart, n, cap, out.bidx, out.bsrc, a.own_sph0, a.n_owners, a.ofam, a.famfixed, out.oany,
+                       w.cell_count, (int64_t)a.grid.nbins + 1);
 }
 
 void launch_judge(const DetectArgs &a_in, CdWork &w, const AcsBuf &cur, int64_t cap, DevCounters *ctr,
