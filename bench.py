@@ -328,7 +328,10 @@ def main():
 
     def path_bytes_per_step(rr):
         # algorithmic bytes of one step of the whole path: the dynamics
-        # kernel(s) every step, detection and remap once per detection
+        # kernel(s) every step, detection once per detection, and the remap
+        # pass once per detection in the two-kernel form (the fused step
+        # right after an adoption carries the history over itself, reading
+        # it for touching pairs only)
         s2 = rr["stats"]
         Cm, act = s2["mean_contacts"], rr["active"]
         if args.dyn_path != 1:
@@ -338,8 +341,9 @@ def main():
         else:
             dyn_b = (algorithmic_bytes("k_force", Ns, No, Cm, act, 0, passes)
                      + algorithmic_bytes("k_fold_integrate", Ns, No, Cm, act, 0, passes, clumps=Ns != No))
-        per_cd = (algorithmic_bytes("detect", Ns, No, Cm, act, rr["info"]["nbins"], passes, n_tri=n_tri)
-                  + algorithmic_bytes("k_remap", Ns, No, Cm, act, 0, passes))
+        per_cd = algorithmic_bytes("detect", Ns, No, Cm, act, rr["info"]["nbins"], passes, n_tri=n_tri)
+        if args.dyn_path == 1:
+            per_cd += algorithmic_bytes("k_remap", Ns, No, Cm, act, 0, passes)
         return dyn_b + per_cd * s2["cds"] / args.steps
 
     modes_out = {}

@@ -150,6 +150,8 @@ struct dem_ctx {
     hipEvent_t ev_wo = nullptr, ev_cd = nullptr;
     KinWorker *kw = nullptr;   // started at the first work order on a separate detection stream
     bool cdk_zeroed = false;   // cdK's bin counts hold zeros (each work order's back part leaves them so)
+    int rm_from = -1;          // set adopted before the next fused step without its history carried over:
+                               // the buffer to carry it from (-1: none)
     // adaptive schedule: per work-order cycle, timing events at the work
     // order (dynamics stream), at the end of its detection (detection
     // stream) and at its adoption step before the wait (dynamics stream)
@@ -414,6 +416,18 @@ DynArgs dyn_args(const dem_ctx *ctx, int64_t step)
     a.poses = nullptr;
     a.has_fixed = ctx->has_fixed ? 1 : 0;
     a.two_kernel = ctx->P.dyn_path == 1 ? 1 : 0;
+    a.rm_start = a.rm_j = nullptr;
+    a.rm_hx = a.rm_hy = a.rm_hz = a.rm_hw = nullptr;
+    a.rm_newbuf = ctx->cur;
+    if (ctx->rm_from >= 0) {
+        const AcsBuf &o = ctx->acs[ctx->rm_from];
+        a.rm_start = o.start;
+        a.rm_j = o.j;
+        a.rm_hx = o.hx;
+        a.rm_hy = o.hy;
+        a.rm_hz = o.hz;
+        a.rm_hw = o.hw;
+    }
     a.dense_rows = 0;
     if (ctx->P.dyn_path == 2) {
         a.dense_rows = 1;
@@ -598,11 +612,6 @@ void kin_stop(dem_ctx *ctx)
     ctx->kw = nullptr;
 }
 
-// Joins the detection-stream thread when dem_step returns, by any path.
-struct KinJoinGuard {
-    dem_ctx *ctx;
-    ~KinJoinGuard() { kin_join(ctx); }
-};
 
 }  // namespace
 
@@ -1076,8 +1085,13 @@ dem_status dem_bin(dem_ctx *ctx, dem_stream stream, uint32_t *sorted_keys, uint3
     return DEM_OK;
 }
 
+static void flush_remap(dem_ctx *ctx, hipStream_t s);
+
 static dem_status detect_now(dem_ctx *ctx, double margin, hipStream_t s, int target)
 {
+    // the buffer written here may be the one a deferred adoption still
+    // carries its history from
+    flush_remap(ctx, s);
     DetectArgs a = detect_args(ctx, margin, ctx->step);
     auto *tp = stage_begin(ctx, 2, s);
     launch_detect(a, ctx->cdD, ctx->acs[target], ctx->cap, ctx->ctr, target, s);
@@ -1086,11 +1100,31 @@ static dem_status detect_now(dem_ctx *ctx, double margin, hipStream_t s, int tar
     return DEM_OK;
 }
 
-static dem_status adopt(dem_ctx *ctx, int target, hipStream_t s)
+// Carries the history of a deferred adoption over now (k_remap).
+static void flush_remap(dem_ctx *ctx, hipStream_t s)
 {
+    if (ctx->rm_from < 0) return;
     auto *tp = stage_begin(ctx, 3, s);
-    launch_remap(ctx->acs[ctx->cur], ctx->acs[target], ctx->Ns, ctx->ctr, target, ctx->rolling ? 1 : 0, s);
+    launch_remap(ctx->acs[ctx->rm_from], ctx->acs[ctx->cur], ctx->Ns, ctx->ctr, ctx->cur, ctx->rolling ? 1 : 0, s);
     stage_end(tp, s);
+    ctx->rm_from = -1;
+}
+
+// Makes buffer `target` the set in use, its history carried over from the
+// set in use before.  With `defer` (dem_step, right before a fused step)
+// the carrying over is left to that step, which looks each touching pair's
+// history up in the previous set: one launch and its stream transitions
+// fewer per adoption.
+static dem_status adopt(dem_ctx *ctx, int target, hipStream_t s, bool defer = false)
+{
+    flush_remap(ctx, s);
+    if (defer && ctx->P.dyn_path != 1) {
+        ctx->rm_from = ctx->cur;
+    } else {
+        auto *tp = stage_begin(ctx, 3, s);
+        launch_remap(ctx->acs[ctx->cur], ctx->acs[target], ctx->Ns, ctx->ctr, target, ctx->rolling ? 1 : 0, s);
+        stage_end(tp, s);
+    }
     HIPCHK(hipGetLastError());
     ctx->cur = target;
     return DEM_OK;
@@ -1416,6 +1450,9 @@ static int64_t issue_work_order(dem_ctx *ctx, hipStream_t dyn, hipStream_t kin, 
     // the previous order's detection-stream part is enqueued (its workspace
     // and events are reused here)
     kin_join(ctx);
+    // the order's buffer may be the one a deferred adoption still carries
+    // its history from (an order at the adoption step)
+    flush_remap(ctx, dyn);
     if (P.cd_mode == DEM_CD_LEARNED) {
         // the learned interval measures the next features against this state
         hipMemcpyAsync(ctx->fref_rec, ctx->rec, sizeof(OwnerRec) * ctx->No, hipMemcpyDeviceToDevice, dyn);
@@ -1480,6 +1517,18 @@ static int64_t issue_work_order(dem_ctx *ctx, hipStream_t dyn, hipStream_t kin, 
     return lam;
 }
 
+// When dem_step returns, by any path: a deferred carrying over of history
+// is done, and the detection-stream thread joined.
+struct StepGuard {
+    dem_ctx *ctx;
+    hipStream_t dyn;
+    ~StepGuard()
+    {
+        flush_remap(ctx, dyn);
+        kin_join(ctx);
+    }
+};
+
 dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream kin_, dem_step_stats *stats)
 {
     if (!ctx) return DEM_ERR_ARG;
@@ -1489,7 +1538,7 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
     }
     ARGCHK(n_steps >= 0, "n_steps must be >= 0");
     hipStream_t dyn = S(dyn_), kin = kin_ ? S(kin_) : dyn;
-    KinJoinGuard kin_guard{ctx};
+    StepGuard guard{ctx, dyn};
     auto t0 = std::chrono::steady_clock::now();
     const dem_params &P = ctx->P;
     int64_t cds = 0, swaps = 0, misses = 0, repairs = 0;
@@ -1527,7 +1576,7 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
             int target = 1 - ctx->cur;
             dem_status st = detect_now(ctx, 0.0, dyn, target);
             if (st != DEM_OK) return st;
-            st = adopt(ctx, target, dyn);
+            st = adopt(ctx, target, dyn, true);
             if (st != DEM_OK) return st;
             ++cds;
             ++swaps;
@@ -1540,7 +1589,7 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
                 int target = 1 - ctx->cur;
                 dem_status st = detect_now(ctx, P.margin, dyn, target);
                 if (st != DEM_OK) return st;
-                st = adopt(ctx, target, dyn);
+                st = adopt(ctx, target, dyn, true);
                 if (st != DEM_OK) return st;
                 ++cds;
                 ++swaps;
@@ -1620,7 +1669,7 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
                     }
                 }
                 if (swap_due) {
-                    dem_status st = adopt(ctx, ctx->pend_buf, dyn);
+                    dem_status st = adopt(ctx, ctx->pend_buf, dyn, true);
                     if (st != DEM_OK) return st;
                     ctx->pending = false;
                     ++swaps;
@@ -1639,7 +1688,7 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
                         const int target = 1 - ctx->cur;
                         dem_status st = detect_now(ctx, P.margin, dyn, target);
                         if (st != DEM_OK) return st;
-                        st = adopt(ctx, target, dyn);
+                        st = adopt(ctx, target, dyn, true);
                         if (st != DEM_OK) return st;
                         hipMemcpyAsync(ctx->fref_rec, ctx->rec, sizeof(OwnerRec) * ctx->No,
                                        hipMemcpyDeviceToDevice, dyn);
@@ -1684,6 +1733,7 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
                 }
             }
             launch_step_fused(a, ctx->rec_alt, ctx->q_alt, ctx->acs[ctx->cur], ctx->cap, ctx->ctr, dyn);
+            ctx->rm_from = -1;   // (the step carried the history over)
             if (ctx->run && ++ctx->run_len == RUN_LAUNCHES) run_close(ctx, dyn);
             std::swap(ctx->rec, ctx->rec_alt);
             std::swap(ctx->q, ctx->q_alt);

@@ -90,11 +90,31 @@ __device__ inline float4 load_hist(const float *hx, const float *hy, const float
     return make_float4(hx[c], hy[c], hz[c], rolling ? hw[c] : 0.f);
 }
 
-// History arrays of a set and the contact's index in them.
+// History arrays of a set and the contact's index in them; with `os`
+// set, the arrays are those of the previous set (the step right after an
+// adoption) and the pair's history is found by partner `kj` in that set's
+// row of sphere `ki` (rows are sorted by partner; a pair it does not list
+// starts from zero).
 struct HistIn {
     const float *x, *y, *z, *w;
     uint32_t c;
+    const uint32_t *os = nullptr, *oj = nullptr;
+    uint32_t ki = 0, kj = 0;
 };
+
+__device__ inline float4 hist_get(const HistIn &h, int rolling)
+{
+    if (!h.os) return load_hist(h.x, h.y, h.z, h.w, h.c, rolling);
+    const uint32_t e = h.os[h.ki + 1];
+    uint32_t lo = h.os[h.ki], hi = e;
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (h.oj[mid] < h.kj) lo = mid + 1u;
+        else hi = mid;
+    }
+    if (lo < e && h.oj[lo] == h.kj) return load_hist(h.x, h.y, h.z, h.w, lo, rolling);
+    return make_float4(0.f, 0.f, 0.f, 0.f);
+}
 
 // One contact evaluated from the side of sphere A (the lower id of the pair
 // or the sphere of a sphere-wall pair): overlap and normal in FP64, the
@@ -240,7 +260,7 @@ __device__ __forceinline__ void contact_eval(const DynArgs &a, const SphRec &sA,
         out.h = make_float4(0.f, 0.f, 0.f, 0.f);
         return;
     }
-    const float4 hold = load_hist(hin.x, hin.y, hin.z, hin.w, hin.c, a.rolling);
+    const float4 hold = hist_get(hin, a.rolling);
     // contact point in the middle of the overlap; arms to both owner centres
     const double sc = radA - 0.5 * delta;
     double cp[3] = {xA[0] - sc * nrm[0], xA[1] - sc * nrm[1], xA[2] - sc * nrm[2]};
@@ -573,7 +593,8 @@ __global__ void __launch_bounds__(TPB) k_fold_integrate(DynArgs a, const uint32_
 // the set may hold sphere-facet contacts; FIXED: some owner is in a fixed
 // family; STAGE: the history of a wave's rows goes through LDS (sets with
 // many contacts per sphere; with few, looking up each wave's range costs
-// more than it saves).  Systems with clumps or meshes get
+// more than it saves); REMAP: the first step on a newly adopted set, which
+// reads the old history from the previous set (DynArgs::rm_*).  Systems with clumps or meshes get
 // 3 waves per SIMD: the clump rotation and the FP64 closest point would
 // otherwise spill registers to scratch inside the contact loop, which costs
 // more than the lost occupancy.
@@ -589,7 +610,7 @@ struct OwnerStep {
 
 // The contact part of one owner's step (see k_step_fused): the sums F, T of
 // the forces and torques on it, its rows' new history put through ho.
-template <bool SINGLES, bool FACETS, bool FIXED, bool AHEAD>
+template <bool SINGLES, bool FACETS, bool FIXED, bool AHEAD, bool REMAP>
 __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, const uint32_t *start,
     const uint32_t *jarr, const uint32_t *bstart, const uint32_t *bidx, const uint32_t *bsrc, const uint8_t *oany,
     const uint8_t fl_fixed, const float *hx, const float *hy, const float *hz, const float *hw, const HistOut &ho,
@@ -649,6 +670,23 @@ __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, 
             // registers are at the limit of 4 waves per SIMD, loads them when
             // it reaches the item.
             float3 FA = f3(0.f, 0.f, 0.f), TA = f3(0.f, 0.f, 0.f);
+            // the history of contact c (pair of spheres ki < kj, or sphere ki
+            // and wall / facet key kj); right after an adoption, looked up
+            // in the previous set
+            auto hin = [&](uint32_t c, uint32_t ki, uint32_t kj) {
+                HistIn h{hx, hy, hz, hw, c};
+                if (REMAP) {
+                    h.x = a.rm_hx;
+                    h.y = a.rm_hy;
+                    h.z = a.rm_hz;
+                    h.w = a.rm_hw;
+                    h.os = a.rm_start;
+                    h.oj = a.rm_j;
+                    h.ki = ki;
+                    h.kj = kj;
+                }
+                return h;
+            };
             uint32_t nj = 0, nc = 0;
             auto fetch = [&](uint32_t t) {
                 if (t < na) {
@@ -669,7 +707,7 @@ __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, 
                 ContactOut co;
                 if constexpr (SINGLES) {
                     if (aside) {
-                        contact_eval<FACETS, false, true>(a, sS, kS, xS, jt, HistIn{hx, hy, hz, hw, c}, co);
+                        contact_eval<FACETS, false, true>(a, sS, kS, xS, jt, hin(c, s, jt), co);
                     } else {
                         const uint32_t iA = jt;
                         // (owner index == sphere index: both loads at once)
@@ -678,7 +716,7 @@ __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, 
                         OwnerKin kA;
                         double xA[3];
                         owner_kin(rA, sA, a.aux, a.q, a.tpos, a.org, kA, xA);
-                        contact_eval<false, true>(a, sA, kA, xA, s, HistIn{hx, hy, hz, hw, c}, co,
+                        contact_eval<false, true>(a, sA, kA, xA, s, hin(c, iA, s), co,
                                                   &sS, &kS, xS);
                     }
                 } else {
@@ -688,7 +726,7 @@ __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, 
                     OwnerKin kA;
                     double xA[3];
                     owner_kin(rA, sA, a.aux, a.q, a.tpos, a.org, kA, xA);
-                    contact_eval<FACETS>(a, sA, kA, xA, jp, HistIn{hx, hy, hz, hw, c}, co);
+                    contact_eval<FACETS>(a, sA, kA, xA, jp, hin(c, iA, jp), co);
                 }
                 if (aside) {
                     put_hist(ho, c, co.h, a.rolling);
@@ -745,9 +783,18 @@ __device__ __forceinline__ void halt_owner(const DynArgs &a, const int64_t o, Ow
         // (a set that overflowed its capacity has no valid rows to copy)
         const uint32_t s0 = SINGLES ? (uint32_t)o : a.own_sph0[o];
         const uint32_t s1 = SINGLES ? (uint32_t)o + 1u : a.own_sph0[o + 1];
-        if ((int64_t)start[a.n_spheres] <= cap)
-            for (uint32_t c = start[s0]; c < start[s1]; ++c)
-                store_hist(ox, oy, oz, ow, c, load_hist(hx, hy, hz, hw, c, a.rolling), a.rolling);
+        if ((int64_t)start[a.n_spheres] <= cap) {
+            for (uint32_t s = s0; s < s1; ++s)
+                for (uint32_t c = start[s]; c < start[s + 1]; ++c) {
+                    HistIn h{hx, hy, hz, hw, c};
+                    if (a.rm_start) {
+                        // (right after an adoption: the history carried over
+                        // from the previous set, as k_remap would have)
+                        h = HistIn{a.rm_hx, a.rm_hy, a.rm_hz, a.rm_hw, c, a.rm_start, a.rm_j, s, jarr[c]};
+                    }
+                    store_hist(ox, oy, oz, ow, c, hist_get(h, a.rolling), a.rolling);
+                }
+        }
 }
 
 // The step of the (up to) 64 consecutive owners from ow of one wave (runs
@@ -755,7 +802,7 @@ __device__ __forceinline__ void halt_owner(const DynArgs &a, const int64_t o, Ow
 // lane of the wave takes part (the history range is written out by all of
 // them, before the owner records, so that the wait for the range's bounds
 // is not a wait for those stores).  Returns the lane's |v|^2.
-template <bool SINGLES, bool FACETS, bool FIXED, bool STAGE>
+template <bool SINGLES, bool FACETS, bool FIXED, bool STAGE, bool REMAP>
 __device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, float *lds, OwnerRec *rec_out, double *q_out,
     const uint32_t *start, const uint32_t *jarr, const uint32_t *bstart, const uint32_t *bidx, const uint32_t *bsrc,
     const uint8_t *oany, const float *hx, const float *hy, const float *hz, const float *hw, float *ox, float *oy,
@@ -780,7 +827,7 @@ __device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, f
     OwnerStep st;
     st.advance = false;
     if (valid)
-        owner_forces<SINGLES, FACETS, FIXED, STAGE || FACETS || !SINGLES>(a, o, start, jarr, bstart, bidx, bsrc, oany, 0, hx, hy, hz, hw, ho, st);
+        owner_forces<SINGLES, FACETS, FIXED, STAGE || FACETS || !SINGLES, REMAP>(a, o, start, jarr, bstart, bidx, bsrc, oany, 0, hx, hy, hz, hw, ho, st);
     const uint32_t n = c_end - ho.c0 < HIST_STAGE ? c_end - ho.c0 : HIST_STAGE;
     if (STAGE && n > 0) {
         // every staged entry was put by some lane of this wave.  The LDS
@@ -800,7 +847,7 @@ __device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, f
     return st.advance ? owner_advance<SINGLES>(a, o, st, rec_out, q_out, ctr) : 0.0f;
 }
 
-template <bool SINGLES, bool FACETS, bool FIXED, bool STAGE>
+template <bool SINGLES, bool FACETS, bool FIXED, bool STAGE, bool REMAP>
 __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fused(DynArgs a, OwnerRec *rec_out, double *q_out,
                                                     const uint32_t *start, const uint32_t *jarr,
                                                     const uint32_t *bstart, const uint32_t *bidx,
@@ -818,7 +865,11 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
     // every (grid size)-th owner, so dormant owners cost their flag byte and
     // not a thread each
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    if (stopped(ctr, a.step)) {
+    // right after an adoption, an overflowed new set stops the run (every
+    // block reads the same flag, so all of them halt)
+    const bool rm_over = REMAP && ctr->overflow[a.rm_newbuf] != 0u;
+    if (rm_over && o0 == 0) ctr->stop_cd = 1u;
+    if (rm_over || stopped(ctr, a.step)) {
         if constexpr (FIXED) {
             for (int64_t o = o0; o < No; o += stride) halt_owner<SINGLES>(a, o, rec_out, q_out, start, jarr, bstart, bidx, bsrc, oany, hx, hy, hz, hw, ox, oy, oz, ow, cap, ctr);
         } else if (o0 < No) {
@@ -841,12 +892,12 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
         const HistOut ho{ox, oy, oz, ow, nullptr, 0u};
         for (int64_t o = o0; o < No; o += stride) {
             OwnerStep st;
-            owner_forces<SINGLES, FACETS, FIXED, STAGE || FACETS || !SINGLES>(a, o, start, jarr, bstart, bidx, bsrc, oany, oany[o], hx, hy, hz,
+            owner_forces<SINGLES, FACETS, FIXED, STAGE || FACETS || !SINGLES, REMAP>(a, o, start, jarr, bstart, bidx, bsrc, oany, oany[o], hx, hy, hz,
                                                  hw, ho, st);
             if (st.advance) v2 = fmaxf(v2, owner_advance<SINGLES>(a, o, st, rec_out, q_out, ctr));
         }
     } else if (w0 < No) {
-        v2 = step_wave<SINGLES, FACETS, FIXED, STAGE>(a, w0, lds, rec_out, q_out, start, jarr, bstart, bidx, bsrc, oany, hx, hy, hz, hw, ox, oy, oz, ow, cap, ctr);
+        v2 = step_wave<SINGLES, FACETS, FIXED, STAGE, REMAP>(a, w0, lds, rec_out, q_out, start, jarr, bstart, bidx, bsrc, oany, hx, hy, hz, hw, ox, oy, oz, ow, cap, ctr);
     }
     block_max_v2(v2, a.blkmax + lb);
 }
@@ -933,20 +984,29 @@ void launch_force(const DynArgs &a, AcsBuf &cur, StepBufs &sb, DevCounters *ctr,
                           sb.cap, (const DevCounters *)ctr);
 }
 
+// The step kernel for the first step on a newly adopted set (REMAP: it
+// carries the history over from the previous set) or any other step.
+template <bool SINGLES, bool FACETS, bool FIXED, bool STAGE>
+decltype(&k_step_fused<true, false, false, false, false>) pick_remap(bool remap)
+{
+    return remap ? k_step_fused<SINGLES, FACETS, FIXED, STAGE, true> : k_step_fused<SINGLES, FACETS, FIXED, STAGE, false>;
+}
+
 void launch_step_fused(const DynArgs &a, OwnerRec *rec_out, double *q_out, const AcsBuf &cur, int64_t cap,
                        DevCounters *ctr, hipStream_t s)
 {
     // runs with fixed families (mostly dormant waves) never stage
-    decltype(&k_step_fused<true, false, false, false>) kern;
+    decltype(&k_step_fused<true, false, false, false, false>) kern;
+    const bool r = a.rm_start != nullptr;
     if (a.has_fixed)
-        kern = a.n_tri > 0 ? (a.has_clumps ? k_step_fused<false, true, true, false> : k_step_fused<true, true, true, false>)
-                           : (a.has_clumps ? k_step_fused<false, false, true, false> : k_step_fused<true, false, true, false>);
+        kern = a.n_tri > 0 ? (a.has_clumps ? pick_remap<false, true, true, false>(r) : pick_remap<true, true, true, false>(r))
+                           : (a.has_clumps ? pick_remap<false, false, true, false>(r) : pick_remap<true, false, true, false>(r));
     else if (a.dense_rows)
-        kern = a.n_tri > 0 ? (a.has_clumps ? k_step_fused<false, true, false, true> : k_step_fused<true, true, false, true>)
-                           : (a.has_clumps ? k_step_fused<false, false, false, true> : k_step_fused<true, false, false, true>);
+        kern = a.n_tri > 0 ? (a.has_clumps ? pick_remap<false, true, false, true>(r) : pick_remap<true, true, false, true>(r))
+                           : (a.has_clumps ? pick_remap<false, false, false, true>(r) : pick_remap<true, false, false, true>(r));
     else
-        kern = a.n_tri > 0 ? (a.has_clumps ? k_step_fused<false, true, false, false> : k_step_fused<true, true, false, false>)
-                           : (a.has_clumps ? k_step_fused<false, false, false, false> : k_step_fused<true, false, false, false>);
+        kern = a.n_tri > 0 ? (a.has_clumps ? pick_remap<false, true, false, false>(r) : pick_remap<true, true, false, false>(r))
+                           : (a.has_clumps ? pick_remap<false, false, false, false>(r) : pick_remap<true, false, false, false>(r));
     hipLaunchKernelGGL(kern, dim3(step_blocks(a)), dim3(TPB), 0, s, a, rec_out, q_out,
                        (const uint32_t *)cur.start, (const uint32_t *)cur.j, (const uint32_t *)cur.bstart,
                        (const uint32_t *)cur.bidx, (const uint32_t *)cur.bsrc, (const uint8_t *)cur.oany,

@@ -281,6 +281,14 @@ struct DynArgs {
     const MeshPose *poses;  // [MAX_MESHES] mesh poses at `step` (device memory; null without meshes)
     int32_t has_fixed;      // some owner is in a fixed family (its flag in AcsBuf::oany, bit 1)
     int32_t two_kernel;     // the step runs as force + fold kernels (one block per 256 owners)
+    // a set adopted right before this step whose history has not been
+    // carried over yet: the fused step reads the old history of each pair
+    // it finds touching from the previous set (rows rm_start / rm_j,
+    // history rm_h*), in place of k_remap; rm_start null: no such set.
+    // rm_newbuf: the adopted buffer (its overflow stops the step)
+    const uint32_t *rm_start, *rm_j;
+    const float *rm_hx, *rm_hy, *rm_hz, *rm_hw;
+    int32_t rm_newbuf;
     int32_t dense_rows;     // the last contact count read back was at least one per two spheres: the
                             // fused step stages its history writes in LDS (a choice of speed only:
                             // both variants give the same bits)
