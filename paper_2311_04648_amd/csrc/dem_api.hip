@@ -150,6 +150,13 @@ struct dem_ctx {
     hipEvent_t ev_wo = nullptr, ev_cd = nullptr;
     KinWorker *kw = nullptr;   // started at the first work order on a separate detection stream
     bool cdk_zeroed = false;   // cdK's bin counts hold zeros (each work order's back part leaves them so)
+    // a work order whose first binning step rides on the next fused step:
+    // what is left to enqueue after that step (the work-order event and the
+    // detection-stream part), and what the step needs (wo_args, wo_target)
+    bool wo_fused = false;
+    std::function<void()> wo_finish;
+    DetectArgs wo_args{};
+    int wo_target = 0;
     int rm_from = -1;          // set adopted before the next fused step without its history carried over:
                                // the buffer to carry it from (-1: none)
     // adaptive schedule: per work-order cycle, timing events at the work
@@ -427,6 +434,15 @@ DynArgs dyn_args(const dem_ctx *ctx, int64_t step)
         a.rm_hy = o.hy;
         a.rm_hz = o.hz;
         a.rm_hw = o.hw;
+    }
+    a.wo_grid = ctx->grid;
+    a.wo_keys = nullptr;
+    a.wo_cand = nullptr;
+    a.wo_count = nullptr;
+    if (ctx->wo_fused) {
+        a.wo_keys = ctx->cdK.keys;
+        a.wo_cand = ctx->cdK.cand_tmp;
+        a.wo_count = ctx->cdK.cell_count;
     }
     a.dense_rows = 0;
     if (ctx->P.dyn_path == 2) {
@@ -1486,13 +1502,19 @@ static int64_t issue_work_order(dem_ctx *ctx, hipStream_t dyn, hipStream_t kin, 
         launch_zero3(ctx->cdK.cell_count, (int64_t)ctx->grid.nbins + 1, nullptr, 0, nullptr, 0, dyn);
         ctx->cdk_zeroed = true;
     }
-    auto *tf = stage_begin(ctx, 2, dyn);
-    launch_detect_front(a, ctx->cdK, ctx->acs[target], dyn);
-    if (tf) {
-        stage_end(tf, dyn);
-        tf->count = 0;   // one detection is counted once, with its back part
+    // in single-sphere runs without fixed families (one-pass bin sort, fused
+    // dynamics) the binning step rides on the step of this iteration, which
+    // reads the same state: one launch and one pass over the state fewer
+    const bool fuse = !ctx->has_clumps && !ctx->has_fixed && ctx->cdK.sort_mode == 0 && P.dyn_path != 1 &&
+                      ctx->rm_from < 0;
+    if (!fuse) {
+        auto *tf = stage_begin(ctx, 2, dyn);
+        launch_detect_front(a, ctx->cdK, ctx->acs[target], dyn);
+        if (tf) {
+            stage_end(tf, dyn);
+            tf->count = 0;   // one detection is counted once, with its back part
+        }
     }
-    hipEventRecord(ctx->ev_wo, dyn);
     auto *tp = stage_slot(ctx, 2);
     auto back = [ctx, a, target, kin, tp, cy]() {
         hipStreamWaitEvent(kin, ctx->ev_wo, 0);
@@ -1504,10 +1526,21 @@ static int64_t issue_work_order(dem_ctx *ctx, hipStream_t dyn, hipStream_t kin, 
     };
     // on a separate detection stream the launches go out from the other
     // host thread; on one stream they must keep their place in its order
-    if (kin != dyn)
-        kin_post(ctx, back);
-    else
-        back();
+    auto finish = [ctx, dyn, kin, back]() {
+        hipEventRecord(ctx->ev_wo, dyn);
+        if (kin != dyn)
+            kin_post(ctx, back);
+        else
+            back();
+    };
+    if (fuse) {
+        ctx->wo_fused = true;
+        ctx->wo_finish = finish;
+        ctx->wo_args = a;
+        ctx->wo_target = target;
+    } else {
+        finish();
+    }
     ctx->pending = true;
     ctx->pend_buf = target;
     ctx->pend_swap = n + lam;
@@ -1517,13 +1550,26 @@ static int64_t issue_work_order(dem_ctx *ctx, hipStream_t dyn, hipStream_t kin, 
     return lam;
 }
 
-// When dem_step returns, by any path: a deferred carrying over of history
-// is done, and the detection-stream thread joined.
+// A work order left waiting for its step (dem_step returned before it):
+// its binning step runs as a kernel of its own, then the rest goes out.
+static void flush_work_order(dem_ctx *ctx, hipStream_t dyn)
+{
+    if (!ctx->wo_fused) return;
+    launch_detect_front(ctx->wo_args, ctx->cdK, ctx->acs[ctx->wo_target], dyn);
+    ctx->wo_fused = false;
+    ctx->wo_finish();
+    ctx->wo_finish = nullptr;
+}
+
+// When dem_step returns, by any path: a pending work order and a deferred
+// carrying over of history are done, and the detection-stream thread
+// joined.
 struct StepGuard {
     dem_ctx *ctx;
     hipStream_t dyn;
     ~StepGuard()
     {
+        flush_work_order(ctx, dyn);
         flush_remap(ctx, dyn);
         kin_join(ctx);
     }
@@ -1734,6 +1780,12 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
             }
             launch_step_fused(a, ctx->rec_alt, ctx->q_alt, ctx->acs[ctx->cur], ctx->cap, ctx->ctr, dyn);
             ctx->rm_from = -1;   // (the step carried the history over)
+            if (ctx->wo_fused) {
+                // (the step wrote the work order's binning)
+                ctx->wo_fused = false;
+                ctx->wo_finish();
+                ctx->wo_finish = nullptr;
+            }
             if (ctx->run && ++ctx->run_len == RUN_LAUNCHES) run_close(ctx, dyn);
             std::swap(ctx->rec, ctx->rec_alt);
             std::swap(ctx->q, ctx->q_alt);

@@ -41,15 +41,6 @@ inline unsigned nblocks(int64_t n, int t = TPB)
 
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-__device__ inline int bin_coord(double x, double lo, double inv_b, int n)
-{
-    double t = floor((x - lo) * inv_b);
-    int c;
-    if (!(t >= 0.0)) c = 0;
-    else if (t > (double)(n - 3)) c = n - 3;
-    else c = (int)t;
-    return c + 1;
-}
 
 __global__ void __launch_bounds__(TPB) k_cd_prepare(DetectArgs a, uint32_t *keys, uint32_t *vals,
                                                     Cand *cand_tmp, uint32_t *cell_count)
@@ -66,10 +57,7 @@ __global__ void __launch_bounds__(TPB) k_cd_prepare(DetectArgs a, uint32_t *keys
     if (!dorm) {
         OwnerRec r = load_rec(a.rec + s.owner);
         sphere_centre(r, s, a.q, a.tpos, a.org, x);
-        int cx = bin_coord(x[0], a.grid.lo[0], a.grid.inv_b, a.grid.nx);
-        int cy = bin_coord(x[1], a.grid.lo[1], a.grid.inv_b, a.grid.ny);
-        int cz = bin_coord(x[2], a.grid.lo[2], a.grid.inv_b, a.grid.nz);
-        key = ((uint32_t)cz * (uint32_t)a.grid.ny + (uint32_t)cy) * (uint32_t)a.grid.nx + (uint32_t)cx;
+        key = bin_key(a.grid, x);
     }
     wave_run_claim(cell_count, key, active && !dorm);
     if (!active) return;

@@ -189,6 +189,28 @@ __device__ inline void sphere_centre(const OwnerRec &r, const SphRec &s, const d
     x[2] = X2 + d[2];
 }
 
+// Bin of a coordinate along one axis: cells 1 .. n-2 hold the domain (0
+// and n-1 are an empty guard layer, so a 3x3x3 stencil never leaves the
+// grid); coordinates outside fall into the outermost inner cells.
+__device__ inline int bin_coord(double x, double lo, double inv_b, int n)
+{
+    double t = floor((x - lo) * inv_b);
+    int c;
+    if (!(t >= 0.0)) c = 0;
+    else if (t > (double)(n - 3)) c = n - 3;
+    else c = (int)t;
+    return c + 1;
+}
+
+// Bin key (x fastest) of a sphere centre.
+__device__ inline uint32_t bin_key(const Grid &g, const double *x)
+{
+    const int cx = bin_coord(x[0], g.lo[0], g.inv_b, g.nx);
+    const int cy = bin_coord(x[1], g.lo[1], g.inv_b, g.ny);
+    const int cz = bin_coord(x[2], g.lo[2], g.inv_b, g.nz);
+    return ((uint32_t)cz * (uint32_t)g.ny + (uint32_t)cy) * (uint32_t)g.nx + (uint32_t)cx;
+}
+
 __device__ inline void wall_point(const WallDev &w, int64_t step, double h, double *p)
 {
     double t = (double)step * h;

@@ -797,12 +797,38 @@ __device__ __forceinline__ void halt_owner(const DynArgs &a, const int64_t o, Ow
         }
 }
 
+// The work order's first binning step for owner o (= sphere o in single-
+// sphere runs) from the state r the step reads: bin key, candidate record,
+// and the bin counts (one claim per run of equal keys in the wave, so every
+// lane of the wave calls it).  The arithmetic of k_cd_prepare.
+__device__ __forceinline__ void wo_front(const DynArgs &a, const int64_t o, const bool valid, const OwnerRec &r,
+                                         const SphRec &sp)
+{
+    uint32_t key = a.wo_grid.nbins;
+    double x[3] = {0.0, 0.0, 0.0};
+    if (valid) {
+        sphere_centre(r, sp, a.q, a.tpos, a.org, x);
+        key = bin_key(a.wo_grid, x);
+    }
+    wave_run_claim(a.wo_count, key, valid);
+    if (valid) {
+        a.wo_keys[o] = key;
+        Cand c;
+        c.x = x[0];
+        c.y = x[1];
+        c.z = x[2];
+        c.r = sp.rad;
+        c.id = (uint32_t)o;
+        a.wo_cand[o] = c;
+    }
+}
+
 // The step of the (up to) 64 consecutive owners from ow of one wave (runs
 // without fixed families); every
 // lane of the wave takes part (the history range is written out by all of
 // them, before the owner records, so that the wait for the range's bounds
 // is not a wait for those stores).  Returns the lane's |v|^2.
-template <bool SINGLES, bool FACETS, bool FIXED, bool STAGE, bool REMAP>
+template <bool SINGLES, bool FACETS, bool FIXED, bool STAGE, bool REMAP, bool WO>
 __device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, float *lds, OwnerRec *rec_out, double *q_out,
     const uint32_t *start, const uint32_t *jarr, const uint32_t *bstart, const uint32_t *bidx, const uint32_t *bsrc,
     const uint8_t *oany, const float *hx, const float *hy, const float *hz, const float *hw, float *ox, float *oy,
@@ -812,6 +838,8 @@ __device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, f
     const uint32_t lane = threadIdx.x & 63u;
     const int64_t o = ow + lane;
     const bool valid = o < No;
+    SphRec spw{};
+    if (WO && valid) spw = load_sph(a.sph + o);
     // the range of the wave's rows, read here and used only once the rows
     // are evaluated (its loads overlap the owners')
     HistOut ho{ox, oy, oz, ohw, nullptr, 0u};
@@ -828,6 +856,8 @@ __device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, f
     st.advance = false;
     if (valid)
         owner_forces<SINGLES, FACETS, FIXED, STAGE || FACETS || !SINGLES, REMAP>(a, o, start, jarr, bstart, bidx, bsrc, oany, 0, hx, hy, hz, hw, ho, st);
+    // (st.r is still the state read, before this step's update)
+    if constexpr (WO) wo_front(a, o, valid, st.r, spw);
     const uint32_t n = c_end - ho.c0 < HIST_STAGE ? c_end - ho.c0 : HIST_STAGE;
     if (STAGE && n > 0) {
         // every staged entry was put by some lane of this wave.  The LDS
@@ -847,7 +877,7 @@ __device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, f
     return st.advance ? owner_advance<SINGLES>(a, o, st, rec_out, q_out, ctr) : 0.0f;
 }
 
-template <bool SINGLES, bool FACETS, bool FIXED, bool STAGE, bool REMAP>
+template <bool SINGLES, bool FACETS, bool FIXED, bool STAGE, bool REMAP, bool WO>
 __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fused(DynArgs a, OwnerRec *rec_out, double *q_out,
                                                     const uint32_t *start, const uint32_t *jarr,
                                                     const uint32_t *bstart, const uint32_t *bidx,
@@ -857,6 +887,7 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
                                                     int64_t cap, DevCounters *ctr)
 {
     static_assert(!(FIXED && STAGE), "runs with fixed families do not stage");
+    static_assert(!WO || (SINGLES && !FIXED && !REMAP), "work orders ride on single-sphere steps only");
     __shared__ float hst[STAGE ? TPB / 64 : 1][STAGE ? 4 * HIST_STAGE : 1];
     const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t o0 = (int64_t)lb * blockDim.x + threadIdx.x;
@@ -870,6 +901,19 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
     const bool rm_over = REMAP && ctr->overflow[a.rm_newbuf] != 0u;
     if (rm_over && o0 == 0) ctr->stop_cd = 1u;
     if (rm_over || stopped(ctr, a.step)) {
+        if constexpr (WO) {
+            // the work order's binning is still written (from the state
+            // carried over unchanged), so the detection chain reads a
+            // consistent snapshot
+            const bool v = o0 < No;
+            OwnerRec r{};
+            SphRec sp{};
+            if (v) {
+                r = load_rec(a.rec + o0);
+                sp = load_sph(a.sph + o0);
+            }
+            wo_front(a, o0, v, r, sp);
+        }
         if constexpr (FIXED) {
             for (int64_t o = o0; o < No; o += stride) halt_owner<SINGLES>(a, o, rec_out, q_out, start, jarr, bstart, bidx, bsrc, oany, hx, hy, hz, hw, ox, oy, oz, ow, cap, ctr);
         } else if (o0 < No) {
@@ -897,7 +941,7 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
             if (st.advance) v2 = fmaxf(v2, owner_advance<SINGLES>(a, o, st, rec_out, q_out, ctr));
         }
     } else if (w0 < No) {
-        v2 = step_wave<SINGLES, FACETS, FIXED, STAGE, REMAP>(a, w0, lds, rec_out, q_out, start, jarr, bstart, bidx, bsrc, oany, hx, hy, hz, hw, ox, oy, oz, ow, cap, ctr);
+        v2 = step_wave<SINGLES, FACETS, FIXED, STAGE, REMAP, WO>(a, w0, lds, rec_out, q_out, start, jarr, bstart, bidx, bsrc, oany, hx, hy, hz, hw, ox, oy, oz, ow, cap, ctr);
     }
     block_max_v2(v2, a.blkmax + lb);
 }
@@ -985,28 +1029,35 @@ void launch_force(const DynArgs &a, AcsBuf &cur, StepBufs &sb, DevCounters *ctr,
 }
 
 // The step kernel for the first step on a newly adopted set (REMAP: it
-// carries the history over from the previous set) or any other step.
+// carries the history over from the previous set), for a step that also
+// does a work order's first binning step (WO; single-sphere runs without
+// fixed families), or for any other step.
+using StepKernel = decltype(&k_step_fused<true, false, false, false, false, false>);
 template <bool SINGLES, bool FACETS, bool FIXED, bool STAGE>
-decltype(&k_step_fused<true, false, false, false, false>) pick_remap(bool remap)
+StepKernel pick_remap(bool remap, bool wo)
 {
-    return remap ? k_step_fused<SINGLES, FACETS, FIXED, STAGE, true> : k_step_fused<SINGLES, FACETS, FIXED, STAGE, false>;
+    if constexpr (SINGLES && !FIXED) {
+        if (wo && !remap) return k_step_fused<SINGLES, FACETS, FIXED, STAGE, false, true>;
+    }
+    return remap ? k_step_fused<SINGLES, FACETS, FIXED, STAGE, true, false>
+                 : k_step_fused<SINGLES, FACETS, FIXED, STAGE, false, false>;
 }
 
 void launch_step_fused(const DynArgs &a, OwnerRec *rec_out, double *q_out, const AcsBuf &cur, int64_t cap,
                        DevCounters *ctr, hipStream_t s)
 {
     // runs with fixed families (mostly dormant waves) never stage
-    decltype(&k_step_fused<true, false, false, false, false>) kern;
-    const bool r = a.rm_start != nullptr;
+    StepKernel kern;
+    const bool r = a.rm_start != nullptr, w = a.wo_keys != nullptr;
     if (a.has_fixed)
-        kern = a.n_tri > 0 ? (a.has_clumps ? pick_remap<false, true, true, false>(r) : pick_remap<true, true, true, false>(r))
-                           : (a.has_clumps ? pick_remap<false, false, true, false>(r) : pick_remap<true, false, true, false>(r));
+        kern = a.n_tri > 0 ? (a.has_clumps ? pick_remap<false, true, true, false>(r, w) : pick_remap<true, true, true, false>(r, w))
+                           : (a.has_clumps ? pick_remap<false, false, true, false>(r, w) : pick_remap<true, false, true, false>(r, w));
     else if (a.dense_rows)
-        kern = a.n_tri > 0 ? (a.has_clumps ? pick_remap<false, true, false, true>(r) : pick_remap<true, true, false, true>(r))
-                           : (a.has_clumps ? pick_remap<false, false, false, true>(r) : pick_remap<true, false, false, true>(r));
+        kern = a.n_tri > 0 ? (a.has_clumps ? pick_remap<false, true, false, true>(r, w) : pick_remap<true, true, false, true>(r, w))
+                           : (a.has_clumps ? pick_remap<false, false, false, true>(r, w) : pick_remap<true, false, false, true>(r, w));
     else
-        kern = a.n_tri > 0 ? (a.has_clumps ? pick_remap<false, true, false, false>(r) : pick_remap<true, true, false, false>(r))
-                           : (a.has_clumps ? pick_remap<false, false, false, false>(r) : pick_remap<true, false, false, false>(r));
+        kern = a.n_tri > 0 ? (a.has_clumps ? pick_remap<false, true, false, false>(r, w) : pick_remap<true, true, false, false>(r, w))
+                           : (a.has_clumps ? pick_remap<false, false, false, false>(r, w) : pick_remap<true, false, false, false>(r, w));
     hipLaunchKernelGGL(kern, dim3(step_blocks(a)), dim3(TPB), 0, s, a, rec_out, q_out,
                        (const uint32_t *)cur.start, (const uint32_t *)cur.j, (const uint32_t *)cur.bstart,
                        (const uint32_t *)cur.bidx, (const uint32_t *)cur.bsrc, (const uint8_t *)cur.oany,

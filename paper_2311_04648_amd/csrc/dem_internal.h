@@ -289,6 +289,14 @@ struct DynArgs {
     const uint32_t *rm_start, *rm_j;
     const float *rm_hx, *rm_hy, *rm_hz, *rm_hw;
     int32_t rm_newbuf;
+    // a work order whose first binning step rides on this step (single-
+    // sphere runs without fixed families): from the state it reads, the
+    // step also writes each sphere's bin key and candidate record and
+    // counts the bins, as k_cd_prepare would; wo_keys null: no such order
+    Grid wo_grid;
+    uint32_t *wo_keys;
+    Cand *wo_cand;
+    uint32_t *wo_count;
     int32_t dense_rows;     // the last contact count read back was at least one per two spheres: the
                             // fused step stages its history writes in LDS (a choice of speed only:
                             // both variants give the same bits)
