@@ -326,7 +326,11 @@ def main():
     roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
     rolling = bool(np.any(np.asarray(sysm.mat_crr) > 0))
 
-    def path_bytes_per_step(rr):
+    # single-sphere runs without fixed families: a delayed work order's
+    # binning step rides on the step kernel, which reads the state anyway
+    fused_front = (Ns == No and not bool(np.any(np.asarray(sysm.fam_fixed) > 0)) and args.dyn_path != 1)
+
+    def path_bytes_per_step(rr, mode):
         # algorithmic bytes of one step of the whole path: the dynamics
         # kernel(s) every step, detection once per detection, and the remap
         # pass once per detection in the two-kernel form (the fused step
@@ -342,6 +346,8 @@ def main():
             dyn_b = (algorithmic_bytes("k_force", Ns, No, Cm, act, 0, passes)
                      + algorithmic_bytes("k_fold_integrate", Ns, No, Cm, act, 0, passes, clumps=Ns != No))
         per_cd = algorithmic_bytes("detect", Ns, No, Cm, act, rr["info"]["nbins"], passes, n_tri=n_tri)
+        if fused_front and mode != "every":
+            per_cd -= 64 * Ns   # (the sphere and owner records are not read a second time)
         if args.dyn_path == 1:
             per_cd += algorithmic_bytes("k_remap", Ns, No, Cm, act, 0, passes)
         return dyn_b + per_cd * s2["cds"] / args.steps
@@ -349,7 +355,7 @@ def main():
     modes_out = {}
     for mode, rr in results.items():
         s2 = rr["stats"]
-        bps = path_bytes_per_step(rr)
+        bps = path_bytes_per_step(rr, mode)
         gbs = bps / (rr["seconds"] / args.steps) / 1e9
         modes_out[mode] = {"value": round(Ns * args.steps / rr["seconds"], 1),
                            "ms_per_step": round(1e3 * rr["seconds"] / args.steps, 5),
