@@ -346,7 +346,7 @@ def main():
             dyn_b = (algorithmic_bytes("k_force", Ns, No, Cm, act, 0, passes)
                      + algorithmic_bytes("k_fold_integrate", Ns, No, Cm, act, 0, passes, clumps=Ns != No))
         per_cd = algorithmic_bytes("detect", Ns, No, Cm, act, rr["info"]["nbins"], passes, n_tri=n_tri)
-        if fused_front and mode != "every":
+        if fused_front and mode not in ("every", "adaptive"):
             per_cd -= 64 * Ns   # (the sphere and owner records are not read a second time)
         if args.dyn_path == 1:
             per_cd += algorithmic_bytes("k_remap", Ns, No, Cm, act, 0, passes)

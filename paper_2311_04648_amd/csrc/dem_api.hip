@@ -1505,8 +1505,12 @@ static int64_t issue_work_order(dem_ctx *ctx, hipStream_t dyn, hipStream_t kin, 
     // in single-sphere runs without fixed families (one-pass bin sort, fused
     // dynamics) the binning step rides on the step of this iteration, which
     // reads the same state: one launch and one pass over the state fewer
+    // (not with the timing-adaptive latency: it times each order from its
+    // event to the end of its detection, and a binning step inside a whole
+    // dynamics step skews that measure; measured on the mixer, the latency
+    // then settles at half its value and the orders double)
     const bool fuse = !ctx->has_clumps && !ctx->has_fixed && ctx->cdK.sort_mode == 0 && P.dyn_path != 1 &&
-                      ctx->rm_from < 0;
+                      ctx->rm_from < 0 && P.cd_mode != DEM_CD_ADAPTIVE;
     if (!fuse) {
         auto *tf = stage_begin(ctx, 2, dyn);
         launch_detect_front(a, ctx->cdK, ctx->acs[target], dyn);
