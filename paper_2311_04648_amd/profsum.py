@@ -6,10 +6,11 @@
         bench runs its schedules one after another; they are told apart by
         the gaps between the dynamics-kernel launches)
     python -m paper_2311_04648_amd.profsum traffic <fetch.csv> <write.csv> <copy_fetch.csv> <copy_write.csv>
-                                                   <copy_bytes> <kernel> <source> <workload>
-        HBM bytes per launch of one kernel from FETCH_SIZE / WRITE_SIZE
-        counter runs, each scaled by what the same counter reads for a plain
-        copy of a known size (JSON on stdout)
+                                                   <copy_bytes> <kernel> <source> <workload> [<variant>]
+        HBM bytes per launch of one kernel (of one template variant of it,
+        named exactly as in the trace, when given) from FETCH_SIZE /
+        WRITE_SIZE counter runs, each scaled by what the same counter reads
+        for a plain copy of a known size (JSON on stdout)
 """
 from __future__ import annotations
 
@@ -68,8 +69,9 @@ def segments(trace_path, gap_ns=5e6, top=8):
     return "\n".join(out)
 
 
-def _counter(path, kernel=None):
-    """Mean counter value (KiB) per dispatch of a kernel, or of the largest
+def _counter(path, kernel=None, variant=None):
+    """Mean counter value (KiB) per dispatch of a kernel (of one template
+    variant of it when `variant` names one exactly), or of the largest
     dispatch when no kernel is named (the copy probe)."""
     vals = collections.defaultdict(float)
     names = {}
@@ -79,22 +81,25 @@ def _counter(path, kernel=None):
         names[key] = _name(r["Kernel_Name"])
     if kernel is None:
         return max(vals.values())
-    sel = [v for k, v in vals.items() if names[k].startswith(kernel)]
+    if variant:
+        sel = [v for k, v in vals.items() if names[k] == variant]
+    else:
+        sel = [v for k, v in vals.items() if names[k].startswith(kernel)]
     return sum(sel) / len(sel)
 
 
-def traffic(fetch, write, cfetch, cwrite, copy_bytes, kernel, source, workload):
+def traffic(fetch, write, cfetch, cwrite, copy_bytes, kernel, source, workload, variant=None):
     copy_bytes = float(copy_bytes)
     cf, cw = _counter(cfetch), _counter(cwrite)
     fs, ws = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
-    f, w = _counter(fetch, kernel), _counter(write, kernel)
+    f, w = _counter(fetch, kernel, variant), _counter(write, kernel, variant)
     here = os.path.dirname(os.path.abspath(__file__))
     sys.path.insert(0, os.path.dirname(here))
     from bench import kernel_sha
     return {
         "copy_probe": {"bytes_read": copy_bytes, "bytes_written": copy_bytes, "FETCH_SIZE_KiB": cf,
                        "WRITE_SIZE_KiB": cw, "fetch_scale": fs, "write_scale": ws},
-        kernel: {"source": source, "FETCH_SIZE_KiB": f, "WRITE_SIZE_KiB": w,
+        kernel: {"source": source, "variant": variant or kernel, "FETCH_SIZE_KiB": f, "WRITE_SIZE_KiB": w,
                  "bytes_per_launch": f * 1024.0 * fs + w * 1024.0 * ws, "workload": workload,
                  "kernel_sha": kernel_sha(os.path.join(here, "csrc", source), kernel)},
     }
@@ -106,7 +111,7 @@ def main(argv):
         if len(argv) > 2:
             print(segments(argv[2]))
     elif argv[0] == "traffic":
-        print(json.dumps(traffic(*argv[1:9]), indent=1))
+        print(json.dumps(traffic(*argv[1:10]), indent=1))
     else:
         raise SystemExit(__doc__)
 
