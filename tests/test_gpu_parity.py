@@ -506,6 +506,28 @@ def test_divergence_guard(dem, dyn_path):
     assert e.value.status == dem.DEM_ERR_DIVERGED
 
 
+def test_divergence_guard_on_the_delayed_schedule(dem):
+    """A run that diverges at its first step under the fixed-margin schedule
+    on two streams: the later steps (a work-order step, whose binning rides
+    on the halted step, and the first step on the adopted set, which carries
+    the history over) copy the state unchanged, and the run ends with the
+    state of the every-step run that diverges the same way."""
+    import torch
+    s = W.small_spheres(1, n=343, vel=0.5)
+    out = []
+    for mode in ("every", "fixed"):
+        ctx = dem.DemContext(s, mode=mode, k=3, lam=1, v_error_out=0.05)
+        ctx.set_state()
+        kw = dict(dyn=torch.cuda.Stream(), kin=torch.cuda.Stream()) if mode == "fixed" else {}
+        with pytest.raises(dem.DemError) as e:
+            ctx.step(12, **kw)
+        assert e.value.status == dem.DEM_ERR_DIVERGED
+        out.append(ctx.get_state())
+        ctx.close()
+    for k in ("X", "V", "W"):
+        np.testing.assert_array_equal(out[0][k], out[1][k])
+
+
 def test_count_missing_matches_oracle(dem):
     s = W.small_spheres(4, n=343, vel=1.0)
     ctx = dem.DemContext(s, mode="fixed", k=10, lam=0)
