@@ -173,7 +173,7 @@ def run_mode(dem, torch, sysm, mode, args, mlp=None, judge=False):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the path runs on one GPU only (no multi-GPU sharding is implemented); --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch

@@ -134,7 +134,7 @@ def calibrate(dem, p, X, T, win, K=K_CAP, margin=0.9):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default="gpurun_out/mlp_interval.json")
+    ap.add_argument("--out", default="mlp_interval_trained.json")
     ap.add_argument("--n1", type=int, default=100_000, help="spheres of the config-1 log runs")
     ap.add_argument("--n2", type=int, default=30_000, help="clumps of the config-2 log runs")
     ap.add_argument("--epochs", type=int, default=300)
