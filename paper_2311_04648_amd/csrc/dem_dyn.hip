@@ -20,6 +20,10 @@
 // offset, FP64 quaternion update by the exponential map for clumps.
 // Single spheres keep their angular velocity in the world frame (their
 // orientation has no physical effect).
+//
+// k_step_fused: the same step in one launch (one thread per owner, its
+// B-side contacts evaluated again from their A side), the default of
+// dem_step; see its comment below.
 #include "dem_device.h"
 
 #include <hip/hip_ext.h>
@@ -594,10 +598,12 @@ __global__ void __launch_bounds__(TPB) k_fold_integrate(DynArgs a, const uint32_
 // family; STAGE: the history of a wave's rows goes through LDS (sets with
 // many contacts per sphere; with few, looking up each wave's range costs
 // more than it saves); REMAP: the first step on a newly adopted set, which
-// reads the old history from the previous set (DynArgs::rm_*).  Systems with clumps or meshes get
-// 3 waves per SIMD: the clump rotation and the FP64 closest point would
-// otherwise spill registers to scratch inside the contact loop, which costs
-// more than the lost occupancy.
+// reads the old history from the previous set (DynArgs::rm_*); WO: a step
+// that also does a work order's first binning step (DynArgs::wo_*).
+// Systems with clumps or meshes get 3 waves per SIMD: the clump rotation
+// and the FP64 closest point would otherwise spill registers to scratch
+// inside the contact loop, which costs more than the lost occupancy.
+
 // What the contact part of an owner's step hands to its integration.
 struct OwnerStep {
     OwnerRec r;
