@@ -620,7 +620,7 @@ template <bool SINGLES, bool FACETS, bool FIXED, bool AHEAD, bool REMAP>
 __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, const uint32_t *start,
     const uint32_t *jarr, const uint32_t *bstart, const uint32_t *bidx, const uint32_t *bsrc, const uint8_t *oany,
     const uint8_t fl_fixed, const float *hx, const float *hy, const float *hz, const float *hw, const HistOut &ho,
-    OwnerStep &st)
+    OwnerStep &st, const OwnerRec *pre = nullptr)
 {
     st.advance = false;
     // The owner's flag byte, written with the set (bit 0: the owner has a
@@ -634,7 +634,7 @@ __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, 
         // record, the inertia, the orientation (clump systems) and (without
         // fixed families) the flag
         OwnerRec &r = st.r;
-        r = load_rec(a.rec + o);
+        r = pre ? *pre : load_rec(a.rec + o);
         st.tmpl = -1;
         st.qv = make_double4(1.0, 0.0, 0.0, 0.0);
         if (SINGLES) {
@@ -835,7 +835,7 @@ __device__ __forceinline__ void wo_front(const DynArgs &a, const int64_t o, cons
 // them, before the owner records, so that the wait for the range's bounds
 // is not a wait for those stores).  Returns the lane's |v|^2.
 template <bool SINGLES, bool FACETS, bool FIXED, bool STAGE, bool REMAP, bool WO>
-__device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, float *lds, OwnerRec *rec_out, double *q_out,
+__device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, uint4 *lrec, float *lds, OwnerRec *rec_out, double *q_out,
     const uint32_t *start, const uint32_t *jarr, const uint32_t *bstart, const uint32_t *bidx, const uint32_t *bsrc,
     const uint8_t *oany, const float *hx, const float *hy, const float *hz, const float *hw, float *ox, float *oy,
     float *oz, float *ohw, int64_t cap, DevCounters *ctr)
@@ -846,6 +846,25 @@ __device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, f
     const bool valid = o < No;
     SphRec spw{};
     if (WO && valid) spw = load_sph(a.sph + o);
+    // The wave's owner records (48 B each, 3 KiB together) move through LDS
+    // in three contiguous 1 KiB loads and stores: a lane's own record read
+    // as three 16-byte pieces at a 48-byte stride would touch every line of
+    // the range three times.  (With STAGE the slice is shared with the
+    // history staging, which is used only while the records sit in
+    // registers.)
+    const uint32_t nv = (uint32_t)(No - ow < 64 ? No - ow : 64);
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.rec + ow);
+        for (uint32_t k = lane; k < 3u * nv; k += 64u) lrec[k] = src[k];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    OwnerRec rpre{};
+    if (valid) rpre = load_rec(reinterpret_cast<const OwnerRec *>(lrec) + lane);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // the range of the wave's rows, read here and used only once the rows
     // are evaluated (its loads overlap the owners')
     HistOut ho{ox, oy, oz, ohw, nullptr, 0u};
@@ -861,7 +880,7 @@ __device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, f
     OwnerStep st;
     st.advance = false;
     if (valid)
-        owner_forces<SINGLES, FACETS, FIXED, STAGE || FACETS || !SINGLES, REMAP>(a, o, start, jarr, bstart, bidx, bsrc, oany, 0, hx, hy, hz, hw, ho, st);
+        owner_forces<SINGLES, FACETS, FIXED, STAGE || FACETS || !SINGLES, REMAP>(a, o, start, jarr, bstart, bidx, bsrc, oany, 0, hx, hy, hz, hw, ho, st, &rpre);
     // (st.r is still the state read, before this step's update)
     if constexpr (WO) wo_front(a, o, valid, st.r, spw);
     const uint32_t n = c_end - ho.c0 < HIST_STAGE ? c_end - ho.c0 : HIST_STAGE;
@@ -880,7 +899,25 @@ __device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, f
             if (a.rolling) ohw[wc0 + k] = lds[3 * HIST_STAGE + k];
         }
     }
-    return st.advance ? owner_advance<SINGLES>(a, o, st, rec_out, q_out, ctr) : 0.0f;
+    // the new records, through LDS again (after every lane is done with the
+    // slice's history entries)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float v2 = 0.0f;
+    if (st.advance) {
+        const bool rotating = !SINGLES && st.tmpl >= 0;
+        v2 = advance(a, st.r, st.inv, rotating, st.F, st.T, st.qv, q_out + 4 * (size_t)o, ctr);
+        store_rec(reinterpret_cast<OwnerRec *>(lrec) + lane, st.r);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    {
+        uint4 *dst = reinterpret_cast<uint4 *>(rec_out + ow);
+        for (uint32_t k = lane; k < 3u * nv; k += 64u) dst[k] = lrec[k];
+    }
+    return v2;
 }
 
 template <bool SINGLES, bool FACETS, bool FIXED, bool STAGE, bool REMAP, bool WO>
@@ -894,7 +931,8 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
 {
     static_assert(!(FIXED && STAGE), "runs with fixed families do not stage");
     static_assert(!WO || (SINGLES && !FIXED && !REMAP), "work orders ride on single-sphere steps only");
-    __shared__ float hst[STAGE ? TPB / 64 : 1][STAGE ? 4 * HIST_STAGE : 1];
+    // per wave: the staged history (STAGE) and the owner records, one slice
+    __shared__ uint4 wbuf[FIXED ? 1 : TPB / 64][FIXED ? 1 : (STAGE ? HIST_STAGE : 192)];
     const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t o0 = (int64_t)lb * blockDim.x + threadIdx.x;
     const int64_t No = a.n_owners;
@@ -935,7 +973,8 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
     float v2 = 0.0f;
     // the wave's index in the block, as a wave-uniform (scalar) value
     const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    float *lds = STAGE ? hst[wv] : nullptr;
+    uint4 *lrec = FIXED ? nullptr : wbuf[wv];
+    float *lds = STAGE ? reinterpret_cast<float *>(wbuf[wv]) : nullptr;
     const int64_t w0 = (int64_t)lb * blockDim.x + 64 * wv;
     if constexpr (FIXED) {
         // (no staging: the owners of a thread are not those of one wave)
@@ -947,7 +986,7 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
             if (st.advance) v2 = fmaxf(v2, owner_advance<SINGLES>(a, o, st, rec_out, q_out, ctr));
         }
     } else if (w0 < No) {
-        v2 = step_wave<SINGLES, FACETS, FIXED, STAGE, REMAP, WO>(a, w0, lds, rec_out, q_out, start, jarr, bstart, bidx, bsrc, oany, hx, hy, hz, hw, ox, oy, oz, ow, cap, ctr);
+        v2 = step_wave<SINGLES, FACETS, FIXED, STAGE, REMAP, WO>(a, w0, lrec, lds, rec_out, q_out, start, jarr, bstart, bidx, bsrc, oany, hx, hy, hz, hw, ox, oy, oz, ow, cap, ctr);
     }
     block_max_v2(v2, a.blkmax + lb);
 }
