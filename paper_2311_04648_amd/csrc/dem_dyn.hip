@@ -846,25 +846,27 @@ __device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, u
     const bool valid = o < No;
     SphRec spw{};
     if (WO && valid) spw = load_sph(a.sph + o);
-    // The wave's owner records (48 B each, 3 KiB together) move through LDS
-    // in three contiguous 1 KiB loads and stores: a lane's own record read
-    // as three 16-byte pieces at a 48-byte stride would touch every line of
-    // the range three times.  (With STAGE the slice is shared with the
-    // history staging, which is used only while the records sit in
-    // registers.)
+    // Single-sphere runs: the wave's owner records (48 B each, 3 KiB
+    // together) move through LDS in three contiguous 1 KiB loads and stores:
+    // a lane's own record read as three 16-byte pieces at a 48-byte stride
+    // would touch every line of the range three times.  (With STAGE the
+    // slice is shared with the history staging, which is used only while
+    // the records sit in registers.)  Clump runs load the record with the
+    // owner's other data (inertia, orientation), which would otherwise wait
+    // for it.
     const uint32_t nv = (uint32_t)(No - ow < 64 ? No - ow : 64);
-    {
+    OwnerRec rpre{};
+    if constexpr (SINGLES) {
         const uint4 *src = reinterpret_cast<const uint4 *>(a.rec + ow);
         for (uint32_t k = lane; k < 3u * nv; k += 64u) lrec[k] = src[k];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (valid) rpre = load_rec(reinterpret_cast<const OwnerRec *>(lrec) + lane);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    OwnerRec rpre{};
-    if (valid) rpre = load_rec(reinterpret_cast<const OwnerRec *>(lrec) + lane);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // the range of the wave's rows, read here and used only once the rows
     // are evaluated (its loads overlap the owners')
     HistOut ho{ox, oy, oz, ohw, nullptr, 0u};
@@ -880,7 +882,8 @@ __device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, u
     OwnerStep st;
     st.advance = false;
     if (valid)
-        owner_forces<SINGLES, FACETS, FIXED, STAGE || FACETS || !SINGLES, REMAP>(a, o, start, jarr, bstart, bidx, bsrc, oany, 0, hx, hy, hz, hw, ho, st, &rpre);
+        owner_forces<SINGLES, FACETS, FIXED, STAGE || FACETS || !SINGLES, REMAP>(a, o, start, jarr, bstart, bidx, bsrc, oany, 0, hx, hy, hz, hw, ho, st,
+                                                                                  SINGLES ? &rpre : nullptr);
     // (st.r is still the state read, before this step's update)
     if constexpr (WO) wo_front(a, o, valid, st.r, spw);
     const uint32_t n = c_end - ho.c0 < HIST_STAGE ? c_end - ho.c0 : HIST_STAGE;
@@ -899,6 +902,7 @@ __device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, u
             if (a.rolling) ohw[wc0 + k] = lds[3 * HIST_STAGE + k];
         }
     }
+    if constexpr (!SINGLES) return st.advance ? owner_advance<SINGLES>(a, o, st, rec_out, q_out, ctr) : 0.0f;
     // the new records, through LDS again (after every lane is done with the
     // slice's history entries)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -906,8 +910,7 @@ __device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, u
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     float v2 = 0.0f;
     if (st.advance) {
-        const bool rotating = !SINGLES && st.tmpl >= 0;
-        v2 = advance(a, st.r, st.inv, rotating, st.F, st.T, st.qv, q_out + 4 * (size_t)o, ctr);
+        v2 = advance(a, st.r, st.inv, false, st.F, st.T, st.qv, q_out + 4 * (size_t)o, ctr);
         store_rec(reinterpret_cast<OwnerRec *>(lrec) + lane, st.r);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
