@@ -257,7 +257,7 @@ def main():
     # timed live with HIP events on its stream; the detection chain (about 20
     # kernels on the second stream) is reported separately
     tot = st["stage_ms"]
-    dom = 0 if tot[0] >= tot[1] else 1
+    dom = 0 if tot[0] > tot[1] else 1
     n_launch = max(int(st["stage_n"][dom]), 1)
     avg_raw = tot[dom] / n_launch
     # every event pair around the dynamics kernel(s) is followed by an empty
@@ -279,18 +279,20 @@ def main():
     algo = algorithmic_bytes(stages[dom], Ns, No, C, r["active"], r["info"]["nbins"], passes,
                              clumps=Ns != No, rolling=bool(np.any(np.asarray(sysm.mat_crr) > 0)),
                              n_clump=n_clump, n_tri=n_tri, n_dormant=n_dormant, n_dormant_clump=n_dormant_clump)
-    achieved = algo / (avg_ms * 1e-3) / 1e9
+    timed = int(st["stage_n"][dom]) > 0    # (none with --timing 0)
+    achieved = algo / (avg_ms * 1e-3) / 1e9 if timed else None
     traffic = load_traffic(stages[dom], args.workload)
-    roofline = {"bound": "hbm", "kernel": stages[dom], "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "algorithmic_bytes_per_launch": int(algo), "avg_launch_ms": round(avg_ms, 5),
+    roofline = {"bound": "hbm", "kernel": stages[dom], "achieved": round(achieved, 2) if timed else None,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4) if timed else None,
+                "traffic": traffic,
+                "algorithmic_bytes_per_launch": int(algo), "avg_launch_ms": round(avg_ms, 5) if timed else None,
                 "event_interval_per_launch_ms": round(avg_raw, 5), "event_pair_overhead_ms": round(stamp_ms, 5),
                 "event_pairs": int(st["stage_n"][4]), "launches": n_launch}
     n_cd = max(int(st["stage_n"][2]), 1)
     cd_ms = tot[2] / n_cd
     cd_bytes = algorithmic_bytes("detect", Ns, No, C, r["active"], r["info"]["nbins"], passes, n_tri=n_tri)
     cd_chain = {"avg_ms": round(cd_ms, 4), "launches": n_cd, "algorithmic_bytes": int(cd_bytes),
-                "achieved_GBs": round(cd_bytes / (cd_ms * 1e-3) / 1e9, 1),
+                "achieved_GBs": round(cd_bytes / (cd_ms * 1e-3) / 1e9, 1) if cd_ms > 0 else None,
                 "note": "detection chain on the second stream, concurrent with the dynamics stream"}
 
     cpu = None
@@ -323,7 +325,7 @@ def main():
     copy_gbs = 2 * 4 * nb / (sorted(times)[len(times) // 2] * 1e-3) / 1e9
     del src, dst
     roofline["measured_copy_GBs"] = round(copy_gbs, 1)
-    roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    roofline["frac_of_copy"] = round(achieved / copy_gbs, 4) if timed else None
     rolling = bool(np.any(np.asarray(sysm.mat_crr) > 0))
 
     # single-sphere runs without fixed families: a delayed work order's
