@@ -11,6 +11,9 @@
         named exactly as in the trace, when given) from FETCH_SIZE /
         WRITE_SIZE counter runs, each scaled by what the same counter reads
         for a plain copy of a known size (JSON on stdout)
+    python -m paper_2311_04648_amd.profsum kernels <fetch.csv> <write.csv> <fetch_scale> <write_scale>
+        markdown table of the mean HBM bytes per launch of every kernel of a
+        run (FETCH_SIZE and WRITE_SIZE scaled by the given copy-probe factors)
 """
 from __future__ import annotations
 
@@ -105,11 +108,40 @@ def traffic(fetch, write, cfetch, cwrite, copy_bytes, kernel, source, workload, 
     }
 
 
+def kernels_traffic(fetch, write, fetch_scale, write_scale, top=20):
+    def per_kernel(path):
+        vals = collections.defaultdict(float)
+        names = {}
+        for r in csv.DictReader(open(path)):
+            vals[r["Dispatch_Id"]] += float(r["Counter_Value"])
+            names[r["Dispatch_Id"]] = _name(r["Kernel_Name"])
+        agg = collections.defaultdict(list)
+        for d, v in vals.items():
+            agg[names[d]].append(v)
+        return agg
+    f, w = per_kernel(fetch), per_kernel(write)
+    fs, ws = float(fetch_scale), float(write_scale)
+    rows = []
+    for k in set(f) | set(w):
+        fv, wv = f.get(k, []), w.get(k, [])
+        fm = sum(fv) / max(len(fv), 1) * 1024.0 * fs / 1e6
+        wm = sum(wv) / max(len(wv), 1) * 1024.0 * ws / 1e6
+        rows.append((k, max(len(fv), len(wv)), fm, wm))
+    rows.sort(key=lambda r: -(r[2] + r[3]) * r[1])
+    out = ["| kernel | dispatches | read MB / launch | written MB / launch | HBM MB / launch |",
+           "|---|---|---|---|---|"]
+    for k, n, a, b in rows[:top]:
+        out.append(f"| {k} | {n} | {a:.2f} | {b:.2f} | {a + b:.2f} |")
+    return "\n".join(out)
+
+
 def main(argv):
     if argv[0] == "stats":
         print(stats_table(argv[1]))
         if len(argv) > 2:
             print(segments(argv[2]))
+    elif argv[0] == "kernels":
+        print(kernels_traffic(*argv[1:5]))
     elif argv[0] == "traffic":
         print(json.dumps(traffic(*argv[1:10]), indent=1))
     else:
