@@ -1509,8 +1509,11 @@ static int64_t issue_work_order(dem_ctx *ctx, hipStream_t dyn, hipStream_t kin, 
     // event to the end of its detection, and a binning step inside a whole
     // dynamics step skews that measure; measured on the mixer, the latency
     // then settles at half its value and the orders double)
+    // Only when the adoption comes at a later step: with lambda = 0 the set
+    // is adopted before this step's kernel runs, so its binning must be done
+    // (and the detection chain enqueued) before that.
     const bool fuse = !ctx->has_clumps && !ctx->has_fixed && ctx->cdK.sort_mode == 0 && P.dyn_path != 1 &&
-                      ctx->rm_from < 0 && P.cd_mode != DEM_CD_ADAPTIVE;
+                      ctx->rm_from < 0 && P.cd_mode != DEM_CD_ADAPTIVE && lam > 0;
     if (!fuse) {
         auto *tf = stage_begin(ctx, 2, dyn);
         launch_detect_front(a, ctx->cdK, ctx->acs[target], dyn);
@@ -1782,7 +1785,12 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
                     ctx->run_due = false;
                 }
             }
-            launch_step_fused(a, ctx->rec_alt, ctx->q_alt, ctx->acs[ctx->cur], ctx->cap, ctx->ctr, dyn);
+            if (!launch_step_fused(a, ctx->rec_alt, ctx->q_alt, ctx->acs[ctx->cur], ctx->cap, ctx->ctr, dyn)) {
+                // (a work order's binning on the step right after an
+                // adoption: issue_work_order never sets one up)
+                ctx->err = "internal: no step kernel carries a work order's binning on this step";
+                return DEM_ERR_STATE;
+            }
             ctx->rm_from = -1;   // (the step carried the history over)
             if (ctx->wo_fused) {
                 // (the step wrote the work order's binning)

@@ -1079,19 +1079,22 @@ void launch_force(const DynArgs &a, AcsBuf &cur, StepBufs &sb, DevCounters *ctr,
 // The step kernel for the first step on a newly adopted set (REMAP: it
 // carries the history over from the previous set), for a step that also
 // does a work order's first binning step (WO; single-sphere runs without
-// fixed families), or for any other step.
+// fixed families), or for any other step.  No variant does both, nor a work
+// order with clumps or fixed families: those combinations get nullptr.
 using StepKernel = decltype(&k_step_fused<true, false, false, false, false, false>);
 template <bool SINGLES, bool FACETS, bool FIXED, bool STAGE>
 StepKernel pick_remap(bool remap, bool wo)
 {
-    if constexpr (SINGLES && !FIXED) {
-        if (wo && !remap) return k_step_fused<SINGLES, FACETS, FIXED, STAGE, false, true>;
+    if (wo && remap) return nullptr;
+    if (wo) {
+        if constexpr (SINGLES && !FIXED) return k_step_fused<SINGLES, FACETS, FIXED, STAGE, false, true>;
+        return nullptr;
     }
     return remap ? k_step_fused<SINGLES, FACETS, FIXED, STAGE, true, false>
                  : k_step_fused<SINGLES, FACETS, FIXED, STAGE, false, false>;
 }
 
-void launch_step_fused(const DynArgs &a, OwnerRec *rec_out, double *q_out, const AcsBuf &cur, int64_t cap,
+bool launch_step_fused(const DynArgs &a, OwnerRec *rec_out, double *q_out, const AcsBuf &cur, int64_t cap,
                        DevCounters *ctr, hipStream_t s)
 {
     // runs with fixed families (mostly dormant waves) never stage
@@ -1106,12 +1109,14 @@ void launch_step_fused(const DynArgs &a, OwnerRec *rec_out, double *q_out, const
     else
         kern = a.n_tri > 0 ? (a.has_clumps ? pick_remap<false, true, false, false>(r, w) : pick_remap<true, true, false, false>(r, w))
                            : (a.has_clumps ? pick_remap<false, false, false, false>(r, w) : pick_remap<true, false, false, false>(r, w));
+    if (!kern) return false;
     hipLaunchKernelGGL(kern, dim3(step_blocks(a)), dim3(TPB), 0, s, a, rec_out, q_out,
                        (const uint32_t *)cur.start, (const uint32_t *)cur.j, (const uint32_t *)cur.bstart,
                        (const uint32_t *)cur.bidx, (const uint32_t *)cur.bsrc, (const uint8_t *)cur.oany,
                        (const float *)cur.hx,
                        (const float *)cur.hy, (const float *)cur.hz, (const float *)cur.hw, cur.hx2, cur.hy2,
                        cur.hz2, cur.hw2, cap, ctr);
+    return true;
 }
 
 void launch_fold_integrate(const DynArgs &a, const AcsBuf &cur, StepBufs &sb, DevCounters *ctr,

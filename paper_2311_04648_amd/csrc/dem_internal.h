@@ -316,8 +316,11 @@ void launch_fold_integrate(const DynArgs &a, const AcsBuf &cur, StepBufs &sb, De
                            int integrate, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // one fused step (forces of both sides, ordered sums, integration): reads
 // a.rec / a.q and cur's history, writes rec_out / q_out and cur's second
-// history buffer; the caller swaps both afterwards
-void launch_step_fused(const DynArgs &a, OwnerRec *rec_out, double *q_out, const AcsBuf &cur, int64_t cap,
+// history buffer; the caller swaps both afterwards.  Returns false (and
+// launches nothing) for a combination no kernel variant covers: a work
+// order's binning on the first step of a newly adopted set, or in a run
+// with clumps or fixed families
+bool launch_step_fused(const DynArgs &a, OwnerRec *rec_out, double *q_out, const AcsBuf &cur, int64_t cap,
                        DevCounters *ctr, hipStream_t s);
 // an empty one-wave kernel stamped with events (overhead of the stamps)
 void launch_noop(hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
@@ -329,4 +332,3 @@ void launch_fix_owners(OwnerRec *rec, OwnerRec *rec_alt, const double *q, double
                        const uint8_t *fixed, int64_t n_owners, hipStream_t s);
 void launch_adaptive_margin(DevCounters *ctr, double t, double gmag, double cap, double vfloor, hipStream_t s);
 void launch_reduce_max(const DynArgs &a, DevCounters *ctr, hipStream_t s);
-

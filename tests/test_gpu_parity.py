@@ -377,6 +377,37 @@ def test_delayed_two_streams_equals_every_step_bitwise(dem):
 
 
 @pytest.mark.parametrize("streams", [1, 2])
+@pytest.mark.parametrize("judge", [False, True])
+def test_zero_latency_schedule_equals_every_step_bitwise(dem, streams, judge):
+    """Sec. 2.1 with no delay (lambda = 0): each set is adopted at the step
+    of its own work order, so that step must run on the new set; the
+    trajectory equals every-step detection bit for bit (single spheres,
+    where a work order's binning may otherwise ride on the step kernel)."""
+    import torch
+    s = W.small_spheres(5, n=512, vel=0.3)
+    a = dem.DemContext(s, mode="every")
+    a.set_state()
+    a.step(120)
+    b = dem.DemContext(s, mode="fixed", k=10, lam=0, judge=judge)
+    b.set_state()
+    if streams == 2:
+        dyn, kin = torch.cuda.Stream(), torch.cuda.Stream()
+        stats = b.step(120, dyn=dyn, kin=kin)
+    else:
+        stats = b.step(120)
+    assert stats["cds"] == 12 and stats["swaps"] == 12
+    if judge:
+        assert stats["misses"] == 0
+    assert stats["mean_contacts"] > 0
+    ga, gb = a.get_state(), b.get_state()
+    for k in ("X", "V", "W", "q"):
+        np.testing.assert_array_equal(ga[k], gb[k])
+    ka, ha = a.get_contacts()
+    kb, hb = b.get_contacts()
+    assert np.array_equal(np.intersect1d(ka, kb), ka)
+
+
+@pytest.mark.parametrize("streams", [1, 2])
 def test_adaptive_schedule_equals_every_step_bitwise(dem, streams):
     """Sec. 2.1's own policy (work order at every adoption, latency adapted
     from timing, margin from n_max = 2 lambda): judged, no contact is
