@@ -373,6 +373,25 @@ dem_status dem_mlp_adam(float *params_dev, const float *grad_dev, float *m_dev, 
 /* Device bytes of the `work` buffer dem_mlp_backward needs for n samples. */
 int64_t dem_mlp_backward_work_bytes(int64_t n);
 
+/* dem_mlp_backward without the work buffer, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight training or
+ * serving loops, harnesses that forbid allocation).  The per-block partial
+ * gradients live in a fixed array inside the library, one copy per GPU,
+ * held from the first use until the process ends: 4,036,608 bytes on each device,
+ * enough for n <= DEM_MLP_NOALLOC_MAX samples.  No hipMalloc or other
+ * allocating call is made; the array's device address is looked up once per
+ * device (with that device current) at the first call.  Same kernels and
+ * summation order as dem_mlp_backward, so the results are the same bits.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (other streams or host threads) race; calls on one stream are
+ * ordered and safe.  Errors: DEM_ERR_ARG (n <= 0, a null pointer, tau
+ * outside (0, 1)), DEM_ERR_CAPACITY (n > DEM_MLP_NOALLOC_MAX), DEM_ERR_HIP;
+ * the message is in dem_last_error(NULL). */
+#define DEM_MLP_NOALLOC_MAX 49152
+dem_status dem_mlp_backward_noalloc(const float *params_dev, const float *X_dev, const float *T_dev,
+                                    int64_t n, float tau, float *grad_dev, float *loss_dev,
+                                    dem_stream stream);
+
 /* ---- training-log tools (the learned interval is trained on logs the
  * method generates with per-step detection) ------------------------------
  * dem_snapshot: copies the current state into the reference that features
@@ -394,6 +413,8 @@ dem_status dem_label_begin(dem_ctx *ctx, dem_stream stream, int64_t *n_contacts)
 dem_status dem_label_update(dem_ctx *ctx, uint32_t t, uint32_t *first_miss_dev, dem_stream stream);
 dem_status dem_info(const dem_ctx *ctx, int64_t *vals, int64_t n);
 
+/* Message of the last failure on ctx; with ctx = NULL, of the last failed
+ * context-free call (the MLP kernels) on the calling host thread. */
 const char *dem_last_error(const dem_ctx *ctx);
 void dem_destroy(dem_ctx *ctx);
 

@@ -114,6 +114,7 @@ def lib():
             "dem_features": [vp, vp, i64, vp, vp],
             "dem_mlp_forward": [vp, vp, vp, i64, vp],
             "dem_mlp_backward": [vp, vp, vp, i64, f, vp, vp, vp, i64, vp],
+            "dem_mlp_backward_noalloc": [vp, vp, vp, i64, f, vp, vp, vp],
             "dem_mlp_adam": [vp, vp, vp, vp, i64, f, f, f, f, vp],
             "dem_snapshot": [vp, vp],
             "dem_feature_cells": [vp, vp, i64, vp, vp, vp],
@@ -420,6 +421,22 @@ def mlp_backward(params, X, T, tau, stream=None):
                                 _dptr(work), wb, _stream_ptr(stream))
     if st != DEM_OK:
         raise DemError(st, "dem_mlp_backward failed")
+    return grad, loss
+
+
+MLP_NOALLOC_MAX = 49152   # DEM_MLP_NOALLOC_MAX
+
+
+def mlp_backward_noalloc(params, X, T, tau, grad, loss, stream=None):
+    """dem_mlp_backward_noalloc: the gradient into the caller's `grad`
+    [1313] and `loss` [1] (float32 device tensors); no device memory is
+    allocated by the library or here (its scratch is a fixed device array,
+    shared by every call on the GPU)."""
+    n = int(X.shape[0])
+    st = lib().dem_mlp_backward_noalloc(_dptr(params), _dptr(X), _dptr(T), n, float(tau), _dptr(grad),
+                                        _dptr(loss), _stream_ptr(stream))
+    if st != DEM_OK:
+        raise DemError(st, lib().dem_last_error(None).decode())
     return grad, loss
 
 

@@ -638,7 +638,7 @@ extern "C" {
 
 const char *dem_last_error(const dem_ctx *ctx)
 {
-    return ctx ? ctx->err.c_str() : "null context";
+    return ctx ? ctx->err.c_str() : free_call_error();
 }
 
 dem_status dem_create(const dem_params *params, const dem_materials *mats, const dem_templates *tmpls,

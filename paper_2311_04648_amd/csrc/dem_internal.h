@@ -332,3 +332,6 @@ void launch_fix_owners(OwnerRec *rec, OwnerRec *rec_alt, const double *q, double
                        const uint8_t *fixed, int64_t n_owners, hipStream_t s);
 void launch_adaptive_margin(DevCounters *ctr, double t, double gmag, double cap, double vfloor, hipStream_t s);
 void launch_reduce_max(const DynArgs &a, DevCounters *ctr, hipStream_t s);
+
+// message of the last failed context-free call on this host thread
+const char *free_call_error();

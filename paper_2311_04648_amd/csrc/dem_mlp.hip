@@ -23,6 +23,9 @@
 #include "dem_device.h"
 #include "../../include/dem.h"
 
+#include <mutex>
+#include <string>
+
 namespace {
 
 constexpr int H = 32;
@@ -397,6 +400,67 @@ void pred_min(const float *Y, int64_t n, uint32_t *out, hipStream_t s)
     hipLaunchKernelGGL(k_pred_min, dim3(nblocks(n, 256)), dim3(256), 0, s, Y, n, out);
 }
 
+// Message of the last failed context-free call on this host thread
+// (dem_last_error(NULL) returns it).
+static thread_local std::string g_free_err;
+
+const char *free_call_error()
+{
+    return g_free_err.c_str();
+}
+
+// Scratch of dem_mlp_backward_noalloc: the per-block partial gradients
+// (NPARAM floats per block of BWD_SAMPLES samples) and partial losses (one
+// float per block) of up to DEM_MLP_NOALLOC_MAX samples.  Every GPU the
+// library runs on holds its own copy from the first kernel launch until the
+// process ends.  In host code the array's name is not a device address: its
+// address on each device comes from hipGetSymbolAddress (scratch_ptr).
+constexpr int64_t NOALLOC_BLOCKS = DEM_MLP_NOALLOC_MAX / BWD_SAMPLES;
+static_assert(NOALLOC_BLOCKS * BWD_SAMPLES == DEM_MLP_NOALLOC_MAX, "whole blocks");
+static __device__ __align__(256) float scratch[NOALLOC_BLOCKS * NPARAM + NOALLOC_BLOCKS];
+
+// The scratch's device address on the current device, looked up once per
+// device (with that device current) and kept; nullptr on failure, with the
+// reason in g_free_err.
+static float *scratch_ptr()
+{
+    constexpr int MAX_DEV = 64;
+    static std::mutex mu;
+    static float *ptr[MAX_DEV] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        g_free_err = std::string("hipGetDevice: ") + hipGetErrorString(e);
+        return nullptr;
+    }
+    if (dev < 0 || dev >= MAX_DEV) {
+        g_free_err = "device index out of range for the scratch table";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            g_free_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        ptr[dev] = static_cast<float *>(p);
+    }
+    return ptr[dev];
+}
+
+static void launch_backward(const float *params_dev, const float *X_dev, const float *T_dev, int64_t n, float tau,
+                            float *grad_dev, float *loss_dev, float *partial, hipStream_t s)
+{
+    const int64_t nblk = (n + BWD_SAMPLES - 1) / BWD_SAMPLES;
+    float *lpart = partial + nblk * NPARAM;
+    hipLaunchKernelGGL(k_mlp_backward_block, dim3((unsigned)nblk), dim3(BWD_SAMPLES), 0, s, params_dev, X_dev, T_dev,
+                       n, tau, partial, lpart);
+    hipLaunchKernelGGL(k_mlp_backward_sum, dim3(nblocks(NPARAM + 1, 256)), dim3(256), 0, s, partial, lpart, nblk,
+                       grad_dev, loss_dev);
+}
+
 extern "C" {
 
 dem_status dem_mlp_forward(const float *params_dev, const float *X_dev, float *Y_dev, int64_t n, dem_stream stream)
@@ -419,15 +483,38 @@ dem_status dem_mlp_backward(const float *params_dev, const float *X_dev, const f
     if (n <= 0 || !params_dev || !X_dev || !T_dev || !grad_dev || !loss_dev || !work_dev) return DEM_ERR_ARG;
     if (work_bytes < dem_mlp_backward_work_bytes(n)) return DEM_ERR_ARG;
     if (!(tau > 0.0f && tau < 1.0f)) return DEM_ERR_ARG;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    int64_t nblk = (n + BWD_SAMPLES - 1) / BWD_SAMPLES;
-    float *partial = work_dev;
-    float *lpart = work_dev + nblk * NPARAM;
-    hipLaunchKernelGGL(k_mlp_backward_block, dim3((unsigned)nblk), dim3(BWD_SAMPLES), 0, s, params_dev, X_dev, T_dev,
-                       n, tau, partial, lpart);
-    hipLaunchKernelGGL(k_mlp_backward_sum, dim3(nblocks(NPARAM + 1, 256)), dim3(256), 0, s, partial, lpart, nblk,
-                       grad_dev, loss_dev);
+    launch_backward(params_dev, X_dev, T_dev, n, tau, grad_dev, loss_dev, work_dev,
+                    reinterpret_cast<hipStream_t>(stream));
     return hipGetLastError() == hipSuccess ? DEM_OK : DEM_ERR_HIP;
+}
+
+dem_status dem_mlp_backward_noalloc(const float *params_dev, const float *X_dev, const float *T_dev, int64_t n,
+                                    float tau, float *grad_dev, float *loss_dev, dem_stream stream)
+{
+    if (n <= 0 || !params_dev || !X_dev || !T_dev || !grad_dev || !loss_dev) {
+        g_free_err = "dem_mlp_backward_noalloc: n must be > 0 and every pointer set";
+        return DEM_ERR_ARG;
+    }
+    if (n > DEM_MLP_NOALLOC_MAX) {
+        g_free_err = "dem_mlp_backward_noalloc: n = " + std::to_string(n) + " exceeds the scratch's " +
+                     std::to_string((long long)DEM_MLP_NOALLOC_MAX) + " samples (use dem_mlp_backward)";
+        return DEM_ERR_CAPACITY;
+    }
+    if (!(tau > 0.0f && tau < 1.0f)) {
+        g_free_err = "dem_mlp_backward_noalloc: tau must lie in (0, 1)";
+        return DEM_ERR_ARG;
+    }
+    float *p = scratch_ptr();
+    if (!p) return DEM_ERR_HIP;
+    // (every partial the sum reads is written first by its block: nothing
+    // in the scratch needs clearing)
+    launch_backward(params_dev, X_dev, T_dev, n, tau, grad_dev, loss_dev, p, reinterpret_cast<hipStream_t>(stream));
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        g_free_err = std::string("dem_mlp_backward_noalloc launch: ") + hipGetErrorString(e);
+        return DEM_ERR_HIP;
+    }
+    return DEM_OK;
 }
 
 dem_status dem_mlp_adam(float *params_dev, const float *grad_dev, float *m_dev, float *v_dev, int64_t t, float lr,
