@@ -213,8 +213,16 @@ typedef struct {
     double mean_contacts;   /* mean size of the active set over the steps */
 } dem_step_stats;
 
-/* Creates a context for one problem.  Copies every array it is given.
- * Errors: DEM_ERR_ARG on inconsistent sizes or values. */
+/* Creates a context for one problem: the set-up of the sample script of
+ * Sec. 3 (materials, clump templates, box walls and analytic objects, time
+ * step, gravity, divergence speed) over the owner / geometry hierarchy of
+ * Sec. 2.4, with the margin and update interval of Sec. 2.1.  Copies every
+ * array it is given (host pointers, read before the call returns); the
+ * context is owned by the caller and released with dem_destroy.  Derives
+ * the detection bins (cubes of edge 2 (r_max + margin), enlarged by a
+ * relative 1e-6) and the voxel origin.
+ * Errors: DEM_ERR_ARG on inconsistent sizes or values (message in
+ * dem_last_error(NULL) when no context is returned). */
 dem_status dem_create(const dem_params *params, const dem_materials *mats,
                       const dem_templates *tmpls, const dem_walls *walls,
                       const dem_bodies *bodies, dem_ctx **out);
@@ -258,15 +266,27 @@ typedef struct {
 dem_status dem_set_families(dem_ctx *ctx, const dem_families *fam, dem_stream stream);
 
 /* Device bytes one binding needs for a contact array of contact_capacity
- * entries (per active-set buffer). */
+ * entries (per active-set buffer).  The paper keeps the whole state, both
+ * active contact sets (the one in use and the one the kinematics side
+ * builds, Sec. 2.1) and their contact history (Sec. 4.2) resident on the
+ * GPUs; this is the size of that residency here: owner state x2, sphere
+ * records, two active sets with history x2, detection workspaces for the
+ * two streams, counters.  Writes *bytes; no device work.
+ * Errors: DEM_ERR_ARG (negative capacity, null pointer). */
 dem_status dem_workspace_size(const dem_ctx *ctx, int64_t contact_capacity, int64_t *bytes);
 
 /* Binds caller-owned device memory (>= dem_workspace_size bytes, 256-byte
- * aligned) and uploads the constant tables.  Re-binding drops the state and
- * the contact set; set them again afterwards. */
+ * aligned; the library carves it and never frees it) and uploads the
+ * constant tables of the problem (Sec. 3: materials as the pairwise
+ * contact parameters of Sec. 4.2.1, templates of Sec. 2.4, walls).
+ * Re-binding drops the state and the contact set; set them again
+ * afterwards.  Synchronous (the uploads finish before it returns).
+ * Errors: DEM_ERR_ARG (null or misaligned pointer, too few bytes),
+ * DEM_ERR_HIP. */
 dem_status dem_bind(dem_ctx *ctx, void *device_workspace, int64_t bytes, int64_t contact_capacity);
 
-/* Uploads a state: X [3*No] world positions (m), q [4*No] unit quaternions
+/* Uploads a state (the owner kinematics of Sec. 2.4, Sec. 4.1; positions in
+ * the compressed form of Sec. 2.3): X [3*No] world positions (m), q [4*No] unit quaternions
  * (w,x,y,z; body to world), v [3*No] velocities, w [3*No] angular velocities
  * in the body frame.  Positions are stored as voxel index + float offset on
  * a 2^-38 m grid; X that lie on that grid are stored exactly.  Single-sphere
@@ -276,13 +296,19 @@ dem_status dem_bind(dem_ctx *ctx, void *device_workspace, int64_t bytes, int64_t
 dem_status dem_set_state(dem_ctx *ctx, const double *X, const double *q, const float *v,
                          const float *w, int64_t step, dem_stream stream);
 
-/* Reads the state back (same layout as dem_set_state; w of clumps in the
- * body frame, of single spheres in the world frame with q = identity). */
+/* Reads the state back (Sec. 2.4 owner kinematics; positions decoded from
+ * the Sec. 2.3 voxel form exactly to FP64; same layout as dem_set_state; w
+ * of clumps in the body frame, of single spheres in the world frame with
+ * q = identity).  Host output arrays (any may be NULL); synchronises the
+ * stream.  Errors: DEM_ERR_STATE before a state is set, DEM_ERR_HIP. */
 dem_status dem_get_state(dem_ctx *ctx, double *X, double *q, float *v, float *w,
                          int64_t *step, dem_stream stream);
 
-/* Sphere binning (a uniform grid of cubic bins of edge 2 (r_max + margin)):
- * sphere centres, bin keys and a stable LSD radix sort of (key, sphere id).
+/* Sphere binning, the first stage of contact detection (Sec. 2.1 and the
+ * binning method the paper cites in Sec. 1): a uniform grid of cubic bins of
+ * edge 2 (r_max + margin); sphere centres (Sec. 2.4: owner position plus
+ * the rotated template offset), bin keys and a stable sort of
+ * (key, sphere id); errors DEM_ERR_STATE before a state is set.
  * Optional read-back to host arrays (NULL to skip): keys [Ns] and ids [Ns] in
  * sorted order; synchronises the stream when reading back. */
 dem_status dem_bin(dem_ctx *ctx, dem_stream stream, uint32_t *sorted_keys, uint32_t *sorted_ids);
@@ -305,9 +331,13 @@ dem_status dem_detect_contacts(dem_ctx *ctx, double margin, dem_stream stream,
  * Updates the contact history as a step would.  Results via dem_get_forces. */
 dem_status dem_forces(dem_ctx *ctx, dem_stream stream);
 
-/* Reads the last dem_forces results: F_owner, T_owner [3*No] (world frame,
- * torque about the owner centre), F_contact [3*n] (force on geometry A of
- * each contact, in set order).  Any pointer may be NULL.  Synchronises. */
+/* Reads the last dem_forces results: the owner sums of Sec. 4.1 Eq. (3)
+ * F_owner, T_owner [3*No] (world frame, torque about the owner centre) and
+ * the per-contact force of Eqs. (1)-(2) F_contact [3*n] (force on geometry
+ * A of each contact, in set order; cap = its capacity in contacts).  Host
+ * arrays, any may be NULL.  Synchronises the stream.
+ * Errors: DEM_ERR_STATE before dem_forces, DEM_ERR_CAPACITY if cap is
+ * below the set size. */
 dem_status dem_get_forces(dem_ctx *ctx, float *F_owner, float *T_owner, float *F_contact,
                           int64_t cap, dem_stream stream);
 
@@ -320,21 +350,27 @@ dem_status dem_get_forces(dem_ctx *ctx, float *F_owner, float *T_owner, float *F
 dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn, dem_stream kin,
                     dem_step_stats *stats);
 
-/* Reads the current contact set: keys [cap] and history [4*cap] (float:
+/* Reads the current active contact set (Sec. 2.1) with its contact history
+ * (the tangential displacement and contact age that the default model keeps
+ * per contact, Sec. 4.2.1): keys [cap] and history [4*cap] (float:
  * tangential displacement xyz, contact age in seconds; the age is tracked
  * only when some material pair has rolling resistance, else reads 0).
  * n receives the set size; DEM_ERR_CAPACITY if cap is smaller. */
 dem_status dem_get_contacts(dem_ctx *ctx, uint64_t *keys, float *hist, int64_t cap,
                             int64_t *n, dem_stream stream);
 
-/* Installs a contact set (strictly ascending keys as dem_detect_contacts
- * produces) with its history ([4*n] as dem_get_contacts; NULL = zero).  Errors: DEM_ERR_ARG on bad keys,
+/* Installs an active contact set (Sec. 2.1; strictly ascending keys as
+ * dem_detect_contacts produces) with its history (Sec. 4.2.1) ([4*n] as dem_get_contacts; NULL = zero).  Errors: DEM_ERR_ARG on bad keys,
  * DEM_ERR_CAPACITY if n exceeds the bound capacity. */
 dem_status dem_set_contacts(dem_ctx *ctx, const uint64_t *keys, const float *hist, int64_t n,
                             dem_stream stream);
 
 /* Counts true contacts (margin 0) absent from the current set -- the judge
- * of the delayed schedule.  Synchronises; writes the count to *missing. */
+ * of the delayed schedule: Sec. 2.1 requires that the margin cover every
+ * contact that can form before the next set arrives, so a set in use
+ * must hold every pair that touches; this counts the pairs for which it
+ * does not.  Synchronises; writes the count to *missing.
+ * Errors: DEM_ERR_STATE before a state and a set exist, DEM_ERR_HIP. */
 dem_status dem_count_missing(dem_ctx *ctx, dem_stream stream, int64_t *missing);
 
 /* ---- learned contact-detection interval ---------------------------------
@@ -347,7 +383,12 @@ dem_status dem_count_missing(dem_ctx *ctx, dem_stream stream, int64_t *missing);
 #define DEM_MLP_NFEAT 6
 #define DEM_MLP_KCAP 1024   /* label horizon K (steps) used by the features */
 
-/* Installs MLP parameters used by DEM_CD_LEARNED (host array). */
+/* Installs MLP parameters used by DEM_CD_LEARNED: the learned replacement
+ * of the update bound n_max of Sec. 2.1.  params is a host array of
+ * DEM_MLP_NPARAM floats, copied into the context (and to device memory once
+ * bound); NULL removes the model, and the learned schedule then uses its
+ * analytic fallback.  Errors: DEM_ERR_ARG on a non-finite value,
+ * DEM_ERR_HIP. */
 dem_status dem_mlp_set(dem_ctx *ctx, const float *params);
 
 /* Computes the per-cell features of the current state relative to the

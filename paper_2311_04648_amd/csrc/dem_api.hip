@@ -293,6 +293,8 @@ void carve(Carver &c, dem_ctx *ctx, int64_t cap)
         a.bsrc = c.take<uint32_t>(cap);
         a.bcur = c.take<uint32_t>(Ns + 1);
         a.oany = c.take<uint8_t>(No);
+        a.olist = c.take<uint32_t>(No);
+        a.otile = c.take<uint32_t>(owner_list_tiles(No) + 1);
     }
     ctx->sb.aF = c.take<float>(3 * Ns);
     ctx->sb.aT = c.take<float>(3 * Ns);
@@ -360,6 +362,13 @@ MeshPoses mesh_poses(const dem_ctx *ctx, int64_t step)
     return M;
 }
 
+// Clump systems without fixed families keep, with every set, the list of
+// its owners with contacts (the split step runs over it).
+inline bool owner_list_wanted(const dem_ctx *ctx)
+{
+    return ctx->has_clumps && !ctx->has_fixed && ctx->P.dyn_path != 1;
+}
+
 DetectArgs detect_args(const dem_ctx *ctx, double margin, int64_t step)
 {
     DetectArgs a;
@@ -390,6 +399,7 @@ DetectArgs detect_args(const dem_ctx *ctx, double margin, int64_t step)
     a.dcell_start = ctx->d_dcell_start;
     a.dcand = ctx->d_dcand;
     a.dcandf = ctx->d_dcandf;
+    a.owner_list = owner_list_wanted(ctx) ? 1 : 0;
     return a;
 }
 
@@ -451,6 +461,9 @@ DynArgs dyn_args(const dem_ctx *ctx, int64_t step)
         const int64_t nc = std::max(ctx->h_ctr->n_contacts[0], ctx->h_ctr->n_contacts[1]);
         a.dense_rows = 2 * nc >= ctx->Ns ? 1 : 0;
     }
+    // clump systems without fixed families: a sparse set runs as the
+    // streaming kernel plus the kernel over the owners with contacts
+    a.split = owner_list_wanted(ctx) && (ctx->P.dyn_path == 4 || (ctx->P.dyn_path == 0 && !a.dense_rows)) ? 1 : 0;
     return a;
 }
 
@@ -505,7 +518,7 @@ void clear_set(dem_ctx *ctx, int b, hipStream_t s)
     launch_fill_u32(ctx->acs[b].start, ctx->Ns + 1, 0u, s);
     launch_fill_u32(ctx->acs[b].bstart, ctx->Ns + 1, 0u, s);
     launch_owner_flags(ctx->acs[b], ctx->has_clumps ? ctx->d_sph0 : nullptr, ctx->No, ctx->Ns, ctx->cap, ctx->d_ofam,
-                       ctx->has_fixed ? ctx->d_famfixed : nullptr, s);
+                       ctx->has_fixed ? ctx->d_famfixed : nullptr, s, owner_list_wanted(ctx), ctx->cdD.partials);
 }
 
 void drain_pair(dem_ctx *ctx, dem_ctx::TimedPair &p)
@@ -660,8 +673,9 @@ dem_status dem_create(const dem_params *params, const dem_materials *mats, const
     if (P.cd_mode < 0 || P.cd_mode > 3) return fail("unknown cd_mode");
     if (P.cd_mode == DEM_CD_ADAPTIVE && (P.cd_latency < 1 || P.cd_interval_max < 1))
         return fail("the adaptive schedule needs cd_latency >= 1 and cd_interval_max >= 1");
-    if (P.dyn_path < 0 || P.dyn_path > 3)
-        return fail("dyn_path must be 0 (fused), 1 (two kernels), 2 or 3 (fused, history staged or not)");
+    if (P.dyn_path < 0 || P.dyn_path > 4)
+        return fail("dyn_path must be 0 (automatic), 1 (two kernels), 2 or 3 (one fused kernel, history staged "
+                    "or not) or 4 (streaming kernel + kernel over the owners with contacts)");
     if (P.bin_sort < 0 || P.bin_sort > 1) return fail("bin_sort must be 0 (one pass) or 1 (radix)");
     if (P.cd_mode != DEM_CD_EVERY) {
         if (P.cd_interval < 1) return fail("cd_interval must be >= 1");
@@ -1391,7 +1405,7 @@ dem_status dem_set_contacts(dem_ctx *ctx, const uint64_t *keys, const float *his
     }
     launch_blists(a, ctx->Ns, ctx->cap, ctx->cdD.partials, s);
     launch_owner_flags(a, ctx->has_clumps ? ctx->d_sph0 : nullptr, ctx->No, ctx->Ns, ctx->cap, ctx->d_ofam,
-                       ctx->has_fixed ? ctx->d_famfixed : nullptr, s);
+                       ctx->has_fixed ? ctx->d_famfixed : nullptr, s, owner_list_wanted(ctx), ctx->cdD.partials);
     HIPCHK(hipGetLastError());
     uint32_t nn = (uint32_t)n, zero = 0;
     HIPCHK(hipMemcpyAsync(&ctx->ctr->n_contacts[b], &nn, 4, hipMemcpyHostToDevice, s));

@@ -835,6 +835,71 @@ __global__ void __launch_bounds__(TPB) k_owner_flags(const uint32_t *start, cons
     flag[o] = (uint8_t)(((start[s0] != start[s1] || bstart[s0] != bstart[s1]) ? 1 : 0) | fx);
 }
 
+// The owners with contacts in a set, ascending: per tile of OL_TILE owners
+// (OL_PER consecutive flags per thread, one 16-byte load) the count, a scan
+// of the counts, then each tile writes its owners at its offset.
+constexpr int OL_PER = 16;
+constexpr int64_t OL_TILE = (int64_t)TPB * OL_PER;
+
+__device__ inline uint32_t olist_bits(const uint8_t *flag, int64_t base, int64_t no)
+{
+    uint32_t bits = 0;
+    if (base + OL_PER <= no) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(flag + base);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 16; ++k) bits |= ((w[k >> 2] >> (8 * (k & 3))) & 1u) << k;
+    } else {
+        for (int k = 0; k < OL_PER; ++k)
+            if (base + k < no) bits |= (uint32_t)(flag[base + k] & 1u) << k;
+    }
+    return bits;
+}
+
+// exclusive prefix of v over the block (256 threads) and the block total
+__device__ inline uint32_t olist_block_scan(uint32_t v, uint32_t *total)
+{
+    __shared__ uint32_t ws[TPB / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += t;
+    }
+    if (lane == 63) ws[wid] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < TPB / 64; ++k) {
+        off += k < wid ? ws[k] : 0u;
+        tot += ws[k];
+    }
+    *total = tot;
+    return inc - v + off;
+}
+
+__global__ void __launch_bounds__(TPB) k_olist_count(const uint8_t *flag, int64_t no, uint32_t *tcount)
+{
+    const int64_t base = (int64_t)blockIdx.x * OL_TILE + (int64_t)threadIdx.x * OL_PER;
+    uint32_t tot;
+    olist_block_scan((uint32_t)__popc(olist_bits(flag, base, no)), &tot);
+    if (threadIdx.x == 0) tcount[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(TPB) k_olist_write(const uint8_t *flag, int64_t no, const uint32_t *toff,
+                                                     uint32_t *olist)
+{
+    const int64_t base = (int64_t)blockIdx.x * OL_TILE + (int64_t)threadIdx.x * OL_PER;
+    uint32_t bits = olist_bits(flag, base, no), tot;
+    uint32_t pos = toff[blockIdx.x] + olist_block_scan((uint32_t)__popc(bits), &tot);
+    while (bits) {
+        const int k = __ffs(bits) - 1;
+        olist[pos++] = (uint32_t)(base + k);
+        bits &= bits - 1u;
+    }
+}
+
 __global__ void __launch_bounds__(TPB) k_remap(const uint32_t *os, const uint32_t *oj, const float *ohx,
                                                const float *ohy, const float *ohz, const float *ohw,
                                                const uint32_t *ns_, const uint32_t *nj, float *nhx, float *nhy,
@@ -1007,11 +1072,30 @@ void launch_detect_front(const DetectArgs &a, CdWork &w, AcsBuf &out, hipStream_
                        w.sort_mode == 0 ? (uint32_t *)nullptr : w.vals, w.cand_tmp, w.cell_count);
 }
 
+int64_t owner_list_tiles(int64_t no)
+{
+    return (no + OL_TILE - 1) / OL_TILE;
+}
+
+void launch_owner_list(AcsBuf &b, int64_t no, uint32_t *partials, hipStream_t s)
+{
+    const int64_t nt = owner_list_tiles(no);
+    if (nt == 0) {
+        launch_fill_u32(b.otile, 1, 0u, s);
+        return;
+    }
+    hipLaunchKernelGGL(k_olist_count, dim3((unsigned)nt), dim3(TPB), 0, s, (const uint8_t *)b.oany, no, b.otile);
+    scan_exclusive_u32(b.otile, b.otile, nt, partials, s);
+    hipLaunchKernelGGL(k_olist_write, dim3((unsigned)nt), dim3(TPB), 0, s, (const uint8_t *)b.oany, no,
+                       (const uint32_t *)b.otile, b.olist);
+}
+
 void launch_owner_flags(AcsBuf &b, const uint32_t *own_sph0, int64_t no, int64_t ns, int64_t cap,
-                        const uint8_t *ofam, const uint8_t *fixed, hipStream_t s)
+                        const uint8_t *ofam, const uint8_t *fixed, hipStream_t s, bool list, uint32_t *partials)
 {
     hipLaunchKernelGGL(k_owner_flags, dim3(nblocks(no)), dim3(TPB), 0, s, (const uint32_t *)b.start,
                        (const uint32_t *)b.bstart, own_sph0, no, ns, cap, ofam, fixed, b.oany);
+    if (list) launch_owner_list(b, no, partials, s);
 }
 
 void launch_detect(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap, DevCounters *ctr, int buf,
@@ -1052,6 +1136,7 @@ void launch_detect_back(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap
     hipLaunchKernelGGL(k_blist_finish, dim3(nblocks(std::max(n, a.n_owners))), dim3(TPB), 0, s, out.start,
                        out.bstart, n, cap, out.bidx, out.bsrc, a.own_sph0, a.n_owners, a.ofam, a.famfixed, out.oany,
                        w.cell_count, (int64_t)a.grid.nbins + 1);
+    if (a.owner_list) launch_owner_list(out, a.n_owners, w.partials, s);
 }
 
 void launch_judge(const DetectArgs &a_in, CdWork &w, const AcsBuf &cur, int64_t cap, DevCounters *ctr,

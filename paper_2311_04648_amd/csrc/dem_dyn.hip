@@ -88,6 +88,14 @@ __device__ inline bool stopped(const DevCounters *c, int64_t step)
     return c->stop_cd != 0u || c->div[(step + 1) & 1] != 0u;
 }
 
+// A step halted by the divergence of the step before marks itself diverged
+// too, so that every later step of the call halts as well (the flags are
+// kept per step parity so that no block of a step sees its own step's flag).
+__device__ inline void halt_mark(DevCounters *c, int64_t step)
+{
+    if (c->div[(step + 1) & 1] != 0u) c->div[step & 1] = 1u;
+}
+
 __device__ inline float4 load_hist(const float *hx, const float *hy, const float *hz, const float *hw,
                                    uint32_t c, int rolling)
 {
@@ -525,14 +533,18 @@ __global__ void __launch_bounds__(TPB) k_fold_integrate(DynArgs a, const uint32_
                                                         float *To, int integrate, const uint8_t *oany,
                                                         DevCounters *ctr)
 {
-    if (stopped(ctr, a.step)) return;
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (stopped(ctr, a.step)) {
+        if (integrate && o == 0) halt_mark(ctr, a.step);
+        return;
+    }
     const int64_t Ns = a.n_spheres, No = a.n_owners;
     const bool valid = o < No;
     float v2 = 0.0f;
     if (integrate && o == 0) {
         ctr->last_step_done = a.step + 1;
         ctr->contact_steps += ctr->n_contacts[a.cur];
+        a.blkmax[gridDim.x] = 0.0f;   // (the slot of the split step's second kernel)
     }
     if (valid) {
         OwnerRec r;
@@ -948,6 +960,7 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
     const bool rm_over = REMAP && ctr->overflow[a.rm_newbuf] != 0u;
     if (rm_over && o0 == 0) ctr->stop_cd = 1u;
     if (rm_over || stopped(ctr, a.step)) {
+        if (o0 == 0) halt_mark(ctr, a.step);
         if constexpr (WO) {
             // the work order's binning is still written (from the state
             // carried over unchanged), so the detection chain reads a
@@ -972,6 +985,7 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
     if (o0 == 0) {
         ctr->last_step_done = a.step + 1;
         ctr->contact_steps += ctr->n_contacts[a.cur];
+        a.blkmax[gridDim.x] = 0.0f;   // (the slot of the split step's second kernel)
     }
     float v2 = 0.0f;
     // the wave's index in the block, as a wave-uniform (scalar) value
@@ -992,6 +1006,140 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
         v2 = step_wave<SINGLES, FACETS, FIXED, STAGE, REMAP, WO>(a, w0, lrec, lds, rec_out, q_out, start, jarr, bstart, bidx, bsrc, oany, hx, hy, hz, hw, ox, oy, oz, ow, cap, ctr);
     }
     block_max_v2(v2, a.blkmax + lb);
+}
+
+
+// The step of a clump system (no fixed families) whose set has few
+// contacts, as two kernels.  Most owners then have no contact: for them the
+// step is a stream of loads, the integration under gravity alone and
+// stores, and the one-kernel step runs them at the occupancy its contact
+// path allows (3 waves per SIMD).  k_step_free streams every owner at the
+// occupancy of that stream: an owner whose flag says it has no contact in
+// the set (bit 0 clear) is integrated with zero force and torque, exactly
+// as the one-kernel step does; the others are copied and left to
+// k_step_listed, which runs after it on the same stream over the set's list
+// of owners with contacts and does for each what the one-kernel step does
+// (owner_forces, then the integration), so both forms give the same bits.
+// A wave's 64 records move through LDS in three contiguous 1 KiB loads and
+// stores, as in the single-sphere step; the inertia and the flag are loaded
+// with them, the orientation (clumps only) once the template is known.
+// REMAP: the first step on a newly adopted set (only its overflow check
+// matters here).
+template <bool REMAP>
+__global__ void __launch_bounds__(TPB) k_step_free(DynArgs a, OwnerRec *rec_out, double *q_out,
+                                                   const uint8_t *oany, DevCounters *ctr)
+{
+    __shared__ uint4 wbuf[TPB / 64][192];
+    const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t No = a.n_owners;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t o0 = (int64_t)lb * blockDim.x + threadIdx.x;
+    const int64_t ow = (int64_t)lb * blockDim.x + 64 * wv;
+    const int64_t o = ow + lane;
+    const bool valid = o < No;
+    const bool rm_over = REMAP && ctr->overflow[a.rm_newbuf] != 0u;
+    if (rm_over && o0 == 0) ctr->stop_cd = 1u;
+    const bool halt = rm_over || stopped(ctr, a.step);
+    if (o0 == 0) {
+        if (halt) {
+            halt_mark(ctr, a.step);
+        } else {
+            ctr->last_step_done = a.step + 1;
+            ctr->contact_steps += ctr->n_contacts[a.cur];
+            a.blkmax[gridDim.x] = 0.0f;   // the second kernel's blocks take their maximum here
+        }
+    }
+    float v2 = 0.0f;
+    if (ow < No) {
+        const uint32_t nv = (uint32_t)(No - ow < 64 ? No - ow : 64);
+        uint8_t fl = 1u;
+        OwnerAux ax{};
+        if (valid) {
+            fl = oany[o];
+            ax = a.aux[o];
+        }
+        uint4 *lrec = wbuf[wv];
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.rec + ow);
+        for (uint32_t k = lane; k < 3u * nv; k += 64u) lrec[k] = src[k];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        OwnerRec r{};
+        if (valid) r = load_rec(reinterpret_cast<const OwnerRec *>(lrec) + lane);
+        const bool rot = valid && ax.tmpl >= 0;
+        double4 qv = make_double4(1.0, 0.0, 0.0, 0.0);
+        if (rot && (halt || !(fl & 1u))) qv = *reinterpret_cast<const double4 *>(a.q + 4 * (size_t)o);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (halt) {
+            // a stopped step: the state is copied unchanged (the records
+            // below, the orientation here; the history by k_step_listed)
+            if (rot) *reinterpret_cast<double4 *>(q_out + 4 * (size_t)o) = qv;
+        } else if (valid && !(fl & 1u)) {
+            const float inv[3] = {ax.inv_moi[0], ax.inv_moi[1], ax.inv_moi[2]};
+            v2 = advance(a, r, inv, rot, f3(0.f, 0.f, 0.f), f3(0.f, 0.f, 0.f), qv, q_out + 4 * (size_t)o, ctr);
+            store_rec(reinterpret_cast<OwnerRec *>(lrec) + lane, r);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // (the records of owners with contacts go out unchanged here and
+        // are overwritten by k_step_listed)
+        uint4 *dst = reinterpret_cast<uint4 *>(rec_out + ow);
+        for (uint32_t k = lane; k < 3u * nv; k += 64u) dst[k] = lrec[k];
+    }
+    if (!halt) block_max_v2(v2, a.blkmax + lb);
+}
+
+// The owners with contacts of a split step (see k_step_free), from the
+// set's owner list (ascending: consecutive threads take consecutive owners,
+// whose rows are neighbours).  The list's length is read on the device, so
+// the grid is fixed and the threads stride over the list.  The largest
+// |v|^2 joins the slot after the first kernel's (an atomic maximum on the
+// bits of non-negative floats, one per block).
+constexpr unsigned LISTED_BLOCKS = 1024;
+
+template <bool FACETS, bool REMAP>
+__global__ void __launch_bounds__(TPB, 3) k_step_listed(DynArgs a, const uint32_t *olist, const uint32_t *ocount,
+                                                       OwnerRec *rec_out, double *q_out, const uint32_t *start,
+                                                       const uint32_t *jarr, const uint32_t *bstart,
+                                                       const uint32_t *bidx, const uint32_t *bsrc,
+                                                       const uint8_t *oany, const float *hx, const float *hy,
+                                                       const float *hz, const float *hw, float *ox, float *oy,
+                                                       float *oz, float *ow, int64_t cap, DevCounters *ctr,
+                                                       uint32_t slot)
+{
+    const bool rm_over = REMAP && ctr->overflow[a.rm_newbuf] != 0u;
+    const bool halt = rm_over || stopped(ctr, a.step);
+    const int64_t n = (int64_t)*ocount;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const HistOut ho{ox, oy, oz, ow, nullptr, 0u};
+    float v2 = 0.0f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int64_t o = (int64_t)olist[i];
+        if (halt) {
+            halt_owner<false>(a, o, rec_out, q_out, start, jarr, bstart, bidx, bsrc, oany, hx, hy, hz, hw, ox, oy,
+                              oz, ow, cap, ctr);
+            continue;
+        }
+        OwnerStep st;
+        owner_forces<false, FACETS, false, true, REMAP>(a, o, start, jarr, bstart, bidx, bsrc, oany, 0, hx, hy, hz,
+                                                        hw, ho, st);
+        if (st.advance) v2 = fmaxf(v2, owner_advance<false>(a, o, st, rec_out, q_out, ctr));
+    }
+    if (halt) return;
+    __shared__ float wmax[TPB / 64];
+    if (!(v2 == v2)) v2 = 3.0e38f;
+    for (int d = 32; d > 0; d >>= 1) v2 = fmaxf(v2, __shfl_xor(v2, d, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m = wmax[0];
+        for (int k = 1; k < TPB / 64; ++k) m = fmaxf(m, wmax[k]);
+        atomicMax(reinterpret_cast<unsigned int *>(a.blkmax + slot), __float_as_uint(m));
+    }
 }
 
 }  // namespace
@@ -1064,7 +1212,9 @@ void launch_adaptive_margin(DevCounters *ctr, double t, double gmag, double cap,
 
 void launch_reduce_max(const DynArgs &a, DevCounters *ctr, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(256), 0, s, a.blkmax, (int64_t)step_blocks(a), ctr);
+    // (the slot after the per-block maxima holds the second kernel's of a
+    // split step, and zero after any other step)
+    hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(256), 0, s, a.blkmax, (int64_t)step_blocks(a) + 1, ctr);
 }
 
 void launch_force(const DynArgs &a, AcsBuf &cur, StepBufs &sb, DevCounters *ctr, hipStream_t s,
@@ -1097,6 +1247,22 @@ StepKernel pick_remap(bool remap, bool wo)
 bool launch_step_fused(const DynArgs &a, OwnerRec *rec_out, double *q_out, const AcsBuf &cur, int64_t cap,
                        DevCounters *ctr, hipStream_t s)
 {
+    if (a.split && a.has_clumps && !a.has_fixed && !a.wo_keys && cur.olist) {
+        const bool r = a.rm_start != nullptr;
+        const unsigned nb = nblocks(a.n_owners);
+        hipLaunchKernelGGL(r ? k_step_free<true> : k_step_free<false>, dim3(nb), dim3(TPB), 0, s, a, rec_out, q_out,
+                           (const uint8_t *)cur.oany, ctr);
+        auto kl = a.n_tri > 0 ? (r ? k_step_listed<true, true> : k_step_listed<true, false>)
+                              : (r ? k_step_listed<false, true> : k_step_listed<false, false>);
+        const unsigned nl = std::min<unsigned>(nb, LISTED_BLOCKS);
+        hipLaunchKernelGGL(kl, dim3(nl), dim3(TPB), 0, s, a, (const uint32_t *)cur.olist,
+                           (const uint32_t *)(cur.otile + owner_list_tiles(a.n_owners)), rec_out, q_out,
+                           (const uint32_t *)cur.start, (const uint32_t *)cur.j, (const uint32_t *)cur.bstart,
+                           (const uint32_t *)cur.bidx, (const uint32_t *)cur.bsrc, (const uint8_t *)cur.oany,
+                           (const float *)cur.hx, (const float *)cur.hy, (const float *)cur.hz,
+                           (const float *)cur.hw, cur.hx2, cur.hy2, cur.hz2, cur.hw2, cap, ctr, nb);
+        return true;
+    }
     // runs with fixed families (mostly dormant waves) never stage
     StepKernel kern;
     const bool r = a.rm_start != nullptr, w = a.wo_keys != nullptr;

@@ -186,6 +186,7 @@ struct DetectArgs {
     const uint32_t *dcell_start;    // [nbins+1] bin ranges of the dormant index
     const Cand *dcand;              // dormant candidates in bin order
     const float4 *dcandf;           // their FP32 copies for the prefilter
+    int32_t owner_list;     // build the owner list of each set written (AcsBuf::olist)
 };
 
 struct CdWork {
@@ -216,7 +217,15 @@ struct AcsBuf {
     uint32_t *bcur;    // [Ns+1] scratch cursor
     uint8_t *oany;     // [No] bit 0: any sphere of the owner has a row or B-list entry in this set;
                        // bit 1: the owner is in a fixed family
+    // the owners with bit 0 set, ascending (built with the flags in clump
+    // systems without fixed families, where a step with a sparse set runs
+    // them in a kernel of their own); their count is otile[owner_list_tiles(No)]
+    uint32_t *olist;   // [No]
+    uint32_t *otile;   // [owner_list_tiles(No) + 1] per-tile offsets, then the count
 };
+
+// tiles of the owner-list compaction
+int64_t owner_list_tiles(int64_t n_owners);
 
 inline void swap_hist(AcsBuf &b)
 {
@@ -249,8 +258,12 @@ void launch_dormant_index(const DetectArgs &a, CdWork &w, uint32_t *dcell_start,
 void launch_blists(AcsBuf &b, int64_t n_spheres, int64_t cap, uint32_t *partials, hipStream_t s);
 // the per-owner contact flags of a set (AcsBuf::oany) from its rows and B
 // lists (an overflowed set flags nothing)
+// With `list`, also the list of the owners with contacts (AcsBuf::olist;
+// `partials` is scan scratch).
 void launch_owner_flags(AcsBuf &b, const uint32_t *own_sph0, int64_t n_owners, int64_t n_spheres, int64_t cap,
-                        const uint8_t *ofam, const uint8_t *fixed, hipStream_t s);
+                        const uint8_t *ofam, const uint8_t *fixed, hipStream_t s, bool list = false,
+                        uint32_t *partials = nullptr);
+void launch_owner_list(AcsBuf &b, int64_t n_owners, uint32_t *partials, hipStream_t s);
 void launch_remap(const AcsBuf &oldb, AcsBuf &newb, int64_t n_spheres, DevCounters *ctr, int newbuf,
                   int rolling, hipStream_t s);
 
@@ -300,6 +313,9 @@ struct DynArgs {
     int32_t dense_rows;     // the last contact count read back was at least one per two spheres: the
                             // fused step stages its history writes in LDS (a choice of speed only:
                             // both variants give the same bits)
+    int32_t split;          // clump systems without fixed families: run the step as a streaming
+                            // kernel over every owner plus a kernel over the set's owners with
+                            // contacts (AcsBuf::olist); the same bits as the one-kernel step
 };
 
 struct StepBufs {

@@ -125,31 +125,47 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_reduce(ScanJob j0, ScanJo
     if (threadIdx.x == 0) j.partials[blockIdx.x] = tot;
 }
 
-// One block per job: partials[0..nb) <- their exclusive prefix sums.
+// One block per job: partials[0..nb) <- their exclusive prefix sums.  The
+// tile sums are taken in chunks of SPINE_THREADS * 4 consecutive values
+// (thread t holds values 4t .. 4t + 3 of the chunk, so a wave's loads are
+// contiguous): a block scan of each chunk plus the carry of the chunks
+// before it.
 __global__ void __launch_bounds__(SPINE_THREADS) k_scan_spine(ScanJob j0, ScanJob j1, int64_t nb)
 {
     __shared__ uint32_t wsum[SPINE_THREADS / 64];
     uint32_t *partials = blockIdx.y == 0 ? j0.partials : j1.partials;
-    const int64_t per = (nb + SPINE_THREADS - 1) / SPINE_THREADS;
-    const int64_t b0 = (int64_t)threadIdx.x * per;
-    uint32_t s = 0;
-    for (int64_t b = b0; b < b0 + per && b < nb; ++b) s += partials[b];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    uint32_t inc = s;
+    constexpr int64_t CHUNK = (int64_t)SPINE_THREADS * 4;
+    uint32_t carry = 0;
+    for (int64_t c0 = 0; c0 < nb; c0 += CHUNK) {
+        const int64_t i0 = c0 + 4 * (int64_t)threadIdx.x;
+        uint32_t v[4];
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t u = __shfl_up(inc, d, 64);
-        if (lane >= d) inc += u;
-    }
-    if (lane == 63) wsum[wid] = inc;
-    __syncthreads();
-    uint32_t off = 0;
-    for (int k = 0; k < wid; ++k) off += wsum[k];
-    uint32_t run = inc - s + off;
-    for (int64_t b = b0; b < b0 + per && b < nb; ++b) {
-        const uint32_t x = partials[b];
-        partials[b] = run;
-        run += x;
+        for (int k = 0; k < 4; ++k) v[k] = i0 + k < nb ? partials[i0 + k] : 0u;
+        const uint32_t s = (v[0] + v[1]) + (v[2] + v[3]);
+        uint32_t inc = s;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t u = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += u;
+        }
+        if (lane == 63) wsum[wid] = inc;
+        __syncthreads();
+        uint32_t off = 0, tot = 0;
+#pragma unroll
+        for (int k = 0; k < SPINE_THREADS / 64; ++k) {
+            const uint32_t w = wsum[k];
+            off += k < wid ? w : 0u;
+            tot += w;
+        }
+        uint32_t run = carry + off + (inc - s);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (i0 + k < nb) partials[i0 + k] = run;
+            run += v[k];
+        }
+        carry += tot;
+        __syncthreads();   // (wsum is rewritten by the next chunk)
     }
 }
 

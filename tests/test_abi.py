@@ -112,7 +112,7 @@ def test_create_rejects_bad_arguments(bad):
     elif bad == "adaptive_latency":
         kw["mode"], kw["lam"] = 3, 0
     elif bad == "dyn_path":
-        kw["dyn_path"] = 4
+        kw["dyn_path"] = 5
     elif bad == "bin_sort":
         kw["bin_sort"] = 7
     else:

@@ -321,11 +321,13 @@ def test_fused_step_equals_two_kernel_path_bitwise(dem, name):
     reactions written, then the ordered fold): state, contact set and
     history, over a delayed schedule on two streams; with its history
     writes staged per wave in LDS (path 2), not staged (3) and staged as
-    the last contact count says (0)."""
+    the last contact count says (0); and, for clump systems, as a streaming
+    kernel plus a kernel over the owners with contacts (4, and 0 when the
+    set is sparse)."""
     import torch
     s = _fused_case(name)
     out = []
-    for path in (1, 0, 2, 3):
+    for path in (1, 0, 2, 3, 4):
         c = dem.DemContext(s, mode="fixed", k=5, lam=2, dyn_path=path, capacity=64 * s.n_spheres)
         c.set_state()
         c.step(120, dyn=torch.cuda.Stream(), kin=torch.cuda.Stream())
@@ -535,6 +537,40 @@ def test_divergence_guard(dem, dyn_path):
     with pytest.raises(dem.DemError) as e:
         ctx.step(5)
     assert e.value.status == dem.DEM_ERR_DIVERGED
+
+
+@pytest.mark.parametrize("dyn_path", [3, 4])
+def test_divergence_guard_clumps(dem, dyn_path):
+    """Clump systems: a run that diverges stops with DEM_ERR_DIVERGED, and
+    every later step of the call copies the state unchanged, with one fused
+    kernel (3) and with the streaming kernel plus the kernel over the owners
+    with contacts (4): the two end in the same state."""
+    s = W.small_clumps(3, n=216, vel=0.5)
+    out = []
+    for p in (1, dyn_path):
+        ctx = dem.DemContext(s, mode="fixed", k=4, lam=2, v_error_out=0.05, dyn_path=p)
+        ctx.set_state()
+        with pytest.raises(dem.DemError) as e:
+            ctx.step(9)
+        assert e.value.status == dem.DEM_ERR_DIVERGED
+        out.append(ctx.get_state())
+        ctx.close()
+    for k in ("X", "V", "W", "q"):
+        np.testing.assert_array_equal(out[0][k], out[1][k])
+
+
+@pytest.mark.parametrize("dyn_path", [3, 4])
+def test_capacity_overflow_during_steps_stops_clumps(dem, dyn_path):
+    s = W.small_clumps(1, n=216, spacing=0.0085)
+    o = oracle.Oracle(s)
+    assert o.detect(o.state(), 0.0).size > 20
+    ctx = dem.DemContext(s, mode="every", capacity=20, dyn_path=dyn_path)
+    ctx.set_state()
+    with pytest.raises(dem.DemError) as e:
+        ctx.step(5)
+    assert e.value.status == dem.DEM_ERR_CAPACITY
+    g = ctx.get_state()
+    np.testing.assert_array_equal(g["X"], s.X)
 
 
 def test_divergence_guard_on_the_delayed_schedule(dem):
