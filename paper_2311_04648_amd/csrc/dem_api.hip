@@ -113,7 +113,8 @@ struct dem_ctx {
     OwnerRec *rec = nullptr;
     OwnerRec *rec_alt = nullptr;    // the fused step writes here, then the two swap
     double *q_alt = nullptr;
-    OwnerRec *fref_rec = nullptr;   // reference state of the learned-interval features
+    SnapRec *fref = nullptr;        // reference state of the learned-interval features
+    float *d_ovol = nullptr;        // volume of each owner's spheres (packing-fraction feature)
     double *q = nullptr;
     OwnerAux *d_aux = nullptr;
     float *d_inv_i = nullptr;
@@ -140,6 +141,15 @@ struct dem_ctx {
     std::vector<float> mlp;
     bool mlp_set = false;
     float *h_pred = nullptr;
+    // the learned schedule's decision: device output (interval, analytic
+    // bound, smallest prediction), its pinned copy, the per-block prediction
+    // minima; a decision enqueued one step ahead of its work order
+    int64_t *d_kdec = nullptr;
+    int64_t *h_kdec = nullptr;
+    float *d_pslot = nullptr;
+    hipEvent_t ev_kdec = nullptr;
+    bool prep_valid = false;
+    int64_t prep_step = -1;
     // schedule
     int64_t step = 0;
     int cur = 0;
@@ -257,7 +267,8 @@ void carve(Carver &c, dem_ctx *ctx, int64_t cap)
     int64_t No = ctx->No, Ns = ctx->Ns;
     ctx->rec = c.take<OwnerRec>(No);
     ctx->rec_alt = c.take<OwnerRec>(No);
-    ctx->fref_rec = c.take<OwnerRec>(No);
+    ctx->fref = c.take<SnapRec>(No);
+    ctx->d_ovol = c.take<float>(No);
     ctx->q = c.take<double>(4 * No);
     ctx->q_alt = c.take<double>(4 * No);
     ctx->d_aux = c.take<OwnerAux>(No);
@@ -317,6 +328,8 @@ void carve(Carver &c, dem_ctx *ctx, int64_t cap)
     ctx->d_fids = c.take<uint32_t>(ctx->ncell_cap + 1);
     ctx->d_feat = c.take<float>(DEM_MLP_NFEAT * ctx->ncell_cap);
     ctx->d_pred = c.take<float>(ctx->ncell_cap + 4);
+    ctx->d_pslot = c.take<float>(learned_slots(ctx->ncell_cap));
+    ctx->d_kdec = c.take<int64_t>(4);
     ctx->d_lab_start = c.take<uint32_t>(Ns + 1);
     ctx->d_lab_j = c.take<uint32_t>(cap);
 }
@@ -945,6 +958,9 @@ dem_status dem_bind(dem_ctx *ctx, void *device_workspace, int64_t bytes, int64_t
         memset(ctx->h_ctr, 0, sizeof(DevCounters));
     }
     if (!ctx->h_pred) HIPCHK(hipHostMalloc((void **)&ctx->h_pred, 64));
+    if (!ctx->h_kdec) HIPCHK(hipHostMalloc((void **)&ctx->h_kdec, 4 * sizeof(int64_t)));
+    if (!ctx->ev_kdec) HIPCHK(hipEventCreateWithFlags(&ctx->ev_kdec, hipEventDisableTiming));
+    ctx->prep_valid = false;
     // (the work-order events order two streams of one device: no
     // system-scope release is needed at their records)
     if (!ctx->ev_wo) HIPCHK(hipEventCreateWithFlags(&ctx->ev_wo, hipEventDisableTiming | hipEventDisableSystemFence));
@@ -970,6 +986,20 @@ dem_status dem_bind(dem_ctx *ctx, void *device_workspace, int64_t bytes, int64_t
         HIPCHK(hipMemcpy(ctx->d_inv_i, inv_i.data(), sizeof(float) * ctx->No, hipMemcpyHostToDevice));
     }
     HIPCHK(hipMemcpy(ctx->d_sph0, ctx->sph0.data(), sizeof(uint32_t) * (ctx->No + 1), hipMemcpyHostToDevice));
+    {
+        // volume of each owner's spheres, 4/3 pi r^3 summed in FP64 (overlaps
+        // of a clump's spheres counted twice), stored as float
+        std::vector<float> vol(ctx->No);
+        for (int64_t o = 0; o < ctx->No; ++o) {
+            double v = 0.0;
+            for (uint32_t q = ctx->sph0[o]; q < ctx->sph0[o + 1]; ++q) {
+                const double r = (double)ctx->sph[q].rad;
+                v += 4.18879020478639098 * r * r * r;
+            }
+            vol[o] = (float)v;
+        }
+        HIPCHK(hipMemcpy(ctx->d_ovol, vol.data(), sizeof(float) * ctx->No, hipMemcpyHostToDevice));
+    }
     HIPCHK(hipMemcpy(ctx->d_sph, ctx->sph.data(), sizeof(SphRec) * ctx->Ns, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_tpos, ctx->tpos.data(), sizeof(float) * ctx->tpos.size(), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(ctx->d_walls, ctx->walls.data(), sizeof(WallDev) * ctx->walls.size(), hipMemcpyHostToDevice));
@@ -994,6 +1024,7 @@ dem_status dem_bind(dem_ctx *ctx, void *device_workspace, int64_t bytes, int64_t
     HIPCHK(hipDeviceSynchronize());
     ctx->cur = 0;
     ctx->sched_init = false;
+    ctx->prep_valid = false;
     ctx->pending = false;
     ctx->bound = true;
     return DEM_OK;
@@ -1061,6 +1092,7 @@ dem_status dem_set_state(dem_ctx *ctx, const double *X, const double *q, const f
     ctx->has_state = true;
     ctx->cur = 0;
     ctx->sched_init = false;
+    ctx->prep_valid = false;
     ctx->pending = false;
     return DEM_OK;
 }
@@ -1175,6 +1207,7 @@ dem_status dem_detect_contacts(dem_ctx *ctx, double margin, dem_stream stream, i
     st = adopt(ctx, target, s);
     if (st != DEM_OK) return st;
     ctx->sched_init = false;
+    ctx->prep_valid = false;
     ctx->pending = false;
     if (n_contacts) {
         st = read_counters(ctx, s);
@@ -1412,6 +1445,7 @@ dem_status dem_set_contacts(dem_ctx *ctx, const uint64_t *keys, const float *his
     HIPCHK(hipMemcpyAsync(&ctx->ctr->overflow[b], &zero, 4, hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     ctx->sched_init = false;
+    ctx->prep_valid = false;
     ctx->pending = false;
     return DEM_OK;
 }
@@ -1438,6 +1472,7 @@ dem_status dem_count_missing(dem_ctx *ctx, dem_stream stream, int64_t *missing)
 // the step loop
 // ---------------------------------------------------------------------------
 int64_t learned_interval(dem_ctx *ctx, hipStream_t s);
+static void prepare_decision(dem_ctx *ctx, hipStream_t s);
 
 // Adaptive schedule: the latency of the next cycle from the timing of a
 // finished one.  The detection of cycle c took d_cd from its work order; the
@@ -1483,11 +1518,8 @@ static int64_t issue_work_order(dem_ctx *ctx, hipStream_t dyn, hipStream_t kin, 
     // the order's buffer may be the one a deferred adoption still carries
     // its history from (an order at the adoption step)
     flush_remap(ctx, dyn);
-    if (P.cd_mode == DEM_CD_LEARNED) {
-        // the learned interval measures the next features against this state
-        hipMemcpyAsync(ctx->fref_rec, ctx->rec, sizeof(OwnerRec) * ctx->No, hipMemcpyDeviceToDevice, dyn);
-        ctx->snap_step = n;
-    }
+    // (the learned interval's feature pass, which decided this order, has
+    // written the snapshot its next features are measured against)
     int64_t lam = P.cd_latency;
     int target = 1 - ctx->cur;
     DetectArgs a = detect_args(ctx, P.margin, n);
@@ -1636,6 +1668,7 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
             // close a timed run before a step that enqueues other work on
             // the dynamics stream
             const bool busy = P.cd_mode == DEM_CD_EVERY || !ctx->sched_init || P.judge || n == ctx->next_wo ||
+                              (P.cd_mode == DEM_CD_LEARNED && n + 1 == ctx->next_wo) ||
                               (ctx->pending && n == ctx->pend_swap);
             if (busy) run_close(ctx, dyn);
         }
@@ -1666,8 +1699,9 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
                 ctx->n_wo = 1;
                 ctx->interval_sum = 0.0;
                 if (P.cd_mode == DEM_CD_LEARNED) {
-                    hipMemcpyAsync(ctx->fref_rec, ctx->rec, sizeof(OwnerRec) * ctx->No, hipMemcpyDeviceToDevice, dyn);
+                    snapshot_write(ctx->rec, ctx->fref, ctx->No, dyn);
                     ctx->snap_step = n;
+                    ctx->prep_valid = false;
                 }
                 // the first interval is the fixed one: the learned interval's
                 // features (and its analytic fallback's top speed) measure
@@ -1728,11 +1762,6 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
                         ctx->next_wo = n + k;
                         k_next = -1;
                         ctx->last_wo = n;
-                        if (P.cd_mode == DEM_CD_LEARNED) {
-                            hipMemcpyAsync(ctx->fref_rec, ctx->rec, sizeof(OwnerRec) * ctx->No,
-                                           hipMemcpyDeviceToDevice, dyn);
-                            ctx->snap_step = n;
-                        }
                     }
                 }
                 if (swap_due) {
@@ -1757,9 +1786,6 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
                         if (st != DEM_OK) return st;
                         st = adopt(ctx, target, dyn, true);
                         if (st != DEM_OK) return st;
-                        hipMemcpyAsync(ctx->fref_rec, ctx->rec, sizeof(OwnerRec) * ctx->No,
-                                       hipMemcpyDeviceToDevice, dyn);
-                        ctx->snap_step = n;
                         if (ctx->n_wo > 0) ctx->interval_sum += (double)(n - ctx->last_wo);
                         ctx->last_wo = n;
                         ctx->n_wo++;
@@ -1775,6 +1801,11 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
                 }
             }
         }
+        // the learned schedule decides a work order due at the next step
+        // from the state this step reads (enqueued before the step kernel)
+        if (P.cd_mode == DEM_CD_LEARNED && ctx->sched_init && n + 1 == ctx->next_wo &&
+            (!ctx->pending || ctx->pend_swap == n + 1))
+            prepare_decision(ctx, dyn);
         DynArgs a = dyn_args(ctx, n);
         if (ctx->NM > 0) {
             // a refill of the pose ring is dynamics-stream work: no timed run spans it
@@ -1789,7 +1820,7 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
             if (!ctx->run && ctx->run_due) {
                 bool open = P.cd_mode == DEM_CD_EVERY || P.judge;
                 if (!open) {
-                    int64_t next_busy = ctx->next_wo;
+                    int64_t next_busy = ctx->next_wo - (P.cd_mode == DEM_CD_LEARNED ? 1 : 0);
                     if (ctx->pending && ctx->pend_swap < next_busy) next_busy = ctx->pend_swap;
                     open = next_busy - n >= RUN_LAUNCHES;
                 }
@@ -1886,6 +1917,11 @@ void dem_destroy(dem_ctx *ctx)
     kin_stop(ctx);
     if (ctx->h_ctr) hipHostFree(ctx->h_ctr);
     if (ctx->h_pred) hipHostFree(ctx->h_pred);
+    if (ctx->ev_kdec) {
+        hipEventSynchronize(ctx->ev_kdec);
+        hipEventDestroy(ctx->ev_kdec);
+    }
+    if (ctx->h_kdec) hipHostFree(ctx->h_kdec);
     if (ctx->ev_wo) hipEventDestroy(ctx->ev_wo);
     if (ctx->ev_cd) hipEventDestroy(ctx->ev_cd);
     if (ctx->h_capped) hipHostFree(ctx->h_capped);
@@ -1912,12 +1948,7 @@ void dem_destroy(dem_ctx *ctx)
 // ---------------------------------------------------------------------------
 // learned interval: features, MLP, policy, training-log tools
 // ---------------------------------------------------------------------------
-void feature_pipeline(const OwnerRec *rec, const OwnerRec *snap, const uint32_t *own_sph0, const SphRec *sph,
-                      Origin org, Grid fg, float h, float margin, float tau, uint32_t *raw, uint32_t *flags,
-                      uint32_t *pos, uint32_t *partials, uint32_t *cellmap, float *out, uint32_t *cell_ids,
-                      int64_t No, hipStream_t s);
 void mlp_forward(const float *params, const float *X, float *Y, int64_t n, hipStream_t s);
-void pred_min(const float *Y, int64_t n, uint32_t *out, hipStream_t s);
 void launch_label_judge(const DetectArgs &a, CdWork &w, const uint32_t *lab_start, const uint32_t *lab_j,
                         int64_t cap, const uint32_t *cellmap, uint32_t *first_miss, uint32_t t, hipStream_t s);
 void launch_detect_plain(const DetectArgs &a, CdWork &w, uint32_t *start, uint32_t *j, int64_t cap,
@@ -1927,25 +1958,48 @@ static void run_features(dem_ctx *ctx, hipStream_t s, float *out, uint32_t *cell
 {
     float tau = (float)(ctx->step - ctx->snap_step);
     float margin = (float)(ctx->P.margin > 0.0 ? ctx->P.margin : 1e-6);
-    feature_pipeline(ctx->rec, ctx->fref_rec, ctx->d_sph0, ctx->d_sph, ctx->org, ctx->fgrid, (float)ctx->P.dt,
-                     margin, tau, ctx->d_fraw, ctx->d_fflag, ctx->d_fpos, ctx->cdD.partials, ctx->d_cellmap, out,
-                     cell_ids, ctx->No, s);
+    feature_pipeline(ctx->rec, ctx->fref, ctx->d_ovol, ctx->org, ctx->fgrid, (float)ctx->P.dt, margin, tau,
+                     ctx->d_fraw, ctx->d_fflag, ctx->d_fpos, ctx->cdD.partials, ctx->d_cellmap, out, cell_ids, ctx->No,
+                     s);
 }
 
-// Analytic interval: the largest n with (k+lambda) steps of motion at the
-// current top speed plus gravity staying inside the margin,
-// v t + g t^2 / 2 < m with t = (n + lambda) h.
-static int64_t analytic_interval(dem_ctx *ctx, double vmax)
+// Enqueues the learned schedule's decision from the current state on s
+// (features against the snapshot, which the state then replaces; the
+// network; the interval, with the analytic bound as its fallback), its
+// copy to pinned host memory and an event after it.
+static void enqueue_decision(dem_ctx *ctx, hipStream_t s)
 {
     const dem_params &P = ctx->P;
-    double g = std::sqrt(P.gravity[0] * P.gravity[0] + P.gravity[1] * P.gravity[1] + P.gravity[2] * P.gravity[2]);
-    double m = P.margin;
-    double t;
-    if (g > 0.0) t = (-vmax + std::sqrt(vmax * vmax + 2.0 * g * m)) / g;
-    else t = vmax > 0.0 ? m / vmax : 1e30;
-    double n = std::floor(t / P.dt) - (double)P.cd_latency;
-    int64_t k = n < 1.0 ? 1 : (n > 1e9 ? (int64_t)1e9 : (int64_t)n);
-    return std::min<int64_t>(k, P.cd_interval_max);
+    LearnedArgs p;
+    p.g = std::sqrt(P.gravity[0] * P.gravity[0] + P.gravity[1] * P.gravity[1] + P.gravity[2] * P.gravity[2]);
+    p.margin = P.margin;
+    p.dt = P.dt;
+    p.safety = P.mlp_safety > 0.0 ? P.mlp_safety : 1.0;
+    p.vmesh = ctx->vmesh;
+    p.lam = P.cd_latency;
+    p.kmax = P.cd_interval_max;
+    p.use_model = ctx->mlp_set ? 1 : 0;
+    p.meshes = ctx->NM > 0 ? 1 : 0;
+    p.speed_valid = ctx->step > 0 ? 1 : 0;
+    const float tau = (float)(ctx->step - ctx->snap_step);
+    const float margin = (float)(P.margin > 0.0 ? P.margin : 1e-6);
+    const DynArgs da = dyn_args(ctx, ctx->step);
+    learned_decide(ctx->rec, ctx->fref, ctx->d_ovol, ctx->org, ctx->fgrid, (float)P.dt, margin, tau, ctx->d_fraw,
+                   ctx->d_mlp, ctx->d_pslot, ctx->d_blkmax, speed_slots(da), p, ctx->d_kdec, ctx->No, s);
+    if (ctx->mlp_set) ctx->snap_step = ctx->step;
+    hipMemcpyAsync(ctx->h_kdec, ctx->d_kdec, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    hipEventRecord(ctx->ev_kdec, s);
+}
+
+// The learned schedule one step ahead: the decision for a work order due at
+// the next step is enqueued before this step's kernel, from the state this
+// step reads, and read back at the order (the host waits only for a copy
+// enqueued a whole step earlier, so the dynamics stream does not drain).
+static void prepare_decision(dem_ctx *ctx, hipStream_t s)
+{
+    enqueue_decision(ctx, s);
+    ctx->prep_valid = true;
+    ctx->prep_step = ctx->step;
 }
 
 // Decides the next detection interval at a work order (LEARNED mode): the
@@ -1953,37 +2007,15 @@ static int64_t analytic_interval(dem_ctx *ctx, double vmax)
 // the minimum over cells, scaled by the model's calibrated safety factor,
 // minus the adoption latency is the interval.  The analytic bound is the
 // fallback when no model is installed or its prediction is not finite.
-// Synchronises `s`.
+// Uses the decision prepared at the step before, if there is one; else
+// enqueues it now and waits for it.
 int64_t learned_interval(dem_ctx *ctx, hipStream_t s)
 {
-    // top speed of the last integrated step
-    DynArgs da = dyn_args(ctx, ctx->step);
-    launch_reduce_max(da, ctx->ctr, s);
-    if (read_counters(ctx, s) != DEM_OK) return 1;
-    float v2;
-    uint32_t bits = ctx->h_ctr->maxv2[0];
-    std::memcpy(&v2, &bits, 4);
-    double vmax = ctx->step > 0 && v2 == v2 ? std::sqrt((double)v2) : 0.0;
-    // a facet closes a gap at the speed of its mesh: the bound takes the
-    // faster of the spheres and the meshes
-    int64_t k_an = analytic_interval(ctx, std::max(vmax, ctx->vmesh));
-    if (!ctx->mlp_set) return k_an;
-    run_features(ctx, s, ctx->d_feat, nullptr);
-    uint32_t ncell = 0;
-    hipMemcpyAsync(&ncell, ctx->d_fpos + ctx->fgrid.nbins, 4, hipMemcpyDeviceToHost, s);
-    hipStreamSynchronize(s);
-    mlp_forward(ctx->d_mlp, ctx->d_feat, ctx->d_pred, ncell, s);
-    pred_min(ctx->d_pred, ncell, reinterpret_cast<uint32_t *>(ctx->d_pred + ctx->ncell_cap), s);
-    hipMemcpyAsync(ctx->h_pred, ctx->d_pred + ctx->ncell_cap, 4, hipMemcpyDeviceToHost, s);
-    hipStreamSynchronize(s);
-    float R = ctx->h_pred[0];
-    if (!(R >= 0.0f) || !std::isfinite(R) || ncell == 0) return k_an;   // fallback
-    double safety = ctx->P.mlp_safety > 0.0 ? ctx->P.mlp_safety : 1.0;
-    double kl = std::floor(safety * (double)R) - (double)ctx->P.cd_latency - 1.0;
-    int64_t k = kl < 1.0 ? 1 : (int64_t)std::min(kl, 1e9);
-    // the features see only the spheres: mesh motion is bounded analytically
-    if (ctx->NM > 0) k = std::min(k, analytic_interval(ctx, ctx->vmesh));
-    return std::min<int64_t>(k, ctx->P.cd_interval_max);
+    if (!(ctx->prep_valid && ctx->prep_step + 1 == ctx->step)) enqueue_decision(ctx, s);
+    ctx->prep_valid = false;
+    hipEventSynchronize(ctx->ev_kdec);
+    const int64_t k = ctx->h_kdec[0];
+    return k < 1 ? 1 : k;
 }
 
 extern "C" {
@@ -2010,8 +2042,10 @@ dem_status dem_snapshot(dem_ctx *ctx, dem_stream stream)
         return DEM_ERR_STATE;
     }
     hipStream_t s = S(stream);
-    HIPCHK(hipMemcpyAsync(ctx->fref_rec, ctx->rec, sizeof(OwnerRec) * ctx->No, hipMemcpyDeviceToDevice, s));
+    snapshot_write(ctx->rec, ctx->fref, ctx->No, s);
+    HIPCHK(hipGetLastError());
     ctx->snap_step = ctx->step;
+    ctx->prep_valid = false;
     return DEM_OK;
 }
 

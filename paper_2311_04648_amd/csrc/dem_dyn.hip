@@ -1146,8 +1146,18 @@ __global__ void __launch_bounds__(TPB, 3) k_step_listed(DynArgs a, const uint32_
 
 __global__ void __launch_bounds__(256) k_reduce_max(const float *blkmax, int64_t n, DevCounters *ctr)
 {
+    // eight independent loads in flight per thread
     float m = 0.0f;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, blkmax[i]);
+    const int64_t bs = blockDim.x;
+    int64_t i = threadIdx.x;
+    for (; i + 7 * bs < n; i += 8 * bs) {
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = blkmax[i + k * bs];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) m = fmaxf(m, v[k]);
+    }
+    for (; i < n; i += bs) m = fmaxf(m, blkmax[i]);
     for (int d = 32; d > 0; d >>= 1) m = fmaxf(m, __shfl_xor(m, d, 64));
     __shared__ float w[4];
     if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = m;
@@ -1208,6 +1218,11 @@ void launch_noop(hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 void launch_adaptive_margin(DevCounters *ctr, double t, double gmag, double cap, double vfloor, hipStream_t s)
 {
     hipLaunchKernelGGL(k_adaptive_margin, dim3(1), dim3(64), 0, s, ctr, t, gmag, cap, vfloor);
+}
+
+int64_t speed_slots(const DynArgs &a)
+{
+    return (int64_t)step_blocks(a) + 1;
 }
 
 void launch_reduce_max(const DynArgs &a, DevCounters *ctr, hipStream_t s)

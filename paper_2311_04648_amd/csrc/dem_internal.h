@@ -35,6 +35,16 @@ struct __align__(16) OwnerAux {
     int32_t tmpl;      // -1: single sphere at the owner centre
 };
 
+// Reference state of the learned-interval features: an owner's position
+// and velocity at the previous feature pass (the features measure motion
+// since then).
+struct __align__(16) SnapRec {
+    uint64_t vox;
+    float off[3];
+    float v[3];
+};
+static_assert(sizeof(SnapRec) == 32, "snapshot record must be 32 bytes");
+
 struct __align__(16) SphRec {
     uint32_t owner;
     float rad;
@@ -348,6 +358,35 @@ void launch_fix_owners(OwnerRec *rec, OwnerRec *rec_alt, const double *q, double
                        const uint8_t *fixed, int64_t n_owners, hipStream_t s);
 void launch_adaptive_margin(DevCounters *ctr, double t, double gmag, double cap, double vfloor, hipStream_t s);
 void launch_reduce_max(const DynArgs &a, DevCounters *ctr, hipStream_t s);
+
+// Inputs of the learned schedule's decision on the device (k_learned_decide).
+struct LearnedArgs {
+    double g;           // |gravity|
+    double margin;
+    double dt;
+    double safety;      // factor on the predicted horizon
+    double vmesh;       // fastest point of any mesh
+    int64_t lam;        // adoption latency (steps)
+    int64_t kmax;       // largest interval
+    int32_t use_model;  // a network is installed: predict; else the analytic bound
+    int32_t meshes;     // the system has meshes (their analytic bound caps the prediction)
+    int32_t speed_valid;// the top speed of the last integration is meaningful (a step was taken)
+};
+
+// Learned interval (dem_mlp.hip): the features, the network and the
+// decision on the device, writing out[0] = the next interval, out[1] = the
+// analytic bound, out[2] = the bits of the smallest prediction; the
+// snapshot is overwritten by the current state.
+void learned_decide(const OwnerRec *rec, SnapRec *snap, const float *ovol, Origin org, Grid fg, float h,
+                    float margin, float tau, uint32_t *raw, const float *params, float *pslot, const float *blkmax,
+                    int64_t nblk, const LearnedArgs &p, int64_t *out, int64_t No, hipStream_t s);
+int64_t learned_slots(int64_t ncell);
+void snapshot_write(const OwnerRec *rec, SnapRec *snap, int64_t No, hipStream_t s);
+void feature_pipeline(const OwnerRec *rec, const SnapRec *snap, const float *ovol, Origin org, Grid fg, float h,
+                      float margin, float tau, uint32_t *raw, uint32_t *flags, uint32_t *pos, uint32_t *partials,
+                      uint32_t *cellmap, float *out, uint32_t *cell_ids, int64_t No, hipStream_t s);
+// number of slots of the per-block |v|^2 maxima the last step wrote
+int64_t speed_slots(const DynArgs &a);
 
 // message of the last failed context-free call on this host thread
 const char *free_call_error();

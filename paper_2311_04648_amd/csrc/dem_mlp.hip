@@ -228,92 +228,177 @@ __global__ void __launch_bounds__(256) k_feat_clear(uint32_t *raw, int64_t ncell
     for (int k = 6; k < RAW; ++k) r[k] = 0u;
 }
 
-// Per-owner contributions to its feature cell.  Owners are numbered in
-// space-filling order often enough that the lanes of a wave share few cells,
-// so each wave first combines the values of its lanes per distinct cell
-// (integer max / min / sums over shuffles, order-free) and one lane per
-// cell issues the atomics.
-__global__ void __launch_bounds__(256) k_feat_accum(const OwnerRec *rec, const OwnerRec *snap, const uint32_t *own_sph0,
-                                                   const SphRec *sph, Origin org, Grid fg, uint32_t *raw,
+// Per-owner contributions to its feature cell.  Each block takes
+// FEAT_OWNERS consecutive owners, each wave 64 consecutive ones at a time.
+// Consecutive owners are mostly spatial neighbours, so the lanes of a wave
+// fall into a few runs of equal cells: a segmented scan over the lanes
+// (integer max / min / sums, order-free) combines each run, and the last
+// lane of a run adds it to the block's table of cells in LDS (LDS atomics,
+// open addressing on the cell id); when the block is done, each cell of
+// its table goes to the global accumulators with one atomic per value.  A
+// cell that finds the table full goes straight to the global accumulators.
+// With snap_out set, each owner's current position and velocity are
+// written there after its snapshot is read (snap_out may equal snap: the
+// thread that reads a record writes it).  With cellmap set, each owner's
+// cell is written there (the training-log tools use it).
+constexpr int FEAT_WAVE_ITERS = 8;
+constexpr int64_t FEAT_OWNERS = 4 * 64 * FEAT_WAVE_ITERS;   // 2048
+constexpr int FEAT_SLOTS = 512;
+constexpr uint32_t FEAT_EMPTY = 0xffffffffu;
+constexpr int FEAT_VALS = 12;   // vmax x3, vmin x3, dv, va, dx, count, volume (2 words)
+
+__device__ inline void feat_global_add(uint32_t *rw, const uint32_t *a, unsigned long long vol)
+{
+    for (int k = 0; k < 3; ++k) {
+        atomicMax(&rw[k], a[k]);
+        atomicMin(&rw[3 + k], a[3 + k]);
+    }
+    atomicMax(&rw[6], a[6]);
+    atomicMax(&rw[7], a[7]);
+    atomicMax(&rw[8], a[8]);
+    atomicAdd(&rw[9], a[9]);
+    atomicAdd(reinterpret_cast<unsigned long long *>(&rw[10]), vol);
+}
+
+__global__ void __launch_bounds__(256) k_feat_accum(const OwnerRec *rec, const SnapRec *snap, SnapRec *snap_out,
+                                                   const float *ovol, Origin org, Grid fg, uint32_t *raw,
                                                    uint32_t *cellmap, int64_t No)
 {
-    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = o < No;
-    uint32_t c = 0xffffffffu;
-    uint32_t vmax[3] = {0u, 0u, 0u}, vmin[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu};
-    uint32_t fdv = 0u, fva = 0u, fdx = 0u, cnt = 0u;
-    unsigned long long iv = 0ull;
-    if (valid) {
-        OwnerRec r = load_rec(rec + o);
-        OwnerRec s = load_rec(snap + o);
-        double X[3], Xs[3];
-        for (int k = 0; k < 3; ++k) {
-            X[k] = decode_axis(r.vox, r.off[k], org.o[k], k);
-            Xs[k] = decode_axis(s.vox, s.off[k], org.o[k], k);
+    __shared__ uint32_t tkey[FEAT_SLOTS];
+    __shared__ uint32_t tval[FEAT_SLOTS][10];
+    __shared__ unsigned long long tvol[FEAT_SLOTS];
+    __shared__ uint4 lrec[4][192];
+    for (int k = threadIdx.x; k < FEAT_SLOTS; k += blockDim.x) {
+        tkey[k] = FEAT_EMPTY;
+        for (int j = 0; j < 3; ++j) {
+            tval[k][j] = 0u;
+            tval[k][3 + j] = 0xffffffffu;
         }
-        c = fcell_of(fg, X[0], X[1], X[2]);
-        cellmap[o] = c;
-        for (int k = 0; k < 3; ++k) {
-            const uint32_t e = ord_enc(r.v[k]);
-            vmax[k] = e;
-            vmin[k] = e;
-        }
-        float dv0 = r.v[0] - s.v[0], dv1 = r.v[1] - s.v[1], dv2 = r.v[2] - s.v[2];
-        float dv = sqrtf((dv0 * dv0 + dv1 * dv1) + dv2 * dv2);
-        float va = sqrtf((r.v[0] * r.v[0] + r.v[1] * r.v[1]) + r.v[2] * r.v[2]);
-        double d0 = X[0] - Xs[0], d1 = X[1] - Xs[1], d2 = X[2] - Xs[2];
-        float dx = (float)sqrt((d0 * d0 + d1 * d1) + d2 * d2);
-        fdv = __float_as_uint(dv);
-        fva = __float_as_uint(va);
-        fdx = __float_as_uint(dx);
-        cnt = 1u;
-        double vol = 0.0;
-        for (uint32_t q = own_sph0[o]; q < own_sph0[o + 1]; ++q) {
-            double rr = (double)sph[q].rad;
-            vol += 4.18879020478639098 * rr * rr * rr;
-        }
-        // fixed-point volume in units of 1e-18 m^3
-        iv = (unsigned long long)(vol * 1e18 + 0.5);
+        for (int j = 6; j < 10; ++j) tval[k][j] = 0u;
+        tvol[k] = 0ull;
     }
-    const int lane = (int)(threadIdx.x & 63);
-    unsigned long long todo = __ballot(valid);
-    while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const uint32_t cl = __shfl(c, leader, 64);
-        const bool mine = valid && c == cl;
-        const unsigned long long grp = __ballot(mine);
-        uint32_t a[11];
-        for (int k = 0; k < 3; ++k) {
-            a[k] = mine ? vmax[k] : 0u;
-            a[3 + k] = mine ? vmin[k] : 0xffffffffu;
+    __syncthreads();
+    const int lane = (int)(threadIdx.x & 63u);
+    const int wv = (int)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int it = 0; it < FEAT_WAVE_ITERS; ++it) {
+        const int64_t ow = (int64_t)blockIdx.x * FEAT_OWNERS + (int64_t)(wv * FEAT_WAVE_ITERS + it) * 64;
+        if (ow >= No) break;
+        const int64_t o = ow + lane;
+        const bool valid = o < No;
+        const uint32_t nv = (uint32_t)(No - ow < 64 ? No - ow : 64);
+        // the wave's records through LDS: three contiguous 1 KiB loads
+        {
+            const uint4 *src = reinterpret_cast<const uint4 *>(rec + ow);
+            for (uint32_t k = lane; k < 3u * nv; k += 64u) lrec[wv][k] = src[k];
         }
-        a[6] = mine ? fdv : 0u;
-        a[7] = mine ? fva : 0u;
-        a[8] = mine ? fdx : 0u;
-        a[9] = mine ? cnt : 0u;
-        unsigned long long sv = mine ? iv : 0ull;
-        for (int d = 32; d > 0; d >>= 1) {
+        SnapRec sr{};
+        float vo = 0.0f;
+        if (valid) {
+            sr = snap[o];
+            vo = ovol[o];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        uint32_t c = FEAT_EMPTY;
+        uint32_t a[10] = {0u, 0u, 0u, 0xffffffffu, 0xffffffffu, 0xffffffffu, 0u, 0u, 0u, 0u};
+        unsigned long long iv = 0ull;
+        if (valid) {
+            const OwnerRec r = load_rec(reinterpret_cast<const OwnerRec *>(lrec[wv]) + lane);
+            double X[3], Xs[3];
             for (int k = 0; k < 3; ++k) {
-                a[k] = max(a[k], (uint32_t)__shfl_xor(a[k], d, 64));
-                a[3 + k] = min(a[3 + k], (uint32_t)__shfl_xor(a[3 + k], d, 64));
+                X[k] = decode_axis(r.vox, r.off[k], org.o[k], k);
+                Xs[k] = decode_axis(sr.vox, sr.off[k], org.o[k], k);
             }
-            for (int k = 6; k < 9; ++k) a[k] = max(a[k], (uint32_t)__shfl_xor(a[k], d, 64));
-            a[9] += (uint32_t)__shfl_xor(a[9], d, 64);
-            sv += (unsigned long long)__shfl_xor((long long)sv, d, 64);
-        }
-        if (lane == leader) {
-            uint32_t *rw = raw + (int64_t)cl * RAW;
+            c = fcell_of(fg, X[0], X[1], X[2]);
+            if (cellmap) cellmap[o] = c;
             for (int k = 0; k < 3; ++k) {
-                atomicMax(&rw[k], a[k]);
-                atomicMin(&rw[3 + k], a[3 + k]);
+                const uint32_t e = ord_enc(r.v[k]);
+                a[k] = e;
+                a[3 + k] = e;
             }
-            atomicMax(&rw[6], a[6]);
-            atomicMax(&rw[7], a[7]);
-            atomicMax(&rw[8], a[8]);
-            atomicAdd(&rw[9], a[9]);
-            atomicAdd(reinterpret_cast<unsigned long long *>(&rw[10]), sv);
+            const float dv0 = r.v[0] - sr.v[0], dv1 = r.v[1] - sr.v[1], dv2 = r.v[2] - sr.v[2];
+            const float dv = sqrtf((dv0 * dv0 + dv1 * dv1) + dv2 * dv2);
+            const float va = sqrtf((r.v[0] * r.v[0] + r.v[1] * r.v[1]) + r.v[2] * r.v[2]);
+            const double d0 = X[0] - Xs[0], d1 = X[1] - Xs[1], d2 = X[2] - Xs[2];
+            const float dx = (float)sqrt((d0 * d0 + d1 * d1) + d2 * d2);
+            a[6] = __float_as_uint(dv);
+            a[7] = __float_as_uint(va);
+            a[8] = __float_as_uint(dx);
+            a[9] = 1u;
+            // fixed-point volume in units of 1e-18 m^3
+            iv = (unsigned long long)((double)vo * 1e18 + 0.5);
+            if (snap_out) {
+                SnapRec nw;
+                nw.vox = r.vox;
+                for (int k = 0; k < 3; ++k) {
+                    nw.off[k] = r.off[k];
+                    nw.v[k] = r.v[k];
+                }
+                snap_out[o] = nw;
+            }
         }
-        todo &= ~grp;
+        // runs of equal cells over the lanes; the scan combines each run
+        const uint32_t cprev = (uint32_t)__shfl_up((int)c, 1, 64);
+        const bool head = lane == 0 || cprev != c;
+        const uint64_t heads = __ballot(head);
+        const int seg0 = 63 - __clzll((long long)(heads & (below | (1ull << lane))));
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const bool take = lane - d >= seg0;
+            uint32_t t[10];
+#pragma unroll
+            for (int k = 0; k < 10; ++k) t[k] = (uint32_t)__shfl_up((int)a[k], d, 64);
+            const unsigned long long tv = (unsigned long long)__shfl_up((long long)iv, d, 64);
+            if (take) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    a[k] = max(a[k], t[k]);
+                    a[3 + k] = min(a[3 + k], t[3 + k]);
+                }
+                a[6] = max(a[6], t[6]);
+                a[7] = max(a[7], t[7]);
+                a[8] = max(a[8], t[8]);
+                a[9] += t[9];
+                iv += tv;
+            }
+        }
+        const uint32_t cnext = (uint32_t)__shfl_down((int)c, 1, 64);
+        const bool tail = valid && (lane == 63 || cnext != c || !(o + 1 < No));
+        if (tail) {
+            uint32_t h = (c * 2654435761u) >> 23;   // 9 bits: FEAT_SLOTS slots
+            int probe = 0;
+            for (; probe < FEAT_SLOTS; ++probe) {
+                const uint32_t old = atomicCAS(&tkey[h], FEAT_EMPTY, c);
+                if (old == FEAT_EMPTY || old == c) break;
+                h = (h + 1u) & (FEAT_SLOTS - 1);
+            }
+            if (probe < FEAT_SLOTS) {
+                for (int k = 0; k < 3; ++k) {
+                    atomicMax(&tval[h][k], a[k]);
+                    atomicMin(&tval[h][3 + k], a[3 + k]);
+                }
+                atomicMax(&tval[h][6], a[6]);
+                atomicMax(&tval[h][7], a[7]);
+                atomicMax(&tval[h][8], a[8]);
+                atomicAdd(&tval[h][9], a[9]);
+                atomicAdd(&tvol[h], iv);
+            } else {
+                feat_global_add(raw + (int64_t)c * RAW, a, iv);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < FEAT_SLOTS; k += blockDim.x) {
+        const uint32_t c = tkey[k];
+        if (c == FEAT_EMPTY) continue;
+        uint32_t a[10];
+        for (int j = 0; j < 10; ++j) a[j] = tval[k][j];
+        feat_global_add(raw + (int64_t)c * RAW, a, tvol[k]);
     }
 }
 
@@ -350,35 +435,161 @@ __global__ void __launch_bounds__(256) k_feat_write(const uint32_t *raw, const u
     if (cell_ids) cell_ids[p] = (uint32_t)c;
 }
 
-// Minimum predicted remaining steps over cells: R = exp(y) - 1 (targets are
-// log(1 + steps)), clamped at >= 0; order-free atomic minimum on float bits.
-__global__ void __launch_bounds__(256) k_pred_min(const float *Y, int64_t n, uint32_t *out)
+// The features of every occupied cell straight into the network (the same
+// arithmetic as k_feat_write and k_mlp_forward), the predicted remaining
+// steps R = exp(y) - 1 of each (clamped at >= 0), and the minimum over the
+// block's cells into slot[blockIdx.x] (3e38 when the block has none).
+__device__ inline void feat_of_cell(const uint32_t *r, float h, float margin, float tau, float K, float cell_vol,
+                                    float *f)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    float r = 3.0e38f;
-    if (i < n) {
-        float y = Y[i];
-        r = expf(y) - 1.0f;
-        if (!(r >= 0.0f)) r = 0.0f;
+    float vr[3];
+    for (int k = 0; k < 3; ++k) vr[k] = ord_dec(r[k]) - ord_dec(r[3 + k]);
+    const float spread = sqrtf((vr[0] * vr[0] + vr[1] * vr[1]) + vr[2] * vr[2]);
+    const float dv = __uint_as_float(r[6]), va = __uint_as_float(r[7]), dx = __uint_as_float(r[8]);
+    const unsigned long long iv = *reinterpret_cast<const unsigned long long *>(r + 10);
+    const float vol = (float)((double)iv * 1e-18);
+    const float t = tau < 1.0f ? 1.0f : tau;
+    f[0] = log1pf(spread * h * K / margin);
+    f[1] = log1pf(dv * K * K * h / (2.0f * t * margin));
+    f[2] = vol / cell_vol;
+    f[3] = tau / K;
+    f[4] = log1pf(va * h * K / margin);
+    f[5] = log1pf(dx / margin);
+}
+
+__global__ void __launch_bounds__(256) k_feat_predict(const uint32_t *raw, int64_t ncell, float h, float margin,
+                                                     float tau, float K, float cell_vol, const float *params,
+                                                     float *slot)
+{
+    __shared__ float sp[NPARAM];
+    load_params(params, sp);
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float rr = 3.0e38f;
+    if (c < ncell && raw[c * RAW + 9] > 0u) {
+        float x[NF], h1[H], h2[H];
+        feat_of_cell(raw + c * RAW, h, margin, tau, K, cell_vol, x);
+        const float y = mlp_eval(sp, x, h1, h2);
+        rr = expf(y) - 1.0f;
+        if (!(rr >= 0.0f)) rr = 0.0f;
     }
-    for (int d = 32; d > 0; d >>= 1) r = fminf(r, __shfl_xor(r, d, 64));
-    if ((threadIdx.x & 63) == 0) atomicMin(out, __float_as_uint(r));
+    __shared__ float wmin[4];
+    for (int d = 32; d > 0; d >>= 1) rr = fminf(rr, __shfl_xor(rr, d, 64));
+    if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = rr;
+    __syncthreads();
+    if (threadIdx.x == 0) slot[blockIdx.x] = fminf(fminf(wmin[0], wmin[1]), fminf(wmin[2], wmin[3]));
+}
+
+// Analytic interval: the largest n with (n + lambda) steps of motion at speed
+// v plus gravity staying inside the margin, v t + g t^2 / 2 < m with
+// t = (n + lambda) h; at least 1, at most kmax.
+__device__ inline int64_t analytic_steps(const LearnedArgs &p, double v)
+{
+    double t;
+    if (p.g > 0.0) t = (-v + sqrt(v * v + 2.0 * p.g * p.margin)) / p.g;
+    else t = v > 0.0 ? p.margin / v : 1e30;
+    const double n = floor(t / p.dt) - (double)p.lam;
+    const int64_t k = n < 1.0 ? 1 : (n > 1e9 ? (int64_t)1e9 : (int64_t)n);
+    return k < p.kmax ? k : p.kmax;
+}
+
+// The interval of the next work order, decided on the device: from the top
+// speed of the last integration (blkmax, nblk slots) the analytic bound;
+// with a model, the minimum over cells of the predicted remaining steps
+// (pslot, npslot slots), scaled by the safety factor, less the adoption
+// latency and one step (the analytic bound of the meshes caps it; the
+// analytic bound replaces it when no cell is occupied or the minimum is not
+// finite).  out[0] = the interval, out[1] = the analytic bound, out[2] the
+// bits of R (float).
+__global__ void __launch_bounds__(256) k_learned_decide(const float *blkmax, int64_t nblk, const float *pslot,
+                                                       int64_t npslot, LearnedArgs p, int64_t *out)
+{
+    float v2 = 0.0f, R = 3.0e38f;
+    // eight independent loads in flight per thread
+    const int64_t bs = blockDim.x;
+    int64_t i = threadIdx.x;
+    for (; i + 7 * bs < nblk; i += 8 * bs) {
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = blkmax[i + k * bs];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v2 = fmaxf(v2, v[k]);
+    }
+    for (; i < nblk; i += bs) v2 = fmaxf(v2, blkmax[i]);
+    for (i = threadIdx.x; i + 7 * bs < npslot; i += 8 * bs) {
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = pslot[i + k * bs];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) R = fminf(R, v[k]);
+    }
+    for (; i < npslot; i += bs) R = fminf(R, pslot[i]);
+    for (int d = 32; d > 0; d >>= 1) {
+        v2 = fmaxf(v2, __shfl_xor(v2, d, 64));
+        R = fminf(R, __shfl_xor(R, d, 64));
+    }
+    __shared__ float wv2[4], wr[4];
+    if ((threadIdx.x & 63) == 0) {
+        wv2[threadIdx.x >> 6] = v2;
+        wr[threadIdx.x >> 6] = R;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    v2 = fmaxf(fmaxf(wv2[0], wv2[1]), fmaxf(wv2[2], wv2[3]));
+    R = fminf(fminf(wr[0], wr[1]), fminf(wr[2], wr[3]));
+    const double vmax = p.speed_valid && v2 == v2 ? sqrt((double)v2) : 0.0;
+    const int64_t k_an = analytic_steps(p, fmax(vmax, p.vmesh));
+    int64_t k = k_an;
+    if (p.use_model && R >= 0.0f && R < 1.0e38f) {
+        const double kl = floor(p.safety * (double)R) - (double)p.lam - 1.0;
+        k = kl < 1.0 ? 1 : (int64_t)fmin(kl, 1e9);
+        if (p.meshes) {
+            const int64_t km = analytic_steps(p, p.vmesh);
+            k = k < km ? k : km;
+        }
+        k = k < p.kmax ? k : p.kmax;
+    }
+    out[0] = k;
+    out[1] = k_an;
+    out[2] = (int64_t)__float_as_uint(R);
+}
+
+__global__ void __launch_bounds__(256) k_snap_write(const OwnerRec *rec, SnapRec *snap, int64_t No)
+{
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= No) return;
+    const OwnerRec r = load_rec(rec + o);
+    SnapRec s;
+    s.vox = r.vox;
+    for (int k = 0; k < 3; ++k) {
+        s.off[k] = r.off[k];
+        s.v[k] = r.v[k];
+    }
+    snap[o] = s;
 }
 
 }  // namespace
 
-// Feature pipeline used by both dem_features and the learned schedule.
-// Writes features of occupied cells to `out` (row-major, cell order) and
-// their count to `*ncell_dev`; cellmap[o] receives each owner's cell.
-void feature_pipeline(const OwnerRec *rec, const OwnerRec *snap, const uint32_t *own_sph0, const SphRec *sph,
-                      Origin org, Grid fg, float h, float margin, float tau, uint32_t *raw, uint32_t *flags,
-                      uint32_t *pos, uint32_t *partials, uint32_t *cellmap, float *out, uint32_t *cell_ids,
-                      int64_t No, hipStream_t s)
+// Feature pipeline used by both dem_features and the learned schedule:
+// the per-cell accumulators of the owners' contributions (see k_feat_accum).
+static void feature_accumulate(const OwnerRec *rec, const SnapRec *snap, SnapRec *snap_out, const float *ovol,
+                               Origin org, Grid fg, uint32_t *raw, uint32_t *cellmap, int64_t No, hipStream_t s)
+{
+    const int64_t nc = (int64_t)fg.nbins;
+    hipLaunchKernelGGL(k_feat_clear, dim3(nblocks(nc, 256)), dim3(256), 0, s, raw, nc);
+    const int64_t nb = (No + FEAT_OWNERS - 1) / FEAT_OWNERS;
+    if (nb > 0)
+        hipLaunchKernelGGL(k_feat_accum, dim3((unsigned)nb), dim3(256), 0, s, rec, snap, snap_out, ovol, org, fg, raw,
+                           cellmap, No);
+}
+
+// Features of occupied cells written to `out` (row-major, cell order) and
+// their count to pos[ncell]; cellmap[o] receives each owner's cell.
+void feature_pipeline(const OwnerRec *rec, const SnapRec *snap, const float *ovol, Origin org, Grid fg, float h,
+                      float margin, float tau, uint32_t *raw, uint32_t *flags, uint32_t *pos, uint32_t *partials,
+                      uint32_t *cellmap, float *out, uint32_t *cell_ids, int64_t No, hipStream_t s)
 {
     int64_t nc = (int64_t)fg.nbins;
-    hipLaunchKernelGGL(k_feat_clear, dim3(nblocks(nc, 256)), dim3(256), 0, s, raw, nc);
-    hipLaunchKernelGGL(k_feat_accum, dim3(nblocks(No, 256)), dim3(256), 0, s, rec, snap, own_sph0, sph, org, fg,
-                       raw, cellmap, No);
+    feature_accumulate(rec, snap, nullptr, ovol, org, fg, raw, cellmap, No, s);
     hipLaunchKernelGGL(k_feat_flags, dim3(nblocks(nc, 256)), dim3(256), 0, s, raw, nc, flags);
     scan_exclusive_u32(flags, pos, nc, partials, s);
     double edge = 1.0 / fg.inv_b;
@@ -387,18 +598,45 @@ void feature_pipeline(const OwnerRec *rec, const OwnerRec *snap, const uint32_t 
                        (float)DEM_MLP_KCAP, cell_vol, out, cell_ids);
 }
 
+// Slots of per-block prediction minima needed for ncell cells.
+int64_t learned_slots(int64_t ncell)
+{
+    return (ncell + 255) / 256 + 1;
+}
+
+// The learned schedule's decision, all on the device (nothing read back
+// here): with a model, the features of the current state against the
+// snapshot (written over by the current state), the network on every
+// occupied cell and the minimum of the predictions; then the interval
+// (k_learned_decide) into out[0..2].
+void learned_decide(const OwnerRec *rec, SnapRec *snap, const float *ovol, Origin org, Grid fg, float h,
+                    float margin, float tau, uint32_t *raw, const float *params, float *pslot, const float *blkmax,
+                    int64_t nblk, const LearnedArgs &p, int64_t *out, int64_t No, hipStream_t s)
+{
+    const int64_t nc = (int64_t)fg.nbins;
+    int64_t np = 0;
+    if (p.use_model) {
+        feature_accumulate(rec, snap, snap, ovol, org, fg, raw, nullptr, No, s);
+        double edge = 1.0 / fg.inv_b;
+        const float cell_vol = (float)(edge * edge * edge);
+        np = (nc + 255) / 256;
+        hipLaunchKernelGGL(k_feat_predict, dim3((unsigned)(np > 0 ? np : 1)), dim3(256), 0, s, raw, nc, h, margin,
+                           tau, (float)DEM_MLP_KCAP, cell_vol, params, pslot);
+    }
+    hipLaunchKernelGGL(k_learned_decide, dim3(1), dim3(256), 0, s, blkmax, nblk, pslot, np, p, out);
+}
+
+void snapshot_write(const OwnerRec *rec, SnapRec *snap, int64_t No, hipStream_t s)
+{
+    if (No > 0) hipLaunchKernelGGL(k_snap_write, dim3(nblocks(No, 256)), dim3(256), 0, s, rec, snap, No);
+}
+
 void mlp_forward(const float *params, const float *X, float *Y, int64_t n, hipStream_t s)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_mlp_forward, dim3(nblocks(n, 256)), dim3(256), 0, s, params, X, Y, n);
 }
 
-void pred_min(const float *Y, int64_t n, uint32_t *out, hipStream_t s)
-{
-    launch_fill_u32(out, 1, 0x7f7fffffu, s);
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_pred_min, dim3(nblocks(n, 256)), dim3(256), 0, s, Y, n, out);
-}
 
 // Message of the last failed context-free call on this host thread
 // (dem_last_error(NULL) returns it).
