@@ -259,9 +259,24 @@ class Oracle:
 
     def run(self, st, n_steps, mode="every", k=10, lam=5, margin=None, judge=False, step=0,
             acs=None, cap=None):
-        """Runs the schedule of Sec. 2.1 (see orc_run).  Returns (state, acs, stats)."""
+        """Runs the schedule of Sec. 2.1 (see orc_run).  Returns (state, acs, stats).
+        Without `cap` the contact buffers hold four times the set the run
+        starts from, and a run that outgrows them is repeated from the same
+        inputs with twice the room."""
         margin = self.sys.margin if margin is None else margin
-        cap = cap or max(256, 16 * self.sys.n_spheres)
+        if cap is None:
+            n0 = self.detect(st, margin if mode != "every" else 0.0, step=step).size
+            n0 = max(n0, 0 if acs is None else acs[0].shape[0])
+            cap = 4 * n0 + 4096
+            st0 = {k: v.copy() for k, v in st.items()}
+            while True:
+                try:
+                    return self.run(st, n_steps, mode=mode, k=k, lam=lam, margin=margin, judge=judge, step=step,
+                                    acs=acs, cap=cap)
+                except RuntimeError:
+                    for key, v in st0.items():
+                        st[key][...] = v
+                    cap *= 2
         keys = np.zeros(cap, dtype=np.uint64)
         hist = np.zeros((cap, 4))
         n_acs = np.zeros(1, dtype=np.int64)

@@ -1815,7 +1815,31 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
         // single kernels are bracketed by marker events, which wait for the
         // previous work on the stream; an empty kernel bracketed the same way
         // measures the markers' own overhead
-        if (P.dyn_path != 1) {
+        const bool split = P.dyn_path != 1 && step_is_split(a, ctx->acs[ctx->cur]);
+        if (split) {
+            // the two kernels of a split step are timed one event pair
+            // each, every `timing`-th step, each pair followed by an empty
+            // kernel bracketed the same way (the markers' own overhead)
+            run_close(ctx, dyn);
+            SplitTiming tm{};
+            dem_ctx::TimedPair *t1 = stage_slot(ctx, 1), *t0 = t1 ? stage_slot(ctx, 0) : nullptr;
+            if (t1 && t0) tm = SplitTiming{t1->a, t1->b, t0->a, t0->b};
+            launch_step_fused(a, ctx->rec_alt, ctx->q_alt, ctx->acs[ctx->cur], ctx->cap, ctx->ctr, dyn,
+                              (t1 && t0) ? &tm : nullptr);
+            if (t1 && t0) {
+                if (auto *tn = stage_begin(ctx, 4, dyn)) {
+                    launch_noop(dyn, nullptr, nullptr);
+                    stage_end(tn, dyn);
+                }
+            } else {
+                if (t1) t1->kind = -1;
+                if (t0) t0->kind = -1;
+            }
+            ctx->rm_from = -1;
+            std::swap(ctx->rec, ctx->rec_alt);
+            std::swap(ctx->q, ctx->q_alt);
+            swap_hist(ctx->acs[ctx->cur]);
+        } else if (P.dyn_path != 1) {
             if (P.timing > 0 && n % P.timing == 0) ctx->run_due = true;
             if (!ctx->run && ctx->run_due) {
                 bool open = P.cd_mode == DEM_CD_EVERY || P.judge;

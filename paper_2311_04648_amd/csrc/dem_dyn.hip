@@ -1259,14 +1259,22 @@ StepKernel pick_remap(bool remap, bool wo)
                  : k_step_fused<SINGLES, FACETS, FIXED, STAGE, false, false>;
 }
 
-bool launch_step_fused(const DynArgs &a, OwnerRec *rec_out, double *q_out, const AcsBuf &cur, int64_t cap,
-                       DevCounters *ctr, hipStream_t s)
+bool step_is_split(const DynArgs &a, const AcsBuf &cur)
 {
-    if (a.split && a.has_clumps && !a.has_fixed && !a.wo_keys && cur.olist) {
+    return a.split && a.has_clumps && !a.has_fixed && !a.wo_keys && cur.olist;
+}
+
+bool launch_step_fused(const DynArgs &a, OwnerRec *rec_out, double *q_out, const AcsBuf &cur, int64_t cap,
+                       DevCounters *ctr, hipStream_t s, const SplitTiming *tm)
+{
+    if (step_is_split(a, cur)) {
         const bool r = a.rm_start != nullptr;
         const unsigned nb = nblocks(a.n_owners);
+        if (tm && tm->free0) hipEventRecord(tm->free0, s);
         hipLaunchKernelGGL(r ? k_step_free<true> : k_step_free<false>, dim3(nb), dim3(TPB), 0, s, a, rec_out, q_out,
                            (const uint8_t *)cur.oany, ctr);
+        if (tm && tm->free1) hipEventRecord(tm->free1, s);
+        if (tm && tm->list0) hipEventRecord(tm->list0, s);
         auto kl = a.n_tri > 0 ? (r ? k_step_listed<true, true> : k_step_listed<true, false>)
                               : (r ? k_step_listed<false, true> : k_step_listed<false, false>);
         const unsigned nl = std::min<unsigned>(nb, LISTED_BLOCKS);
@@ -1276,6 +1284,7 @@ bool launch_step_fused(const DynArgs &a, OwnerRec *rec_out, double *q_out, const
                            (const uint32_t *)cur.bidx, (const uint32_t *)cur.bsrc, (const uint8_t *)cur.oany,
                            (const float *)cur.hx, (const float *)cur.hy, (const float *)cur.hz,
                            (const float *)cur.hw, cur.hx2, cur.hy2, cur.hz2, cur.hw2, cap, ctr, nb);
+        if (tm && tm->list1) hipEventRecord(tm->list1, s);
         return true;
     }
     // runs with fixed families (mostly dormant waves) never stage

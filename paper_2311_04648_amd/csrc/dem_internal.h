@@ -346,8 +346,15 @@ void launch_fold_integrate(const DynArgs &a, const AcsBuf &cur, StepBufs &sb, De
 // launches nothing) for a combination no kernel variant covers: a work
 // order's binning on the first step of a newly adopted set, or in a run
 // with clumps or fixed families
+// Optional event pairs around the two kernels of a split step.
+struct SplitTiming {
+    hipEvent_t free0, free1, list0, list1;
+};
+// the step runs as the streaming kernel plus the kernel over the owners with
+// contacts (DynArgs::split, for a system and set that allow it)
+bool step_is_split(const DynArgs &a, const AcsBuf &cur);
 bool launch_step_fused(const DynArgs &a, OwnerRec *rec_out, double *q_out, const AcsBuf &cur, int64_t cap,
-                       DevCounters *ctr, hipStream_t s);
+                       DevCounters *ctr, hipStream_t s, const SplitTiming *tm = nullptr);
 // an empty one-wave kernel stamped with events (overhead of the stamps)
 void launch_noop(hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 // max |v|^2 of the last integration into ctr->maxv2[0]
