@@ -74,7 +74,7 @@ def lib():
         _lib.orc_count_missing.argtypes = [vp, vp, vp, vp, i64, vp, i64]
         _lib.orc_count_missing.restype = i64
         _lib.orc_remap.argtypes = [vp, vp, i64, vp, vp, i64]
-        _lib.orc_forces.argtypes = [vp, vp, vp, vp, vp, i64, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+        _lib.orc_forces.argtypes = [vp, vp, vp, vp, vp, i64, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         _lib.orc_integrate.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         _lib.orc_run.argtypes = [vp, vp, vp, vp, vp, vp, i64, C.c_int, i64, i64, d, C.c_int,
                                  vp, vp, vp, i64, vp]
@@ -226,10 +226,10 @@ class Oracle:
         hist = _hist4(hist, n)
         out = dict(Fc=np.zeros((n, 3)), TA=np.zeros((n, 3)), TB=np.zeros((n, 3)),
                    Fo=np.zeros((No, 3)), To=np.zeros((No, 3)), Fw=np.zeros((max(W, 1), 3)),
-                   touch=np.zeros(n, dtype=np.int32))
+                   touch=np.zeros(n, dtype=np.int32), scale=np.zeros(n))
         lib().orc_forces(self.ps, _p(st["X"]), _p(st["q"]), _p(st["V"]), _p(st["W"]), int(step),
                          _p(keys), n, _p(hist), _p(out["Fc"]), _p(out["TA"]), _p(out["TB"]),
-                         _p(out["Fo"]), _p(out["To"]), _p(out["Fw"]), _p(out["touch"]))
+                         _p(out["Fo"]), _p(out["To"]), _p(out["Fw"]), _p(out["touch"]), _p(out["scale"]))
         out["Fw"] = out["Fw"][:W]
         out["hist"] = hist
         return out

@@ -538,10 +538,60 @@ static void point_velocity(const double *V, const double *Wb, const double *q, c
  *   TcA   [3n] torque on owner A about its centre; TcB [3n] on owner B
  *   Fo,To [3No] per-owner sums; Fw [3W] force on each wall (may be NULL)
  *   touch [n]  1 if the pair is in contact (may be NULL)                 */
+/* How long a contact's first impact lasts, the phase in which rolling
+ * resistance does not act (the default model's walk-through, Sec. 4.2.1):
+ * the contact as a mass m on the linear spring k = (4/3) E* Re^(1/2) and
+ * dashpot c = -2 sqrt((5/3) m E*) beta Re^(1/4), Re = sqrt(R_bar) (the
+ * walk-through's simplified constants), rebounds after half a period of its
+ * damped oscillation, pi / w_d, w_d^2 = k/m - (c/(2m))^2.  An overdamped
+ * contact has no rebound: -1 (the resistance acts at once). */
+static double first_impact_duration(double Estar, double beta, double Rbar, double m)
+{
+    double Re = sqrt(Rbar);
+    double k = 4.0 / 3.0 * Estar * sqrt(Re);
+    double c = -2.0 * sqrt(5.0 / 3.0 * m * Estar) * beta * pow(Re, 0.25);
+    double half = c / (2.0 * m);
+    double wd2 = k / m - half * half;
+    return wd2 > 0.0 ? M_PI / sqrt(wd2) : -1.0;
+}
+
+/* Mindlin's tangential spring-dashpot for a contact (Sec. 4.1 Eq. (2)):
+ * stiffness k_t = 8 G* sqrt(R_bar delta), damping c_t = 2 sqrt(5/6) |beta|
+ * sqrt(m k_t), force f = -k_t xi - c_t u_t.  Where |f| exceeds the Coulomb
+ * limit the force is scaled to the limit and the stored displacement is
+ * moved to where the spring-dashpot gives that force (reading R3); a force
+ * below 1e-12 N is dropped.  Writes f, updates xi, returns |k_t xi| + |c_t| vsum
+ * (vsum: the magnitudes the relative velocity is summed from). */
+static double mindlin_tangential(double Gstar, double beta, double sqrtRd, double m, double limit,
+                                 const double *ut, double vsum, double *xi, double *f)
+{
+    double kt = 8.0 * Gstar * sqrtRd;
+    double ct = -2.0 * sqrt(5.0 / 6.0) * beta * sqrt(m * kt);
+    double spring[3], damper[3];
+    for (int k = 0; k < 3; ++k) {
+        spring[k] = -kt * xi[k];
+        damper[k] = -ct * ut[k];
+        f[k] = spring[k] + damper[k];
+    }
+    double terms = sqrt(dot(spring, spring)) + fabs(ct) * vsum;
+    double fmag = sqrt(dot(f, f));
+    if (!(fmag > 1e-12)) {
+        f[0] = f[1] = f[2] = 0.0;
+        return terms;
+    }
+    if (fmag > limit) {
+        for (int k = 0; k < 3; ++k) {
+            f[k] *= limit / fmag;
+            xi[k] = -(f[k] + ct * ut[k]) / kt;
+        }
+    }
+    return terms;
+}
+
 void orc_forces(const orc_sys *s, const double *X, const double *q, const double *V,
                 const double *Wb, int64_t step, const uint64_t *keys, int64_t n, double *hist,
                 double *Fc, double *TcA, double *TcB, double *Fo, double *To, double *Fw,
-                int32_t *touch)
+                int32_t *touch, double *scale)
 {
     int64_t Ns = s->n_spheres, No = s->n_owners;
     double *xs = malloc(sizeof(double) * 3 * (size_t)(Ns > 0 ? Ns : 1));
@@ -629,6 +679,7 @@ void orc_forces(const orc_sys *s, const double *X, const double *q, const double
             }
         }
         if (touch) touch[c] = touching;
+        if (scale) scale[c] = 0.0;
         if (!touching) {
             /* false positive of the margin: zero force, history released */
             for (int k = 0; k < 3; ++k) {
@@ -692,54 +743,39 @@ void orc_forces(const orc_sys *s, const double *X, const double *q, const double
         double gn = 2.0 * sqrt(5.0 / 6.0) * beta * sqrt(Sn * mbar);
         double F[3];
         for (int k = 0; k < 3; ++k) F[k] = (kn * delta + gn * pn) * nrm[k];
-        /* rolling resistance (Eq. (2) and the default-model walk-through): a
-         * torque-only force of magnitude C_rr |F_n| along the rolling part of
-         * the relative velocity at the contact point, applied once the
-         * contact has lasted longer than the damped Hertz collision time
-         * estimated with the walk-through's simplified constants */
+        /* magnitudes of what the force sums (for the rounding bound of a
+         * float evaluation): the normal spring, and the dampers acting on a
+         * relative velocity summed from parts of these magnitudes */
+        double vsum = 0.0;
+        {
+            double rA[3], rB[3];
+            for (int k = 0; k < 3; ++k) { rA[k] = vA[k] - V[3 * oA + k]; rB[k] = vB[k] - VBl[k]; }
+            vsum = sqrt(dot(V + 3 * oA, V + 3 * oA)) + sqrt(dot(rA, rA)) + sqrt(dot(VBl, VBl)) + sqrt(dot(rB, rB));
+        }
+        double mag = fabs(kn * delta) + fabs(gn) * vsum;
+        /* rolling resistance (Sec. 4.1 Eq. (2), Sec. 4.3.1): a torque-only
+         * force of magnitude C_rr |F| along the rolling part of the relative
+         * velocity at the contact point, once the contact has outlasted its
+         * first impact (reading R4) */
         double Fr[3] = {0.0, 0.0, 0.0};
-        if (crr > 0.0) {
-            int add = 1;
-            double Reff = sqrt(Rbar);
-            double kns = 4.0 / 3.0 * Estar * sqrt(Reff);
-            double gns = -2.0 * sqrt(5.0 / 3.0 * mbar * Estar) * beta * pow(Reff, 0.25);
-            double dc = gns / (2.0 * sqrt(kns * mbar));
-            if (dc < 1.0) {
-                double tcol = M_PI * sqrt(mbar / (kns * (1.0 - dc * dc)));
-                if (xi[3] <= tcol) add = 0;
-            }
-            if (add) {
-                double rvA[3], rvB[3], vr[3];
-                for (int k = 0; k < 3; ++k) { rvA[k] = vA[k] - V[3 * oA + k]; rvB[k] = vB[k] - VBl[k]; }
-                for (int k = 0; k < 3; ++k) vr[k] = rvB[k] - rvA[k];
-                double vrn = sqrt(dot(vr, vr));
-                if (vrn > 1e-12) {
-                    double fn = sqrt(dot(F, F));
-                    for (int k = 0; k < 3; ++k) Fr[k] = vr[k] / vrn * (crr * fn);
-                }
+        if (crr > 0.0 && xi[3] > first_impact_duration(Estar, beta, Rbar, mbar)) {
+            double wrA[3], wrB[3], vr[3];   /* rotational parts of vA and vB */
+            for (int k = 0; k < 3; ++k) { wrA[k] = vA[k] - V[3 * oA + k]; wrB[k] = vB[k] - VBl[k]; }
+            for (int k = 0; k < 3; ++k) vr[k] = wrB[k] - wrA[k];
+            double vrn = sqrt(dot(vr, vr));
+            if (vrn > 1e-12) {
+                double fmag = sqrt(dot(F, F));
+                for (int k = 0; k < 3; ++k) Fr[k] = (crr * fmag) * (vr[k] / vrn);
             }
         }
-        /* Mindlin tangential spring-damper with Coulomb capping */
+        /* Mindlin tangential force (Sec. 4.1 Eq. (2)) under the Coulomb
+         * limit (reading R3) */
         if (mu > 0.0) {
-            double kt = 8.0 * Gstar * sqrtRd;
-            double gt = -2.0 * sqrt(5.0 / 6.0) * beta * sqrt(mbar * kt);
             double ft[3];
-            for (int k = 0; k < 3; ++k) ft[k] = -kt * xi[k] - gt * ut[k];
-            double ftn = sqrt(dot(ft, ft));
-            if (ftn > 1e-12) {
-                double ftmax = sqrt(dot(F, F)) * mu;
-                if (ftn > ftmax) {
-                    double sc = ftmax / ftn;
-                    for (int k = 0; k < 3; ++k) {
-                        ft[k] = sc * ft[k];
-                        xi[k] = (ft[k] + gt * ut[k]) / (-kt);
-                    }
-                }
-            } else {
-                ft[0] = ft[1] = ft[2] = 0.0;
-            }
+            mag += mindlin_tangential(Gstar, beta, sqrtRd, mbar, mu * sqrt(dot(F, F)), ut, vsum, xi, ft);
             for (int k = 0; k < 3; ++k) F[k] += ft[k];
         }
+        if (scale) scale[c] = mag;
         double tA[3], tB[3], mF[3] = {-F[0], -F[1], -F[2]};
         double FA_t[3] = {F[0] + Fr[0], F[1] + Fr[1], F[2] + Fr[2]};
         double FB_t[3] = {-FA_t[0], -FA_t[1], -FA_t[2]};
@@ -903,7 +939,7 @@ int orc_run(const orc_sys *s, double *X, double *q, double *V, double *Wb, int64
         }
         if (cur.n > st->max_acs) st->max_acs = cur.n;
         st->sum_acs += cur.n;
-        orc_forces(s, X, q, V, Wb, n, cur.keys, cur.n, cur.hist, Fc, TA, TB, Fo, To, NULL, NULL);
+        orc_forces(s, X, q, V, Wb, n, cur.keys, cur.n, cur.hist, Fc, TA, TB, Fo, To, NULL, NULL, NULL);
         orc_integrate(s, X, q, V, Wb, Fo, To);
         *step = n + 1;
     }

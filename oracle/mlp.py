@@ -6,7 +6,7 @@ cell, how many more steps a freshly detected active set stays complete.
 This module is the plain definition of what the GPU kernels compute:
 
 * ``features``: the six per-cell features of a state relative to the state
-  at the previous detection (definitions below, cells of 4 x 4 x 4 bins);
+  at the previous detection (definitions below; cells of edge 8 (r_max + m));
 * ``labels``: the first step at which a true contact touching a cell is
   missing from a set detected with the margin;
 * ``forward`` / ``loss_and_grad`` / ``adam_step``: the 6-32-32-1 tanh MLP,
@@ -97,18 +97,22 @@ def adam_step(p, g, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
 # ---------------------------------------------------------------------------
 
 def feature_grid(sysm):
-    """Feature cells: cubes of 4 x 4 x 4 detection bins of edge
-    b = 2 (r_max + m) (1 + 1e-6) + 1e-12 over the domain padded by one bin
-    and one extra bin per side."""
-    b = 2.0 * (float(np.max(sysm.sph_rad)) + sysm.margin) * (1.0 + 1e-6) + 1e-12
-    lo = np.asarray(sysm.domain_lo, dtype=np.float64) - b
-    hi = np.asarray(sysm.domain_hi, dtype=np.float64) + b
-    n = np.maximum(np.ceil((hi - lo) / b).astype(np.int64), 1) + 2
-    nf = (n + 3) // 4
-    return lo, 4.0 * b, nf
+    """Feature cells: cubes of edge E = 8 (r_max + m) -- four times the
+    smallest edge a detection bin may have, 2 (r_max + m) -- tiling the
+    domain box from its low corner, ceil(extent / E) cells per axis (at
+    least one).  Returns (low corner, E, cells per axis)."""
+    E = 8.0 * (float(np.max(sysm.sph_rad)) + sysm.margin)
+    if not E > 0.0:
+        E = 1.0
+    lo = np.asarray(sysm.domain_lo, dtype=np.float64)
+    hi = np.asarray(sysm.domain_hi, dtype=np.float64)
+    n = np.maximum(np.ceil((hi - lo) / E).astype(np.int64), 1)
+    return lo, E, n
 
 
 def owner_cells(sysm, X):
+    """Cell id of each owner centre, (cz ny + cy) nx + cx, a centre outside
+    the box taken to the nearest cell."""
     lo, edge, nf = feature_grid(sysm)
     c = np.floor((np.asarray(X) - lo) * (1.0 / edge))
     c = np.clip(c, 0, nf - 1).astype(np.int64)

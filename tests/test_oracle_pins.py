@@ -460,3 +460,45 @@ def test_history_survives_active_set_updates():
     assert np.abs(acs_a[1]).max() > 0
     np.testing.assert_array_equal(acs_a[0], acs_b[0])
     np.testing.assert_array_equal(acs_a[1], acs_b[1])
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_count_missing_equals_brute_set_difference(seed):
+    """The judge's count (Sec. 2.1: every pair that touches must be in the
+    set in use) equals the size of a set difference taken directly: the
+    touching pairs of a brute-force O(N^2) enumeration at margin 0, minus
+    the set in use, computed with numpy.  The set in use is one detected
+    with a margin on an earlier state, so some pairs that touch now are
+    absent from it and some pairs in it no longer touch."""
+    s = W.small_clumps(seed, n=150, vel=1.5, spacing=0.0088)
+    o = oracle.Oracle(s)
+    st0 = o.state()
+    stale = o.detect(st0, 0.00005)
+    st, *_ = o.run(o.state(), 400, mode="every")
+    true = o.detect(st, 0.0, brute=True)
+    expect = np.setdiff1d(true, stale).size
+    assert expect > 0, "the case must have missing pairs"
+    assert np.setdiff1d(stale, true).size > 0
+    assert o.count_missing(st, stale) == expect
+    # a set holding every true pair misses nothing
+    assert o.count_missing(st, np.union1d(true, stale)) == 0
+
+
+def test_detect_row_equals_filtered_brute_force():
+    """The one-row detection used for sampled checks of very large inputs
+    equals the rows of the brute-force enumeration of the whole system."""
+    s = W.small_clumps(4, n=120, with_cylinder=True, spacing=0.0085)
+    o = oracle.Oracle(s)
+    st = o.state()
+    m = 0.0004
+    brute = o.detect(st, m, brute=True)
+    owners = (brute >> np.uint64(32)).astype(np.int64)
+    rng = np.random.default_rng(0)
+    rows = np.unique(np.concatenate([rng.integers(0, s.n_spheres, 40), owners[:: max(1, owners.size // 20)]]))
+    got = o.detect_rows(st, m, rows)
+    nonempty = 0
+    for i, g in zip(rows, got):
+        exp = brute[owners == i]
+        np.testing.assert_array_equal(g, exp)
+        nonempty += exp.size > 0
+    assert nonempty >= 10
