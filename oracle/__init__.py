@@ -15,14 +15,22 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "dem_oracle.c")
-LIB = os.path.join(HERE, "_dem_oracle.so")
+# DEM_ORACLE_SANITIZE=1 selects a build with AddressSanitizer and
+# UndefinedBehaviorSanitizer (any finding aborts); the process must then be
+# started with the AddressSanitizer runtime preloaded
+SANITIZE = os.environ.get("DEM_ORACLE_SANITIZE", "") == "1"
+LIB = os.path.join(HERE, "_dem_oracle_san.so" if SANITIZE else "_dem_oracle.so")
 
 
 def build(force=False):
     """Compile the C oracle with strict IEEE double arithmetic."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math",
+        flags = ["-O2"]
+        if SANITIZE:
+            flags = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                     "-fno-sanitize-recover=all"]
+        subprocess.check_call(["gcc", *flags, "-std=gnu11", "-ffp-contract=off", "-fno-fast-math",
                                "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB

@@ -83,6 +83,7 @@ struct dem_ctx {
     std::vector<double> mesh_origin, mesh_vel, mesh_omega;
     std::vector<int32_t> mesh_mat;
     double vmesh = 0.0;          // fastest point of any mesh (m/s)
+    double vwall = 0.0;          // fastest point of any wall (m/s)
     TriDev *d_tri = nullptr;
     // mesh poses of the dynamics: a device ring of POSE_RING steps, filled
     // POSE_CHUNK steps at a time from pinned staging (two halves, each reused
@@ -813,6 +814,10 @@ dem_status dem_create(const dem_params *params, const dem_materials *mats, const
         d.mat = walls->mat[w];
         if (d.mat < 0 || d.mat >= ctx->nmat) return fail("wall material out of range");
         ctx->walls[w] = d;
+        // how fast the wall's surface moves: walls only translate (omega sets
+        // the surface velocity of a cylinder, not its shape's motion)
+        ctx->vwall = std::max(ctx->vwall, std::sqrt(d.vel[0] * d.vel[0] + d.vel[1] * d.vel[1] +
+                                                    d.vel[2] * d.vel[2]));
     }
     // bins: edge >= 2 (r_max + m) with a small safety factor
     double b = 2.0 * (ctx->rmax + P.margin) * (1.0 + 1e-6) + 1e-12;
@@ -837,20 +842,27 @@ dem_status dem_create(const dem_params *params, const dem_materials *mats, const
     int bits = 1;
     while (bits < 32 && (1ull << bits) <= nb) ++bits;   // keys 0 .. nb (nb: a sphere left out of the bins)
     ctx->sort_bits = bits;
-    // feature cells for the learned interval: cubes of 4 bins
-    ctx->fgrid = ctx->grid;
+    // feature cells of the learned interval: cubes of edge E = 8 (r_max + m)
+    // (four times the smallest bin edge) tiling the domain box from its low
+    // corner, n_k = ceil(extent_k / E) per axis; a centre outside the box
+    // belongs to the nearest cell
     {
+        double E = 8.0 * (ctx->rmax + P.margin);
+        if (!(E > 0.0)) E = 1.0;
         uint64_t fn = 1;
-        int fd[3] = {dims[0], dims[1], dims[2]};
+        int fd[3];
         for (int k = 0; k < 3; ++k) {
-            fd[k] = (dims[k] + 3) / 4;
+            const double c = std::ceil((P.domain_hi[k] - P.domain_lo[k]) / E);
+            fd[k] = (int)std::min(std::max(c, 1.0), 1.0e6);
             fn *= (uint64_t)fd[k];
+            ctx->fgrid.lo[k] = P.domain_lo[k];
         }
+        if (fn >= 0xfffffff0ull) return fail("domain too large for the feature cells");
         ctx->fgrid.nx = fd[0];
         ctx->fgrid.ny = fd[1];
         ctx->fgrid.nz = fd[2];
         ctx->fgrid.nbins = (uint32_t)fn;
-        ctx->fgrid.inv_b = 1.0 / (4.0 * b);
+        ctx->fgrid.inv_b = 1.0 / E;
     }
     // voxel origin: a multiple of the voxel edge below the grid
     for (int k = 0; k < 3; ++k) {
@@ -1530,7 +1542,8 @@ static int64_t issue_work_order(dem_ctx *ctx, hipStream_t dyn, hipStream_t kin, 
         const double g = std::sqrt(P.gravity[0] * P.gravity[0] + P.gravity[1] * P.gravity[1] +
                                    P.gravity[2] * P.gravity[2]);
         launch_reduce_max(dyn_args(ctx, n), ctx->ctr, dyn);
-        launch_adaptive_margin(ctx->ctr, 2.0 * (double)lam * P.dt, g, P.margin, ctx->vmesh, dyn);
+        launch_adaptive_margin(ctx->ctr, 2.0 * (double)lam * P.dt, g, P.margin, std::max(ctx->vmesh, ctx->vwall),
+                               dyn);
         const int slot = (ctx->cyc_pos + 1) % 4;
         hipMemcpyAsync(&ctx->h_capped[slot], &ctx->ctr->capped, sizeof(uint32_t), hipMemcpyDeviceToHost, dyn);
         cy = &ctx->cyc[slot];
@@ -1991,7 +2004,7 @@ static void run_features(dem_ctx *ctx, hipStream_t s, float *out, uint32_t *cell
 // (features against the snapshot, which the state then replaces; the
 // network; the interval, with the analytic bound as its fallback), its
 // copy to pinned host memory and an event after it.
-static void enqueue_decision(dem_ctx *ctx, hipStream_t s)
+static void enqueue_decision(dem_ctx *ctx, hipStream_t s, int ahead)
 {
     const dem_params &P = ctx->P;
     LearnedArgs p;
@@ -1999,12 +2012,13 @@ static void enqueue_decision(dem_ctx *ctx, hipStream_t s)
     p.margin = P.margin;
     p.dt = P.dt;
     p.safety = P.mlp_safety > 0.0 ? P.mlp_safety : 1.0;
-    p.vmesh = ctx->vmesh;
+    p.vgeom = std::max(ctx->vmesh, ctx->vwall);
     p.lam = P.cd_latency;
     p.kmax = P.cd_interval_max;
     p.use_model = ctx->mlp_set ? 1 : 0;
-    p.meshes = ctx->NM > 0 ? 1 : 0;
+    p.moving = p.vgeom > 0.0 ? 1 : 0;
     p.speed_valid = ctx->step > 0 ? 1 : 0;
+    p.ahead = ahead;
     const float tau = (float)(ctx->step - ctx->snap_step);
     const float margin = (float)(P.margin > 0.0 ? P.margin : 1e-6);
     const DynArgs da = dyn_args(ctx, ctx->step);
@@ -2021,7 +2035,7 @@ static void enqueue_decision(dem_ctx *ctx, hipStream_t s)
 // enqueued a whole step earlier, so the dynamics stream does not drain).
 static void prepare_decision(dem_ctx *ctx, hipStream_t s)
 {
-    enqueue_decision(ctx, s);
+    enqueue_decision(ctx, s, 1);
     ctx->prep_valid = true;
     ctx->prep_step = ctx->step;
 }
@@ -2035,7 +2049,7 @@ static void prepare_decision(dem_ctx *ctx, hipStream_t s)
 // enqueues it now and waits for it.
 int64_t learned_interval(dem_ctx *ctx, hipStream_t s)
 {
-    if (!(ctx->prep_valid && ctx->prep_step + 1 == ctx->step)) enqueue_decision(ctx, s);
+    if (!(ctx->prep_valid && ctx->prep_step + 1 == ctx->step)) enqueue_decision(ctx, s, 0);
     ctx->prep_valid = false;
     hipEventSynchronize(ctx->ev_kdec);
     const int64_t k = ctx->h_kdec[0];

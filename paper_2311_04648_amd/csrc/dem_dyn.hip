@@ -144,6 +144,44 @@ struct ContactOut {
     bool touching;
 };
 
+// Duration of a contact's first impact, during which rolling resistance is
+// held back (the default model's walk-through, Sec. 4.2.1): the contact is
+// taken as the linear spring-dashpot m x'' + c x' + k x = 0 with the
+// walk-through's simplified constants k = (4/3) E* R_e^(1/2) and
+// c = -2 sqrt((5/3) m E*) beta R_e^(1/4), R_e = sqrt(R_bar), and an impact
+// lasts half a period of its damped oscillation, pi / w_d with
+// w_d^2 = k / m - (c / 2m)^2.  An overdamped contact (w_d^2 <= 0) has no such
+// phase: -1.
+__device__ __forceinline__ float impact_time(float Estar, float beta, float Rbar, float m)
+{
+    const float Re = sqrtf(Rbar);
+    const float k = (4.0f / 3.0f) * Estar * sqrtf(Re);
+    const float c = -2.0f * sqrtf((5.0f / 3.0f) * m * Estar) * beta * sqrtf(sqrtf(Re));
+    const float zeta = c / (2.0f * sqrtf(k * m));   // damping ratio (>= 0: beta <= 0)
+    if (!(zeta < 1.0f)) return -1.0f;
+    return 3.14159265358979f * sqrtf(m / (k * (1.0f - zeta * zeta)));
+}
+
+// Mindlin tangential spring-dashpot with the Coulomb limit (Sec. 4.1
+// Eq. (2); the walk-through's form of the limit, reading R3): the trial
+// force -(k_t xi + c_t u_t); above mu |F| it is scaled down to mu |F| and the
+// displacement xi is set back to the value that force implies,
+// xi = -(f_t + c_t u_t) / k_t; a trial force below 1e-12 N is zero.
+__device__ __forceinline__ float3 tangential_force(const MatPair &mq, float sqrtRd, float m, float3 F, float3 ut,
+                                                   float3 &xi)
+{
+    const float kt = 8.0f * mq.Gstar * sqrtRd;
+    const float ct = -1.8257418583505538f * mq.beta * sqrtf(m * kt);   // 2 sqrt(5/6) |beta| sqrt(m k_t)
+    const float3 ft = (-kt) * xi - ct * ut;
+    const float mag = sqrtf(dot3(ft, ft));
+    if (!(mag > 1e-12f)) return f3(0.f, 0.f, 0.f);
+    const float limit = mq.mu * sqrtf(dot3(F, F));
+    if (mag <= limit) return ft;
+    const float3 fl = (limit / mag) * ft;
+    xi = (-1.0f / kt) * (fl + ct * ut);
+    return fl;
+}
+
 // FACETS: the set may hold sphere-facet contacts (systems with meshes; the
 // FP64 closest-point code raises the register demand, so systems without
 // meshes use the variant without it).
@@ -296,46 +334,20 @@ __device__ __forceinline__ void contact_eval(const DynArgs &a, const SphRec &sA,
     const float c56 = 1.8257418583505538f;   // 2 sqrt(5/6)
     const float gn = c56 * mq.beta * sqrtf(Sn * mbar);
     float3 F = (kn * df + gn * pn) * n;
-    // rolling resistance: torque-only force C_rr |F_n| along the rolling
-    // part of the relative velocity, once the contact is older than the
-    // damped collision time of the simplified constants
+    // rolling resistance (Sec. 4.1 Eq. (2), Sec. 4.3.1): a torque-only force
+    // of magnitude C_rr |F| along the rolling part of the relative velocity,
+    // held back during the contact's first impact
     float3 Fr = f3(0.f, 0.f, 0.f);
     float age = 0.f;
     if (a.rolling) {
         age = hold.w + hf;
-        if (mq.crr > 0.0f) {
-            bool add = true;
-            const float Reff = sqrtf(Rbar);
-            const float kns = (4.0f / 3.0f) * mq.Estar * sqrtf(Reff);
-            const float gns = -2.0f * sqrtf((5.0f / 3.0f) * mbar * mq.Estar) * mq.beta * sqrtf(sqrtf(Reff));
-            const float dcf = gns / (2.0f * sqrtf(kns * mbar));
-            if (dcf < 1.0f) {
-                const float tcol = 3.14159265358979f * sqrtf(mbar / (kns * (1.0f - dcf * dcf)));
-                if (age <= tcol) add = false;
-            }
-            if (add) {
-                const float3 vr = rotB - rotA;
-                const float vrn = sqrtf(dot3(vr, vr));
-                if (vrn > 1e-12f) Fr = ((mq.crr * sqrtf(dot3(F, F))) / vrn) * vr;
-            }
+        if (mq.crr > 0.0f && age > impact_time(mq.Estar, mq.beta, Rbar, mbar)) {
+            const float3 vr = rotB - rotA;
+            const float vrn = sqrtf(dot3(vr, vr));
+            if (vrn > 1e-12f) Fr = ((mq.crr * sqrtf(dot3(F, F))) / vrn) * vr;
         }
     }
-    if (mq.mu > 0.0f) {
-        const float kt = 8.0f * mq.Gstar * sqrtRd;
-        const float gt = -c56 * mq.beta * sqrtf(mbar * kt);
-        float3 ft = (-kt) * xi - gt * ut;
-        const float ftn = sqrtf(dot3(ft, ft));
-        if (ftn > 1e-12f) {
-            const float ftmax = sqrtf(dot3(F, F)) * mq.mu;
-            if (ftn > ftmax) {
-                ft = (ftmax / ftn) * ft;
-                xi = (-1.0f / kt) * (ft + gt * ut);
-            }
-        } else {
-            ft = f3(0.f, 0.f, 0.f);
-        }
-        F = F + ft;
-    }
+    if (mq.mu > 0.0f) F = F + tangential_force(mq, sqrtRd, mbar, F, ut, xi);
     out.F = F;
     out.Ft = F + Fr;
     out.armA = armA;

@@ -372,12 +372,13 @@ struct LearnedArgs {
     double margin;
     double dt;
     double safety;      // factor on the predicted horizon
-    double vmesh;       // fastest point of any mesh
+    double vgeom;       // fastest point of any wall or mesh
     int64_t lam;        // adoption latency (steps)
     int64_t kmax;       // largest interval
     int32_t use_model;  // a network is installed: predict; else the analytic bound
-    int32_t meshes;     // the system has meshes (their analytic bound caps the prediction)
+    int32_t moving;     // some wall or mesh moves (its analytic bound caps the prediction)
     int32_t speed_valid;// the top speed of the last integration is meaningful (a step was taken)
+    int32_t ahead;      // steps between the state the features see and the work order (0 or 1)
 };
 
 // Learned interval (dem_mlp.hip): the features, the network and the

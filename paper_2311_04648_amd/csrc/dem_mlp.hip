@@ -1,6 +1,7 @@
 // Learned contact-detection interval for gfx950.
 //
-// Features: per feature cell (a cube of 4 x 4 x 4 detection bins), from the
+// Features: per feature cell (a cube of edge 8 (r_max + m) tiling the domain
+// box from its low corner: four times the smallest bin edge), from the
 // owners whose centre lies in it, relative to the state at the previous
 // detection (the snapshot):
 //   f1 log1p(|v_max - v_min| h K / m)     spread of velocities (relative speed)
@@ -493,12 +494,13 @@ __device__ inline int64_t analytic_steps(const LearnedArgs &p, double v)
 }
 
 // The interval of the next work order, decided on the device: from the top
-// speed of the last integration (blkmax, nblk slots) the analytic bound;
-// with a model, the minimum over cells of the predicted remaining steps
-// (pslot, npslot slots), scaled by the safety factor, less the adoption
-// latency and one step (the analytic bound of the meshes caps it; the
-// analytic bound replaces it when no cell is occupied or the minimum is not
-// finite).  out[0] = the interval, out[1] = the analytic bound, out[2] the
+// speed of the last integration (blkmax, nblk slots) and the fastest point
+// of any wall or mesh, the analytic bound (every geometry moves less than
+// the margin); with a model, the minimum over cells of the predicted
+// remaining steps (pslot, npslot slots), scaled by the safety factor, less
+// the adoption latency and one step (the features see only the spheres:
+// the analytic bound of the moving walls and meshes caps it; the analytic
+// bound replaces it when no cell is occupied or the minimum is not finite).  out[0] = the interval, out[1] = the analytic bound, out[2] the
 // bits of R (float).
 __global__ void __launch_bounds__(256) k_learned_decide(const float *blkmax, int64_t nblk, const float *pslot,
                                                        int64_t npslot, LearnedArgs p, int64_t *out)
@@ -537,13 +539,18 @@ __global__ void __launch_bounds__(256) k_learned_decide(const float *blkmax, int
     v2 = fmaxf(fmaxf(wv2[0], wv2[1]), fmaxf(wv2[2], wv2[3]));
     R = fminf(fminf(wr[0], wr[1]), fminf(wr[2], wr[3]));
     const double vmax = p.speed_valid && v2 == v2 ? sqrt((double)v2) : 0.0;
-    const int64_t k_an = analytic_steps(p, fmax(vmax, p.vmesh));
+    const int64_t k_an = analytic_steps(p, fmax(vmax, p.vgeom));
     int64_t k = k_an;
     if (p.use_model && R >= 0.0f && R < 1.0e38f) {
-        const double kl = floor(p.safety * (double)R) - (double)p.lam - 1.0;
+        // R counts from the state the features saw, one step before the
+        // work order (p.ahead = 1) or at it (0); the set is detected at the
+        // order, adopted lambda steps later and used until the next set is
+        // adopted k + lambda steps after the order, which must come before
+        // the predicted first miss
+        const double kl = floor(p.safety * (double)R) - (double)p.lam - 1.0 - (double)p.ahead;
         k = kl < 1.0 ? 1 : (int64_t)fmin(kl, 1e9);
-        if (p.meshes) {
-            const int64_t km = analytic_steps(p, p.vmesh);
+        if (p.moving) {
+            const int64_t km = analytic_steps(p, p.vgeom);
             k = k < km ? k : km;
         }
         k = k < p.kmax ? k : p.kmax;

@@ -6,7 +6,9 @@ outputs the FP64 oracle computes one by one:
   bit-exact;
 * forces of every contact of the sampled spheres within 1e-5;
 * one integration step of the sampled owners against the oracle given all of
-  their contacts.
+  their contacts;
+
+each configuration run long enough that its bed holds touching contacts.
 """
 import os
 
@@ -30,16 +32,21 @@ def dem():
 
 
 def _full(name):
+    # pre-steps: configs 1, 3 and 4 start with almost every sphere clear of
+    # the others and of the floor (smallest floor gaps 0.056 and 0.065 mm in
+    # configs 1 and 3), so they fall until the bottom layer lands (a 0.3 mm
+    # gap closes in about 1560 steps) and the layer above reaches it
     if name == "config1":
-        return W.config1(seed=0), 200
+        return W.config1(seed=0), 4000
     if name == "config2":
         return W.config2(seed=0), 400
     if name == "config3":
-        return W.config3(seed=7), 200
+        return W.config3(seed=7), 3000
     if name == "config4":
-        return W.config4(seed=0), 100
+        return W.config4(seed=0), 2000
     if name == "mixer":
-        return W.mixer(seed=0), 400
+        # (dt 5e-7 s: the blade tips sweep 4.5 mm into the bed in 3000 steps)
+        return W.mixer(seed=0), 3000
     raise ValueError(name)
 
 
@@ -48,11 +55,20 @@ def _sample_spheres(keys, Ns, rng, n):
     return np.sort(rng.choice(i, size=min(n, i.size), replace=False))
 
 
+def _world_w(st):
+    from scipy.spatial.transform import Rotation
+    R = Rotation.from_quat(st["q"][:, [1, 2, 3, 0]]).as_matrix()
+    return np.einsum("nij,nj->ni", R, st["W"])
+
+
 @pytest.mark.parametrize("name", ["config1", "config2", "config3", "config4", "mixer"])
 def test_full_size_sampled_parity(dem, name):
+    """Sampled rows bit-exact, every contact of the sampled owners within
+    1e-5 (at least 20 of them touching), and one step of the sampled owners
+    against the oracle's integration under those forces."""
     import torch
     s, presteps = _full(name)
-    print(f"{name}: {s.n_spheres} spheres, {s.n_owners} owners", flush=True)
+    print(f"{name}: {s.n_spheres} spheres, {s.n_owners} owners, {presteps} pre-steps", flush=True)
     ctx = dem.DemContext(s, mode="fixed", k=10, lam=5, capacity=(4 if name == "config4" else 8) * s.n_spheres)
     ctx.set_state()
     dyn, kin = torch.cuda.Stream(), torch.cuda.Stream()
@@ -61,59 +77,153 @@ def test_full_size_sampled_parity(dem, name):
     keys, hist = ctx.get_contacts()
     g = ctx.get_state()
     st = {"X": g["X"], "q": g["q"], "V": g["V"].astype(np.float64), "W": g["W"].astype(np.float64)}
+    before = {k: v.copy() for k, v in st.items()}
+    ctx.forces()
+    Fo, To, Fc = ctx.get_forces(keys.size)
     o = oracle.Oracle(s)
     rng = np.random.default_rng(1)
     nrow = 24 if name == "config4" else 60
+    ki = (keys >> np.uint64(32)).astype(np.int64)
+    kj = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
     sample = _sample_spheres(keys, s.n_spheres, rng, nrow)
+    # spheres with contacts that carry a force (which rows to check is
+    # chosen from the GPU's output; every value checked is the oracle's)
+    pressed = np.unique(ki[np.linalg.norm(Fc, axis=1) > 0])
+    print(f"{name}: {keys.size} pairs in the set, {pressed.size} spheres pressed", flush=True)
+    sample = np.unique(np.r_[sample, rng.choice(pressed, size=min(40, pressed.size), replace=False)])
     # also a few spheres with no contact
     sample = np.unique(np.r_[sample, rng.choice(s.n_spheres, 8, replace=False)])
     if s.n_tri > 0:
         # and spheres touching the impeller's facets
-        kj0 = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
-        fi = np.unique((keys >> np.uint64(32)).astype(np.int64)[kj0 >= s.n_spheres + s.n_walls])
+        fi = np.unique(ki[kj >= s.n_spheres + s.n_walls])
         print(f"{name}: {fi.size} spheres with facet contacts", flush=True)
         assert fi.size > 0
         sample = np.unique(np.r_[sample, rng.choice(fi, size=min(24, fi.size), replace=False)])
     rows = o.detect_rows(st, s.margin, sample, step=g["step"])
-    ki = (keys >> np.uint64(32)).astype(np.int64)
     for i, row in zip(sample, rows):
         np.testing.assert_array_equal(keys[ki == i], row)
     # forces of every contact of the sampled owners (A side and B side)
     owners = np.unique(s.sph_owner[sample])
-    kj = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
     own_of = s.sph_owner
     mine = np.isin(own_of[ki], owners) | ((kj < s.n_spheres) & np.isin(own_of[np.minimum(kj, s.n_spheres - 1)], owners))
     sel = np.nonzero(mine)[0]
-    ctx.forces()
-    Fo, To, Fc = ctx.get_forces(keys.size)
     ref = o.forces(st, keys[sel], hist[sel].astype(np.float64), step=g["step"])
     Fn = np.linalg.norm(ref["Fc"], axis=1)
     touch = ref["touch"] > 0
-    if touch.any():
-        floor = 1e-3 * np.median(Fn[touch])
-        rel = np.linalg.norm(Fc[sel] - ref["Fc"], axis=1) / np.maximum(Fn, floor)
-        print(f"{name}: sampled {sample.size} spheres, {sel.size} contacts ({touch.sum()} touching), "
-              f"max rel F err {rel.max():.2e}", flush=True)
-        assert rel.max() <= 1e-5
+    print(f"{name}: sampled {sample.size} spheres, {sel.size} contacts ({touch.sum()} touching)", flush=True)
+    assert touch.sum() >= 20
+    floor = 1e-3 * np.median(Fn[touch])
+    # 1e-5 of the force, or where the force is a small difference of large
+    # terms (a contact separating: spring and damper nearly cancel), the
+    # float rounding of those terms: 2^-21 of their summed magnitude
+    tol = 1e-5 * np.maximum(Fn, floor) + 2.0 ** -21 * ref["scale"]
+    err = np.linalg.norm(Fc[sel] - ref["Fc"], axis=1)
+    print(f"{name}: max err / tol {(err / tol).max():.2e}, max rel F err "
+          f"{(err / np.maximum(Fn, floor)).max():.2e}", flush=True)
+    for c in np.argsort(err / tol)[-3:]:
+        print(f"  contact {keys[sel][c]:#x} |F| {Fn[c]:.4e} terms {ref['scale'][c]:.3e} err {err[c]:.3e} "
+              f"tol {tol[c]:.3e}", flush=True)
+    assert np.all(err <= tol)
+    # per owner: the summed magnitudes of its contact forces and the summed
+    # per-contact error allowances (floors for its sums and increments)
     L1 = np.zeros(s.n_owners)
+    T1 = np.zeros(s.n_owners)
+    tc = 2.0 ** -21 * ref["scale"]
     np.add.at(L1, own_of[ki[sel]], Fn)
+    np.add.at(T1, own_of[ki[sel]], tc)
     sph = kj[sel] < s.n_spheres
     np.add.at(L1, own_of[kj[sel][sph]], Fn[sph])
+    np.add.at(T1, own_of[kj[sel][sph]], tc[sph])
+    L1 = L1 + 1e5 * T1
     ferr = np.linalg.norm(Fo[owners] - ref["Fo"][owners], axis=1)
     assert np.all(ferr <= 1e-5 * np.maximum(L1[owners], 1e-12) + 1e-12 * s.own_mass[owners])
+    # one step from the same state and set: the sampled owners' increments
+    # against the oracle's integration under their forces
+    ctx.set_state(X=g["X"], q=g["q"], V=g["V"], W=g["W"], step=g["step"])
+    ctx.set_contacts(keys, hist)
+    ctx.step(1)
+    g1 = ctx.get_state()
+    st1 = o.integrate({k: v.copy() for k, v in before.items()}, ref["Fo"], ref["To"])
+    h = s.dt
+    m = s.own_mass[owners]
+    dv_g = g1["V"][owners].astype(np.float64) - before["V"][owners]
+    dv_o = st1["V"][owners] - before["V"][owners]
+    tol_v = 1e-5 * np.linalg.norm(dv_o, axis=1) + np.spacing(np.abs(g1["V"][owners]).max(1).astype(np.float32)) \
+        + 1e-5 * h * L1[owners] / m
+    assert np.all(np.linalg.norm(dv_g - dv_o, axis=1) <= tol_v)
+    dx_g = g1["X"][owners] - before["X"][owners]
+    dx_o = st1["X"][owners] - before["X"][owners]
+    tol_x = 1e-5 * np.linalg.norm(dx_o, axis=1) + h * np.linalg.norm(dv_g - dv_o, axis=1) + 2.0 ** -37
+    assert np.all(np.linalg.norm(dx_g - dx_o, axis=1) <= tol_x)
+    clump = s.own_tmpl[owners] >= 0
+    w0 = _world_w(before)[owners]
+    wg = np.asarray(g1["W"][owners], dtype=np.float64)
+    if clump.any():
+        from scipy.spatial.transform import Rotation
+        R = Rotation.from_quat(g1["q"][owners][clump][:, [1, 2, 3, 0]]).as_matrix()
+        wg[clump] = np.einsum("nij,nj->ni", R, wg[clump])
+    wo = _world_w(st1)[owners]
+    Iinv = 1.0 / s.own_moi[owners].min(1)
+    tol_w = 1e-5 * np.linalg.norm(wo - w0, axis=1) + 4 * np.spacing(np.abs(wg).max(1).astype(np.float32)) \
+        + 1e-5 * h * L1[owners] * 0.01 * Iinv
+    assert np.all(np.linalg.norm((wg - w0) - (wo - w0), axis=1) <= tol_w)
+    if clump.any():
+        dq_g = g1["q"][owners][clump] - before["q"][owners][clump]
+        dq_o = st1["q"][owners][clump] - before["q"][owners][clump]
+        tol_q = 1e-5 * np.linalg.norm(dq_o, axis=1) + h * np.linalg.norm((wg - wo)[clump], axis=1) + 1e-15
+        assert np.all(np.linalg.norm(dq_g - dq_o, axis=1) <= tol_q)
 
 
-def test_config1_bench_configuration_deterministic_and_exact(dem):
-    """The bench's headline run (1 M spheres, k = 10 on a second stream) is
-    deterministic and equals every-step detection bit for bit."""
+def test_config1_fixed_equals_every_step_past_first_contact(dem):
+    """The 1 M-sphere settling bed (k = 10 on a second stream) is
+    deterministic and equals every-step detection bit for bit, over 4000
+    steps, by which the bottom layer has landed (contacts exist)."""
     import torch
     s = W.config1(seed=0)
     outs = []
     for mode in ("fixed", "every"):
         c = dem.DemContext(s, mode=mode, k=10, lam=5, capacity=8 * s.n_spheres)
         c.set_state()
-        c.step(300, dyn=torch.cuda.Stream(), kin=torch.cuda.Stream())
+        c.step(4000, dyn=torch.cuda.Stream(), kin=torch.cuda.Stream())
         outs.append(c.get_state())
+        if mode == "every":
+            keys, _ = c.get_contacts()
+            print(f"{keys.size} true contacts at the end", flush=True)
+            assert keys.size > 100
         c.close()
     for k in ("X", "V", "W"):
+        np.testing.assert_array_equal(outs[0][k], outs[1][k])
+
+
+MODEL = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2311_04648_amd",
+                     "mlp_interval.json")
+
+
+@pytest.mark.skipif(not os.path.exists(MODEL), reason="no trained interval model in the tree")
+def test_config4_bench_window_learned_equals_every_step(dem):
+    """The bench's headline run -- the 60 M-sphere bed, learned interval on
+    a second stream, 5 + 20 steps -- misses nothing (judged) and ends in the
+    every-step state bit for bit; the bed holds touching contacts (about a
+    hundred: the cylinder resting on it)."""
+    import json
+    import torch
+    s = W.config4(seed=0)
+    md = json.load(open(MODEL))
+    outs = []
+    for mode in ("learned", "every"):
+        c = dem.DemContext(s, mode=mode, k=10, lam=5, judge=mode == "learned", capacity=4 * s.n_spheres,
+                           k_max=1024, mlp_safety=md.get("safety", 1.0))
+        if mode == "learned":
+            c.mlp_set(np.array(md["params"], dtype=np.float32))
+        c.set_state()
+        st = c.step(25, dyn=torch.cuda.Stream(), kin=torch.cuda.Stream())
+        if mode == "learned":
+            assert st["misses"] == 0
+        else:
+            keys, _ = c.get_contacts()
+            print(f"{keys.size} true contacts at the end", flush=True)
+            assert keys.size > 50
+        outs.append(c.get_state())
+        c.close()
+    for k in ("X", "V", "W", "q"):
         np.testing.assert_array_equal(outs[0][k], outs[1][k])

@@ -185,3 +185,31 @@ def test_short_predicted_horizon_detects_synchronously(dem):
     a, b = c.get_state(), e.get_state()
     for k in ("X", "V", "W"):
         np.testing.assert_array_equal(a[k], b[k])
+
+
+@pytest.mark.skipif(not os.path.exists(MODEL), reason="no trained interval model in the tree")
+def test_network_gains_over_its_analytic_fallback(dem):
+    """What the network adds to the schedule without it: on a held-out bed
+    (the large-bed recipe at seed 7, 500 k owners, the cylinder rolling on
+    the bed; 1000 steps, adoption latency 5) the learned interval and its
+    analytic fallback alone (the top-speed bound, no network) both miss
+    nothing (judged), and the learned interval needs far fewer detections
+    (measured: 78 against 135)."""
+    md = json.load(open(MODEL))
+    params = np.array(md["params"], dtype=np.float32)
+    s = W.config4(seed=7, n_owners=500_000)
+    steps = 1000
+    out = {}
+    for name in ("learned", "analytic"):
+        c = dem.DemContext(s, mode="learned", k=10, lam=5, judge=True, k_max=1024, capacity=16 * s.n_spheres,
+                           mlp_safety=md.get("safety", 1.0))
+        if name == "learned":
+            c.mlp_set(params)
+        c.set_state()
+        out[name] = c.step(steps)
+        c.close()
+    ls, an = out["learned"], out["analytic"]
+    print(f"learned: {ls['cds']} detections, {ls['misses']} missed; analytic fallback: {an['cds']} detections, "
+          f"{an['misses']} missed", flush=True)
+    assert ls["misses"] == 0 and an["misses"] == 0
+    assert ls["cds"] <= 0.75 * an["cds"]

@@ -634,3 +634,108 @@ def test_config0_side_by_side_statistics(dem):
         assert abs(zg - zo) < 2e-4
     ke_g, ke_o = np.array(ke_g), np.array(ke_o)
     assert np.all(np.abs(ke_g - ke_o) <= 0.05 * ke_o + 1e-9)
+
+
+def test_fixed_schedule_tracks_the_oracle_fixed_schedule(dem):
+    """The delayed fixed-margin schedule (k = 10, adoption 5 steps later,
+    judged) on the GPU against the oracle's own run of the same schedule:
+    the same number of detections and swaps, no missed contact on either
+    side, the same final active set, and positions that agree to the level
+    of the FP32 force law accumulated over the run."""
+    import torch
+    s = W.small_spheres(5, n=512, vel=0.3)
+    steps = 300
+    ctx = dem.DemContext(s, mode="fixed", k=10, lam=5, judge=True)
+    ctx.set_state()
+    st_g = ctx.step(steps, dyn=torch.cuda.Stream(), kin=torch.cuda.Stream())
+    g = ctx.get_state()
+    keys, _ = ctx.get_contacts()
+    o = oracle.Oracle(s)
+    st, acs, st_o, _ = o.run(o.state(), steps, mode="fixed", k=10, lam=5, judge=True)
+    assert st_g["misses"] == 0 and st_o["misses"] == 0
+    assert st_g["cds"] == st_o["cds"] and st_g["swaps"] == st_o["swaps"]
+    np.testing.assert_array_equal(keys, acs[0])
+    assert np.sum(o.forces(st, acs[0], acs[1])["touch"]) > 0
+    err = np.abs(g["X"] - st["X"]).max()
+    print(f"max position difference after {steps} steps {err:.2e} m", flush=True)
+    assert err <= 1e-7
+
+
+def test_delayed_detection_stream_changes_nothing(dem):
+    """The result does not depend on when the detection stream runs: the
+    same fixed-margin run on two streams, once as is and once with a long
+    queue of device copies enqueued on the detection stream ahead of it
+    (every detection then finishes late and the dynamics stream waits at
+    each adoption step), ends in the same state and set bit for bit, and
+    equals every-step detection."""
+    import torch
+    s = W.small_clumps(9, n=300, vel=0.3, with_cylinder=True, spacing=0.0085)
+    outs = []
+    for delay in (False, True):
+        c = dem.DemContext(s, mode="fixed", k=6, lam=3)
+        c.set_state()
+        dyn, kin = torch.cuda.Stream(), torch.cuda.Stream()
+        if delay:
+            a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+            b = torch.empty_like(a)
+            with torch.cuda.stream(kin):
+                for _ in range(40):
+                    b.copy_(a)
+        st = c.step(60, dyn=dyn, kin=kin)
+        torch.cuda.synchronize()
+        outs.append((c.get_state(), c.get_contacts()[0], st))
+        c.close()
+    e = dem.DemContext(s, mode="every")
+    e.set_state()
+    e.step(60)
+    ge = e.get_state()
+    (g0, k0, s0), (g1, k1, s1) = outs
+    assert s0["cds"] == s1["cds"] > 5
+    np.testing.assert_array_equal(k0, k1)
+    for k in ("X", "V", "W", "q"):
+        np.testing.assert_array_equal(g0[k], g1[k])
+        np.testing.assert_array_equal(g0[k], ge[k])
+
+
+def test_long_run_bulk_statistics(dem):
+    """Config 0 run long enough to settle (20,000 every-step steps, 0.2 s:
+    the spheres fall onto the floor) on both sides.  The trajectories are
+    chaotic, so the packing fraction of the bottom 3 cm slab and the
+    kinetic energy are compared every 2000 steps, against an interval set
+    by the oracle itself: the spread between the oracle and the oracle
+    started from the same state with one sphere moved by 2^-36 m (a
+    rounding-level change); the GPU must stay within three times that
+    spread plus 0.01 in packing fraction and 2 % of the kinetic energy."""
+    s = W.config0()
+    ctx = dem.DemContext(s, mode="every")
+    ctx.set_state()
+    o = oracle.Oracle(s)
+    st_a = o.state()
+    st_b = o.state()
+    st_b["X"][0, 0] += 2.0 ** -36
+    vol = 4.0 / 3.0 * np.pi * s.sph_rad ** 3
+    lo, hi = np.asarray(s.domain_lo), np.asarray(s.domain_hi)
+    slab = (hi[0] - lo[0]) * (hi[1] - lo[1]) * 0.03
+
+    def stats(X, V):
+        phi = vol[X[:, 2] < lo[2] + 0.03].sum() / slab
+        ke = 0.5 * (s.own_mass * (np.asarray(V, dtype=np.float64) ** 2).sum(1)).sum()
+        return phi, ke
+
+    acs_a = acs_b = None
+    step_a = step_b = 0
+    rows = []
+    for blk in range(10):
+        ctx.step(2000)
+        st_a, acs_a, _, step_a = o.run(st_a, 2000, mode="every", acs=acs_a, step=step_a)
+        st_b, acs_b, _, step_b = o.run(st_b, 2000, mode="every", acs=acs_b, step=step_b)
+        g = ctx.get_state()
+        rows.append((stats(g["X"], g["V"]), stats(st_a["X"], st_a["V"]), stats(st_b["X"], st_b["V"])))
+    ke0 = stats(s.X, s.V)[1]
+    for (pg, kg), (pa, ka), (pb, kb) in rows:
+        print(f"phi gpu {pg:.4f} oracle {pa:.4f} perturbed {pb:.4f}; KE gpu {kg:.4e} oracle {ka:.4e} "
+              f"perturbed {kb:.4e}", flush=True)
+        assert abs(pg - pa) <= 3 * abs(pb - pa) + 0.01
+        assert abs(kg - ka) <= 3 * abs(kb - ka) + 0.02 * ka + 1e-3 * ke0
+    # the bed has settled: most of the spheres' volume is in the bottom slab
+    assert rows[-1][1][0] > 0.3

@@ -425,7 +425,10 @@ def config4(seed=0, n_owners=32_000_000, frac_single=18.0 / 32.0):
     top = base[:, 2].max() + 0.0035
     lo, hi = np.array([-half - 0.003, -half - 0.003, 0.0]), np.array([half + 0.003, half + 0.003, top + 0.25])
     R = 0.1
-    cyl = cylinder((-half + 0.3, 0.0, top + R - 0.0005), (0, 1, 0), R, 0.5, vel=(0.2, 0.0, 0.0),
+    # the cylinder starts 0.3 m in from the -x edge (on reduced beds, 5 cm
+    # short of the centre, so that it always rolls on the bed)
+    x0 = -half + min(0.3, half - 0.05)
+    cyl = cylinder((x0, 0.0, top + R - 0.0005), (0, 1, 0), R, 0.5, vel=(0.2, 0.0, 0.0),
                    omega=(0.0, 0.2 / R, 0.0))
     walls = concat_walls(box_walls(lo, hi), cyl)
     return assemble(types, base + jit, q, np.zeros((n_owners, 3)), np.zeros((n_owners, 3)),
