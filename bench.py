@@ -74,7 +74,7 @@ def parse():
 
 
 def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, rolling=False, n_clump=None, n_tri=0,
-                      n_dormant=0, n_dormant_clump=0):
+                      n_dormant=0, n_dormant_clump=0, n_dormant_sph=0):
     """Bytes one launch of a stage must move at minimum (unique data);
     `active` = spheres that appear in at least one contact:
     k_force: per sphere its row offset (4); per active sphere its record
@@ -102,7 +102,10 @@ def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, roll
       count and offsets (8), staging (4 per partner), B lists (16); per
       contact partner id (4) and B-list bytes (16); the bin table (12 per bin);
       with meshes, per facet its vertices read (80), its world vertices, box
-      and bin range written (144) and its row count and offset (8).
+      and bin range written (144) and its row count and offset (8).  Only
+      the spheres the detection bins count: the spheres of dormant owners
+      are left out of it (the binned spheres' walks over the dormant index
+      read data the caches serve and are not counted).
     k_remap: per sphere both row offsets (16); per contact new id (4), old id
       (4), history read (12) and written (12)."""
     if stage == "k_force":
@@ -115,7 +118,7 @@ def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, roll
     if stage == "k_fold_integrate":
         return No * (116 if clumps else 100) + Ns * 8 + active * 24 + C * 28
     if stage == "detect":
-        return Ns * (64 + 8 + 32 + 16 * passes + 68 + 32 + 8 + 16) + C * 24 + nbins * 12 + n_tri * 232
+        return (Ns - n_dormant_sph) * (64 + 8 + 32 + 16 * passes + 68 + 32 + 8 + 16) + C * 24 + nbins * 12 + n_tri * 232
     if stage == "k_remap":
         return Ns * 16 + C * 32
     raise ValueError(stage)
@@ -438,6 +441,7 @@ def main():
     dormant = (np.asarray(sysm.fam_fixed)[fam] > 0) if fam.size else np.zeros(No, dtype=bool)
     n_dormant = int(dormant.sum())
     n_dormant_clump = int(np.sum(dormant & (np.asarray(sysm.own_tmpl) >= 0)))
+    n_dormant_sph = int(np.sum(dormant[np.asarray(sysm.sph_owner)])) if n_dormant else 0
     rolling = bool(np.any(np.asarray(sysm.mat_crr) > 0))
     passes = 1   # one-pass bin sort (the LSD radix option would take (sort_bits + 7) // 8)
     # the dynamics form the timed run used: the split clump step (streaming
@@ -492,7 +496,8 @@ def main():
                                      "achieved": round(algo_k[other] / (o_ms * 1e-3) / 1e9, 1)}
     n_cd = max(int(cnt[2]), 1)
     cd_ms = tot[2] / n_cd
-    cd_bytes = algorithmic_bytes("detect", Ns, No, C, r["active"], r["info"]["nbins"], passes, n_tri=n_tri)
+    cd_bytes = algorithmic_bytes("detect", Ns, No, C, r["active"], r["info"]["nbins"], passes, n_tri=n_tri,
+                                 n_dormant_sph=n_dormant_sph)
     cd_chain = {"avg_ms": round(cd_ms, 4), "launches": n_cd, "algorithmic_bytes": int(cd_bytes),
                 "achieved_GBs": round(cd_bytes / (cd_ms * 1e-3) / 1e9, 1) if cd_ms > 0 else None,
                 "note": "detection chain on the second stream, concurrent with the dynamics stream"}
@@ -539,9 +544,10 @@ def main():
         else:
             dyn_b = (algorithmic_bytes("k_force", Ns, No, Cm, act, 0, passes)
                      + algorithmic_bytes("k_fold_integrate", Ns, No, Cm, act, 0, passes, clumps=Ns != No))
-        per_cd = algorithmic_bytes("detect", Ns, No, Cm, act, rr["info"]["nbins"], passes, n_tri=n_tri)
+        per_cd = algorithmic_bytes("detect", Ns, No, Cm, act, rr["info"]["nbins"], passes, n_tri=n_tri,
+                                   n_dormant_sph=n_dormant_sph)
         if fused_front and mode not in ("every", "adaptive"):
-            per_cd -= 64 * Ns   # (the sphere and owner records are not read a second time)
+            per_cd -= 64 * (Ns - n_dormant_sph)   # (the sphere and owner records are not read a second time)
         if args.dyn_path == 1:
             per_cd += algorithmic_bytes("k_remap", Ns, No, Cm, act, 0, passes)
         return dyn_b + per_cd * s2["cds"] / args.steps

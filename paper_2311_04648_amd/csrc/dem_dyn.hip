@@ -1037,23 +1037,27 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
 // with them, the orientation (clumps only) once the template is known.
 // REMAP: the first step on a newly adopted set (only its overflow check
 // matters here).
+constexpr int FREE_WAVES = 2;    // waves per block of k_step_free
+constexpr int FREE_CHUNKS = 2;   // 64-owner chunks per wave (FREE_WAVES * FREE_CHUNKS * 64 == TPB owners per block)
+static_assert(FREE_WAVES * FREE_CHUNKS * 64 == TPB, "a streaming block covers the owners of one speed slot");
+
 template <bool REMAP>
-__global__ void __launch_bounds__(TPB) k_step_free(DynArgs a, OwnerRec *rec_out, double *q_out,
-                                                   const uint8_t *oany, DevCounters *ctr)
+__global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, OwnerRec *rec_out, double *q_out,
+                                                              const uint8_t *oany, DevCounters *ctr)
 {
-    __shared__ uint4 wbuf[TPB / 64][192];
+    // each wave streams FREE_CHUNKS chunks of 64 consecutive owners: every
+    // load of all its chunks is issued before any chunk is computed, so a
+    // wave keeps twice the bytes in flight
+    __shared__ uint4 wbuf[FREE_WAVES][FREE_CHUNKS][192];
     const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t No = a.n_owners;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int64_t o0 = (int64_t)lb * blockDim.x + threadIdx.x;
-    const int64_t ow = (int64_t)lb * blockDim.x + 64 * wv;
-    const int64_t o = ow + lane;
-    const bool valid = o < No;
+    const int64_t ob = (int64_t)lb * TPB;
     const bool rm_over = REMAP && ctr->overflow[a.rm_newbuf] != 0u;
-    if (rm_over && o0 == 0) ctr->stop_cd = 1u;
+    if (rm_over && ob + threadIdx.x == 0) ctr->stop_cd = 1u;
     const bool halt = rm_over || stopped(ctr, a.step);
-    if (o0 == 0) {
+    if (ob + threadIdx.x == 0) {
         if (halt) {
             halt_mark(ctr, a.step);
         } else {
@@ -1063,46 +1067,86 @@ __global__ void __launch_bounds__(TPB) k_step_free(DynArgs a, OwnerRec *rec_out,
         }
     }
     float v2 = 0.0f;
-    if (ow < No) {
-        const uint32_t nv = (uint32_t)(No - ow < 64 ? No - ow : 64);
-        uint8_t fl = 1u;
-        OwnerAux ax{};
-        if (valid) {
-            fl = oany[o];
-            ax = a.aux[o];
+    uint8_t fl[FREE_CHUNKS];
+    OwnerAux ax[FREE_CHUNKS];
+    uint32_t nv[FREE_CHUNKS];
+    // loads: flags, inertia and the records (through LDS) of every chunk
+#pragma unroll
+    for (int c = 0; c < FREE_CHUNKS; ++c) {
+        const int64_t ow = ob + (int64_t)(wv * FREE_CHUNKS + c) * 64;
+        const int64_t o = ow + lane;
+        nv[c] = ow < No ? (uint32_t)(No - ow < 64 ? No - ow : 64) : 0u;
+        fl[c] = 1u;
+        ax[c] = OwnerAux{};
+        if (o < No) {
+            fl[c] = oany[o];
+            ax[c] = a.aux[o];
         }
-        uint4 *lrec = wbuf[wv];
         const uint4 *src = reinterpret_cast<const uint4 *>(a.rec + ow);
-        for (uint32_t k = lane; k < 3u * nv; k += 64u) lrec[k] = src[k];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        OwnerRec r{};
-        if (valid) r = load_rec(reinterpret_cast<const OwnerRec *>(lrec) + lane);
-        const bool rot = valid && ax.tmpl >= 0;
-        double4 qv = make_double4(1.0, 0.0, 0.0, 0.0);
-        if (rot && (halt || !(fl & 1u))) qv = *reinterpret_cast<const double4 *>(a.q + 4 * (size_t)o);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (uint32_t k = lane; k < 3u * nv[c]; k += 64u) wbuf[wv][c][k] = src[k];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    OwnerRec r[FREE_CHUNKS];
+    double4 qv[FREE_CHUNKS];
+#pragma unroll
+    for (int c = 0; c < FREE_CHUNKS; ++c) {
+        const bool valid = lane < nv[c];
+        const int64_t o = ob + (int64_t)(wv * FREE_CHUNKS + c) * 64 + lane;
+        r[c] = OwnerRec{};
+        if (valid) r[c] = load_rec(reinterpret_cast<const OwnerRec *>(wbuf[wv][c]) + lane);
+        qv[c] = make_double4(1.0, 0.0, 0.0, 0.0);
+        if (valid && ax[c].tmpl >= 0 && (halt || !(fl[c] & 1u)))
+            qv[c] = *reinterpret_cast<const double4 *>(a.q + 4 * (size_t)o);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // (the orientation buffer is written for single spheres too, with the
+    // identity they keep: whole lines of it are written, none read back to
+    // merge a partial write)
+#pragma unroll
+    for (int c = 0; c < FREE_CHUNKS; ++c) {
+        const bool valid = lane < nv[c];
+        const int64_t o = ob + (int64_t)(wv * FREE_CHUNKS + c) * 64 + lane;
+        const bool rot = valid && ax[c].tmpl >= 0;
+        double *qo = q_out + 4 * (size_t)o;
         if (halt) {
             // a stopped step: the state is copied unchanged (the records
             // below, the orientation here; the history by k_step_listed)
-            if (rot) *reinterpret_cast<double4 *>(q_out + 4 * (size_t)o) = qv;
-        } else if (valid && !(fl & 1u)) {
-            const float inv[3] = {ax.inv_moi[0], ax.inv_moi[1], ax.inv_moi[2]};
-            v2 = advance(a, r, inv, rot, f3(0.f, 0.f, 0.f), f3(0.f, 0.f, 0.f), qv, q_out + 4 * (size_t)o, ctr);
-            store_rec(reinterpret_cast<OwnerRec *>(lrec) + lane, r);
+            if (valid) *reinterpret_cast<double4 *>(qo) = qv[c];
+        } else if (valid && !(fl[c] & 1u)) {
+            const float inv[3] = {ax[c].inv_moi[0], ax[c].inv_moi[1], ax[c].inv_moi[2]};
+            v2 = fmaxf(v2, advance(a, r[c], inv, rot, f3(0.f, 0.f, 0.f), f3(0.f, 0.f, 0.f), qv[c], qo, ctr));
+            if (!rot) *reinterpret_cast<double4 *>(qo) = qv[c];
+            store_rec(reinterpret_cast<OwnerRec *>(wbuf[wv][c]) + lane, r[c]);
+        } else if (valid && !rot) {
+            *reinterpret_cast<double4 *>(qo) = qv[c];
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // (the records of owners with contacts go out unchanged here and
-        // are overwritten by k_step_listed)
-        uint4 *dst = reinterpret_cast<uint4 *>(rec_out + ow);
-        for (uint32_t k = lane; k < 3u * nv; k += 64u) dst[k] = lrec[k];
     }
-    if (!halt) block_max_v2(v2, a.blkmax + lb);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // (the records of owners with contacts go out unchanged here and are
+    // overwritten by k_step_listed)
+#pragma unroll
+    for (int c = 0; c < FREE_CHUNKS; ++c) {
+        const int64_t ow = ob + (int64_t)(wv * FREE_CHUNKS + c) * 64;
+        uint4 *dst = reinterpret_cast<uint4 *>(rec_out + ow);
+        for (uint32_t k = lane; k < 3u * nv[c]; k += 64u) dst[k] = wbuf[wv][c][k];
+    }
+    if (halt) return;
+    __shared__ float wmax[FREE_WAVES];
+    if (!(v2 == v2)) v2 = 3.0e38f;
+    for (int d = 32; d > 0; d >>= 1) v2 = fmaxf(v2, __shfl_xor(v2, d, 64));
+    if (lane == 0) wmax[wv] = v2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m = wmax[0];
+        for (int k = 1; k < FREE_WAVES; ++k) m = fmaxf(m, wmax[k]);
+        a.blkmax[lb] = m;
+    }
 }
 
 // The owners with contacts of a split step (see k_step_free), from the
@@ -1283,8 +1327,8 @@ bool launch_step_fused(const DynArgs &a, OwnerRec *rec_out, double *q_out, const
         const bool r = a.rm_start != nullptr;
         const unsigned nb = nblocks(a.n_owners);
         if (tm && tm->free0) hipEventRecord(tm->free0, s);
-        hipLaunchKernelGGL(r ? k_step_free<true> : k_step_free<false>, dim3(nb), dim3(TPB), 0, s, a, rec_out, q_out,
-                           (const uint8_t *)cur.oany, ctr);
+        hipLaunchKernelGGL(r ? k_step_free<true> : k_step_free<false>, dim3(nb), dim3(FREE_WAVES * 64), 0, s, a,
+                           rec_out, q_out, (const uint8_t *)cur.oany, ctr);
         if (tm && tm->free1) hipEventRecord(tm->free1, s);
         if (tm && tm->list0) hipEventRecord(tm->list0, s);
         auto kl = a.n_tri > 0 ? (r ? k_step_listed<true, true> : k_step_listed<true, false>)

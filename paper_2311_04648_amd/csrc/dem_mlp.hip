@@ -246,7 +246,8 @@ constexpr int FEAT_WAVE_ITERS = 8;
 constexpr int64_t FEAT_OWNERS = 4 * 64 * FEAT_WAVE_ITERS;   // 2048
 constexpr int FEAT_SLOTS = 512;
 constexpr uint32_t FEAT_EMPTY = 0xffffffffu;
-constexpr int FEAT_VALS = 12;   // vmax x3, vmin x3, dv, va, dx, count, volume (2 words)
+// per cell: vmax x3, vmin x3 (words 0-5), max dv, va, dx (6-8), volume (u64, 10-11); a cell is
+// occupied once its x-velocity minimum is set (word 3 below 0xffffffff)
 
 __device__ inline void feat_global_add(uint32_t *rw, const uint32_t *a, unsigned long long vol)
 {
@@ -257,7 +258,6 @@ __device__ inline void feat_global_add(uint32_t *rw, const uint32_t *a, unsigned
     atomicMax(&rw[6], a[6]);
     atomicMax(&rw[7], a[7]);
     atomicMax(&rw[8], a[8]);
-    atomicAdd(&rw[9], a[9]);
     atomicAdd(reinterpret_cast<unsigned long long *>(&rw[10]), vol);
 }
 
@@ -266,7 +266,7 @@ __global__ void __launch_bounds__(256) k_feat_accum(const OwnerRec *rec, const S
                                                    uint32_t *cellmap, int64_t No)
 {
     __shared__ uint32_t tkey[FEAT_SLOTS];
-    __shared__ uint32_t tval[FEAT_SLOTS][10];
+    __shared__ uint32_t tval[FEAT_SLOTS][9];
     __shared__ unsigned long long tvol[FEAT_SLOTS];
     __shared__ uint4 lrec[4][192];
     for (int k = threadIdx.x; k < FEAT_SLOTS; k += blockDim.x) {
@@ -275,7 +275,7 @@ __global__ void __launch_bounds__(256) k_feat_accum(const OwnerRec *rec, const S
             tval[k][j] = 0u;
             tval[k][3 + j] = 0xffffffffu;
         }
-        for (int j = 6; j < 10; ++j) tval[k][j] = 0u;
+        for (int j = 6; j < 9; ++j) tval[k][j] = 0u;
         tvol[k] = 0ull;
     }
     __syncthreads();
@@ -303,7 +303,7 @@ __global__ void __launch_bounds__(256) k_feat_accum(const OwnerRec *rec, const S
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         uint32_t c = FEAT_EMPTY;
-        uint32_t a[10] = {0u, 0u, 0u, 0xffffffffu, 0xffffffffu, 0xffffffffu, 0u, 0u, 0u, 0u};
+        uint32_t a[9] = {0u, 0u, 0u, 0xffffffffu, 0xffffffffu, 0xffffffffu, 0u, 0u, 0u};
         unsigned long long iv = 0ull;
         if (valid) {
             const OwnerRec r = load_rec(reinterpret_cast<const OwnerRec *>(lrec[wv]) + lane);
@@ -327,7 +327,6 @@ __global__ void __launch_bounds__(256) k_feat_accum(const OwnerRec *rec, const S
             a[6] = __float_as_uint(dv);
             a[7] = __float_as_uint(va);
             a[8] = __float_as_uint(dx);
-            a[9] = 1u;
             // fixed-point volume in units of 1e-18 m^3
             iv = (unsigned long long)((double)vo * 1e18 + 0.5);
             if (snap_out) {
@@ -348,9 +347,9 @@ __global__ void __launch_bounds__(256) k_feat_accum(const OwnerRec *rec, const S
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
             const bool take = lane - d >= seg0;
-            uint32_t t[10];
+            uint32_t t[9];
 #pragma unroll
-            for (int k = 0; k < 10; ++k) t[k] = (uint32_t)__shfl_up((int)a[k], d, 64);
+            for (int k = 0; k < 9; ++k) t[k] = (uint32_t)__shfl_up((int)a[k], d, 64);
             const unsigned long long tv = (unsigned long long)__shfl_up((long long)iv, d, 64);
             if (take) {
 #pragma unroll
@@ -361,7 +360,6 @@ __global__ void __launch_bounds__(256) k_feat_accum(const OwnerRec *rec, const S
                 a[6] = max(a[6], t[6]);
                 a[7] = max(a[7], t[7]);
                 a[8] = max(a[8], t[8]);
-                a[9] += t[9];
                 iv += tv;
             }
         }
@@ -383,7 +381,6 @@ __global__ void __launch_bounds__(256) k_feat_accum(const OwnerRec *rec, const S
                 atomicMax(&tval[h][6], a[6]);
                 atomicMax(&tval[h][7], a[7]);
                 atomicMax(&tval[h][8], a[8]);
-                atomicAdd(&tval[h][9], a[9]);
                 atomicAdd(&tvol[h], iv);
             } else {
                 feat_global_add(raw + (int64_t)c * RAW, a, iv);
@@ -397,8 +394,8 @@ __global__ void __launch_bounds__(256) k_feat_accum(const OwnerRec *rec, const S
     for (int k = threadIdx.x; k < FEAT_SLOTS; k += blockDim.x) {
         const uint32_t c = tkey[k];
         if (c == FEAT_EMPTY) continue;
-        uint32_t a[10];
-        for (int j = 0; j < 10; ++j) a[j] = tval[k][j];
+        uint32_t a[9];
+        for (int j = 0; j < 9; ++j) a[j] = tval[k][j];
         feat_global_add(raw + (int64_t)c * RAW, a, tvol[k]);
     }
 }
@@ -407,7 +404,7 @@ __global__ void __launch_bounds__(256) k_feat_flags(const uint32_t *raw, int64_t
 {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
-    flag[c] = raw[c * RAW + 9] > 0u ? 1u : 0u;
+    flag[c] = raw[c * RAW + 3] != 0xffffffffu ? 1u : 0u;
 }
 
 __global__ void __launch_bounds__(256) k_feat_write(const uint32_t *raw, const uint32_t *pos, int64_t ncell,
@@ -417,7 +414,7 @@ __global__ void __launch_bounds__(256) k_feat_write(const uint32_t *raw, const u
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
     const uint32_t *r = raw + c * RAW;
-    if (r[9] == 0u) return;
+    if (r[3] == 0xffffffffu) return;
     uint32_t p = pos[c];
     float vr[3];
     for (int k = 0; k < 3; ++k) vr[k] = ord_dec(r[k]) - ord_dec(r[3 + k]);
@@ -466,7 +463,7 @@ __global__ void __launch_bounds__(256) k_feat_predict(const uint32_t *raw, int64
     load_params(params, sp);
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     float rr = 3.0e38f;
-    if (c < ncell && raw[c * RAW + 9] > 0u) {
+    if (c < ncell && raw[c * RAW + 3] != 0xffffffffu) {
         float x[NF], h1[H], h2[H];
         feat_of_cell(raw + c * RAW, h, margin, tau, K, cell_vol, x);
         const float y = mlp_eval(sp, x, h1, h2);

@@ -23,7 +23,7 @@ import json
 import os
 import sys
 
-DYN_KERNELS = ("k_step_fused", "k_fold_integrate")
+DYN_KERNELS = ("k_step_fused", "k_fold_integrate", "k_step_free")
 
 
 def _name(raw):

@@ -55,8 +55,20 @@ def test_mlp_backward_matches_oracle(dem, n, tau):
     lref, gref = omlp.loss_and_grad(p, X, T, tau)
     assert abs(loss.item() - lref) <= 1e-5 * abs(lref)
     scale = np.abs(gref).max()
-    err = np.abs(g - gref) / np.maximum(np.abs(gref), 1e-3 * scale)
-    assert err.max() <= 1e-5 * 10, err.max()
+    # 1e-5 of the gradient (floored at 1e-3 of its largest component), plus
+    # the float32 rounding of a sum that cancels: each per-sample term
+    # carries up to ~20 roundings of the forward and backward passes, a
+    # block adds 64 terms in order and the blocks' partial sums are added in
+    # order, each addition rounding at most 2^-24 of the magnitudes summed so
+    # far, so |error| <= 2^-24 (20 + 64 + blocks) times the summed term
+    # magnitudes (oracle grad_term_magnitudes)
+    nblk = (n + 63) // 64
+    A = omlp.grad_term_magnitudes(p, X, T, tau)
+    tol = 1e-5 * np.maximum(np.abs(gref), 1e-3 * scale) + 2.0 ** -24 * (20 + 64 + nblk) * A
+    err = np.abs(g - gref)
+    print(f"n {n}: max err / tol {(err / tol).max():.3f}, max rel err "
+          f"{(err / np.maximum(np.abs(gref), 1e-3 * scale)).max():.2e}", flush=True)
+    assert np.all(err <= tol)
     # deterministic: same bits twice
     g2, _ = dem.mlp_backward(torch.tensor(p, dtype=torch.float32, device=dev),
                              torch.tensor(X, dtype=torch.float32, device=dev),

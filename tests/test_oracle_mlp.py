@@ -140,3 +140,26 @@ def test_labels_first_miss_at_touch_time():
     gap_exact = abs(s.X[1, 0] - s.X[0, 0]) - 2 * s.sph_rad[0]
     t_touch = math.floor(gap_exact / (v * s.dt)) + 1
     assert first.min() == t_touch
+
+
+def test_grad_term_magnitudes_bound_the_gradient():
+    """The summed term magnitudes bound the gradient component by component
+    (|sum| <= sum of |terms|), equal it where no term changes sign (a
+    single sample with positive inputs, weights and residual), and scale
+    linearly with the number of identical samples."""
+    rng = np.random.default_rng(3)
+    p = rng.normal(0, 0.3, size=mlp.NPARAM)
+    X = rng.normal(0, 1.0, size=(50, mlp.NF))
+    T = rng.normal(0, 1.0, size=50)
+    _, g = mlp.loss_and_grad(p, X, T, 0.05)
+    A = mlp.grad_term_magnitudes(p, X, T, 0.05)
+    assert np.all(np.abs(g) <= A * (1 + 1e-12) + 1e-300)
+    pp = np.abs(p)
+    x1 = np.abs(X[:1])
+    t1 = np.array([-5.0])   # prediction above the target: positive residual
+    _, g1 = mlp.loss_and_grad(pp, x1, t1, 0.05)
+    A1 = mlp.grad_term_magnitudes(pp, x1, t1, 0.05)
+    np.testing.assert_allclose(np.abs(g1), A1, rtol=1e-12, atol=1e-300)
+    A3 = mlp.grad_term_magnitudes(p, np.repeat(X[:1], 3, 0), np.repeat(T[:1], 3), 0.05)
+    Ab = mlp.grad_term_magnitudes(p, X[:1], T[:1], 0.05)
+    np.testing.assert_allclose(A3, Ab, rtol=1e-12)   # (the mean over n: 3 equal samples, 1/3 each)
