@@ -83,6 +83,29 @@ def loss_and_grad(p, X, T, tau):
     return loss, pack(dW1, db1, dW2, db2, dW3, db3)
 
 
+def grad_term_magnitudes(p, X, T, tau):
+    """Per parameter, the summed magnitudes of the per-sample terms its
+    gradient adds up (back-propagation with every factor replaced by its
+    magnitude, and every inner sum by the sum of its terms' magnitudes):
+    the scale against which a float32 evaluation's rounding is bounded."""
+    W1, b1, W2, b2, W3, b3 = unpack(p)
+    y, (X, h1, h2) = forward(p, X)
+    n = X.shape[0]
+    r = y - np.asarray(T, dtype=np.float64)
+    w = np.where(r > 0.0, 1.0 - tau, tau)
+    g = np.abs(2.0 * w * r / n)
+    aX, a1, a2 = np.abs(X), np.abs(h1), np.abs(h2)
+    dW3 = (g @ a2)[None, :]
+    db3 = np.array([g.sum()])
+    d2 = (g[:, None] * np.abs(W3)) * (1.0 - h2 * h2)
+    dW2 = d2.T @ a1
+    db2 = d2.sum(0)
+    d1 = (d2 @ np.abs(W2)) * (1.0 - h1 * h1)
+    dW1 = d1.T @ aX
+    db1 = d1.sum(0)
+    return pack(dW1, db1, dW2, db2, dW3, db3)
+
+
 def adam_step(p, g, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     """One Adam update (Kingma & Ba), returning new (p, m, v)."""
     m = beta1 * m + (1.0 - beta1) * g
