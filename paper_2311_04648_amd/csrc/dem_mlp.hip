@@ -220,24 +220,23 @@ __device__ inline uint32_t fcell_of(const Grid &g, double x, double y, double z)
 __global__ void __launch_bounds__(256) k_feat_clear(uint32_t *raw, int64_t ncell)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ncell) return;
-    uint32_t *r = raw + i * RAW;
-    for (int k = 0; k < 3; ++k) {
-        r[k] = 0u;            // max of encoded v (encoded values are > 0)
-        r[3 + k] = 0xffffffffu;  // min of encoded v
-    }
-    for (int k = 6; k < RAW; ++k) r[k] = 0u;
+    if (i >= ncell * (RAW / 4)) return;
+    reinterpret_cast<uint4 *>(raw)[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 // Per-owner contributions to its feature cell.  Each block takes
 // FEAT_OWNERS consecutive owners, each wave 64 consecutive ones at a time.
 // Consecutive owners are mostly spatial neighbours, so the lanes of a wave
 // fall into a few runs of equal cells: a segmented scan over the lanes
-// (integer max / min / sums, order-free) combines each run, and the last
-// lane of a run adds it to the block's table of cells in LDS (LDS atomics,
-// open addressing on the cell id); when the block is done, each cell of
-// its table goes to the global accumulators with one atomic per value.  A
-// cell that finds the table full goes straight to the global accumulators.
+// (integer max and sums, order-free) combines each run, and the last lane
+// of a run adds it to the block's table of cells in LDS (LDS atomics, open
+// addressing on the low bits of the cell id, so that neighbouring cells take
+// neighbouring slots).  When the block is done, its table goes to the global
+// accumulators a few cells per wave instruction, one lane per accumulator
+// word, so that an instruction's atomics fall on the consecutive words of
+// consecutive cells (a few cache lines) rather than on 64 cells spread over
+// the grid.  A cell that finds the table full goes straight to the global
+// accumulators.
 // With snap_out set, each owner's current position and velocity are
 // written there after its snapshot is read (snap_out may equal snap: the
 // thread that reads a record writes it).  With cellmap set, each owner's
@@ -246,18 +245,17 @@ constexpr int FEAT_WAVE_ITERS = 8;
 constexpr int64_t FEAT_OWNERS = 4 * 64 * FEAT_WAVE_ITERS;   // 2048
 constexpr int FEAT_SLOTS = 512;
 constexpr uint32_t FEAT_EMPTY = 0xffffffffu;
-// per cell: vmax x3, vmin x3 (words 0-5), max dv, va, dx (6-8), volume (u64, 10-11); a cell is
-// occupied once its x-velocity minimum is set (word 3 below 0xffffffff)
+// Per cell (RAW words, zero when cleared), every word but the volume a
+// maximum: words 0-2 the largest encoded velocity component, 3-5 the
+// complement of the smallest (~enc: the complement turns the minimum into a
+// maximum), 6-8 max dv, va, dx (non-negative float bits), 10-11 the volume
+// (u64 sum).  The complement of an encoded value is zero only for one NaN
+// pattern, so a cell is occupied once word 3 is non-zero.
+constexpr int FEAT_MAXW = 9;
 
 __device__ inline void feat_global_add(uint32_t *rw, const uint32_t *a, unsigned long long vol)
 {
-    for (int k = 0; k < 3; ++k) {
-        atomicMax(&rw[k], a[k]);
-        atomicMin(&rw[3 + k], a[3 + k]);
-    }
-    atomicMax(&rw[6], a[6]);
-    atomicMax(&rw[7], a[7]);
-    atomicMax(&rw[8], a[8]);
+    for (int k = 0; k < FEAT_MAXW; ++k) atomicMax(&rw[k], a[k]);
     atomicAdd(reinterpret_cast<unsigned long long *>(&rw[10]), vol);
 }
 
@@ -266,16 +264,12 @@ __global__ void __launch_bounds__(256) k_feat_accum(const OwnerRec *rec, const S
                                                    uint32_t *cellmap, int64_t No)
 {
     __shared__ uint32_t tkey[FEAT_SLOTS];
-    __shared__ uint32_t tval[FEAT_SLOTS][9];
+    __shared__ uint32_t tval[FEAT_SLOTS][FEAT_MAXW];
     __shared__ unsigned long long tvol[FEAT_SLOTS];
     __shared__ uint4 lrec[4][192];
     for (int k = threadIdx.x; k < FEAT_SLOTS; k += blockDim.x) {
         tkey[k] = FEAT_EMPTY;
-        for (int j = 0; j < 3; ++j) {
-            tval[k][j] = 0u;
-            tval[k][3 + j] = 0xffffffffu;
-        }
-        for (int j = 6; j < 9; ++j) tval[k][j] = 0u;
+        for (int j = 0; j < FEAT_MAXW; ++j) tval[k][j] = 0u;
         tvol[k] = 0ull;
     }
     __syncthreads();
@@ -303,7 +297,7 @@ __global__ void __launch_bounds__(256) k_feat_accum(const OwnerRec *rec, const S
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         uint32_t c = FEAT_EMPTY;
-        uint32_t a[9] = {0u, 0u, 0u, 0xffffffffu, 0xffffffffu, 0xffffffffu, 0u, 0u, 0u};
+        uint32_t a[FEAT_MAXW] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
         unsigned long long iv = 0ull;
         if (valid) {
             const OwnerRec r = load_rec(reinterpret_cast<const OwnerRec *>(lrec[wv]) + lane);
@@ -317,7 +311,7 @@ __global__ void __launch_bounds__(256) k_feat_accum(const OwnerRec *rec, const S
             for (int k = 0; k < 3; ++k) {
                 const uint32_t e = ord_enc(r.v[k]);
                 a[k] = e;
-                a[3 + k] = e;
+                a[3 + k] = ~e;
             }
             const float dv0 = r.v[0] - sr.v[0], dv1 = r.v[1] - sr.v[1], dv2 = r.v[2] - sr.v[2];
             const float dv = sqrtf((dv0 * dv0 + dv1 * dv1) + dv2 * dv2);
@@ -347,26 +341,20 @@ __global__ void __launch_bounds__(256) k_feat_accum(const OwnerRec *rec, const S
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
             const bool take = lane - d >= seg0;
-            uint32_t t[9];
+            uint32_t t[FEAT_MAXW];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) t[k] = (uint32_t)__shfl_up((int)a[k], d, 64);
+            for (int k = 0; k < FEAT_MAXW; ++k) t[k] = (uint32_t)__shfl_up((int)a[k], d, 64);
             const unsigned long long tv = (unsigned long long)__shfl_up((long long)iv, d, 64);
             if (take) {
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    a[k] = max(a[k], t[k]);
-                    a[3 + k] = min(a[3 + k], t[3 + k]);
-                }
-                a[6] = max(a[6], t[6]);
-                a[7] = max(a[7], t[7]);
-                a[8] = max(a[8], t[8]);
+                for (int k = 0; k < FEAT_MAXW; ++k) a[k] = max(a[k], t[k]);
                 iv += tv;
             }
         }
         const uint32_t cnext = (uint32_t)__shfl_down((int)c, 1, 64);
         const bool tail = valid && (lane == 63 || cnext != c || !(o + 1 < No));
         if (tail) {
-            uint32_t h = (c * 2654435761u) >> 23;   // 9 bits: FEAT_SLOTS slots
+            uint32_t h = c & (FEAT_SLOTS - 1);
             int probe = 0;
             for (; probe < FEAT_SLOTS; ++probe) {
                 const uint32_t old = atomicCAS(&tkey[h], FEAT_EMPTY, c);
@@ -374,13 +362,7 @@ __global__ void __launch_bounds__(256) k_feat_accum(const OwnerRec *rec, const S
                 h = (h + 1u) & (FEAT_SLOTS - 1);
             }
             if (probe < FEAT_SLOTS) {
-                for (int k = 0; k < 3; ++k) {
-                    atomicMax(&tval[h][k], a[k]);
-                    atomicMin(&tval[h][3 + k], a[3 + k]);
-                }
-                atomicMax(&tval[h][6], a[6]);
-                atomicMax(&tval[h][7], a[7]);
-                atomicMax(&tval[h][8], a[8]);
+                for (int k = 0; k < FEAT_MAXW; ++k) atomicMax(&tval[h][k], a[k]);
                 atomicAdd(&tvol[h], iv);
             } else {
                 feat_global_add(raw + (int64_t)c * RAW, a, iv);
@@ -391,12 +373,20 @@ __global__ void __launch_bounds__(256) k_feat_accum(const OwnerRec *rec, const S
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < FEAT_SLOTS; k += blockDim.x) {
+    // the table out: RAW lanes per slot, lane w adding word w of its slot's
+    // cell (the maxima, then the volume; the other words stay unused)
+    static_assert(RAW == 16 && 256 % RAW == 0, "one lane per accumulator word");
+    const int w = (int)(threadIdx.x & (RAW - 1));
+    for (int k = (int)threadIdx.x / RAW; k < FEAT_SLOTS; k += 256 / RAW) {
         const uint32_t c = tkey[k];
         if (c == FEAT_EMPTY) continue;
-        uint32_t a[9];
-        for (int j = 0; j < 9; ++j) a[j] = tval[k][j];
-        feat_global_add(raw + (int64_t)c * RAW, a, tvol[k]);
+        uint32_t *rw = raw + (int64_t)c * RAW;
+        if (w < FEAT_MAXW) {
+            const uint32_t v = tval[k][w];
+            if (v != 0u) atomicMax(&rw[w], v);
+        } else if (w == 10) {
+            atomicAdd(reinterpret_cast<unsigned long long *>(&rw[10]), tvol[k]);
+        }
     }
 }
 
@@ -404,7 +394,7 @@ __global__ void __launch_bounds__(256) k_feat_flags(const uint32_t *raw, int64_t
 {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
-    flag[c] = raw[c * RAW + 3] != 0xffffffffu ? 1u : 0u;
+    flag[c] = raw[c * RAW + 3] != 0u ? 1u : 0u;
 }
 
 __global__ void __launch_bounds__(256) k_feat_write(const uint32_t *raw, const uint32_t *pos, int64_t ncell,
@@ -414,10 +404,10 @@ __global__ void __launch_bounds__(256) k_feat_write(const uint32_t *raw, const u
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
     const uint32_t *r = raw + c * RAW;
-    if (r[3] == 0xffffffffu) return;
+    if (r[3] == 0u) return;
     uint32_t p = pos[c];
     float vr[3];
-    for (int k = 0; k < 3; ++k) vr[k] = ord_dec(r[k]) - ord_dec(r[3 + k]);
+    for (int k = 0; k < 3; ++k) vr[k] = ord_dec(r[k]) - ord_dec(~r[3 + k]);
     float spread = sqrtf((vr[0] * vr[0] + vr[1] * vr[1]) + vr[2] * vr[2]);
     float dv = __uint_as_float(r[6]), va = __uint_as_float(r[7]), dx = __uint_as_float(r[8]);
     unsigned long long iv = *reinterpret_cast<const unsigned long long *>(r + 10);
@@ -441,7 +431,7 @@ __device__ inline void feat_of_cell(const uint32_t *r, float h, float margin, fl
                                     float *f)
 {
     float vr[3];
-    for (int k = 0; k < 3; ++k) vr[k] = ord_dec(r[k]) - ord_dec(r[3 + k]);
+    for (int k = 0; k < 3; ++k) vr[k] = ord_dec(r[k]) - ord_dec(~r[3 + k]);
     const float spread = sqrtf((vr[0] * vr[0] + vr[1] * vr[1]) + vr[2] * vr[2]);
     const float dv = __uint_as_float(r[6]), va = __uint_as_float(r[7]), dx = __uint_as_float(r[8]);
     const unsigned long long iv = *reinterpret_cast<const unsigned long long *>(r + 10);
@@ -463,7 +453,7 @@ __global__ void __launch_bounds__(256) k_feat_predict(const uint32_t *raw, int64
     load_params(params, sp);
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     float rr = 3.0e38f;
-    if (c < ncell && raw[c * RAW + 3] != 0xffffffffu) {
+    if (c < ncell && raw[c * RAW + 3] != 0u) {
         float x[NF], h1[H], h2[H];
         feat_of_cell(raw + c * RAW, h, margin, tau, K, cell_vol, x);
         const float y = mlp_eval(sp, x, h1, h2);
@@ -579,7 +569,7 @@ static void feature_accumulate(const OwnerRec *rec, const SnapRec *snap, SnapRec
                                Origin org, Grid fg, uint32_t *raw, uint32_t *cellmap, int64_t No, hipStream_t s)
 {
     const int64_t nc = (int64_t)fg.nbins;
-    hipLaunchKernelGGL(k_feat_clear, dim3(nblocks(nc, 256)), dim3(256), 0, s, raw, nc);
+    hipLaunchKernelGGL(k_feat_clear, dim3(nblocks(nc * (RAW / 4), 256)), dim3(256), 0, s, raw, nc);
     const int64_t nb = (No + FEAT_OWNERS - 1) / FEAT_OWNERS;
     if (nb > 0)
         hipLaunchKernelGGL(k_feat_accum, dim3((unsigned)nb), dim3(256), 0, s, rec, snap, snap_out, ovol, org, fg, raw,
