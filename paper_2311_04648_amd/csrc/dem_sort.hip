@@ -1,10 +1,14 @@
 // Scan and stable LSD radix sort for gfx950 (wave64).
 //
-// Scan: tile sums, then tile scan + offset, deterministic.  A tile is 1024
-// values, four per thread loaded and stored as one 16-byte vector (a wave
-// touches 1 KiB contiguously).  With few tiles each block adds up the tile
-// sums before it itself; with many, a one-block pass scans the tile sums
-// in between.  Radix sort: 8-bit digits; per pass an
+// Scan, deterministic (integer sums): with few tiles of 1024 values (four
+// per thread loaded and stored as one 16-byte vector, so a wave touches
+// 1 KiB contiguously), tile sums, then a tile scan where each block adds up
+// the tile sums before it.  With many, one pass over tiles of 16384 values
+// with decoupled look-back (Merrill and Garland's single-pass scan): each
+// block takes its tile from a ticket counter, so every tile before it
+// belongs to a block that has already started, publishes its tile sum,
+// adds up the published sums and prefixes of the tiles before it, and
+// publishes its own prefix.  Radix sort: 8-bit digits; per pass an
 // up-sweep histogram per 2048-key tile (LDS atomics), a digit-major scan of
 // the histograms, and a down-sweep that ranks keys stably inside the tile
 // with wave64 ballots (match-by-digit from 8 ballots, popcount of the lower
@@ -19,7 +23,9 @@ constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 4;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
 constexpr int64_t SCAN_DIRECT_TILES = 2048;   // up to this many tiles: no separate pass over tile sums
-constexpr int SPINE_THREADS = 1024;
+// single-pass scan: tiles of LB_SUB sub-tiles of SCAN_TILE values
+constexpr int LB_SUB = 16;
+constexpr int64_t LB_TILE = (int64_t)LB_SUB * SCAN_TILE;
 
 constexpr int RADIX_THREADS = 256;
 constexpr int RADIX_ITEMS = 8;
@@ -125,74 +131,41 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_reduce(ScanJob j0, ScanJo
     if (threadIdx.x == 0) j.partials[blockIdx.x] = tot;
 }
 
-// One block per job: partials[0..nb) <- their exclusive prefix sums.  The
-// tile sums are taken in chunks of SPINE_THREADS * 4 consecutive values
-// (thread t holds values 4t .. 4t + 3 of the chunk, so a wave's loads are
-// contiguous): a block scan of each chunk plus the carry of the chunks
-// before it.
-__global__ void __launch_bounds__(SPINE_THREADS) k_scan_spine(ScanJob j0, ScanJob j1, int64_t nb)
+// The total of a job: out[n], its copy, and the optional capacity check.
+__device__ inline void scan_total(const ScanJob &j, int64_t n, uint32_t total)
 {
-    __shared__ uint32_t wsum[SPINE_THREADS / 64];
-    uint32_t *partials = blockIdx.y == 0 ? j0.partials : j1.partials;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    constexpr int64_t CHUNK = (int64_t)SPINE_THREADS * 4;
-    uint32_t carry = 0;
-    for (int64_t c0 = 0; c0 < nb; c0 += CHUNK) {
-        const int64_t i0 = c0 + 4 * (int64_t)threadIdx.x;
-        uint32_t v[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = i0 + k < nb ? partials[i0 + k] : 0u;
-        const uint32_t s = (v[0] + v[1]) + (v[2] + v[3]);
-        uint32_t inc = s;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t u = __shfl_up(inc, d, 64);
-            if (lane >= d) inc += u;
+    j.out[n] = total;
+    if (j.out2) j.out2[n] = total;
+    if (j.ctr) {
+        j.ctr->n_contacts[j.buf] = total;
+        if ((int64_t)total > j.cap) {
+            j.ctr->overflow[j.buf] = 1u;
+            atomicMax(&j.ctr->required, total);
+        } else {
+            j.ctr->overflow[j.buf] = 0u;
         }
-        if (lane == 63) wsum[wid] = inc;
-        __syncthreads();
-        uint32_t off = 0, tot = 0;
-#pragma unroll
-        for (int k = 0; k < SPINE_THREADS / 64; ++k) {
-            const uint32_t w = wsum[k];
-            off += k < wid ? w : 0u;
-            tot += w;
-        }
-        uint32_t run = carry + off + (inc - s);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (i0 + k < nb) partials[i0 + k] = run;
-            run += v[k];
-        }
-        carry += tot;
-        __syncthreads();   // (wsum is rewritten by the next chunk)
     }
 }
 
-// Tile scan + offset.  The tile is loaded first; its offset is either the
-// sum of the tile sums before it (few tiles: strided over the threads, then
-// a block reduction; integer sums are exact in any order) or, after the
-// spine pass, partials[blockIdx.x].  Also writes out[n] = total, the
-// optional copy, and the optional capacity check of the total.
-__global__ void __launch_bounds__(SCAN_THREADS) k_scan_down(ScanJob j0, ScanJob j1, int64_t n, int64_t nb,
-                                                            int spine)
+// Tile scan + offset (few tiles).  The tile is loaded first; its offset is
+// the sum of the tile sums before it (strided over the threads, then a
+// block reduction; integer sums are exact in any order).  Also writes
+// out[n] = total, the optional copy, and the optional capacity check of
+// the total.
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_down(ScanJob j0, ScanJob j1, int64_t n, int64_t nb)
 {
     __shared__ uint32_t red[SCAN_THREADS / 64];
     const ScanJob &j = blockIdx.y == 0 ? j0 : j1;
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + 4 * (int64_t)threadIdx.x;
     const uint4 v = load4(j.in, base, n);
     uint32_t pre = 0;
-    if (spine) {
-        pre = j.partials[blockIdx.x];
-    } else {
-        for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += SCAN_THREADS) pre += j.partials[b];
-        for (int d = 32; d > 0; d >>= 1) pre += __shfl_xor(pre, d, 64);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = pre;
-        __syncthreads();
-        pre = 0;
+    for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += SCAN_THREADS) pre += j.partials[b];
+    for (int d = 32; d > 0; d >>= 1) pre += __shfl_xor(pre, d, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = pre;
+    __syncthreads();
+    pre = 0;
 #pragma unroll
-        for (int k = 0; k < SCAN_THREADS / 64; ++k) pre += red[k];
-    }
+    for (int k = 0; k < SCAN_THREADS / 64; ++k) pre += red[k];
     const uint32_t s = (v.x + v.y) + (v.z + v.w);
     uint32_t tot;
     const uint32_t ex = block_excl_scan(s, &tot) + pre;
@@ -203,21 +176,120 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_scan_down(ScanJob j0, ScanJob 
     o.w = o.z + v.z;
     store4(j.out, base, n, o);
     if (j.out2) store4(j.out2, base, n, o);
-    if (blockIdx.x == nb - 1 && threadIdx.x == SCAN_THREADS - 1) {
-        // the last thread of the last tile (values past n read as 0)
-        const uint32_t total = ex + s;
-        j.out[n] = total;
-        if (j.out2) j.out2[n] = total;
-        if (j.ctr) {
-            j.ctr->n_contacts[j.buf] = total;
-            if ((int64_t)total > j.cap) {
-                j.ctr->overflow[j.buf] = 1u;
-                atomicMax(&j.ctr->required, total);
-            } else {
-                j.ctr->overflow[j.buf] = 0u;
-            }
-        }
+    // the last thread of the last tile (values past n read as 0)
+    if (blockIdx.x == nb - 1 && threadIdx.x == SCAN_THREADS - 1) scan_total(j, n, ex + s);
+}
+
+// Single-pass scan state in a job's partials: word 0 the ticket counter,
+// then (from the next 8-byte boundary) one status word per tile: the flag
+// in the high half (0 nothing yet, LB_AGG the tile's own sum, LB_PREFIX the
+// sum of every value up to the tile's end), the sum in the low half.  The
+// flag and the sum travel in one 64-bit word, so a reader that sees the
+// flag sees its sum.
+constexpr unsigned long long LB_AGG = 1ull << 32;
+constexpr unsigned long long LB_PREFIX = 2ull << 32;
+
+__device__ inline unsigned long long *lb_status(uint32_t *partials)
+{
+    return reinterpret_cast<unsigned long long *>(partials + 2 - (reinterpret_cast<uintptr_t>(partials) >> 2 & 1u));
+}
+
+// Clears the ticket and the tile statuses of each job before the pass.
+__global__ void __launch_bounds__(256) k_scan_lb_init(ScanJob j0, ScanJob j1, int64_t nb)
+{
+    const ScanJob &j = blockIdx.y == 0 ? j0 : j1;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) j.partials[0] = 0u;
+    if (i < nb) lb_status(j.partials)[i] = 0ull;
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_lookback(ScanJob j0, ScanJob j1, int64_t n, int64_t nb)
+{
+    __shared__ uint32_t wsum[LB_SUB][SCAN_THREADS / 64];
+    __shared__ uint32_t s_tile, s_excl;
+    const ScanJob &j = blockIdx.y == 0 ? j0 : j1;
+    unsigned long long *st = lb_status(j.partials);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_tile = atomicAdd(&j.partials[0], 1u);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t base = tile * LB_TILE + 4 * (int64_t)threadIdx.x;
+    // sub-tile k: thread t holds its values 4t .. 4t + 3
+    uint4 v[LB_SUB];
+    uint32_t sk[LB_SUB], inc[LB_SUB];
+#pragma unroll
+    for (int k = 0; k < LB_SUB; ++k) v[k] = load4(j.in, base + (int64_t)k * SCAN_TILE, n);
+#pragma unroll
+    for (int k = 0; k < LB_SUB; ++k) {
+        sk[k] = (v[k].x + v[k].y) + (v[k].z + v[k].w);
+        inc[k] = wave_incl_scan(sk[k]);
+        if (lane == 63) wsum[k][wid] = inc[k];
     }
+    __syncthreads();
+    // per sub-tile: the offset of this wave and the sub-tile's sum
+    uint32_t off[LB_SUB], agg = 0;
+#pragma unroll
+    for (int k = 0; k < LB_SUB; ++k) {
+        uint32_t o = 0, t = 0;
+#pragma unroll
+        for (int w = 0; w < SCAN_THREADS / 64; ++w) {
+            const uint32_t x = wsum[k][w];
+            o += w < wid ? x : 0u;
+            t += x;
+        }
+        off[k] = agg + o;
+        agg += t;
+    }
+    if (wid == 0) {
+        // publish the tile's sum, then (tiles after the first) add up what
+        // the tiles before it published, 64 at a time from the nearest one,
+        // down to the nearest that holds a prefix
+        if (lane == 0)
+            __hip_atomic_store(&st[tile], (tile == 0 ? LB_PREFIX : LB_AGG) | agg, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t excl = 0;
+        if (tile > 0) {
+            int64_t top = tile - 1;
+            while (true) {
+                const int64_t q = top - lane;
+                const unsigned long long w =
+                    q >= 0 ? __hip_atomic_load(&st[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : LB_PREFIX;
+                const unsigned long long fl = w & ~0xffffffffull;
+                const uint64_t pm = __ballot(fl == LB_PREFIX);
+                const uint64_t zm = __ballot(fl == 0ull);
+                // lanes up to the nearest prefix are needed
+                const int p = pm ? __builtin_ctzll(pm) : 64;
+                const uint64_t need = p >= 63 ? ~0ull : ((1ull << (p + 1)) - 1ull);
+                if (zm & need) {
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                uint32_t x = lane <= p ? (uint32_t)w : 0u;
+                for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d, 64);
+                excl += x;
+                if (p < 64) break;
+                top -= 64;
+            }
+            if (lane == 0)
+                __hip_atomic_store(&st[tile], LB_PREFIX | (uint32_t)(excl + agg), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (lane == 0) s_excl = excl;
+    }
+    __syncthreads();
+    const uint32_t excl = s_excl;
+#pragma unroll
+    for (int k = 0; k < LB_SUB; ++k) {
+        uint4 o;
+        o.x = excl + off[k] + (inc[k] - sk[k]);
+        o.y = o.x + v[k].x;
+        o.z = o.y + v[k].y;
+        o.w = o.z + v[k].z;
+        store4(j.out, base + (int64_t)k * SCAN_TILE, n, o);
+        if (j.out2) store4(j.out2, base + (int64_t)k * SCAN_TILE, n, o);
+    }
+    // (values past n read as 0)
+    if (tile == nb - 1 && threadIdx.x == 0) scan_total(j, n, excl + agg);
 }
 
 __global__ void __launch_bounds__(RADIX_THREADS) k_radix_up(const uint32_t *keys, int64_t n, int shift,
@@ -295,7 +367,9 @@ inline unsigned grid_for(int64_t n, int threads, int64_t cap = 1 << 16)
 
 int64_t scan_tmp_elems(int64_t n)
 {
-    return (n + SCAN_TILE - 1) / SCAN_TILE + 2;
+    // tile sums of the few-tile pass; the single-pass state (ticket, an
+    // alignment word, two words per 16384-value tile) fits in the same room
+    return (n + SCAN_TILE - 1) / SCAN_TILE + 8;
 }
 
 int64_t radix_hist_elems(int64_t n)
@@ -335,11 +409,17 @@ static void scan_jobs(const ScanJob &j0, const ScanJob &j1, int njobs, int64_t n
         }
         return;
     }
-    const dim3 grid((unsigned)nb, (unsigned)njobs);
-    hipLaunchKernelGGL(k_scan_reduce, grid, dim3(SCAN_THREADS), 0, s, j0, j1, n);
-    const int spine = nb > SCAN_DIRECT_TILES ? 1 : 0;
-    if (spine) hipLaunchKernelGGL(k_scan_spine, dim3(1, (unsigned)njobs), dim3(SPINE_THREADS), 0, s, j0, j1, nb);
-    hipLaunchKernelGGL(k_scan_down, grid, dim3(SCAN_THREADS), 0, s, j0, j1, n, nb, spine);
+    if (nb <= SCAN_DIRECT_TILES) {
+        const dim3 grid((unsigned)nb, (unsigned)njobs);
+        hipLaunchKernelGGL(k_scan_reduce, grid, dim3(SCAN_THREADS), 0, s, j0, j1, n);
+        hipLaunchKernelGGL(k_scan_down, grid, dim3(SCAN_THREADS), 0, s, j0, j1, n, nb);
+        return;
+    }
+    const int64_t nl = (n + LB_TILE - 1) / LB_TILE;
+    hipLaunchKernelGGL(k_scan_lb_init, dim3((unsigned)((nl + 255) / 256), (unsigned)njobs), dim3(256), 0, s, j0, j1,
+                       nl);
+    hipLaunchKernelGGL(k_scan_lookback, dim3((unsigned)nl, (unsigned)njobs), dim3(SCAN_THREADS), 0, s, j0, j1, n,
+                       nl);
 }
 
 void scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *partials,

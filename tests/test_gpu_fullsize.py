@@ -227,3 +227,23 @@ def test_config4_bench_window_learned_equals_every_step(dem):
         c.close()
     for k in ("X", "V", "W", "q"):
         np.testing.assert_array_equal(outs[0][k], outs[1][k])
+
+
+def test_large_binning_is_the_stable_sort(dem):
+    """8 M spheres: the bin counts and the per-sphere counts are scanned in
+    one pass with look-back over thousands of tiles; the one-pass bin sort
+    must still give numpy's stable argsort of the bin keys, and the set's
+    rows must be those the detection counted."""
+    s = W.config3(seed=7)
+    ctx = dem.DemContext(s, mode="every", bin_sort=0, capacity=8 * s.n_spheres)
+    ctx.set_state()
+    keys, ids = ctx.bin()
+    assert s.n_spheres > 4 * 1024 * 1024
+    assert np.array_equal(np.sort(ids), np.arange(s.n_spheres, dtype=np.uint32))
+    order = np.argsort(keys[np.argsort(ids)], kind="stable")
+    np.testing.assert_array_equal(ids, order.astype(np.uint32))
+    assert np.all(np.diff(keys.astype(np.int64)) >= 0)
+    n = ctx.detect_contacts(s.margin)
+    k, _ = ctx.get_contacts()
+    assert k.size == n
+    assert np.all(k[1:] > k[:-1])
