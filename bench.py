@@ -74,7 +74,7 @@ def parse():
 
 
 def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, rolling=False, n_clump=None, n_tri=0,
-                      n_dormant=0, n_dormant_clump=0, n_dormant_sph=0):
+                      n_dormant=0, n_dormant_clump=0, n_dormant_sph=0, pair_keys=False):
     """Bytes one launch of a stage must move at minimum (unique data);
     `active` = spheres that appear in at least one contact:
     k_force: per sphere its row offset (4); per active sphere its record
@@ -88,7 +88,9 @@ def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, roll
       per contact the partner id (4), the new history written (12, 16 with
       contact age) and the B-list entry with its source sphere (8); the old
       history is read only for pairs that touch and is not counted (so the
-      figure is a lower bound);
+      figure is a lower bound); with pair skipping (single spheres, dense
+      sets) also each pair's gap key (4; it is rewritten only for the pairs
+      the step evaluates, not counted);
       with meshes, each facet's vertices and mesh index (80).  An owner of a
       fixed family without contacts reads its flag only (1).
     k_fold_integrate: per owner the record read + write (96) and the inverse
@@ -114,7 +116,7 @@ def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, roll
         nc = (No if n_clump is None else n_clump) if clumps else 0
         nc -= n_dormant_clump if clumps else 0
         return ((No - n_dormant) * (113 if clumps else 101) + n_dormant + nc * 64 + active * 28
-                + C * (28 if rolling else 24) + n_tri * 80)
+                + C * ((28 if rolling else 24) + (4 if pair_keys else 0)) + n_tri * 80)
     if stage == "k_fold_integrate":
         return No * (116 if clumps else 100) + Ns * 8 + active * 24 + C * 28
     if stage == "detect":
@@ -474,9 +476,13 @@ def main():
                   "k_step_listed": listed_bytes(r["active_owners"], n_clump_share(sysm, r), r["active"], C,
                                                 rolling)}
     else:
+        # (pair skipping: single spheres without fixed families, dense sets)
+        keys_on = (Ns == No and n_dormant == 0 and not bool(np.any(np.asarray(sysm.fam_fixed) > 0))
+                   and args.dyn_path != 1 and 2 * C >= Ns)
         algo_k = {names[dom]: algorithmic_bytes(names[dom] if names[dom] != "k_force" or args.dyn_path == 1
                                                 else "k_step_fused", Ns, No, C, r["active"],
-                                                r["info"]["nbins"], passes, **kw)}
+                                                r["info"]["nbins"], passes,
+                                                pair_keys=keys_on and names[dom] == "k_step_fused", **kw)}
     algo = algo_k[names[dom]]
     timed = int(cnt[dom]) > 0
     achieved = algo / (avg_ms * 1e-3) / 1e9 if timed else None
@@ -531,6 +537,11 @@ def main():
     # binning step rides on the step kernel, which reads the state anyway
     fused_front = (Ns == No and not bool(np.any(np.asarray(sysm.fam_fixed) > 0)) and args.dyn_path != 1)
 
+    def skip_keys(C):
+        # pair skipping runs in the staged step of single-sphere systems
+        # without fixed families: dense sets (one contact per two spheres)
+        return fused_front and 2 * C >= Ns
+
     def path_bytes_per_step(rr, mode):
         # algorithmic bytes of one step of the whole path: the dynamics
         # kernel(s) every step, detection once per detection, and the remap
@@ -540,7 +551,7 @@ def main():
         s2 = rr["stats"]
         Cm, act = s2["mean_contacts"], rr["active"]
         if args.dyn_path != 1:
-            dyn_b = algorithmic_bytes("k_step_fused", Ns, No, Cm, act, 0, passes, **kw)
+            dyn_b = algorithmic_bytes("k_step_fused", Ns, No, Cm, act, 0, passes, pair_keys=skip_keys(Cm), **kw)
         else:
             dyn_b = (algorithmic_bytes("k_force", Ns, No, Cm, act, 0, passes)
                      + algorithmic_bytes("k_fold_integrate", Ns, No, Cm, act, 0, passes, clumps=Ns != No))

@@ -182,7 +182,18 @@ typedef struct {
                                kernel with its history writes always (2) or never (3)
                                gathered per wave in LDS, which 0 decides from the last
                                contact count read back (at least one per two spheres:
-                               gathered); all give the same bits */
+                               gathered); 4 in clump systems without fixed families, a
+                               streaming kernel over every owner plus a kernel over the
+                               owners with contacts (0 picks it for sparse sets); all
+                               give the same bits */
+    int32_t no_pair_skip;   /* 0 (default): in single-sphere systems without fixed
+                               families, a dense set's pairs proven apart are skipped by
+                               the fused step (each pair keeps a lower bound of its gap,
+                               the step a bound of how far any two surfaces can have
+                               closed in since; such a pair cannot touch, and the step
+                               gives it exactly what evaluating it would: no force, zero
+                               history); nonzero: every pair is evaluated every step.
+                               Both give the same bits. */
 } dem_params;
 
 /* Statistics of a dem_step call (Sec. 2.1, thread collaboration stats). */

@@ -36,7 +36,7 @@ class Params(C.Structure):
                 ("cd_mode", C.c_int32), ("cd_interval", C.c_int32), ("cd_latency", C.c_int32),
                 ("judge", C.c_int32), ("repair", C.c_int32), ("cd_interval_max", C.c_int32),
                 ("timing", C.c_int32), ("mlp_safety", C.c_double), ("bin_sort", C.c_int32),
-                ("dyn_path", C.c_int32)]
+                ("dyn_path", C.c_int32), ("no_pair_skip", C.c_int32)]
 
 
 class Materials(C.Structure):
@@ -162,7 +162,7 @@ class DemContext:
 
     def __init__(self, system, mode="every", k=10, lam=5, judge=False, repair=True, capacity=None,
                  margin=None, v_error_out=0.0, k_max=None, device="cuda:0", timing=False, mlp_safety=1.0,
-                 bin_sort=0, dyn_path=0):
+                 bin_sort=0, dyn_path=0, pair_skip=True):
         torch = _torch()
         self.torch = torch
         self.device = torch.device(device)
@@ -194,6 +194,7 @@ class DemContext:
         P.mlp_safety = float(mlp_safety)
         P.bin_sort = int(bin_sort)
         P.dyn_path = int(dyn_path)
+        P.no_pair_skip = 0 if pair_skip else 1
         self.params = P
         Mt = Materials(int(np.asarray(s.mat_E).shape[0]), keep(s.mat_E, np.float64), keep(s.mat_nu, np.float64),
                        keep(s.mat_cor, np.float64), keep(s.mat_mu, np.float64), keep(s.mat_crr, np.float64))

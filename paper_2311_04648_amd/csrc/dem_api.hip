@@ -129,6 +129,11 @@ struct dem_ctx {
     CdWork cdK{}, cdD{};
     DevCounters *ctr = nullptr;
     DevCounters *h_ctr = nullptr;
+    // pair skipping (single-sphere systems): the speed slots and reaches of
+    // the chains, and a count of adoptions (a chain lives on one adopted set)
+    float *d_gvs = nullptr;
+    double *d_gD = nullptr;
+    uint64_t adopt_epoch = 0;
     // learned interval
     float *d_blkmax = nullptr;
     float *d_mlp = nullptr;
@@ -307,7 +312,10 @@ void carve(Carver &c, dem_ctx *ctx, int64_t cap)
         a.oany = c.take<uint8_t>(No);
         a.olist = c.take<uint32_t>(No);
         a.otile = c.take<uint32_t>(owner_list_tiles(No) + 1);
+        a.gk = ctx->has_clumps ? nullptr : c.take<float>(cap);
     }
+    ctx->d_gvs = c.take<float>(3 * 64 * 16);
+    ctx->d_gD = c.take<double>(2);
     ctx->sb.aF = c.take<float>(3 * Ns);
     ctx->sb.aT = c.take<float>(3 * Ns);
     ctx->sb.bF = c.take<float>(3 * cap);
@@ -478,7 +486,21 @@ DynArgs dyn_args(const dem_ctx *ctx, int64_t step)
     // clump systems without fixed families: a sparse set runs as the
     // streaming kernel plus the kernel over the owners with contacts
     a.split = owner_list_wanted(ctx) && (ctx->P.dyn_path == 4 || (ctx->P.dyn_path == 0 && !a.dense_rows)) ? 1 : 0;
+    // pair skipping: off unless dem_step opens or continues a chain
+    a.gk = ctx->acs[ctx->cur].gk;
+    a.gap = 0;
+    a.gvs = ctx->d_gvs;
+    a.gD = ctx->d_gD;
+    a.vgeom = std::max(ctx->vmesh, ctx->vwall);
     return a;
+}
+
+// Single-sphere systems without fixed families skip the pairs of a dense
+// set that are proven apart (the step kernels' staged variant)
+static bool pair_skip_allowed(const dem_ctx *ctx, const DynArgs &a)
+{
+    return !ctx->P.no_pair_skip && !ctx->has_clumps && !ctx->has_fixed && a.dense_rows && a.gk &&
+           ctx->P.dyn_path != 1;
 }
 
 inline hipStream_t S(dem_stream s) { return reinterpret_cast<hipStream_t>(s); }
@@ -1029,6 +1051,8 @@ dem_status dem_bind(dem_ctx *ctx, void *device_workspace, int64_t bytes, int64_t
     HIPCHK(hipMemcpy(ctx->d_mat, ctx->mat.data(), sizeof(MatPair) * ctx->mat.size(), hipMemcpyHostToDevice));
     DevCounters z{};
     HIPCHK(hipMemcpy(ctx->ctr, &z, sizeof(DevCounters), hipMemcpyHostToDevice));
+    launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->d_gvs), 3 * 64 * 16, 0u, nullptr);
+    launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->d_gD), 4, 0u, nullptr);
     if (ctx->mlp_set)
         HIPCHK(hipMemcpy(ctx->d_mlp, ctx->mlp.data(), sizeof(float) * DEM_MLP_NPARAM, hipMemcpyHostToDevice));
     clear_set(ctx, 0, nullptr);
@@ -1201,6 +1225,7 @@ static dem_status adopt(dem_ctx *ctx, int target, hipStream_t s, bool defer = fa
     }
     HIPCHK(hipGetLastError());
     ctx->cur = target;
+    ++ctx->adopt_epoch;
     return DEM_OK;
 }
 
@@ -1675,6 +1700,10 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
         cs0 = ctx->h_ctr->contact_steps;
     }
     if (ctx->n_wo == 0) ctx->interval_sum = 0.0;
+    // the chain of pair-skipping steps: its set (by adoption count) and the
+    // step that may continue it (every call starts a new one)
+    uint64_t gap_epoch = 0;
+    int64_t gap_next = -1;
     for (int64_t t = 0; t < n_steps; ++t) {
         const int64_t n = ctx->step;
         {
@@ -1834,6 +1863,7 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
             // each, every `timing`-th step, each pair followed by an empty
             // kernel bracketed the same way (the markers' own overhead)
             run_close(ctx, dyn);
+            gap_next = -1;
             SplitTiming tm{};
             dem_ctx::TimedPair *t1 = stage_slot(ctx, 1), *t0 = t1 ? stage_slot(ctx, 0) : nullptr;
             if (t1 && t0) tm = SplitTiming{t1->a, t1->b, t0->a, t0->b};
@@ -1867,6 +1897,10 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
                     ctx->run_due = false;
                 }
             }
+            const bool gap = pair_skip_allowed(ctx, a);
+            if (gap) a.gap = (gap_next == n && gap_epoch == ctx->adopt_epoch && !a.rm_start) ? 2 : 1;
+            gap_next = gap ? n + 1 : -1;
+            gap_epoch = ctx->adopt_epoch;
             if (!launch_step_fused(a, ctx->rec_alt, ctx->q_alt, ctx->acs[ctx->cur], ctx->cap, ctx->ctr, dyn)) {
                 // (a work order's binning on the step right after an
                 // adoption: issue_work_order never sets one up)
@@ -1885,6 +1919,7 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
             std::swap(ctx->q, ctx->q_alt);
             swap_hist(ctx->acs[ctx->cur]);
         } else {
+            gap_next = -1;
             auto *tf = stage_begin(ctx, 0, dyn);
             launch_force(a, ctx->acs[ctx->cur], ctx->sb, ctx->ctr, dyn);
             stage_end(tf, dyn);

@@ -142,6 +142,7 @@ struct ContactOut {
     float3 armB;     // contact point minus B's owner centre (wall: wall point; facet: mesh reference point)
     float4 h;        // history after the step (xi, contact age)
     bool touching;
+    double gap;      // (GAPW) the pair's gap, exact in FP64; negative when touching
 };
 
 // Duration of a contact's first impact, during which rolling resistance is
@@ -190,7 +191,8 @@ __device__ __forceinline__ float3 tangential_force(const MatPair &mq, float sqrt
 // its own sphere as B); otherwise B is loaded from jp.  SINGLES: every owner
 // is one sphere, so B's owner record is at jp and is loaded with its sphere
 // record rather than after it.
-template <bool FACETS, bool KNOWN_B = false, bool SINGLES = false>
+// GAPW: also report the pair's gap (out.gap) when it does not touch.
+template <bool FACETS, bool KNOWN_B = false, bool SINGLES = false, bool GAPW = false>
 __device__ __forceinline__ void contact_eval(const DynArgs &a, const SphRec &sA, const OwnerKin &kA,
                                              const double *xA, uint32_t jp, const HistIn &hin, ContactOut &out,
                                              const SphRec *sBk = nullptr, const OwnerKin *kBk = nullptr,
@@ -224,6 +226,7 @@ __device__ __forceinline__ void contact_eval(const DynArgs &a, const SphRec &sA,
         double radB = (double)sB.rad;
         double T = radA + radB;
         touching = d2 < T * T;
+        if (GAPW) out.gap = touching ? -1.0 : sqrt(d2) - T;
         if (touching) {
             double d = sqrt(d2);
             nrm[0] = dx / d;
@@ -249,6 +252,7 @@ __device__ __forceinline__ void contact_eval(const DynArgs &a, const SphRec &sA,
         facet_world(t, P, w);
         const double d2 = facet_dist2(w, xA, q);
         touching = d2 < radA * radA && d2 > 0.0;
+        if (GAPW) out.gap = touching || !(d2 > 0.0) ? -1.0 : sqrt(d2) - radA;
         if (touching) {
             const double d = sqrt(d2);
             nrm[0] = (xA[0] - q[0]) / d;
@@ -272,6 +276,7 @@ __device__ __forceinline__ void contact_eval(const DynArgs &a, const SphRec &sA,
         if (wd.type == 0) {
             double sd = (rx * wd.geom[3] + ry * wd.geom[4]) + rz * wd.geom[5];
             touching = sd < radA;
+            if (GAPW) out.gap = touching ? -1.0 : sd - radA;
             if (touching) {
                 nrm[0] = wd.geom[3];
                 nrm[1] = wd.geom[4];
@@ -286,6 +291,9 @@ __device__ __forceinline__ void contact_eval(const DynArgs &a, const SphRec &sA,
             double d2 = (px * px + py * py) + pz * pz;
             double T = wd.geom[6] + radA;
             touching = (ax <= hl && ax >= -hl) && d2 < T * T && d2 > 0.0;
+            // (apart: at least as far as the farther of the two bounds of
+            // the touching region, the radius and the axial extent)
+            if (GAPW) out.gap = touching ? -1.0 : fmax(sqrt(d2) - T, fabs(ax) - hl);
             if (touching) {
                 double d = sqrt(d2);
                 nrm[0] = px / d;
@@ -517,19 +525,22 @@ __device__ __forceinline__ float advance(const DynArgs &a, OwnerRec &r, const fl
 }
 
 // Block-wide max of |v|^2 written to the block's slot (no atomics); the
-// maximum over blocks is reduced only when it is read.
-__device__ __forceinline__ void block_max_v2(float v2, float *slot)
+// maximum over blocks is reduced only when it is read.  Returns it in
+// thread 0.
+__device__ __forceinline__ float block_max_v2(float v2, float *slot)
 {
     __shared__ float wmax[TPB / 64];
     if (!(v2 == v2)) v2 = 3.0e38f;
     for (int d = 32; d > 0; d >>= 1) v2 = fmaxf(v2, __shfl_xor(v2, d, 64));
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v2;
     __syncthreads();
+    float m = 0.0f;
     if (threadIdx.x == 0) {
-        float m = wmax[0];
+        m = wmax[0];
         for (int k = 1; k < TPB / 64; ++k) m = fmaxf(m, wmax[k]);
         *slot = m;
     }
+    return m;
 }
 
 // SINGLES: every owner is one sphere (sphere index == owner index), so the
@@ -638,14 +649,63 @@ struct OwnerStep {
     bool advance;    // the owner is integrated (not in a fixed family)
 };
 
+// Pairs proven apart (see DynArgs::gap).  Per step, room for the rounding
+// of two re-encoded positions (2^-38 m per axis each) and of the facet and
+// wall poses; per pair, room for the rounding of its FP64 gap and of the
+// touching test.  Both are far above those roundings and far below any gap
+// worth skipping.
+constexpr double GAP_STEP_SLACK = 1e-10;
+constexpr double GAP_PAIR_SLACK = 1e-9;
+constexpr int GAP_SLOTS = 64;    // speed slots per step
+constexpr int GAP_STRIDE = 16;   // floats from one slot to the next (64 B)
+
+__device__ inline float *gap_slot(const DynArgs &a, int64_t step, uint32_t k)
+{
+    return a.gvs + ((size_t)(step % 3) * GAP_SLOTS + (k & (GAP_SLOTS - 1))) * GAP_STRIDE;
+}
+
+// The reach D of this step (every lane of the wave calls it; all waves of
+// the launch get the same value): 0 on the first step of a chain, else the
+// previous step's reach plus how far any two surfaces can have closed in
+// during that step: h times twice the largest sphere speed it integrated
+// (its blocks' maxima, in the speed slots) plus the fastest wall or mesh
+// point, plus the slack.
+__device__ inline double gap_reach(const DynArgs &a)
+{
+    if (a.gap != 2) return 0.0;
+    const uint32_t lane = threadIdx.x & 63u;
+    float m = *gap_slot(a, a.step + 2, lane);
+    for (int d = 32; d > 0; d >>= 1) m = fmaxf(m, __shfl_xor(m, d, 64));
+    // (the maxima are FP32 squares: a relative allowance of 1e-6 on the speed)
+    const double v = sqrt((double)m) * (1.0 + 1e-6);
+    return a.gD[(a.step + 1) & 1] + a.h * (2.0 * v + a.vgeom) + GAP_STEP_SLACK;
+}
+
+// The key of a pair evaluated at reach D with gap g: (g - slack) + D
+// rounded down to FP32; a pair that touches or nearly does gets a key no
+// reach can pass.
+__device__ inline float gap_key(double g, double D)
+{
+    if (!(g > GAP_PAIR_SLACK)) return -3.0e38f;
+    const double k = (g - GAP_PAIR_SLACK) + D;
+    float f = (float)k;
+    if ((double)f > k) f = __uint_as_float(__float_as_uint(f) - 1u);   // (k > 0: one ulp down)
+    return f;
+}
+
 // The contact part of one owner's step (see k_step_fused): the sums F, T of
 // the forces and torques on it, its rows' new history put through ho.
-template <bool SINGLES, bool FACETS, bool FIXED, bool AHEAD, bool REMAP>
+// GAP (single spheres without fixed families, dense sets): items are
+// skipped by the pairs' keys and the A rows' keys written (DynArgs::gap; Dn
+// is the step's reach), and an item's indices are loaded two items ahead,
+// its key one item ahead.
+template <bool SINGLES, bool FACETS, bool FIXED, bool AHEAD, bool REMAP, bool GAP = false>
 __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, const uint32_t *start,
     const uint32_t *jarr, const uint32_t *bstart, const uint32_t *bidx, const uint32_t *bsrc, const uint8_t *oany,
     const uint8_t fl_fixed, const float *hx, const float *hy, const float *hz, const float *hw, const HistOut &ho,
-    OwnerStep &st, const OwnerRec *pre = nullptr)
+    OwnerStep &st, const OwnerRec *pre = nullptr, const double Dn = 0.0)
 {
+    static_assert(!GAP || (SINGLES && !FIXED), "pair skipping is for single spheres without fixed families");
     st.advance = false;
     // The owner's flag byte, written with the set (bit 0: the owner has a
     // contact in it; bit 1: the owner is in a fixed family), read by the
@@ -717,46 +777,47 @@ __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, 
                 }
                 return h;
             };
-            uint32_t nj = 0, nc = 0;
-            auto fetch = [&](uint32_t t) {
+            auto fetch = [&](uint32_t t, uint32_t &cc, uint32_t &jj) {
                 if (t < na) {
-                    nc = c0 + t;
-                    nj = jarr[nc];
+                    cc = c0 + t;
+                    jj = jarr[cc];
                 } else {
                     const uint32_t b = b0 + (t - na);
-                    nc = bidx[b];
-                    nj = bsrc[b];
+                    cc = bidx[b];
+                    jj = bsrc[b];
                 }
             };
-            if (AHEAD && nall > 0) fetch(0);
-            for (uint32_t t = 0; t < nall; ++t) {
+            // item t (contact c, partner or source jt), its sums; skipped:
+            // what a pair that does not touch gives
+            auto item = [&](uint32_t t, uint32_t c, uint32_t jt, bool skip) {
                 const bool aside = t < na;
-                if (!AHEAD) fetch(t);
-                const uint32_t c = nc, jt = nj;
-                if (AHEAD && t + 1 < nall) fetch(t + 1);
                 ContactOut co;
-                if constexpr (SINGLES) {
-                    if (aside) {
-                        contact_eval<FACETS, false, true>(a, sS, kS, xS, jt, hin(c, s, jt), co);
+                co.touching = false;
+                co.h = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (!skip) {
+                    if constexpr (SINGLES) {
+                        if (aside) {
+                            contact_eval<FACETS, false, true, GAP>(a, sS, kS, xS, jt, hin(c, s, jt), co);
+                            if (GAP && a.gap != 0) a.gk[c] = gap_key(co.gap, Dn);
+                        } else {
+                            const uint32_t iA = jt;
+                            // (owner index == sphere index: both loads at once)
+                            const SphRec sA = load_sph(a.sph + iA);
+                            const OwnerRec rA = load_rec(a.rec + iA);
+                            OwnerKin kA;
+                            double xA[3];
+                            owner_kin(rA, sA, a.aux, a.q, a.tpos, a.org, kA, xA);
+                            contact_eval<false, true>(a, sA, kA, xA, s, hin(c, iA, s), co, &sS, &kS, xS);
+                        }
                     } else {
-                        const uint32_t iA = jt;
-                        // (owner index == sphere index: both loads at once)
+                        const uint32_t iA = aside ? s : jt, jp = aside ? jt : s;
                         const SphRec sA = load_sph(a.sph + iA);
-                        const OwnerRec rA = load_rec(a.rec + iA);
+                        const OwnerRec rA = load_rec(a.rec + sA.owner);
                         OwnerKin kA;
                         double xA[3];
                         owner_kin(rA, sA, a.aux, a.q, a.tpos, a.org, kA, xA);
-                        contact_eval<false, true>(a, sA, kA, xA, s, hin(c, iA, s), co,
-                                                  &sS, &kS, xS);
+                        contact_eval<FACETS>(a, sA, kA, xA, jp, hin(c, iA, jp), co);
                     }
-                } else {
-                    const uint32_t iA = aside ? s : jt, jp = aside ? jt : s;
-                    const SphRec sA = load_sph(a.sph + iA);
-                    const OwnerRec rA = load_rec(a.rec + sA.owner);
-                    OwnerKin kA;
-                    double xA[3];
-                    owner_kin(rA, sA, a.aux, a.q, a.tpos, a.org, kA, xA);
-                    contact_eval<FACETS>(a, sA, kA, xA, jp, hin(c, iA, jp), co);
                 }
                 if (aside) {
                     put_hist(ho, c, co.h, a.rolling);
@@ -776,6 +837,34 @@ __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, 
                     }
                     F = F + mF;
                     T = T + tB;
+                }
+            };
+            if constexpr (GAP) {
+                // a skipped item waits for nothing: its key was loaded an
+                // item earlier, after its indices had arrived
+                const bool skipping = a.gap == 2;
+                uint32_t c1 = 0, j1 = 0, c2 = 0, j2 = 0;
+                float k1 = -3.0e38f;
+                if (nall > 0) fetch(0, c1, j1);
+                if (nall > 1) fetch(1, c2, j2);
+                if (skipping && nall > 0) k1 = a.gk[c1];
+                for (uint32_t t = 0; t < nall; ++t) {
+                    const uint32_t c = c1, jt = j1;
+                    const float key = k1;
+                    c1 = c2;
+                    j1 = j2;
+                    if (skipping && t + 1 < nall) k1 = a.gk[c1];
+                    if (t + 2 < nall) fetch(t + 2, c2, j2);
+                    item(t, c, jt, skipping && (double)key - Dn > 0.0);
+                }
+            } else {
+                uint32_t nj = 0, nc = 0;
+                if (AHEAD && nall > 0) fetch(0, nc, nj);
+                for (uint32_t t = 0; t < nall; ++t) {
+                    if (!AHEAD) fetch(t, nc, nj);
+                    const uint32_t c = nc, jt = nj;
+                    if (AHEAD && t + 1 < nall) fetch(t + 1, nc, nj);
+                    item(t, c, jt, false);
                 }
             }
         }
@@ -903,11 +992,22 @@ __device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, u
         ho.c0 = start[sb];
         c_end = start[se];
     }
+    // pair skipping: the step's reach; the launch's first wave records it
+    // and clears the speed slots the next step fills
+    constexpr bool GAP = SINGLES && !FIXED && STAGE;
+    double Dn = 0.0;
+    if constexpr (GAP) {
+        Dn = gap_reach(a);
+        if (a.gap != 0 && ow == 0) {
+            if (lane == 0) a.gD[a.step & 1] = Dn;
+            *gap_slot(a, a.step + 1, lane) = 0.0f;
+        }
+    }
     OwnerStep st;
     st.advance = false;
     if (valid)
-        owner_forces<SINGLES, FACETS, FIXED, STAGE || FACETS || !SINGLES, REMAP>(a, o, start, jarr, bstart, bidx, bsrc, oany, 0, hx, hy, hz, hw, ho, st,
-                                                                                  SINGLES ? &rpre : nullptr);
+        owner_forces<SINGLES, FACETS, FIXED, STAGE || FACETS || !SINGLES, REMAP, GAP>(a, o, start, jarr, bstart, bidx, bsrc, oany, 0, hx, hy, hz, hw, ho, st,
+                                                                                       SINGLES ? &rpre : nullptr, Dn);
     // (st.r is still the state read, before this step's update)
     if constexpr (WO) wo_front(a, o, valid, st.r, spw);
     const uint32_t n = c_end - ho.c0 < HIST_STAGE ? c_end - ho.c0 : HIST_STAGE;
@@ -1017,7 +1117,12 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
     } else if (w0 < No) {
         v2 = step_wave<SINGLES, FACETS, FIXED, STAGE, REMAP, WO>(a, w0, lrec, lds, rec_out, q_out, start, jarr, bstart, bidx, bsrc, oany, hx, hy, hz, hw, ox, oy, oz, ow, cap, ctr);
     }
-    block_max_v2(v2, a.blkmax + lb);
+    const float bm = block_max_v2(v2, a.blkmax + lb);
+    // pair skipping: the block's maximum into one of the step's speed slots
+    // (non-negative floats order as their bits)
+    if constexpr (SINGLES && !FIXED && STAGE) {
+        if (a.gap != 0 && threadIdx.x == 0) atomicMax(reinterpret_cast<unsigned *>(gap_slot(a, a.step, lb)), __float_as_uint(bm));
+    }
 }
 
 

@@ -232,6 +232,10 @@ struct AcsBuf {
     // them in a kernel of their own); their count is otile[owner_list_tiles(No)]
     uint32_t *olist;   // [No]
     uint32_t *otile;   // [owner_list_tiles(No) + 1] per-tile offsets, then the count
+    // single-sphere systems: per contact a lower bound of the pair's gap
+    // plus the reach of the chain it was written in (DynArgs::gap); null
+    // in clump systems
+    float *gk;         // [cap]
 };
 
 // tiles of the owner-list compaction
@@ -326,6 +330,21 @@ struct DynArgs {
     int32_t split;          // clump systems without fixed families: run the step as a streaming
                             // kernel over every owner plus a kernel over the set's owners with
                             // contacts (AcsBuf::olist); the same bits as the one-kernel step
+    // Pairs provably apart (single-sphere systems without fixed families).
+    // A chain is a run of consecutive steps on one set; its reach D(n) bounds
+    // how far any two surfaces can have closed in since the chain began:
+    // D(first) = 0, D(n) = D(n-1) + h (2 v(n) + vgeom) + GAP_STEP_SLACK with
+    // v(n) the largest sphere speed the step before integrated.  Evaluating
+    // a pair, the step writes gk[c] = (its gap - GAP_PAIR_SLACK) + D(n),
+    // rounded down; while gk[c] - D(n) > 0 the pair cannot touch, and the
+    // step gives it what evaluating it would: no force, zero history.
+    // gap: 0 off, 1 the first step of a chain (every pair evaluated, keys
+    // written), 2 a later step (pairs skipped by their keys).
+    float *gk;
+    int32_t gap;
+    float *gvs;             // [3][64] speed slots (max |v|^2 bits, one per 64 B), by step mod 3
+    double *gD;             // [2] reach D by step parity
+    double vgeom;           // fastest point of any wall or mesh
 };
 
 struct StepBufs {

@@ -1,0 +1,98 @@
+"""Pair skipping in the fused step (single-sphere systems, dense sets).
+
+A pair whose key says it cannot touch is given exactly what evaluating it
+would give (no force, zero history), so runs with skipping and runs that
+evaluate every pair must end bit for bit in the same state, set and
+history: over long chains (fixed and learned intervals), on a bed swept by
+a turning mesh, and against a moving cylinder and plane walls.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dem():
+    import os
+    import paper_2311_04648_amd as d
+    if not os.path.exists(d.LIB_PATH):
+        from paper_2311_04648_amd import build
+        build.build()
+    d._torch()
+    return d
+
+
+def _run(dem, s, n, skip, **kw):
+    import torch
+    c = dem.DemContext(s, pair_skip=skip, **kw)
+    c.set_state()
+    st = c.step(n, dyn=torch.cuda.Stream(), kin=torch.cuda.Stream())
+    g = c.get_state()
+    keys, hist = c.get_contacts()
+    c.close()
+    return st, g, keys, hist
+
+
+def _same(a, b):
+    for k in ("X", "V", "W"):
+        np.testing.assert_array_equal(a[1][k], b[1][k])
+    np.testing.assert_array_equal(a[2], b[2])
+    np.testing.assert_array_equal(a[3], b[3])
+
+
+def cylinder_cloud(seed=3, n=600):
+    """A packed sphere cloud in a box with a cylinder (radius 1 cm, axis
+    along y) driven through it at 1 m/s: plane and cylinder walls, both
+    the radial and the axial bound of the cylinder's gap."""
+    rng = np.random.default_rng(seed)
+    side = int(math.ceil(n ** (1 / 3)))
+    sp = 0.0062
+    base = W.lattice((side, side, side), sp, -0.5 * (side - 1) * sp * np.ones(3), n_take=n)
+    rad = rng.uniform(0.0025, 0.003, size=n)
+    X = base + rng.uniform(-0.0003, 0.0003, size=(n, 3))
+    V = rng.normal(0.0, 0.05, size=(n, 3))
+    half = 0.5 * side * sp + 0.02
+    lo, hi = -half * np.ones(3), half * np.ones(3)
+    cyl = W.cylinder((-half + 0.012, 0.0, 0.0), (0, 1, 0), 0.01, 0.5 * half, vel=(1.0, 0.0, 0.0))
+    walls = W.concat_walls(W.box_walls(lo, hi), cyl)
+    return W.assemble(np.full(n, -1), X, W._qid(n), V, np.zeros((n, 3)), [], rad, None, walls, W.materials(),
+                      (0, 0, -9.81), 5e-6, 0.0006, lo, hi, name="cylinder_cloud")
+
+
+@pytest.mark.parametrize("mode,k", [("fixed", 10), ("fixed", 60), ("learned", 10), ("every", 1)])
+def test_mixer_bed_skipping_changes_nothing(dem, mode, k):
+    s = W.small_mixer_bed(4, n=500)
+    kw = dict(mode=mode, k=k, lam=5, dyn_path=2, k_max=200)
+    a = _run(dem, s, 1200, True, **kw)
+    b = _run(dem, s, 1200, False, **kw)
+    print(f"{mode} k={k}: {a[2].size} pairs at the end, cds {a[0]['cds']}", flush=True)
+    assert a[2].size > 0
+    _same(a, b)
+
+
+@pytest.mark.parametrize("mode", ["fixed", "learned"])
+def test_moving_cylinder_and_walls_skipping_changes_nothing(dem, mode):
+    s = cylinder_cloud()
+    kw = dict(mode=mode, k=40, lam=5, dyn_path=2, k_max=200)
+    a = _run(dem, s, 3000, True, **kw)
+    b = _run(dem, s, 3000, False, **kw)
+    ki = (a[2] >> np.uint64(32)).astype(np.int64)
+    kj = (a[2] & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    walls = np.unique(kj[kj >= s.n_spheres] - s.n_spheres)
+    print(f"{mode}: {a[2].size} pairs, wall pairs with walls {walls.tolist()}, cds {a[0]['cds']}", flush=True)
+    # the cylinder (the last wall) is in the set at the end
+    assert s.n_walls - 1 in walls.tolist()
+    _same(a, b)
+
+
+def test_skipping_equals_the_two_kernel_form(dem):
+    """The two-kernel form evaluates every pair every step."""
+    s = W.small_mixer_bed(6, n=500)
+    a = _run(dem, s, 800, True, mode="fixed", k=20, lam=5, dyn_path=0)
+    b = _run(dem, s, 800, True, mode="fixed", k=20, lam=5, dyn_path=1)
+    _same(a, b)
