@@ -126,12 +126,13 @@ def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, roll
     raise ValueError(stage)
 
 
-def stream_bytes(No, n_clump):
+def stream_bytes(No, n_turn):
     """k_step_free: per owner its contact flag (1), inertia and template (16)
-    and record read + written (96); per clump its orientation read + written
-    (64).  Owners with contacts are counted here (their records are read and
-    written, then written again by k_step_listed)."""
-    return No * 113 + n_clump * 64
+    and record read + written (96); per turning clump its orientation read +
+    written (64; a clump at rest keeps its orientation in both buffers and
+    the step touches neither).  Owners with contacts are counted here (their
+    records are read and written, then written again by k_step_listed)."""
+    return No * 113 + n_turn * 64
 
 
 def n_clump_share(sysm, rr):
@@ -191,7 +192,7 @@ def make_ctx(dem, sysm, mode, args, mlp, judge, dyn_path=None):
     return ctx
 
 
-def run_mode(dem, torch, sysm, mode, args, mlp=None, judge=False):
+def run_mode(dem, torch, sysm, mode, args, mlp=None, judge=False, turning=False):
     ctx = make_ctx(dem, sysm, mode, args, mlp, judge)
     ctx.set_state()
     dyn, kin = torch.cuda.Stream(), torch.cuda.Stream()
@@ -208,9 +209,16 @@ def run_mode(dem, torch, sysm, mode, args, mlp=None, judge=False):
     jj = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
     active = np.unique(np.concatenate([ii, jj[jj < sysm.n_spheres]])).size
     act_own = np.unique(np.asarray(sysm.sph_owner)[np.unique(np.concatenate([ii, jj[jj < sysm.n_spheres]]))]).size
+    n_turn = None
+    if turning:
+        # clumps turning at the end of the run: the streaming step reads and
+        # writes the orientation of these only
+        g = ctx.get_state()
+        n_turn = int(np.sum((np.asarray(sysm.own_tmpl) >= 0) & np.any(np.asarray(g["W"]) != 0, axis=1)))
     ctx.close()
     del ctx
-    return dict(seconds=t1 - t0, stats=stats, info=info, active=int(active), active_owners=int(act_own))
+    return dict(seconds=t1 - t0, stats=stats, info=info, active=int(active), active_owners=int(act_own),
+                n_turn=n_turn)
 
 
 def priming_system(W, sysm):
@@ -411,8 +419,9 @@ def main():
         print(f"# primed every schedule on a small system in {time.perf_counter() - t0:.1f}s", file=sys.stderr,
               flush=True)
     results = {}
+    head = "learned" if "learned" in modes else ("fixed" if "fixed" in modes else modes[0])
     for mode in modes:
-        r = run_mode(dem, torch, sysm, mode, args, mlp=mlp)
+        r = run_mode(dem, torch, sysm, mode, args, mlp=mlp, turning=mode == head and Ns != No)
         st = r["stats"]
         rate = Ns * args.steps / r["seconds"]
         results[mode] = r
@@ -433,7 +442,6 @@ def main():
             ctx.close()
             print(f"# judged {mode}: misses {st['misses']} repairs {st['repairs']}", file=sys.stderr, flush=True)
 
-    head = "learned" if "learned" in results else ("fixed" if "fixed" in results else modes[0])
     r = results[head]
     st = r["stats"]
     value = Ns * args.steps / r["seconds"]
@@ -469,10 +477,12 @@ def main():
     pairs_dom = n_launch if (split or args.dyn_path == 1) else n_noop
     avg_ms = max((tot[dom] - stamp_ms * pairs_dom) / n_launch, 1e-6)
     C = st["mean_contacts"]
-    kw = dict(clumps=Ns != No, rolling=rolling, n_clump=n_clump, n_tri=n_tri, n_dormant=n_dormant,
-              n_dormant_clump=n_dormant_clump)
+    # (the split clump step moves the orientation of turning clumps only)
+    n_clump_q = r["n_turn"] if (split and r["n_turn"] is not None) else n_clump
+    kw = dict(clumps=Ns != No, rolling=rolling, n_clump=n_clump_q, n_tri=n_tri, n_dormant=n_dormant,
+              n_dormant_clump=min(n_dormant_clump, n_clump_q))
     if split:
-        algo_k = {"k_step_free": stream_bytes(No, n_clump),
+        algo_k = {"k_step_free": stream_bytes(No, r["n_turn"] if r["n_turn"] is not None else n_clump),
                   "k_step_listed": listed_bytes(r["active_owners"], n_clump_share(sysm, r), r["active"], C,
                                                 rolling)}
     else:

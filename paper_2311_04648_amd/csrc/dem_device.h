@@ -43,6 +43,13 @@ __host__ __device__ inline void encode_axis(double x, double origin, uint32_t *i
     *off = (float)(kq * DEM_OFF_QUANT);
 }
 
+// The top bit of an owner record's voxel word (the three axes use the
+// low 63 bits; pack_vox leaves it clear): set by the streaming clump step
+// when both orientation buffers hold the owner's orientation, so that a
+// clump at rest on that path needs neither read nor write of it.  Every
+// other writer of a record clears it (pack_vox) or copies both buffers.
+constexpr uint64_t DEM_VOX_QSAME = 1ull << 63;
+
 __host__ __device__ inline uint64_t pack_vox(uint32_t x, uint32_t y, uint32_t z)
 {
     return (uint64_t)x | ((uint64_t)y << DEM_VOX_BITS) | ((uint64_t)z << (2 * DEM_VOX_BITS));

@@ -1193,8 +1193,14 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, OwnerR
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // Orientations: a single sphere's is the identity in both buffers and
+    // is never touched; a clump without contacts that does not turn (zero
+    // angular velocity: without torque it keeps it, and its orientation
+    // stays) and whose record says both buffers already hold its
+    // orientation (DEM_VOX_QSAME) needs neither read nor write of it.
     OwnerRec r[FREE_CHUNKS];
     double4 qv[FREE_CHUNKS];
+    bool still[FREE_CHUNKS];
 #pragma unroll
     for (int c = 0; c < FREE_CHUNKS; ++c) {
         const bool valid = lane < nv[c];
@@ -1202,15 +1208,13 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, OwnerR
         r[c] = OwnerRec{};
         if (valid) r[c] = load_rec(reinterpret_cast<const OwnerRec *>(wbuf[wv][c]) + lane);
         qv[c] = make_double4(1.0, 0.0, 0.0, 0.0);
-        if (valid && ax[c].tmpl >= 0 && (halt || !(fl[c] & 1u)))
+        still[c] = (r[c].vox & DEM_VOX_QSAME) != 0 && r[c].w[0] == 0.0f && r[c].w[1] == 0.0f && r[c].w[2] == 0.0f;
+        if (valid && ax[c].tmpl >= 0 && (halt || (!(fl[c] & 1u) && !still[c])))
             qv[c] = *reinterpret_cast<const double4 *>(a.q + 4 * (size_t)o);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // (the orientation buffer is written for single spheres too, with the
-    // identity they keep: whole lines of it are written, none read back to
-    // merge a partial write)
 #pragma unroll
     for (int c = 0; c < FREE_CHUNKS; ++c) {
         const bool valid = lane < nv[c];
@@ -1220,14 +1224,17 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, OwnerR
         if (halt) {
             // a stopped step: the state is copied unchanged (the records
             // below, the orientation here; the history by k_step_listed)
-            if (valid) *reinterpret_cast<double4 *>(qo) = qv[c];
+            if (rot) *reinterpret_cast<double4 *>(qo) = qv[c];
         } else if (valid && !(fl[c] & 1u)) {
             const float inv[3] = {ax[c].inv_moi[0], ax[c].inv_moi[1], ax[c].inv_moi[2]};
-            v2 = fmaxf(v2, advance(a, r[c], inv, rot, f3(0.f, 0.f, 0.f), f3(0.f, 0.f, 0.f), qv[c], qo, ctr));
-            if (!rot) *reinterpret_cast<double4 *>(qo) = qv[c];
+            // (a still clump: no orientation is read and none written, as
+            // the rotation by a zero angle would write back the one read)
+            v2 = fmaxf(v2, advance(a, r[c], inv, rot, f3(0.f, 0.f, 0.f), f3(0.f, 0.f, 0.f), qv[c],
+                                   still[c] ? nullptr : qo, ctr));
+            // after this step both buffers hold the orientation if the
+            // clump did not turn in it
+            if (rot && r[c].w[0] == 0.0f && r[c].w[1] == 0.0f && r[c].w[2] == 0.0f) r[c].vox |= DEM_VOX_QSAME;
             store_rec(reinterpret_cast<OwnerRec *>(wbuf[wv][c]) + lane, r[c]);
-        } else if (valid && !rot) {
-            *reinterpret_cast<double4 *>(qo) = qv[c];
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

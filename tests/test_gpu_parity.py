@@ -573,6 +573,34 @@ def test_capacity_overflow_during_steps_stops_clumps(dem, dyn_path):
     np.testing.assert_array_equal(g["X"], s.X)
 
 
+def test_resting_clumps_split_step_equals_two_kernel_form(dem):
+    """Clumps released at rest, half of them not turning, fall onto the
+    floor (strong gravity) and start to turn where they land.  The
+    streaming step touches the orientation of a clump at rest neither to
+    read nor to write it; the split step must still give the two-kernel
+    form's state bit for bit, orientations included, on two streams."""
+    import torch
+    s = W.small_clumps(12, n=200, vel=0.0, spacing=0.0125, jitter=0.0002, gravity=(0, 0, -200.0))
+    s.W[::2] = 0.0
+    out = []
+    for path in (4, 1):
+        c = dem.DemContext(s, mode="fixed", k=10, lam=5, dyn_path=path)
+        c.set_state()
+        c.step(3000, dyn=torch.cuda.Stream(), kin=torch.cuda.Stream())
+        out.append((c.get_state(), c.get_contacts()[0]))
+        c.close()
+    (ga, ka), (gb, kb) = out
+    for k in ("X", "q", "V", "W"):
+        np.testing.assert_array_equal(ga[k], gb[k])
+    np.testing.assert_array_equal(ka, kb)
+    clump = s.own_tmpl >= 0
+    turning = np.any(ga["W"] != 0, axis=1)
+    print(f"{ka.size} pairs; clumps turning {np.sum(clump & turning)}, at rest {np.sum(clump & ~turning)}",
+          flush=True)
+    assert ka.size > 20
+    assert np.sum(clump & turning) > 0 and np.sum(clump & ~turning) > 0
+
+
 def test_divergence_guard_on_the_delayed_schedule(dem):
     """A run that diverges at its first step under the fixed-margin schedule
     on two streams: the later steps (a work-order step, whose binning rides
