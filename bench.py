@@ -126,13 +126,15 @@ def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, roll
     raise ValueError(stage)
 
 
-def stream_bytes(No, n_turn):
-    """k_step_free: per owner its contact flag (1), inertia and template (16)
-    and record read + written (96); per turning clump its orientation read +
-    written (64; a clump at rest keeps its orientation in both buffers and
-    the step touches neither).  Owners with contacts are counted here (their
-    records are read and written, then written again by k_step_listed)."""
-    return No * 113 + n_turn * 64
+def stream_bytes(No, n_turn, n_spin=None):
+    """k_step_free: per owner its contact flag (1) and record read + written
+    (96); per turning owner (nonzero angular velocity) its inertia and
+    template (16), and per turning clump its orientation read + written
+    (64): an owner at rest in rotation keeps its orientation in both buffers
+    and needs neither (without n_spin every owner is counted with its
+    inertia).  Owners with contacts are counted here (their records are read
+    and written, then written again by k_step_listed)."""
+    return No * 97 + (No if n_spin is None else n_spin) * 16 + n_turn * 64
 
 
 def n_clump_share(sysm, rr):
@@ -209,16 +211,18 @@ def run_mode(dem, torch, sysm, mode, args, mlp=None, judge=False, turning=False)
     jj = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
     active = np.unique(np.concatenate([ii, jj[jj < sysm.n_spheres]])).size
     act_own = np.unique(np.asarray(sysm.sph_owner)[np.unique(np.concatenate([ii, jj[jj < sysm.n_spheres]]))]).size
-    n_turn = None
+    n_turn = n_spin = None
     if turning:
-        # clumps turning at the end of the run: the streaming step reads and
-        # writes the orientation of these only
+        # owners turning at the end of the run: the streaming step reads the
+        # inertia of these only, and the orientation of the clumps among them
         g = ctx.get_state()
-        n_turn = int(np.sum((np.asarray(sysm.own_tmpl) >= 0) & np.any(np.asarray(g["W"]) != 0, axis=1)))
+        spin = np.any(np.asarray(g["W"]) != 0, axis=1)
+        n_spin = int(np.sum(spin))
+        n_turn = int(np.sum((np.asarray(sysm.own_tmpl) >= 0) & spin))
     ctx.close()
     del ctx
     return dict(seconds=t1 - t0, stats=stats, info=info, active=int(active), active_owners=int(act_own),
-                n_turn=n_turn)
+                n_turn=n_turn, n_spin=n_spin)
 
 
 def priming_system(W, sysm):
@@ -482,7 +486,7 @@ def main():
     kw = dict(clumps=Ns != No, rolling=rolling, n_clump=n_clump_q, n_tri=n_tri, n_dormant=n_dormant,
               n_dormant_clump=min(n_dormant_clump, n_clump_q))
     if split:
-        algo_k = {"k_step_free": stream_bytes(No, r["n_turn"] if r["n_turn"] is not None else n_clump),
+        algo_k = {"k_step_free": stream_bytes(No, r["n_turn"] if r["n_turn"] is not None else n_clump, r["n_spin"]),
                   "k_step_listed": listed_bytes(r["active_owners"], n_clump_share(sysm, r), r["active"], C,
                                                 rolling)}
     else:

@@ -1138,8 +1138,8 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
 // of owners with contacts and does for each what the one-kernel step does
 // (owner_forces, then the integration), so both forms give the same bits.
 // A wave's 64 records move through LDS in three contiguous 1 KiB loads and
-// stores, as in the single-sphere step; the inertia and the flag are loaded
-// with them, the orientation (clumps only) once the template is known.
+// stores, as in the single-sphere step, with the flags; the inertia and
+// orientation only for owners that turn or have just stopped turning.
 // REMAP: the first step on a newly adopted set (only its overflow check
 // matters here).
 constexpr int FREE_WAVES = 2;    // waves per block of k_step_free
@@ -1173,32 +1173,30 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, OwnerR
     }
     float v2 = 0.0f;
     uint8_t fl[FREE_CHUNKS];
-    OwnerAux ax[FREE_CHUNKS];
     uint32_t nv[FREE_CHUNKS];
-    // loads: flags, inertia and the records (through LDS) of every chunk
+    // loads: flags and the records (through LDS) of every chunk
 #pragma unroll
     for (int c = 0; c < FREE_CHUNKS; ++c) {
         const int64_t ow = ob + (int64_t)(wv * FREE_CHUNKS + c) * 64;
         const int64_t o = ow + lane;
         nv[c] = ow < No ? (uint32_t)(No - ow < 64 ? No - ow : 64) : 0u;
         fl[c] = 1u;
-        ax[c] = OwnerAux{};
-        if (o < No) {
-            fl[c] = oany[o];
-            ax[c] = a.aux[o];
-        }
+        if (o < No) fl[c] = oany[o];
         const uint4 *src = reinterpret_cast<const uint4 *>(a.rec + ow);
         for (uint32_t k = lane; k < 3u * nv[c]; k += 64u) wbuf[wv][c][k] = src[k];
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // Orientations: a single sphere's is the identity in both buffers and
-    // is never touched; a clump without contacts that does not turn (zero
-    // angular velocity: without torque it keeps it, and its orientation
-    // stays) and whose record says both buffers already hold its
-    // orientation (DEM_VOX_QSAME) needs neither read nor write of it.
+    // An owner without contacts that does not turn (zero angular velocity:
+    // without torque it keeps it) and whose record marks both orientation
+    // buffers as holding its orientation (DEM_VOX_QSAME; always true of a
+    // single sphere's identity) is still: its step needs neither its inertia
+    // nor its orientation, and neither buffer is written.  The others load
+    // their inertia and template, and their orientation with it (used by
+    // clumps only).
     OwnerRec r[FREE_CHUNKS];
+    OwnerAux ax[FREE_CHUNKS];
     double4 qv[FREE_CHUNKS];
     bool still[FREE_CHUNKS];
 #pragma unroll
@@ -1207,10 +1205,14 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, OwnerR
         const int64_t o = ob + (int64_t)(wv * FREE_CHUNKS + c) * 64 + lane;
         r[c] = OwnerRec{};
         if (valid) r[c] = load_rec(reinterpret_cast<const OwnerRec *>(wbuf[wv][c]) + lane);
+        still[c] = !halt && !(fl[c] & 1u) && (r[c].vox & DEM_VOX_QSAME) != 0 && r[c].w[0] == 0.0f &&
+                   r[c].w[1] == 0.0f && r[c].w[2] == 0.0f;
+        ax[c] = OwnerAux{{0.0f, 0.0f, 0.0f}, -1};
         qv[c] = make_double4(1.0, 0.0, 0.0, 0.0);
-        still[c] = (r[c].vox & DEM_VOX_QSAME) != 0 && r[c].w[0] == 0.0f && r[c].w[1] == 0.0f && r[c].w[2] == 0.0f;
-        if (valid && ax[c].tmpl >= 0 && (halt || (!(fl[c] & 1u) && !still[c])))
+        if (valid && (halt || (!(fl[c] & 1u) && !still[c]))) {
+            ax[c] = a.aux[o];
             qv[c] = *reinterpret_cast<const double4 *>(a.q + 4 * (size_t)o);
+        }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -1226,14 +1228,15 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, OwnerR
             // below, the orientation here; the history by k_step_listed)
             if (rot) *reinterpret_cast<double4 *>(qo) = qv[c];
         } else if (valid && !(fl[c] & 1u)) {
+            // (a still owner: zero torque on zero angular velocity, no
+            // turn; the integration of a turning path would give the same
+            // bits and write back the orientation it read)
             const float inv[3] = {ax[c].inv_moi[0], ax[c].inv_moi[1], ax[c].inv_moi[2]};
-            // (a still clump: no orientation is read and none written, as
-            // the rotation by a zero angle would write back the one read)
             v2 = fmaxf(v2, advance(a, r[c], inv, rot, f3(0.f, 0.f, 0.f), f3(0.f, 0.f, 0.f), qv[c],
-                                   still[c] ? nullptr : qo, ctr));
+                                   rot ? qo : nullptr, ctr));
             // after this step both buffers hold the orientation if the
-            // clump did not turn in it
-            if (rot && r[c].w[0] == 0.0f && r[c].w[1] == 0.0f && r[c].w[2] == 0.0f) r[c].vox |= DEM_VOX_QSAME;
+            // owner did not turn in it
+            if (r[c].w[0] == 0.0f && r[c].w[1] == 0.0f && r[c].w[2] == 0.0f) r[c].vox |= DEM_VOX_QSAME;
             store_rec(reinterpret_cast<OwnerRec *>(wbuf[wv][c]) + lane, r[c]);
         }
     }
