@@ -467,18 +467,72 @@ __device__ inline void dormant_walk(const DetectArgs &a, uint32_t key, const flo
     }
 }
 
-__global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32_t *keys, const Cand *cand,
-                                                      const float4 *candf, const uint32_t *cell_start,
-                                                      uint32_t *count, uint32_t *stage, uint32_t *bcount)
+// Whether sphere (FP32 copy cif relative to the grid origin, radius r)
+// may be within the margin of wall w: the test of wall_hit on the centre
+// recovered from its FP32 copy, with every threshold widened by the FP32
+// rounding of that copy (each coordinate within 2^-24 M of the exact one,
+// M its largest magnitude; 8 2^-24 M covers the three components through
+// the projections) and 1e-9 m.  False means wall_hit is false.
+__device__ inline bool wall_near(const WallDev &w, const double *p, const Grid &g, const float4 &cif, double r,
+                                 double m)
+{
+    const double M = (double)fmaxf(fabsf(cif.x), fmaxf(fabsf(cif.y), fabsf(cif.z)));
+    const double slack = 8.0 * 5.9604644775390625e-8 * M + 1e-9;
+    const double rx = ((double)cif.x + g.lo[0]) - p[0], ry = ((double)cif.y + g.lo[1]) - p[1],
+                 rz = ((double)cif.z + g.lo[2]) - p[2];
+    if (w.type == 0) {
+        const double sd = (rx * w.geom[3] + ry * w.geom[4]) + rz * w.geom[5];
+        return sd < r + 2.0 * m + slack;
+    }
+    const double ax = (rx * w.geom[3] + ry * w.geom[4]) + rz * w.geom[5];
+    const double hl = 0.5 * w.geom[7] + 2.0 * m + slack;
+    if (!(ax <= hl && ax >= -hl)) return false;
+    const double px = rx - ax * w.geom[3], py = ry - ax * w.geom[4], pz = rz - ax * w.geom[5];
+    const double d2 = (px * px + py * py) + pz * pz;
+    const double T = (w.geom[6] + r) + 2.0 * m + slack;
+    return d2 < T * T;
+}
+
+// Sphere p of the bin order (id vals[p]) against the candidates after it:
+// an FP32 prefilter, then (clump systems) the other sphere's id against the
+// sphere range of p's owner (spheres of one owner are consecutive and never
+// a contact), then the exact FP64 predicate on the candidates' exact
+// centres; walls are prefiltered the same way.  The exact centre of p, and
+// its owner, are loaded when a candidate first needs them.
+__global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32_t *keys, const uint32_t *vals,
+                                                      const Cand *cand, const float4 *candf,
+                                                      const uint32_t *cell_start, uint32_t *count, uint32_t *stage,
+                                                      uint32_t *bcount)
 {
     const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (p >= a.n_spheres || p >= (int64_t)cell_start[a.grid.nbins]) return;   // (dormant spheres are not binned)
-    const Cand ci = cand[p];
     const float4 cif = candf[p];
-    const uint32_t i = ci.id;
+    const uint32_t i = vals[p];
     const uint32_t key = keys[p];
-    const double xi = ci.x, yi = ci.y, zi = ci.z, ri = (double)ci.r;
+    const double ri = (double)cif.w;
     const double m = a.margin_dev ? *a.margin_dev : a.margin;
+    // the exact centre of p and its owner's sphere range, on first use
+    double xi = 0.0, yi = 0.0, zi = 0.0;
+    bool have_x = false;
+    auto exact = [&]() {
+        if (!have_x) {
+            const Cand ci = cand[p];
+            xi = ci.x;
+            yi = ci.y;
+            zi = ci.z;
+            have_x = true;
+        }
+    };
+    uint32_t own_i = 0xffffffffu, s0 = i, s1 = i + 1u;
+    auto owner = [&]() {
+        if (own_i == 0xffffffffu) {
+            own_i = a.sph[i].owner;
+            if (a.own_sph0) {
+                s0 = a.own_sph0[own_i];
+                s1 = a.own_sph0[own_i + 1];
+            }
+        }
+    };
     // FP32 prefilter: a candidate is rejected only when its FP32 distance
     // exceeds the pair threshold T by more than a bound on the rounding.
     // Each FP32 coordinate is within 2^-24 |c| of the exact one (c: the
@@ -509,10 +563,9 @@ __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32
         }
     }
     const uint32_t total = (rl[0] + rl[1]) + (rl[2] + rl[3] + rl[4]);
-    uint32_t own_i = 0xffffffffu;
     for (uint32_t v0 = 0; v0 < total; v0 += DETECT_BATCH) {
         float4 cb[DETECT_BATCH];
-        uint32_t qb[DETECT_BATCH];
+        uint32_t qb[DETECT_BATCH], jb[DETECT_BATCH];
 #pragma unroll
         for (int u = 0; u < DETECT_BATCH; ++u) {
             uint32_t v = v0 + (uint32_t)u;
@@ -527,6 +580,7 @@ __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32
                     }
                 qb[u] = ra[r] + v;
                 cb[u] = candf[qb[u]];
+                jb[u] = vals[qb[u]];
             }
         }
 #pragma unroll
@@ -537,20 +591,28 @@ __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32
             const float T32 = (cif.w + cb[u].w) + twom;
             const float tf = T32 + ((4.77e-7f * (Mi + Mj) + 9.54e-7f * T32) + 1e-12f);
             if ((dxf * dxf + dyf * dyf) + dzf * dzf > tf * tf) continue;
+            const uint32_t j = jb[u];
+            if (a.own_sph0) {
+                // (two spheres of one clump: never a contact)
+                owner();
+                if (j >= s0 && j < s1) continue;
+            }
+            exact();
             const Cand cj = cand[qb[u]];
             if (!sphere_pair_hit(xi, yi, zi, ri, cj, m)) continue;
-            if (own_i == 0xffffffffu) own_i = a.sph[i].owner;
-            const uint32_t own_j = a.sph[cj.id].owner;
-            if (own_j == own_i) continue;
-            if (a.pairoff && !fam_on(a, a.ofam[own_i], a.ofam[own_j])) continue;
-            const uint32_t lo = i < cj.id ? i : cj.id, hi = i < cj.id ? cj.id : i;
+            if (a.pairoff) {
+                owner();
+                if (!fam_on(a, a.ofam[own_i], a.ofam[a.sph[j].owner])) continue;
+            }
+            const uint32_t lo = i < j ? i : j, hi = i < j ? j : i;
             const uint32_t slot = atomicAdd(&count[lo], 1u);
             if (slot < (uint32_t)STAGE_K) stage[(size_t)lo * STAGE_K + slot] = hi;
             if (bcount) atomicAdd(&bcount[hi], 1u);
         }
     }
     if (a.famdormant) {
-        if (own_i == 0xffffffffu) own_i = a.sph[i].owner;
+        owner();
+        exact();
         dormant_walk(a, key, cif, xi, yi, zi, ri, m, a.ofam[own_i], [&](uint32_t j) {
             const uint32_t lo = i < j ? i : j, hi = i < j ? j : i;
             const uint32_t slot = atomicAdd(&count[lo], 1u);
@@ -562,8 +624,13 @@ __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32
         WallDev wd = a.walls[w];
         double pw[3];
         wall_point(wd, a.step, a.h, pw);
+        if (!wall_near(wd, pw, a.grid, cif, ri, m)) continue;
+        exact();
         if (!wall_hit(wd, pw, xi, yi, zi, ri, m)) continue;
-        if (a.pairoff && !fam_on(a, a.ofam[a.sph[i].owner], (uint32_t)wd.family)) continue;
+        if (a.pairoff) {
+            owner();
+            if (!fam_on(a, a.ofam[own_i], (uint32_t)wd.family)) continue;
+        }
         const uint32_t slot = atomicAdd(&count[i], 1u);
         if (slot < (uint32_t)STAGE_K) stage[(size_t)i * STAGE_K + slot] = (uint32_t)a.n_spheres + (uint32_t)w;
     }
@@ -1113,7 +1180,7 @@ void launch_detect_back(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap
     int64_t n = a.n_spheres;
     // (the per-sphere counters out.bcur and w.count zeroed by the gather)
     launch_bin_back(a, w, s, false, out.bcur, w.count);
-    hipLaunchKernelGGL(k_detect_stage, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,
+    hipLaunchKernelGGL(k_detect_stage, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.vals, w.cand,
                        (const float4 *)w.candf, w.cell_start, w.count, w.stage, out.bcur);
     if (a.n_tri > 0) {
         launch_facet_prepare(a, w, s);
@@ -1175,7 +1242,7 @@ void launch_detect_plain(const DetectArgs &a_in, CdWork &w, uint32_t *start, uin
     a.famdormant = nullptr;
     int64_t n = a.n_spheres;
     launch_bin(a, w, s, w.count, n + 1, nullptr, 0, false);
-    hipLaunchKernelGGL(k_detect_stage, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.cand,
+    hipLaunchKernelGGL(k_detect_stage, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.vals, w.cand,
                        (const float4 *)w.candf, w.cell_start, w.count, w.stage, (uint32_t *)nullptr);
     if (a.n_tri > 0) {
         launch_facet_prepare(a, w, s);
