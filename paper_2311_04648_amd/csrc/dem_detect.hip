@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(TPB) k_cand_gather(const uint32_t *vals, const
     }
     if (p >= n || p >= (int64_t)cell_start[g.nbins]) return;   // (dormant spheres sit after the binned ones)
     const Cand c = cand_tmp[vals[p]];
-    cand[p] = c;
+    if (cand) cand[p] = c;   // (null: no walk over bins reads the records in bin order)
     candf[p] = make_float4((float)(c.x - g.lo[0]), (float)(c.y - g.lo[1]), (float)(c.z - g.lo[2]), c.r);
 }
 
@@ -498,9 +498,11 @@ __device__ inline bool wall_near(const WallDev &w, const double *p, const Grid &
 // sphere range of p's owner (spheres of one owner are consecutive and never
 // a contact), then the exact FP64 predicate on the candidates' exact
 // centres; walls are prefiltered the same way.  The exact centre of p, and
-// its owner, are loaded when a candidate first needs them.
+// its owner, are loaded when a candidate first needs them.  Exact centres
+// come from the candidate records by sphere id (cand_id), so the binning
+// need not copy them into bin order.
 __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32_t *keys, const uint32_t *vals,
-                                                      const Cand *cand, const float4 *candf,
+                                                      const Cand *cand_id, const float4 *candf,
                                                       const uint32_t *cell_start, uint32_t *count, uint32_t *stage,
                                                       uint32_t *bcount)
 {
@@ -516,7 +518,7 @@ __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32
     bool have_x = false;
     auto exact = [&]() {
         if (!have_x) {
-            const Cand ci = cand[p];
+            const Cand ci = cand_id[i];
             xi = ci.x;
             yi = ci.y;
             zi = ci.z;
@@ -598,7 +600,7 @@ __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32
                 if (j >= s0 && j < s1) continue;
             }
             exact();
-            const Cand cj = cand[qb[u]];
+            const Cand cj = cand_id[j];
             if (!sphere_pair_hit(xi, yi, zi, ri, cj, m)) continue;
             if (a.pairoff) {
                 owner();
@@ -655,10 +657,12 @@ __device__ inline void fill_blists(const uint32_t *row, uint32_t base, uint32_t 
 // than STAGE_K is found again by a full-stencil walk for its sphere (its
 // centre from the unsorted candidate records, its bin recomputed the same
 // way as when binning), written, and sorted in place.
+// (cand null: the candidates of the walk below are read by sphere id from
+// cand_tmp, through the sorted ids vals)
 __global__ void __launch_bounds__(TPB) k_compact(DetectArgs a, const Cand *cand_tmp, const Cand *cand,
-                                                 const uint32_t *cell_start, const uint32_t *start,
-                                                 const uint32_t *stage, uint32_t *out_j, int64_t cap,
-                                                 uint32_t *bcur, uint32_t *bidx, uint32_t *bsrc,
+                                                 const uint32_t *vals, const uint32_t *cell_start,
+                                                 const uint32_t *start, const uint32_t *stage, uint32_t *out_j,
+                                                 int64_t cap, uint32_t *bcur, uint32_t *bidx, uint32_t *bsrc,
                                                  const FacetDev *fac)
 {
     const int64_t ns = a.n_spheres;
@@ -728,7 +732,7 @@ __global__ void __launch_bounds__(TPB) k_compact(DetectArgs a, const Cand *cand_
             const uint32_t rw = key + (uint32_t)((int)nxy * dz) + (uint32_t)((int)nx * dy);
             const uint32_t q0 = cell_start[rw - 1], q1 = cell_start[rw + 2];
             for (uint32_t qq = q0; qq < q1; ++qq) {
-                const Cand cj = cand[qq];
+                const Cand cj = cand ? cand[qq] : cand_tmp[vals[qq]];
                 if (cj.id <= (uint32_t)i) continue;
                 if (!sphere_pair_hit(xi, yi, zi, ri, cj, m)) continue;
                 const uint32_t own_j = a.sph[cj.id].owner;
@@ -1075,8 +1079,11 @@ void launch_bin_front(const DetectArgs &a, CdWork &w, hipStream_t s, uint32_t *z
 // With `order_bins` the ids inside each bin are put in ascending order (a
 // stable sort of (bin, id)); the detection does not need it: the pairs it
 // finds do not depend on the order of the candidates inside a bin.
+// With `bin_cand` false the candidate records are not copied into bin
+// order (only their FP32 copies are written): the detection reads them by
+// sphere id.
 void launch_bin_back(const DetectArgs &a, CdWork &w, hipStream_t s, bool order_bins, uint32_t *z1 = nullptr,
-                     uint32_t *z2 = nullptr)
+                     uint32_t *z2 = nullptr, bool bin_cand = true)
 {
     int64_t n = a.n_spheres;
     const int64_t nb = (int64_t)a.grid.nbins;
@@ -1095,8 +1102,9 @@ void launch_bin_back(const DetectArgs &a, CdWork &w, hipStream_t s, bool order_b
     }
     // candidate records in bin order (random 32-byte reads, coalesced writes;
     // moving the records in the scatter instead costs more: random writes)
-    hipLaunchKernelGGL(k_cand_gather, dim3(nblocks(n)), dim3(TPB), 0, s, w.vals, w.cand_tmp, w.cand, w.candf,
-                       a.grid, n, (const uint32_t *)w.cell_start, z1, z2);
+    hipLaunchKernelGGL(k_cand_gather, dim3(nblocks(n)), dim3(TPB), 0, s, w.vals, w.cand_tmp,
+                       bin_cand ? w.cand : (Cand *)nullptr, w.candf, a.grid, n, (const uint32_t *)w.cell_start, z1,
+                       z2);
 }
 
 void launch_bin(const DetectArgs &a, CdWork &w, hipStream_t s, uint32_t *z1, int64_t n1, uint32_t *z2,
@@ -1179,8 +1187,11 @@ void launch_detect_back(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap
 {
     int64_t n = a.n_spheres;
     // (the per-sphere counters out.bcur and w.count zeroed by the gather)
-    launch_bin_back(a, w, s, false, out.bcur, w.count);
-    hipLaunchKernelGGL(k_detect_stage, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.vals, w.cand,
+    // (the facet walk reads candidate records in bin order; without meshes
+    // they are not copied)
+    const bool bin_cand = a.n_tri > 0;
+    launch_bin_back(a, w, s, false, out.bcur, w.count, bin_cand);
+    hipLaunchKernelGGL(k_detect_stage, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.vals, w.cand_tmp,
                        (const float4 *)w.candf, w.cell_start, w.count, w.stage, out.bcur);
     if (a.n_tri > 0) {
         launch_facet_prepare(a, w, s);
@@ -1195,9 +1206,9 @@ void launch_detect_back(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap
     scan_exclusive_u32_pair(w.count, out.start, nullptr, ctr, cap, buf, out.bcur, out.bstart, out.bcur, n,
                             w.partials, s);
     hipLaunchKernelGGL(k_compact, dim3(nblocks(n)), dim3(TPB), 0, s, a, (const Cand *)w.cand_tmp,
-                       (const Cand *)w.cand, (const uint32_t *)w.cell_start, (const uint32_t *)out.start,
-                       (const uint32_t *)w.stage, out.j, cap, out.bcur, out.bidx, out.bsrc,
-                       (const FacetDev *)w.fac);
+                       bin_cand ? (const Cand *)w.cand : (const Cand *)nullptr, (const uint32_t *)w.vals,
+                       (const uint32_t *)w.cell_start, (const uint32_t *)out.start, (const uint32_t *)w.stage, out.j,
+                       cap, out.bcur, out.bidx, out.bsrc, (const FacetDev *)w.fac);
     // B lists sorted, owner flags, and the bin counts (dead since the
     // scatter) zeroed for the next front, in one launch
     hipLaunchKernelGGL(k_blist_finish, dim3(nblocks(std::max(n, a.n_owners))), dim3(TPB), 0, s, out.start,
@@ -1242,7 +1253,7 @@ void launch_detect_plain(const DetectArgs &a_in, CdWork &w, uint32_t *start, uin
     a.famdormant = nullptr;
     int64_t n = a.n_spheres;
     launch_bin(a, w, s, w.count, n + 1, nullptr, 0, false);
-    hipLaunchKernelGGL(k_detect_stage, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.vals, w.cand,
+    hipLaunchKernelGGL(k_detect_stage, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys, w.vals, w.cand_tmp,
                        (const float4 *)w.candf, w.cell_start, w.count, w.stage, (uint32_t *)nullptr);
     if (a.n_tri > 0) {
         launch_facet_prepare(a, w, s);
@@ -1255,9 +1266,9 @@ void launch_detect_plain(const DetectArgs &a_in, CdWork &w, uint32_t *start, uin
     scan_exclusive_u32(w.count, start, n, w.partials, s);
     hipLaunchKernelGGL(k_record_total, dim3(1), dim3(1), 0, s, start, n, ctr);
     hipLaunchKernelGGL(k_compact, dim3(nblocks(n)), dim3(TPB), 0, s, a, (const Cand *)w.cand_tmp,
-                       (const Cand *)w.cand, (const uint32_t *)w.cell_start, (const uint32_t *)start,
-                       (const uint32_t *)w.stage, j, cap, (uint32_t *)nullptr, (uint32_t *)nullptr,
-                       (uint32_t *)nullptr, (const FacetDev *)w.fac);
+                       (const Cand *)w.cand, (const uint32_t *)w.vals, (const uint32_t *)w.cell_start,
+                       (const uint32_t *)start, (const uint32_t *)w.stage, j, cap, (uint32_t *)nullptr,
+                       (uint32_t *)nullptr, (uint32_t *)nullptr, (const FacetDev *)w.fac);
 }
 
 void launch_label_judge(const DetectArgs &a_in, CdWork &w, const uint32_t *lab_start, const uint32_t *lab_j,

@@ -601,6 +601,37 @@ def test_resting_clumps_split_step_equals_two_kernel_form(dem):
     assert np.sum(clump & turning) > 0 and np.sum(clump & ~turning) > 0
 
 
+def test_packed_clumps_split_step_equals_two_kernel_form(dem):
+    """Packed clumps (many contacts per owner): the split step's kernel over
+    the owners with contacts evaluates an owner's items a few at a time in
+    a group of lanes and adds them in order; owners with more items than a
+    group has lanes take several rounds.  Bit for bit the two-kernel form,
+    on two streams, over a delayed schedule."""
+    import torch
+    # (a 3 mm margin: every clump lists dozens of pairs with its neighbours)
+    s = W.small_clumps(3, n=216, spacing=0.0085, vel=0.02, margin=0.003)
+    out = []
+    for path in (4, 1):
+        c = dem.DemContext(s, mode="fixed", k=5, lam=2, dyn_path=path, capacity=64 * s.n_spheres)
+        c.set_state()
+        c.step(400, dyn=torch.cuda.Stream(), kin=torch.cuda.Stream())
+        out.append((c.get_state(), c.get_contacts()))
+        c.close()
+    (ga, (ka, ha)), (gb, (kb, hb)) = out
+    for k in ("X", "q", "V", "W"):
+        np.testing.assert_array_equal(ga[k], gb[k])
+    np.testing.assert_array_equal(ka, kb)
+    np.testing.assert_array_equal(ha, hb)
+    # items per owner: its spheres' row entries and B-list entries
+    ki = (ka >> np.uint64(32)).astype(np.int64)
+    kj = (ka & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    items = np.bincount(s.sph_owner[ki], minlength=s.n_owners)
+    sph = kj < s.n_spheres
+    items += np.bincount(s.sph_owner[kj[sph]], minlength=s.n_owners)
+    print(f"{ka.size} pairs; largest item count of an owner {items.max()}", flush=True)
+    assert items.max() > 16
+
+
 def test_divergence_guard_on_the_delayed_schedule(dem):
     """A run that diverges at its first step under the fixed-margin schedule
     on two streams: the later steps (a work-order step, whose binning rides
