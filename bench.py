@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--no-prime", action="store_true", help="skip the small priming runs")
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--lam", type=int, default=5)
+    ap.add_argument("--no-pair-skip", action="store_true",
+                    help="evaluate every pair of a dense single-sphere set every step (no skipping by gap keys)")
     ap.add_argument("--dyn-path", type=int, default=0,
                     help="dynamics: 0 one fused kernel per step, 1 force kernel + fold/integrate kernel, 2/3 fused with the history always/never staged in LDS")
     ap.add_argument("--timing", type=int, default=0,
@@ -188,7 +190,8 @@ def make_ctx(dem, sysm, mode, args, mlp, judge, dyn_path=None):
     lib_mode = "learned" if mode == "analytic" else mode
     ctx = dem.DemContext(sysm, mode=lib_mode, k=args.k, lam=args.lam, judge=judge,
                          timing=0 if judge else args.timing, capacity=max(64, 8 * sysm.n_spheres), k_max=1024,
-                         mlp_safety=args.mlp_safety, dyn_path=args.dyn_path if dyn_path is None else dyn_path)
+                         mlp_safety=args.mlp_safety, dyn_path=args.dyn_path if dyn_path is None else dyn_path,
+                         pair_skip=not args.no_pair_skip)
     if mode == "learned":
         ctx.mlp_set(mlp)
     return ctx
