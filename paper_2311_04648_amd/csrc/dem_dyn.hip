@@ -699,7 +699,12 @@ __device__ inline float gap_key(double g, double D)
 // skipped by the pairs' keys and the A rows' keys written (DynArgs::gap; Dn
 // is the step's reach), and an item's indices are loaded two items ahead,
 // its key one item ahead.
-template <bool SINGLES, bool FACETS, bool FIXED, bool AHEAD, bool REMAP, bool GAP = false>
+// BOUNDS (clumps): the row and B-list bounds of the owner's first
+// BOUND_SPHERES spheres are loaded in one round before the sphere loop, so
+// that a sphere without items costs no round trip of its own.
+constexpr uint32_t BOUND_SPHERES = 6;
+
+template <bool SINGLES, bool FACETS, bool FIXED, bool AHEAD, bool REMAP, bool GAP = false, bool BOUNDS = false>
 __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, const uint32_t *start,
     const uint32_t *jarr, const uint32_t *bstart, const uint32_t *bidx, const uint32_t *bsrc, const uint8_t *oany,
     const uint8_t fl_fixed, const float *hx, const float *hy, const float *hz, const float *hw, const HistOut &ho,
@@ -737,9 +742,43 @@ __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, 
         float3 F = f3(0.f, 0.f, 0.f), T = f3(0.f, 0.f, 0.f);
         const uint32_t s0 = SINGLES ? (uint32_t)o : (any ? a.own_sph0[o] : 0u);
         const uint32_t s1 = SINGLES ? (uint32_t)o + 1u : (any ? a.own_sph0[o + 1] : 0u);
+        uint32_t sb[BOUNDS ? BOUND_SPHERES + 1 : 1], bb[BOUNDS ? BOUND_SPHERES + 1 : 1];
+        const bool pre = BOUNDS && any && s1 - s0 <= BOUND_SPHERES;
+        if constexpr (BOUNDS) {
+#pragma unroll
+            for (uint32_t k = 0; k <= BOUND_SPHERES; ++k) {
+                sb[k] = 0u;
+                bb[k] = 0u;
+                if (pre && k <= s1 - s0) {
+                    sb[k] = start[s0 + k];
+                    bb[k] = bstart[s0 + k];
+                }
+            }
+        }
         for (uint32_t s = s0; any && s < s1; ++s) {
-            const uint32_t c0 = start[s], na = start[s + 1] - c0;
-            const uint32_t b0 = bstart[s], nall = fixed ? na : na + (bstart[s + 1] - b0);
+            uint32_t c0, na, b0, nall;
+            if (pre) {
+                // (registers indexed by a loop counter: a short select chain)
+                uint32_t sa = sb[0], se = sb[1], ba = bb[0], be = bb[1];
+#pragma unroll
+                for (uint32_t k = 1; k < BOUND_SPHERES; ++k)
+                    if (s - s0 == k) {
+                        sa = sb[k];
+                        se = sb[k + 1];
+                        ba = bb[k];
+                        be = bb[k + 1];
+                    }
+                c0 = sa;
+                na = se - sa;
+                b0 = ba;
+                nall = fixed ? na : na + (be - ba);
+                if (nall == 0) continue;
+            } else {
+                c0 = start[s];
+                na = start[s + 1] - c0;
+                b0 = bstart[s];
+                nall = fixed ? na : na + (bstart[s + 1] - b0);
+            }
             // single spheres: the sphere's own record and kinematics come
             // from the owner record already loaded, once, as geometry A of
             // its row and geometry B of its B list (for clumps, whose
@@ -1296,8 +1335,8 @@ __global__ void __launch_bounds__(TPB, 3) k_step_listed(DynArgs a, const uint32_
             continue;
         }
         OwnerStep st;
-        owner_forces<false, FACETS, false, true, REMAP>(a, o, start, jarr, bstart, bidx, bsrc, oany, 0, hx, hy, hz,
-                                                        hw, ho, st);
+        owner_forces<false, FACETS, false, true, REMAP, false, true>(a, o, start, jarr, bstart, bidx, bsrc, oany, 0,
+                                                                     hx, hy, hz, hw, ho, st);
         if (st.advance) v2 = fmaxf(v2, owner_advance<false>(a, o, st, rec_out, q_out, ctr));
     }
     if (halt) return;
