@@ -416,17 +416,14 @@ __global__ void __launch_bounds__(TPB) k_detect(DetectArgs a, const uint32_t *ke
 }
 
 // Single traversal over the forward half of the bin stencil: each sphere
-// (thread, in bin order) tests only the candidates after itself in its own
-// bin and the 13 neighbour bins that follow its bin in key order -- bin
-// x+1, the three bins of row y+1, the nine bins of plane z+1 -- so each pair
-// of candidates is tested once.  The FP64 predicate is symmetric bit for
-// bit.  A pair found goes to the row of its lower id: the row's count is
-// claimed with an atomic and the first STAGE_K partners are staged (their
-// order is fixed later by sorting each row); the higher id's B-list count is
-// bumped.  Walls go to the sphere's own row.  `count` must be zero on entry.
-// Candidate loads are issued four at a time over the concatenation of the
-// five contiguous ranges, so each thread has several loads in flight.
-constexpr int DETECT_BATCH = 4;
+// (in bin order) tests only the candidates after itself in its own bin and
+// the 13 neighbour bins that follow its bin in key order -- bin x+1, the
+// three bins of row y+1, the nine bins of plane z+1 -- so each pair of
+// candidates is tested once.  The FP64 predicate is symmetric bit for bit.
+// A pair found goes to the row of its lower id: the row's count is claimed
+// with an atomic and the first STAGE_K partners are staged (their order is
+// fixed later by sorting each row); the higher id's B-list count is bumped.
+// Walls go to the sphere's own row.  `count` must be zero on entry.
 
 // The FP32 prefilter of the detection walk (bound derived in
 // k_detect_stage): true when candidate cj is farther from ci than the pair
@@ -493,64 +490,48 @@ __device__ inline bool wall_near(const WallDev &w, const double *p, const Grid &
     return d2 < T * T;
 }
 
-// Sphere p of the bin order (id vals[p]) against the candidates after it:
-// an FP32 prefilter, then (clump systems) the other sphere's id against the
-// sphere range of p's owner (spheres of one owner are consecutive and never
-// a contact), then the exact FP64 predicate on the candidates' exact
-// centres; walls are prefiltered the same way.  The exact centre of p, and
-// its owner, are loaded when a candidate first needs them.  Exact centres
-// come from the candidate records by sphere id (cand_id), so the binning
-// need not copy them into bin order.
+// Sphere p of the bin order (id vals[p]) against the candidates after it
+// in five contiguous ranges of the bin order (own bin after p and bin x+1;
+// row y+1; rows y-1, y, y+1 of plane z+1).  The 64 spheres of a wave share
+// one walk: their ranges are concatenated (a wave prefix sum of their
+// counts, the ranges and per-sphere data in the wave's LDS slice) and each
+// round every lane takes WALK_U candidates of the concatenation, finds the
+// sphere they belong to (a binary search over the counts' prefix sums) and
+// tests the pair, so a wave runs as long as its spheres' mean candidate
+// count, not its largest.  Per pair: an FP32 prefilter, then (clump
+// systems) the candidate's id against the sphere range of the sphere's
+// owner (spheres of one owner are consecutive and never a contact), then
+// the exact FP64 predicate on both exact centres, read by sphere id
+// (cand_id), so the binning need not copy them into bin order.  Walls are
+// prefiltered from the FP32 copy and each sphere's own lane tests them.
+constexpr int WALK_U = 4;
+
 __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32_t *keys, const uint32_t *vals,
                                                       const Cand *cand_id, const float4 *candf,
                                                       const uint32_t *cell_start, uint32_t *count, uint32_t *stage,
                                                       uint32_t *bcount)
 {
+    // per wave and lane: range starts, cumulative range ends, FP32 copy,
+    // its largest coordinate, sphere id, owner's sphere range, prefix of the
+    // candidate counts
+    __shared__ uint32_t l_ra[TPB / 64][5][64], l_ce[TPB / 64][5][64];
+    __shared__ float4 l_cif[TPB / 64][64];
+    __shared__ float l_mi[TPB / 64][64];
+    __shared__ uint32_t l_id[TPB / 64][64], l_s0[TPB / 64][64], l_s1[TPB / 64][64], l_ex[TPB / 64][64];
     const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (p >= a.n_spheres || p >= (int64_t)cell_start[a.grid.nbins]) return;   // (dormant spheres are not binned)
-    const float4 cif = candf[p];
-    const uint32_t i = vals[p];
-    const uint32_t key = keys[p];
-    const double ri = (double)cif.w;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    // (dormant spheres are not binned: they sit after the binned ones)
+    const bool valid = p < a.n_spheres && p < (int64_t)cell_start[a.grid.nbins];
     const double m = a.margin_dev ? *a.margin_dev : a.margin;
-    // the exact centre of p and its owner's sphere range, on first use
-    double xi = 0.0, yi = 0.0, zi = 0.0;
-    bool have_x = false;
-    auto exact = [&]() {
-        if (!have_x) {
-            const Cand ci = cand_id[i];
-            xi = ci.x;
-            yi = ci.y;
-            zi = ci.z;
-            have_x = true;
-        }
-    };
-    uint32_t own_i = 0xffffffffu, s0 = i, s1 = i + 1u;
-    auto owner = [&]() {
-        if (own_i == 0xffffffffu) {
-            own_i = a.sph[i].owner;
-            if (a.own_sph0) {
-                s0 = a.own_sph0[own_i];
-                s1 = a.own_sph0[own_i + 1];
-            }
-        }
-    };
-    // FP32 prefilter: a candidate is rejected only when its FP32 distance
-    // exceeds the pair threshold T by more than a bound on the rounding.
-    // Each FP32 coordinate is within 2^-24 |c| of the exact one (c: the
-    // coordinate relative to the grid origin), so each difference is within
-    // 2^-24 (M_i + M_j + |dx|) (M: largest coordinate magnitude of a sphere)
-    // and the distance within sqrt(3) times that; the squares, sums and T
-    // itself add a few 2^-24 relative.  The slack 8 2^-24 (M_i + M_j) +
-    // 16 2^-24 T + 1e-12 m exceeds all of it, so no true pair is rejected;
-    // the exact FP64 predicate decides the rest.
-    const float twom = (float)(2.0 * m);
-    const float Mi = fmaxf(fabsf(cif.x), fmaxf(fabsf(cif.y), fabsf(cif.z)));
     const uint32_t nx = (uint32_t)a.grid.nx, nxy = (uint32_t)a.grid.nx * (uint32_t)a.grid.ny;
-    // five contiguous candidate ranges: own bin after p + bin x+1; row y+1;
-    // the rows y-1, y, y+1 of plane z+1
-    uint32_t ra[5], rl[5];
-    {
+    float4 cif = make_float4(0.f, 0.f, 0.f, 0.f);
+    uint32_t i = 0, key = 0, total = 0, s0 = 0, s1 = 0;
+    uint32_t ra[5] = {0u, 0u, 0u, 0u, 0u}, rl[5] = {0u, 0u, 0u, 0u, 0u};
+    if (valid) {
+        cif = candf[p];
+        i = vals[p];
+        key = keys[p];
         const uint32_t e0 = cell_start[key + 2];
         ra[0] = (uint32_t)p + 1u;
         rl[0] = e0 - ra[0];
@@ -563,55 +544,125 @@ __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32
             ra[2 + t] = cell_start[row - 1];
             rl[2 + t] = cell_start[row + 2] - ra[2 + t];
         }
+        total = (rl[0] + rl[1]) + (rl[2] + rl[3] + rl[4]);
+        s0 = i;
+        s1 = i + 1u;
+        if (a.own_sph0 && total > 0) {
+            const uint32_t own = a.sph[i].owner;
+            s0 = a.own_sph0[own];
+            s1 = a.own_sph0[own + 1];
+        }
     }
-    const uint32_t total = (rl[0] + rl[1]) + (rl[2] + rl[3] + rl[4]);
-    for (uint32_t v0 = 0; v0 < total; v0 += DETECT_BATCH) {
-        float4 cb[DETECT_BATCH];
-        uint32_t qb[DETECT_BATCH], jb[DETECT_BATCH];
+    // the concatenation: exclusive prefix of the counts over the wave
+    uint32_t inc = total;
 #pragma unroll
-        for (int u = 0; u < DETECT_BATCH; ++u) {
-            uint32_t v = v0 + (uint32_t)u;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_up((int)inc, d, 64);
+        if ((int)lane >= d) inc += t;
+    }
+    const uint32_t T = (uint32_t)__shfl((int)inc, 63, 64);
+    {
+        uint32_t ce = 0u;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            ce += rl[k];
+            l_ra[wv][k][lane] = ra[k];
+            l_ce[wv][k][lane] = ce;
+        }
+        l_cif[wv][lane] = cif;
+        l_mi[wv][lane] = fmaxf(fabsf(cif.x), fmaxf(fabsf(cif.y), fabsf(cif.z)));
+        l_id[wv][lane] = i;
+        l_s0[wv][lane] = s0;
+        l_s1[wv][lane] = s1;
+        l_ex[wv][lane] = inc - total;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // FP32 prefilter: a candidate is rejected only when its FP32 distance
+    // exceeds the pair threshold T by more than a bound on the rounding.
+    // Each FP32 coordinate is within 2^-24 |c| of the exact one (c: the
+    // coordinate relative to the grid origin), so each difference is within
+    // 2^-24 (M_i + M_j + |dx|) (M: largest coordinate magnitude of a sphere)
+    // and the distance within sqrt(3) times that; the squares, sums and T
+    // itself add a few 2^-24 relative.  The slack 8 2^-24 (M_i + M_j) +
+    // 16 2^-24 T + 1e-12 m exceeds all of it, so no true pair is rejected;
+    // the exact FP64 predicate decides the rest.
+    const float twom = (float)(2.0 * m);
+    for (uint32_t base = 0; base < T; base += 64u * WALK_U) {
+        uint32_t qb[WALK_U], jb[WALK_U], ob[WALK_U];
+        float4 cb[WALK_U];
+#pragma unroll
+        for (int u = 0; u < WALK_U; ++u) {
+            const uint32_t g = base + (uint32_t)u * 64u + lane;
             qb[u] = 0xffffffffu;
-            if (v < total) {
-                int r = 0;
+            ob[u] = 0u;
+            if (g < T) {
+                // the sphere of candidate g: the last lane whose prefix is <= g
+                uint32_t lo = 0u, hi = 63u;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi + 1u) >> 1;
+                    if (l_ex[wv][mid] <= g) lo = mid;
+                    else hi = mid - 1u;
+                }
+                const uint32_t v = g - l_ex[wv][lo];
+                uint32_t r = 0u, before = 0u;
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (r == k && v >= rl[k]) {
-                        v -= rl[k];
-                        r = k + 1;
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t e = l_ce[wv][k][lo];
+                    if (v >= e) {
+                        r = (uint32_t)k + 1u;
+                        before = e;
                     }
-                qb[u] = ra[r] + v;
+                }
+                qb[u] = l_ra[wv][r][lo] + (v - before);
+                ob[u] = lo;
                 cb[u] = candf[qb[u]];
                 jb[u] = vals[qb[u]];
             }
         }
 #pragma unroll
-        for (int u = 0; u < DETECT_BATCH; ++u) {
-            if (qb[u] == 0xffffffffu) break;
-            const float dxf = cif.x - cb[u].x, dyf = cif.y - cb[u].y, dzf = cif.z - cb[u].z;
+        for (int u = 0; u < WALK_U; ++u) {
+            if (qb[u] == 0xffffffffu) continue;
+            const uint32_t o = ob[u];
+            const float4 ci = l_cif[wv][o];
+            const float dxf = ci.x - cb[u].x, dyf = ci.y - cb[u].y, dzf = ci.z - cb[u].z;
             const float Mj = fmaxf(fabsf(cb[u].x), fmaxf(fabsf(cb[u].y), fabsf(cb[u].z)));
-            const float T32 = (cif.w + cb[u].w) + twom;
-            const float tf = T32 + ((4.77e-7f * (Mi + Mj) + 9.54e-7f * T32) + 1e-12f);
+            const float T32 = (ci.w + cb[u].w) + twom;
+            const float tf = T32 + ((4.77e-7f * (l_mi[wv][o] + Mj) + 9.54e-7f * T32) + 1e-12f);
             if ((dxf * dxf + dyf * dyf) + dzf * dzf > tf * tf) continue;
             const uint32_t j = jb[u];
-            if (a.own_sph0) {
-                // (two spheres of one clump: never a contact)
-                owner();
-                if (j >= s0 && j < s1) continue;
-            }
-            exact();
+            // (two spheres of one clump: never a contact)
+            if (a.own_sph0 && j >= l_s0[wv][o] && j < l_s1[wv][o]) continue;
+            const uint32_t io = l_id[wv][o];
+            const Cand c0 = cand_id[io];
             const Cand cj = cand_id[j];
-            if (!sphere_pair_hit(xi, yi, zi, ri, cj, m)) continue;
-            if (a.pairoff) {
-                owner();
-                if (!fam_on(a, a.ofam[own_i], a.ofam[a.sph[j].owner])) continue;
-            }
-            const uint32_t lo = i < j ? i : j, hi = i < j ? j : i;
+            if (!sphere_pair_hit(c0.x, c0.y, c0.z, (double)ci.w, cj, m)) continue;
+            if (a.pairoff && !fam_on(a, a.ofam[a.sph[io].owner], a.ofam[a.sph[j].owner])) continue;
+            const uint32_t lo = io < j ? io : j, hi = io < j ? j : io;
             const uint32_t slot = atomicAdd(&count[lo], 1u);
             if (slot < (uint32_t)STAGE_K) stage[(size_t)lo * STAGE_K + slot] = hi;
             if (bcount) atomicAdd(&bcount[hi], 1u);
         }
     }
+    if (!valid) return;
+    // the sphere's own pairs with dormant spheres and walls
+    const double ri = (double)cif.w;
+    double xi = 0.0, yi = 0.0, zi = 0.0;
+    bool have_x = false;
+    auto exact = [&]() {
+        if (!have_x) {
+            const Cand ci = cand_id[i];
+            xi = ci.x;
+            yi = ci.y;
+            zi = ci.z;
+            have_x = true;
+        }
+    };
+    uint32_t own_i = 0xffffffffu;
+    auto owner = [&]() {
+        if (own_i == 0xffffffffu) own_i = a.sph[i].owner;
+    };
     if (a.famdormant) {
         owner();
         exact();
