@@ -101,7 +101,9 @@ def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, roll
       sphere the row and B-list offsets (8); per active sphere the A-side sums
       (24); per contact the B-list entry (4) and the reaction (24).
     detect: per sphere record + owner record (64), key/id (8) and candidate
-      (32) written, radix passes (16 each), candidate gather (36 r + 32 w),
+      (32) written, radix passes (16 each), candidate gather (36 r + 16 w
+      for the FP32 copy, + 32 w for the FP64 record in bin order with
+      meshes),
       one traversal reading 32 B of candidates per neighbour-row hit, row
       count and offsets (8), staging (4 per partner), B lists (16); per
       contact partner id (4) and B-list bytes (16); the bin table (12 per bin);
@@ -122,7 +124,8 @@ def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, roll
     if stage == "k_fold_integrate":
         return No * (116 if clumps else 100) + Ns * 8 + active * 24 + C * 28
     if stage == "detect":
-        return (Ns - n_dormant_sph) * (64 + 8 + 32 + 16 * passes + 68 + 32 + 8 + 16) + C * 24 + nbins * 12 + n_tri * 232
+        gather = 36 + 16 + (32 if n_tri > 0 else 0)
+        return (Ns - n_dormant_sph) * (64 + 8 + 32 + 16 * passes + gather + 32 + 8 + 16) + C * 24 + nbins * 12 + n_tri * 232
     if stage == "k_remap":
         return Ns * 16 + C * 32
     raise ValueError(stage)
