@@ -120,6 +120,7 @@ struct dem_ctx {
     OwnerAux *d_aux = nullptr;
     float *d_inv_i = nullptr;
     uint32_t *d_sph0 = nullptr;
+    uint2 *d_sph_range = nullptr;   // [Ns] owner's sphere range of each sphere (clump systems)
     SphRec *d_sph = nullptr;
     float *d_tpos = nullptr;
     WallDev *d_walls = nullptr;
@@ -280,6 +281,7 @@ void carve(Carver &c, dem_ctx *ctx, int64_t cap)
     ctx->d_aux = c.take<OwnerAux>(No);
     ctx->d_inv_i = c.take<float>(No);
     ctx->d_sph0 = c.take<uint32_t>(No + 1);
+    ctx->d_sph_range = c.take<uint2>(ctx->has_clumps ? Ns : 0);
     ctx->d_sph = c.take<SphRec>(Ns);
     ctx->d_tpos = c.take<float>(4 * std::max(ctx->ncomp, 1));
     ctx->d_walls = c.take<WallDev>(std::max(ctx->W, 1));
@@ -407,6 +409,7 @@ DetectArgs detect_args(const dem_ctx *ctx, double margin, int64_t step)
     a.margin = margin;
     a.margin_dev = nullptr;
     a.own_sph0 = ctx->has_clumps ? ctx->d_sph0 : nullptr;
+    a.sph_range = ctx->has_clumps ? ctx->d_sph_range : nullptr;
     a.n_owners = ctx->No;
     a.h = ctx->P.dt;
     a.step = step;
@@ -1020,6 +1023,12 @@ dem_status dem_bind(dem_ctx *ctx, void *device_workspace, int64_t bytes, int64_t
         HIPCHK(hipMemcpy(ctx->d_inv_i, inv_i.data(), sizeof(float) * ctx->No, hipMemcpyHostToDevice));
     }
     HIPCHK(hipMemcpy(ctx->d_sph0, ctx->sph0.data(), sizeof(uint32_t) * (ctx->No + 1), hipMemcpyHostToDevice));
+    if (ctx->has_clumps) {
+        std::vector<uint2> rng(ctx->Ns);
+        for (int64_t o = 0; o < ctx->No; ++o)
+            for (uint32_t q = ctx->sph0[o]; q < ctx->sph0[o + 1]; ++q) rng[q] = make_uint2(ctx->sph0[o], ctx->sph0[o + 1]);
+        HIPCHK(hipMemcpy(ctx->d_sph_range, rng.data(), sizeof(uint2) * ctx->Ns, hipMemcpyHostToDevice));
+    }
     {
         // volume of each owner's spheres, 4/3 pi r^3 summed in FP64 (overlaps
         // of a clump's spheres counted twice), stored as float

@@ -396,7 +396,7 @@ __global__ void __launch_bounds__(TPB) k_detect(DetectArgs a, const uint32_t *ke
         }
     }
     for (int w = 0; w < a.n_walls; ++w) {
-        WallDev wd = a.walls[w];
+        const WallDev wd = wall_at(a.walls, w);
         double pw[3];
         wall_point(wd, a.step, a.h, pw);
         if (!wall_hit(wd, pw, xi, yi, zi, ri, m)) continue;
@@ -494,34 +494,51 @@ __device__ inline bool wall_near(const WallDev &w, const double *p, const Grid &
 // in five contiguous ranges of the bin order (own bin after p and bin x+1;
 // row y+1; rows y-1, y, y+1 of plane z+1).  The 64 spheres of a wave share
 // one walk: their ranges are concatenated (a wave prefix sum of their
-// counts, the ranges and per-sphere data in the wave's LDS slice) and each
-// round every lane takes WALK_U candidates of the concatenation, finds the
-// sphere they belong to (a binary search over the counts' prefix sums) and
-// tests the pair, so a wave runs as long as its spheres' mean candidate
-// count, not its largest.  Per pair: an FP32 prefilter, then (clump
-// systems) the candidate's id against the sphere range of the sphere's
-// owner (spheres of one owner are consecutive and never a contact), then
-// the exact FP64 predicate on both exact centres, read by sphere id
-// (cand_id), so the binning need not copy them into bin order.  Walls are
-// prefiltered from the FP32 copy and each sphere's own lane tests them.
+// counts; per sphere, in the wave's LDS slice, where each range ends in the
+// concatenation and the offset that turns a concatenation index of the
+// range into its bin-order position), and each round the wave takes the
+// next 64 WALK_U candidates of the concatenation, one per lane and block of
+// 64.  The sphere of a candidate is found without a search: each sphere
+// whose candidates start in the round marks that slot (a byte per slot in
+// LDS), and a lane takes the last mark at or before its slot (a ballot of
+// the marked slots) or, with none, the sphere of the block's previous
+// slot; so a wave runs as long as its spheres' mean candidate count, not
+// its largest.  Per pair: an FP32 prefilter, then (clump systems) the
+// candidate's id against the sphere range of the sphere's owner (spheres of
+// one owner are consecutive and never a contact), then the exact FP64
+// predicate on both exact centres, read by sphere id (cand_id), so the
+// binning need not copy them into bin order.  Walls are prefiltered from
+// the FP32 copy and each sphere's own lane tests them.
 constexpr int WALK_U = 4;
+
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32_t *keys, const uint32_t *vals,
                                                       const Cand *cand_id, const float4 *candf,
                                                       const uint32_t *cell_start, uint32_t *count, uint32_t *stage,
                                                       uint32_t *bcount)
 {
-    // per wave and lane: range starts, cumulative range ends, FP32 copy,
-    // its largest coordinate, sphere id, owner's sphere range, prefix of the
-    // candidate counts
-    __shared__ uint32_t l_ra[TPB / 64][5][64], l_ce[TPB / 64][5][64];
+    // per wave and sphere lane: concatenation ends of ranges 0-3, position
+    // offsets of ranges 0-4, FP32 copy, {largest coordinate of the copy,
+    // owner's sphere range, sphere id}; per wave the start marks of a round
+    __shared__ uint4 l_end[TPB / 64][64];
+    __shared__ uint32_t l_off[TPB / 64][64 * 5];
     __shared__ float4 l_cif[TPB / 64][64];
-    __shared__ float l_mi[TPB / 64][64];
-    __shared__ uint32_t l_id[TPB / 64][64], l_s0[TPB / 64][64], l_s1[TPB / 64][64], l_ex[TPB / 64][64];
+    __shared__ uint4 l_aux[TPB / 64][64];
+    __shared__ uint32_t l_mark[TPB / 64][64 * WALK_U / 4];
     const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    // (dormant spheres are not binned: they sit after the binned ones)
+    // (dormant spheres are not binned: they sit after the binned ones; the
+    // sphere's own loads are issued, in bounds, before that is known)
+    const int64_t pc = p < a.n_spheres ? p : 0;
+    const float4 cif_p = candf[pc];
+    const uint32_t i_p = vals[pc], key_p = keys[pc];
     const bool valid = p < a.n_spheres && p < (int64_t)cell_start[a.grid.nbins];
     const double m = a.margin_dev ? *a.margin_dev : a.margin;
     const uint32_t nx = (uint32_t)a.grid.nx, nxy = (uint32_t)a.grid.nx * (uint32_t)a.grid.ny;
@@ -529,9 +546,15 @@ __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32
     uint32_t i = 0, key = 0, total = 0, s0 = 0, s1 = 0;
     uint32_t ra[5] = {0u, 0u, 0u, 0u, 0u}, rl[5] = {0u, 0u, 0u, 0u, 0u};
     if (valid) {
-        cif = candf[p];
-        i = vals[p];
-        key = keys[p];
+        cif = cif_p;
+        i = i_p;
+        key = key_p;
+        // (one load either way, so that it shares the round trip of the
+        // bin ranges: without clumps a re-read of the sphere's own copy)
+        const bool clumps = a.sph_range != nullptr;
+        const uint2 sr = *(clumps ? a.sph_range + i : reinterpret_cast<const uint2 *>(candf + pc));
+        s0 = clumps ? sr.x : i;
+        s1 = clumps ? sr.y : i + 1u;
         const uint32_t e0 = cell_start[key + 2];
         ra[0] = (uint32_t)p + 1u;
         rl[0] = e0 - ra[0];
@@ -545,13 +568,6 @@ __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32
             rl[2 + t] = cell_start[row + 2] - ra[2 + t];
         }
         total = (rl[0] + rl[1]) + (rl[2] + rl[3] + rl[4]);
-        s0 = i;
-        s1 = i + 1u;
-        if (a.own_sph0 && total > 0) {
-            const uint32_t own = a.sph[i].owner;
-            s0 = a.own_sph0[own];
-            s1 = a.own_sph0[own + 1];
-        }
     }
     // the concatenation: exclusive prefix of the counts over the wave
     uint32_t inc = total;
@@ -560,25 +576,24 @@ __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32
         const uint32_t t = (uint32_t)__shfl_up((int)inc, d, 64);
         if ((int)lane >= d) inc += t;
     }
-    const uint32_t T = (uint32_t)__shfl((int)inc, 63, 64);
+    const uint32_t T = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+    const uint32_t ex = inc - total;
     {
-        uint32_t ce = 0u;
+        // range k holds concatenation indices [c_k, c_k + rl[k]) and
+        // bin-order positions ra[k] + (index - c_k): offset ra[k] - c_k
+        // (modulo 2^32)
+        uint32_t c = ex, e[4];
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
-            ce += rl[k];
-            l_ra[wv][k][lane] = ra[k];
-            l_ce[wv][k][lane] = ce;
+            l_off[wv][5 * lane + k] = ra[k] - c;
+            c += rl[k];
+            if (k < 4) e[k] = c;
         }
+        l_end[wv][lane] = make_uint4(e[0], e[1], e[2], e[3]);
         l_cif[wv][lane] = cif;
-        l_mi[wv][lane] = fmaxf(fabsf(cif.x), fmaxf(fabsf(cif.y), fabsf(cif.z)));
-        l_id[wv][lane] = i;
-        l_s0[wv][lane] = s0;
-        l_s1[wv][lane] = s1;
-        l_ex[wv][lane] = inc - total;
+        l_aux[wv][lane] = make_uint4(__float_as_uint(fmaxf(fabsf(cif.x), fmaxf(fabsf(cif.y), fabsf(cif.z)))), s0,
+                                     s1, i);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // FP32 prefilter: a candidate is rejected only when its FP32 distance
     // exceeds the pair threshold T by more than a bound on the rounding.
     // Each FP32 coordinate is within 2^-24 |c| of the exact one (c: the
@@ -589,36 +604,39 @@ __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32
     // 16 2^-24 T + 1e-12 m exceeds all of it, so no true pair is rejected;
     // the exact FP64 predicate decides the rest.
     const float twom = (float)(2.0 * m);
+    const uint8_t *mark = reinterpret_cast<const uint8_t *>(l_mark[wv]);
+    uint32_t carry = 0u;   // the sphere of the last slot of the block before
     for (uint32_t base = 0; base < T; base += 64u * WALK_U) {
+        // start marks of the round (lane + 1; 0: no sphere starts here)
+        wave_sync();
+        l_mark[wv][lane] = 0u;
+        wave_sync();
+        if (total > 0u && ex >= base && ex - base < 64u * WALK_U)
+            reinterpret_cast<uint8_t *>(l_mark[wv])[ex - base] = (uint8_t)(lane + 1u);
+        wave_sync();
         uint32_t qb[WALK_U], jb[WALK_U], ob[WALK_U];
         float4 cb[WALK_U];
 #pragma unroll
         for (int u = 0; u < WALK_U; ++u) {
-            const uint32_t g = base + (uint32_t)u * 64u + lane;
+            const uint32_t g0 = base + (uint32_t)u * 64u;
+            const uint32_t g = g0 + lane;
             qb[u] = 0xffffffffu;
             ob[u] = 0u;
-            if (g < T) {
-                // the sphere of candidate g: the last lane whose prefix is <= g
-                uint32_t lo = 0u, hi = 63u;
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi + 1u) >> 1;
-                    if (l_ex[wv][mid] <= g) lo = mid;
-                    else hi = mid - 1u;
+            if (g0 < T) {
+                const uint32_t mk = mark[(uint32_t)u * 64u + lane];
+                const uint64_t below = __ballot(mk != 0u) & (~0ull >> (63u - lane));
+                uint32_t o = carry;
+                if (below != 0ull) o = (uint32_t)mark[(uint32_t)u * 64u + (uint32_t)(63 - __clzll((long long)below))] - 1u;
+                carry = (uint32_t)__builtin_amdgcn_readlane((int)o, 63);
+                if (g < T) {
+                    const uint4 e = l_end[wv][o];
+                    const uint32_t r = (uint32_t)(g >= e.x) + (uint32_t)(g >= e.y) + (uint32_t)(g >= e.z) +
+                                       (uint32_t)(g >= e.w);
+                    qb[u] = g + l_off[wv][5u * o + r];
+                    ob[u] = o;
+                    cb[u] = candf[qb[u]];
+                    jb[u] = vals[qb[u]];
                 }
-                const uint32_t v = g - l_ex[wv][lo];
-                uint32_t r = 0u, before = 0u;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const uint32_t e = l_ce[wv][k][lo];
-                    if (v >= e) {
-                        r = (uint32_t)k + 1u;
-                        before = e;
-                    }
-                }
-                qb[u] = l_ra[wv][r][lo] + (v - before);
-                ob[u] = lo;
-                cb[u] = candf[qb[u]];
-                jb[u] = vals[qb[u]];
             }
         }
 #pragma unroll
@@ -626,15 +644,16 @@ __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32
             if (qb[u] == 0xffffffffu) continue;
             const uint32_t o = ob[u];
             const float4 ci = l_cif[wv][o];
+            const uint4 ax = l_aux[wv][o];
             const float dxf = ci.x - cb[u].x, dyf = ci.y - cb[u].y, dzf = ci.z - cb[u].z;
             const float Mj = fmaxf(fabsf(cb[u].x), fmaxf(fabsf(cb[u].y), fabsf(cb[u].z)));
             const float T32 = (ci.w + cb[u].w) + twom;
-            const float tf = T32 + ((4.77e-7f * (l_mi[wv][o] + Mj) + 9.54e-7f * T32) + 1e-12f);
+            const float tf = T32 + ((4.77e-7f * (__uint_as_float(ax.x) + Mj) + 9.54e-7f * T32) + 1e-12f);
             if ((dxf * dxf + dyf * dyf) + dzf * dzf > tf * tf) continue;
             const uint32_t j = jb[u];
             // (two spheres of one clump: never a contact)
-            if (a.own_sph0 && j >= l_s0[wv][o] && j < l_s1[wv][o]) continue;
-            const uint32_t io = l_id[wv][o];
+            if (j >= ax.y && j < ax.z) continue;
+            const uint32_t io = ax.w;
             const Cand c0 = cand_id[io];
             const Cand cj = cand_id[j];
             if (!sphere_pair_hit(c0.x, c0.y, c0.z, (double)ci.w, cj, m)) continue;
@@ -674,7 +693,7 @@ __global__ void __launch_bounds__(TPB) k_detect_stage(DetectArgs a, const uint32
         });
     }
     for (int w = 0; w < a.n_walls; ++w) {
-        WallDev wd = a.walls[w];
+        const WallDev wd = wall_at(a.walls, w);
         double pw[3];
         wall_point(wd, a.step, a.h, pw);
         if (!wall_near(wd, pw, a.grid, cif, ri, m)) continue;
@@ -804,7 +823,7 @@ __global__ void __launch_bounds__(TPB) k_compact(DetectArgs a, const Cand *cand_
         });
     }
     for (int w = 0; w < a.n_walls; ++w) {
-        WallDev wd = a.walls[w];
+        const WallDev wd = wall_at(a.walls, w);
         double pw[3];
         wall_point(wd, a.step, a.h, pw);
         if (!wall_hit(wd, pw, xi, yi, zi, ri, m)) continue;

@@ -218,6 +218,20 @@ __device__ inline uint32_t bin_key(const Grid &g, const double *x)
     return ((uint32_t)cz * (uint32_t)g.ny + (uint32_t)cy) * (uint32_t)g.nx + (uint32_t)cx;
 }
 
+// Wall w of a launch's wall table, read through the constant address space:
+// the table is never written while a kernel runs, and with a uniform index
+// the read is a scalar load, not one vector memory round trip per wall
+// (a kernel that has stored to memory before its wall loop would otherwise
+// read the table with vector loads).
+__device__ inline WallDev wall_at(const WallDev *walls, int w)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return ((const __attribute__((address_space(4))) WallDev *)walls)[w];
+#else
+    return walls[w];   // (the host pass only parses device functions)
+#endif
+}
+
 __device__ inline void wall_point(const WallDev &w, int64_t step, double h, double *p)
 {
     double t = (double)step * h;

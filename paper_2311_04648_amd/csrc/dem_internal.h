@@ -178,6 +178,7 @@ struct DetectArgs {
     double margin;
     const double *margin_dev;   // if set, the margin is read from device memory
     const uint32_t *own_sph0;   // [No+1] first sphere of each owner (null: one sphere per owner)
+    const uint2 *sph_range;     // [Ns] per sphere its owner's sphere range (null with own_sph0)
     int64_t n_owners;
     double h;
     int64_t step;
