@@ -254,6 +254,7 @@ void carve_cd(Carver &c, const dem_ctx *ctx, CdWork &w)
     w.vals = c.take<uint32_t>(ns);
     w.keys_alt = c.take<uint32_t>(ns);
     w.vals_alt = c.take<uint32_t>(ns);
+    w.rank = c.take<uint32_t>(ns);
     w.cand_tmp = c.take<Cand>(ns);
     w.cand = c.take<Cand>(ns);
     w.candf = c.take<float4>(ns);
@@ -474,10 +475,12 @@ DynArgs dyn_args(const dem_ctx *ctx, int64_t step)
     a.wo_keys = nullptr;
     a.wo_cand = nullptr;
     a.wo_count = nullptr;
+    a.wo_rank = nullptr;
     if (ctx->wo_fused) {
         a.wo_keys = ctx->cdK.keys;
         a.wo_cand = ctx->cdK.cand_tmp;
         a.wo_count = ctx->cdK.cell_count;
+        a.wo_rank = ctx->cdK.rank;
     }
     a.dense_rows = 0;
     if (ctx->P.dyn_path == 2) {

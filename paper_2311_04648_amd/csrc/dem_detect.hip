@@ -43,7 +43,7 @@ __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > 
 
 
 __global__ void __launch_bounds__(TPB) k_cd_prepare(DetectArgs a, uint32_t *keys, uint32_t *vals,
-                                                    Cand *cand_tmp, uint32_t *cell_count)
+                                                    Cand *cand_tmp, uint32_t *cell_count, uint32_t *rank)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = i < a.n_spheres;
@@ -59,11 +59,12 @@ __global__ void __launch_bounds__(TPB) k_cd_prepare(DetectArgs a, uint32_t *keys
         sphere_centre(r, s, a.q, a.tpos, a.org, x);
         key = bin_key(a.grid, x);
     }
-    wave_run_claim(cell_count, key, active && !dorm);
+    const uint32_t rk = wave_run_claim(cell_count, key, active && !dorm);
     if (!active) return;
     keys[i] = key;
     if (vals) vals[i] = (uint32_t)i;   // ids to sort (the one-pass sort writes its own)
     if (dorm) return;
+    rank[i] = rk;
     Cand c;
     c.x = x[0];
     c.y = x[1];
@@ -75,18 +76,20 @@ __global__ void __launch_bounds__(TPB) k_cd_prepare(DetectArgs a, uint32_t *keys
 
 // One-pass sort of (bin key, sphere id): the per-bin counts and their scan
 // (the cell ranges) are the histogram and offsets of a single radix digit
-// as wide as the key; each sphere claims a slot of its bin with an atomic
-// cursor (one atomic per run of equal keys in a wave), and when asked each
-// bin then orders its few ids ascending, so the result is identical to a
-// stable sort.
-__global__ void __launch_bounds__(TPB) k_bucket_scatter(const uint32_t *keys_in, int64_t n, uint32_t nbins,
-                                                        uint32_t *cursor, uint32_t *keys_out, uint32_t *vals_out)
+// as wide as the key; each sphere's slot in its bin was claimed when the
+// bins were counted (one atomic per run of equal keys in a wave), so the
+// scatter writes each sphere at its bin's offset plus that slot, with no
+// atomics; when asked each bin then orders its few ids ascending, so the
+// result is identical to a stable sort.
+__global__ void __launch_bounds__(TPB) k_bucket_scatter(const uint32_t *keys_in, const uint32_t *rank, int64_t n,
+                                                        uint32_t nbins, const uint32_t *cell_start,
+                                                        uint32_t *keys_out, uint32_t *vals_out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t k = keys_in[i < n ? i : n - 1];
-    const bool active = i < n && k < nbins;   // (key nbins: a dormant sphere, not binned)
-    const uint32_t pos = wave_run_claim(cursor, k, active);
-    if (!active) return;
+    if (i >= n) return;
+    const uint32_t k = keys_in[i];
+    if (k >= nbins) return;   // (key nbins: a dormant sphere, not binned)
+    const uint32_t pos = cell_start[k] + rank[i];
     keys_out[pos] = k;
     vals_out[pos] = (uint32_t)i;
 }
@@ -1142,7 +1145,7 @@ void launch_bin_front(const DetectArgs &a, CdWork &w, hipStream_t s, uint32_t *z
     const int64_t n = a.n_spheres;
     launch_zero3(w.cell_count, (int64_t)a.grid.nbins + 1, z1, n1, z2, n2, s);
     hipLaunchKernelGGL(k_cd_prepare, dim3(nblocks(n)), dim3(TPB), 0, s, a, w.keys,
-                       w.sort_mode == 0 ? (uint32_t *)nullptr : w.vals, w.cand_tmp, w.cell_count);
+                       w.sort_mode == 0 ? (uint32_t *)nullptr : w.vals, w.cand_tmp, w.cell_count, w.rank);
 }
 
 // Rest of binning: cell ranges, sort by bin, candidates in bin order.
@@ -1158,10 +1161,11 @@ void launch_bin_back(const DetectArgs &a, CdWork &w, hipStream_t s, bool order_b
     int64_t n = a.n_spheres;
     const int64_t nb = (int64_t)a.grid.nbins;
     if (w.sort_mode == 0) {
-        // cell ranges, with a copy of the offsets as the per-bin cursor
-        scan_exclusive_u32(w.cell_count, w.cell_start, nb, w.partials, s, w.cell_count);
-        hipLaunchKernelGGL(k_bucket_scatter, dim3(nblocks(n)), dim3(TPB), 0, s, w.keys, n, a.grid.nbins,
-                           w.cell_count, w.keys_alt, w.vals_alt);
+        // cell ranges; each sphere then goes to its bin's offset plus its slot
+        scan_exclusive_u32(w.cell_count, w.cell_start, nb, w.partials, s);
+        hipLaunchKernelGGL(k_bucket_scatter, dim3(nblocks(n)), dim3(TPB), 0, s, (const uint32_t *)w.keys,
+                           (const uint32_t *)w.rank, n, a.grid.nbins, (const uint32_t *)w.cell_start, w.keys_alt,
+                           w.vals_alt);
         if (order_bins)
             hipLaunchKernelGGL(k_bucket_order, dim3(nblocks(nb)), dim3(TPB), 0, s, w.cell_start, nb, w.vals_alt);
         uint32_t *t = w.keys; w.keys = w.keys_alt; w.keys_alt = t;
@@ -1214,7 +1218,7 @@ inline unsigned facet_walk_blocks(const DetectArgs &a)
 void launch_detect_front(const DetectArgs &a, CdWork &w, AcsBuf &out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_cd_prepare, dim3(nblocks(a.n_spheres)), dim3(TPB), 0, s, a, w.keys,
-                       w.sort_mode == 0 ? (uint32_t *)nullptr : w.vals, w.cand_tmp, w.cell_count);
+                       w.sort_mode == 0 ? (uint32_t *)nullptr : w.vals, w.cand_tmp, w.cell_count, w.rank);
 }
 
 int64_t owner_list_tiles(int64_t no)

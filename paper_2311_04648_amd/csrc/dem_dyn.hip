@@ -957,8 +957,9 @@ __device__ __forceinline__ void halt_owner(const DynArgs &a, const int64_t o, Ow
 
 // The work order's first binning step for owner o (= sphere o in single-
 // sphere runs) from the state r the step reads: bin key, candidate record,
-// and the bin counts (one claim per run of equal keys in the wave, so every
-// lane of the wave calls it).  The arithmetic of k_cd_prepare.
+// and the bin counts with the sphere's slot among its bin's spheres (one
+// claim per run of equal keys in the wave, so every lane of the wave calls
+// it).  The arithmetic of k_cd_prepare.
 __device__ __forceinline__ void wo_front(const DynArgs &a, const int64_t o, const bool valid, const OwnerRec &r,
                                          const SphRec &sp)
 {
@@ -968,9 +969,10 @@ __device__ __forceinline__ void wo_front(const DynArgs &a, const int64_t o, cons
         sphere_centre(r, sp, a.q, a.tpos, a.org, x);
         key = bin_key(a.wo_grid, x);
     }
-    wave_run_claim(a.wo_count, key, valid);
+    const uint32_t rank = wave_run_claim(a.wo_count, key, valid);
     if (valid) {
         a.wo_keys[o] = key;
+        a.wo_rank[o] = rank;
         Cand c;
         c.x = x[0];
         c.y = x[1];

@@ -202,6 +202,7 @@ struct DetectArgs {
 
 struct CdWork {
     uint32_t *keys, *vals, *keys_alt, *vals_alt;   // sorted result lands in keys/vals
+    uint32_t *rank;        // [Ns] each binned sphere's slot among its bin's spheres (from the counting)
     Cand *cand_tmp, *cand;
     float4 *candf;         // [Ns] bin order: FP32 centre relative to the grid origin, radius
     uint32_t *cell_count, *cell_start;
@@ -320,11 +321,13 @@ struct DynArgs {
     // a work order whose first binning step rides on this step (single-
     // sphere runs without fixed families): from the state it reads, the
     // step also writes each sphere's bin key and candidate record and
-    // counts the bins, as k_cd_prepare would; wo_keys null: no such order
+    // counts the bins (each sphere's slot in its bin kept), as k_cd_prepare
+    // would; wo_keys null: no such order
     Grid wo_grid;
     uint32_t *wo_keys;
     Cand *wo_cand;
     uint32_t *wo_count;
+    uint32_t *wo_rank;
     int32_t dense_rows;     // the last contact count read back was at least one per two spheres: the
                             // fused step stages its history writes in LDS (a choice of speed only:
                             // both variants give the same bits)
