@@ -72,6 +72,7 @@ struct dem_ctx {
     std::vector<uint32_t> sph0;
     std::vector<SphRec> sph;
     std::vector<float> tpos;
+    float arm = 0.0f;   // largest |template position| (rounded up)
     std::vector<WallDev> walls;
     std::vector<MatPair> mat;
     std::vector<float> mass;
@@ -315,7 +316,7 @@ void carve(Carver &c, dem_ctx *ctx, int64_t cap)
         a.oany = c.take<uint8_t>(No);
         a.olist = c.take<uint32_t>(No);
         a.otile = c.take<uint32_t>(owner_list_tiles(No) + 1);
-        a.gk = ctx->has_clumps ? nullptr : c.take<float>(cap);
+        a.gk = c.take<float>(cap);
     }
     ctx->d_gvs = c.take<float>(3 * 64 * 16);
     ctx->d_gD = c.take<double>(2);
@@ -498,15 +499,22 @@ DynArgs dyn_args(const dem_ctx *ctx, int64_t step)
     a.gvs = ctx->d_gvs;
     a.gD = ctx->d_gD;
     a.vgeom = std::max(ctx->vmesh, ctx->vwall);
+    a.arm = ctx->arm;
     return a;
 }
 
-// Single-sphere systems without fixed families skip the pairs of a dense
-// set that are proven apart (the step kernels' staged variant)
+// Systems without fixed families skip the pairs proven apart: single
+// spheres in the one-kernel step over a dense set (its staged variant),
+// clumps in the split step
 static bool pair_skip_allowed(const dem_ctx *ctx, const DynArgs &a)
 {
     return !ctx->P.no_pair_skip && !ctx->has_clumps && !ctx->has_fixed && a.dense_rows && a.gk &&
            ctx->P.dyn_path != 1;
+}
+
+static bool pair_skip_split_allowed(const dem_ctx *ctx, const DynArgs &a)
+{
+    return !ctx->P.no_pair_skip && ctx->has_clumps && !ctx->has_fixed && a.gk;
 }
 
 inline hipStream_t S(dem_stream s) { return reinterpret_cast<hipStream_t>(s); }
@@ -773,6 +781,15 @@ dem_status dem_create(const dem_params *params, const dem_materials *mats, const
                 if ((double)f != v) return fail("template positions must be float32-representable");
                 ctx->tpos[4 * k + d] = f;
             }
+        // (FP64 norms of FP32 positions, rounded up to FP32)
+        double am = 0.0;
+        for (int k = 0; k < ctx->ncomp; ++k) {
+            const double x = ctx->tpos[4 * k], y = ctx->tpos[4 * k + 1], z = ctx->tpos[4 * k + 2];
+            am = std::max(am, std::sqrt(x * x + y * y + z * z));
+        }
+        float af = (float)am;
+        if ((double)af < am) af = std::nextafter(af, 1.0f);
+        ctx->arm = af;
     } else {
         ctx->tpos.assign(4, 0.0f);
     }
@@ -1875,7 +1892,10 @@ dem_status dem_step(dem_ctx *ctx, int64_t n_steps, dem_stream dyn_, dem_stream k
             // each, every `timing`-th step, each pair followed by an empty
             // kernel bracketed the same way (the markers' own overhead)
             run_close(ctx, dyn);
-            gap_next = -1;
+            const bool gap = pair_skip_split_allowed(ctx, a);
+            if (gap) a.gap = (gap_next == n && gap_epoch == ctx->adopt_epoch && !a.rm_start) ? 2 : 1;
+            gap_next = gap ? n + 1 : -1;
+            gap_epoch = ctx->adopt_epoch;
             SplitTiming tm{};
             dem_ctx::TimedPair *t1 = stage_slot(ctx, 1), *t0 = t1 ? stage_slot(ctx, 0) : nullptr;
             if (t1 && t0) tm = SplitTiming{t1->a, t1->b, t0->a, t0->b};

@@ -681,6 +681,17 @@ __device__ inline double gap_reach(const DynArgs &a)
     return a.gD[(a.step + 1) & 1] + a.h * (2.0 * v + a.vgeom) + GAP_STEP_SLACK;
 }
 
+// The speed bound of an integrated owner for the reach: |v| + |w| arm
+// (arm 0 for single spheres), squared, with a relative allowance of 1e-6
+// for its FP32 rounding.
+__device__ inline float reach_speed2(const OwnerRec &r, float arm)
+{
+    const float v = sqrtf((r.v[0] * r.v[0] + r.v[1] * r.v[1]) + r.v[2] * r.v[2]);
+    const float w = sqrtf((r.w[0] * r.w[0] + r.w[1] * r.w[1]) + r.w[2] * r.w[2]);
+    const float sp = (v + w * arm) * 1.000001f;
+    return sp * sp;
+}
+
 // The key of a pair evaluated at reach D with gap g: (g - slack) + D
 // rounded down to FP32; a pair that touches or nearly does gets a key no
 // reach can pass.
@@ -710,7 +721,7 @@ __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, 
     const uint8_t fl_fixed, const float *hx, const float *hy, const float *hz, const float *hw, const HistOut &ho,
     OwnerStep &st, const OwnerRec *pre = nullptr, const double Dn = 0.0)
 {
-    static_assert(!GAP || (SINGLES && !FIXED), "pair skipping is for single spheres without fixed families");
+    static_assert(!GAP || !FIXED, "pair skipping is for systems without fixed families");
     st.advance = false;
     // The owner's flag byte, written with the set (bit 0: the owner has a
     // contact in it; bit 1: the owner is in a fixed family), read by the
@@ -855,7 +866,8 @@ __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, 
                         OwnerKin kA;
                         double xA[3];
                         owner_kin(rA, sA, a.aux, a.q, a.tpos, a.org, kA, xA);
-                        contact_eval<FACETS>(a, sA, kA, xA, jp, hin(c, iA, jp), co);
+                        contact_eval<FACETS, false, false, GAP>(a, sA, kA, xA, jp, hin(c, iA, jp), co);
+                        if (GAP && aside && a.gap != 0) a.gk[c] = gap_key(co.gap, Dn);
                     }
                 }
                 if (aside) {
@@ -1212,7 +1224,15 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, OwnerR
             a.blkmax[gridDim.x] = 0.0f;   // the second kernel's blocks take their maximum here
         }
     }
-    float v2 = 0.0f;
+    // pair skipping: the launch's first wave records the step's reach and
+    // clears the speed slots the next step fills (the second kernel of the
+    // step computes the same reach for itself)
+    if (!halt && a.gap != 0 && lb == 0 && wv == 0) {
+        const double Dn = gap_reach(a);
+        if (lane == 0) a.gD[a.step & 1] = Dn;
+        *gap_slot(a, a.step + 1, lane) = 0.0f;
+    }
+    float v2 = 0.0f, g2 = 0.0f;
     uint8_t fl[FREE_CHUNKS];
     uint32_t nv[FREE_CHUNKS];
     // loads: flags and the records (through LDS) of every chunk
@@ -1275,6 +1295,7 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, OwnerR
             const float inv[3] = {ax[c].inv_moi[0], ax[c].inv_moi[1], ax[c].inv_moi[2]};
             v2 = fmaxf(v2, advance(a, r[c], inv, rot, f3(0.f, 0.f, 0.f), f3(0.f, 0.f, 0.f), qv[c],
                                    rot ? qo : nullptr, ctr));
+            if (a.gap != 0) g2 = fmaxf(g2, reach_speed2(r[c], a.arm));
             // after this step both buffers hold the orientation if the
             // owner did not turn in it
             if (r[c].w[0] == 0.0f && r[c].w[1] == 0.0f && r[c].w[2] == 0.0f) r[c].vox |= DEM_VOX_QSAME;
@@ -1293,15 +1314,28 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, OwnerR
         for (uint32_t k = lane; k < 3u * nv[c]; k += 64u) dst[k] = wbuf[wv][c][k];
     }
     if (halt) return;
-    __shared__ float wmax[FREE_WAVES];
+    __shared__ float wmax[2][FREE_WAVES];
     if (!(v2 == v2)) v2 = 3.0e38f;
-    for (int d = 32; d > 0; d >>= 1) v2 = fmaxf(v2, __shfl_xor(v2, d, 64));
-    if (lane == 0) wmax[wv] = v2;
+    if (!(g2 == g2)) g2 = 3.0e38f;
+    for (int d = 32; d > 0; d >>= 1) {
+        v2 = fmaxf(v2, __shfl_xor(v2, d, 64));
+        g2 = fmaxf(g2, __shfl_xor(g2, d, 64));
+    }
+    if (lane == 0) {
+        wmax[0][wv] = v2;
+        wmax[1][wv] = g2;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        float m = wmax[0];
-        for (int k = 1; k < FREE_WAVES; ++k) m = fmaxf(m, wmax[k]);
+        float m = wmax[0][0], mg = wmax[1][0];
+        for (int k = 1; k < FREE_WAVES; ++k) {
+            m = fmaxf(m, wmax[0][k]);
+            mg = fmaxf(mg, wmax[1][k]);
+        }
         a.blkmax[lb] = m;
+        // pair skipping: the block's speed bound into one of the step's
+        // speed slots (non-negative floats order as their bits)
+        if (a.gap != 0) atomicMax(reinterpret_cast<unsigned *>(gap_slot(a, a.step, lb)), __float_as_uint(mg));
     }
 }
 
@@ -1313,7 +1347,7 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, OwnerR
 // bits of non-negative floats, one per block).
 constexpr unsigned LISTED_BLOCKS = 1024;
 
-template <bool FACETS, bool REMAP>
+template <bool FACETS, bool REMAP, bool GAP>
 __global__ void __launch_bounds__(TPB, 3) k_step_listed(DynArgs a, const uint32_t *olist, const uint32_t *ocount,
                                                        OwnerRec *rec_out, double *q_out, const uint32_t *start,
                                                        const uint32_t *jarr, const uint32_t *bstart,
@@ -1328,7 +1362,10 @@ __global__ void __launch_bounds__(TPB, 3) k_step_listed(DynArgs a, const uint32_
     const int64_t n = (int64_t)*ocount;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const HistOut ho{ox, oy, oz, ow, nullptr, 0u};
-    float v2 = 0.0f;
+    // pair skipping: the step's reach (the first kernel of the step records
+    // the same value); every lane of the wave takes part
+    const double Dn = GAP && !halt ? gap_reach(a) : 0.0;
+    float v2 = 0.0f, g2 = 0.0f;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const int64_t o = (int64_t)olist[i];
         if (halt) {
@@ -1337,20 +1374,34 @@ __global__ void __launch_bounds__(TPB, 3) k_step_listed(DynArgs a, const uint32_
             continue;
         }
         OwnerStep st;
-        owner_forces<false, FACETS, false, true, REMAP, false, true>(a, o, start, jarr, bstart, bidx, bsrc, oany, 0,
-                                                                     hx, hy, hz, hw, ho, st);
-        if (st.advance) v2 = fmaxf(v2, owner_advance<false>(a, o, st, rec_out, q_out, ctr));
+        owner_forces<false, FACETS, false, true, REMAP, GAP, true>(a, o, start, jarr, bstart, bidx, bsrc, oany, 0,
+                                                                   hx, hy, hz, hw, ho, st, nullptr, Dn);
+        if (st.advance) {
+            v2 = fmaxf(v2, owner_advance<false>(a, o, st, rec_out, q_out, ctr));
+            if (GAP) g2 = fmaxf(g2, reach_speed2(st.r, a.arm));
+        }
     }
     if (halt) return;
-    __shared__ float wmax[TPB / 64];
+    __shared__ float wmax[2][TPB / 64];
     if (!(v2 == v2)) v2 = 3.0e38f;
-    for (int d = 32; d > 0; d >>= 1) v2 = fmaxf(v2, __shfl_xor(v2, d, 64));
-    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v2;
+    if (!(g2 == g2)) g2 = 3.0e38f;
+    for (int d = 32; d > 0; d >>= 1) {
+        v2 = fmaxf(v2, __shfl_xor(v2, d, 64));
+        g2 = fmaxf(g2, __shfl_xor(g2, d, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        wmax[0][threadIdx.x >> 6] = v2;
+        wmax[1][threadIdx.x >> 6] = g2;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        float m = wmax[0];
-        for (int k = 1; k < TPB / 64; ++k) m = fmaxf(m, wmax[k]);
+        float m = wmax[0][0], mg = wmax[1][0];
+        for (int k = 1; k < TPB / 64; ++k) {
+            m = fmaxf(m, wmax[0][k]);
+            mg = fmaxf(mg, wmax[1][k]);
+        }
         atomicMax(reinterpret_cast<unsigned int *>(a.blkmax + slot), __float_as_uint(m));
+        if (GAP) atomicMax(reinterpret_cast<unsigned *>(gap_slot(a, a.step, blockIdx.x)), __float_as_uint(mg));
     }
 }
 
@@ -1487,8 +1538,11 @@ bool launch_step_fused(const DynArgs &a, OwnerRec *rec_out, double *q_out, const
                            rec_out, q_out, (const uint8_t *)cur.oany, ctr);
         if (tm && tm->free1) hipEventRecord(tm->free1, s);
         if (tm && tm->list0) hipEventRecord(tm->list0, s);
-        auto kl = a.n_tri > 0 ? (r ? k_step_listed<true, true> : k_step_listed<true, false>)
-                              : (r ? k_step_listed<false, true> : k_step_listed<false, false>);
+        auto kl = a.gap != 0
+                      ? (a.n_tri > 0 ? (r ? k_step_listed<true, true, true> : k_step_listed<true, false, true>)
+                                     : (r ? k_step_listed<false, true, true> : k_step_listed<false, false, true>))
+                      : (a.n_tri > 0 ? (r ? k_step_listed<true, true, false> : k_step_listed<true, false, false>)
+                                     : (r ? k_step_listed<false, true, false> : k_step_listed<false, false, false>));
         const unsigned nl = std::min<unsigned>(nb, LISTED_BLOCKS);
         hipLaunchKernelGGL(kl, dim3(nl), dim3(TPB), 0, s, a, (const uint32_t *)cur.olist,
                            (const uint32_t *)(cur.otile + owner_list_tiles(a.n_owners)), rec_out, q_out,

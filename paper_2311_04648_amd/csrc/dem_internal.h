@@ -334,11 +334,14 @@ struct DynArgs {
     int32_t split;          // clump systems without fixed families: run the step as a streaming
                             // kernel over every owner plus a kernel over the set's owners with
                             // contacts (AcsBuf::olist); the same bits as the one-kernel step
-    // Pairs provably apart (single-sphere systems without fixed families).
+    // Pairs provably apart (systems without fixed families: single spheres
+    // in the one-kernel step, clumps in the split step).
     // A chain is a run of consecutive steps on one set; its reach D(n) bounds
     // how far any two surfaces can have closed in since the chain began:
     // D(first) = 0, D(n) = D(n-1) + h (2 v(n) + vgeom) + GAP_STEP_SLACK with
-    // v(n) the largest sphere speed the step before integrated.  Evaluating
+    // v(n) the largest sphere speed the step before integrated (for a clump
+    // sphere its owner's |v| + |w| arm: the step turns it by h |w|, which
+    // moves a sphere at most h |w| arm).  Evaluating
     // a pair, the step writes gk[c] = (its gap - GAP_PAIR_SLACK) + D(n),
     // rounded down; while gk[c] - D(n) > 0 the pair cannot touch, and the
     // step gives it what evaluating it would: no force, zero history.
@@ -346,9 +349,10 @@ struct DynArgs {
     // written), 2 a later step (pairs skipped by their keys).
     float *gk;
     int32_t gap;
-    float *gvs;             // [3][64] speed slots (max |v|^2 bits, one per 64 B), by step mod 3
+    float *gvs;             // [3][64] speed slots (max squared speed bits, one per 64 B), by step mod 3
     double *gD;             // [2] reach D by step parity
     double vgeom;           // fastest point of any wall or mesh
+    float arm;              // largest distance of a template sphere's centre from its owner's (0: none)
 };
 
 struct StepBufs {
