@@ -100,7 +100,8 @@ def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, roll
       else three values and the template (16) plus the sphere range (4); per
       sphere the row and B-list offsets (8); per active sphere the A-side sums
       (24); per contact the B-list entry (4) and the reaction (24).
-    detect: per sphere record + owner record (64), key/id (8) and candidate
+    detect: per sphere record + the owner record's hot part (48), key and
+      slot in its bin (8) and candidate
       (32) written, radix passes (16 each), candidate gather (36 r + 16 w
       for the FP32 copy, + 32 w for the FP64 record in bin order with
       meshes),
@@ -125,21 +126,23 @@ def algorithmic_bytes(stage, Ns, No, C, active, nbins, passes, clumps=True, roll
         return No * (116 if clumps else 100) + Ns * 8 + active * 24 + C * 28
     if stage == "detect":
         gather = 36 + 16 + (32 if n_tri > 0 else 0)
-        return (Ns - n_dormant_sph) * (64 + 8 + 32 + 16 * passes + gather + 32 + 8 + 16) + C * 24 + nbins * 12 + n_tri * 232
+        return (Ns - n_dormant_sph) * (48 + 8 + 32 + 16 * passes + gather + 32 + 8 + 16) + C * 24 + nbins * 12 + n_tri * 232
     if stage == "k_remap":
         return Ns * 16 + C * 32
     raise ValueError(stage)
 
 
 def stream_bytes(No, n_turn, n_spin=None):
-    """k_step_free: per owner its contact flag (1) and record read + written
-    (96); per turning owner (nonzero angular velocity) its inertia and
-    template (16), and per turning clump its orientation read + written
-    (64): an owner at rest in rotation keeps its orientation in both buffers
-    and needs neither (without n_spin every owner is counted with its
-    inertia).  Owners with contacts are counted here (their records are read
-    and written, then written again by k_step_listed)."""
-    return No * 97 + (No if n_spin is None else n_spin) * 16 + n_turn * 64
+    """k_step_free: per owner its contact flag (1) and the hot part of its
+    record (position, velocity) read + written (64); per turning owner
+    (nonzero angular velocity) the cold part of its record (angular
+    velocity, mass) read + written (32) and its inertia and template (16),
+    and per turning clump its orientation read + written (64): an owner at
+    rest in rotation keeps its angular velocity and orientation in both
+    buffers and needs none of them (without n_spin every owner is counted
+    as turning).  Owners with contacts are counted here (their hot parts are
+    read and written, then written again by k_step_listed)."""
+    return No * 65 + (No if n_spin is None else n_spin) * 48 + n_turn * 64
 
 
 def n_clump_share(sysm, rr):

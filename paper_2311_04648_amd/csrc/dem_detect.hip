@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(TPB) k_cd_prepare(DetectArgs a, uint32_t *keys
     uint32_t key = a.grid.nbins;
     double x[3] = {0.0, 0.0, 0.0};
     if (!dorm) {
-        OwnerRec r = load_rec(a.rec + s.owner);
+        const OwnerRec r = load_rec_hot(a.recs, s.owner);   // (the centre needs the hot part only)
         sphere_centre(r, s, a.q, a.tpos, a.org, x);
         key = bin_key(a.grid, x);
     }
@@ -780,7 +780,7 @@ __global__ void __launch_bounds__(TPB) k_compact(DetectArgs a, const Cand *cand_
     if (dorm_i) {
         const SphRec si = load_sph(a.sph + i);
         double x[3];
-        sphere_centre(load_rec(a.rec + own_i), si, a.q, a.tpos, a.org, x);
+        sphere_centre(load_rec_hot(a.recs, own_i), si, a.q, a.tpos, a.org, x);
         xi = x[0];
         yi = x[1];
         zi = x[2];
@@ -1085,7 +1085,7 @@ __global__ void __launch_bounds__(TPB) k_dorm_count(DetectArgs a, uint32_t *dkey
     uint32_t key = 0;
     if (dorm) {
         double x[3];
-        sphere_centre(load_rec(a.rec + s.owner), s, a.q, a.tpos, a.org, x);
+        sphere_centre(load_rec_hot(a.recs, s.owner), s, a.q, a.tpos, a.org, x);
         const int cx = bin_coord(x[0], a.grid.lo[0], a.grid.inv_b, a.grid.nx);
         const int cy = bin_coord(x[1], a.grid.lo[1], a.grid.inv_b, a.grid.ny);
         const int cz = bin_coord(x[2], a.grid.lo[2], a.grid.inv_b, a.grid.nz);
@@ -1109,7 +1109,7 @@ __global__ void __launch_bounds__(TPB) k_dorm_fill(DetectArgs a, const uint32_t 
     const uint32_t pos = wave_run_claim(dcursor, key, dorm);
     if (!dorm) return;
     double x[3];
-    sphere_centre(load_rec(a.rec + s.owner), s, a.q, a.tpos, a.org, x);
+    sphere_centre(load_rec_hot(a.recs, s.owner), s, a.q, a.tpos, a.org, x);
     Cand c;
     c.x = x[0];
     c.y = x[1];

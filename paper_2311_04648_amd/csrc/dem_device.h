@@ -130,11 +130,9 @@ __device__ inline float3 cross3(float3 a, float3 b)
     return f3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
 
-// Loads an owner record with three 16-byte loads.
-__device__ inline OwnerRec load_rec(const OwnerRec *p)
+// An owner record from its hot part (a, b) and cold part (c).
+__device__ inline OwnerRec rec_from(uint4 a, uint4 b, uint4 c)
 {
-    const uint4 *u = reinterpret_cast<const uint4 *>(p);
-    uint4 a = u[0], b = u[1], c = u[2];
     OwnerRec r;
     r.vox = (uint64_t)a.x | ((uint64_t)a.y << 32);
     r.off[0] = __uint_as_float(a.z);
@@ -150,15 +148,74 @@ __device__ inline OwnerRec load_rec(const OwnerRec *p)
     return r;
 }
 
-__device__ inline void store_rec(OwnerRec *p, const OwnerRec &r)
+__device__ inline uint4 rec_hot0(const OwnerRec &r)
 {
-    uint4 *u = reinterpret_cast<uint4 *>(p);
-    u[0] = make_uint4((uint32_t)r.vox, (uint32_t)(r.vox >> 32), __float_as_uint(r.off[0]),
-                      __float_as_uint(r.off[1]));
-    u[1] = make_uint4(__float_as_uint(r.off[2]), __float_as_uint(r.v[0]), __float_as_uint(r.v[1]),
+    return make_uint4((uint32_t)r.vox, (uint32_t)(r.vox >> 32), __float_as_uint(r.off[0]), __float_as_uint(r.off[1]));
+}
+
+__device__ inline uint4 rec_hot1(const OwnerRec &r)
+{
+    return make_uint4(__float_as_uint(r.off[2]), __float_as_uint(r.v[0]), __float_as_uint(r.v[1]),
                       __float_as_uint(r.v[2]));
-    u[2] = make_uint4(__float_as_uint(r.w[0]), __float_as_uint(r.w[1]), __float_as_uint(r.w[2]),
+}
+
+__device__ inline uint4 rec_cold(const OwnerRec &r)
+{
+    return make_uint4(__float_as_uint(r.w[0]), __float_as_uint(r.w[1]), __float_as_uint(r.w[2]),
                       __float_as_uint(r.mass));
+}
+
+// Owner o's record from the tiled storage (or from one tile staged in LDS,
+// o = the lane): three 16-byte loads.
+__device__ inline OwnerRec load_rec(const RecTile *t, int64_t o)
+{
+    const RecTile &T = t[o >> 6];
+    const uint32_t l = (uint32_t)o & 63u;
+    return rec_from(T.hot[2 * l], T.hot[2 * l + 1], T.cold[l]);
+}
+
+// Its hot part only (position and velocity; w and mass read as zero).
+__device__ inline OwnerRec load_rec_hot(const RecTile *t, int64_t o)
+{
+    const RecTile &T = t[o >> 6];
+    const uint32_t l = (uint32_t)o & 63u;
+    return rec_from(T.hot[2 * l], T.hot[2 * l + 1], make_uint4(0u, 0u, 0u, 0u));
+}
+
+// Its cold part into r (w, mass).
+__device__ inline void load_rec_cold(const RecTile *t, int64_t o, OwnerRec &r)
+{
+    const uint4 c = t[o >> 6].cold[(uint32_t)o & 63u];
+    r.w[0] = __uint_as_float(c.x);
+    r.w[1] = __uint_as_float(c.y);
+    r.w[2] = __uint_as_float(c.z);
+    r.mass = __uint_as_float(c.w);
+}
+
+__device__ inline void store_rec(RecTile *t, int64_t o, const OwnerRec &r)
+{
+    RecTile &T = t[o >> 6];
+    const uint32_t l = (uint32_t)o & 63u;
+    T.hot[2 * l] = rec_hot0(r);
+    T.hot[2 * l + 1] = rec_hot1(r);
+    T.cold[l] = rec_cold(r);
+}
+
+__device__ inline void store_rec_hot(RecTile *t, int64_t o, const OwnerRec &r)
+{
+    RecTile &T = t[o >> 6];
+    const uint32_t l = (uint32_t)o & 63u;
+    T.hot[2 * l] = rec_hot0(r);
+    T.hot[2 * l + 1] = rec_hot1(r);
+}
+
+// One wave copies the first n owners of a tile (src to dst, global memory
+// or LDS): their hot parts, and their cold parts if `cold`.
+__device__ inline void tile_copy(uint4 *dst, const uint4 *src, uint32_t n, uint32_t lane, bool cold)
+{
+    for (uint32_t k = lane; k < 2u * n; k += 64u) dst[k] = src[k];
+    if (cold)
+        for (uint32_t k = lane; k < n; k += 64u) dst[2 * REC_TILE + k] = src[2 * REC_TILE + k];
 }
 
 __device__ inline SphRec load_sph(const SphRec *p)

@@ -217,8 +217,10 @@ __device__ __forceinline__ void contact_eval(const DynArgs &a, const SphRec &sA,
             xB[1] = xBk[1];
             xB[2] = xBk[2];
         } else {
+            // the partner's hot part first (its centre); its angular
+            // velocity and mass only if the pair touches
             sB = load_sph(a.sph + jp);
-            const OwnerRec rB = load_rec(a.rec + (SINGLES ? jp : sB.owner));
+            OwnerRec rB = load_rec_hot(a.recs, SINGLES ? jp : sB.owner);
             owner_kin(rB, sB, a.aux, a.q, a.tpos, a.org, kB, xB);
         }
         double dx = xA[0] - xB[0], dy = xA[1] - xB[1], dz = xA[2] - xB[2];
@@ -227,6 +229,11 @@ __device__ __forceinline__ void contact_eval(const DynArgs &a, const SphRec &sA,
         double T = radA + radB;
         touching = d2 < T * T;
         if (GAPW) out.gap = touching ? -1.0 : sqrt(d2) - T;
+        if (!KNOWN_B && touching) {
+            OwnerRec rB = load_rec_hot(a.recs, SINGLES ? jp : sB.owner);
+            load_rec_cold(a.recs, SINGLES ? jp : sB.owner, rB);
+            owner_kin(rB, sB, a.aux, a.q, a.tpos, a.org, kB, xB);
+        }
         if (touching) {
             double d = sqrt(d2);
             nrm[0] = dx / d;
@@ -415,7 +422,7 @@ __global__ void __launch_bounds__(TPB) k_force(DynArgs a, const uint32_t *start,
     const uint32_t c0 = start[i], c1 = start[i + 1];
     if (c0 < c1) {
         const SphRec sA = load_sph(a.sph + i);
-        const OwnerRec rA = load_rec(a.rec + sA.owner);
+        const OwnerRec rA = load_rec(a.recs, sA.owner);
         OwnerKin kA;
         double xA[3];
         owner_kin(rA, sA, a.aux, a.q, a.tpos, a.org, kA, xA);
@@ -574,7 +581,7 @@ __global__ void __launch_bounds__(TPB) k_fold_integrate(DynArgs a, const uint32_
         float inv[3];
         int32_t tmpl = -1;
         if (integrate) {
-            r = load_rec(a.rec + o);
+            r = load_rec(a.recs, o);
             if (SINGLES) {
                 inv[0] = inv[1] = inv[2] = a.inv_i[o];
             } else {
@@ -613,7 +620,7 @@ __global__ void __launch_bounds__(TPB) k_fold_integrate(DynArgs a, const uint32_
             double *qp = a.q + 4 * (size_t)o;
             const double4 qv = rot ? *reinterpret_cast<const double4 *>(qp) : make_double4(1.0, 0.0, 0.0, 0.0);
             v2 = advance(a, r, inv, rot, F, T, qv, rot ? qp : nullptr, ctr);
-            store_rec(a.rec + o, r);
+            store_rec(a.recs, o, r);
         }
     }
     if (integrate) block_max_v2(v2, a.blkmax + blockIdx.x);
@@ -625,7 +632,7 @@ __global__ void __launch_bounds__(TPB) k_fold_integrate(DynArgs a, const uint32_
 // so the owner needs no reaction written by another thread.  The sums run in
 // the order of the two-kernel path -- per sphere the A-row sum, then the
 // B-side reactions by ascending contact index -- and the integration is the
-// same, so both paths give the same bits.  Reads (a.rec, a.q, history),
+// same, so both paths give the same bits.  Reads (a.recs, a.q, history),
 // writes (rec_out, q_out, second history): no thread reads what another
 // writes.  When the step is stopped (capacity or divergence) the state and
 // history are copied unchanged.  SINGLES: every owner is one sphere; FACETS:
@@ -734,7 +741,7 @@ __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, 
         // record, the inertia, the orientation (clump systems) and (without
         // fixed families) the flag
         OwnerRec &r = st.r;
-        r = pre ? *pre : load_rec(a.rec + o);
+        r = pre ? *pre : load_rec(a.recs, o);
         st.tmpl = -1;
         st.qv = make_double4(1.0, 0.0, 0.0, 0.0);
         if (SINGLES) {
@@ -853,7 +860,7 @@ __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, 
                             const uint32_t iA = jt;
                             // (owner index == sphere index: both loads at once)
                             const SphRec sA = load_sph(a.sph + iA);
-                            const OwnerRec rA = load_rec(a.rec + iA);
+                            const OwnerRec rA = load_rec(a.recs, iA);
                             OwnerKin kA;
                             double xA[3];
                             owner_kin(rA, sA, a.aux, a.q, a.tpos, a.org, kA, xA);
@@ -862,7 +869,7 @@ __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, 
                     } else {
                         const uint32_t iA = aside ? s : jt, jp = aside ? jt : s;
                         const SphRec sA = load_sph(a.sph + iA);
-                        const OwnerRec rA = load_rec(a.rec + sA.owner);
+                        const OwnerRec rA = load_rec(a.recs, sA.owner);
                         OwnerKin kA;
                         double xA[3];
                         owner_kin(rA, sA, a.aux, a.q, a.tpos, a.org, kA, xA);
@@ -927,7 +934,7 @@ __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, 
 
 // The integration part of an owner's step; returns its |v|^2.
 template <bool SINGLES>
-__device__ __forceinline__ float owner_advance(const DynArgs &a, const int64_t o, OwnerStep &st, OwnerRec *rec_out,
+__device__ __forceinline__ float owner_advance(const DynArgs &a, const int64_t o, OwnerStep &st, RecTile *rec_out,
                                                double *q_out, DevCounters *ctr)
 {
     const bool rotating = !SINGLES && st.tmpl >= 0;
@@ -935,18 +942,18 @@ __device__ __forceinline__ float owner_advance(const DynArgs &a, const int64_t o
     // (a single sphere's orientation never changes and both buffers hold
     // it, so nothing is copied for it)
     const float v2 = advance(a, st.r, st.inv, rotating, st.F, st.T, st.qv, qo, ctr);
-    store_rec(rec_out + o, st.r);
+    store_rec(rec_out, o, st.r);
     return v2;
 }
 
 // A stopped step: the owner's state and history are copied unchanged.
 template <bool SINGLES>
-__device__ __forceinline__ void halt_owner(const DynArgs &a, const int64_t o, OwnerRec *rec_out, double *q_out, const uint32_t *start,
+__device__ __forceinline__ void halt_owner(const DynArgs &a, const int64_t o, RecTile *rec_out, double *q_out, const uint32_t *start,
     const uint32_t *jarr, const uint32_t *bstart, const uint32_t *bidx, const uint32_t *bsrc, const uint8_t *oany,
     const float *hx, const float *hy, const float *hz, const float *hw, float *ox, float *oy, float *oz, float *ow,
     int64_t cap, DevCounters *ctr)
 {
-        store_rec(rec_out + o, load_rec(a.rec + o));
+        store_rec(rec_out, o, load_rec(a.recs, o));
         if (!SINGLES)
             *reinterpret_cast<double4 *>(q_out + 4 * (size_t)o) =
                 *reinterpret_cast<const double4 *>(a.q + 4 * (size_t)o);
@@ -1001,7 +1008,7 @@ __device__ __forceinline__ void wo_front(const DynArgs &a, const int64_t o, cons
 // them, before the owner records, so that the wait for the range's bounds
 // is not a wait for those stores).  Returns the lane's |v|^2.
 template <bool SINGLES, bool FACETS, bool FIXED, bool STAGE, bool REMAP, bool WO>
-__device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, uint4 *lrec, float *lds, OwnerRec *rec_out, double *q_out,
+__device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, uint4 *lrec, float *lds, RecTile *rec_out, double *q_out,
     const uint32_t *start, const uint32_t *jarr, const uint32_t *bstart, const uint32_t *bidx, const uint32_t *bsrc,
     const uint8_t *oany, const float *hx, const float *hy, const float *hz, const float *hw, float *ox, float *oy,
     float *oz, float *ohw, int64_t cap, DevCounters *ctr)
@@ -1012,10 +1019,10 @@ __device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, u
     const bool valid = o < No;
     SphRec spw{};
     if (WO && valid) spw = load_sph(a.sph + o);
-    // Single-sphere runs: the wave's owner records (48 B each, 3 KiB
-    // together) move through LDS in three contiguous 1 KiB loads and stores:
-    // a lane's own record read as three 16-byte pieces at a 48-byte stride
-    // would touch every line of the range three times.  (With STAGE the
+    // Single-sphere runs: the wave's owner records (one 3 KiB tile) move
+    // through LDS in three contiguous 1 KiB loads and stores: a lane's own
+    // record read as three 16-byte pieces would touch every line of the
+    // tile several times.  (With STAGE the
     // slice is shared with the history staging, which is used only while
     // the records sit in registers.)  Clump runs load the record with the
     // owner's other data (inertia, orientation), which would otherwise wait
@@ -1023,12 +1030,11 @@ __device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, u
     const uint32_t nv = (uint32_t)(No - ow < 64 ? No - ow : 64);
     OwnerRec rpre{};
     if constexpr (SINGLES) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(a.rec + ow);
-        for (uint32_t k = lane; k < 3u * nv; k += 64u) lrec[k] = src[k];
+        tile_copy(lrec, reinterpret_cast<const uint4 *>(a.recs + (ow >> 6)), nv, lane, true);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (valid) rpre = load_rec(reinterpret_cast<const OwnerRec *>(lrec) + lane);
+        if (valid) rpre = load_rec(reinterpret_cast<const RecTile *>(lrec), lane);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1088,20 +1094,17 @@ __device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, u
     float v2 = 0.0f;
     if (st.advance) {
         v2 = advance(a, st.r, st.inv, false, st.F, st.T, st.qv, q_out + 4 * (size_t)o, ctr);
-        store_rec(reinterpret_cast<OwnerRec *>(lrec) + lane, st.r);
+        store_rec(reinterpret_cast<RecTile *>(lrec), lane, st.r);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    {
-        uint4 *dst = reinterpret_cast<uint4 *>(rec_out + ow);
-        for (uint32_t k = lane; k < 3u * nv; k += 64u) dst[k] = lrec[k];
-    }
+    tile_copy(reinterpret_cast<uint4 *>(rec_out + (ow >> 6)), lrec, nv, lane, true);
     return v2;
 }
 
 template <bool SINGLES, bool FACETS, bool FIXED, bool STAGE, bool REMAP, bool WO>
-__global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fused(DynArgs a, OwnerRec *rec_out, double *q_out,
+__global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fused(DynArgs a, RecTile *rec_out, double *q_out,
                                                     const uint32_t *start, const uint32_t *jarr,
                                                     const uint32_t *bstart, const uint32_t *bidx,
                                                     const uint32_t *bsrc, const uint8_t *oany,
@@ -1134,7 +1137,7 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
             OwnerRec r{};
             SphRec sp{};
             if (v) {
-                r = load_rec(a.rec + o0);
+                r = load_rec(a.recs, o0);
                 sp = load_sph(a.sph + o0);
             }
             wo_front(a, o0, v, r, sp);
@@ -1190,9 +1193,10 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
 // k_step_listed, which runs after it on the same stream over the set's list
 // of owners with contacts and does for each what the one-kernel step does
 // (owner_forces, then the integration), so both forms give the same bits.
-// A wave's 64 records move through LDS in three contiguous 1 KiB loads and
-// stores, as in the single-sphere step, with the flags; the inertia and
-// orientation only for owners that turn or have just stopped turning.
+// A wave's 64 records (one tile) move through LDS, their hot parts in two
+// contiguous 1 KiB loads and stores, with the flags; the cold parts, the
+// inertia and the orientation only for owners that turn or have just
+// stopped turning.
 // REMAP: the first step on a newly adopted set (only its overflow check
 // matters here).
 constexpr int FREE_WAVES = 2;    // waves per block of k_step_free
@@ -1200,7 +1204,7 @@ constexpr int FREE_CHUNKS = 2;   // 64-owner chunks per wave (FREE_WAVES * FREE_
 static_assert(FREE_WAVES * FREE_CHUNKS * 64 == TPB, "a streaming block covers the owners of one speed slot");
 
 template <bool REMAP>
-__global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, OwnerRec *rec_out, double *q_out,
+__global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, RecTile *rec_out, double *q_out,
                                                               const uint8_t *oany, DevCounters *ctr)
 {
     // each wave streams FREE_CHUNKS chunks of 64 consecutive owners: every
@@ -1235,7 +1239,9 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, OwnerR
     float v2 = 0.0f, g2 = 0.0f;
     uint8_t fl[FREE_CHUNKS];
     uint32_t nv[FREE_CHUNKS];
-    // loads: flags and the records (through LDS) of every chunk
+    // loads: flags and the hot parts of the records (through LDS) of every
+    // chunk (a chunk is one record tile); a stopped step copies the cold
+    // parts too
 #pragma unroll
     for (int c = 0; c < FREE_CHUNKS; ++c) {
         const int64_t ow = ob + (int64_t)(wv * FREE_CHUNKS + c) * 64;
@@ -1243,34 +1249,37 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, OwnerR
         nv[c] = ow < No ? (uint32_t)(No - ow < 64 ? No - ow : 64) : 0u;
         fl[c] = 1u;
         if (o < No) fl[c] = oany[o];
-        const uint4 *src = reinterpret_cast<const uint4 *>(a.rec + ow);
-        for (uint32_t k = lane; k < 3u * nv[c]; k += 64u) wbuf[wv][c][k] = src[k];
+        if (nv[c] > 0) tile_copy(wbuf[wv][c], reinterpret_cast<const uint4 *>(a.recs + (ow >> 6)), nv[c], lane, halt);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // An owner without contacts that does not turn (zero angular velocity:
-    // without torque it keeps it) and whose record marks both orientation
-    // buffers as holding its orientation (DEM_VOX_QSAME; always true of a
-    // single sphere's identity) is still: its step needs neither its inertia
-    // nor its orientation, and neither buffer is written.  The others load
-    // their inertia and template, and their orientation with it (used by
-    // clumps only).
+    // An owner without contacts whose record carries DEM_VOX_QSAME is
+    // still: its angular velocity is zero in both record buffers (without
+    // torque it stays zero) and both orientation buffers hold its
+    // orientation (always true of a single sphere's identity).  Its step
+    // needs neither the cold part of its record (angular velocity, mass:
+    // with zero force the mass does not enter) nor its inertia nor its
+    // orientation, and it writes only its hot part.  The others load their
+    // cold part, inertia and template, and their orientation with them
+    // (used by clumps only).
     OwnerRec r[FREE_CHUNKS];
     OwnerAux ax[FREE_CHUNKS];
     double4 qv[FREE_CHUNKS];
-    bool still[FREE_CHUNKS];
+    bool still[FREE_CHUNKS], cold[FREE_CHUNKS];
 #pragma unroll
     for (int c = 0; c < FREE_CHUNKS; ++c) {
         const bool valid = lane < nv[c];
         const int64_t o = ob + (int64_t)(wv * FREE_CHUNKS + c) * 64 + lane;
         r[c] = OwnerRec{};
-        if (valid) r[c] = load_rec(reinterpret_cast<const OwnerRec *>(wbuf[wv][c]) + lane);
-        still[c] = !halt && !(fl[c] & 1u) && (r[c].vox & DEM_VOX_QSAME) != 0 && r[c].w[0] == 0.0f &&
-                   r[c].w[1] == 0.0f && r[c].w[2] == 0.0f;
+        if (valid) r[c] = load_rec_hot(reinterpret_cast<const RecTile *>(wbuf[wv][c]), lane);
+        still[c] = !halt && !(fl[c] & 1u) && (r[c].vox & DEM_VOX_QSAME) != 0;
+        cold[c] = valid && !halt && !(fl[c] & 1u) && !still[c];
+        r[c].mass = 1.0f;   // (a still owner's: any positive value gives the same zero force term)
         ax[c] = OwnerAux{{0.0f, 0.0f, 0.0f}, -1};
         qv[c] = make_double4(1.0, 0.0, 0.0, 0.0);
-        if (valid && (halt || (!(fl[c] & 1u) && !still[c]))) {
+        if (cold[c]) load_rec_cold(a.recs, o, r[c]);
+        if (valid && (halt || cold[c])) {
             ax[c] = a.aux[o];
             qv[c] = *reinterpret_cast<const double4 *>(a.q + 4 * (size_t)o);
         }
@@ -1292,14 +1301,17 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, OwnerR
             // (a still owner: zero torque on zero angular velocity, no
             // turn; the integration of a turning path would give the same
             // bits and write back the orientation it read)
+            const bool w0 = r[c].w[0] == 0.0f && r[c].w[1] == 0.0f && r[c].w[2] == 0.0f;
             const float inv[3] = {ax[c].inv_moi[0], ax[c].inv_moi[1], ax[c].inv_moi[2]};
             v2 = fmaxf(v2, advance(a, r[c], inv, rot, f3(0.f, 0.f, 0.f), f3(0.f, 0.f, 0.f), qv[c],
                                    rot ? qo : nullptr, ctr));
             if (a.gap != 0) g2 = fmaxf(g2, reach_speed2(r[c], a.arm));
-            // after this step both buffers hold the orientation if the
-            // owner did not turn in it
-            if (r[c].w[0] == 0.0f && r[c].w[1] == 0.0f && r[c].w[2] == 0.0f) r[c].vox |= DEM_VOX_QSAME;
-            store_rec(reinterpret_cast<OwnerRec *>(wbuf[wv][c]) + lane, r[c]);
+            // after this step both record buffers hold a zero angular
+            // velocity, and both orientation buffers the orientation, if
+            // the owner neither turned before this step nor in it
+            if (w0 && r[c].w[0] == 0.0f && r[c].w[1] == 0.0f && r[c].w[2] == 0.0f) r[c].vox |= DEM_VOX_QSAME;
+            store_rec_hot(reinterpret_cast<RecTile *>(wbuf[wv][c]), lane, r[c]);
+            if (cold[c]) rec_out[o >> 6].cold[(uint32_t)o & 63u] = rec_cold(r[c]);
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1310,8 +1322,7 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, OwnerR
 #pragma unroll
     for (int c = 0; c < FREE_CHUNKS; ++c) {
         const int64_t ow = ob + (int64_t)(wv * FREE_CHUNKS + c) * 64;
-        uint4 *dst = reinterpret_cast<uint4 *>(rec_out + ow);
-        for (uint32_t k = lane; k < 3u * nv[c]; k += 64u) dst[k] = wbuf[wv][c][k];
+        if (nv[c] > 0) tile_copy(reinterpret_cast<uint4 *>(rec_out + (ow >> 6)), wbuf[wv][c], nv[c], lane, halt);
     }
     if (halt) return;
     __shared__ float wmax[2][FREE_WAVES];
@@ -1349,7 +1360,7 @@ constexpr unsigned LISTED_BLOCKS = 1024;
 
 template <bool FACETS, bool REMAP, bool GAP>
 __global__ void __launch_bounds__(TPB, 3) k_step_listed(DynArgs a, const uint32_t *olist, const uint32_t *ocount,
-                                                       OwnerRec *rec_out, double *q_out, const uint32_t *start,
+                                                       RecTile *rec_out, double *q_out, const uint32_t *start,
                                                        const uint32_t *jarr, const uint32_t *bstart,
                                                        const uint32_t *bidx, const uint32_t *bsrc,
                                                        const uint8_t *oany, const float *hx, const float *hy,
@@ -1452,22 +1463,22 @@ __global__ void __launch_bounds__(64) k_noop() {}
 
 // Owners of fixed families: zero velocity and angular velocity, the same
 // record (and orientation) in both state buffers.
-__global__ void __launch_bounds__(256) k_fix_owners(OwnerRec *rec, OwnerRec *rec_alt, const double *q, double *q_alt,
+__global__ void __launch_bounds__(256) k_fix_owners(RecTile *rec, RecTile *rec_alt, const double *q, double *q_alt,
                                                     const uint8_t *ofam, const uint8_t *fixed, int64_t n)
 {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= n || !fixed[ofam[o]]) return;
-    OwnerRec r = load_rec(rec + o);
+    OwnerRec r = load_rec(rec, o);
     for (int k = 0; k < 3; ++k) {
         r.v[k] = 0.0f;
         r.w[k] = 0.0f;
     }
-    store_rec(rec + o, r);
-    store_rec(rec_alt + o, r);
+    store_rec(rec, o, r);
+    store_rec(rec_alt, o, r);
     *reinterpret_cast<double4 *>(q_alt + 4 * (size_t)o) = *reinterpret_cast<const double4 *>(q + 4 * (size_t)o);
 }
 
-void launch_fix_owners(OwnerRec *rec, OwnerRec *rec_alt, const double *q, double *q_alt, const uint8_t *ofam,
+void launch_fix_owners(RecTile *rec, RecTile *rec_alt, const double *q, double *q_alt, const uint8_t *ofam,
                        const uint8_t *fixed, int64_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fix_owners, dim3(nblocks(n)), dim3(256), 0, s, rec, rec_alt, q, q_alt, ofam, fixed, n);
@@ -1527,7 +1538,7 @@ bool step_is_split(const DynArgs &a, const AcsBuf &cur)
     return a.split && a.has_clumps && !a.has_fixed && !a.wo_keys && cur.olist;
 }
 
-bool launch_step_fused(const DynArgs &a, OwnerRec *rec_out, double *q_out, const AcsBuf &cur, int64_t cap,
+bool launch_step_fused(const DynArgs &a, RecTile *rec_out, double *q_out, const AcsBuf &cur, int64_t cap,
                        DevCounters *ctr, hipStream_t s, const SplitTiming *tm)
 {
     if (step_is_split(a, cur)) {
