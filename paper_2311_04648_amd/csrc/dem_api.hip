@@ -112,8 +112,8 @@ struct dem_ctx {
     bool bound = false;
     char *ws = nullptr;
     int64_t ws_bytes = 0, cap = 0;
-    RecTile *rec = nullptr;
-    RecTile *rec_alt = nullptr;    // the fused step writes here, then the two swap
+    RecBuf rec{nullptr, nullptr};
+    RecBuf rec_alt{nullptr, nullptr};    // the fused step writes here, then the two swap
     double *q_alt = nullptr;
     SnapRec *fref = nullptr;        // reference state of the learned-interval features
     float *d_ovol = nullptr;        // volume of each owner's spheres (packing-fraction feature)
@@ -274,8 +274,10 @@ void carve_cd(Carver &c, const dem_ctx *ctx, CdWork &w)
 void carve(Carver &c, dem_ctx *ctx, int64_t cap)
 {
     int64_t No = ctx->No, Ns = ctx->Ns;
-    ctx->rec = c.take<RecTile>(rec_tiles(No));
-    ctx->rec_alt = c.take<RecTile>(rec_tiles(No));
+    ctx->rec.hot = c.take<uint4>(2 * No);
+    ctx->rec.cold = c.take<uint4>(No);
+    ctx->rec_alt.hot = c.take<uint4>(2 * No);
+    ctx->rec_alt.cold = c.take<uint4>(No);
     ctx->fref = c.take<SnapRec>(No);
     ctx->d_ovol = c.take<float>(No);
     ctx->q = c.take<double>(4 * No);
@@ -1097,30 +1099,25 @@ dem_status dem_bind(dem_ctx *ctx, void *device_workspace, int64_t bytes, int64_t
 
 static void rebuild_dormant_index(dem_ctx *ctx, hipStream_t s);
 
-// Owner records to and from their tiled device form: bytes 0-31 of an
-// OwnerRec are its hot part, bytes 32-47 its cold part.
-static std::vector<RecTile> rec_tile_pack(const std::vector<OwnerRec> &rec)
+// Owner records to and from their device form: bytes 0-31 of an OwnerRec
+// are its hot part (two uint4 of the hot array), bytes 32-47 its cold part.
+static void rec_split(const std::vector<OwnerRec> &rec, std::vector<uint4> &hot, std::vector<uint4> &cold)
 {
-    const int64_t n = (int64_t)rec.size();
-    std::vector<RecTile> t(rec_tiles(n));
-    std::memset(static_cast<void *>(t.data()), 0, sizeof(RecTile) * t.size());
-    for (int64_t o = 0; o < n; ++o) {
-        RecTile &T = t[o / REC_TILE];
-        const int64_t l = o % REC_TILE;
-        std::memcpy(static_cast<void *>(&T.hot[2 * l]), &rec[o], 32);
-        std::memcpy(static_cast<void *>(&T.cold[l]), reinterpret_cast<const char *>(&rec[o]) + 32, 16);
+    const size_t n = rec.size();
+    hot.resize(2 * n);
+    cold.resize(n);
+    for (size_t o = 0; o < n; ++o) {
+        std::memcpy(static_cast<void *>(&hot[2 * o]), &rec[o], 32);
+        std::memcpy(static_cast<void *>(&cold[o]), reinterpret_cast<const char *>(&rec[o]) + 32, 16);
     }
-    return t;
 }
 
-static std::vector<OwnerRec> rec_tile_unpack(const std::vector<RecTile> &t, int64_t n)
+static std::vector<OwnerRec> rec_join(const std::vector<uint4> &hot, const std::vector<uint4> &cold)
 {
-    std::vector<OwnerRec> rec(n);
-    for (int64_t o = 0; o < n; ++o) {
-        const RecTile &T = t[o / REC_TILE];
-        const int64_t l = o % REC_TILE;
-        std::memcpy(&rec[o], &T.hot[2 * l], 32);
-        std::memcpy(reinterpret_cast<char *>(&rec[o]) + 32, &T.cold[l], 16);
+    std::vector<OwnerRec> rec(cold.size());
+    for (size_t o = 0; o < rec.size(); ++o) {
+        std::memcpy(&rec[o], &hot[2 * o], 32);
+        std::memcpy(reinterpret_cast<char *>(&rec[o]) + 32, &cold[o], 16);
     }
     return rec;
 }
@@ -1167,11 +1164,14 @@ dem_status dem_set_state(dem_ctx *ctx, const double *X, const double *q, const f
         }
         rec[o] = r;
     }
-    const std::vector<RecTile> tiles = rec_tile_pack(rec);
-    HIPCHK(hipMemcpyAsync(ctx->rec, tiles.data(), sizeof(RecTile) * tiles.size(), hipMemcpyHostToDevice, s));
+    std::vector<uint4> hot, cold;
+    rec_split(rec, hot, cold);
     // the fused step does not rewrite the records of fixed owners: both
     // buffers start equal
-    HIPCHK(hipMemcpyAsync(ctx->rec_alt, tiles.data(), sizeof(RecTile) * tiles.size(), hipMemcpyHostToDevice, s));
+    for (const RecBuf &b : {ctx->rec, ctx->rec_alt}) {
+        HIPCHK(hipMemcpyAsync(b.hot, hot.data(), sizeof(uint4) * hot.size(), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(b.cold, cold.data(), sizeof(uint4) * cold.size(), hipMemcpyHostToDevice, s));
+    }
     HIPCHK(hipMemcpyAsync(ctx->q, qd.data(), sizeof(double) * 4 * ctx->No, hipMemcpyHostToDevice, s));
     // the fused step leaves the orientations of single-sphere systems alone,
     // so both buffers hold them
@@ -1200,12 +1200,13 @@ dem_status dem_get_state(dem_ctx *ctx, double *X, double *q, float *v, float *w,
         return DEM_ERR_STATE;
     }
     hipStream_t s = S(stream);
-    std::vector<RecTile> tiles(rec_tiles(ctx->No));
+    std::vector<uint4> hot(2 * ctx->No), cold(ctx->No);
     std::vector<double> qd(4 * ctx->No);
-    HIPCHK(hipMemcpyAsync(tiles.data(), ctx->rec, sizeof(RecTile) * tiles.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hot.data(), ctx->rec.hot, sizeof(uint4) * hot.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(cold.data(), ctx->rec.cold, sizeof(uint4) * cold.size(), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(qd.data(), ctx->q, sizeof(double) * 4 * ctx->No, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    const std::vector<OwnerRec> rec = rec_tile_unpack(tiles, ctx->No);
+    const std::vector<OwnerRec> rec = rec_join(hot, cold);
     for (int64_t o = 0; o < ctx->No; ++o) {
         const OwnerRec &r = rec[o];
         for (int k = 0; k < 3; ++k) {

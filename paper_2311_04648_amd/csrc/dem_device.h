@@ -165,57 +165,56 @@ __device__ inline uint4 rec_cold(const OwnerRec &r)
                       __float_as_uint(r.mass));
 }
 
-// Owner o's record from the tiled storage (or from one tile staged in LDS,
-// o = the lane): three 16-byte loads.
-__device__ inline OwnerRec load_rec(const RecTile *t, int64_t o)
+// Owner o's record: three 16-byte loads.
+__device__ inline OwnerRec load_rec(const RecBuf &b, int64_t o)
 {
-    const RecTile &T = t[o >> 6];
-    const uint32_t l = (uint32_t)o & 63u;
-    return rec_from(T.hot[2 * l], T.hot[2 * l + 1], T.cold[l]);
+    return rec_from(b.hot[2 * o], b.hot[2 * o + 1], b.cold[o]);
 }
 
 // Its hot part only (position and velocity; w and mass read as zero).
-__device__ inline OwnerRec load_rec_hot(const RecTile *t, int64_t o)
+__device__ inline OwnerRec load_rec_hot(const RecBuf &b, int64_t o)
 {
-    const RecTile &T = t[o >> 6];
-    const uint32_t l = (uint32_t)o & 63u;
-    return rec_from(T.hot[2 * l], T.hot[2 * l + 1], make_uint4(0u, 0u, 0u, 0u));
+    return rec_from(b.hot[2 * o], b.hot[2 * o + 1], make_uint4(0u, 0u, 0u, 0u));
 }
 
 // Its cold part into r (w, mass).
-__device__ inline void load_rec_cold(const RecTile *t, int64_t o, OwnerRec &r)
+__device__ inline void load_rec_cold(const RecBuf &b, int64_t o, OwnerRec &r)
 {
-    const uint4 c = t[o >> 6].cold[(uint32_t)o & 63u];
+    const uint4 c = b.cold[o];
     r.w[0] = __uint_as_float(c.x);
     r.w[1] = __uint_as_float(c.y);
     r.w[2] = __uint_as_float(c.z);
     r.mass = __uint_as_float(c.w);
 }
 
-__device__ inline void store_rec(RecTile *t, int64_t o, const OwnerRec &r)
+__device__ inline void store_rec(const RecBuf &b, int64_t o, const OwnerRec &r)
 {
-    RecTile &T = t[o >> 6];
-    const uint32_t l = (uint32_t)o & 63u;
-    T.hot[2 * l] = rec_hot0(r);
-    T.hot[2 * l + 1] = rec_hot1(r);
-    T.cold[l] = rec_cold(r);
+    b.hot[2 * o] = rec_hot0(r);
+    b.hot[2 * o + 1] = rec_hot1(r);
+    b.cold[o] = rec_cold(r);
 }
 
-__device__ inline void store_rec_hot(RecTile *t, int64_t o, const OwnerRec &r)
+__device__ inline void store_rec_hot(const RecBuf &b, int64_t o, const OwnerRec &r)
 {
-    RecTile &T = t[o >> 6];
-    const uint32_t l = (uint32_t)o & 63u;
-    T.hot[2 * l] = rec_hot0(r);
-    T.hot[2 * l + 1] = rec_hot1(r);
+    b.hot[2 * o] = rec_hot0(r);
+    b.hot[2 * o + 1] = rec_hot1(r);
 }
 
-// One wave copies the first n owners of a tile (src to dst, global memory
-// or LDS): their hot parts, and their cold parts if `cold`.
-__device__ inline void tile_copy(uint4 *dst, const uint4 *src, uint32_t n, uint32_t lane, bool cold)
+// A wave's 64 records in LDS (192 uint4: hot parts, then cold parts).
+__device__ inline RecBuf rec_lds(uint4 *buf)
 {
-    for (uint32_t k = lane; k < 2u * n; k += 64u) dst[k] = src[k];
+    return RecBuf{buf, buf + 128};
+}
+
+// One wave copies the records of n owners, from src owner s0 to dst owner
+// d0 (global memory or LDS): their hot parts, and their cold parts if
+// `cold`.
+__device__ inline void rec_copy(const RecBuf &dst, int64_t d0, const RecBuf &src, int64_t s0, uint32_t n,
+                                uint32_t lane, bool cold)
+{
+    for (uint32_t k = lane; k < 2u * n; k += 64u) dst.hot[2 * d0 + k] = src.hot[2 * s0 + k];
     if (cold)
-        for (uint32_t k = lane; k < n; k += 64u) dst[2 * REC_TILE + k] = src[2 * REC_TILE + k];
+        for (uint32_t k = lane; k < n; k += 64u) dst.cold[d0 + k] = src.cold[s0 + k];
 }
 
 __device__ inline SphRec load_sph(const SphRec *p)

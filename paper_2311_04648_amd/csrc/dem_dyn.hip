@@ -934,7 +934,7 @@ __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, 
 
 // The integration part of an owner's step; returns its |v|^2.
 template <bool SINGLES>
-__device__ __forceinline__ float owner_advance(const DynArgs &a, const int64_t o, OwnerStep &st, RecTile *rec_out,
+__device__ __forceinline__ float owner_advance(const DynArgs &a, const int64_t o, OwnerStep &st, RecBuf rec_out,
                                                double *q_out, DevCounters *ctr)
 {
     const bool rotating = !SINGLES && st.tmpl >= 0;
@@ -948,7 +948,7 @@ __device__ __forceinline__ float owner_advance(const DynArgs &a, const int64_t o
 
 // A stopped step: the owner's state and history are copied unchanged.
 template <bool SINGLES>
-__device__ __forceinline__ void halt_owner(const DynArgs &a, const int64_t o, RecTile *rec_out, double *q_out, const uint32_t *start,
+__device__ __forceinline__ void halt_owner(const DynArgs &a, const int64_t o, RecBuf rec_out, double *q_out, const uint32_t *start,
     const uint32_t *jarr, const uint32_t *bstart, const uint32_t *bidx, const uint32_t *bsrc, const uint8_t *oany,
     const float *hx, const float *hy, const float *hz, const float *hw, float *ox, float *oy, float *oz, float *ow,
     int64_t cap, DevCounters *ctr)
@@ -1008,7 +1008,7 @@ __device__ __forceinline__ void wo_front(const DynArgs &a, const int64_t o, cons
 // them, before the owner records, so that the wait for the range's bounds
 // is not a wait for those stores).  Returns the lane's |v|^2.
 template <bool SINGLES, bool FACETS, bool FIXED, bool STAGE, bool REMAP, bool WO>
-__device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, uint4 *lrec, float *lds, RecTile *rec_out, double *q_out,
+__device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, uint4 *lrec, float *lds, RecBuf rec_out, double *q_out,
     const uint32_t *start, const uint32_t *jarr, const uint32_t *bstart, const uint32_t *bidx, const uint32_t *bsrc,
     const uint8_t *oany, const float *hx, const float *hy, const float *hz, const float *hw, float *ox, float *oy,
     float *oz, float *ohw, int64_t cap, DevCounters *ctr)
@@ -1030,11 +1030,11 @@ __device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, u
     const uint32_t nv = (uint32_t)(No - ow < 64 ? No - ow : 64);
     OwnerRec rpre{};
     if constexpr (SINGLES) {
-        tile_copy(lrec, reinterpret_cast<const uint4 *>(a.recs + (ow >> 6)), nv, lane, true);
+        rec_copy(rec_lds(lrec), 0, a.recs, ow, nv, lane, true);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (valid) rpre = load_rec(reinterpret_cast<const RecTile *>(lrec), lane);
+        if (valid) rpre = load_rec(rec_lds(lrec), lane);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1094,17 +1094,17 @@ __device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, u
     float v2 = 0.0f;
     if (st.advance) {
         v2 = advance(a, st.r, st.inv, false, st.F, st.T, st.qv, q_out + 4 * (size_t)o, ctr);
-        store_rec(reinterpret_cast<RecTile *>(lrec), lane, st.r);
+        store_rec(rec_lds(lrec), lane, st.r);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    tile_copy(reinterpret_cast<uint4 *>(rec_out + (ow >> 6)), lrec, nv, lane, true);
+    rec_copy(rec_out, ow, rec_lds(lrec), 0, nv, lane, true);
     return v2;
 }
 
 template <bool SINGLES, bool FACETS, bool FIXED, bool STAGE, bool REMAP, bool WO>
-__global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fused(DynArgs a, RecTile *rec_out, double *q_out,
+__global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fused(DynArgs a, RecBuf rec_out, double *q_out,
                                                     const uint32_t *start, const uint32_t *jarr,
                                                     const uint32_t *bstart, const uint32_t *bidx,
                                                     const uint32_t *bsrc, const uint8_t *oany,
@@ -1204,13 +1204,14 @@ constexpr int FREE_CHUNKS = 2;   // 64-owner chunks per wave (FREE_WAVES * FREE_
 static_assert(FREE_WAVES * FREE_CHUNKS * 64 == TPB, "a streaming block covers the owners of one speed slot");
 
 template <bool REMAP>
-__global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, RecTile *rec_out, double *q_out,
+__global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, RecBuf rec_out, double *q_out,
                                                               const uint8_t *oany, DevCounters *ctr)
 {
-    // each wave streams FREE_CHUNKS chunks of 64 consecutive owners: every
-    // load of all its chunks is issued before any chunk is computed, so a
-    // wave keeps twice the bytes in flight
-    __shared__ uint4 wbuf[FREE_WAVES][FREE_CHUNKS][192];
+    // each wave streams FREE_CHUNKS chunks of 64 consecutive owners (record
+    // tiles): the loads of all its chunks are issued before any chunk is
+    // computed, so a wave keeps that many tiles in flight; the chunks are
+    // then computed one after the other (registers for one at a time)
+    __shared__ uint4 wbuf[FREE_WAVES][FREE_CHUNKS][128];   // hot parts
     const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t No = a.n_owners;
     const uint32_t lane = threadIdx.x & 63u;
@@ -1238,18 +1239,19 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, RecTil
     }
     float v2 = 0.0f, g2 = 0.0f;
     uint8_t fl[FREE_CHUNKS];
-    uint32_t nv[FREE_CHUNKS];
     // loads: flags and the hot parts of the records (through LDS) of every
-    // chunk (a chunk is one record tile); a stopped step copies the cold
-    // parts too
+    // chunk; a stopped step copies the cold parts, unchanged, straight over
 #pragma unroll
     for (int c = 0; c < FREE_CHUNKS; ++c) {
         const int64_t ow = ob + (int64_t)(wv * FREE_CHUNKS + c) * 64;
         const int64_t o = ow + lane;
-        nv[c] = ow < No ? (uint32_t)(No - ow < 64 ? No - ow : 64) : 0u;
+        const uint32_t nv = ow < No ? (uint32_t)(No - ow < 64 ? No - ow : 64) : 0u;
         fl[c] = 1u;
         if (o < No) fl[c] = oany[o];
-        if (nv[c] > 0) tile_copy(wbuf[wv][c], reinterpret_cast<const uint4 *>(a.recs + (ow >> 6)), nv[c], lane, halt);
+        if (nv > 0) {
+            rec_copy(RecBuf{wbuf[wv][c], nullptr}, 0, a.recs, ow, nv, lane, false);
+            if (halt && lane < nv) rec_out.cold[ow + lane] = a.recs.cold[ow + lane];
+        }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -1263,55 +1265,45 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, RecTil
     // orientation, and it writes only its hot part.  The others load their
     // cold part, inertia and template, and their orientation with them
     // (used by clumps only).
-    OwnerRec r[FREE_CHUNKS];
-    OwnerAux ax[FREE_CHUNKS];
-    double4 qv[FREE_CHUNKS];
-    bool still[FREE_CHUNKS], cold[FREE_CHUNKS];
-#pragma unroll
+#pragma unroll 1
     for (int c = 0; c < FREE_CHUNKS; ++c) {
-        const bool valid = lane < nv[c];
-        const int64_t o = ob + (int64_t)(wv * FREE_CHUNKS + c) * 64 + lane;
-        r[c] = OwnerRec{};
-        if (valid) r[c] = load_rec_hot(reinterpret_cast<const RecTile *>(wbuf[wv][c]), lane);
-        still[c] = !halt && !(fl[c] & 1u) && (r[c].vox & DEM_VOX_QSAME) != 0;
-        cold[c] = valid && !halt && !(fl[c] & 1u) && !still[c];
-        r[c].mass = 1.0f;   // (a still owner's: any positive value gives the same zero force term)
-        ax[c] = OwnerAux{{0.0f, 0.0f, 0.0f}, -1};
-        qv[c] = make_double4(1.0, 0.0, 0.0, 0.0);
-        if (cold[c]) load_rec_cold(a.recs, o, r[c]);
-        if (valid && (halt || cold[c])) {
-            ax[c] = a.aux[o];
-            qv[c] = *reinterpret_cast<const double4 *>(a.q + 4 * (size_t)o);
+        const int64_t ow = ob + (int64_t)(wv * FREE_CHUNKS + c) * 64;
+        const int64_t o = ow + lane;
+        const bool valid = o < No;
+        OwnerRec r{};
+        if (valid) r = load_rec_hot(RecBuf{wbuf[wv][c], nullptr}, lane);
+        const bool still = !halt && !(fl[c] & 1u) && (r.vox & DEM_VOX_QSAME) != 0;
+        const bool cold = valid && !halt && !(fl[c] & 1u) && !still;
+        r.mass = 1.0f;   // (a still owner's: any positive value gives the same zero force term)
+        OwnerAux ax{{0.0f, 0.0f, 0.0f}, -1};
+        double4 qv = make_double4(1.0, 0.0, 0.0, 0.0);
+        if (cold) load_rec_cold(a.recs, o, r);
+        if (valid && (halt || cold)) {
+            ax = a.aux[o];
+            qv = *reinterpret_cast<const double4 *>(a.q + 4 * (size_t)o);
         }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-    for (int c = 0; c < FREE_CHUNKS; ++c) {
-        const bool valid = lane < nv[c];
-        const int64_t o = ob + (int64_t)(wv * FREE_CHUNKS + c) * 64 + lane;
-        const bool rot = valid && ax[c].tmpl >= 0;
+        const bool rot = valid && ax.tmpl >= 0;
         double *qo = q_out + 4 * (size_t)o;
         if (halt) {
             // a stopped step: the state is copied unchanged (the records
-            // below, the orientation here; the history by k_step_listed)
-            if (rot) *reinterpret_cast<double4 *>(qo) = qv[c];
+            // here and below, the orientation here; the history by
+            // k_step_listed)
+            if (rot) *reinterpret_cast<double4 *>(qo) = qv;
         } else if (valid && !(fl[c] & 1u)) {
             // (a still owner: zero torque on zero angular velocity, no
             // turn; the integration of a turning path would give the same
             // bits and write back the orientation it read)
-            const bool w0 = r[c].w[0] == 0.0f && r[c].w[1] == 0.0f && r[c].w[2] == 0.0f;
-            const float inv[3] = {ax[c].inv_moi[0], ax[c].inv_moi[1], ax[c].inv_moi[2]};
-            v2 = fmaxf(v2, advance(a, r[c], inv, rot, f3(0.f, 0.f, 0.f), f3(0.f, 0.f, 0.f), qv[c],
-                                   rot ? qo : nullptr, ctr));
-            if (a.gap != 0) g2 = fmaxf(g2, reach_speed2(r[c], a.arm));
+            const bool w0 = r.w[0] == 0.0f && r.w[1] == 0.0f && r.w[2] == 0.0f;
+            const float inv[3] = {ax.inv_moi[0], ax.inv_moi[1], ax.inv_moi[2]};
+            v2 = fmaxf(v2, advance(a, r, inv, rot, f3(0.f, 0.f, 0.f), f3(0.f, 0.f, 0.f), qv, rot ? qo : nullptr,
+                                   ctr));
+            if (a.gap != 0) g2 = fmaxf(g2, reach_speed2(r, a.arm));
             // after this step both record buffers hold a zero angular
             // velocity, and both orientation buffers the orientation, if
             // the owner neither turned before this step nor in it
-            if (w0 && r[c].w[0] == 0.0f && r[c].w[1] == 0.0f && r[c].w[2] == 0.0f) r[c].vox |= DEM_VOX_QSAME;
-            store_rec_hot(reinterpret_cast<RecTile *>(wbuf[wv][c]), lane, r[c]);
-            if (cold[c]) rec_out[o >> 6].cold[(uint32_t)o & 63u] = rec_cold(r[c]);
+            if (w0 && r.w[0] == 0.0f && r.w[1] == 0.0f && r.w[2] == 0.0f) r.vox |= DEM_VOX_QSAME;
+            store_rec_hot(RecBuf{wbuf[wv][c], nullptr}, lane, r);
+            if (cold) rec_out.cold[o] = rec_cold(r);
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1322,7 +1314,8 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, RecTil
 #pragma unroll
     for (int c = 0; c < FREE_CHUNKS; ++c) {
         const int64_t ow = ob + (int64_t)(wv * FREE_CHUNKS + c) * 64;
-        if (nv[c] > 0) tile_copy(reinterpret_cast<uint4 *>(rec_out + (ow >> 6)), wbuf[wv][c], nv[c], lane, halt);
+        const uint32_t nv = ow < No ? (uint32_t)(No - ow < 64 ? No - ow : 64) : 0u;
+        if (nv > 0) rec_copy(rec_out, ow, RecBuf{wbuf[wv][c], nullptr}, 0, nv, lane, false);
     }
     if (halt) return;
     __shared__ float wmax[2][FREE_WAVES];
@@ -1360,7 +1353,7 @@ constexpr unsigned LISTED_BLOCKS = 1024;
 
 template <bool FACETS, bool REMAP, bool GAP>
 __global__ void __launch_bounds__(TPB, 3) k_step_listed(DynArgs a, const uint32_t *olist, const uint32_t *ocount,
-                                                       RecTile *rec_out, double *q_out, const uint32_t *start,
+                                                       RecBuf rec_out, double *q_out, const uint32_t *start,
                                                        const uint32_t *jarr, const uint32_t *bstart,
                                                        const uint32_t *bidx, const uint32_t *bsrc,
                                                        const uint8_t *oany, const float *hx, const float *hy,
@@ -1463,7 +1456,7 @@ __global__ void __launch_bounds__(64) k_noop() {}
 
 // Owners of fixed families: zero velocity and angular velocity, the same
 // record (and orientation) in both state buffers.
-__global__ void __launch_bounds__(256) k_fix_owners(RecTile *rec, RecTile *rec_alt, const double *q, double *q_alt,
+__global__ void __launch_bounds__(256) k_fix_owners(RecBuf rec, RecBuf rec_alt, const double *q, double *q_alt,
                                                     const uint8_t *ofam, const uint8_t *fixed, int64_t n)
 {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1478,7 +1471,7 @@ __global__ void __launch_bounds__(256) k_fix_owners(RecTile *rec, RecTile *rec_a
     *reinterpret_cast<double4 *>(q_alt + 4 * (size_t)o) = *reinterpret_cast<const double4 *>(q + 4 * (size_t)o);
 }
 
-void launch_fix_owners(RecTile *rec, RecTile *rec_alt, const double *q, double *q_alt, const uint8_t *ofam,
+void launch_fix_owners(RecBuf rec, RecBuf rec_alt, const double *q, double *q_alt, const uint8_t *ofam,
                        const uint8_t *fixed, int64_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fix_owners, dim3(nblocks(n)), dim3(256), 0, s, rec, rec_alt, q, q_alt, ofam, fixed, n);
@@ -1538,7 +1531,7 @@ bool step_is_split(const DynArgs &a, const AcsBuf &cur)
     return a.split && a.has_clumps && !a.has_fixed && !a.wo_keys && cur.olist;
 }
 
-bool launch_step_fused(const DynArgs &a, RecTile *rec_out, double *q_out, const AcsBuf &cur, int64_t cap,
+bool launch_step_fused(const DynArgs &a, RecBuf rec_out, double *q_out, const AcsBuf &cur, int64_t cap,
                        DevCounters *ctr, hipStream_t s, const SplitTiming *tm)
 {
     if (step_is_split(a, cur)) {

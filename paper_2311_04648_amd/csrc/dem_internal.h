@@ -1,10 +1,9 @@
 // Internal declarations shared by the HIP kernels and the host side of the
 // DEM library (gfx950).  Device data layout:
-//   owners   records in tiles of 64 owners (RecTile, 3 KiB): the 64 hot
-//            parts (voxel word, offsets, velocity: 32 B, one line segment
-//            per owner) then the 64 cold parts (angular velocity, mass:
-//            16 B), so a stream over owners at rest and a gather of a
-//            contact partner's position move the hot parts only;
+//   owners   records as two arrays (RecBuf): hot parts (voxel word,
+//            offsets, velocity: 32 B per owner) and cold parts (angular
+//            velocity, mass: 16 B), so a stream over owners at rest and a
+//            gather of a contact partner's position move hot parts only;
 //            OwnerAux[No] (inverse inertia + template), double4 q[No]
 //   spheres  SphRec[Ns] (owner, radius, material, template component)
 //   contacts per active-set buffer: acs_start[Ns+1] (CSR by lower sphere
@@ -34,16 +33,14 @@ struct __align__(16) OwnerRec {
 static_assert(sizeof(OwnerRec) == 48, "owner record must be 48 bytes");
 
 // Owner records in device memory (OwnerRec is their form in registers):
-// tiles of REC_TILE consecutive owners, owner o in tile o / 64 at lane
-// o % 64; its hot part is hot[2 lane .. 2 lane + 1] (the record's first 32
-// bytes: vox, off, v), its cold part cold[lane] (w, mass).
-constexpr int REC_TILE = 64;
-struct __align__(16) RecTile {
-    uint4 hot[2 * REC_TILE];
-    uint4 cold[REC_TILE];
+// two arrays, the hot parts (voxel word, offsets, velocity: the record's
+// first 32 bytes, hot[2 o] and hot[2 o + 1]) and the cold parts (angular
+// velocity, mass: cold[o]).  A wave's 64 records staged in LDS take the
+// same form (rec_lds).
+struct RecBuf {
+    uint4 *hot;
+    uint4 *cold;
 };
-static_assert(sizeof(RecTile) == 3072, "record tile must be 3 KiB");
-inline int64_t rec_tiles(int64_t n_owners) { return (n_owners + REC_TILE - 1) / REC_TILE; }
 
 struct __align__(16) OwnerAux {
     float inv_moi[3];
@@ -180,7 +177,7 @@ void radix_sort_u32(uint32_t **keys, uint32_t **vals, uint32_t **keys_alt, uint3
                     int64_t n, int bits, uint32_t *hist, uint32_t *partials, hipStream_t s);
 
 struct DetectArgs {
-    const RecTile *recs;
+    RecBuf recs;
     const double *q;        // 4 per owner
     const OwnerAux *aux;
     const SphRec *sph;
@@ -299,7 +296,7 @@ void launch_remap(const AcsBuf &oldb, AcsBuf &newb, int64_t n_spheres, DevCounte
                   int rolling, hipStream_t s);
 
 struct DynArgs {
-    RecTile *recs;
+    RecBuf recs;
     double *q;
     const OwnerAux *aux;
     const float *inv_i;     // per owner: isotropic inverse moment of inertia (single spheres)
@@ -395,7 +392,7 @@ struct SplitTiming {
 // the step runs as the streaming kernel plus the kernel over the owners with
 // contacts (DynArgs::split, for a system and set that allow it)
 bool step_is_split(const DynArgs &a, const AcsBuf &cur);
-bool launch_step_fused(const DynArgs &a, RecTile *rec_out, double *q_out, const AcsBuf &cur, int64_t cap,
+bool launch_step_fused(const DynArgs &a, RecBuf rec_out, double *q_out, const AcsBuf &cur, int64_t cap,
                        DevCounters *ctr, hipStream_t s, const SplitTiming *tm = nullptr);
 // an empty one-wave kernel stamped with events (overhead of the stamps)
 void launch_noop(hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
@@ -403,7 +400,7 @@ void launch_noop(hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 // adaptive schedule: margin of the next detection from the top speed
 // (after launch_reduce_max), into ctr->margin
 // owners of fixed families: v = w = 0 in `rec`, and both state buffers equal
-void launch_fix_owners(RecTile *rec, RecTile *rec_alt, const double *q, double *q_alt, const uint8_t *ofam,
+void launch_fix_owners(RecBuf rec, RecBuf rec_alt, const double *q, double *q_alt, const uint8_t *ofam,
                        const uint8_t *fixed, int64_t n_owners, hipStream_t s);
 void launch_adaptive_margin(DevCounters *ctr, double t, double gmag, double cap, double vfloor, hipStream_t s);
 void launch_reduce_max(const DynArgs &a, DevCounters *ctr, hipStream_t s);
@@ -427,12 +424,12 @@ struct LearnedArgs {
 // decision on the device, writing out[0] = the next interval, out[1] = the
 // analytic bound, out[2] = the bits of the smallest prediction; the
 // snapshot is overwritten by the current state.
-void learned_decide(const RecTile *rec, SnapRec *snap, const float *ovol, Origin org, Grid fg, float h,
+void learned_decide(RecBuf rec, SnapRec *snap, const float *ovol, Origin org, Grid fg, float h,
                     float margin, float tau, uint32_t *raw, const float *params, float *pslot, const float *blkmax,
                     int64_t nblk, const LearnedArgs &p, int64_t *out, int64_t No, hipStream_t s);
 int64_t learned_slots(int64_t ncell);
-void snapshot_write(const RecTile *rec, SnapRec *snap, int64_t No, hipStream_t s);
-void feature_pipeline(const RecTile *rec, const SnapRec *snap, const float *ovol, Origin org, Grid fg, float h,
+void snapshot_write(RecBuf rec, SnapRec *snap, int64_t No, hipStream_t s);
+void feature_pipeline(RecBuf rec, const SnapRec *snap, const float *ovol, Origin org, Grid fg, float h,
                       float margin, float tau, uint32_t *raw, uint32_t *flags, uint32_t *pos, uint32_t *partials,
                       uint32_t *cellmap, float *out, uint32_t *cell_ids, int64_t No, hipStream_t s);
 // number of slots of the per-block |v|^2 maxima the last step wrote

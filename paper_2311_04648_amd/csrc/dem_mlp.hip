@@ -259,14 +259,14 @@ __device__ inline void feat_global_add(uint32_t *rw, const uint32_t *a, unsigned
     atomicAdd(reinterpret_cast<unsigned long long *>(&rw[10]), vol);
 }
 
-__global__ void __launch_bounds__(256) k_feat_accum(const RecTile *rec, const SnapRec *snap, SnapRec *snap_out,
+__global__ void __launch_bounds__(256) k_feat_accum(RecBuf rec, const SnapRec *snap, SnapRec *snap_out,
                                                    const float *ovol, Origin org, Grid fg, uint32_t *raw,
                                                    uint32_t *cellmap, int64_t No)
 {
     __shared__ uint32_t tkey[FEAT_SLOTS];
     __shared__ uint32_t tval[FEAT_SLOTS][FEAT_MAXW];
     __shared__ unsigned long long tvol[FEAT_SLOTS];
-    __shared__ uint4 lrec[4][192];
+    __shared__ uint4 lrec[4][128];   // hot parts
     for (int k = threadIdx.x; k < FEAT_SLOTS; k += blockDim.x) {
         tkey[k] = FEAT_EMPTY;
         for (int j = 0; j < FEAT_MAXW; ++j) tval[k][j] = 0u;
@@ -284,7 +284,7 @@ __global__ void __launch_bounds__(256) k_feat_accum(const RecTile *rec, const Sn
         const uint32_t nv = (uint32_t)(No - ow < 64 ? No - ow : 64);
         // the hot parts of the wave's records (one tile) through LDS: two
         // contiguous 1 KiB loads (the features need position and velocity)
-        tile_copy(lrec[wv], reinterpret_cast<const uint4 *>(rec + (ow >> 6)), nv, lane, false);
+        rec_copy(RecBuf{lrec[wv], nullptr}, 0, rec, ow, nv, lane, false);
         SnapRec sr{};
         float vo = 0.0f;
         if (valid) {
@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(256) k_feat_accum(const RecTile *rec, const Sn
         uint32_t a[FEAT_MAXW] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
         unsigned long long iv = 0ull;
         if (valid) {
-            const OwnerRec r = load_rec_hot(reinterpret_cast<const RecTile *>(lrec[wv]), lane);
+            const OwnerRec r = load_rec_hot(RecBuf{lrec[wv], nullptr}, lane);
             double X[3], Xs[3];
             for (int k = 0; k < 3; ++k) {
                 X[k] = decode_axis(r.vox, r.off[k], org.o[k], k);
@@ -545,7 +545,7 @@ __global__ void __launch_bounds__(256) k_learned_decide(const float *blkmax, int
     out[2] = (int64_t)__float_as_uint(R);
 }
 
-__global__ void __launch_bounds__(256) k_snap_write(const RecTile *rec, SnapRec *snap, int64_t No)
+__global__ void __launch_bounds__(256) k_snap_write(RecBuf rec, SnapRec *snap, int64_t No)
 {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= No) return;
@@ -563,7 +563,7 @@ __global__ void __launch_bounds__(256) k_snap_write(const RecTile *rec, SnapRec 
 
 // Feature pipeline used by both dem_features and the learned schedule:
 // the per-cell accumulators of the owners' contributions (see k_feat_accum).
-static void feature_accumulate(const RecTile *rec, const SnapRec *snap, SnapRec *snap_out, const float *ovol,
+static void feature_accumulate(RecBuf rec, const SnapRec *snap, SnapRec *snap_out, const float *ovol,
                                Origin org, Grid fg, uint32_t *raw, uint32_t *cellmap, int64_t No, hipStream_t s)
 {
     const int64_t nc = (int64_t)fg.nbins;
@@ -576,7 +576,7 @@ static void feature_accumulate(const RecTile *rec, const SnapRec *snap, SnapRec 
 
 // Features of occupied cells written to `out` (row-major, cell order) and
 // their count to pos[ncell]; cellmap[o] receives each owner's cell.
-void feature_pipeline(const RecTile *rec, const SnapRec *snap, const float *ovol, Origin org, Grid fg, float h,
+void feature_pipeline(RecBuf rec, const SnapRec *snap, const float *ovol, Origin org, Grid fg, float h,
                       float margin, float tau, uint32_t *raw, uint32_t *flags, uint32_t *pos, uint32_t *partials,
                       uint32_t *cellmap, float *out, uint32_t *cell_ids, int64_t No, hipStream_t s)
 {
@@ -601,7 +601,7 @@ int64_t learned_slots(int64_t ncell)
 // snapshot (written over by the current state), the network on every
 // occupied cell and the minimum of the predictions; then the interval
 // (k_learned_decide) into out[0..2].
-void learned_decide(const RecTile *rec, SnapRec *snap, const float *ovol, Origin org, Grid fg, float h,
+void learned_decide(RecBuf rec, SnapRec *snap, const float *ovol, Origin org, Grid fg, float h,
                     float margin, float tau, uint32_t *raw, const float *params, float *pslot, const float *blkmax,
                     int64_t nblk, const LearnedArgs &p, int64_t *out, int64_t No, hipStream_t s)
 {
@@ -618,7 +618,7 @@ void learned_decide(const RecTile *rec, SnapRec *snap, const float *ovol, Origin
     hipLaunchKernelGGL(k_learned_decide, dim3(1), dim3(256), 0, s, blkmax, nblk, pslot, np, p, out);
 }
 
-void snapshot_write(const RecTile *rec, SnapRec *snap, int64_t No, hipStream_t s)
+void snapshot_write(RecBuf rec, SnapRec *snap, int64_t No, hipStream_t s)
 {
     if (No > 0) hipLaunchKernelGGL(k_snap_write, dim3(nblocks(No, 256)), dim3(256), 0, s, rec, snap, No);
 }
