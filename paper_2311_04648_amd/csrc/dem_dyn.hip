@@ -1193,10 +1193,10 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
 // k_step_listed, which runs after it on the same stream over the set's list
 // of owners with contacts and does for each what the one-kernel step does
 // (owner_forces, then the integration), so both forms give the same bits.
-// A wave's 64 records (one tile) move through LDS, their hot parts in two
-// contiguous 1 KiB loads and stores, with the flags; the cold parts, the
-// inertia and the orientation only for owners that turn or have just
-// stopped turning.
+// Each lane loads and stores its owner's hot part (consecutive lanes,
+// consecutive 32-byte parts), with the flag; the cold part, the inertia
+// and the orientation only for owners that turn or have just stopped
+// turning.
 // REMAP: the first step on a newly adopted set (only its overflow check
 // matters here).
 constexpr int FREE_WAVES = 2;    // waves per block of k_step_free
@@ -1207,11 +1207,9 @@ template <bool REMAP>
 __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, RecBuf rec_out, double *q_out,
                                                               const uint8_t *oany, DevCounters *ctr)
 {
-    // each wave streams FREE_CHUNKS chunks of 64 consecutive owners (record
-    // tiles): the loads of all its chunks are issued before any chunk is
-    // computed, so a wave keeps that many tiles in flight; the chunks are
-    // then computed one after the other (registers for one at a time)
-    __shared__ uint4 wbuf[FREE_WAVES][FREE_CHUNKS][128];   // hot parts
+    // each wave streams FREE_CHUNKS chunks of 64 consecutive owners: the
+    // loads of all its chunks are issued before any chunk is computed, so a
+    // wave keeps that many chunks in flight
     const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t No = a.n_owners;
     const uint32_t lane = threadIdx.x & 63u;
@@ -1239,23 +1237,22 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, RecBuf
     }
     float v2 = 0.0f, g2 = 0.0f;
     uint8_t fl[FREE_CHUNKS];
-    // loads: flags and the hot parts of the records (through LDS) of every
-    // chunk; a stopped step copies the cold parts, unchanged, straight over
+    OwnerRec rh[FREE_CHUNKS];
+    // loads: flags and the hot parts of the records of every chunk, all
+    // issued before any is used (consecutive lanes read consecutive 32-byte
+    // hot parts: each pair of 16-byte loads covers whole lines); a stopped
+    // step copies the cold parts, unchanged, straight over
 #pragma unroll
     for (int c = 0; c < FREE_CHUNKS; ++c) {
-        const int64_t ow = ob + (int64_t)(wv * FREE_CHUNKS + c) * 64;
-        const int64_t o = ow + lane;
-        const uint32_t nv = ow < No ? (uint32_t)(No - ow < 64 ? No - ow : 64) : 0u;
+        const int64_t o = ob + (int64_t)(wv * FREE_CHUNKS + c) * 64 + lane;
         fl[c] = 1u;
-        if (o < No) fl[c] = oany[o];
-        if (nv > 0) {
-            rec_copy(RecBuf{wbuf[wv][c], nullptr}, 0, a.recs, ow, nv, lane, false);
-            if (halt && lane < nv) rec_out.cold[ow + lane] = a.recs.cold[ow + lane];
+        rh[c] = OwnerRec{};
+        if (o < No) {
+            fl[c] = oany[o];
+            rh[c] = load_rec_hot(a.recs, o);
+            if (halt) rec_out.cold[o] = a.recs.cold[o];
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // An owner without contacts whose record carries DEM_VOX_QSAME is
     // still: its angular velocity is zero in both record buffers (without
     // torque it stays zero) and both orientation buffers hold its
@@ -1264,14 +1261,13 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, RecBuf
     // with zero force the mass does not enter) nor its inertia nor its
     // orientation, and it writes only its hot part.  The others load their
     // cold part, inertia and template, and their orientation with them
-    // (used by clumps only).
-#pragma unroll 1
+    // (used by clumps only).  (The hot parts of owners with contacts go out
+    // unchanged here and are overwritten by k_step_listed.)
+#pragma unroll
     for (int c = 0; c < FREE_CHUNKS; ++c) {
-        const int64_t ow = ob + (int64_t)(wv * FREE_CHUNKS + c) * 64;
-        const int64_t o = ow + lane;
+        const int64_t o = ob + (int64_t)(wv * FREE_CHUNKS + c) * 64 + lane;
         const bool valid = o < No;
-        OwnerRec r{};
-        if (valid) r = load_rec_hot(RecBuf{wbuf[wv][c], nullptr}, lane);
+        OwnerRec r = rh[c];
         const bool still = !halt && !(fl[c] & 1u) && (r.vox & DEM_VOX_QSAME) != 0;
         const bool cold = valid && !halt && !(fl[c] & 1u) && !still;
         r.mass = 1.0f;   // (a still owner's: any positive value gives the same zero force term)
@@ -1286,8 +1282,7 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, RecBuf
         double *qo = q_out + 4 * (size_t)o;
         if (halt) {
             // a stopped step: the state is copied unchanged (the records
-            // here and below, the orientation here; the history by
-            // k_step_listed)
+            // here, the orientation here; the history by k_step_listed)
             if (rot) *reinterpret_cast<double4 *>(qo) = qv;
         } else if (valid && !(fl[c] & 1u)) {
             // (a still owner: zero torque on zero angular velocity, no
@@ -1302,20 +1297,9 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, RecBuf
             // velocity, and both orientation buffers the orientation, if
             // the owner neither turned before this step nor in it
             if (w0 && r.w[0] == 0.0f && r.w[1] == 0.0f && r.w[2] == 0.0f) r.vox |= DEM_VOX_QSAME;
-            store_rec_hot(RecBuf{wbuf[wv][c], nullptr}, lane, r);
             if (cold) rec_out.cold[o] = rec_cold(r);
         }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // (the records of owners with contacts go out unchanged here and are
-    // overwritten by k_step_listed)
-#pragma unroll
-    for (int c = 0; c < FREE_CHUNKS; ++c) {
-        const int64_t ow = ob + (int64_t)(wv * FREE_CHUNKS + c) * 64;
-        const uint32_t nv = ow < No ? (uint32_t)(No - ow < 64 ? No - ow : 64) : 0u;
-        if (nv > 0) rec_copy(rec_out, ow, RecBuf{wbuf[wv][c], nullptr}, 0, nv, lane, false);
+        if (valid) store_rec_hot(rec_out, o, r);
     }
     if (halt) return;
     __shared__ float wmax[2][FREE_WAVES];
