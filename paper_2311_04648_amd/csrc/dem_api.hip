@@ -274,10 +274,12 @@ void carve_cd(Carver &c, const dem_ctx *ctx, CdWork &w)
 void carve(Carver &c, dem_ctx *ctx, int64_t cap)
 {
     int64_t No = ctx->No, Ns = ctx->Ns;
-    ctx->rec.hot = c.take<uint4>(2 * No);
-    ctx->rec.cold = c.take<uint4>(No);
-    ctx->rec_alt.hot = c.take<uint4>(2 * No);
-    ctx->rec_alt.cold = c.take<uint4>(No);
+    // (clump systems split each record into a hot and a cold part; single-
+    // sphere systems keep whole records)
+    for (RecBuf *b : {&ctx->rec, &ctx->rec_alt}) {
+        b->hot = c.take<uint4>((ctx->has_clumps ? 2 : 3) * No);
+        b->cold = ctx->has_clumps ? c.take<uint4>(No) : nullptr;
+    }
     ctx->fref = c.take<SnapRec>(No);
     ctx->d_ovol = c.take<float>(No);
     ctx->q = c.take<double>(4 * No);
@@ -1099,27 +1101,44 @@ dem_status dem_bind(dem_ctx *ctx, void *device_workspace, int64_t bytes, int64_t
 
 static void rebuild_dormant_index(dem_ctx *ctx, hipStream_t s);
 
-// Owner records to and from their device form: bytes 0-31 of an OwnerRec
-// are its hot part (two uint4 of the hot array), bytes 32-47 its cold part.
-static void rec_split(const std::vector<OwnerRec> &rec, std::vector<uint4> &hot, std::vector<uint4> &cold)
+// Owner records to and from their device form (RecBuf): split, bytes 0-31
+// of an OwnerRec are its hot part (two uint4 of the hot array), bytes 32-47
+// its cold part; whole records are the OwnerRec bytes themselves.
+static dem_status rec_upload(dem_ctx *ctx, const RecBuf &b, const std::vector<OwnerRec> &rec, hipStream_t s)
 {
     const size_t n = rec.size();
-    hot.resize(2 * n);
-    cold.resize(n);
+    if (!b.cold) {
+        HIPCHK(hipMemcpyAsync(b.hot, rec.data(), sizeof(OwnerRec) * n, hipMemcpyHostToDevice, s));
+        return DEM_OK;
+    }
+    std::vector<uint4> hot(2 * n), cold(n);
     for (size_t o = 0; o < n; ++o) {
         std::memcpy(static_cast<void *>(&hot[2 * o]), &rec[o], 32);
         std::memcpy(static_cast<void *>(&cold[o]), reinterpret_cast<const char *>(&rec[o]) + 32, 16);
     }
+    HIPCHK(hipMemcpyAsync(b.hot, hot.data(), sizeof(uint4) * hot.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(b.cold, cold.data(), sizeof(uint4) * cold.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));   // (the staging vectors end here)
+    return DEM_OK;
 }
 
-static std::vector<OwnerRec> rec_join(const std::vector<uint4> &hot, const std::vector<uint4> &cold)
+static dem_status rec_download(dem_ctx *ctx, const RecBuf &b, std::vector<OwnerRec> &rec, hipStream_t s)
 {
-    std::vector<OwnerRec> rec(cold.size());
-    for (size_t o = 0; o < rec.size(); ++o) {
+    const int64_t n = (int64_t)rec.size();
+    if (!b.cold) {
+        HIPCHK(hipMemcpyAsync(rec.data(), b.hot, sizeof(OwnerRec) * n, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return DEM_OK;
+    }
+    std::vector<uint4> hot(2 * n), cold(n);
+    HIPCHK(hipMemcpyAsync(hot.data(), b.hot, sizeof(uint4) * hot.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(cold.data(), b.cold, sizeof(uint4) * cold.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int64_t o = 0; o < n; ++o) {
         std::memcpy(&rec[o], &hot[2 * o], 32);
         std::memcpy(reinterpret_cast<char *>(&rec[o]) + 32, &cold[o], 16);
     }
-    return rec;
+    return DEM_OK;
 }
 
 dem_status dem_set_state(dem_ctx *ctx, const double *X, const double *q, const float *v, const float *w,
@@ -1164,13 +1183,11 @@ dem_status dem_set_state(dem_ctx *ctx, const double *X, const double *q, const f
         }
         rec[o] = r;
     }
-    std::vector<uint4> hot, cold;
-    rec_split(rec, hot, cold);
     // the fused step does not rewrite the records of fixed owners: both
     // buffers start equal
     for (const RecBuf &b : {ctx->rec, ctx->rec_alt}) {
-        HIPCHK(hipMemcpyAsync(b.hot, hot.data(), sizeof(uint4) * hot.size(), hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(b.cold, cold.data(), sizeof(uint4) * cold.size(), hipMemcpyHostToDevice, s));
+        const dem_status st = rec_upload(ctx, b, rec, s);
+        if (st != DEM_OK) return st;
     }
     HIPCHK(hipMemcpyAsync(ctx->q, qd.data(), sizeof(double) * 4 * ctx->No, hipMemcpyHostToDevice, s));
     // the fused step leaves the orientations of single-sphere systems alone,
@@ -1200,13 +1217,12 @@ dem_status dem_get_state(dem_ctx *ctx, double *X, double *q, float *v, float *w,
         return DEM_ERR_STATE;
     }
     hipStream_t s = S(stream);
-    std::vector<uint4> hot(2 * ctx->No), cold(ctx->No);
     std::vector<double> qd(4 * ctx->No);
-    HIPCHK(hipMemcpyAsync(hot.data(), ctx->rec.hot, sizeof(uint4) * hot.size(), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(cold.data(), ctx->rec.cold, sizeof(uint4) * cold.size(), hipMemcpyDeviceToHost, s));
+    std::vector<OwnerRec> rec(ctx->No);
+    const dem_status st = rec_download(ctx, ctx->rec, rec, s);
+    if (st != DEM_OK) return st;
     HIPCHK(hipMemcpyAsync(qd.data(), ctx->q, sizeof(double) * 4 * ctx->No, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    const std::vector<OwnerRec> rec = rec_join(hot, cold);
     for (int64_t o = 0; o < ctx->No; ++o) {
         const OwnerRec &r = rec[o];
         for (int k = 0; k < 3; ++k) {

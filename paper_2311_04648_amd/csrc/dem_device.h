@@ -165,22 +165,26 @@ __device__ inline uint4 rec_cold(const OwnerRec &r)
                       __float_as_uint(r.mass));
 }
 
-// Owner o's record: three 16-byte loads.
+// Owner o's record: three 16-byte loads.  Two layouts (RecBuf): clump
+// systems keep hot and cold parts in two arrays; single-sphere systems
+// (cold null) whole 48-byte records in one array, three uint4 per owner.
 __device__ inline OwnerRec load_rec(const RecBuf &b, int64_t o)
 {
-    return rec_from(b.hot[2 * o], b.hot[2 * o + 1], b.cold[o]);
+    if (b.cold) return rec_from(b.hot[2 * o], b.hot[2 * o + 1], b.cold[o]);
+    return rec_from(b.hot[3 * o], b.hot[3 * o + 1], b.hot[3 * o + 2]);
 }
 
 // Its hot part only (position and velocity; w and mass read as zero).
 __device__ inline OwnerRec load_rec_hot(const RecBuf &b, int64_t o)
 {
-    return rec_from(b.hot[2 * o], b.hot[2 * o + 1], make_uint4(0u, 0u, 0u, 0u));
+    const int64_t k = (b.cold ? 2 : 3) * o;
+    return rec_from(b.hot[k], b.hot[k + 1], make_uint4(0u, 0u, 0u, 0u));
 }
 
 // Its cold part into r (w, mass).
 __device__ inline void load_rec_cold(const RecBuf &b, int64_t o, OwnerRec &r)
 {
-    const uint4 c = b.cold[o];
+    const uint4 c = b.cold ? b.cold[o] : b.hot[3 * o + 2];
     r.w[0] = __uint_as_float(c.x);
     r.w[1] = __uint_as_float(c.y);
     r.w[2] = __uint_as_float(c.z);
@@ -189,29 +193,49 @@ __device__ inline void load_rec_cold(const RecBuf &b, int64_t o, OwnerRec &r)
 
 __device__ inline void store_rec(const RecBuf &b, int64_t o, const OwnerRec &r)
 {
-    b.hot[2 * o] = rec_hot0(r);
-    b.hot[2 * o + 1] = rec_hot1(r);
-    b.cold[o] = rec_cold(r);
+    const int64_t k = (b.cold ? 2 : 3) * o;
+    b.hot[k] = rec_hot0(r);
+    b.hot[k + 1] = rec_hot1(r);
+    if (b.cold) b.cold[o] = rec_cold(r);
+    else b.hot[k + 2] = rec_cold(r);
 }
 
 __device__ inline void store_rec_hot(const RecBuf &b, int64_t o, const OwnerRec &r)
 {
+    const int64_t k = (b.cold ? 2 : 3) * o;
+    b.hot[k] = rec_hot0(r);
+    b.hot[k + 1] = rec_hot1(r);
+}
+
+// The same for split records (clump systems) only: no layout test.
+__device__ inline OwnerRec load_split_hot(const RecBuf &b, int64_t o)
+{
+    return rec_from(b.hot[2 * o], b.hot[2 * o + 1], make_uint4(0u, 0u, 0u, 0u));
+}
+
+__device__ inline void store_split_hot(const RecBuf &b, int64_t o, const OwnerRec &r)
+{
     b.hot[2 * o] = rec_hot0(r);
     b.hot[2 * o + 1] = rec_hot1(r);
 }
 
-// A wave's 64 records in LDS (192 uint4: hot parts, then cold parts).
-__device__ inline RecBuf rec_lds(uint4 *buf)
+// A wave's 64 records in LDS (192 uint4) in the layout of `like`.
+__device__ inline RecBuf rec_lds(uint4 *buf, const RecBuf &like)
 {
-    return RecBuf{buf, buf + 128};
+    return RecBuf{buf, like.cold ? buf + 128 : nullptr};
 }
 
 // One wave copies the records of n owners, from src owner s0 to dst owner
-// d0 (global memory or LDS): their hot parts, and their cold parts if
-// `cold`.
+// d0 (global memory or LDS, both in one layout): their hot parts, and
+// their cold parts if `cold` (whole records are copied where they are not
+// split).
 __device__ inline void rec_copy(const RecBuf &dst, int64_t d0, const RecBuf &src, int64_t s0, uint32_t n,
                                 uint32_t lane, bool cold)
 {
+    if (!src.cold) {
+        for (uint32_t k = lane; k < 3u * n; k += 64u) dst.hot[3 * d0 + k] = src.hot[3 * s0 + k];
+        return;
+    }
     for (uint32_t k = lane; k < 2u * n; k += 64u) dst.hot[2 * d0 + k] = src.hot[2 * s0 + k];
     if (cold)
         for (uint32_t k = lane; k < n; k += 64u) dst.cold[d0 + k] = src.cold[s0 + k];

@@ -217,10 +217,12 @@ __device__ __forceinline__ void contact_eval(const DynArgs &a, const SphRec &sA,
             xB[1] = xBk[1];
             xB[2] = xBk[2];
         } else {
-            // the partner's hot part first (its centre); its angular
-            // velocity and mass only if the pair touches
+            // (the whole record in one round trip: reading the cold part
+            // only once the pair is found touching costs touching pairs a
+            // second round trip, which the step pays for more than the
+            // bytes)
             sB = load_sph(a.sph + jp);
-            OwnerRec rB = load_rec_hot(a.recs, SINGLES ? jp : sB.owner);
+            const OwnerRec rB = load_rec(a.recs, SINGLES ? jp : sB.owner);
             owner_kin(rB, sB, a.aux, a.q, a.tpos, a.org, kB, xB);
         }
         double dx = xA[0] - xB[0], dy = xA[1] - xB[1], dz = xA[2] - xB[2];
@@ -229,11 +231,6 @@ __device__ __forceinline__ void contact_eval(const DynArgs &a, const SphRec &sA,
         double T = radA + radB;
         touching = d2 < T * T;
         if (GAPW) out.gap = touching ? -1.0 : sqrt(d2) - T;
-        if (!KNOWN_B && touching) {
-            OwnerRec rB = load_rec_hot(a.recs, SINGLES ? jp : sB.owner);
-            load_rec_cold(a.recs, SINGLES ? jp : sB.owner, rB);
-            owner_kin(rB, sB, a.aux, a.q, a.tpos, a.org, kB, xB);
-        }
         if (touching) {
             double d = sqrt(d2);
             nrm[0] = dx / d;
@@ -1030,11 +1027,11 @@ __device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, u
     const uint32_t nv = (uint32_t)(No - ow < 64 ? No - ow : 64);
     OwnerRec rpre{};
     if constexpr (SINGLES) {
-        rec_copy(rec_lds(lrec), 0, a.recs, ow, nv, lane, true);
+        rec_copy(rec_lds(lrec, a.recs), 0, a.recs, ow, nv, lane, true);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (valid) rpre = load_rec(rec_lds(lrec), lane);
+        if (valid) rpre = load_rec(rec_lds(lrec, a.recs), lane);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1094,12 +1091,12 @@ __device__ __forceinline__ float step_wave(const DynArgs &a, const int64_t ow, u
     float v2 = 0.0f;
     if (st.advance) {
         v2 = advance(a, st.r, st.inv, false, st.F, st.T, st.qv, q_out + 4 * (size_t)o, ctr);
-        store_rec(rec_lds(lrec), lane, st.r);
+        store_rec(rec_lds(lrec, a.recs), lane, st.r);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    rec_copy(rec_out, ow, rec_lds(lrec), 0, nv, lane, true);
+    rec_copy(rec_out, ow, rec_lds(lrec, rec_out), 0, nv, lane, true);
     return v2;
 }
 
@@ -1194,9 +1191,9 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
 // of owners with contacts and does for each what the one-kernel step does
 // (owner_forces, then the integration), so both forms give the same bits.
 // Each lane loads and stores its owner's hot part (consecutive lanes,
-// consecutive 32-byte parts), with the flag; the cold part, the inertia
-// and the orientation only for owners that turn or have just stopped
-// turning.
+// consecutive 32-byte parts: clump systems split their records), with the
+// flag; the cold part, the inertia and the orientation only for owners
+// that turn or have just stopped turning.
 // REMAP: the first step on a newly adopted set (only its overflow check
 // matters here).
 constexpr int FREE_WAVES = 2;    // waves per block of k_step_free
@@ -1249,7 +1246,7 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, RecBuf
         rh[c] = OwnerRec{};
         if (o < No) {
             fl[c] = oany[o];
-            rh[c] = load_rec_hot(a.recs, o);
+            rh[c] = load_split_hot(a.recs, o);
             if (halt) rec_out.cold[o] = a.recs.cold[o];
         }
     }
@@ -1273,7 +1270,13 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, RecBuf
         r.mass = 1.0f;   // (a still owner's: any positive value gives the same zero force term)
         OwnerAux ax{{0.0f, 0.0f, 0.0f}, -1};
         double4 qv = make_double4(1.0, 0.0, 0.0, 0.0);
-        if (cold) load_rec_cold(a.recs, o, r);
+        if (cold) {
+            const uint4 cw = a.recs.cold[o];
+            r.w[0] = __uint_as_float(cw.x);
+            r.w[1] = __uint_as_float(cw.y);
+            r.w[2] = __uint_as_float(cw.z);
+            r.mass = __uint_as_float(cw.w);
+        }
         if (valid && (halt || cold)) {
             ax = a.aux[o];
             qv = *reinterpret_cast<const double4 *>(a.q + 4 * (size_t)o);
@@ -1299,7 +1302,7 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, RecBuf
             if (w0 && r.w[0] == 0.0f && r.w[1] == 0.0f && r.w[2] == 0.0f) r.vox |= DEM_VOX_QSAME;
             if (cold) rec_out.cold[o] = rec_cold(r);
         }
-        if (valid) store_rec_hot(rec_out, o, r);
+        if (valid) store_split_hot(rec_out, o, r);
     }
     if (halt) return;
     __shared__ float wmax[2][FREE_WAVES];

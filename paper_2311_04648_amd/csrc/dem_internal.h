@@ -1,9 +1,10 @@
 // Internal declarations shared by the HIP kernels and the host side of the
 // DEM library (gfx950).  Device data layout:
-//   owners   records as two arrays (RecBuf): hot parts (voxel word,
-//            offsets, velocity: 32 B per owner) and cold parts (angular
-//            velocity, mass: 16 B), so a stream over owners at rest and a
-//            gather of a contact partner's position move hot parts only;
+//   owners   records (RecBuf): in clump systems two arrays, hot parts
+//            (voxel word, offsets, velocity: 32 B per owner) and cold parts
+//            (angular velocity, mass: 16 B), so a stream over owners at rest
+//            moves hot parts only; in single-sphere systems whole 48 B
+//            records, so a gather of a contact partner reads one record;
 //            OwnerAux[No] (inverse inertia + template), double4 q[No]
 //   spheres  SphRec[Ns] (owner, radius, material, template component)
 //   contacts per active-set buffer: acs_start[Ns+1] (CSR by lower sphere
@@ -32,11 +33,13 @@ struct __align__(16) OwnerRec {
 };
 static_assert(sizeof(OwnerRec) == 48, "owner record must be 48 bytes");
 
-// Owner records in device memory (OwnerRec is their form in registers):
-// two arrays, the hot parts (voxel word, offsets, velocity: the record's
-// first 32 bytes, hot[2 o] and hot[2 o + 1]) and the cold parts (angular
-// velocity, mass: cold[o]).  A wave's 64 records staged in LDS take the
-// same form (rec_lds).
+// Owner records in device memory (OwnerRec is their form in registers).
+// Clump systems: two arrays, the hot parts (voxel word, offsets, velocity:
+// the record's first 32 bytes, hot[2 o] and hot[2 o + 1]) and the cold
+// parts (angular velocity, mass: cold[o]).  Single-sphere systems, whose
+// steps gather whole partner records: one array of whole records,
+// hot[3 o .. 3 o + 2], cold null.  A wave's 64 records staged in LDS take
+// the layout of the array they come from (rec_lds).
 struct RecBuf {
     uint4 *hot;
     uint4 *cold;

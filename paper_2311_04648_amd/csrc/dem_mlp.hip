@@ -266,7 +266,7 @@ __global__ void __launch_bounds__(256) k_feat_accum(RecBuf rec, const SnapRec *s
     __shared__ uint32_t tkey[FEAT_SLOTS];
     __shared__ uint32_t tval[FEAT_SLOTS][FEAT_MAXW];
     __shared__ unsigned long long tvol[FEAT_SLOTS];
-    __shared__ uint4 lrec[4][128];   // hot parts
+    __shared__ uint4 lrec[4][192];
     for (int k = threadIdx.x; k < FEAT_SLOTS; k += blockDim.x) {
         tkey[k] = FEAT_EMPTY;
         for (int j = 0; j < FEAT_MAXW; ++j) tval[k][j] = 0u;
@@ -282,9 +282,10 @@ __global__ void __launch_bounds__(256) k_feat_accum(RecBuf rec, const SnapRec *s
         const int64_t o = ow + lane;
         const bool valid = o < No;
         const uint32_t nv = (uint32_t)(No - ow < 64 ? No - ow : 64);
-        // the hot parts of the wave's records (one tile) through LDS: two
-        // contiguous 1 KiB loads (the features need position and velocity)
-        rec_copy(RecBuf{lrec[wv], nullptr}, 0, rec, ow, nv, lane, false);
+        // the wave's records through LDS, in contiguous 1 KiB loads (of
+        // hot parts only where records are split: the features need
+        // position and velocity)
+        rec_copy(rec_lds(lrec[wv], rec), 0, rec, ow, nv, lane, false);
         SnapRec sr{};
         float vo = 0.0f;
         if (valid) {
@@ -298,7 +299,7 @@ __global__ void __launch_bounds__(256) k_feat_accum(RecBuf rec, const SnapRec *s
         uint32_t a[FEAT_MAXW] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
         unsigned long long iv = 0ull;
         if (valid) {
-            const OwnerRec r = load_rec_hot(RecBuf{lrec[wv], nullptr}, lane);
+            const OwnerRec r = load_rec_hot(rec_lds(lrec[wv], rec), lane);
             double X[3], Xs[3];
             for (int k = 0; k < 3; ++k) {
                 X[k] = decode_axis(r.vox, r.off[k], org.o[k], k);
