@@ -431,6 +431,7 @@ DetectArgs detect_args(const dem_ctx *ctx, double margin, int64_t step)
     a.dcand = ctx->d_dcand;
     a.dcandf = ctx->d_dcandf;
     a.owner_list = owner_list_wanted(ctx) ? 1 : 0;
+    a.nt = stream_nt(ctx->No) ? 1 : 0;
     return a;
 }
 
@@ -504,6 +505,7 @@ DynArgs dyn_args(const dem_ctx *ctx, int64_t step)
     a.gD = ctx->d_gD;
     a.vgeom = std::max(ctx->vmesh, ctx->vwall);
     a.arm = ctx->arm;
+    a.nt = stream_nt(ctx->No) ? 1 : 0;
     return a;
 }
 

@@ -61,17 +61,25 @@ __global__ void __launch_bounds__(TPB) k_cd_prepare(DetectArgs a, uint32_t *keys
     }
     const uint32_t rk = wave_run_claim(cell_count, key, active && !dorm);
     if (!active) return;
-    keys[i] = key;
+    if (a.nt) st_nt_u32(key, keys + i);
+    else keys[i] = key;
     if (vals) vals[i] = (uint32_t)i;   // ids to sort (the one-pass sort writes its own)
     if (dorm) return;
-    rank[i] = rk;
+    if (a.nt) st_nt_u32(rk, rank + i);
+    else rank[i] = rk;
     Cand c;
     c.x = x[0];
     c.y = x[1];
     c.z = x[2];
     c.r = s.rad;
     c.id = (uint32_t)i;
-    cand_tmp[i] = c;
+    if (a.nt) {
+        uint4 *d = reinterpret_cast<uint4 *>(cand_tmp + i);
+        st_nt(make_uint4(__double2loint(c.x), __double2hiint(c.x), __double2loint(c.y), __double2hiint(c.y)), d);
+        st_nt(make_uint4(__double2loint(c.z), __double2hiint(c.z), __float_as_uint(c.r), c.id), d + 1);
+    } else {
+        cand_tmp[i] = c;
+    }
 }
 
 // One-pass sort of (bin key, sphere id): the per-bin counts and their scan
@@ -116,7 +124,7 @@ __global__ void __launch_bounds__(TPB) k_bucket_order(const uint32_t *cell_start
 // n + 1 entries each, zeroed here rather than by a launch of their own)
 __global__ void __launch_bounds__(TPB) k_cand_gather(const uint32_t *vals, const Cand *cand_tmp,
                                                      Cand *cand, float4 *candf, Grid g, int64_t n,
-                                                     const uint32_t *cell_start, uint32_t *z1, uint32_t *z2)
+                                                     const uint32_t *cell_start, uint32_t *z1, uint32_t *z2, bool nt)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (z1 && p < n) {
@@ -130,7 +138,9 @@ __global__ void __launch_bounds__(TPB) k_cand_gather(const uint32_t *vals, const
     if (p >= n || p >= (int64_t)cell_start[g.nbins]) return;   // (dormant spheres sit after the binned ones)
     const Cand c = cand_tmp[vals[p]];
     if (cand) cand[p] = c;   // (null: no walk over bins reads the records in bin order)
-    candf[p] = make_float4((float)(c.x - g.lo[0]), (float)(c.y - g.lo[1]), (float)(c.z - g.lo[2]), c.r);
+    const float4 f = make_float4((float)(c.x - g.lo[0]), (float)(c.y - g.lo[1]), (float)(c.z - g.lo[2]), c.r);
+    if (nt) st_nt(make_uint4(__float_as_uint(f.x), __float_as_uint(f.y), __float_as_uint(f.z), __float_as_uint(f.w)), reinterpret_cast<uint4 *>(candf + p));
+    else candf[p] = f;
 }
 
 __device__ inline bool sphere_pair_hit(double xi, double yi, double zi, double ri, const Cand &cj,
@@ -1178,7 +1188,7 @@ void launch_bin_back(const DetectArgs &a, CdWork &w, hipStream_t s, bool order_b
     // moving the records in the scatter instead costs more: random writes)
     hipLaunchKernelGGL(k_cand_gather, dim3(nblocks(n)), dim3(TPB), 0, s, w.vals, w.cand_tmp,
                        bin_cand ? w.cand : (Cand *)nullptr, w.candf, a.grid, n, (const uint32_t *)w.cell_start, z1,
-                       z2);
+                       z2, a.nt != 0);
 }
 
 void launch_bin(const DetectArgs &a, CdWork &w, hipStream_t s, uint32_t *z1, int64_t n1, uint32_t *z2,

@@ -208,15 +208,37 @@ __device__ inline void store_rec_hot(const RecBuf &b, int64_t o, const OwnerRec 
 }
 
 // The same for split records (clump systems) only: no layout test.
+// Stores of streams that no kernel reads back soon enough for a cache to
+// serve it (whole arrays larger than the caches): non-temporal, so they do
+// not evict data that is reused.
+typedef unsigned int u32x4_nt __attribute__((ext_vector_type(4)));
+__device__ inline void st_nt(uint4 v, uint4 *p)
+{
+    const u32x4_nt w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<u32x4_nt *>(p));
+}
+
+__device__ inline void st_nt_u32(uint32_t v, uint32_t *p)
+{
+    __builtin_nontemporal_store(v, p);
+}
+
 __device__ inline OwnerRec load_split_hot(const RecBuf &b, int64_t o)
 {
     return rec_from(b.hot[2 * o], b.hot[2 * o + 1], make_uint4(0u, 0u, 0u, 0u));
 }
 
-__device__ inline void store_split_hot(const RecBuf &b, int64_t o, const OwnerRec &r)
+// (nt: the streaming step's output of a state larger than the caches, read
+// back a whole array later)
+__device__ inline void store_split_hot(const RecBuf &b, int64_t o, const OwnerRec &r, bool nt)
 {
-    b.hot[2 * o] = rec_hot0(r);
-    b.hot[2 * o + 1] = rec_hot1(r);
+    if (nt) {
+        st_nt(rec_hot0(r), &b.hot[2 * o]);
+        st_nt(rec_hot1(r), &b.hot[2 * o + 1]);
+    } else {
+        b.hot[2 * o] = rec_hot0(r);
+        b.hot[2 * o + 1] = rec_hot1(r);
+    }
 }
 
 // A wave's 64 records in LDS (192 uint4) in the layout of `like`.

@@ -714,9 +714,11 @@ __device__ inline float gap_key(double g, double D)
 // skipped by the pairs' keys and the A rows' keys written (DynArgs::gap; Dn
 // is the step's reach), and an item's indices are loaded two items ahead,
 // its key one item ahead.
-// BOUNDS (clumps): the row and B-list bounds of the owner's first
-// BOUND_SPHERES spheres are loaded in one round before the sphere loop, so
-// that a sphere without items costs no round trip of its own.
+// BOUNDS (clumps, the owners of a set's list of owners with contacts): the
+// row and B-list bounds of the owner's first BOUND_SPHERES spheres are
+// loaded in one round before the sphere loop, so that a sphere without
+// items costs no round trip of its own; the owner's flag is known (it has
+// contacts, and such runs have no fixed families) and is not read.
 constexpr uint32_t BOUND_SPHERES = 6;
 
 template <bool SINGLES, bool FACETS, bool FIXED, bool AHEAD, bool REMAP, bool GAP = false, bool BOUNDS = false>
@@ -726,6 +728,7 @@ __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, 
     OwnerStep &st, const OwnerRec *pre = nullptr, const double Dn = 0.0)
 {
     static_assert(!GAP || !FIXED, "pair skipping is for systems without fixed families");
+    static_assert(!BOUNDS || !FIXED, "listed owners run without fixed families");
     st.advance = false;
     // The owner's flag byte, written with the set (bit 0: the owner has a
     // contact in it; bit 1: the owner is in a fixed family), read by the
@@ -751,7 +754,7 @@ __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, 
             st.tmpl = ax.tmpl;
             st.qv = *reinterpret_cast<const double4 *>(a.q + 4 * (size_t)o);
         }
-        const uint8_t fl = FIXED ? fl_fixed : oany[o];
+        const uint8_t fl = FIXED ? fl_fixed : (BOUNDS ? (uint8_t)1u : oany[o]);
         const bool any = (fl & 1u) != 0;
         const bool fixed = FIXED && (fl & 2u) != 0;
         float3 F = f3(0.f, 0.f, 0.f), T = f3(0.f, 0.f, 0.f);
@@ -1302,7 +1305,7 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, RecBuf
             if (w0 && r.w[0] == 0.0f && r.w[1] == 0.0f && r.w[2] == 0.0f) r.vox |= DEM_VOX_QSAME;
             if (cold) rec_out.cold[o] = rec_cold(r);
         }
-        if (valid) store_split_hot(rec_out, o, r);
+        if (valid) store_split_hot(rec_out, o, r, a.nt != 0);
     }
     if (halt) return;
     __shared__ float wmax[2][FREE_WAVES];

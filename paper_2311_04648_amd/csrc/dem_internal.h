@@ -45,6 +45,13 @@ struct RecBuf {
     uint4 *cold;
 };
 
+// Whether the streams over a system's state (each step's records, a
+// detection's candidate records, the learned interval's snapshot) are
+// stored non-temporally: when the state is larger than the last-level
+// cache (256 MB), a stream is not read back from a cache anyway, and
+// normal stores would evict data that is.
+inline bool stream_nt(int64_t n_owners) { return n_owners * 48 > (int64_t)256 << 20; }
+
 struct __align__(16) OwnerAux {
     float inv_moi[3];
     int32_t tmpl;      // -1: single sphere at the owner centre
@@ -213,6 +220,7 @@ struct DetectArgs {
     const Cand *dcand;              // dormant candidates in bin order
     const float4 *dcandf;           // their FP32 copies for the prefilter
     int32_t owner_list;     // build the owner list of each set written (AcsBuf::olist)
+    int32_t nt;             // store the binning's streams non-temporally (stream_nt)
 };
 
 struct CdWork {
@@ -368,6 +376,7 @@ struct DynArgs {
     double *gD;             // [2] reach D by step parity
     double vgeom;           // fastest point of any wall or mesh
     float arm;              // largest distance of a template sphere's centre from its owner's (0: none)
+    int32_t nt;             // store the streaming step's records non-temporally (stream_nt)
 };
 
 struct StepBufs {

@@ -261,7 +261,7 @@ __device__ inline void feat_global_add(uint32_t *rw, const uint32_t *a, unsigned
 
 __global__ void __launch_bounds__(256) k_feat_accum(RecBuf rec, const SnapRec *snap, SnapRec *snap_out,
                                                    const float *ovol, Origin org, Grid fg, uint32_t *raw,
-                                                   uint32_t *cellmap, int64_t No)
+                                                   uint32_t *cellmap, int64_t No, bool nt)
 {
     __shared__ uint32_t tkey[FEAT_SLOTS];
     __shared__ uint32_t tval[FEAT_SLOTS][FEAT_MAXW];
@@ -323,13 +323,20 @@ __global__ void __launch_bounds__(256) k_feat_accum(RecBuf rec, const SnapRec *s
             // fixed-point volume in units of 1e-18 m^3
             iv = (unsigned long long)((double)vo * 1e18 + 0.5);
             if (snap_out) {
-                SnapRec nw;
-                nw.vox = r.vox;
-                for (int k = 0; k < 3; ++k) {
-                    nw.off[k] = r.off[k];
-                    nw.v[k] = r.v[k];
+                // (a snapshot holds what a record's hot part holds: voxel
+                // word, offsets, velocity)
+                if (nt) {
+                    st_nt(rec_hot0(r), reinterpret_cast<uint4 *>(snap_out + o));
+                    st_nt(rec_hot1(r), reinterpret_cast<uint4 *>(snap_out + o) + 1);
+                } else {
+                    SnapRec nw;
+                    nw.vox = r.vox;
+                    for (int k = 0; k < 3; ++k) {
+                        nw.off[k] = r.off[k];
+                        nw.v[k] = r.v[k];
+                    }
+                    snap_out[o] = nw;
                 }
-                snap_out[o] = nw;
             }
         }
         // runs of equal cells over the lanes; the scan combines each run
@@ -572,7 +579,7 @@ static void feature_accumulate(RecBuf rec, const SnapRec *snap, SnapRec *snap_ou
     const int64_t nb = (No + FEAT_OWNERS - 1) / FEAT_OWNERS;
     if (nb > 0)
         hipLaunchKernelGGL(k_feat_accum, dim3((unsigned)nb), dim3(256), 0, s, rec, snap, snap_out, ovol, org, fg, raw,
-                           cellmap, No);
+                           cellmap, No, stream_nt(No));
 }
 
 // Features of occupied cells written to `out` (row-major, cell order) and
