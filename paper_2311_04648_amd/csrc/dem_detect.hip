@@ -60,26 +60,43 @@ __global__ void __launch_bounds__(TPB) k_cd_prepare(DetectArgs a, uint32_t *keys
         key = bin_key(a.grid, x);
     }
     const uint32_t rk = wave_run_claim(cell_count, key, active && !dorm);
+    if (a.nt) {
+        // streams of a state larger than the caches: non-temporal stores,
+        // the 32-byte candidate records through LDS so that each store
+        // instruction writes 1 KiB of consecutive pieces (whole lines); a
+        // dormant sphere's record (never read) is written too
+        __shared__ uint4 lc[TPB / 64][128];
+        const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+        lc[wv][2 * lane] = make_uint4(__double2loint(x[0]), __double2hiint(x[0]), __double2loint(x[1]),
+                                      __double2hiint(x[1]));
+        lc[wv][2 * lane + 1] = make_uint4(__double2loint(x[2]), __double2hiint(x[2]), __float_as_uint(s.rad),
+                                          (uint32_t)i);
+        if (active) {
+            st_nt_u32(key, keys + i);
+            if (vals) vals[i] = (uint32_t)i;
+            if (!dorm) st_nt_u32(rk, rank + i);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int64_t w0 = (int64_t)blockIdx.x * blockDim.x + 64 * wv;
+        const uint32_t nv = w0 < a.n_spheres ? (uint32_t)(a.n_spheres - w0 < 64 ? a.n_spheres - w0 : 64) : 0u;
+        uint4 *d = reinterpret_cast<uint4 *>(cand_tmp + w0);
+        for (uint32_t k = lane; k < 2u * nv; k += 64u) st_nt(lc[wv][k], d + k);
+        return;
+    }
     if (!active) return;
-    if (a.nt) st_nt_u32(key, keys + i);
-    else keys[i] = key;
+    keys[i] = key;
     if (vals) vals[i] = (uint32_t)i;   // ids to sort (the one-pass sort writes its own)
     if (dorm) return;
-    if (a.nt) st_nt_u32(rk, rank + i);
-    else rank[i] = rk;
+    rank[i] = rk;
     Cand c;
     c.x = x[0];
     c.y = x[1];
     c.z = x[2];
     c.r = s.rad;
     c.id = (uint32_t)i;
-    if (a.nt) {
-        uint4 *d = reinterpret_cast<uint4 *>(cand_tmp + i);
-        st_nt(make_uint4(__double2loint(c.x), __double2hiint(c.x), __double2loint(c.y), __double2hiint(c.y)), d);
-        st_nt(make_uint4(__double2loint(c.z), __double2hiint(c.z), __float_as_uint(c.r), c.id), d + 1);
-    } else {
-        cand_tmp[i] = c;
-    }
+    cand_tmp[i] = c;
 }
 
 // One-pass sort of (bin key, sphere id): the per-bin counts and their scan

@@ -1193,10 +1193,11 @@ __global__ void __launch_bounds__(TPB, (FACETS || !SINGLES) ? 3 : 4) k_step_fuse
 // k_step_listed, which runs after it on the same stream over the set's list
 // of owners with contacts and does for each what the one-kernel step does
 // (owner_forces, then the integration), so both forms give the same bits.
-// Each lane loads and stores its owner's hot part (consecutive lanes,
-// consecutive 32-byte parts: clump systems split their records), with the
-// flag; the cold part, the inertia and the orientation only for owners
-// that turn or have just stopped turning.
+// Each lane loads its owner's hot part (consecutive lanes, consecutive
+// 32-byte parts: clump systems split their records), with the flag; the
+// new hot parts go out through LDS in whole lines; the cold part, the
+// inertia and the orientation only for owners that turn or have just
+// stopped turning.
 // REMAP: the first step on a newly adopted set (only its overflow check
 // matters here).
 constexpr int FREE_WAVES = 2;    // waves per block of k_step_free
@@ -1236,6 +1237,7 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, RecBuf
         *gap_slot(a, a.step + 1, lane) = 0.0f;
     }
     float v2 = 0.0f, g2 = 0.0f;
+    __shared__ uint4 wout[FREE_WAVES][FREE_CHUNKS][128];   // the chunks' new hot parts
     uint8_t fl[FREE_CHUNKS];
     OwnerRec rh[FREE_CHUNKS];
     // loads: flags and the hot parts of the records of every chunk, all
@@ -1305,7 +1307,23 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, RecBuf
             if (w0 && r.w[0] == 0.0f && r.w[1] == 0.0f && r.w[2] == 0.0f) r.vox |= DEM_VOX_QSAME;
             if (cold) rec_out.cold[o] = rec_cold(r);
         }
-        if (valid) store_split_hot(rec_out, o, r, a.nt != 0);
+        if (valid) store_split_hot(RecBuf{wout[wv][c], nullptr}, lane, r, false);
+    }
+    // the hot parts go out through LDS: each store instruction then writes
+    // 1 KiB of consecutive 16-byte pieces (whole lines), which non-temporal
+    // stores need (a lane's own two pieces, 32 bytes apart across the wave,
+    // reach memory as partial lines)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int c = 0; c < FREE_CHUNKS; ++c) {
+        const int64_t ow = ob + (int64_t)(wv * FREE_CHUNKS + c) * 64;
+        const uint32_t nv = ow < No ? (uint32_t)(No - ow < 64 ? No - ow : 64) : 0u;
+        for (uint32_t k = lane; k < 2u * nv; k += 64u) {
+            if (a.nt) st_nt(wout[wv][c][k], &rec_out.hot[2 * ow + k]);
+            else rec_out.hot[2 * ow + k] = wout[wv][c][k];
+        }
     }
     if (halt) return;
     __shared__ float wmax[2][FREE_WAVES];

@@ -324,11 +324,12 @@ __global__ void __launch_bounds__(256) k_feat_accum(RecBuf rec, const SnapRec *s
             iv = (unsigned long long)((double)vo * 1e18 + 0.5);
             if (snap_out) {
                 // (a snapshot holds what a record's hot part holds: voxel
-                // word, offsets, velocity)
-                if (nt) {
+                // word, offsets, velocity; split records write it from the
+                // staged hot parts below, in whole lines)
+                if (nt && !rec.cold) {
                     st_nt(rec_hot0(r), reinterpret_cast<uint4 *>(snap_out + o));
                     st_nt(rec_hot1(r), reinterpret_cast<uint4 *>(snap_out + o) + 1);
-                } else {
+                } else if (!nt) {
                     SnapRec nw;
                     nw.vox = r.vox;
                     for (int k = 0; k < 3; ++k) {
@@ -338,6 +339,11 @@ __global__ void __launch_bounds__(256) k_feat_accum(RecBuf rec, const SnapRec *s
                     snap_out[o] = nw;
                 }
             }
+        }
+        if (snap_out && nt && rec.cold) {
+            // the staged hot parts are the wave's new snapshot records
+            uint4 *d = reinterpret_cast<uint4 *>(snap_out + ow);
+            for (uint32_t k = (uint32_t)lane; k < 2u * nv; k += 64u) st_nt(lrec[wv][k], d + k);
         }
         // runs of equal cells over the lanes; the scan combines each run
         const uint32_t cprev = (uint32_t)__shfl_up((int)c, 1, 64);
