@@ -154,13 +154,13 @@ def n_clump_share(sysm, rr):
 
 
 def listed_bytes(n_own, n_clump, active, C, rolling):
-    """k_step_listed: per owner with contacts its list entry (4), flag (1),
-    inertia and template (16), sphere range (8) and record read + written
-    (96); per clump among them its orientation read + written (64); per
-    active sphere its record, row and B-list offsets (28); per contact the
-    partner id (4), the new history written (12, 16 with contact age) and
-    the B-list entry with its source sphere (8)."""
-    return n_own * 125 + n_clump * 64 + active * 28 + C * (28 if rolling else 24)
+    """k_step_listed: per owner with contacts its list entry (32: the owner,
+    its first sphere and its spheres' row and B-list bounds), inertia and
+    template (16) and record read + written (96); per clump among them its
+    orientation read + written (64); per active sphere its record (20); per
+    contact the partner id (4), the new history written (12, 16 with
+    contact age) and the B-list entry with its source sphere (8)."""
+    return n_own * 144 + n_clump * 64 + active * 20 + C * (28 if rolling else 24)
 
 
 def kernel_sha(path, kernel):

@@ -318,7 +318,7 @@ void carve(Carver &c, dem_ctx *ctx, int64_t cap)
         a.bsrc = c.take<uint32_t>(cap);
         a.bcur = c.take<uint32_t>(Ns + 1);
         a.oany = c.take<uint8_t>(No);
-        a.olist = c.take<uint32_t>(No);
+        a.olist = c.take<uint4>(ctx->has_clumps ? 2 * No : 1);
         a.otile = c.take<uint32_t>(owner_list_tiles(No) + 1);
         a.gk = c.take<float>(cap);
     }

@@ -1058,16 +1058,36 @@ __global__ void __launch_bounds__(TPB) k_olist_count(const uint8_t *flag, int64_
     if (threadIdx.x == 0) tcount[blockIdx.x] = tot;
 }
 
+// Each listed owner's record carries its first sphere and the bounds of its
+// spheres' rows and B lists (AcsBuf::olist), read here once per set so that
+// the step reads them with the owner, in one sequential load.
 __global__ void __launch_bounds__(TPB) k_olist_write(const uint8_t *flag, int64_t no, const uint32_t *toff,
-                                                     uint32_t *olist)
+                                                     const uint32_t *own_sph0, const uint32_t *start,
+                                                     const uint32_t *bstart, uint4 *olist)
 {
     const int64_t base = (int64_t)blockIdx.x * OL_TILE + (int64_t)threadIdx.x * OL_PER;
     uint32_t bits = olist_bits(flag, base, no), tot;
     uint32_t pos = toff[blockIdx.x] + olist_block_scan((uint32_t)__popc(bits), &tot);
     while (bits) {
-        const int k = __ffs(bits) - 1;
-        olist[pos++] = (uint32_t)(base + k);
+        const uint32_t o = (uint32_t)(base + __ffs(bits) - 1);
         bits &= bits - 1u;
+        const uint32_t s0 = own_sph0 ? own_sph0[o] : o, s1 = own_sph0 ? own_sph0[o + 1] : o + 1u;
+        uint32_t sa = start[s0], ba = bstart[s0], n = s1 - s0;
+        const uint4 head = make_uint4(o, s0, sa, ba);
+        uint64_t rows = 0, blist = 0;
+        if (n > LIST_SPHERES) n = LIST_NOPACK;
+        for (uint32_t m = 0; n != LIST_NOPACK && m < n; ++m) {
+            const uint32_t se = start[s0 + m + 1], be = bstart[s0 + m + 1];
+            if (se - sa > 255u || be - ba > 255u) n = LIST_NOPACK;
+            rows |= (uint64_t)(se - sa) << (8 * m);
+            blist |= (uint64_t)(be - ba) << (8 * m);
+            sa = se;
+            ba = be;
+        }
+        olist[2 * (size_t)pos] = head;
+        olist[2 * (size_t)pos + 1] = make_uint4((uint32_t)rows, (uint32_t)(rows >> 32) | (uint32_t)blist << 16,
+                                                (uint32_t)(blist >> 16), n);
+        ++pos;
     }
 }
 
@@ -1253,7 +1273,7 @@ int64_t owner_list_tiles(int64_t no)
     return (no + OL_TILE - 1) / OL_TILE;
 }
 
-void launch_owner_list(AcsBuf &b, int64_t no, uint32_t *partials, hipStream_t s)
+void launch_owner_list(AcsBuf &b, const uint32_t *own_sph0, int64_t no, uint32_t *partials, hipStream_t s)
 {
     const int64_t nt = owner_list_tiles(no);
     if (nt == 0) {
@@ -1263,7 +1283,8 @@ void launch_owner_list(AcsBuf &b, int64_t no, uint32_t *partials, hipStream_t s)
     hipLaunchKernelGGL(k_olist_count, dim3((unsigned)nt), dim3(TPB), 0, s, (const uint8_t *)b.oany, no, b.otile);
     scan_exclusive_u32(b.otile, b.otile, nt, partials, s);
     hipLaunchKernelGGL(k_olist_write, dim3((unsigned)nt), dim3(TPB), 0, s, (const uint8_t *)b.oany, no,
-                       (const uint32_t *)b.otile, b.olist);
+                       (const uint32_t *)b.otile, own_sph0, (const uint32_t *)b.start, (const uint32_t *)b.bstart,
+                       b.olist);
 }
 
 void launch_owner_flags(AcsBuf &b, const uint32_t *own_sph0, int64_t no, int64_t ns, int64_t cap,
@@ -1271,7 +1292,7 @@ void launch_owner_flags(AcsBuf &b, const uint32_t *own_sph0, int64_t no, int64_t
 {
     hipLaunchKernelGGL(k_owner_flags, dim3(nblocks(no)), dim3(TPB), 0, s, (const uint32_t *)b.start,
                        (const uint32_t *)b.bstart, own_sph0, no, ns, cap, ofam, fixed, b.oany);
-    if (list) launch_owner_list(b, no, partials, s);
+    if (list) launch_owner_list(b, own_sph0, no, partials, s);
 }
 
 void launch_detect(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap, DevCounters *ctr, int buf,
@@ -1315,7 +1336,7 @@ void launch_detect_back(const DetectArgs &a, CdWork &w, AcsBuf &out, int64_t cap
     hipLaunchKernelGGL(k_blist_finish, dim3(nblocks(std::max(n, a.n_owners))), dim3(TPB), 0, s, out.start,
                        out.bstart, n, cap, out.bidx, out.bsrc, a.own_sph0, a.n_owners, a.ofam, a.famfixed, out.oany,
                        w.cell_count, (int64_t)a.grid.nbins + 1);
-    if (a.owner_list) launch_owner_list(out, a.n_owners, w.partials, s);
+    if (a.owner_list) launch_owner_list(out, a.own_sph0, a.n_owners, w.partials, s);
 }
 
 void launch_judge(const DetectArgs &a_in, CdWork &w, const AcsBuf &cur, int64_t cap, DevCounters *ctr,

@@ -715,17 +715,21 @@ __device__ inline float gap_key(double g, double D)
 // is the step's reach), and an item's indices are loaded two items ahead,
 // its key one item ahead.
 // BOUNDS (clumps, the owners of a set's list of owners with contacts): the
-// row and B-list bounds of the owner's first BOUND_SPHERES spheres are
-// loaded in one round before the sphere loop, so that a sphere without
-// items costs no round trip of its own; the owner's flag is known (it has
-// contacts, and such runs have no fixed families) and is not read.
-constexpr uint32_t BOUND_SPHERES = 6;
+// first sphere and the row and B-list bounds of the owner's spheres come
+// with its record in the list (lrec, AcsBuf::olist), so that neither they
+// nor a sphere without items cost a round trip of their own (an owner
+// whose record holds no lengths loads them per sphere); the owner's flag is
+// known (it has contacts, and such runs have no fixed families) and is not
+// read.
+struct ListRec {
+    uint4 h, c;
+};
 
 template <bool SINGLES, bool FACETS, bool FIXED, bool AHEAD, bool REMAP, bool GAP = false, bool BOUNDS = false>
 __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, const uint32_t *start,
     const uint32_t *jarr, const uint32_t *bstart, const uint32_t *bidx, const uint32_t *bsrc, const uint8_t *oany,
     const uint8_t fl_fixed, const float *hx, const float *hy, const float *hz, const float *hw, const HistOut &ho,
-    OwnerStep &st, const OwnerRec *pre = nullptr, const double Dn = 0.0)
+    OwnerStep &st, const OwnerRec *pre = nullptr, const double Dn = 0.0, const ListRec lrec = ListRec{})
 {
     static_assert(!GAP || !FIXED, "pair skipping is for systems without fixed families");
     static_assert(!BOUNDS || !FIXED, "listed owners run without fixed families");
@@ -758,38 +762,32 @@ __device__ __forceinline__ void owner_forces(const DynArgs &a, const int64_t o, 
         const bool any = (fl & 1u) != 0;
         const bool fixed = FIXED && (fl & 2u) != 0;
         float3 F = f3(0.f, 0.f, 0.f), T = f3(0.f, 0.f, 0.f);
-        const uint32_t s0 = SINGLES ? (uint32_t)o : (any ? a.own_sph0[o] : 0u);
-        const uint32_t s1 = SINGLES ? (uint32_t)o + 1u : (any ? a.own_sph0[o + 1] : 0u);
-        uint32_t sb[BOUNDS ? BOUND_SPHERES + 1 : 1], bb[BOUNDS ? BOUND_SPHERES + 1 : 1];
-        const bool pre = BOUNDS && any && s1 - s0 <= BOUND_SPHERES;
+        const bool packed = BOUNDS && lrec.c.w != LIST_NOPACK;
+        const uint32_t s0 = BOUNDS ? lrec.h.y : SINGLES ? (uint32_t)o : (any ? a.own_sph0[o] : 0u);
+        const uint32_t s1 = packed ? s0 + lrec.c.w
+                                   : SINGLES ? (uint32_t)o + 1u : (any ? a.own_sph0[o + 1] : 0u);
+        // (packed: the next sphere's row and B-list starts, and the lengths
+        // still to come, a byte per sphere)
+        uint32_t pc = 0u, pb = 0u;
+        uint64_t prow = 0u, pbl = 0u;
         if constexpr (BOUNDS) {
-#pragma unroll
-            for (uint32_t k = 0; k <= BOUND_SPHERES; ++k) {
-                sb[k] = 0u;
-                bb[k] = 0u;
-                if (pre && k <= s1 - s0) {
-                    sb[k] = start[s0 + k];
-                    bb[k] = bstart[s0 + k];
-                }
-            }
+            pc = lrec.h.z;
+            pb = lrec.h.w;
+            prow = (uint64_t)lrec.c.x | (uint64_t)(lrec.c.y & 0xffffu) << 32;
+            pbl = (uint64_t)(lrec.c.y >> 16) | (uint64_t)lrec.c.z << 16;
         }
         for (uint32_t s = s0; any && s < s1; ++s) {
             uint32_t c0, na, b0, nall;
-            if (pre) {
-                // (registers indexed by a loop counter: a short select chain)
-                uint32_t sa = sb[0], se = sb[1], ba = bb[0], be = bb[1];
-#pragma unroll
-                for (uint32_t k = 1; k < BOUND_SPHERES; ++k)
-                    if (s - s0 == k) {
-                        sa = sb[k];
-                        se = sb[k + 1];
-                        ba = bb[k];
-                        be = bb[k + 1];
-                    }
-                c0 = sa;
-                na = se - sa;
-                b0 = ba;
-                nall = fixed ? na : na + (be - ba);
+            if (packed) {
+                const uint32_t nb = (uint32_t)pbl & 0xffu;
+                na = (uint32_t)prow & 0xffu;
+                c0 = pc;
+                b0 = pb;
+                prow >>= 8;
+                pbl >>= 8;
+                pc += na;
+                pb += nb;
+                nall = na + nb;
                 if (nall == 0) continue;
             } else {
                 c0 = start[s];
@@ -1353,14 +1351,15 @@ __global__ void __launch_bounds__(FREE_WAVES * 64) k_step_free(DynArgs a, RecBuf
 
 // The owners with contacts of a split step (see k_step_free), from the
 // set's owner list (ascending: consecutive threads take consecutive owners,
-// whose rows are neighbours).  The list's length is read on the device, so
+// whose rows are neighbours; each entry brings the owner's first sphere and
+// the bounds of its spheres' rows and B lists).  The list's length is read on the device, so
 // the grid is fixed and the threads stride over the list.  The largest
 // |v|^2 joins the slot after the first kernel's (an atomic maximum on the
 // bits of non-negative floats, one per block).
 constexpr unsigned LISTED_BLOCKS = 1024;
 
 template <bool FACETS, bool REMAP, bool GAP>
-__global__ void __launch_bounds__(TPB, 3) k_step_listed(DynArgs a, const uint32_t *olist, const uint32_t *ocount,
+__global__ void __launch_bounds__(TPB, 3) k_step_listed(DynArgs a, const uint4 *olist, const uint32_t *ocount,
                                                        RecBuf rec_out, double *q_out, const uint32_t *start,
                                                        const uint32_t *jarr, const uint32_t *bstart,
                                                        const uint32_t *bidx, const uint32_t *bsrc,
@@ -1379,7 +1378,8 @@ __global__ void __launch_bounds__(TPB, 3) k_step_listed(DynArgs a, const uint32_
     const double Dn = GAP && !halt ? gap_reach(a) : 0.0;
     float v2 = 0.0f, g2 = 0.0f;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const int64_t o = (int64_t)olist[i];
+        const ListRec lr{olist[2 * i], olist[2 * i + 1]};
+        const int64_t o = (int64_t)lr.h.x;
         if (halt) {
             halt_owner<false>(a, o, rec_out, q_out, start, jarr, bstart, bidx, bsrc, oany, hx, hy, hz, hw, ox, oy,
                               oz, ow, cap, ctr);
@@ -1387,7 +1387,7 @@ __global__ void __launch_bounds__(TPB, 3) k_step_listed(DynArgs a, const uint32_
         }
         OwnerStep st;
         owner_forces<false, FACETS, false, true, REMAP, GAP, true>(a, o, start, jarr, bstart, bidx, bsrc, oany, 0,
-                                                                   hx, hy, hz, hw, ho, st, nullptr, Dn);
+                                                                   hx, hy, hz, hw, ho, st, nullptr, Dn, lr);
         if (st.advance) {
             v2 = fmaxf(v2, owner_advance<false>(a, o, st, rec_out, q_out, ctr));
             if (GAP) g2 = fmaxf(g2, reach_speed2(st.r, a.arm));
@@ -1556,7 +1556,7 @@ bool launch_step_fused(const DynArgs &a, RecBuf rec_out, double *q_out, const Ac
                       : (a.n_tri > 0 ? (r ? k_step_listed<true, true, false> : k_step_listed<true, false, false>)
                                      : (r ? k_step_listed<false, true, false> : k_step_listed<false, false, false>));
         const unsigned nl = std::min<unsigned>(nb, LISTED_BLOCKS);
-        hipLaunchKernelGGL(kl, dim3(nl), dim3(TPB), 0, s, a, (const uint32_t *)cur.olist,
+        hipLaunchKernelGGL(kl, dim3(nl), dim3(TPB), 0, s, a, (const uint4 *)cur.olist,
                            (const uint32_t *)(cur.otile + owner_list_tiles(a.n_owners)), rec_out, q_out,
                            (const uint32_t *)cur.start, (const uint32_t *)cur.j, (const uint32_t *)cur.bstart,
                            (const uint32_t *)cur.bidx, (const uint32_t *)cur.bsrc, (const uint8_t *)cur.oany,

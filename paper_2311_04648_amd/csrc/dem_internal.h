@@ -238,6 +238,15 @@ struct CdWork {
     int sort_mode;         // 0: one-pass bin sort, 1: 8-bit LSD radix passes
 };
 
+// A listed owner's record (AcsBuf::olist): {owner, first sphere s0, the row
+// start and the B-list start of s0}, then the row and B-list lengths of its
+// spheres as bytes (.x: rows of spheres 0-3; .y: rows of 4-5 in the low
+// half, B lists of 0-1 in the high half; .z: B lists of 2-5) and in .w the
+// sphere count, or LIST_NOPACK for an owner of more than LIST_SPHERES
+// spheres or with a row or B list longer than 255.
+constexpr uint32_t LIST_SPHERES = 6;
+constexpr uint32_t LIST_NOPACK = 0xffffffffu;
+
 struct AcsBuf {
     uint32_t *start;   // [Ns+1]
     uint32_t *j;       // [cap]
@@ -254,8 +263,9 @@ struct AcsBuf {
                        // bit 1: the owner is in a fixed family
     // the owners with bit 0 set, ascending (built with the flags in clump
     // systems without fixed families, where a step with a sparse set runs
-    // them in a kernel of their own); their count is otile[owner_list_tiles(No)]
-    uint32_t *olist;   // [No]
+    // them in a kernel of their own), as two uint4 each (see LIST_SPHERES);
+    // their count is otile[owner_list_tiles(No)]
+    uint4 *olist;      // [2 No]
     uint32_t *otile;   // [owner_list_tiles(No) + 1] per-tile offsets, then the count
     // single-sphere systems: per contact a lower bound of the pair's gap
     // plus the reach of the chain it was written in (DynArgs::gap); null
@@ -302,7 +312,7 @@ void launch_blists(AcsBuf &b, int64_t n_spheres, int64_t cap, uint32_t *partials
 void launch_owner_flags(AcsBuf &b, const uint32_t *own_sph0, int64_t n_owners, int64_t n_spheres, int64_t cap,
                         const uint8_t *ofam, const uint8_t *fixed, hipStream_t s, bool list = false,
                         uint32_t *partials = nullptr);
-void launch_owner_list(AcsBuf &b, int64_t n_owners, uint32_t *partials, hipStream_t s);
+void launch_owner_list(AcsBuf &b, const uint32_t *own_sph0, int64_t n_owners, uint32_t *partials, hipStream_t s);
 void launch_remap(const AcsBuf &oldb, AcsBuf &newb, int64_t n_spheres, DevCounters *ctr, int newbuf,
                   int rolling, hipStream_t s);
 
