@@ -1060,34 +1060,48 @@ __global__ void __launch_bounds__(TPB) k_olist_count(const uint8_t *flag, int64_
 
 // Each listed owner's record carries its first sphere and the bounds of its
 // spheres' rows and B lists (AcsBuf::olist), read here once per set so that
-// the step reads them with the owner, in one sequential load.
+// the step reads them with the owner, in one sequential load.  The tile's
+// listed owners are gathered in LDS first, then the block's threads take
+// one each, so that a thread with several of them does not hold its wave.
 __global__ void __launch_bounds__(TPB) k_olist_write(const uint8_t *flag, int64_t no, const uint32_t *toff,
                                                      const uint32_t *own_sph0, const uint32_t *start,
                                                      const uint32_t *bstart, uint4 *olist)
 {
+    __shared__ uint32_t lo[OL_TILE];
     const int64_t base = (int64_t)blockIdx.x * OL_TILE + (int64_t)threadIdx.x * OL_PER;
     uint32_t bits = olist_bits(flag, base, no), tot;
-    uint32_t pos = toff[blockIdx.x] + olist_block_scan((uint32_t)__popc(bits), &tot);
+    uint32_t at = olist_block_scan((uint32_t)__popc(bits), &tot);
     while (bits) {
-        const uint32_t o = (uint32_t)(base + __ffs(bits) - 1);
+        lo[at++] = (uint32_t)(base + __ffs(bits) - 1);
         bits &= bits - 1u;
+    }
+    __syncthreads();
+    const size_t pos0 = toff[blockIdx.x];
+    for (uint32_t t = threadIdx.x; t < tot; t += TPB) {
+        const uint32_t o = lo[t];
         const uint32_t s0 = own_sph0 ? own_sph0[o] : o, s1 = own_sph0 ? own_sph0[o + 1] : o + 1u;
-        uint32_t sa = start[s0], ba = bstart[s0], n = s1 - s0;
-        const uint4 head = make_uint4(o, s0, sa, ba);
-        uint64_t rows = 0, blist = 0;
-        if (n > LIST_SPHERES) n = LIST_NOPACK;
-        for (uint32_t m = 0; n != LIST_NOPACK && m < n; ++m) {
-            const uint32_t se = start[s0 + m + 1], be = bstart[s0 + m + 1];
-            if (se - sa > 255u || be - ba > 255u) n = LIST_NOPACK;
-            rows |= (uint64_t)(se - sa) << (8 * m);
-            blist |= (uint64_t)(be - ba) << (8 * m);
-            sa = se;
-            ba = be;
+        uint32_t n = s1 - s0;
+        // every bound at once (up to s0 + LIST_SPHERES, and never past s1)
+        uint32_t sb[LIST_SPHERES + 1], bb[LIST_SPHERES + 1];
+#pragma unroll
+        for (uint32_t m = 0; m <= LIST_SPHERES; ++m) {
+            sb[m] = m <= n ? start[s0 + m] : 0u;
+            bb[m] = m <= n ? bstart[s0 + m] : 0u;
         }
-        olist[2 * (size_t)pos] = head;
-        olist[2 * (size_t)pos + 1] = make_uint4((uint32_t)rows, (uint32_t)(rows >> 32) | (uint32_t)blist << 16,
-                                                (uint32_t)(blist >> 16), n);
-        ++pos;
+        uint64_t rows = 0, blist = 0;
+        bool fits = n <= LIST_SPHERES;
+#pragma unroll
+        for (uint32_t m = 0; m < LIST_SPHERES; ++m)
+            if (m < n) {
+                const uint32_t na = sb[m + 1] - sb[m], nb = bb[m + 1] - bb[m];
+                fits = fits && na <= 255u && nb <= 255u;
+                rows |= (uint64_t)(na & 0xffu) << (8 * m);
+                blist |= (uint64_t)(nb & 0xffu) << (8 * m);
+            }
+        if (!fits) n = LIST_NOPACK;
+        olist[2 * (pos0 + t)] = make_uint4(o, s0, sb[0], bb[0]);
+        olist[2 * (pos0 + t) + 1] = make_uint4((uint32_t)rows, (uint32_t)(rows >> 32) | (uint32_t)blist << 16,
+                                               (uint32_t)(blist >> 16), n);
     }
 }
 
