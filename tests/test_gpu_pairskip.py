@@ -142,3 +142,55 @@ def test_clump_skipping_split_equals_two_kernel_form(dem):
     a = _run(dem, s, 800, True, dyn_path=4, **kw)
     b = _run(dem, s, 800, True, dyn_path=1, **kw)
     _same(a, b)
+
+
+def _cube_clumps(seed, n=216, spacing=0.0095):
+    """Tri-sphere clumps, eight-sphere clumps (spheres at the corners of a
+    cube) and single spheres: an owner of more than six spheres takes the
+    split step's path whose list entry holds no per-sphere lengths."""
+    rng = np.random.default_rng(seed)
+    side = int(math.ceil(n ** (1 / 3)))
+    base = W.lattice((side, side, side), spacing, -0.5 * (side - 1) * spacing * np.ones(3), n_take=n)
+    base = base + rng.uniform(-0.0004, 0.0004, size=(n, 3))
+    q = W.random_quaternions(rng, n)
+    V = rng.normal(0.0, 0.2, size=(n, 3))
+    Wb = rng.normal(0.0, 20.0, size=(n, 3))
+    types = rng.integers(-1, 2, size=n).astype(np.int32)
+    q[types < 0] = np.array([1.0, 0, 0, 0])
+    corner = 0.0017 * np.array([[x, y, z] for x in (-1, 1) for y in (-1, 1) for z in (-1, 1)], dtype=np.float64)
+    cube = (corner.astype(np.float32), np.full(8, 0.0019, dtype=np.float32))
+    half = 0.5 * side * spacing + 0.006
+    lo, hi = -half * np.ones(3), half * np.ones(3)
+    walls = W.box_walls(lo, hi, moving={0: (0.1, 0.0, 0.0)})
+    return W.assemble(types, base, q, V, Wb, [W.tri_template(0.003, 0.002), cube], 0.0025, [0, 0],
+                      W.concat_walls(walls), W.materials(), (0, 0, -9.81), 5e-6, 0.0002, lo, hi,
+                      name=f"cube_clumps{seed}")
+
+
+def test_eight_sphere_clumps_split_equals_two_kernel_form(dem):
+    """Owners of eight spheres in the split step: their bounds are read per
+    sphere, the others' from their list entries; both forms end bit for
+    bit in the same state, set and history."""
+    s = _cube_clumps(7)
+    sph0 = np.asarray(s.own_sph0)
+    assert int(np.max(np.diff(sph0))) == 8
+    kw = dict(mode="fixed", k=10, lam=5, capacity=64 * s.n_spheres)
+    a = _run(dem, s, 1500, True, dyn_path=4, **kw)
+    b = _run(dem, s, 1500, True, dyn_path=1, **kw)
+    # touching pairs with a sphere of an eight-sphere owner
+    keys, hist = a[2], a[3]
+    touch = np.any(hist[:, :3] != 0.0, axis=1)
+    big = np.diff(sph0) == 8
+
+    def of_big(sph):
+        return big[np.searchsorted(sph0, sph, side="right") - 1]
+
+    i = (keys >> np.uint64(32)).astype(np.int64)
+    j = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    jb = np.zeros_like(i, dtype=bool)
+    jb[j < s.n_spheres] = of_big(j[j < s.n_spheres])
+    n_big = int(np.count_nonzero(touch & (of_big(i) | jb)))
+    print(f"{keys.size} pairs, {_touching(a)} with history ({n_big} with an eight-sphere clump), "
+          f"cds {a[0]['cds']}", flush=True)
+    assert n_big > 0
+    _same(a, b)
